@@ -1,0 +1,356 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module only builds *inputs*: skeleton meshes with interface labels,
+material draws and incident plane-wave parameters.  It holds none of the
+formulation's arithmetic (no basis functions, kernels or quadrature), so the
+oracle and the GPU library can both consume its output without sharing any
+of the method's code.
+
+Mesh format (used by every consumer):
+
+* ``xyz``   float64 [nv, 3]  vertex coordinates
+* ``tri``   int32   [nt, 3]  vertex ids; the right-hand normal
+                             (v1 - v0) x (v2 - v0) points from the subdomain
+                             ``label[t, 0]`` towards ``label[t, 1]``
+* ``label`` int32   [nt, 2]  the two subdomains a skeleton triangle separates;
+                             0 is the unbounded exterior.  Generators emit
+                             ``label[t, 0] < label[t, 1]`` (the min -> max
+                             orientation convention of the skeleton mesh,
+                             Section 4.2 of the paper).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "SplitMix64", "Mesh", "icosphere", "box_skeleton", "cube_partition",
+    "fibonacci_directions", "polarisations", "sphere_cluster",
+    "config_sphere", "config_cube", "config_cube_multi_rhs", "config_clusters",
+    "warm_start_samples",
+]
+
+_MASK64 = (1 << 64) - 1
+
+
+class SplitMix64:
+    """SplitMix64 (Steele, Lea & Flood 2014): the seeded generator for every draw."""
+
+    def __init__(self, seed: int):
+        self.state = seed & _MASK64
+
+    def next_u64(self) -> int:
+        self.state = (self.state + 0x9E3779B97F4A7C15) & _MASK64
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+        return z ^ (z >> 31)
+
+    def uniform(self, lo: float = 0.0, hi: float = 1.0) -> float:
+        """53-bit uniform double in [lo, hi)."""
+        return lo + (hi - lo) * ((self.next_u64() >> 11) * (1.0 / (1 << 53)))
+
+    def integer(self, lo: int, hi: int) -> int:
+        """Uniform integer in [lo, hi] (inclusive)."""
+        span = hi - lo + 1
+        return lo + int(self.next_u64() % span)
+
+
+@dataclass
+class Mesh:
+    xyz: np.ndarray
+    tri: np.ndarray
+    label: np.ndarray
+    M: int
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nv(self) -> int:
+        return int(self.xyz.shape[0])
+
+    @property
+    def nt(self) -> int:
+        return int(self.tri.shape[0])
+
+
+# ---------------------------------------------------------------------------
+# sphere meshes
+# ---------------------------------------------------------------------------
+
+def _icosahedron():
+    t = (1.0 + math.sqrt(5.0)) / 2.0
+    v = np.array([
+        [-1, t, 0], [1, t, 0], [-1, -t, 0], [1, -t, 0],
+        [0, -1, t], [0, 1, t], [0, -1, -t], [0, 1, -t],
+        [t, 0, -1], [t, 0, 1], [-t, 0, -1], [-t, 0, 1]], dtype=np.float64)
+    f = np.array([
+        [0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11],
+        [1, 5, 9], [5, 11, 4], [11, 10, 2], [10, 7, 6], [7, 1, 8],
+        [3, 9, 4], [3, 4, 2], [3, 2, 6], [3, 6, 8], [3, 8, 9],
+        [4, 9, 5], [2, 4, 11], [6, 2, 10], [8, 6, 7], [9, 8, 1]], dtype=np.int64)
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    return v, f
+
+
+def _outward(v, f):
+    """Reorder faces so the right-hand normal points away from the centroid."""
+    c = v.mean(axis=0)
+    a, b, d = v[f[:, 0]], v[f[:, 1]], v[f[:, 2]]
+    n = np.cross(b - a, d - a)
+    flip = np.einsum("ij,ij->i", n, (a + b + d) / 3.0 - c) < 0
+    f = f.copy()
+    f[flip] = f[flip][:, [0, 2, 1]]
+    return f
+
+
+def icosphere(subdivisions: int, radius: float = 1.0, center=(0.0, 0.0, 0.0),
+              inside: int = 1, outside: int = 0) -> Mesh:
+    """Icosahedron refined ``subdivisions`` times, vertices projected to the sphere.
+
+    2 subdivisions give 162 vertices and 320 triangles.  The sphere separates
+    ``outside`` from ``inside``; triangles are oriented from the smaller label
+    to the larger one.
+    """
+    v, f = _icosahedron()
+    for _ in range(subdivisions):
+        cache = {}
+        verts = [p for p in v]
+
+        def mid(a, b):
+            key = (a, b) if a < b else (b, a)
+            if key not in cache:
+                p = verts[a] + verts[b]
+                verts.append(p / np.linalg.norm(p))
+                cache[key] = len(verts) - 1
+            return cache[key]
+
+        nf = []
+        for a, b, c in f:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            nf += [[a, ab, ca], [b, bc, ab], [c, ca, bc], [ab, bc, ca]]
+        v = np.array(verts)
+        f = np.array(nf, dtype=np.int64)
+    f = _outward(v, f)                      # outward = from inside to outside
+    lo, hi = min(inside, outside), max(inside, outside)
+    if lo == inside:                        # outward already points lo -> hi
+        tri = f
+    else:                                   # need inward normals
+        tri = f[:, [0, 2, 1]]
+    xyz = v * radius + np.asarray(center, dtype=np.float64)
+    label = np.tile(np.array([lo, hi], dtype=np.int32), (tri.shape[0], 1))
+    return Mesh(xyz=xyz, tri=tri.astype(np.int32), label=label, M=max(inside, outside),
+                meta={"kind": "icosphere", "subdivisions": subdivisions, "radius": radius})
+
+
+# ---------------------------------------------------------------------------
+# structured box skeletons (cube partitions)
+# ---------------------------------------------------------------------------
+
+def box_skeleton(nsub, cells, size=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0), ids=None) -> Mesh:
+    """Skeleton of a box split into ``nsub = (nx, ny, nz)`` sub-boxes.
+
+    Each sub-box is ``cells = (cx, cy, cz)`` grid cells wide; every skeleton
+    square is split along the diagonal joining its min-(u, v) corner to its
+    max-(u, v) corner.  ``ids[iz][iy][ix]`` gives the subdomain id of each
+    sub-box (default ``1 + ix + nx*iy + nx*ny*iz``); 0 is the exterior.
+    """
+    nsub = np.asarray(nsub, dtype=np.int64)
+    cells = np.asarray(cells, dtype=np.int64)
+    g = nsub * cells                       # grid cells per axis
+    size = np.asarray(size, dtype=np.float64)
+    origin = np.asarray(origin, dtype=np.float64)
+    if ids is None:
+        ids = np.zeros((nsub[2], nsub[1], nsub[0]), dtype=np.int64)
+        for iz in range(nsub[2]):
+            for iy in range(nsub[1]):
+                for ix in range(nsub[0]):
+                    ids[iz, iy, ix] = 1 + ix + nsub[0] * iy + nsub[0] * nsub[1] * iz
+    ids = np.asarray(ids, dtype=np.int64)
+
+    def sub_id(cx, cy, cz):
+        if cx < 0 or cy < 0 or cz < 0 or cx >= g[0] or cy >= g[1] or cz >= g[2]:
+            return 0
+        return int(ids[cz // cells[2], cy // cells[1], cx // cells[0]])
+
+    vid = {}
+    xyz = []
+
+    def vertex(p):
+        key = tuple(int(q) for q in p)
+        if key not in vid:
+            vid[key] = len(xyz)
+            xyz.append(origin + size * np.array(key, dtype=np.float64) / g)
+        return vid[key]
+
+    tris, labels = [], []
+    for a in range(3):
+        u, v = (a + 1) % 3, (a + 2) % 3     # e_u x e_v = e_a
+        for p in range(0, g[a] + 1, cells[a]):
+            for iu in range(g[u]):
+                for iv in range(g[v]):
+                    below = [0, 0, 0]
+                    above = [0, 0, 0]
+                    below[a], above[a] = p - 1, p
+                    below[u] = above[u] = iu
+                    below[v] = above[v] = iv
+                    lb, la = sub_id(*below), sub_id(*above)
+                    if lb == la:
+                        continue
+                    corner = []
+                    for du, dv in ((0, 0), (1, 0), (1, 1), (0, 1)):
+                        q = [0, 0, 0]
+                        q[a], q[u], q[v] = p, iu + du, iv + dv
+                        corner.append(vertex(q))
+                    t1 = [corner[0], corner[1], corner[2]]
+                    t2 = [corner[0], corner[2], corner[3]]
+                    lo, hi = min(lb, la), max(lb, la)
+                    # counter-clockwise in (u, v) gives normal +e_a (below -> above)
+                    flip = lo != lb
+                    for t in (t1, t2):
+                        tris.append([t[0], t[2], t[1]] if flip else t)
+                        labels.append([lo, hi])
+    return Mesh(xyz=np.array(xyz), tri=np.array(tris, dtype=np.int32),
+                label=np.array(labels, dtype=np.int32), M=int(ids.max()),
+                meta={"kind": "box_skeleton", "nsub": nsub.tolist(), "cells": cells.tolist()})
+
+
+def cube_partition(n: int, h_inv: int) -> Mesh:
+    """Unit cube split into n x n x n sub-cubes, structured skeleton at h = 1/h_inv."""
+    if h_inv % n:
+        raise ValueError("h_inv must be a multiple of n")
+    c = h_inv // n
+    return box_skeleton((n, n, n), (c, c, c))
+
+
+# ---------------------------------------------------------------------------
+# incidences
+# ---------------------------------------------------------------------------
+
+def fibonacci_directions(n: int) -> np.ndarray:
+    """n unit vectors on a Fibonacci sphere: z_j = 1-(2j+1)/n, phi_j = j*pi*(3-sqrt5)."""
+    j = np.arange(n, dtype=np.float64)
+    z = 1.0 - (2.0 * j + 1.0) / n
+    phi = j * math.pi * (3.0 - math.sqrt(5.0))
+    s = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    return np.stack([s * np.cos(phi), s * np.sin(phi), z], axis=1)
+
+
+def polarisations(d: np.ndarray):
+    """Unit vectors e_theta, e_phi orthogonal to each direction d (rows)."""
+    d = np.atleast_2d(d)
+    theta = np.arccos(np.clip(d[:, 2], -1.0, 1.0))
+    phi = np.arctan2(d[:, 1], d[:, 0])
+    et = np.stack([np.cos(theta) * np.cos(phi), np.cos(theta) * np.sin(phi), -np.sin(theta)], axis=1)
+    ep = np.stack([-np.sin(phi), np.cos(phi), np.zeros_like(phi)], axis=1)
+    return et, ep
+
+
+# ---------------------------------------------------------------------------
+# sphere clusters (convex hulls of Fibonacci points)
+# ---------------------------------------------------------------------------
+
+def fibonacci_sphere_mesh(npts: int, radius: float, center, sid: int) -> Mesh:
+    from scipy.spatial import ConvexHull
+    p = fibonacci_directions(npts)
+    hull = ConvexHull(p)
+    f = _outward(p, hull.simplices.astype(np.int64))
+    tri = f[:, [0, 2, 1]]                    # exterior 0 < sid: inward normals
+    xyz = p * radius + np.asarray(center, dtype=np.float64)
+    label = np.tile(np.array([0, sid], dtype=np.int32), (tri.shape[0], 1))
+    return Mesh(xyz=xyz, tri=tri.astype(np.int32), label=label, M=sid)
+
+
+def sphere_cluster(rng: SplitMix64, tmin=200, tmax=2000, rmin=0.3, rmax=1.0,
+                   emin=1.5, emax=4.0, nmin=1, nmax=8, gap=0.2):
+    """One cluster of 1..8 disjoint dielectric spheres (Fibonacci-hull meshes)."""
+    ns = rng.integer(nmin, nmax)
+    spheres = []
+    tries = 0
+    while len(spheres) < ns:
+        tries += 1
+        r = rng.uniform(rmin, rmax)
+        t_s = 2 * rng.integer(tmin // 2, tmax // 2)      # even triangle count
+        box = 1.5 * (ns ** (1.0 / 3.0)) + 1.0
+        c = np.array([rng.uniform(-box, box) for _ in range(3)])
+        ok = True
+        for (c2, r2, _) in spheres:
+            if np.linalg.norm(c - c2) < r + r2 + gap * min(r, r2):
+                ok = False
+                break
+        if ok or tries > 10000:
+            spheres.append((c, r, t_s))
+    eps = [rng.uniform(emin, emax) for _ in spheres]
+    xyz, tri, lab = [], [], []
+    off = 0
+    for sid, (c, r, t_s) in enumerate(spheres, start=1):
+        m = fibonacci_sphere_mesh(t_s // 2 + 2, r, c, sid)
+        xyz.append(m.xyz)
+        tri.append(m.tri + off)
+        lab.append(m.label)
+        off += m.nv
+    mesh = Mesh(xyz=np.concatenate(xyz), tri=np.concatenate(tri).astype(np.int32),
+                label=np.concatenate(lab).astype(np.int32), M=len(spheres),
+                meta={"kind": "sphere_cluster", "radii": [s[1] for s in spheres],
+                      "tri_per_sphere": [s[2] for s in spheres]})
+    return mesh, np.array([1.0] + eps)
+
+
+# ---------------------------------------------------------------------------
+# named workloads
+# ---------------------------------------------------------------------------
+
+def config_sphere(subdivisions: int = 2):
+    """Dielectric unit sphere (eps_r = 2, mu_r = 1) in vacuum, k0 = 1, x-polarised wave along +z."""
+    mesh = icosphere(subdivisions)
+    return dict(mesh=mesh, k0=1.0, eps_r=np.array([1.0, 2.0]), mu_r=np.array([1.0, 1.0]),
+                d=np.array([[0.0, 0.0, 1.0]]), p=np.array([[1.0, 0.0, 0.0]], dtype=np.complex128))
+
+
+def config_cube(n: int = 2, h_inv: int = 16, seed: int = 0, k0: float = 2 * math.pi):
+    """Unit cube split into n^3 sub-cubes, eps_r ~ U[1,4] (SplitMix64, sub-cube id order), mu_r = 1."""
+    mesh = cube_partition(n, h_inv)
+    rng = SplitMix64(seed)
+    eps = np.array([1.0] + [rng.uniform(1.0, 4.0) for _ in range(mesh.M)])
+    return dict(mesh=mesh, k0=k0, eps_r=eps, mu_r=np.ones(mesh.M + 1),
+                d=np.array([[0.0, 0.0, 1.0]]), p=np.array([[1.0, 0.0, 0.0]], dtype=np.complex128))
+
+
+def config_cube_multi_rhs(n: int = 4, h_inv: int = 24, ndir: int = 128, seed: int = 0):
+    cfg = config_cube(n, h_inv, seed)
+    d = fibonacci_directions(ndir)
+    et, ep = polarisations(d)
+    cfg["d"] = np.repeat(d, 2, axis=0)
+    p = np.empty((2 * ndir, 3))
+    p[0::2], p[1::2] = et, ep
+    cfg["p"] = p.astype(np.complex128)
+    return cfg
+
+
+def config_clusters(nclusters: int = 64, seed: int = 0, k0: float = 1.5, **kw):
+    rng = SplitMix64(seed)
+    out = []
+    for _ in range(nclusters):
+        mesh, eps = sphere_cluster(rng, **kw)
+        out.append(dict(mesh=mesh, k0=k0, eps_r=eps, mu_r=np.ones(mesh.M + 1),
+                        d=np.array([[0.0, 0.0, 1.0]]), p=np.array([[1.0, 0.0, 0.0]], dtype=np.complex128)))
+    return out
+
+
+def warm_start_samples(nsamples: int, nsub: int = 8, seed: int = 1):
+    """Random (direction, polarisation, eps_r per sub-cube) triples for the learned warm start."""
+    rng = SplitMix64(seed)
+    d = np.empty((nsamples, 3))
+    p = np.empty((nsamples, 3))
+    eps = np.empty((nsamples, nsub))
+    for s in range(nsamples):
+        z = rng.uniform(-1.0, 1.0)
+        ph = rng.uniform(0.0, 2 * math.pi)
+        r = math.sqrt(max(0.0, 1 - z * z))
+        d[s] = (r * math.cos(ph), r * math.sin(ph), z)
+        et, ep = polarisations(d[s:s + 1])
+        a = rng.uniform(0.0, math.pi)
+        p[s] = math.cos(a) * et[0] + math.sin(a) * ep[0]
+        eps[s] = [rng.uniform(1.0, 4.0) for _ in range(nsub)]
+    return d, p, eps
