@@ -1,0 +1,211 @@
+/*
+ * mtf.h -- C ABI of the MI355X library for the local multiple traces
+ * formulation (MTF) of heterogeneous Maxwell scattering.
+ *
+ * Problem statement followed by the calls (paper: "Local Multiple Traces
+ * Formulation for Heterogeneous Electromagnetic Scattering: Implementation and
+ * Preconditioning"):
+ *   - geometry: a conforming skeleton mesh, every triangle labelled with the
+ *     two subdomains it separates (Section 2.1, Section 3.2);
+ *   - materials eps_r,i, mu_r,i and wavenumbers k_i = k0 sqrt(eps_r mu_r)
+ *     (eq. relativeParameters);
+ *   - incident plane waves E_inc = p exp(i k0 d.x) (eq. incidentNumexp);
+ *   - the Galerkin system of Problem 2 (Section 3.2) on RWG_i spaces built by
+ *     Algorithm 1 (Section 4.2).
+ *
+ * Conventions shared by every call
+ *   Status codes: 0 = success; MTF_NOT_CONVERGED (1) = warning, outputs hold
+ *   the best iterate; negative = error, nothing was written to outputs.
+ *   mtf_last_error() returns a thread-local message for the last failing call.
+ *   No C++ exception crosses the ABI.  Arguments are validated on the host
+ *   before any device work, so invalid calls fail without touching the GPU.
+ *
+ *   Complex numbers are interleaved (re, im) pairs: complex128 = double[2],
+ *   complex64 = float[2].  Matrices are column-major.
+ *
+ *   Unknown ordering (length N = 2 sum_i E_i):
+ *       [u_0D, u_0N, u_1D, u_1N, ..., u_MD, u_MN]
+ *   each block of length E_i = dim RWG_i in the dof order of
+ *   mtf_get_dof_map.  u_iD holds the coefficients of gamma_D,i E, u_iN those
+ *   of rho_i gamma_N,i E (eq. boundary_conditions_traces).
+ *
+ *   Pointers named *_dev are device pointers on the problem's device (for
+ *   example torch CUDA/HIP tensor data); all other pointers are host memory.
+ *   The caller owns every buffer it passes; the library copies what it keeps.
+ *   Device work is ordered on the problem's stream; calls that return host
+ *   data synchronise that stream.  A problem must not be used from two threads
+ *   at once.
+ */
+#ifndef MTF_H
+#define MTF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MTF_OK                 0
+#define MTF_NOT_CONVERGED      1
+#define MTF_ERR_ARG           -1
+#define MTF_ERR_MESH          -2
+#define MTF_ERR_NONFINITE     -3
+#define MTF_ERR_HIP           -4
+#define MTF_ERR_OOM           -5
+#define MTF_ERR_STATE         -6
+#define MTF_ERR_UNSUPPORTED   -7
+
+#define MTF_FP64               0   /* complex128 quadrature, storage and matvec            */
+#define MTF_FP32_MIXED         1   /* complex64 separated pairs, FP64 Sauter-Schwab pairs  */
+
+#define MTF_BLOCK_T            0
+#define MTF_BLOCK_K            1
+
+#define MTF_PREC_NONE          0
+#define MTF_PREC_BLOCK_TINV    1   /* right block preconditioner from T_i^-1 (see mtf_solve) */
+
+typedef struct mtf_problem_s* mtf_problem;
+
+/* Message of the last failing call on this thread (never NULL). */
+const char* mtf_last_error(void);
+
+/* Library version. */
+int mtf_version(int* major, int* minor);
+
+/* Create a problem bound to HIP device `device` and HIP stream `stream`
+ * (a hipStream_t; NULL = the default stream).  *out receives an opaque handle
+ * owned by the library until mtf_problem_destroy. */
+int mtf_problem_create(mtf_problem* out, int device, void* stream);
+
+/* Free every device and host resource of the problem. NULL is accepted. */
+int mtf_problem_destroy(mtf_problem p);
+
+/* Skeleton mesh (Section 3.2 and the remark on meshing conventions).
+ *   xyz   [nv][3]  vertex coordinates
+ *   tri   [nt][3]  vertex ids in [0, nv); the right-hand normal
+ *                  (v1-v0)x(v2-v0) points from label[t][0] to label[t][1]
+ *   label [nt][2]  the two subdomains separated by the triangle, in [0, M],
+ *                  distinct; 0 is the unbounded exterior Omega_0.  The paper's
+ *                  convention is label[t][0] < label[t][1] (normal from min to
+ *                  max); the opposite order is accepted per triangle.
+ * Builds, on the host, Algorithm 1 for every subdomain (exterior normal n_i =
+ * mesh normal when i == label[t][0], else its opposite), the RWG_i spaces and
+ * the triangle-pair classes.  Fails with MTF_ERR_MESH when a Gamma_i is not a
+ * closed, consistently oriented 2-manifold (every Gamma_i edge shared by exactly
+ * two Gamma_i triangles traversing it in opposite directions), when a triangle
+ * is degenerate, or when a subdomain has no triangle.  Arrays are copied. */
+int mtf_set_mesh(mtf_problem p, int64_t nv, const double* xyz, int64_t nt,
+                 const int32_t* tri, const int32_t* label, int32_t M);
+
+/* Materials (eq. relativeParameters): eps_r[M+1], mu_r[M+1] > 0, k0 > 0.
+ * k_i = k0 sqrt(eps_r,i mu_r,i), rho_i = sqrt(eps_r,i / mu_r,i). */
+int mtf_set_materials(mtf_problem p, double k0, const double* eps_r, const double* mu_r);
+
+/* Sizes: N (total unknowns) and E[M+1] (dim RWG_i); either may be NULL. */
+int mtf_get_sizes(mtf_problem p, int64_t* N, int64_t* E);
+
+/* Dof map of RWG_i: for dof m, edge_vtx[2m..2m+1] = its edge's vertex ids
+ * (a < b) and plus_tri[m] = the skeleton triangle tau+ (the Gamma_i triangle
+ * whose oriented boundary runs from a to b; the RWG function is +l/(2A)(x-p) on
+ * tau+ and -l/(2A)(x-p) on tau-).  Either output may be NULL. */
+int mtf_get_dof_map(mtf_problem p, int32_t i, int32_t* edge_vtx, int32_t* plus_tri);
+
+typedef struct {
+    int32_t struct_size;     /* sizeof(mtf_assembly_opts)                            */
+    int32_t precision;       /* MTF_FP64 or MTF_FP32_MIXED                             */
+    int32_t singular_order;  /* Gauss-Legendre points per coordinate, 1..8 (default 4) */
+    int32_t flags;           /* reserved, 0                                            */
+} mtf_assembly_opts;
+
+/* Galerkin assembly of T_i and K_i for every subdomain (eq. boundary_operators,
+ * twisted pairing of eq. self_duality_identity) and of the transmission blocks
+ * (eq. trick_transmission).  Separated triangle pairs use the symmetric
+ * degree-4 six-point rule per triangle; pairs sharing a vertex, an edge or the
+ * whole triangle use Sauter-Schwab rules in FP64.  MTF_FP64 also keeps the
+ * FP64 blocks; MTF_FP32_MIXED assembles separated pairs in FP32 and stores
+ * complex64 blocks.  Both precisions may be assembled on one problem (call
+ * twice).  Asynchronous on the problem's stream. */
+int mtf_assemble(mtf_problem p, const mtf_assembly_opts* opts);
+
+/* Copy the dense E_i x E_i block `which` (MTF_BLOCK_T / MTF_BLOCK_K) of the
+ * given precision to host memory dst (complex128 [E_i][E_i], column-major,
+ * converted from complex64 for MTF_FP32_MIXED).  Synchronises. */
+int mtf_copy_block(mtf_problem p, int32_t i, int32_t which, int32_t precision, double* dst);
+
+/* Copy the transmission block G^ij (row block i, column block j, j in
+ * Lambda_i; real, dense E_i x E_j column-major) to host memory.  Zero if
+ * Gamma_ij is empty.  Synchronises. */
+int mtf_copy_transmission(mtf_problem p, int32_t i, int32_t j, double* dst);
+
+/* Right-hand sides for nrhs plane waves E_inc = p exp(i k0 d.x):
+ *   d[nrhs][3] real unit directions, p_re/p_im [nrhs][3] polarisations;
+ *   b_dev: complex128 [nrhs][ldb], ldb >= N (column r at b_dev + r*ldb).
+ * Only the Gamma_0 rows are nonzero:
+ *   b_0D[m] = 2 int E_inc . phi_m,  b_0N[m] = 2 rho_0 int (d x p) e^{i k0 d.x} . phi_m
+ * (Proposition 1 read with the Stratton-Chu formula as printed:
+ *  2 A_0 u_0 - u_0 = -2 u_inc, tested in the twisted pairing). */
+int mtf_rhs_plane_waves(mtf_problem p, int32_t nrhs, const double* d, const double* p_re,
+                        const double* p_im, void* b_dev, int64_t ldb);
+
+/* y = M x for nrhs complex128 vectors (x_dev, y_dev: [nrhs][ld], ld >= N),
+ * with M = 2A + X of Problem 2 applied from the stored blocks of `precision`. */
+int mtf_matvec(mtf_problem p, int32_t nrhs, const void* x_dev, void* y_dev, int64_t ld,
+               int32_t precision);
+
+typedef struct {
+    int32_t struct_size;      /* sizeof(mtf_solve_opts)                                     */
+    int32_t precision;        /* operator used by the inner iteration: MTF_FP64 or MTF_FP32_MIXED */
+    int32_t preconditioner;   /* MTF_PREC_NONE or MTF_PREC_BLOCK_TINV                        */
+    int32_t max_iters;        /* Arnoldi steps per GMRES cycle, 0 = 2000                     */
+    int32_t max_refinements;  /* outer FP64 refinement steps (MTF_FP32_MIXED), 0 = 10        */
+    int32_t reserved;
+    double  rtol;             /* ||b - M x||_2 <= rtol ||b||_2 with the FP64 operator        */
+    double  inner_rtol;       /* inner GMRES tolerance of a refinement step, 0 = 1e-3*... */
+    const void* x0_dev;       /* complex128 initial guess [nrhs][ld] or NULL (zero)          */
+} mtf_solve_opts;
+
+typedef struct {
+    int32_t iterations;       /* total Arnoldi steps                                   */
+    int32_t refinements;      /* FP64 residual evaluations after the first             */
+    int32_t converged;        /* 1 if rtol was met                                     */
+    int32_t reserved;
+    double  rel_residual;     /* final ||b - M x|| / ||b|| with the FP64 operator       */
+    double  t_precond_s;      /* time to build the preconditioner (first call only)    */
+    double  t_solve_s;        /* wall time of the solve                                */
+} mtf_solve_stats;
+
+/* Solve M x = b by GMRES (full, classical Gram-Schmidt applied twice, FP64
+ * Arnoldi) for each of nrhs right-hand sides (b_dev, x_dev: complex128
+ * [nrhs][ld]).  With MTF_PREC_BLOCK_TINV the iteration runs on M P, with P the
+ * block-diagonal right preconditioner
+ *     P_i = 1/2 [[0, -T_i^-1 / rho_i], [rho_i T_i^-1, 0]]
+ * (the inverse of the off-diagonal part of 2 A_i; the block shape of the
+ * block-OSRC preconditioner of Section 4.4 with the exact discrete T_i^-1),
+ * T_i^-1 computed once per problem on the GPU in complex64.  Right
+ * preconditioning leaves the judged residual ||b - M x|| unchanged.
+ * MTF_FP32_MIXED runs the inner GMRES on the complex64 operator and corrects
+ * with FP64 residuals (iterative refinement) until rtol holds for the FP64
+ * operator, which must have been assembled too.  stats[nrhs] may be NULL.
+ * Returns MTF_NOT_CONVERGED if some right-hand side missed rtol. */
+int mtf_solve(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int64_t ld,
+              const mtf_solve_opts* opts, mtf_solve_stats* stats);
+
+/* Far field E_inf(xhat) (E_sc ~ exp(i k0 |x|)/|x| E_inf) of nrhs solutions
+ * x_dev [nrhs][ld] in ndir unit directions dir[ndir][3] (host), written to host
+ * out: complex128 [nrhs][ndir][3].  From the Stratton-Chu formula in Omega_0:
+ *   E_inf = i k0 [xhat x F(u_0D) - xhat x (xhat x F(u_0N / rho_0))],
+ *   F(v) = 1/(4 pi) int_{Gamma_0} exp(-i k0 xhat.y) v(y) dy.  Synchronises. */
+int mtf_far_field(mtf_problem p, int32_t nrhs, const void* x_dev, int64_t ld, int32_t ndir,
+                  const double* dir, double* out);
+
+/* Statistics of the last mtf_assemble: pair counts by class
+ * (counts[0] separated, [1] vertex, [2] edge, [3] coincident, summed over
+ * subdomains, ordered pairs) and the device time of the assembly kernels in
+ * seconds (HIP events).  Synchronises. */
+int mtf_assembly_stats(mtf_problem p, int64_t* counts, double* seconds);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MTF_H */

@@ -1,0 +1,265 @@
+"""MI355X library for the local multiple traces formulation (MTF) of heterogeneous
+Maxwell scattering: thin Python binding over the C ABI of ``libmtf.so``.
+
+Every operation runs in the HIP library; this module only marshals arguments.
+Device buffers are torch tensors on a HIP device (complex128, contiguous, shape
+[nrhs, N] so that right-hand side r starts at r * N); host arrays are numpy.
+The library is built in-tree by ``paper_2502_10907_amd.build.build()``; importing
+this module without it raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmtf.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "mtf.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2502_10907_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+OK, NOT_CONVERGED = 0, 1
+ERR_NAMES = {-1: "ARG", -2: "MESH", -3: "NONFINITE", -4: "HIP", -5: "OOM", -6: "STATE", -7: "UNSUPPORTED"}
+FP64, FP32_MIXED = 0, 1
+BLOCK_T, BLOCK_K = 0, 1
+PREC_NONE, PREC_BLOCK_TINV = 0, 1
+
+
+class MTFError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"MTF_ERR_{ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class AssemblyOpts(C.Structure):
+    _fields_ = [("struct_size", C.c_int32), ("precision", C.c_int32), ("singular_order", C.c_int32),
+                ("flags", C.c_int32)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("struct_size", C.c_int32), ("precision", C.c_int32), ("preconditioner", C.c_int32),
+                ("max_iters", C.c_int32), ("max_refinements", C.c_int32), ("reserved", C.c_int32),
+                ("rtol", C.c_double), ("inner_rtol", C.c_double), ("x0_dev", C.c_void_p)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("refinements", C.c_int32), ("converged", C.c_int32),
+                ("reserved", C.c_int32), ("rel_residual", C.c_double), ("t_precond_s", C.c_double),
+                ("t_solve_s", C.c_double)]
+
+
+_P = C.c_void_p
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_lp = C.POINTER(C.c_int64)
+_SIGS = {
+    "mtf_last_error": (C.c_char_p, []),
+    "mtf_version": (C.c_int, [_ip, _ip]),
+    "mtf_problem_create": (C.c_int, [C.POINTER(_P), C.c_int, _P]),
+    "mtf_problem_destroy": (C.c_int, [_P]),
+    "mtf_set_mesh": (C.c_int, [_P, C.c_int64, _dp, C.c_int64, _ip, _ip, C.c_int32]),
+    "mtf_set_materials": (C.c_int, [_P, C.c_double, _dp, _dp]),
+    "mtf_get_sizes": (C.c_int, [_P, _lp, _lp]),
+    "mtf_get_dof_map": (C.c_int, [_P, C.c_int32, _ip, _ip]),
+    "mtf_assemble": (C.c_int, [_P, C.POINTER(AssemblyOpts)]),
+    "mtf_copy_block": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, _dp]),
+    "mtf_copy_transmission": (C.c_int, [_P, C.c_int32, C.c_int32, _dp]),
+    "mtf_rhs_plane_waves": (C.c_int, [_P, C.c_int32, _dp, _dp, _dp, _P, C.c_int64]),
+    "mtf_matvec": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.c_int32]),
+    "mtf_solve": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
+    "mtf_far_field": (C.c_int, [_P, C.c_int32, _P, C.c_int64, C.c_int32, _dp, _dp]),
+    "mtf_assembly_stats": (C.c_int, [_P, _lp, _dp]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def header_symbols() -> list[str]:
+    """Every function declared in include/mtf.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mtf_[a-z0-9_]+)\s*\(", txt)))
+
+
+def last_error() -> str:
+    return _lib.mtf_last_error().decode()
+
+
+def version() -> tuple[int, int]:
+    a, b = C.c_int32(), C.c_int32()
+    _check(_lib.mtf_version(C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def _check(code: int) -> int:
+    if code < 0:
+        raise MTFError(code, last_error())
+    return code
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(_ip)
+
+
+def _dev(t, n):
+    """Device pointer and leading dimension of a complex128 tensor of shape [nrhs, ld] (or [ld])."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError("device buffers must be complex128 torch tensors on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("device buffers must be contiguous")
+    t2 = t.view(1, -1) if t.dim() == 1 else t
+    if t2.dim() != 2 or t2.shape[1] < n:
+        raise ValueError(f"expected shape [nrhs, >= {n}]")
+    return C.c_void_p(t2.data_ptr()), t2.shape[0], t2.shape[1]
+
+
+@dataclass
+class Stats:
+    iterations: int
+    refinements: int
+    converged: bool
+    rel_residual: float
+    t_precond_s: float
+    t_solve_s: float
+
+
+class Problem:
+    """One MTF problem on one HIP device; every call is ordered on ``stream``
+    (default: torch's current stream of that device)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self._h = C.c_void_p()
+        _check(_lib.mtf_problem_create(C.byref(self._h), int(device), C.c_void_p(stream)))
+        self.device = device
+        self.N = 0
+        self.E = None
+        self.M = 0
+
+    def close(self):
+        if self._h:
+            _lib.mtf_problem_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- setup -------------------------------------------------------------
+    def set_mesh(self, xyz, tri, label, M: int):
+        xyz, px = _f64(xyz)
+        tri, pt = _i32(tri)
+        label, pl = _i32(label)
+        if xyz.ndim != 2 or xyz.shape[1] != 3 or tri.ndim != 2 or tri.shape[1] != 3 or label.shape != (tri.shape[0], 2):
+            raise ValueError("xyz [nv,3], tri [nt,3], label [nt,2] expected")
+        _check(_lib.mtf_set_mesh(self._h, xyz.shape[0], px, tri.shape[0], pt, pl, int(M)))
+        self.M = int(M)
+        N = C.c_int64()
+        E = np.zeros(self.M + 1, dtype=np.int64)
+        _check(_lib.mtf_get_sizes(self._h, C.byref(N), E.ctypes.data_as(_lp)))
+        self.N, self.E = int(N.value), E
+
+    def set_materials(self, k0: float, eps_r, mu_r):
+        eps_r, pe = _f64(eps_r)
+        mu_r, pm = _f64(mu_r)
+        if eps_r.shape != (self.M + 1,) or mu_r.shape != (self.M + 1,):
+            raise ValueError("eps_r and mu_r need M+1 entries")
+        _check(_lib.mtf_set_materials(self._h, float(k0), pe, pm))
+
+    def dof_map(self, i: int):
+        E = int(self.E[i])
+        ev = np.zeros((E, 2), dtype=np.int32)
+        pt = np.zeros(E, dtype=np.int32)
+        _check(_lib.mtf_get_dof_map(self._h, int(i), ev.ctypes.data_as(_ip), pt.ctypes.data_as(_ip)))
+        return ev, pt
+
+    # -- assembly ------------------------------------------------------------
+    def assemble(self, precision: int = FP64, singular_order: int = 4):
+        o = AssemblyOpts(C.sizeof(AssemblyOpts), int(precision), int(singular_order), 0)
+        _check(_lib.mtf_assemble(self._h, C.byref(o)))
+
+    def assembly_stats(self):
+        counts = np.zeros(4, dtype=np.int64)
+        sec = C.c_double()
+        _check(_lib.mtf_assembly_stats(self._h, counts.ctypes.data_as(_lp), C.byref(sec)))
+        return counts, sec.value
+
+    def copy_block(self, i: int, which: int, precision: int = FP64) -> np.ndarray:
+        E = int(self.E[i])
+        out = np.zeros(2 * E * E, dtype=np.float64)
+        _check(_lib.mtf_copy_block(self._h, int(i), int(which), int(precision), out.ctypes.data_as(_dp)))
+        return out.view(np.complex128).reshape(E, E, order="F")
+
+    def copy_transmission(self, i: int, j: int) -> np.ndarray:
+        out = np.zeros(int(self.E[i]) * int(self.E[j]), dtype=np.float64)
+        _check(_lib.mtf_copy_transmission(self._h, int(i), int(j), out.ctypes.data_as(_dp)))
+        return out.reshape(int(self.E[i]), int(self.E[j]), order="F")
+
+    # -- vectors -------------------------------------------------------------
+    def rhs_plane_waves(self, d, p, b):
+        d, pd = _f64(np.atleast_2d(d))
+        p = np.atleast_2d(np.asarray(p, dtype=np.complex128))
+        pr, ppr = _f64(p.real)
+        pi, ppi = _f64(p.imag)
+        ptr, nrhs, ld = _dev(b, self.N)
+        if d.shape != (nrhs, 3) or p.shape != (nrhs, 3):
+            raise ValueError("d and p need one row per right-hand side")
+        _check(_lib.mtf_rhs_plane_waves(self._h, nrhs, pd, ppr, ppi, ptr, ld))
+
+    def matvec(self, x, y, precision: int = FP64):
+        px, nrhs, ld = _dev(x, self.N)
+        py, nrhs2, ld2 = _dev(y, self.N)
+        if (nrhs, ld) != (nrhs2, ld2):
+            raise ValueError("x and y shapes differ")
+        _check(_lib.mtf_matvec(self._h, nrhs, px, py, ld, int(precision)))
+
+    def solve(self, b, x, rtol: float = 1e-6, precision: int = FP64, preconditioner: int = PREC_BLOCK_TINV,
+              max_iters: int = 0, max_refinements: int = 0, inner_rtol: float = 0.0, x0=None) -> list[Stats]:
+        pb, nrhs, ld = _dev(b, self.N)
+        px, nrhs2, ld2 = _dev(x, self.N)
+        if (nrhs, ld) != (nrhs2, ld2):
+            raise ValueError("b and x shapes differ")
+        x0p = None
+        if x0 is not None:
+            x0p, n3, ld3 = _dev(x0, self.N)
+            if (n3, ld3) != (nrhs, ld):
+                raise ValueError("x0 shape differs")
+        o = SolveOpts(C.sizeof(SolveOpts), int(precision), int(preconditioner), int(max_iters),
+                      int(max_refinements), 0, float(rtol), float(inner_rtol), x0p)
+        st = (SolveStats * nrhs)()
+        code = _check(_lib.mtf_solve(self._h, nrhs, pb, px, ld, C.byref(o), st))
+        self.last_status = code
+        return [Stats(s.iterations, s.refinements, bool(s.converged), s.rel_residual, s.t_precond_s, s.t_solve_s)
+                for s in st]
+
+    def far_field(self, x, dirs) -> np.ndarray:
+        px, nrhs, ld = _dev(x, self.N)
+        dirs, pd = _f64(np.atleast_2d(dirs))
+        out = np.zeros(nrhs * dirs.shape[0] * 6)
+        _check(_lib.mtf_far_field(self._h, nrhs, px, ld, dirs.shape[0], pd, out.ctypes.data_as(_dp)))
+        return out.view(np.complex128).reshape(nrhs, dirs.shape[0], 3)

@@ -1,0 +1,883 @@
+// C ABI of the MTF library: problem object, uploads, assembly and solver drivers.
+#include "../../include/mtf.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "quadrature.h"
+#include "skeleton.h"
+
+namespace {
+
+using namespace mtf;
+using cd = std::complex<double>;
+
+thread_local std::string g_err = "no error";
+
+struct HipError : std::runtime_error {
+    explicit HipError(const std::string& s) : std::runtime_error(s) {}
+};
+struct StateError : std::runtime_error {
+    explicit StateError(const std::string& s) : std::runtime_error(s) {}
+};
+struct OomError : std::runtime_error {
+    explicit OomError(const std::string& s) : std::runtime_error(s) {}
+};
+struct NonFiniteError : std::runtime_error {
+    explicit NonFiniteError(const std::string& s) : std::runtime_error(s) {}
+};
+
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess)                                                              \
+            throw HipError(std::string(#x) + ": " + hipGetErrorString(e_));                \
+    } while (0)
+
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { reset(); }
+    void reset() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void alloc(size_t count) {
+        if (count == n && p) return;
+        reset();
+        if (count == 0) return;
+        hipError_t e = hipMalloc((void**)&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            if (e == hipErrorOutOfMemory) throw OomError("device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+            throw HipError(std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        n = count;
+    }
+    void upload(const std::vector<T>& v, hipStream_t s) {
+        alloc(v.size());
+        if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+};
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        HIPCHK(hipGetDevice(&prev));
+        if (prev != dev) HIPCHK(hipSetDevice(dev));
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+constexpr int kTile = 16;     // triangles per side of a separated-pair tile
+constexpr int kRows = 256;    // rows per dense-matvec workgroup
+constexpr int kChunk = 256;   // columns per dense-matvec workgroup
+constexpr int kNblk = 32;     // partial sums of GMRES reductions
+
+struct GmresWork {
+    int64_t n = 0;
+    int maxit = 0;
+    DevBuf<double> V, tmp, tmp2, r, hpart, h, hsum, npart, y;
+    double* hh_host = nullptr;   // pinned: hsum (2*(maxit+1)) + npart (kNblk)
+    ~GmresWork() {
+        if (hh_host) (void)hipHostFree(hh_host);
+    }
+};
+
+}  // namespace
+
+struct mtf_problem_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+
+    bool has_mesh = false, has_mat = false;
+    Skeleton sk;
+    double k0 = 0;
+    std::vector<double> eps, mu, kw, rho;
+
+    std::vector<DomDesc> doms;
+    int64_t nrec = 0, ndof = 0, mat_entries = 0, part_entries = 0;
+    DevBuf<double> d_xyz;
+    DevBuf<int32_t> d_verts, d_tdof, d_other_rec, d_other_dom, d_rec_dom, d_dplus, d_dminus, d_dof_dom;
+    DevBuf<int8_t> d_tsign;
+    DevBuf<TriGeom> d_geom;
+    DevBuf<DomDesc> d_doms;
+    DevBuf<double> d_gval;
+    DevBuf<int64_t> d_gcol;
+    DevBuf<int4> d_tiles, d_mtiles;
+    int64_t ntiles = 0, nmtiles = 0;
+    DevBuf<SingPair> d_sing;
+    DevBuf<double> d_ss;
+    DevBuf<int32_t> d_ss_meta;   // off[4], cnt[4]
+    int ss_order = 0;
+
+    DevBuf<double> T64, K64;
+    DevBuf<float> T32, K32, Tinv;
+    bool have64 = false, have32 = false, have_tinv = false;
+    double t_precond = 0;
+    DevBuf<double> part;
+    DevBuf<double> scratch_dirs;
+    double t_assemble = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    GmresWork gw;
+
+    ~mtf_problem_s() {
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+    }
+};
+
+namespace {
+
+void sync(mtf_problem p) { HIPCHK(hipStreamSynchronize(p->stream)); }
+
+void upload_doms(mtf_problem p) {
+    for (size_t i = 0; i < p->doms.size(); ++i) {
+        p->doms[i].k = p->has_mat ? p->kw[i] : 0.0;
+        p->doms[i].rho = p->has_mat ? p->rho[i] : 1.0;
+    }
+    p->d_doms.upload(p->doms, p->stream);
+}
+
+void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, const int32_t* tri, const int32_t* label,
+                   int32_t M) {
+    Skeleton sk = build_skeleton(nv, xyz, nt, tri, label, M);
+    DeviceGuard g(p->device);
+    hipStream_t s = p->stream;
+    // record and dof tables concatenated over subdomains
+    std::vector<DomDesc> doms(M + 1);
+    int64_t rec = 0, dof = 0, mat = 0, part = 0;
+    for (int i = 0; i <= M; ++i) {
+        const Domain& d = sk.dom[i];
+        DomDesc& dd = doms[i];
+        std::memset(&dd, 0, sizeof(dd));
+        dd.rec0 = rec;
+        dd.dof0 = dof;
+        dd.mat0 = mat;
+        dd.off = sk.offset[i];
+        dd.part0 = part;
+        dd.T = d.T;
+        dd.E = d.E;
+        dd.nchunk = (d.E + kChunk - 1) / kChunk;
+        dd.rho = 1.0;
+        rec += d.T;
+        dof += d.E;
+        mat += (int64_t)d.E * d.E;
+        part += (int64_t)dd.nchunk * 2 * d.E;
+    }
+    std::vector<int32_t> verts(3 * rec), tdof(3 * rec), other_rec(rec), other_dom(rec), rec_dom(rec);
+    std::vector<int8_t> tsign(3 * rec);
+    std::vector<int32_t> dplus(2 * dof), dminus(2 * dof), dof_dom(dof);
+    for (int i = 0; i <= M; ++i) {
+        const Domain& d = sk.dom[i];
+        const int64_t r0 = doms[i].rec0;
+        for (int lt = 0; lt < d.T; ++lt) {
+            for (int a = 0; a < 3; ++a) {
+                verts[3 * (r0 + lt) + a] = d.verts[3 * lt + a];
+                tdof[3 * (r0 + lt) + a] = d.tri_dof[3 * lt + a];
+                tsign[3 * (r0 + lt) + a] = d.tri_sign[3 * lt + a];
+            }
+            other_dom[r0 + lt] = d.other[lt];
+            other_rec[r0 + lt] = (int32_t)(doms[d.other[lt]].rec0 + d.other_lt[lt]);
+            rec_dom[r0 + lt] = i;
+        }
+        const int64_t f0 = doms[i].dof0;
+        for (int m = 0; m < d.E; ++m) {
+            dplus[2 * (f0 + m)] = d.plus[2 * m];
+            dplus[2 * (f0 + m) + 1] = d.plus[2 * m + 1];
+            dminus[2 * (f0 + m)] = d.minus[2 * m];
+            dminus[2 * (f0 + m) + 1] = d.minus[2 * m + 1];
+            dof_dom[f0 + m] = i;
+        }
+    }
+    std::vector<int4> tiles, mtiles;
+    for (int i = 0; i <= M; ++i) {
+        const int T = sk.dom[i].T;
+        for (int x0 = 0; x0 < T; x0 += kTile)
+            for (int y0 = 0; y0 < T; y0 += kTile) tiles.push_back(make_int4(i, x0, y0, 0));
+        const int E = sk.dom[i].E;
+        for (int c = 0; c < doms[i].nchunk; ++c)
+            for (int r0 = 0; r0 < E; r0 += kRows) mtiles.push_back(make_int4(i, r0, c, 0));
+    }
+    std::vector<SingPair> sing(sk.singular.size());
+    for (size_t q = 0; q < sk.singular.size(); ++q) {
+        const auto& a = sk.singular[q];
+        SingPair& b = sing[q];
+        b.dom = a.domain; b.tx = a.tx; b.ty = a.ty; b.kind = a.kind;
+        for (int k = 0; k < 3; ++k) { b.px[k] = a.px[k]; b.py[k] = a.py[k]; }
+    }
+
+    p->d_xyz.upload(sk.xyz, s);
+    p->d_verts.upload(verts, s);
+    p->d_tdof.upload(tdof, s);
+    p->d_tsign.upload(tsign, s);
+    p->d_other_rec.upload(other_rec, s);
+    p->d_other_dom.upload(other_dom, s);
+    p->d_rec_dom.upload(rec_dom, s);
+    p->d_dplus.upload(dplus, s);
+    p->d_dminus.upload(dminus, s);
+    p->d_dof_dom.upload(dof_dom, s);
+    p->d_tiles.upload(tiles, s);
+    p->d_mtiles.upload(mtiles, s);
+    p->d_sing.upload(sing, s);
+    p->ntiles = (int64_t)tiles.size();
+    p->nmtiles = (int64_t)mtiles.size();
+    p->doms = doms;
+    p->nrec = rec;
+    p->ndof = dof;
+    p->mat_entries = mat;
+    p->part_entries = part;
+    p->d_geom.alloc(rec);
+    double bary[6][3], w[6];
+    triangle_rule6(bary, w);
+    launch_tri_setup_rule(p->d_xyz.p, p->d_verts.p, rec, &bary[0][0], w, p->d_geom.p, s);
+    p->has_mat = false;
+    upload_doms(p);
+    p->d_gval.alloc(9 * rec);
+    p->d_gcol.alloc(6 * rec);
+    launch_gram_local(p->d_doms.p, M + 1, rec, p->d_rec_dom.p, p->d_geom.p, p->d_other_rec.p, p->d_tsign.p,
+                      p->d_tdof.p, p->d_other_dom.p, p->d_gval.p, p->d_gcol.p, s);
+    p->part.alloc(2 * part);
+    HIPCHK(hipGetLastError());
+    sync(p);   // host vectors above go out of scope
+    p->sk = std::move(sk);
+    p->has_mesh = true;
+    p->have64 = p->have32 = p->have_tinv = false;
+    p->T64.reset(); p->K64.reset(); p->T32.reset(); p->K32.reset(); p->Tinv.reset();
+}
+
+void ensure_ss(mtf_problem p, int order) {
+    if (p->ss_order == order && p->d_ss.p) return;
+    std::vector<double> tab;
+    std::vector<int32_t> meta(8, 0);
+    for (int kind = 1; kind <= 3; ++kind) {
+        meta[kind] = (int32_t)(tab.size() / 5);
+        sauter_schwab_rule(kind, order, tab);
+        meta[4 + kind] = (int32_t)(tab.size() / 5) - meta[kind];
+    }
+    p->d_ss.upload(tab, p->stream);
+    p->d_ss_meta.upload(meta, p->stream);
+    sync(p);
+    p->ss_order = order;
+}
+
+void assemble_impl(mtf_problem p, const mtf_assembly_opts* o) {
+    if (!p->has_mesh || !p->has_mat) throw StateError("mtf_assemble needs mtf_set_mesh and mtf_set_materials first");
+    int prec = MTF_FP64, order = 4;
+    if (o) {
+        if (o->struct_size < (int)sizeof(mtf_assembly_opts)) throw ArgError("mtf_assembly_opts.struct_size too small");
+        prec = o->precision;
+        if (o->singular_order) order = o->singular_order;
+    }
+    if (prec != MTF_FP64 && prec != MTF_FP32_MIXED) throw ArgError("unknown precision");
+    if (order < 1 || order > 8) throw ArgError("singular_order must be in 1..8");
+    DeviceGuard g(p->device);
+    ensure_ss(p, order);
+    hipStream_t s = p->stream;
+    if (!p->ev0) { HIPCHK(hipEventCreate(&p->ev0)); HIPCHK(hipEventCreate(&p->ev1)); }
+    const int64_t n2 = 2 * p->mat_entries;
+    if (prec == MTF_FP64) { p->T64.alloc(n2); p->K64.alloc(n2); }
+    else { p->T32.alloc(n2); p->K32.alloc(n2); }
+    HIPCHK(hipEventRecord(p->ev0, s));
+    const int32_t* meta = p->d_ss_meta.p;
+    if (prec == MTF_FP64) {
+        launch_fill(p->T64.p, n2, 0.0, s);
+        launch_fill(p->K64.p, n2, 0.0, s);
+        launch_regular_f64(p->d_tiles.p, p->ntiles, p->d_doms.p, p->d_geom.p, p->d_verts.p, p->d_tdof.p, p->d_tsign.p,
+                           p->T64.p, p->K64.p, s);
+        launch_singular(p->d_sing.p, (int64_t)p->d_sing.n, p->d_doms.p, p->d_geom.p, p->d_xyz.p, p->d_verts.p,
+                        p->d_tdof.p, p->d_tsign.p, p->d_ss.p, meta, meta + 4, p->T64.p, p->K64.p, nullptr, nullptr, s);
+    } else {
+        launch_fill_f(p->T32.p, n2, 0.f, s);
+        launch_fill_f(p->K32.p, n2, 0.f, s);
+        launch_regular_f32(p->d_tiles.p, p->ntiles, p->d_doms.p, p->d_geom.p, p->d_verts.p, p->d_tdof.p, p->d_tsign.p,
+                           p->T32.p, p->K32.p, s);
+        launch_singular(p->d_sing.p, (int64_t)p->d_sing.n, p->d_doms.p, p->d_geom.p, p->d_xyz.p, p->d_verts.p,
+                        p->d_tdof.p, p->d_tsign.p, p->d_ss.p, meta, meta + 4, nullptr, nullptr, p->T32.p, p->K32.p, s);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(p->ev1, s));
+    if (prec == MTF_FP64) p->have64 = true; else p->have32 = true;
+    p->have_tinv = false;
+}
+
+void check_prec_available(mtf_problem p, int prec) {
+    if (prec == MTF_FP64 && !p->have64) throw StateError("FP64 blocks not assembled");
+    if (prec == MTF_FP32_MIXED && !p->have32) throw StateError("FP32 blocks not assembled");
+    if (prec != MTF_FP64 && prec != MTF_FP32_MIXED) throw ArgError("unknown precision");
+}
+
+// y = M x for one vector (device pointers, complex128 length N)
+void matvec1(mtf_problem p, const double* x, double* y, int prec) {
+    hipStream_t s = p->stream;
+    if (prec == MTF_FP64)
+        launch_matvec_dense_f64(p->d_doms.p, p->d_mtiles.p, p->nmtiles, p->T64.p, p->K64.p, x, p->part.p, s);
+    else
+        launch_matvec_dense_f32(p->d_doms.p, p->d_mtiles.p, p->nmtiles, p->T32.p, p->K32.p, x, p->part.p, s);
+    launch_matvec_finish(p->d_doms.p, (int)p->doms.size(), p->d_dof_dom.p, p->ndof, p->d_dplus.p, p->d_dminus.p,
+                         p->d_gval.p, p->d_gcol.p, p->part.p, x, y, s);
+}
+
+void precond1(mtf_problem p, const double* x, double* z) {
+    launch_precond_apply(p->d_doms.p, p->d_mtiles.p, p->nmtiles, p->Tinv.p, x, p->part.p, p->stream);
+    launch_precond_finish(p->d_doms.p, (int)p->doms.size(), p->d_dof_dom.p, p->ndof, p->part.p, z, p->stream);
+}
+
+// X = inv(A) by recursive 2 x 2 Schur-complement splitting; A (complex64, ld lda) is overwritten.
+void inv_rec(float* A, int64_t lda, float* X, int64_t ldx, int n, float* work, int* info, hipStream_t s) {
+    if (n <= 64) {
+        HIPCHK(hipMemcpy2DAsync(X, ldx * 8, A, lda * 8, (size_t)n * 8, n, hipMemcpyDeviceToDevice, s));
+        launch_cinv_small_f32(X, ldx, n, info, s);
+        return;
+    }
+    int n1 = ((n / 2 + 63) / 64) * 64;
+    if (n1 >= n) n1 = n - 64;
+    const int n2 = n - n1;
+    float* A11 = A;
+    float* A21 = A + 2 * (int64_t)n1;
+    float* A12 = A + 2 * (int64_t)n1 * lda;
+    float* A22 = A + 2 * ((int64_t)n1 + (int64_t)n1 * lda);
+    float* X11 = X;
+    float* X21 = X + 2 * (int64_t)n1;
+    float* X12 = X + 2 * (int64_t)n1 * ldx;
+    float* X22 = X + 2 * ((int64_t)n1 + (int64_t)n1 * ldx);
+    float* W = work;                          // n1 x n2
+    float* V = W + 2 * (int64_t)n1 * n2;      // n2 x n1
+    float* next = V + 2 * (int64_t)n2 * n1;
+    inv_rec(A11, lda, X11, ldx, n1, next, info, s);
+    launch_cgemm_f32(n1, n2, n1, 1.f, 0.f, X11, ldx, A12, lda, 0.f, nullptr, 0, W, n1, s);
+    launch_cgemm_f32(n2, n2, n1, -1.f, 0.f, A21, lda, W, n1, 1.f, A22, lda, A22, lda, s);
+    inv_rec(A22, lda, X22, ldx, n2, next, info, s);
+    launch_cgemm_f32(n1, n2, n2, -1.f, 0.f, W, n1, X22, ldx, 0.f, nullptr, 0, X12, ldx, s);
+    launch_cgemm_f32(n2, n1, n1, 1.f, 0.f, A21, lda, X11, ldx, 0.f, nullptr, 0, V, n2, s);
+    launch_cgemm_f32(n2, n1, n2, -1.f, 0.f, X22, ldx, V, n2, 0.f, nullptr, 0, X21, ldx, s);
+    launch_cgemm_f32(n1, n1, n2, -1.f, 0.f, X12, ldx, V, n2, 1.f, X11, ldx, X11, ldx, s);
+}
+
+void build_tinv(mtf_problem p) {
+    if (p->have_tinv) return;
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = p->stream;
+    p->Tinv.alloc(2 * p->mat_entries);
+    int64_t emax = 0;
+    for (auto& d : p->doms) emax = std::max<int64_t>(emax, d.E);
+    DevBuf<float> A, work;
+    DevBuf<int> info;
+    A.alloc(2 * emax * emax);
+    work.alloc(2 * emax * emax + 4096);
+    info.alloc(2);
+    HIPCHK(hipMemsetAsync(info.p, 0, 2 * sizeof(int), s));
+    for (auto& d : p->doms) {
+        const int64_t ne = 2 * (int64_t)d.E * d.E;
+        if (p->have32) HIPCHK(hipMemcpyAsync(A.p, p->T32.p + 2 * d.mat0, ne * sizeof(float), hipMemcpyDeviceToDevice, s));
+        else launch_copy_block_f64_to_f32(p->T64.p + 2 * d.mat0, A.p, ne, s);
+        inv_rec(A.p, d.E, p->Tinv.p + 2 * d.mat0, d.E, d.E, work.p, info.p, s);
+    }
+    launch_nonfinite_check(p->Tinv.p, 2 * p->mat_entries, info.p + 1, s);
+    HIPCHK(hipGetLastError());
+    int h[2];
+    HIPCHK(hipMemcpyAsync(h, info.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    sync(p);
+    if (h[0] || h[1]) throw NonFiniteError("block preconditioner: singular pivot or non-finite inverse of T_i");
+    p->have_tinv = true;
+    p->t_precond = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+void gmres_alloc(mtf_problem p, int maxit) {
+    GmresWork& w = p->gw;
+    const int64_t n = p->sk.N;
+    if (w.n == n && w.maxit >= maxit) return;
+    w.n = n;
+    w.maxit = maxit;
+    w.V.alloc(2 * n * (int64_t)(maxit + 1));
+    w.tmp.alloc(2 * n);
+    w.tmp2.alloc(2 * n);
+    w.r.alloc(2 * n);
+    w.hpart.alloc(2 * (int64_t)(maxit + 1) * kNblk);
+    w.h.alloc(2 * (maxit + 1));
+    w.hsum.alloc(2 * (maxit + 1) + kNblk);
+    w.npart.alloc(kNblk);
+    w.y.alloc(2 * (maxit + 1));
+    if (w.hh_host) (void)hipHostFree(w.hh_host);
+    w.hh_host = nullptr;
+    HIPCHK(hipHostMalloc((void**)&w.hh_host, (2 * (maxit + 1) + kNblk) * sizeof(double), hipHostMallocDefault));
+}
+
+double norm_dev(mtf_problem p, const double* v) {
+    GmresWork& w = p->gw;
+    launch_norm2(v, w.n, w.npart.p, kNblk, p->stream);
+    HIPCHK(hipMemcpyAsync(w.hh_host, w.npart.p, kNblk * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    sync(p);
+    double s = 0;
+    for (int k = 0; k < kNblk; ++k) s += w.hh_host[k];
+    return std::sqrt(s);
+}
+
+// One GMRES cycle on A = M_prec (P) for right-hand side r (device), starting from zero; adds the
+// correction to x.  Returns the number of Arnoldi steps; *est = final recurrence residual / ||r||.
+int gmres_cycle(mtf_problem p, const double* r, double* x, int prec, bool use_pc, double tol, int maxit, double* est) {
+    GmresWork& w = p->gw;
+    hipStream_t s = p->stream;
+    const int64_t n = w.n;
+    double* V = w.V.p;
+    auto Vc = [&](int j) { return V + 2 * n * (int64_t)j; };
+    const double beta = norm_dev(p, r);
+    *est = 0.0;
+    if (beta == 0.0) return 0;
+    HIPCHK(hipMemcpyAsync(Vc(0), r, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_axpby(Vc(0), Vc(0), n, 0.0, 0.0, 1.0 / beta, s);
+    std::vector<cd> H((size_t)(maxit + 1) * maxit, cd(0));
+    std::vector<double> cs(maxit, 0.0);
+    std::vector<cd> sn(maxit, cd(0)), gvec(maxit + 1, cd(0));
+    gvec[0] = beta;
+    int it = 0;
+    double resid = beta;
+    for (int j = 0; j < maxit; ++j) {
+        const double* src = Vc(j);
+        if (use_pc) { precond1(p, src, w.tmp.p); src = w.tmp.p; }
+        double* wv = Vc(j + 1);
+        matvec1(p, src, wv, prec);
+        const int nv = j + 1;
+        for (int pass = 0; pass < 2; ++pass) {
+            launch_multidot(V, n, nv, wv, n, w.hpart.p, kNblk, s);
+            launch_reduce_h(w.hpart.p, nv, kNblk, w.h.p, w.hsum.p, pass, s);
+            launch_update(V, n, nv, w.h.p, wv, n, s);
+        }
+        launch_norm2(wv, n, w.hsum.p + 2 * (maxit + 1), kNblk, s);
+        HIPCHK(hipMemcpyAsync(w.hh_host, w.hsum.p, 2 * nv * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(w.hh_host + 2 * (maxit + 1), w.hsum.p + 2 * (maxit + 1), kNblk * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+        launch_scale_dev(wv, wv, n, w.hsum.p + 2 * (maxit + 1), kNblk, s);
+        sync(p);
+        double hn2 = 0;
+        for (int k = 0; k < kNblk; ++k) hn2 += w.hh_host[2 * (maxit + 1) + k];
+        const double hn = std::sqrt(hn2);
+        cd* Hc = &H[(size_t)j * (maxit + 1)];
+        for (int i = 0; i < nv; ++i) Hc[i] = cd(w.hh_host[2 * i], w.hh_host[2 * i + 1]);
+        Hc[j + 1] = hn;
+        for (int i = 0; i < j; ++i) {
+            const cd t = cs[i] * Hc[i] + sn[i] * Hc[i + 1];
+            Hc[i + 1] = -std::conj(sn[i]) * Hc[i] + cs[i] * Hc[i + 1];
+            Hc[i] = t;
+        }
+        const cd a = Hc[j];
+        const double c = hn;
+        const double den = std::sqrt(std::norm(a) + c * c);
+        if (std::abs(a) == 0.0) { cs[j] = 0.0; sn[j] = 1.0; }
+        else { cs[j] = std::abs(a) / den; sn[j] = (a / std::abs(a)) * c / den; }
+        Hc[j] = cs[j] * a + sn[j] * c;
+        Hc[j + 1] = 0.0;
+        gvec[j + 1] = -std::conj(sn[j]) * gvec[j];
+        gvec[j] = cs[j] * gvec[j];
+        it = j + 1;
+        resid = std::abs(gvec[j + 1]);
+        if (!std::isfinite(resid)) throw NonFiniteError("GMRES produced a non-finite residual");
+        if (resid <= tol * beta || hn == 0.0) break;
+    }
+    // back substitution
+    std::vector<cd> yv(it);
+    for (int i = it - 1; i >= 0; --i) {
+        cd acc = gvec[i];
+        for (int k = i + 1; k < it; ++k) acc -= H[(size_t)k * (maxit + 1) + i] * yv[k];
+        yv[i] = acc / H[(size_t)i * (maxit + 1) + i];
+    }
+    std::vector<double> yh(2 * it);
+    for (int i = 0; i < it; ++i) { yh[2 * i] = yv[i].real(); yh[2 * i + 1] = yv[i].imag(); }
+    HIPCHK(hipMemcpyAsync(w.y.p, yh.data(), yh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    if (use_pc) {
+        launch_fill(w.tmp2.p, 2 * n, 0.0, s);
+        launch_combine(w.tmp2.p, V, n, it, w.y.p, n, s);
+        precond1(p, w.tmp2.p, w.tmp.p);
+        launch_axpby(x, w.tmp.p, n, 1.0, 0.0, 1.0, s);
+    } else {
+        launch_combine(x, V, n, it, w.y.p, n, s);
+    }
+    sync(p);
+    *est = resid / beta;
+    return it;
+}
+
+int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int64_t ld, const mtf_solve_opts* o,
+               mtf_solve_stats* stats) {
+    if (!p->has_mesh || !p->has_mat) throw StateError("mtf_solve before mesh/materials");
+    if (nrhs < 1 || !b_dev || !x_dev || ld < p->sk.N) throw ArgError("mtf_solve: bad nrhs, pointers or ld");
+    mtf_solve_opts opts;
+    std::memset(&opts, 0, sizeof(opts));
+    opts.struct_size = sizeof(opts);
+    opts.rtol = 1e-6;
+    if (o) {
+        if (o->struct_size < (int)sizeof(mtf_solve_opts)) throw ArgError("mtf_solve_opts.struct_size too small");
+        opts = *o;
+    }
+    if (!(opts.rtol > 0.0) || !(opts.rtol < 1.0)) throw ArgError("rtol must be in (0, 1)");
+    if (opts.max_iters < 0 || opts.max_refinements < 0) throw ArgError("negative iteration limits");
+    const int maxit = opts.max_iters ? opts.max_iters : 2000;
+    const int maxref = opts.max_refinements ? opts.max_refinements : 10;
+    const int prec = opts.precision;
+    check_prec_available(p, prec);
+    if (!p->have64) throw StateError("mtf_solve checks residuals with the FP64 operator: assemble MTF_FP64 first");
+    if (opts.preconditioner != MTF_PREC_NONE && opts.preconditioner != MTF_PREC_BLOCK_TINV)
+        throw ArgError("unknown preconditioner");
+    DeviceGuard g(p->device);
+    const bool use_pc = opts.preconditioner == MTF_PREC_BLOCK_TINV;
+    double t_pc = 0;
+    if (use_pc && !p->have_tinv) { build_tinv(p); t_pc = p->t_precond; }
+    gmres_alloc(p, maxit);
+    GmresWork& w = p->gw;
+    hipStream_t s = p->stream;
+    const int64_t n = p->sk.N;
+    int status = MTF_OK;
+    for (int rhs = 0; rhs < nrhs; ++rhs) {
+        auto t0 = std::chrono::steady_clock::now();
+        const double* b = static_cast<const double*>(b_dev) + 2 * ld * (int64_t)rhs;
+        double* x = static_cast<double*>(x_dev) + 2 * ld * (int64_t)rhs;
+        if (opts.x0_dev) HIPCHK(hipMemcpyAsync(x, static_cast<const double*>(opts.x0_dev) + 2 * ld * (int64_t)rhs,
+                                               2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        else launch_fill(x, 2 * n, 0.0, s);
+        const double bn = norm_dev(p, b);
+        int iters = 0, refin = 0;
+        double rel = 1.0;
+        bool conv = false;
+        if (bn == 0.0) { conv = true; rel = 0.0; }
+        for (int outer = 0; !conv && outer <= maxref; ++outer) {
+            // true residual with the FP64 operator
+            matvec1(p, x, w.r.p, MTF_FP64);
+            launch_axpby(w.r.p, b, n, 1.0, 0.0, -1.0, s);   // r = b - M x
+            const double rn = norm_dev(p, w.r.p);
+            rel = rn / bn;
+            if (outer > 0) ++refin;
+            if (rel <= opts.rtol) { conv = true; break; }
+            if (outer == maxref || iters >= maxit * (maxref + 1)) break;
+            double tol = opts.rtol * bn / rn;
+            if (prec == MTF_FP32_MIXED) tol = std::max(tol, opts.inner_rtol > 0 ? opts.inner_rtol : 1e-6);
+            else if (opts.inner_rtol > 0) tol = std::max(tol, opts.inner_rtol);
+            double est = 0;
+            iters += gmres_cycle(p, w.r.p, x, prec, use_pc, 0.9 * tol, maxit, &est);
+        }
+        if (stats) {
+            stats[rhs].iterations = iters;
+            stats[rhs].refinements = refin;
+            stats[rhs].converged = conv ? 1 : 0;
+            stats[rhs].rel_residual = rel;
+            stats[rhs].t_precond_s = rhs == 0 ? t_pc : 0.0;
+            stats[rhs].t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        if (!conv) status = MTF_NOT_CONVERGED;
+    }
+    return status;
+}
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+template <typename F>
+int guarded(F&& f) {
+    try {
+        return f();
+    } catch (const MeshError& e) {
+        return fail(MTF_ERR_MESH, e.what());
+    } catch (const ArgError& e) {
+        return fail(MTF_ERR_ARG, e.what());
+    } catch (const StateError& e) {
+        return fail(MTF_ERR_STATE, e.what());
+    } catch (const OomError& e) {
+        return fail(MTF_ERR_OOM, e.what());
+    } catch (const NonFiniteError& e) {
+        return fail(MTF_ERR_NONFINITE, e.what());
+    } catch (const HipError& e) {
+        return fail(MTF_ERR_HIP, e.what());
+    } catch (const std::bad_alloc&) {
+        return fail(MTF_ERR_OOM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(MTF_ERR_ARG, e.what());
+    } catch (...) {
+        return fail(MTF_ERR_ARG, "unknown error");
+    }
+}
+
+bool finite_all(const double* a, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mtf_last_error(void) { return g_err.c_str(); }
+
+int mtf_version(int* major, int* minor) {
+    if (major) *major = 0;
+    if (minor) *minor = 1;
+    return MTF_OK;
+}
+
+int mtf_problem_create(mtf_problem* out, int device, void* stream) {
+    return guarded([&] {
+        if (!out) throw ArgError("out is NULL");
+        *out = nullptr;
+        int n = 0;
+        HIPCHK(hipGetDeviceCount(&n));
+        if (device < 0 || device >= n) throw ArgError("device index out of range");
+        auto p = std::make_unique<mtf_problem_s>();
+        p->device = device;
+        p->stream = static_cast<hipStream_t>(stream);
+        *out = p.release();
+        return MTF_OK;
+    });
+}
+
+int mtf_problem_destroy(mtf_problem p) {
+    if (!p) return MTF_OK;
+    return guarded([&] {
+        {
+            DeviceGuard g(p->device);
+            (void)hipStreamSynchronize(p->stream);
+            delete p;
+        }
+        return MTF_OK;
+    });
+}
+
+int mtf_set_mesh(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, const int32_t* tri, const int32_t* label,
+                 int32_t M) {
+    return guarded([&] {
+        if (!p) throw ArgError("problem is NULL");
+        set_mesh_impl(p, nv, xyz, nt, tri, label, M);
+        return MTF_OK;
+    });
+}
+
+int mtf_set_materials(mtf_problem p, double k0, const double* eps_r, const double* mu_r) {
+    return guarded([&] {
+        if (!p) throw ArgError("problem is NULL");
+        if (!p->has_mesh) throw StateError("mtf_set_materials before mtf_set_mesh");
+        if (!eps_r || !mu_r) throw ArgError("eps_r / mu_r is NULL");
+        if (!(k0 > 0.0) || !std::isfinite(k0)) throw ArgError("k0 must be positive and finite");
+        const int M = p->sk.M;
+        for (int i = 0; i <= M; ++i)
+            if (!(eps_r[i] > 0.0) || !(mu_r[i] > 0.0) || !std::isfinite(eps_r[i]) || !std::isfinite(mu_r[i]))
+                throw ArgError("eps_r and mu_r must be positive and finite");
+        DeviceGuard g(p->device);
+        p->k0 = k0;
+        p->eps.assign(eps_r, eps_r + M + 1);
+        p->mu.assign(mu_r, mu_r + M + 1);
+        p->kw.resize(M + 1);
+        p->rho.resize(M + 1);
+        for (int i = 0; i <= M; ++i) {
+            p->kw[i] = k0 * std::sqrt(eps_r[i] * mu_r[i]);
+            p->rho[i] = std::sqrt(eps_r[i] / mu_r[i]);
+        }
+        p->has_mat = true;
+        upload_doms(p);
+        sync(p);
+        p->have64 = p->have32 = p->have_tinv = false;
+        return MTF_OK;
+    });
+}
+
+int mtf_get_sizes(mtf_problem p, int64_t* N, int64_t* E) {
+    return guarded([&] {
+        if (!p) throw ArgError("problem is NULL");
+        if (!p->has_mesh) throw StateError("no mesh");
+        if (N) *N = p->sk.N;
+        if (E)
+            for (int i = 0; i <= p->sk.M; ++i) E[i] = p->sk.dom[i].E;
+        return MTF_OK;
+    });
+}
+
+int mtf_get_dof_map(mtf_problem p, int32_t i, int32_t* edge_vtx, int32_t* plus_tri) {
+    return guarded([&] {
+        if (!p) throw ArgError("problem is NULL");
+        if (!p->has_mesh) throw StateError("no mesh");
+        if (i < 0 || i > p->sk.M) throw ArgError("subdomain index out of range");
+        const Domain& d = p->sk.dom[i];
+        if (edge_vtx) std::memcpy(edge_vtx, d.edge_vtx.data(), 2 * d.E * sizeof(int32_t));
+        if (plus_tri)
+            for (int m = 0; m < d.E; ++m) plus_tri[m] = d.tri[d.plus[2 * m]];
+        return MTF_OK;
+    });
+}
+
+int mtf_assemble(mtf_problem p, const mtf_assembly_opts* opts) {
+    return guarded([&] {
+        if (!p) throw ArgError("problem is NULL");
+        assemble_impl(p, opts);
+        return MTF_OK;
+    });
+}
+
+int mtf_copy_block(mtf_problem p, int32_t i, int32_t which, int32_t precision, double* dst) {
+    return guarded([&] {
+        if (!p || !dst) throw ArgError("NULL argument");
+        if (!p->has_mesh) throw StateError("no mesh");
+        if (i < 0 || i > p->sk.M) throw ArgError("subdomain index out of range");
+        if (which != MTF_BLOCK_T && which != MTF_BLOCK_K) throw ArgError("which must be MTF_BLOCK_T or MTF_BLOCK_K");
+        check_prec_available(p, precision);
+        DeviceGuard g(p->device);
+        const DomDesc& d = p->doms[i];
+        const int64_t ne = 2 * (int64_t)d.E * d.E;
+        if (precision == MTF_FP64) {
+            const double* src = (which == MTF_BLOCK_T ? p->T64.p : p->K64.p) + 2 * d.mat0;
+            HIPCHK(hipMemcpyAsync(dst, src, ne * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+            sync(p);
+        } else {
+            std::vector<float> tmp(ne);
+            const float* src = (which == MTF_BLOCK_T ? p->T32.p : p->K32.p) + 2 * d.mat0;
+            HIPCHK(hipMemcpyAsync(tmp.data(), src, ne * sizeof(float), hipMemcpyDeviceToHost, p->stream));
+            sync(p);
+            for (int64_t e = 0; e < ne; ++e) dst[e] = tmp[e];
+        }
+        return MTF_OK;
+    });
+}
+
+int mtf_copy_transmission(mtf_problem p, int32_t i, int32_t j, double* dst) {
+    return guarded([&] {
+        if (!p || !dst) throw ArgError("NULL argument");
+        if (!p->has_mesh) throw StateError("no mesh");
+        const int M = p->sk.M;
+        if (i < 0 || i > M || j < 0 || j > M) throw ArgError("subdomain index out of range");
+        DeviceGuard g(p->device);
+        const DomDesc& di = p->doms[i];
+        const DomDesc& dj = p->doms[j];
+        std::vector<double> gval(9 * (size_t)di.T);
+        std::vector<int64_t> gcol(6 * (size_t)di.T);
+        HIPCHK(hipMemcpyAsync(gval.data(), p->d_gval.p + 9 * di.rec0, gval.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+        HIPCHK(hipMemcpyAsync(gcol.data(), p->d_gcol.p + 6 * di.rec0, gcol.size() * sizeof(int64_t), hipMemcpyDeviceToHost, p->stream));
+        sync(p);
+        std::memset(dst, 0, sizeof(double) * (size_t)di.E * dj.E);
+        const Domain& d = p->sk.dom[i];
+        for (int lt = 0; lt < d.T; ++lt) {
+            if (d.other[lt] != j) continue;
+            for (int a = 0; a < 3; ++a) {
+                const int m = d.tri_dof[3 * lt + a];
+                for (int c = 0; c < 3; ++c) {
+                    const int64_t col = gcol[6 * lt + c] - dj.off;
+                    dst[m + col * di.E] += gval[9 * lt + 3 * a + c];
+                }
+            }
+        }
+        return MTF_OK;
+    });
+}
+
+int mtf_rhs_plane_waves(mtf_problem p, int32_t nrhs, const double* d, const double* p_re, const double* p_im,
+                        void* b_dev, int64_t ldb) {
+    return guarded([&] {
+        if (!p) throw ArgError("problem is NULL");
+        if (!p->has_mesh || !p->has_mat) throw StateError("mtf_rhs_plane_waves before mesh/materials");
+        if (nrhs < 1 || !d || !p_re || !p_im || !b_dev || ldb < p->sk.N) throw ArgError("bad arguments");
+        if (!finite_all(d, 3 * nrhs) || !finite_all(p_re, 3 * nrhs) || !finite_all(p_im, 3 * nrhs))
+            throw ArgError("non-finite direction or polarisation");
+        for (int r = 0; r < nrhs; ++r) {
+            const double nn = d[3 * r] * d[3 * r] + d[3 * r + 1] * d[3 * r + 1] + d[3 * r + 2] * d[3 * r + 2];
+            if (std::fabs(nn - 1.0) > 1e-9) throw ArgError("directions must be unit vectors");
+        }
+        DeviceGuard g(p->device);
+        std::vector<double> host(3 * nrhs + 6 * nrhs);
+        std::memcpy(host.data(), d, 3 * nrhs * sizeof(double));
+        for (int r = 0; r < nrhs; ++r)
+            for (int k = 0; k < 3; ++k) {
+                host[3 * nrhs + 6 * r + 2 * k] = p_re[3 * r + k];
+                host[3 * nrhs + 6 * r + 2 * k + 1] = p_im[3 * r + k];
+            }
+        DevBuf<double> buf;
+        buf.upload(host, p->stream);
+        double* b = static_cast<double*>(b_dev);
+        launch_fill(b, 2 * ldb * (int64_t)nrhs, 0.0, p->stream);
+        launch_rhs(&p->doms[0], p->d_geom.p, p->d_dplus.p, p->d_dminus.p, p->doms[0].E, p->k0, p->rho[0], nrhs, buf.p,
+                   buf.p + 3 * nrhs, b, ldb, p->stream);
+        HIPCHK(hipGetLastError());
+        sync(p);
+        return MTF_OK;
+    });
+}
+
+int mtf_matvec(mtf_problem p, int32_t nrhs, const void* x_dev, void* y_dev, int64_t ld, int32_t precision) {
+    return guarded([&] {
+        if (!p) throw ArgError("problem is NULL");
+        if (!p->has_mesh || !p->has_mat) throw StateError("mtf_matvec before mesh/materials");
+        if (nrhs < 1 || !x_dev || !y_dev || ld < p->sk.N) throw ArgError("bad arguments");
+        if (x_dev == y_dev) throw ArgError("x and y must not alias");
+        check_prec_available(p, precision);
+        DeviceGuard g(p->device);
+        for (int r = 0; r < nrhs; ++r)
+            matvec1(p, static_cast<const double*>(x_dev) + 2 * ld * (int64_t)r, static_cast<double*>(y_dev) + 2 * ld * (int64_t)r, precision);
+        HIPCHK(hipGetLastError());
+        return MTF_OK;
+    });
+}
+
+int mtf_solve(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int64_t ld, const mtf_solve_opts* opts,
+              mtf_solve_stats* stats) {
+    return guarded([&] {
+        if (!p) throw ArgError("problem is NULL");
+        return solve_impl(p, nrhs, b_dev, x_dev, ld, opts, stats);
+    });
+}
+
+int mtf_far_field(mtf_problem p, int32_t nrhs, const void* x_dev, int64_t ld, int32_t ndir, const double* dir,
+                  double* out) {
+    return guarded([&] {
+        if (!p) throw ArgError("problem is NULL");
+        if (!p->has_mesh || !p->has_mat) throw StateError("mtf_far_field before mesh/materials");
+        if (nrhs < 1 || ndir < 1 || !x_dev || !dir || !out || ld < p->sk.N) throw ArgError("bad arguments");
+        if (!finite_all(dir, 3 * ndir)) throw ArgError("non-finite direction");
+        DeviceGuard g(p->device);
+        std::vector<double> host(dir, dir + 3 * ndir);
+        DevBuf<double> dd, o;
+        dd.upload(host, p->stream);
+        o.alloc(6 * (size_t)nrhs * ndir);
+        launch_far_field(&p->doms[0], p->d_geom.p, p->d_tdof.p, p->d_tsign.p, p->doms[0].T, p->k0, p->rho[0],
+                         static_cast<const double*>(x_dev), ld, nrhs, dd.p, ndir, o.p, p->stream);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(out, o.p, o.n * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+        sync(p);
+        return MTF_OK;
+    });
+}
+
+int mtf_assembly_stats(mtf_problem p, int64_t* counts, double* seconds) {
+    return guarded([&] {
+        if (!p) throw ArgError("problem is NULL");
+        if (!p->has_mesh) throw StateError("no mesh");
+        if (counts)
+            for (int k = 0; k < 4; ++k) counts[k] = p->sk.pair_counts[k];
+        if (seconds) {
+            *seconds = 0;
+            if (p->ev0 && (p->have64 || p->have32)) {
+                DeviceGuard g(p->device);
+                HIPCHK(hipEventSynchronize(p->ev1));
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+                *seconds = ms * 1e-3;
+            }
+        }
+        return MTF_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// Device data structures and kernel launchers (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mtf {
+
+// Geometry of one triangle of one Gamma_i (Gamma_i orientation), FP64.
+// Coordinates other than the centroid are relative to the centroid.
+struct TriGeom {
+    double c[3];      // centroid
+    double p[9];      // vertices P_a - c
+    double q[18];     // six quadrature points x_q - c
+    double w[6];      // quadrature weights times area
+    double coef[3];   // l_a / (2 A): RWG scale of the local function opposite vertex a
+    double n[3];      // unit normal n_i
+    double area;
+    double pad;
+};
+static_assert(sizeof(TriGeom) == 44 * 8, "TriGeom layout");
+
+struct DomDesc {
+    int64_t rec0;     // first triangle record of the domain
+    int64_t dof0;     // first dof record of the domain (concatenated dof tables)
+    int64_t mat0;     // first entry of T_i / K_i in the concatenated matrix arrays
+    int64_t off;      // first unknown of block i (u_iD), u_iN starts at off + E
+    int64_t part0;    // first partial-sum slot of the domain in the matvec workspace
+    int32_t T, E;
+    int32_t nchunk;   // column chunks of the dense matvec
+    int32_t pad;
+    double k, rho;
+};
+
+struct SingPair {     // device copy of a touching pair
+    int32_t dom, tx, ty, kind;
+    int32_t px[3], py[3];
+};
+
+// ---- launchers (all asynchronous on `s`) ----
+void launch_fill(double* p, int64_t n, double v, hipStream_t s);
+void launch_fill_f(float* p, int64_t n, float v, hipStream_t s);
+
+void launch_tri_setup_rule(const double* xyz, const int32_t* verts, int64_t nrec, const double* bary18,
+                           const double* w6, TriGeom* geom, hipStream_t s);
+
+// Separated pairs over tiles (int4: dom, x0, y0, unused) of 16 x 16 triangles.
+void launch_regular_f64(const int4* tiles, int64_t ntiles, const DomDesc* doms, const TriGeom* geom,
+                        const int32_t* verts, const int32_t* tdof, const int8_t* tsign,
+                        double* T, double* K, hipStream_t s);
+void launch_regular_f32(const int4* tiles, int64_t ntiles, const DomDesc* doms, const TriGeom* geom,
+                        const int32_t* verts, const int32_t* tdof, const int8_t* tsign,
+                        float* T, float* K, hipStream_t s);
+
+// Touching pairs (Sauter-Schwab, FP64 arithmetic), results added to FP64 or FP32 blocks.
+void launch_singular(const SingPair* pairs, int64_t npairs, const DomDesc* doms, const TriGeom* geom,
+                     const double* xyz, const int32_t* verts, const int32_t* tdof, const int8_t* tsign,
+                     const double* ss_table, const int32_t* ss_off, const int32_t* ss_cnt,
+                     double* T64, double* K64, float* T32, float* K32, hipStream_t s);
+
+// Signed local transmission values and column indices per triangle record.
+void launch_gram_local(const DomDesc* doms, int ndom, int64_t nrec, const int32_t* rec_dom,
+                       const TriGeom* geom, const int32_t* other_rec, const int8_t* tsign,
+                       const int32_t* tdof, const int32_t* other_dom, double* gval, int64_t* gcol,
+                       hipStream_t s);
+
+void launch_rhs(const DomDesc* d0, const TriGeom* geom, const int32_t* dplus, const int32_t* dminus,
+                int32_t E0, double k0, double rho0, int nrhs, const double* dirs, const double* pol,
+                double* b, int64_t ldb, hipStream_t s);
+
+// Dense part of y = M x: partial sums of the 2x2 block products per column chunk.
+void launch_matvec_dense_f64(const DomDesc* doms, const int4* mtiles, int64_t nmt, const double* T,
+                             const double* K, const double* x, double* part, hipStream_t s);
+void launch_matvec_dense_f32(const DomDesc* doms, const int4* mtiles, int64_t nmt, const float* T,
+                             const float* K, const double* x, double* part, hipStream_t s);
+// y = sum of partials + transmission; one thread per unknown pair (D, N) of a dof.
+void launch_matvec_finish(const DomDesc* doms, int ndom, const int32_t* dof_dom, int64_t ndof_total,
+                          const int32_t* dplus, const int32_t* dminus, const double* gval,
+                          const int64_t* gcol, const double* part, const double* x, double* y,
+                          hipStream_t s);
+
+// GMRES vector kernels (complex128, length n).
+void launch_multidot(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* hpart,
+                     int nblk, hipStream_t s);
+void launch_reduce_h(const double* hpart, int nv, int nblk, double* h, double* hsum, int accumulate,
+                     hipStream_t s);
+void launch_update(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n, hipStream_t s);
+void launch_norm2(const double* w, int64_t n, double* part, int nblk, hipStream_t s);
+void launch_axpby(double* y, const double* x, int64_t n, double a_re, double a_im, double b,
+                  hipStream_t s);       // y = b*y + a*x (a complex, b real)
+void launch_scale_dev(double* y, const double* x, int64_t n, const double* inv_norm_part, int nblk,
+                      hipStream_t s);   // y = x / sqrt(sum parts)
+void launch_combine(double* x, const double* V, int64_t ldv, int nv, const double* coef, int64_t n,
+                    hipStream_t s);     // x += V coef
+
+void launch_far_field(const DomDesc* d0, const TriGeom* geom, const int32_t* tdof, const int8_t* tsign,
+                      int32_t T0, double k0, double rho0, const double* x, int64_t ldx, int nrhs,
+                      const double* dirs, int ndir, double* out, hipStream_t s);
+
+// Complex64 helpers for the preconditioner.
+void launch_copy_block_f64_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+void launch_cgemm_f32(int m, int n, int k, float alpha_re, float alpha_im,
+                      const float* A, int64_t lda, const float* B, int64_t ldb,
+                      float beta_re, const float* C, int64_t ldc, float* D, int64_t ldd,
+                      hipStream_t s);          // D = alpha A B + beta C (beta real)
+int  launch_cinv_small_f32(float* A, int64_t lda, int n, int* info, hipStream_t s);   // n <= 64, in place
+void launch_precond_apply(const DomDesc* doms, const int4* mtiles, int64_t nmt, const float* Tinv,
+                          const double* x, double* part, hipStream_t s);
+void launch_precond_finish(const DomDesc* doms, int ndom, const int32_t* dof_dom, int64_t ndof_total,
+                           const double* part, double* y, hipStream_t s);
+void launch_nonfinite_check(const float* A, int64_t n, int* flag, hipStream_t s);
+
+}  // namespace mtf

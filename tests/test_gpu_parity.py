@@ -1,0 +1,187 @@
+"""Parity of the HIP library (through the C ABI) with the FP64 oracle.
+
+Tolerances (relative to the largest entry of the compared quantity):
+* FP64 blocks: both sides evaluate the same quadrature sums in FP64 with
+  different arithmetic (moment epilogue and atomics vs direct evaluation);
+  rounding bounds the difference far below 1e-11.
+* FP32 separated pairs: complex64 storage and arithmetic, unit roundoff
+  6e-8, phase error ~ k r eps ~ 1e-6; bound 3e-5.
+* Solutions: GMRES to ||b - Mx|| <= 1e-10 ||b|| and cond(M) ~ 1e2-1e3 bound
+  the error against the LU solution by ~1e-7.
+"""
+import numpy as np
+import pytest
+
+import mtf_inputs as mi
+from oracle import operators as op
+from oracle import skeleton as sk
+from oracle import system as sy
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2502_10907_amd as mtf  # noqa: E402
+
+
+def _gpu_problem(cfg, precisions=(mtf.FP64,)):
+    m = cfg["mesh"]
+    P = mtf.Problem(0)
+    P.set_mesh(m.xyz, m.tri, m.label, m.M)
+    P.set_materials(cfg["k0"], cfg["eps_r"], cfg["mu_r"])
+    for pr in precisions:
+        P.assemble(pr)
+    return P
+
+
+class Case:
+    def __init__(self, cfg, lu=True):
+        self.cfg = cfg
+        self.pb = sy.Problem.from_config(cfg)
+        self.T, self.K, self.G = sy.assemble_blocks(self.pb)
+        self.b = sy.rhs(self.pb, cfg["d"], cfg["p"])[:, 0]
+        self.M = sy.dense_matrix(self.pb, self.T, self.K, self.G)
+        self.x = sy.solve_direct(self.M, self.b) if lu else None
+        self.P = _gpu_problem(cfg, (mtf.FP64, mtf.FP32_MIXED))
+
+
+@pytest.fixture(scope="module")
+def sphere():
+    print("\n[case] icosphere 320 triangles, eps_r=2, k0=1", flush=True)
+    return Case(mi.config_sphere(2))
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    # Gamma_i with triangle counts not multiple of the 16-triangle tile, dofs not multiple of 256
+    m = mi.box_skeleton((2, 1, 1), (1, 2, 3), size=(1.0, 0.8, 0.9))
+    print(f"\n[case] ragged 2-box skeleton, {m.nt} triangles", flush=True)
+    cfg = dict(mesh=m, k0=2.5, eps_r=np.array([1.0, 2.5, 1.7]), mu_r=np.array([1.0, 1.2, 1.0]),
+               d=np.array([[0.0, 0.6, 0.8]]), p=np.array([[1.0, 0.0, 0.0]], dtype=np.complex128))
+    return Case(cfg)
+
+
+@pytest.fixture(scope="module")
+def cube():
+    print("\n[case] 2x2x2 cube partition h=1/4", flush=True)
+    return Case(mi.config_cube(2, 4))
+
+
+CASES = ["sphere", "ragged", "cube"]
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_dof_map_matches_oracle(name, request):
+    c = request.getfixturevalue(name)
+    for i, sp in enumerate(c.pb.spaces):
+        ev, pt = c.P.dof_map(i)
+        assert np.array_equal(ev, sp.edges)
+        assert np.array_equal(pt, sp.tris[sp.plus[:, 0]])
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_blocks_fp64(name, request):
+    c = request.getfixturevalue(name)
+    for i in range(c.pb.M + 1):
+        assert _rel(c.P.copy_block(i, mtf.BLOCK_T), c.T[i]) < 1e-11
+        assert _rel(c.P.copy_block(i, mtf.BLOCK_K), c.K[i]) < 1e-11 * max(1.0, np.abs(c.T[i]).max() / np.abs(c.K[i]).max())
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_blocks_fp32(name, request):
+    c = request.getfixturevalue(name)
+    for i in range(c.pb.M + 1):
+        scale = np.abs(c.T[i]).max()
+        assert np.abs(c.P.copy_block(i, mtf.BLOCK_T, mtf.FP32_MIXED) - c.T[i]).max() < 3e-5 * scale
+        assert np.abs(c.P.copy_block(i, mtf.BLOCK_K, mtf.FP32_MIXED) - c.K[i]).max() < 3e-5 * scale
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_transmission_blocks(name, request):
+    c = request.getfixturevalue(name)
+    for (i, j), Gij in c.G.items():
+        assert np.abs(c.P.copy_transmission(i, j) - Gij).max() < 1e-14 * max(1.0, np.abs(Gij).max())
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_rhs(name, request):
+    c = request.getfixturevalue(name)
+    b = torch.zeros((1, c.P.N), dtype=torch.complex128, device="cuda")
+    c.P.rhs_plane_waves(c.cfg["d"], c.cfg["p"], b)
+    assert _rel(b[0].cpu().numpy(), c.b) < 1e-13
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_matvec(name, request):
+    c = request.getfixturevalue(name)
+    rng = np.random.default_rng(7)
+    xs = rng.standard_normal((2, c.P.N)) + 1j * rng.standard_normal((2, c.P.N))
+    x = torch.tensor(xs, device="cuda")
+    y = torch.zeros_like(x)
+    c.P.matvec(x, y)
+    ref = (c.M @ xs.T).T
+    assert _rel(y.cpu().numpy(), ref) < 1e-12
+    c.P.matvec(x, y, mtf.FP32_MIXED)
+    assert _rel(y.cpu().numpy(), ref) < 1e-4
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("pc", [mtf.PREC_NONE, mtf.PREC_BLOCK_TINV])
+def test_solve_fp64(name, pc, request):
+    c = request.getfixturevalue(name)
+    b = torch.tensor(c.b[None, :], device="cuda")
+    x = torch.zeros_like(b)
+    st = c.P.solve(b, x, rtol=1e-10, preconditioner=pc, max_iters=3000)[0]
+    print(f"[{name} pc={pc}] iterations {st.iterations} residual {st.rel_residual:.2e}", flush=True)
+    assert st.converged and st.rel_residual <= 1e-10
+    xs = x[0].cpu().numpy()
+    assert np.linalg.norm(c.M @ xs - c.b) / np.linalg.norm(c.b) < 2e-10
+    assert np.linalg.norm(xs - c.x) / np.linalg.norm(c.x) < 1e-7
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_solve_mixed_refinement(name, request):
+    """complex64 operator inside GMRES, FP64 residuals outside: reaches the FP64 tolerance."""
+    c = request.getfixturevalue(name)
+    b = torch.tensor(c.b[None, :], device="cuda")
+    x = torch.zeros_like(b)
+    st = c.P.solve(b, x, rtol=1e-9, precision=mtf.FP32_MIXED, max_iters=3000)[0]
+    print(f"[{name} mixed] iterations {st.iterations} refinements {st.refinements} residual {st.rel_residual:.2e}", flush=True)
+    assert st.converged and st.rel_residual <= 1e-9
+    xs = x[0].cpu().numpy()
+    assert np.linalg.norm(xs - c.x) / np.linalg.norm(c.x) < 1e-6
+
+
+def test_far_field_sphere(sphere):
+    c = sphere
+    th = np.linspace(0.1, np.pi - 0.1, 9)
+    dirs = np.concatenate([np.stack([np.sin(th), 0 * th, np.cos(th)], 1), np.stack([0 * th, np.sin(th), np.cos(th)], 1)])
+    E0 = c.pb.E[0]
+    ref = op.far_field(c.pb.xyz, c.pb.spaces[0], c.pb.k0, c.pb.rho[0], c.x[:E0], c.x[E0:2 * E0], dirs)
+    x = torch.tensor(c.x[None, :], device="cuda")
+    got = c.P.far_field(x, dirs)[0]
+    assert _rel(got, ref) < 1e-12
+
+
+def test_assembly_stats(sphere):
+    counts, sec = sphere.P.assembly_stats()
+    # icosphere(2): per surface 320 coincident, 960 edge-adjacent, 2820 vertex-adjacent ordered pairs
+    assert list(counts[1:]) == [2 * 2820, 2 * 960, 2 * 320]
+    assert counts.sum() == 2 * 320 * 320
+    assert sec > 0
+
+
+def test_invalid_mesh_rejected_on_gpu_box():
+    m = mi.cube_partition(1, 2)
+    P = mtf.Problem(0)
+    with pytest.raises(mtf.MTFError) as e:
+        P.set_mesh(m.xyz, m.tri[1:], m.label[1:], m.M)
+    assert e.value.code == -2
+    with pytest.raises(mtf.MTFError) as e:
+        P.assemble()
+    assert e.value.code == -6
