@@ -1,0 +1,178 @@
+"""Time-to-solution of the local MTF on one MI355X.
+
+One step = the whole hot path on one batch of synthetic input: Galerkin
+assembly of every T_i, K_i and transmission block, the plane-wave right-hand
+side, the block T^-1 preconditioner, and GMRES to ||b - M x|| <= 1e-6 ||b||
+(FP64 operator and Arnoldi).  Workload: unit cube split into 2x2x2 sub-cubes,
+structured skeleton at h = 1/16 (4,608 triangles, N = 27,648 unknowns),
+eps_r ~ U[1,4] per sub-cube (SplitMix64 seed 0), mu_r = 1, k0 = 2 pi, one
+x-polarised plane wave along +z.
+
+Prints one JSON line (rank 0).  The dense matvec roofline is measured live with
+HIP events on the library's stream; ``--no-cpu-baseline`` skips the oracle leg.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--h-inv", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--matvec-reps", type=int, default=20)
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, gpu_iters, nrows=64):
+    """The oracle, timed on a bounded sample of the same workload and scaled to seconds per solve.
+
+    Sample: ``nrows`` full rows of T_1, K_1 of one sub-cube computed by the oracle (each row
+    integrates both triangles of its dof against every triangle of Gamma_1), and 5 oracle
+    matvecs with that sub-cube's 2x2 Calderon block.  Scaling: the assembly by ordered
+    triangle pairs (whole skeleton / pairs evaluated in the sample), the iteration by the
+    matrix bytes of the whole system times the GPU's GMRES iteration count (one M and one
+    preconditioner application per iteration, counted as two matvec equivalents).
+    """
+    from oracle import operators as op
+    from oracle import system as sy
+    pb = sy.Problem.from_config(cfg)
+    sp = pb.spaces[1]
+    T1 = sp.verts.shape[0]
+    rows = np.linspace(0, sp.ndof - 1, nrows).astype(int)
+    t0 = time.perf_counter()
+    op.rows_TK(pb.xyz, sp, rows, pb.k[1])
+    t_rows = time.perf_counter() - t0
+    pairs_sample = 2 * nrows * T1
+    pairs_total = sum(s.verts.shape[0] ** 2 for s in pb.spaces)
+    E = sp.ndof
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((E, E)) + 1j * rng.standard_normal((E, E))
+    B = rng.standard_normal((E, E)) + 1j * rng.standard_normal((E, E))
+    x = np.ones(2 * E, dtype=np.complex128)
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y = np.concatenate([2 * (B @ x[:E]) + (2 / pb.rho[1]) * (A @ x[E:]),
+                            -2 * pb.rho[1] * (A @ x[:E]) + 2 * (B @ x[E:])])
+    t_mv = (time.perf_counter() - t0) / reps
+    del y
+    bytes_sample = 2 * E * E
+    bytes_total = 2 * sum(int(s.ndof) ** 2 for s in pb.spaces)
+    t_iter = 2 * t_mv * bytes_total / bytes_sample
+    total = t_rows * pairs_total / pairs_sample + gpu_iters * t_iter
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"value": total, "unit": "s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"oracle rows of T_1,K_1 for {nrows} dofs of one sub-cube ({pairs_sample} triangle pairs, "
+                       f"{t_rows:.1f} s) and {reps} 2x2-block matvecs of the oracle's form ({t_mv * 1e3:.1f} ms each); "
+                       f"scaled by ordered pairs ({pairs_total}) and matrix bytes x {gpu_iters} GMRES iterations "
+                       "(2 matvec-equivalents each); extrapolated, not a full run")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import mtf_inputs as mi
+    import paper_2502_10907_amd as mtf
+
+    cfg = mi.config_cube(2, args.h_inv)
+    m = cfg["mesh"]
+    dev = torch.device("cuda:0")
+    P = mtf.Problem(0)
+    P.set_mesh(m.xyz, m.tri, m.label, m.M)
+    P.set_materials(cfg["k0"], cfg["eps_r"], cfg["mu_r"])
+    N = P.N
+    b = torch.zeros((1, N), dtype=torch.complex128, device=dev)
+    x = torch.zeros((1, N), dtype=torch.complex128, device=dev)
+
+    def step():
+        P.assemble(mtf.FP64)
+        P.rhs_plane_waves(cfg["d"], cfg["p"], b)
+        return P.solve(b, x, rtol=1e-6, preconditioner=mtf.PREC_BLOCK_TINV, max_iters=4000)[0]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    st = stats[-1]
+    counts, t_asm = P.assembly_stats()
+
+    # live roofline of the dense block matvec (FP64 T_i, K_i streamed once per product)
+    xr = torch.randn((1, N), dtype=torch.complex128, device=dev)
+    yr = torch.zeros_like(xr)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    P.matvec(xr, yr)
+    e0.record(s)
+    for _ in range(args.matvec_reps):
+        P.matvec(xr, yr)
+    e1.record(s)
+    torch.cuda.synchronize()
+    t_mv = e0.elapsed_time(e1) * 1e-3 / args.matvec_reps
+    mat_bytes = 2 * 16 * int(np.sum(P.E.astype(np.int64) ** 2))
+    achieved = mat_bytes / t_mv / 1e9
+
+    mixed = None
+    if not args.no_mixed:
+        P.assemble(mtf.FP64)
+        torch.cuda.synchronize()
+        tm0 = time.perf_counter()
+        P.assemble(mtf.FP32_MIXED)
+        P.rhs_plane_waves(cfg["d"], cfg["p"], b)
+        xm = torch.zeros_like(x)
+        sm = P.solve(b, xm, rtol=1e-6, precision=mtf.FP32_MIXED, preconditioner=mtf.PREC_BLOCK_TINV, max_iters=4000)[0]
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - tm0
+        diff = (torch.linalg.vector_norm(xm - x) / torch.linalg.vector_norm(x)).item()
+        mixed = {"s_per_solve_excl_fp64_assembly": tm, "iterations": sm.iterations, "refinements": sm.refinements,
+                 "rel_residual_fp64": sm.rel_residual, "rel_diff_vs_fp64_solution": diff}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, st.iterations)
+
+    out = {
+        "metric": "MTF solve s to GMRES 1e-6 (assembly+matvec), mixed/batched vs FP64; % peak",
+        "value": dt, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128", "data": "synthetic",
+        "config": {"workload": f"unit cube 2x2x2 sub-cubes, structured skeleton h=1/{args.h_inv}, eps_r~U[1,4] seed 0, "
+                               "k0=2pi, one plane wave; FP64 assembly + block T^-1 right preconditioner + full GMRES",
+                   "triangles": int(m.nt), "N": int(N), "pairs_separated": int(counts[0]),
+                   "pairs_touching": int(counts[1:].sum())},
+        "gmres": {"iterations": st.iterations, "rel_residual_fp64": st.rel_residual, "converged": st.converged,
+                  "t_precond_s": st.t_precond_s, "t_solve_s": st.t_solve_s},
+        "assembly_s": t_asm,
+        "roofline": {"bound": "hbm", "kernel": "block matvec (dense T_i,K_i FP64)", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": mat_bytes, "avg_launch_s": t_mv},
+        "mixed_fp32": mixed,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

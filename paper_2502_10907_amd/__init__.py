@@ -22,6 +22,9 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "mtf.h")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2502_10907_amd.build`")
+# torch first: its HIP runtime is then the one libmtf.so binds to (same soname), so the
+# process holds a single runtime and torch streams and pointers are valid in the library.
+import torch  # noqa: E402,F401
 _lib = C.CDLL(LIB_PATH)
 
 OK, NOT_CONVERGED = 0, 1
