@@ -163,7 +163,8 @@ def main():
                    "triangles": int(m.nt), "N": int(N), "pairs_separated": int(counts[0]),
                    "pairs_touching": int(counts[1:].sum())},
         "gmres": {"iterations": st.iterations, "rel_residual_fp64": st.rel_residual, "converged": st.converged,
-                  "t_precond_s": st.t_precond_s, "t_solve_s": st.t_solve_s},
+                  "t_precond_s": st.t_precond_s, "t_solve_s": st.t_solve_s,
+                  "second_gs_passes": st.reorthogonalizations},
         "assembly_s": t_asm,
         "roofline": {"bound": "hbm", "kernel": "block matvec (dense T_i,K_i FP64)", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,

@@ -168,14 +168,14 @@ typedef struct {
     int32_t iterations;       /* total Arnoldi steps                                   */
     int32_t refinements;      /* FP64 residual evaluations after the first             */
     int32_t converged;        /* 1 if rtol was met                                     */
-    int32_t reserved;
+    int32_t reorthogonalizations; /* Arnoldi steps that needed a second Gram-Schmidt pass */
     double  rel_residual;     /* final ||b - M x|| / ||b|| with the FP64 operator       */
     double  t_precond_s;      /* time to build the preconditioner (first call only)    */
     double  t_solve_s;        /* wall time of the solve                                */
 } mtf_solve_stats;
 
-/* Solve M x = b by GMRES (full, classical Gram-Schmidt applied twice, FP64
- * Arnoldi) for each of nrhs right-hand sides (b_dev, x_dev: complex128
+/* Solve M x = b by GMRES (full; FP64 Arnoldi by classical Gram-Schmidt with a
+ * second pass when the first loses more than half the norm) for each of nrhs right-hand sides (b_dev, x_dev: complex128
  * [nrhs][ld]).  With MTF_PREC_BLOCK_TINV the iteration runs on M P, with P the
  * block-diagonal right preconditioner
  *     P_i = 1/2 [[0, -T_i^-1 / rho_i], [rho_i T_i^-1, 0]]

@@ -53,7 +53,7 @@ class SolveOpts(C.Structure):
 
 class SolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("refinements", C.c_int32), ("converged", C.c_int32),
-                ("reserved", C.c_int32), ("rel_residual", C.c_double), ("t_precond_s", C.c_double),
+                ("reorthogonalizations", C.c_int32), ("rel_residual", C.c_double), ("t_precond_s", C.c_double),
                 ("t_solve_s", C.c_double)]
 
 
@@ -139,6 +139,7 @@ class Stats:
     rel_residual: float
     t_precond_s: float
     t_solve_s: float
+    reorthogonalizations: int = 0
 
 
 class Problem:
@@ -257,8 +258,8 @@ class Problem:
         st = (SolveStats * nrhs)()
         code = _check(_lib.mtf_solve(self._h, nrhs, pb, px, ld, C.byref(o), st))
         self.last_status = code
-        return [Stats(s.iterations, s.refinements, bool(s.converged), s.rel_residual, s.t_precond_s, s.t_solve_s)
-                for s in st]
+        return [Stats(s.iterations, s.refinements, bool(s.converged), s.rel_residual, s.t_precond_s, s.t_solve_s,
+                      s.reorthogonalizations) for s in st]
 
     def far_field(self, x, dirs) -> np.ndarray:
         px, nrhs, ld = _dev(x, self.N)

@@ -89,16 +89,18 @@ struct DeviceGuard {
 
 constexpr int kTile = 16;     // triangles per side of a separated-pair tile
 constexpr int kRows = 256;    // rows per dense-matvec workgroup
-constexpr int kChunk = 256;   // columns per dense-matvec workgroup
+constexpr int kChunk = 64;    // columns per dense-matvec workgroup (matches solver.hip)
 constexpr int kNblk = 32;     // partial sums of GMRES reductions
+constexpr int kSync = 8;      // Arnoldi steps between host reads of the Hessenberg columns
 
 struct GmresWork {
     int64_t n = 0;
     int maxit = 0;
-    DevBuf<double> V, tmp, tmp2, r, hpart, h, hsum, npart, y;
-    double* hh_host = nullptr;   // pinned: hsum (2*(maxit+1)) + npart (kNblk)
+    DevBuf<double> V, tmp, tmp2, r, hpart, h, H, wn2, npart, upart, y;
+    DevBuf<int> flag;                // [0] second-pass flag, [1] number of second passes
+    double* host = nullptr;          // pinned: kSync Hessenberg columns + norm parts
     ~GmresWork() {
-        if (hh_host) (void)hipHostFree(hh_host);
+        if (host) (void)hipHostFree(host);
     }
 };
 
@@ -407,97 +409,113 @@ void gmres_alloc(mtf_problem p, int maxit) {
     if (w.n == n && w.maxit >= maxit) return;
     w.n = n;
     w.maxit = maxit;
+    const int64_t ldh = maxit + 1;
     w.V.alloc(2 * n * (int64_t)(maxit + 1));
     w.tmp.alloc(2 * n);
     w.tmp2.alloc(2 * n);
     w.r.alloc(2 * n);
-    w.hpart.alloc(2 * (int64_t)(maxit + 1) * kNblk);
+    w.hpart.alloc(2 * (int64_t)(maxit + 2) * kNblk);
     w.h.alloc(2 * (maxit + 1));
-    w.hsum.alloc(2 * (maxit + 1) + kNblk);
-    w.npart.alloc(kNblk);
+    w.H.alloc(2 * ldh * (int64_t)maxit);
+    w.wn2.alloc(2);
+    w.npart.alloc(2 * kNblk);
+    w.upart.alloc(2 * n * (int64_t)((maxit + 63) / 64 + 1));
     w.y.alloc(2 * (maxit + 1));
-    if (w.hh_host) (void)hipHostFree(w.hh_host);
-    w.hh_host = nullptr;
-    HIPCHK(hipHostMalloc((void**)&w.hh_host, (2 * (maxit + 1) + kNblk) * sizeof(double), hipHostMallocDefault));
+    w.flag.alloc(2);
+    if (w.host) (void)hipHostFree(w.host);
+    w.host = nullptr;
+    HIPCHK(hipHostMalloc((void**)&w.host, (2 * ldh * kSync + kNblk) * sizeof(double), hipHostMallocDefault));
 }
 
 double norm_dev(mtf_problem p, const double* v) {
     GmresWork& w = p->gw;
     launch_norm2(v, w.n, w.npart.p, kNblk, p->stream);
-    HIPCHK(hipMemcpyAsync(w.hh_host, w.npart.p, kNblk * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipMemcpyAsync(w.host, w.npart.p, kNblk * sizeof(double), hipMemcpyDeviceToHost, p->stream));
     sync(p);
     double s = 0;
-    for (int k = 0; k < kNblk; ++k) s += w.hh_host[k];
+    for (int k = 0; k < kNblk; ++k) s += w.host[k];
     return std::sqrt(s);
 }
 
 // One GMRES cycle on A = M_prec (P) for right-hand side r (device), starting from zero; adds the
-// correction to x.  Returns the number of Arnoldi steps; *est = final recurrence residual / ||r||.
-int gmres_cycle(mtf_problem p, const double* r, double* x, int prec, bool use_pc, double tol, int maxit, double* est) {
+// correction to x.  Arnoldi: one classical Gram-Schmidt pass, a second one only when the DGKS
+// test asks for it (decided on the device), Hessenberg columns kept on the device and read by
+// the host every kSync steps for the Givens rotations and the convergence test.
+// Returns the number of Arnoldi steps; *est = final recurrence residual / ||r||.
+int gmres_cycle(mtf_problem p, const double* r, double* x, int prec, bool use_pc, double tol, int maxit, double* est,
+                int* reorth) {
     GmresWork& w = p->gw;
     hipStream_t s = p->stream;
     const int64_t n = w.n;
+    const int64_t ldh = w.maxit + 1;
     double* V = w.V.p;
     auto Vc = [&](int j) { return V + 2 * n * (int64_t)j; };
+    auto Hc = [&](int j) { return w.H.p + 2 * ldh * (int64_t)j; };
     const double beta = norm_dev(p, r);
     *est = 0.0;
     if (beta == 0.0) return 0;
     HIPCHK(hipMemcpyAsync(Vc(0), r, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
     launch_axpby(Vc(0), Vc(0), n, 0.0, 0.0, 1.0 / beta, s);
-    std::vector<cd> H((size_t)(maxit + 1) * maxit, cd(0));
+    HIPCHK(hipMemsetAsync(w.flag.p, 0, 2 * sizeof(int), s));
+    std::vector<cd> H((size_t)ldh * maxit, cd(0));
     std::vector<double> cs(maxit, 0.0);
     std::vector<cd> sn(maxit, cd(0)), gvec(maxit + 1, cd(0));
     gvec[0] = beta;
-    int it = 0;
+    int it = 0, done_cols = 0;
     double resid = beta;
-    for (int j = 0; j < maxit; ++j) {
+    bool stop = false;
+    for (int j = 0; j < maxit && !stop; ++j) {
         const double* src = Vc(j);
         if (use_pc) { precond1(p, src, w.tmp.p); src = w.tmp.p; }
         double* wv = Vc(j + 1);
         matvec1(p, src, wv, prec);
         const int nv = j + 1;
-        for (int pass = 0; pass < 2; ++pass) {
-            launch_multidot(V, n, nv, wv, n, w.hpart.p, kNblk, s);
-            launch_reduce_h(w.hpart.p, nv, kNblk, w.h.p, w.hsum.p, pass, s);
-            launch_update(V, n, nv, w.h.p, wv, n, s);
-        }
-        launch_norm2(wv, n, w.hsum.p + 2 * (maxit + 1), kNblk, s);
-        HIPCHK(hipMemcpyAsync(w.hh_host, w.hsum.p, 2 * nv * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(w.hh_host + 2 * (maxit + 1), w.hsum.p + 2 * (maxit + 1), kNblk * sizeof(double),
-                              hipMemcpyDeviceToHost, s));
-        launch_scale_dev(wv, wv, n, w.hsum.p + 2 * (maxit + 1), kNblk, s);
+        launch_multidot(V, n, nv, wv, n, w.hpart.p, kNblk, 1, nullptr, s);
+        launch_reduce_h(w.hpart.p, nv, kNblk, w.h.p, Hc(j), w.wn2.p, 0, nullptr, s);
+        launch_update(V, n, nv, w.h.p, wv, n, w.upart.p, nullptr, s);
+        launch_norm2(wv, n, w.npart.p, kNblk, s);
+        launch_reorth_flag(w.wn2.p, w.npart.p, kNblk, w.flag.p, w.flag.p + 1, s);
+        launch_multidot(V, n, nv, wv, n, w.hpart.p, kNblk, 0, w.flag.p, s);
+        launch_reduce_h(w.hpart.p, nv, kNblk, w.h.p, Hc(j), w.wn2.p, 1, w.flag.p, s);
+        launch_update(V, n, nv, w.h.p, wv, n, w.upart.p, w.flag.p, s);
+        launch_norm2(wv, n, w.npart.p, kNblk, s);
+        launch_scale_dev(wv, wv, n, w.npart.p, kNblk, Hc(j) + 2 * (j + 1), s);
+        if ((j + 1) % kSync != 0 && j + 1 != maxit) continue;
+        // host: Givens rotations for the columns produced since the last read
+        const int c0 = done_cols, nc = j + 1 - done_cols;
+        HIPCHK(hipMemcpyAsync(w.host, Hc(c0), 2 * ldh * nc * sizeof(double), hipMemcpyDeviceToHost, s));
         sync(p);
-        double hn2 = 0;
-        for (int k = 0; k < kNblk; ++k) hn2 += w.hh_host[2 * (maxit + 1) + k];
-        const double hn = std::sqrt(hn2);
-        cd* Hc = &H[(size_t)j * (maxit + 1)];
-        for (int i = 0; i < nv; ++i) Hc[i] = cd(w.hh_host[2 * i], w.hh_host[2 * i + 1]);
-        Hc[j + 1] = hn;
-        for (int i = 0; i < j; ++i) {
-            const cd t = cs[i] * Hc[i] + sn[i] * Hc[i + 1];
-            Hc[i + 1] = -std::conj(sn[i]) * Hc[i] + cs[i] * Hc[i + 1];
-            Hc[i] = t;
+        for (int q = 0; q < nc && !stop; ++q) {
+            const int jj = c0 + q;
+            cd* col = &H[(size_t)jj * ldh];
+            for (int i = 0; i <= jj + 1; ++i) col[i] = cd(w.host[2 * (ldh * q + i)], w.host[2 * (ldh * q + i) + 1]);
+            const double hn = col[jj + 1].real();
+            for (int i = 0; i < jj; ++i) {
+                const cd t = cs[i] * col[i] + sn[i] * col[i + 1];
+                col[i + 1] = -std::conj(sn[i]) * col[i] + cs[i] * col[i + 1];
+                col[i] = t;
+            }
+            const cd a = col[jj];
+            const double den = std::sqrt(std::norm(a) + hn * hn);
+            if (std::abs(a) == 0.0) { cs[jj] = 0.0; sn[jj] = 1.0; }
+            else { cs[jj] = std::abs(a) / den; sn[jj] = (a / std::abs(a)) * hn / den; }
+            col[jj] = cs[jj] * a + sn[jj] * hn;
+            col[jj + 1] = 0.0;
+            gvec[jj + 1] = -std::conj(sn[jj]) * gvec[jj];
+            gvec[jj] = cs[jj] * gvec[jj];
+            it = jj + 1;
+            resid = std::abs(gvec[jj + 1]);
+            if (!std::isfinite(resid)) throw NonFiniteError("GMRES produced a non-finite residual");
+            if (resid <= tol * beta || hn == 0.0) stop = true;
         }
-        const cd a = Hc[j];
-        const double c = hn;
-        const double den = std::sqrt(std::norm(a) + c * c);
-        if (std::abs(a) == 0.0) { cs[j] = 0.0; sn[j] = 1.0; }
-        else { cs[j] = std::abs(a) / den; sn[j] = (a / std::abs(a)) * c / den; }
-        Hc[j] = cs[j] * a + sn[j] * c;
-        Hc[j + 1] = 0.0;
-        gvec[j + 1] = -std::conj(sn[j]) * gvec[j];
-        gvec[j] = cs[j] * gvec[j];
-        it = j + 1;
-        resid = std::abs(gvec[j + 1]);
-        if (!std::isfinite(resid)) throw NonFiniteError("GMRES produced a non-finite residual");
-        if (resid <= tol * beta || hn == 0.0) break;
+        done_cols = j + 1;
     }
-    // back substitution
+    // back substitution on the first `it` columns
     std::vector<cd> yv(it);
     for (int i = it - 1; i >= 0; --i) {
         cd acc = gvec[i];
-        for (int k = i + 1; k < it; ++k) acc -= H[(size_t)k * (maxit + 1) + i] * yv[k];
-        yv[i] = acc / H[(size_t)i * (maxit + 1) + i];
+        for (int k = i + 1; k < it; ++k) acc -= H[(size_t)k * ldh + i] * yv[k];
+        yv[i] = acc / H[(size_t)i * ldh + i];
     }
     std::vector<double> yh(2 * it);
     for (int i = 0; i < it; ++i) { yh[2 * i] = yv[i].real(); yh[2 * i + 1] = yv[i].imag(); }
@@ -510,7 +528,10 @@ int gmres_cycle(mtf_problem p, const double* r, double* x, int prec, bool use_pc
     } else {
         launch_combine(x, V, n, it, w.y.p, n, s);
     }
+    int cnt[2];
+    HIPCHK(hipMemcpyAsync(cnt, w.flag.p, sizeof(cnt), hipMemcpyDeviceToHost, s));
     sync(p);
+    if (reorth) *reorth += cnt[1];
     *est = resid / beta;
     return it;
 }
@@ -553,7 +574,7 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
                                                2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
         else launch_fill(x, 2 * n, 0.0, s);
         const double bn = norm_dev(p, b);
-        int iters = 0, refin = 0;
+        int iters = 0, refin = 0, reorth = 0;
         double rel = 1.0;
         bool conv = false;
         if (bn == 0.0) { conv = true; rel = 0.0; }
@@ -570,12 +591,13 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
             if (prec == MTF_FP32_MIXED) tol = std::max(tol, opts.inner_rtol > 0 ? opts.inner_rtol : 1e-6);
             else if (opts.inner_rtol > 0) tol = std::max(tol, opts.inner_rtol);
             double est = 0;
-            iters += gmres_cycle(p, w.r.p, x, prec, use_pc, 0.9 * tol, maxit, &est);
+            iters += gmres_cycle(p, w.r.p, x, prec, use_pc, 0.9 * tol, maxit, &est, &reorth);
         }
         if (stats) {
             stats[rhs].iterations = iters;
             stats[rhs].refinements = refin;
             stats[rhs].converged = conv ? 1 : 0;
+            stats[rhs].reorthogonalizations = reorth;
             stats[rhs].rel_residual = rel;
             stats[rhs].t_precond_s = rhs == 0 ? t_pc : 0.0;
             stats[rhs].t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

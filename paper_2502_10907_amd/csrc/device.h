@@ -79,17 +79,19 @@ void launch_matvec_finish(const DomDesc* doms, int ndom, const int32_t* dof_dom,
                           const int64_t* gcol, const double* part, const double* x, double* y,
                           hipStream_t s);
 
-// GMRES vector kernels (complex128, length n).
+// GMRES vector kernels (complex128, length n).  Kernels taking `flag` do nothing when *flag == 0.
 void launch_multidot(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* hpart,
-                     int nblk, hipStream_t s);
-void launch_reduce_h(const double* hpart, int nv, int nblk, double* h, double* hsum, int accumulate,
-                     hipStream_t s);
-void launch_update(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n, hipStream_t s);
+                     int nblk, int self, const int* flag, hipStream_t s);
+void launch_reduce_h(const double* hpart, int nv, int nblk, double* h, double* Hcol, double* wn2, int second,
+                     const int* flag, hipStream_t s);
+void launch_reorth_flag(const double* wn2, const double* part, int nblk, int* flag, int* count, hipStream_t s);
+void launch_update(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n, double* part,
+                   const int* flag, hipStream_t s);   // w -= V h (split over 64-vector chunks)
 void launch_norm2(const double* w, int64_t n, double* part, int nblk, hipStream_t s);
 void launch_axpby(double* y, const double* x, int64_t n, double a_re, double a_im, double b,
                   hipStream_t s);       // y = b*y + a*x (a complex, b real)
-void launch_scale_dev(double* y, const double* x, int64_t n, const double* inv_norm_part, int nblk,
-                      hipStream_t s);   // y = x / sqrt(sum parts)
+void launch_scale_dev(double* y, const double* x, int64_t n, const double* part, int nblk, double* hsub,
+                      hipStream_t s);   // y = x / sqrt(sum parts); hsub (if set) = that norm
 void launch_combine(double* x, const double* V, int64_t ldv, int nv, const double* coef, int64_t n,
                     hipStream_t s);     // x += V coef
 

@@ -17,7 +17,7 @@ namespace mtf {
 
 namespace {
 
-constexpr int kChunk = 256;   // columns per dense-matvec workgroup (must match the host tiling)
+constexpr int kChunk = 64;    // columns per dense-matvec workgroup (must match the host tiling)
 
 template <typename RM>
 struct C2 {
@@ -165,14 +165,17 @@ __device__ inline double wsum(double v) {
     return v;
 }
 
-// hpart[i * nblk + blk] = sum_{n in chunk blk} conj(V_i[n]) w[n]
-__global__ __launch_bounds__(256) void k_multidot(const double* __restrict__ V, int64_t ldv, const double* __restrict__ w,
-                                                  int64_t n, double* __restrict__ hpart, int nblk) {
+// hpart[i * nblk + blk] = sum_{n in chunk blk} conj(V_i[n]) w[n] for i < nv; with `self`, slot nv
+// receives w^H w.  Skipped entirely when `flag` is given and *flag == 0.
+__global__ __launch_bounds__(256) void k_multidot(const double* __restrict__ V, int64_t ldv, int nv,
+                                                  const double* __restrict__ w, int64_t n, double* __restrict__ hpart,
+                                                  int nblk, const int* __restrict__ flag) {
+    if (flag && *flag == 0) return;
     const int i = blockIdx.y;
     const int blk = blockIdx.x;
     const int64_t chunk = (n + nblk - 1) / nblk;
     const int64_t lo = blk * chunk, hi = min(n, lo + chunk);
-    const double* v = V + 2 * (int64_t)i * ldv;
+    const double* v = (i == nv) ? w : V + 2 * (int64_t)i * ldv;
     double re = 0, im = 0;
     for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
         const double vr = v[2 * e], vi = v[2 * e + 1], wr = w[2 * e], wi = w[2 * e + 1];
@@ -193,16 +196,80 @@ __global__ __launch_bounds__(256) void k_multidot(const double* __restrict__ V, 
     }
 }
 
+// h[i] = sum of partials; Hcol[i] = h[i] (first pass) or Hcol[i] + h[i] (second pass);
+// slot nv (first pass only) gives wn2 = w^H w.
 __global__ void k_reduce_h(const double* __restrict__ hpart, int nv, int nblk, double* __restrict__ h,
-                           double* __restrict__ hsum, int accumulate) {
+                           double* __restrict__ Hcol, double* __restrict__ wn2, int second,
+                           const int* __restrict__ flag) {
+    if (flag && *flag == 0) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nv) return;
+    const int top = second ? nv : nv + 1;
+    if (i >= top) return;
     double a = 0, b = 0;
     for (int k = 0; k < nblk; ++k) { a += hpart[2 * ((int64_t)i * nblk + k)]; b += hpart[2 * ((int64_t)i * nblk + k) + 1]; }
+    if (i == nv) { wn2[0] = a; return; }
     h[2 * i] = a;
     h[2 * i + 1] = b;
-    if (accumulate) { hsum[2 * i] += a; hsum[2 * i + 1] += b; }
-    else { hsum[2 * i] = a; hsum[2 * i + 1] = b; }
+    if (second) { Hcol[2 * i] += a; Hcol[2 * i + 1] += b; }
+    else { Hcol[2 * i] = a; Hcol[2 * i + 1] = b; }
+}
+
+// Second Gram-Schmidt pass only when the first lost too much: ||w'||^2 < ||w||^2 / 2 (DGKS test).
+__global__ void k_reorth_flag(const double* __restrict__ wn2, const double* __restrict__ part, int nblk,
+                              int* __restrict__ flag, int* __restrict__ count) {
+    double s = 0;
+    for (int k = 0; k < nblk; ++k) s += part[k];
+    const int f = s < 0.5 * wn2[0] ? 1 : 0;
+    flag[0] = f;
+    count[0] += f;
+}
+
+// part[c][e] = sum_{i in vector chunk c} V_i[e] h[i]   (64 vectors per chunk)
+__global__ __launch_bounds__(256) void k_update_part(const double* __restrict__ V, int64_t ldv, int nv,
+                                                     const double* __restrict__ h, double* __restrict__ part,
+                                                     int64_t n, const int* __restrict__ flag) {
+    if (flag && *flag == 0) return;
+    __shared__ double hs[2 * 64];
+    const int c = blockIdx.y;
+    const int i0 = c * 64;
+    const int cnt = min(64, nv - i0);
+    if ((int)threadIdx.x < cnt) { hs[2 * threadIdx.x] = h[2 * (i0 + threadIdx.x)]; hs[2 * threadIdx.x + 1] = h[2 * (i0 + threadIdx.x) + 1]; }
+    __syncthreads();
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double re = 0, im = 0;
+    const double* v = V + 2 * ((int64_t)i0 * ldv + e);
+    int i = 0;
+    for (; i + 8 <= cnt; i += 8) {
+        double vr[8], vi[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) { vr[u] = v[2 * (int64_t)(i + u) * ldv]; vi[u] = v[2 * (int64_t)(i + u) * ldv + 1]; }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double hr = hs[2 * (i + u)], hi = hs[2 * (i + u) + 1];
+            re += vr[u] * hr - vi[u] * hi;
+            im += vr[u] * hi + vi[u] * hr;
+        }
+    }
+    for (; i < cnt; ++i) {
+        const double vr = v[2 * (int64_t)i * ldv], vi = v[2 * (int64_t)i * ldv + 1];
+        const double hr = hs[2 * i], hi = hs[2 * i + 1];
+        re += vr * hr - vi * hi;
+        im += vr * hi + vi * hr;
+    }
+    part[2 * ((int64_t)c * n + e)] = re;
+    part[2 * ((int64_t)c * n + e) + 1] = im;
+}
+
+__global__ __launch_bounds__(256) void k_update_apply(const double* __restrict__ part, int nchunk, double* __restrict__ w,
+                                                      int64_t n, const int* __restrict__ flag) {
+    if (flag && *flag == 0) return;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double re = 0, im = 0;
+    for (int c = 0; c < nchunk; ++c) { re += part[2 * ((int64_t)c * n + e)]; im += part[2 * ((int64_t)c * n + e) + 1]; }
+    w[2 * e] -= re;
+    w[2 * e + 1] -= im;
 }
 
 // w -= V h
@@ -275,12 +342,14 @@ __global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, in
 }
 
 __global__ void k_scale_dev(double* __restrict__ y, const double* __restrict__ x, int64_t n,
-                            const double* __restrict__ part, int nblk) {
+                            const double* __restrict__ part, int nblk, double* __restrict__ hsub) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
     double s = 0;
     for (int k = 0; k < nblk; ++k) s += part[k];
-    const double inv = s > 0 ? 1.0 / sqrt(s) : 0.0;
+    const double nrm = sqrt(s);
+    if (e == 0 && hsub) { hsub[0] = nrm; hsub[1] = 0.0; }
+    if (e >= n) return;
+    const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
     y[2 * e] = x[2 * e] * inv;
     y[2 * e + 1] = x[2 * e + 1] * inv;
 }
@@ -471,16 +540,25 @@ void launch_precond_finish(const DomDesc* doms, int /*ndom*/, const int32_t* dof
 }
 
 void launch_multidot(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* hpart, int nblk,
-                     hipStream_t s) {
-    hipLaunchKernelGGL(k_multidot, dim3((unsigned)nblk, (unsigned)nv), dim3(256), 0, s, V, ldv, w, n, hpart, nblk);
+                     int self, const int* flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_multidot, dim3((unsigned)nblk, (unsigned)(nv + (self ? 1 : 0))), dim3(256), 0, s, V, ldv, nv, w,
+                       n, hpart, nblk, flag);
 }
 
-void launch_reduce_h(const double* hpart, int nv, int nblk, double* h, double* hsum, int accumulate, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_h, dim3(gridn(nv, 128)), dim3(128), 0, s, hpart, nv, nblk, h, hsum, accumulate);
+void launch_reduce_h(const double* hpart, int nv, int nblk, double* h, double* Hcol, double* wn2, int second,
+                     const int* flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_h, dim3(gridn(nv + 1, 128)), dim3(128), 0, s, hpart, nv, nblk, h, Hcol, wn2, second, flag);
 }
 
-void launch_update(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_update, dim3(gridn(n, 256)), dim3(256), 0, s, V, ldv, nv, h, w, n);
+void launch_reorth_flag(const double* wn2, const double* part, int nblk, int* flag, int* count, hipStream_t s) {
+    hipLaunchKernelGGL(k_reorth_flag, dim3(1), dim3(1), 0, s, wn2, part, nblk, flag, count);
+}
+
+void launch_update(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n, double* part,
+                   const int* flag, hipStream_t s) {
+    const int nchunk = (nv + 63) / 64;
+    hipLaunchKernelGGL(k_update_part, dim3(gridn(n, 256), (unsigned)nchunk), dim3(256), 0, s, V, ldv, nv, h, part, n, flag);
+    hipLaunchKernelGGL(k_update_apply, dim3(gridn(n, 256)), dim3(256), 0, s, part, nchunk, w, n, flag);
 }
 
 void launch_combine(double* x, const double* V, int64_t ldv, int nv, const double* coef, int64_t n, hipStream_t s) {
@@ -495,8 +573,9 @@ void launch_axpby(double* y, const double* x, int64_t n, double ar, double ai, d
     hipLaunchKernelGGL(k_axpby, dim3(gridn(n, 256)), dim3(256), 0, s, y, x, n, ar, ai, b);
 }
 
-void launch_scale_dev(double* y, const double* x, int64_t n, const double* part, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL(k_scale_dev, dim3(gridn(n, 256)), dim3(256), 0, s, y, x, n, part, nblk);
+void launch_scale_dev(double* y, const double* x, int64_t n, const double* part, int nblk, double* hsub,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_dev, dim3(gridn(n, 256)), dim3(256), 0, s, y, x, n, part, nblk, hsub);
 }
 
 void launch_copy_block_f64_to_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
