@@ -57,6 +57,9 @@ extern "C" {
 
 #define MTF_FP64               0   /* complex128 quadrature, storage and matvec            */
 #define MTF_FP32_MIXED         1   /* complex64 separated pairs, FP64 Sauter-Schwab pairs  */
+#define MTF_BF16_SPLIT         2   /* products with many right-hand sides on MFMA: the complex64
+                                      blocks split into bfloat16 hi/lo planes, three bf16
+                                      products per real product, FP32 accumulation          */
 
 #define MTF_BLOCK_T            0
 #define MTF_BLOCK_K            1
@@ -148,7 +151,11 @@ int mtf_rhs_plane_waves(mtf_problem p, int32_t nrhs, const double* d, const doub
                         const double* p_im, void* b_dev, int64_t ldb);
 
 /* y = M x for nrhs complex128 vectors (x_dev, y_dev: [nrhs][ld], ld >= N),
- * with M = 2A + X of Problem 2 applied from the stored blocks of `precision`. */
+ * with M = 2A + X of Problem 2 applied from the stored blocks of `precision`.
+ * MTF_BF16_SPLIT applies every subdomain's 2x2 Calderon block to all nrhs
+ * columns as one GEMM, [Y_iD | Y_iN] = [K_i | T_i] [[2X_iD, 2X_iN], [2/rho X_iN,
+ * -2 rho X_iD]], on MFMA (needs the MTF_FP32_MIXED blocks; relative error of the
+ * product ~1e-5). */
 int mtf_matvec(mtf_problem p, int32_t nrhs, const void* x_dev, void* y_dev, int64_t ld,
                int32_t precision);
 

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmtf.so")
-SOURCES = ["skeleton.cpp", "quadrature.cpp", "capi.cpp", "assembly.hip", "solver.hip"]
+SOURCES = ["skeleton.cpp", "quadrature.cpp", "capi.cpp", "assembly.hip", "solver.hip", "gemm.hip"]
 ARCH = os.environ.get("MTF_OFFLOAD_ARCH", "gfx950")
 
 

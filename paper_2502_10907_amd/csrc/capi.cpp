@@ -134,6 +134,15 @@ struct mtf_problem_s {
     DevBuf<double> T64, K64;
     DevBuf<float> T32, K32, Tinv;
     bool have64 = false, have32 = false, have_tinv = false;
+    // multi-RHS GEMM state
+    DevBuf<uint16_t> Apl, Bpl;
+    DevBuf<float> Cgm;
+    DevBuf<GemmDesc> d_gdesc;
+    DevBuf<int4> d_gtiles;
+    std::vector<GemmDesc> gdesc;
+    int64_t ngtiles = 0, gemm_kp_max = 0, gemm_np = 0;
+    int gemm_nrhs = 0;
+    bool have_split = false;
     double t_precond = 0;
     DevBuf<double> part;
     DevBuf<double> scratch_dirs;
@@ -317,14 +326,80 @@ void assemble_impl(mtf_problem p, const mtf_assembly_opts* o) {
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(p->ev1, s));
-    if (prec == MTF_FP64) p->have64 = true; else p->have32 = true;
+    if (prec == MTF_FP64) p->have64 = true; else { p->have32 = true; p->have_split = false; }
     p->have_tinv = false;
 }
 
 void check_prec_available(mtf_problem p, int prec) {
     if (prec == MTF_FP64 && !p->have64) throw StateError("FP64 blocks not assembled");
-    if (prec == MTF_FP32_MIXED && !p->have32) throw StateError("FP32 blocks not assembled");
-    if (prec != MTF_FP64 && prec != MTF_FP32_MIXED) throw ArgError("unknown precision");
+    if ((prec == MTF_FP32_MIXED || prec == MTF_BF16_SPLIT) && !p->have32)
+        throw StateError("FP32 blocks not assembled (MTF_FP32_MIXED)");
+    if (prec != MTF_FP64 && prec != MTF_FP32_MIXED && prec != MTF_BF16_SPLIT) throw ArgError("unknown precision");
+}
+
+// GEMM descriptors, tiles and workspaces for nrhs columns; the A planes are (re)built when the
+// complex64 blocks change.
+void gemm_prepare(mtf_problem p, int nrhs) {
+    hipStream_t s = p->stream;
+    const int ndom = (int)p->doms.size();
+    if (!p->have_split || p->gemm_nrhs != nrhs) {
+        const int64_t Np = ((2 * (int64_t)nrhs + 127) / 128) * 128;
+        std::vector<GemmDesc> gd(ndom);
+        std::vector<int4> tiles;
+        int64_t a = 0, b = 0, c = 0, kpmax = 0;
+        for (int i = 0; i < ndom; ++i) {
+            const int64_t E = p->doms[i].E;
+            GemmDesc& g = gd[i];
+            g.Mp = ((E + 127) / 128) * 128;
+            g.Kp = ((2 * E + 31) / 32) * 32;
+            g.Np = Np;
+            g.M = E;
+            g.N = 2 * nrhs;
+            g.ldc = E;
+            g.a_off = a;
+            g.b_off = b;
+            g.c_off = c;
+            a += 4 * g.Mp * g.Kp;
+            b += 4 * g.Np * g.Kp;
+            c += E * 2 * nrhs;
+            kpmax = std::max(kpmax, g.Kp);
+            for (int64_t m0 = 0; m0 < g.Mp; m0 += 128)
+                for (int64_t n0 = 0; n0 < Np; n0 += 128) tiles.push_back(make_int4(i, (int)m0, (int)n0, 0));
+        }
+        const bool rebuild_a = !p->have_split || p->Apl.n != (size_t)a;
+        p->gdesc = gd;
+        p->d_gdesc.upload(gd, s);
+        p->d_gtiles.upload(tiles, s);
+        p->ngtiles = (int64_t)tiles.size();
+        p->gemm_kp_max = kpmax;
+        p->gemm_np = Np;
+        p->Bpl.alloc(b);
+        p->Cgm.alloc(2 * c);
+        if (rebuild_a) {
+            p->Apl.alloc(a);
+            std::vector<int4> st;
+            for (int i = 0; i < ndom; ++i)
+                for (int64_t r0 = 0; r0 < gd[i].Mp; r0 += 64)
+                    for (int64_t k0 = 0; k0 < gd[i].Kp; k0 += 64) st.push_back(make_int4(i, (int)r0, (int)k0, 0));
+            DevBuf<int4> dst;
+            dst.upload(st, s);
+            launch_split_A(p->d_gdesc.p, p->d_doms.p, dst.p, (int64_t)st.size(), p->T32.p, p->K32.p, p->Apl.p, s);
+            HIPCHK(hipGetLastError());
+            sync(p);
+        }
+        p->gemm_nrhs = nrhs;
+        p->have_split = true;
+    }
+}
+
+// Y = M X for nrhs columns with the MFMA block products.
+void matvec_gemm(mtf_problem p, int nrhs, const double* x, int64_t ld, double* y) {
+    gemm_prepare(p, nrhs);
+    hipStream_t s = p->stream;
+    launch_split_B(p->d_gdesc.p, p->d_doms.p, (int)p->doms.size(), p->gemm_kp_max, p->gemm_np, x, ld, nrhs, p->Bpl.p, s);
+    launch_gemm_bf16x3(p->d_gdesc.p, p->d_gtiles.p, p->ngtiles, p->Apl.p, p->Bpl.p, p->Cgm.p, s);
+    launch_gemm_finish(p->d_doms.p, p->d_gdesc.p, p->d_dof_dom.p, p->ndof, p->d_dplus.p, p->d_dminus.p, p->d_gval.p,
+                       p->d_gcol.p, p->Cgm.p, x, y, ld, nrhs, s);
 }
 
 // y = M x for one vector (device pointers, complex128 length N)
@@ -846,8 +921,13 @@ int mtf_matvec(mtf_problem p, int32_t nrhs, const void* x_dev, void* y_dev, int6
         if (x_dev == y_dev) throw ArgError("x and y must not alias");
         check_prec_available(p, precision);
         DeviceGuard g(p->device);
-        for (int r = 0; r < nrhs; ++r)
-            matvec1(p, static_cast<const double*>(x_dev) + 2 * ld * (int64_t)r, static_cast<double*>(y_dev) + 2 * ld * (int64_t)r, precision);
+        if (precision == MTF_BF16_SPLIT) {
+            matvec_gemm(p, nrhs, static_cast<const double*>(x_dev), ld, static_cast<double*>(y_dev));
+        } else {
+            for (int r = 0; r < nrhs; ++r)
+                matvec1(p, static_cast<const double*>(x_dev) + 2 * ld * (int64_t)r,
+                        static_cast<double*>(y_dev) + 2 * ld * (int64_t)r, precision);
+        }
         HIPCHK(hipGetLastError());
         return MTF_OK;
     });

@@ -32,6 +32,15 @@ struct DomDesc {
     double k, rho;
 };
 
+// One subdomain's multi-RHS GEMM (bf16-split planes; see gemm.hip).
+struct GemmDesc {
+    int64_t a_off;    // first element of the subdomain's A planes (4 planes of Mp x Kp bf16)
+    int64_t b_off;    // first element of its B planes (4 planes of Np x Kp bf16)
+    int64_t c_off;    // first complex64 of its output block (M x N, column-major, ld = ldc)
+    int64_t Mp, Kp, Np;
+    int64_t M, N, ldc;
+};
+
 struct SingPair {     // device copy of a touching pair
     int32_t dom, tx, ty, kind;
     int32_t px[3], py[3];
@@ -111,5 +120,16 @@ void launch_precond_apply(const DomDesc* doms, const int4* mtiles, int64_t nmt, 
 void launch_precond_finish(const DomDesc* doms, int ndom, const int32_t* dof_dom, int64_t ndof_total,
                            const double* part, double* y, hipStream_t s);
 void launch_nonfinite_check(const float* A, int64_t n, int* flag, hipStream_t s);
+
+// Multi-RHS block products (gemm.hip).
+void launch_split_A(const GemmDesc* descs, const DomDesc* doms, const int4* tiles, int64_t ntiles, const float* T,
+                    const float* K, uint16_t* A, hipStream_t s);
+void launch_split_B(const GemmDesc* descs, const DomDesc* doms, int ndom, int64_t kp_max, int64_t np, const double* x,
+                    int64_t ld, int nrhs, uint16_t* B, hipStream_t s);
+void launch_gemm_bf16x3(const GemmDesc* descs, const int4* tiles, int64_t ntiles, const uint16_t* A, const uint16_t* B,
+                        float* C, hipStream_t s);
+void launch_gemm_finish(const DomDesc* doms, const GemmDesc* descs, const int32_t* dof_dom, int64_t ndof,
+                        const int32_t* dplus, const int32_t* dminus, const double* gval, const int64_t* gcol,
+                        const float* C, const double* x, double* y, int64_t ld, int nrhs, hipStream_t s);
 
 }  // namespace mtf
