@@ -92,13 +92,25 @@ constexpr int kRows = 256;    // rows per dense-matvec workgroup
 constexpr int kChunk = 64;    // columns per dense-matvec workgroup (matches solver.hip)
 constexpr int kNblk = 32;     // partial sums of GMRES reductions
 constexpr int kSync = 8;      // Arnoldi steps between host reads of the Hessenberg columns
+constexpr int kMaxBatch = 64; // right-hand sides per lockstep GMRES batch (MFMA products)
+
+struct GemmOp {
+    DevBuf<uint16_t> A, B;
+    DevBuf<float> C;
+    DevBuf<GemmDesc> d;
+    DevBuf<int4> tiles;
+    int64_t ntiles = 0, kpmax = 0, np = 0;
+    int nrhs = 0;
+    bool haveA = false;
+};
 
 struct GmresWork {
     int64_t n = 0;
-    int maxit = 0;
+    int maxit = 0, nb = 0;
     DevBuf<double> V, tmp, tmp2, r, hpart, h, H, wn2, npart, upart, y;
-    DevBuf<int> flag;                // [0] second-pass flag, [1] number of second passes
-    double* host = nullptr;          // pinned: kSync Hessenberg columns + norm parts
+    DevBuf<int> flag;                // [0, nb) second-pass flags, [nb, 2nb) their counts
+    DevBuf<int> cnt;                 // Arnoldi steps kept per right-hand side
+    double* host = nullptr;          // pinned: nb x kSync Hessenberg columns + norm parts
     ~GmresWork() {
         if (host) (void)hipHostFree(host);
     }
@@ -134,15 +146,7 @@ struct mtf_problem_s {
     DevBuf<double> T64, K64;
     DevBuf<float> T32, K32, Tinv;
     bool have64 = false, have32 = false, have_tinv = false;
-    // multi-RHS GEMM state
-    DevBuf<uint16_t> Apl, Bpl;
-    DevBuf<float> Cgm;
-    DevBuf<GemmDesc> d_gdesc;
-    DevBuf<int4> d_gtiles;
-    std::vector<GemmDesc> gdesc;
-    int64_t ngtiles = 0, gemm_kp_max = 0, gemm_np = 0;
-    int gemm_nrhs = 0;
-    bool have_split = false;
+    GemmOp gm, gp;                   // multi-RHS MFMA products: operator blocks, preconditioner blocks
     double t_precond = 0;
     DevBuf<double> part;
     DevBuf<double> scratch_dirs;
@@ -326,8 +330,9 @@ void assemble_impl(mtf_problem p, const mtf_assembly_opts* o) {
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(p->ev1, s));
-    if (prec == MTF_FP64) p->have64 = true; else { p->have32 = true; p->have_split = false; }
+    if (prec == MTF_FP64) p->have64 = true; else { p->have32 = true; p->gm.haveA = false; }
     p->have_tinv = false;
+    p->gp.haveA = false;
 }
 
 void check_prec_available(mtf_problem p, int prec) {
@@ -337,70 +342,73 @@ void check_prec_available(mtf_problem p, int prec) {
     if (prec != MTF_FP64 && prec != MTF_FP32_MIXED && prec != MTF_BF16_SPLIT) throw ArgError("unknown precision");
 }
 
-// GEMM descriptors, tiles and workspaces for nrhs columns; the A planes are (re)built when the
-// complex64 blocks change.
-void gemm_prepare(mtf_problem p, int nrhs) {
+// GEMM descriptors, tiles and workspaces of one multi-RHS operator (mode 0: the diagonal
+// blocks [K_i | T_i]; mode 1: the preconditioner blocks T_i^-1) for nrhs columns; the bf16
+// A planes are rebuilt whenever their source blocks change.
+void gemm_prepare(mtf_problem p, GemmOp& op, int mode, int nrhs) {
+    if (op.haveA && op.nrhs == nrhs) return;
     hipStream_t s = p->stream;
     const int ndom = (int)p->doms.size();
-    if (!p->have_split || p->gemm_nrhs != nrhs) {
-        const int64_t Np = ((2 * (int64_t)nrhs + 127) / 128) * 128;
-        std::vector<GemmDesc> gd(ndom);
-        std::vector<int4> tiles;
-        int64_t a = 0, b = 0, c = 0, kpmax = 0;
-        for (int i = 0; i < ndom; ++i) {
-            const int64_t E = p->doms[i].E;
-            GemmDesc& g = gd[i];
-            g.Mp = ((E + 127) / 128) * 128;
-            g.Kp = ((2 * E + 31) / 32) * 32;
-            g.Np = Np;
-            g.M = E;
-            g.N = 2 * nrhs;
-            g.ldc = E;
-            g.a_off = a;
-            g.b_off = b;
-            g.c_off = c;
-            a += 4 * g.Mp * g.Kp;
-            b += 4 * g.Np * g.Kp;
-            c += E * 2 * nrhs;
-            kpmax = std::max(kpmax, g.Kp);
-            for (int64_t m0 = 0; m0 < g.Mp; m0 += 128)
-                for (int64_t n0 = 0; n0 < Np; n0 += 128) tiles.push_back(make_int4(i, (int)m0, (int)n0, 0));
-        }
-        const bool rebuild_a = !p->have_split || p->Apl.n != (size_t)a;
-        p->gdesc = gd;
-        p->d_gdesc.upload(gd, s);
-        p->d_gtiles.upload(tiles, s);
-        p->ngtiles = (int64_t)tiles.size();
-        p->gemm_kp_max = kpmax;
-        p->gemm_np = Np;
-        p->Bpl.alloc(b);
-        p->Cgm.alloc(2 * c);
-        if (rebuild_a) {
-            p->Apl.alloc(a);
-            std::vector<int4> st;
-            for (int i = 0; i < ndom; ++i)
-                for (int64_t r0 = 0; r0 < gd[i].Mp; r0 += 64)
-                    for (int64_t k0 = 0; k0 < gd[i].Kp; k0 += 64) st.push_back(make_int4(i, (int)r0, (int)k0, 0));
-            DevBuf<int4> dst;
-            dst.upload(st, s);
-            launch_split_A(p->d_gdesc.p, p->d_doms.p, dst.p, (int64_t)st.size(), p->T32.p, p->K32.p, p->Apl.p, s);
-            HIPCHK(hipGetLastError());
-            sync(p);
-        }
-        p->gemm_nrhs = nrhs;
-        p->have_split = true;
+    const int64_t Np = ((2 * (int64_t)nrhs + 127) / 128) * 128;
+    std::vector<GemmDesc> gd(ndom);
+    std::vector<int4> tiles;
+    int64_t a = 0, b = 0, c = 0, kpmax = 0;
+    for (int i = 0; i < ndom; ++i) {
+        const int64_t E = p->doms[i].E;
+        GemmDesc& g = gd[i];
+        g.Mp = ((E + 127) / 128) * 128;
+        g.Kp = (((mode == 0 ? 2 * E : E) + 31) / 32) * 32;
+        g.Np = Np;
+        g.M = E;
+        g.N = 2 * nrhs;
+        g.ldc = E;
+        g.a_off = a;
+        g.b_off = b;
+        g.c_off = c;
+        a += 4 * g.Mp * g.Kp;
+        b += 4 * g.Np * g.Kp;
+        c += E * 2 * nrhs;
+        kpmax = std::max(kpmax, g.Kp);
+        for (int64_t m0 = 0; m0 < g.Mp; m0 += 128)
+            for (int64_t n0 = 0; n0 < Np; n0 += 128) tiles.push_back(make_int4(i, (int)m0, (int)n0, 0));
     }
+    op.d.upload(gd, s);
+    op.tiles.upload(tiles, s);
+    op.ntiles = (int64_t)tiles.size();
+    op.kpmax = kpmax;
+    op.np = Np;
+    op.B.alloc(b);
+    op.C.alloc(2 * c);
+    if (!op.haveA) {
+        op.A.alloc(a);
+        std::vector<int4> st;
+        for (int i = 0; i < ndom; ++i)
+            for (int64_t r0 = 0; r0 < gd[i].Mp; r0 += 64)
+                for (int64_t k0 = 0; k0 < gd[i].Kp; k0 += 64) st.push_back(make_int4(i, (int)r0, (int)k0, 0));
+        DevBuf<int4> dst;
+        dst.upload(st, s);
+        const float* T = mode == 0 ? p->T32.p : p->Tinv.p;
+        const float* K = mode == 0 ? p->K32.p : p->Tinv.p;
+        launch_split_A(op.d.p, p->d_doms.p, dst.p, (int64_t)st.size(), T, K, op.A.p, mode, s);
+        HIPCHK(hipGetLastError());
+        sync(p);
+    }
+    op.nrhs = nrhs;
+    op.haveA = true;
 }
 
-// Y = M X for nrhs columns with the MFMA block products.
-void matvec_gemm(mtf_problem p, int nrhs, const double* x, int64_t ld, double* y) {
-    gemm_prepare(p, nrhs);
+// Y = M X (mode 0) or Z = P X (mode 1) for nrhs columns of ld with the MFMA block products.
+void apply_gemm(mtf_problem p, int mode, int nrhs, const double* x, int64_t ld, double* y) {
+    GemmOp& op = mode == 0 ? p->gm : p->gp;
+    gemm_prepare(p, op, mode, nrhs);
     hipStream_t s = p->stream;
-    launch_split_B(p->d_gdesc.p, p->d_doms.p, (int)p->doms.size(), p->gemm_kp_max, p->gemm_np, x, ld, nrhs, p->Bpl.p, s);
-    launch_gemm_bf16x3(p->d_gdesc.p, p->d_gtiles.p, p->ngtiles, p->Apl.p, p->Bpl.p, p->Cgm.p, s);
-    launch_gemm_finish(p->d_doms.p, p->d_gdesc.p, p->d_dof_dom.p, p->ndof, p->d_dplus.p, p->d_dminus.p, p->d_gval.p,
-                       p->d_gcol.p, p->Cgm.p, x, y, ld, nrhs, s);
+    launch_split_B(op.d.p, p->d_doms.p, (int)p->doms.size(), op.kpmax, op.np, x, ld, nrhs, op.B.p, mode, s);
+    launch_gemm_bf16x3(op.d.p, op.tiles.p, op.ntiles, op.A.p, op.B.p, op.C.p, s);
+    launch_gemm_finish(p->d_doms.p, op.d.p, p->d_dof_dom.p, p->ndof, p->d_dplus.p, p->d_dminus.p, p->d_gval.p,
+                       p->d_gcol.p, op.C.p, x, y, ld, nrhs, mode, s);
 }
+
+void matvec_gemm(mtf_problem p, int nrhs, const double* x, int64_t ld, double* y) { apply_gemm(p, 0, nrhs, x, ld, y); }
 
 // y = M x for one vector (device pointers, complex128 length N)
 void matvec1(mtf_problem p, const double* x, double* y, int prec) {
@@ -475,140 +483,186 @@ void build_tinv(mtf_problem p) {
     sync(p);
     if (h[0] || h[1]) throw NonFiniteError("block preconditioner: singular pivot or non-finite inverse of T_i");
     p->have_tinv = true;
+    p->gp.haveA = false;
     p->t_precond = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
-void gmres_alloc(mtf_problem p, int maxit) {
+void gmres_alloc(mtf_problem p, int maxit, int nb) {
     GmresWork& w = p->gw;
     const int64_t n = p->sk.N;
-    if (w.n == n && w.maxit >= maxit) return;
+    if (w.n == n && w.maxit >= maxit && w.nb >= nb) return;
     w.n = n;
     w.maxit = maxit;
+    w.nb = nb;
     const int64_t ldh = maxit + 1;
-    w.V.alloc(2 * n * (int64_t)(maxit + 1));
-    w.tmp.alloc(2 * n);
-    w.tmp2.alloc(2 * n);
-    w.r.alloc(2 * n);
-    w.hpart.alloc(2 * (int64_t)(maxit + 2) * kNblk);
-    w.h.alloc(2 * (maxit + 1));
-    w.H.alloc(2 * ldh * (int64_t)maxit);
-    w.wn2.alloc(2);
-    w.npart.alloc(2 * kNblk);
-    w.upart.alloc(2 * n * (int64_t)((maxit + 63) / 64 + 1));
-    w.y.alloc(2 * (maxit + 1));
-    w.flag.alloc(2);
+    w.V.alloc(2 * n * (int64_t)nb * (maxit + 1));
+    w.tmp.alloc(2 * n * nb);
+    w.tmp2.alloc(2 * n * nb);
+    w.r.alloc(2 * n * nb);
+    w.hpart.alloc(2 * (int64_t)nb * (maxit + 2) * kNblk);
+    w.h.alloc(2 * (int64_t)nb * (maxit + 1));
+    w.H.alloc(2 * ldh * (int64_t)maxit * nb);
+    w.wn2.alloc(nb);
+    w.npart.alloc((int64_t)nb * kNblk);
+    w.upart.alloc(2 * n * (int64_t)nb * ((maxit + 63) / 64 + 1));
+    w.y.alloc(2 * (int64_t)nb * (maxit + 1));
+    w.flag.alloc(2 * nb);
+    w.cnt.alloc(nb);
     if (w.host) (void)hipHostFree(w.host);
     w.host = nullptr;
-    HIPCHK(hipHostMalloc((void**)&w.host, (2 * ldh * kSync + kNblk) * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&w.host, ((size_t)2 * ldh * kSync * nb + (size_t)kNblk * nb) * sizeof(double),
+                         hipHostMallocDefault));
 }
 
-double norm_dev(mtf_problem p, const double* v) {
+// column norms of nb vectors (stride ld)
+std::vector<double> norms_dev(mtf_problem p, const double* v, int64_t ld, int nb) {
     GmresWork& w = p->gw;
-    launch_norm2(v, w.n, w.npart.p, kNblk, p->stream);
-    HIPCHK(hipMemcpyAsync(w.host, w.npart.p, kNblk * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    launch_norm2(v, ld, w.n, w.npart.p, kNblk, nb, p->stream);
+    HIPCHK(hipMemcpyAsync(w.host, w.npart.p, (size_t)kNblk * nb * sizeof(double), hipMemcpyDeviceToHost, p->stream));
     sync(p);
-    double s = 0;
-    for (int k = 0; k < kNblk; ++k) s += w.host[k];
-    return std::sqrt(s);
+    std::vector<double> out(nb);
+    for (int b = 0; b < nb; ++b) {
+        double s = 0;
+        for (int k = 0; k < kNblk; ++k) s += w.host[(size_t)b * kNblk + k];
+        out[b] = std::sqrt(s);
+    }
+    return out;
 }
 
-// One GMRES cycle on A = M_prec (P) for right-hand side r (device), starting from zero; adds the
-// correction to x.  Arnoldi: one classical Gram-Schmidt pass, a second one only when the DGKS
-// test asks for it (decided on the device), Hessenberg columns kept on the device and read by
-// the host every kSync steps for the Givens rotations and the convergence test.
-// Returns the number of Arnoldi steps; *est = final recurrence residual / ||r||.
-int gmres_cycle(mtf_problem p, const double* r, double* x, int prec, bool use_pc, double tol, int maxit, double* est,
-                int* reorth) {
+// Inner operator A = M_prec P on the nb columns of slab src (ld n) into slab dst (ld n).
+void apply_inner(mtf_problem p, const double* src, double* dst, int nb, int prec, bool use_pc) {
+    GmresWork& w = p->gw;
+    const int64_t n = w.n;
+    const double* in = src;
+    if (use_pc) {
+        if (prec == MTF_BF16_SPLIT) apply_gemm(p, 1, nb, src, n, w.tmp.p);
+        else
+            for (int b = 0; b < nb; ++b) precond1(p, src + 2 * n * b, w.tmp.p + 2 * n * b);
+        in = w.tmp.p;
+    }
+    if (prec == MTF_BF16_SPLIT) apply_gemm(p, 0, nb, in, n, dst);
+    else
+        for (int b = 0; b < nb; ++b) matvec1(p, in + 2 * n * b, dst + 2 * n * b, prec);
+}
+
+// One GMRES cycle for nb right-hand sides in lockstep: residual slab R (ld n), corrections added to
+// the nb columns of X (ld ldx).  Arnoldi: one classical Gram-Schmidt pass, a second one only where
+// the DGKS test asks for it (decided on the device); Hessenberg columns stay on the device and the
+// host applies the Givens rotations every kSync steps.  Each right-hand side stops at its own step.
+// Returns the largest number of Arnoldi steps; it[b], est[b] (recurrence residual / ||r_b||) per column.
+int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, int prec, bool use_pc,
+                const std::vector<double>& tol, int maxit, std::vector<int>& itv, std::vector<double>& est,
+                std::vector<int>& reorth) {
     GmresWork& w = p->gw;
     hipStream_t s = p->stream;
     const int64_t n = w.n;
     const int64_t ldh = w.maxit + 1;
+    const int64_t hstride = ldh * (int64_t)w.maxit;
+    const int64_t ldv = n * nb;
+    const int nvmax = w.maxit;
     double* V = w.V.p;
-    auto Vc = [&](int j) { return V + 2 * n * (int64_t)j; };
+    auto Vs = [&](int j) { return V + 2 * ldv * (int64_t)j; };
     auto Hc = [&](int j) { return w.H.p + 2 * ldh * (int64_t)j; };
-    const double beta = norm_dev(p, r);
-    *est = 0.0;
-    if (beta == 0.0) return 0;
-    HIPCHK(hipMemcpyAsync(Vc(0), r, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    launch_axpby(Vc(0), Vc(0), n, 0.0, 0.0, 1.0 / beta, s);
-    HIPCHK(hipMemsetAsync(w.flag.p, 0, 2 * sizeof(int), s));
-    std::vector<cd> H((size_t)ldh * maxit, cd(0));
-    std::vector<double> cs(maxit, 0.0);
-    std::vector<cd> sn(maxit, cd(0)), gvec(maxit + 1, cd(0));
-    gvec[0] = beta;
-    int it = 0, done_cols = 0;
-    double resid = beta;
-    bool stop = false;
-    for (int j = 0; j < maxit && !stop; ++j) {
-        const double* src = Vc(j);
-        if (use_pc) { precond1(p, src, w.tmp.p); src = w.tmp.p; }
-        double* wv = Vc(j + 1);
-        matvec1(p, src, wv, prec);
+    std::vector<double> beta = norms_dev(p, R, n, nb);
+    launch_scale_dev(Vs(0), R, n, n, w.npart.p, kNblk, nullptr, 0, nb, s);
+    HIPCHK(hipMemsetAsync(w.flag.p, 0, 2 * nb * sizeof(int), s));
+    std::vector<std::vector<cd>> H(nb, std::vector<cd>((size_t)ldh * maxit, cd(0)));
+    std::vector<std::vector<double>> cs(nb, std::vector<double>(maxit, 0.0));
+    std::vector<std::vector<cd>> sn(nb, std::vector<cd>(maxit, cd(0))), gv(nb, std::vector<cd>(maxit + 1, cd(0)));
+    std::vector<char> stop(nb, 0);
+    std::vector<double> resid(beta);
+    itv.assign(nb, 0);
+    int live = 0;
+    for (int b = 0; b < nb; ++b) {
+        gv[b][0] = beta[b];
+        if (beta[b] == 0.0) stop[b] = 1; else ++live;
+    }
+    int done_cols = 0, steps = 0;
+    for (int j = 0; j < maxit && live > 0; ++j) {
+        double* wv = Vs(j + 1);
+        apply_inner(p, Vs(j), wv, nb, prec, use_pc);
         const int nv = j + 1;
-        launch_multidot(V, n, nv, wv, n, w.hpart.p, kNblk, 1, nullptr, s);
-        launch_reduce_h(w.hpart.p, nv, kNblk, w.h.p, Hc(j), w.wn2.p, 0, nullptr, s);
-        launch_update(V, n, nv, w.h.p, wv, n, w.upart.p, nullptr, s);
-        launch_norm2(wv, n, w.npart.p, kNblk, s);
-        launch_reorth_flag(w.wn2.p, w.npart.p, kNblk, w.flag.p, w.flag.p + 1, s);
-        launch_multidot(V, n, nv, wv, n, w.hpart.p, kNblk, 0, w.flag.p, s);
-        launch_reduce_h(w.hpart.p, nv, kNblk, w.h.p, Hc(j), w.wn2.p, 1, w.flag.p, s);
-        launch_update(V, n, nv, w.h.p, wv, n, w.upart.p, w.flag.p, s);
-        launch_norm2(wv, n, w.npart.p, kNblk, s);
-        launch_scale_dev(wv, wv, n, w.npart.p, kNblk, Hc(j) + 2 * (j + 1), s);
+        launch_multidot(V, ldv, nv, nvmax, wv, n, w.hpart.p, kNblk, 1, nullptr, nb, s);
+        launch_reduce_h(w.hpart.p, nv, nvmax, kNblk, w.h.p, Hc(j), hstride, w.wn2.p, 0, nullptr, nb, s);
+        launch_update(V, ldv, nv, nvmax, w.h.p, wv, n, w.upart.p, nullptr, nb, s);
+        launch_norm2(wv, n, n, w.npart.p, kNblk, nb, s);
+        launch_reorth_flag(w.wn2.p, w.npart.p, kNblk, nb, w.flag.p, w.flag.p + nb, s);
+        launch_multidot(V, ldv, nv, nvmax, wv, n, w.hpart.p, kNblk, 0, w.flag.p, nb, s);
+        launch_reduce_h(w.hpart.p, nv, nvmax, kNblk, w.h.p, Hc(j), hstride, w.wn2.p, 1, w.flag.p, nb, s);
+        launch_update(V, ldv, nv, nvmax, w.h.p, wv, n, w.upart.p, w.flag.p, nb, s);
+        launch_norm2(wv, n, n, w.npart.p, kNblk, nb, s);
+        launch_scale_dev(wv, wv, n, n, w.npart.p, kNblk, Hc(j) + 2 * (j + 1), hstride, nb, s);
+        steps = j + 1;
         if ((j + 1) % kSync != 0 && j + 1 != maxit) continue;
-        // host: Givens rotations for the columns produced since the last read
         const int c0 = done_cols, nc = j + 1 - done_cols;
-        HIPCHK(hipMemcpyAsync(w.host, Hc(c0), 2 * ldh * nc * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpy2DAsync(w.host, (size_t)2 * ldh * nc * sizeof(double), Hc(c0), (size_t)2 * hstride * sizeof(double),
+                                (size_t)2 * ldh * nc * sizeof(double), nb, hipMemcpyDeviceToHost, s));
         sync(p);
-        for (int q = 0; q < nc && !stop; ++q) {
-            const int jj = c0 + q;
-            cd* col = &H[(size_t)jj * ldh];
-            for (int i = 0; i <= jj + 1; ++i) col[i] = cd(w.host[2 * (ldh * q + i)], w.host[2 * (ldh * q + i) + 1]);
-            const double hn = col[jj + 1].real();
-            for (int i = 0; i < jj; ++i) {
-                const cd t = cs[i] * col[i] + sn[i] * col[i + 1];
-                col[i + 1] = -std::conj(sn[i]) * col[i] + cs[i] * col[i + 1];
-                col[i] = t;
+        for (int b = 0; b < nb; ++b) {
+            if (stop[b]) continue;
+            const double* hb = w.host + (size_t)2 * ldh * nc * b;
+            for (int q = 0; q < nc && !stop[b]; ++q) {
+                const int jj = c0 + q;
+                cd* col = &H[b][(size_t)jj * ldh];
+                for (int i = 0; i <= jj + 1; ++i) col[i] = cd(hb[2 * (ldh * q + i)], hb[2 * (ldh * q + i) + 1]);
+                const double hn = col[jj + 1].real();
+                for (int i = 0; i < jj; ++i) {
+                    const cd t = cs[b][i] * col[i] + sn[b][i] * col[i + 1];
+                    col[i + 1] = -std::conj(sn[b][i]) * col[i] + cs[b][i] * col[i + 1];
+                    col[i] = t;
+                }
+                const cd a = col[jj];
+                const double den = std::sqrt(std::norm(a) + hn * hn);
+                if (std::abs(a) == 0.0) { cs[b][jj] = 0.0; sn[b][jj] = 1.0; }
+                else { cs[b][jj] = std::abs(a) / den; sn[b][jj] = (a / std::abs(a)) * hn / den; }
+                col[jj] = cs[b][jj] * a + sn[b][jj] * hn;
+                col[jj + 1] = 0.0;
+                gv[b][jj + 1] = -std::conj(sn[b][jj]) * gv[b][jj];
+                gv[b][jj] = cs[b][jj] * gv[b][jj];
+                itv[b] = jj + 1;
+                resid[b] = std::abs(gv[b][jj + 1]);
+                if (!std::isfinite(resid[b])) throw NonFiniteError("GMRES produced a non-finite residual");
+                if (resid[b] <= tol[b] * beta[b] || hn == 0.0) { stop[b] = 1; --live; }
             }
-            const cd a = col[jj];
-            const double den = std::sqrt(std::norm(a) + hn * hn);
-            if (std::abs(a) == 0.0) { cs[jj] = 0.0; sn[jj] = 1.0; }
-            else { cs[jj] = std::abs(a) / den; sn[jj] = (a / std::abs(a)) * hn / den; }
-            col[jj] = cs[jj] * a + sn[jj] * hn;
-            col[jj + 1] = 0.0;
-            gvec[jj + 1] = -std::conj(sn[jj]) * gvec[jj];
-            gvec[jj] = cs[jj] * gvec[jj];
-            it = jj + 1;
-            resid = std::abs(gvec[jj + 1]);
-            if (!std::isfinite(resid)) throw NonFiniteError("GMRES produced a non-finite residual");
-            if (resid <= tol * beta || hn == 0.0) stop = true;
         }
         done_cols = j + 1;
     }
-    // back substitution on the first `it` columns
-    std::vector<cd> yv(it);
-    for (int i = it - 1; i >= 0; --i) {
-        cd acc = gvec[i];
-        for (int k = i + 1; k < it; ++k) acc -= H[(size_t)k * ldh + i] * yv[k];
-        yv[i] = acc / H[(size_t)i * ldh + i];
+    // back substitution per right-hand side, then X_b += P (V_b y_b)
+    std::vector<double> yh((size_t)2 * nb * (nvmax + 1), 0.0);
+    for (int b = 0; b < nb; ++b) {
+        const int it = itv[b];
+        std::vector<cd> yv(it);
+        for (int i = it - 1; i >= 0; --i) {
+            cd acc = gv[b][i];
+            for (int k = i + 1; k < it; ++k) acc -= H[b][(size_t)k * ldh + i] * yv[k];
+            yv[i] = acc / H[b][(size_t)i * ldh + i];
+        }
+        for (int i = 0; i < it; ++i) {
+            yh[(size_t)2 * b * (nvmax + 1) + 2 * i] = yv[i].real();
+            yh[(size_t)2 * b * (nvmax + 1) + 2 * i + 1] = yv[i].imag();
+        }
     }
-    std::vector<double> yh(2 * it);
-    for (int i = 0; i < it; ++i) { yh[2 * i] = yv[i].real(); yh[2 * i + 1] = yv[i].imag(); }
     HIPCHK(hipMemcpyAsync(w.y.p, yh.data(), yh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(w.cnt.p, itv.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
+    launch_fill(w.tmp2.p, 2 * n * nb, 0.0, s);
+    launch_combine(w.tmp2.p, n, V, ldv, w.cnt.p, nvmax, w.y.p, n, nb, s);
+    const double* corr = w.tmp2.p;
     if (use_pc) {
-        launch_fill(w.tmp2.p, 2 * n, 0.0, s);
-        launch_combine(w.tmp2.p, V, n, it, w.y.p, n, s);
-        precond1(p, w.tmp2.p, w.tmp.p);
-        launch_axpby(x, w.tmp.p, n, 1.0, 0.0, 1.0, s);
-    } else {
-        launch_combine(x, V, n, it, w.y.p, n, s);
+        if (prec == MTF_BF16_SPLIT) apply_gemm(p, 1, nb, w.tmp2.p, n, w.tmp.p);
+        else
+            for (int b = 0; b < nb; ++b) precond1(p, w.tmp2.p + 2 * n * b, w.tmp.p + 2 * n * b);
+        corr = w.tmp.p;
     }
-    int cnt[2];
-    HIPCHK(hipMemcpyAsync(cnt, w.flag.p, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    for (int b = 0; b < nb; ++b) launch_axpby(X + 2 * ldx * (int64_t)b, corr + 2 * n * b, n, 1.0, 0.0, 1.0, s);
+    std::vector<int> cnt(2 * nb);
+    HIPCHK(hipMemcpyAsync(cnt.data(), w.flag.p, cnt.size() * sizeof(int), hipMemcpyDeviceToHost, s));
     sync(p);
-    if (reorth) *reorth += cnt[1];
-    *est = resid / beta;
-    return it;
+    est.assign(nb, 0.0);
+    for (int b = 0; b < nb; ++b) {
+        reorth[b] += cnt[nb + b];
+        est[b] = beta[b] > 0 ? resid[b] / beta[b] : 0.0;
+    }
+    return steps;
 }
 
 int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int64_t ld, const mtf_solve_opts* o,
@@ -636,48 +690,68 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
     const bool use_pc = opts.preconditioner == MTF_PREC_BLOCK_TINV;
     double t_pc = 0;
     if (use_pc && !p->have_tinv) { build_tinv(p); t_pc = p->t_precond; }
-    gmres_alloc(p, maxit);
+    // right-hand sides advance in lockstep batches when the products are GEMMs
+    const int nbmax = prec == MTF_BF16_SPLIT ? std::min<int>(nrhs, kMaxBatch) : 1;
+    gmres_alloc(p, maxit, nbmax);
     GmresWork& w = p->gw;
     hipStream_t s = p->stream;
     const int64_t n = p->sk.N;
     int status = MTF_OK;
-    for (int rhs = 0; rhs < nrhs; ++rhs) {
+    for (int r0 = 0; r0 < nrhs; r0 += nbmax) {
+        const int nb = std::min(nbmax, nrhs - r0);
         auto t0 = std::chrono::steady_clock::now();
-        const double* b = static_cast<const double*>(b_dev) + 2 * ld * (int64_t)rhs;
-        double* x = static_cast<double*>(x_dev) + 2 * ld * (int64_t)rhs;
-        if (opts.x0_dev) HIPCHK(hipMemcpyAsync(x, static_cast<const double*>(opts.x0_dev) + 2 * ld * (int64_t)rhs,
-                                               2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        else launch_fill(x, 2 * n, 0.0, s);
-        const double bn = norm_dev(p, b);
-        int iters = 0, refin = 0, reorth = 0;
-        double rel = 1.0;
-        bool conv = false;
-        if (bn == 0.0) { conv = true; rel = 0.0; }
-        for (int outer = 0; !conv && outer <= maxref; ++outer) {
-            // true residual with the FP64 operator
-            matvec1(p, x, w.r.p, MTF_FP64);
-            launch_axpby(w.r.p, b, n, 1.0, 0.0, -1.0, s);   // r = b - M x
-            const double rn = norm_dev(p, w.r.p);
-            rel = rn / bn;
-            if (outer > 0) ++refin;
-            if (rel <= opts.rtol) { conv = true; break; }
-            if (outer == maxref || iters >= maxit * (maxref + 1)) break;
-            double tol = opts.rtol * bn / rn;
-            if (prec == MTF_FP32_MIXED) tol = std::max(tol, opts.inner_rtol > 0 ? opts.inner_rtol : 1e-6);
-            else if (opts.inner_rtol > 0) tol = std::max(tol, opts.inner_rtol);
-            double est = 0;
-            iters += gmres_cycle(p, w.r.p, x, prec, use_pc, 0.9 * tol, maxit, &est, &reorth);
+        const double* B = static_cast<const double*>(b_dev) + 2 * ld * (int64_t)r0;
+        double* X = static_cast<double*>(x_dev) + 2 * ld * (int64_t)r0;
+        for (int b = 0; b < nb; ++b) {
+            if (opts.x0_dev)
+                HIPCHK(hipMemcpyAsync(X + 2 * ld * b, static_cast<const double*>(opts.x0_dev) + 2 * ld * (int64_t)(r0 + b),
+                                      2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            else launch_fill(X + 2 * ld * b, 2 * n, 0.0, s);
         }
-        if (stats) {
-            stats[rhs].iterations = iters;
-            stats[rhs].refinements = refin;
-            stats[rhs].converged = conv ? 1 : 0;
-            stats[rhs].reorthogonalizations = reorth;
-            stats[rhs].rel_residual = rel;
-            stats[rhs].t_precond_s = rhs == 0 ? t_pc : 0.0;
-            stats[rhs].t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        const std::vector<double> bn = norms_dev(p, B, ld, nb);
+        std::vector<int> iters(nb, 0), refin(nb, 0), reorth(nb, 0), itv;
+        std::vector<double> rel(nb, 1.0), est;
+        std::vector<char> conv(nb, 0);
+        int total = 0;
+        for (int outer = 0; outer <= maxref; ++outer) {
+            // true residuals with the FP64 operator
+            for (int b = 0; b < nb; ++b) {
+                double* rb = w.r.p + 2 * n * b;
+                matvec1(p, X + 2 * ld * b, rb, MTF_FP64);
+                launch_axpby(rb, B + 2 * ld * b, n, 1.0, 0.0, -1.0, s);   // r = b - M x
+            }
+            const std::vector<double> rn = norms_dev(p, w.r.p, n, nb);
+            bool all = true;
+            std::vector<double> tol(nb, 1.0);
+            for (int b = 0; b < nb; ++b) {
+                rel[b] = bn[b] > 0 ? rn[b] / bn[b] : 0.0;
+                if (outer > 0 && !conv[b]) ++refin[b];
+                conv[b] = rel[b] <= opts.rtol;
+                if (conv[b]) { launch_fill(w.r.p + 2 * n * b, 2 * n, 0.0, s); continue; }
+                all = false;
+                double t = opts.rtol * bn[b] / rn[b];
+                if (prec != MTF_FP64) t = std::max(t, opts.inner_rtol > 0 ? opts.inner_rtol : 1e-6);
+                else if (opts.inner_rtol > 0) t = std::max(t, opts.inner_rtol);
+                tol[b] = 0.9 * t;
+            }
+            if (all || outer == maxref || total >= maxit * (maxref + 1)) break;
+            total += gmres_cycle(p, w.r.p, X, ld, nb, prec, use_pc, tol, maxit, itv, est, reorth);
+            for (int b = 0; b < nb; ++b) iters[b] += itv[b];
         }
-        if (!conv) status = MTF_NOT_CONVERGED;
+        const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (int b = 0; b < nb; ++b) {
+            if (stats) {
+                mtf_solve_stats& st = stats[r0 + b];
+                st.iterations = iters[b];
+                st.refinements = refin[b];
+                st.converged = conv[b] ? 1 : 0;
+                st.reorthogonalizations = reorth[b];
+                st.rel_residual = rel[b];
+                st.t_precond_s = (r0 + b) == 0 ? t_pc : 0.0;
+                st.t_solve_s = dt;
+            }
+            if (!conv[b]) status = MTF_NOT_CONVERGED;
+        }
     }
     return status;
 }

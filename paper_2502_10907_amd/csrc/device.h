@@ -88,21 +88,23 @@ void launch_matvec_finish(const DomDesc* doms, int ndom, const int32_t* dof_dom,
                           const int64_t* gcol, const double* part, const double* x, double* y,
                           hipStream_t s);
 
-// GMRES vector kernels (complex128, length n).  Kernels taking `flag` do nothing when *flag == 0.
-void launch_multidot(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* hpart,
-                     int nblk, int self, const int* flag, hipStream_t s);
-void launch_reduce_h(const double* hpart, int nv, int nblk, double* h, double* Hcol, double* wn2, int second,
-                     const int* flag, hipStream_t s);
-void launch_reorth_flag(const double* wn2, const double* part, int nblk, int* flag, int* count, hipStream_t s);
-void launch_update(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n, double* part,
-                   const int* flag, hipStream_t s);   // w -= V h (split over 64-vector chunks)
-void launch_norm2(const double* w, int64_t n, double* part, int nblk, hipStream_t s);
+// GMRES vector kernels (complex128, length n), batched over nb right-hand sides in lockstep
+// (Krylov slab j at V + j*ldv with ldv = nb*n; column b of each slab is right-hand side b).
+// Kernels taking `flag` skip right-hand side b when flag[b] == 0.
+void launch_multidot(const double* V, int64_t ldv, int nv, int nvmax, const double* w, int64_t n, double* hpart,
+                     int nblk, int self, const int* flag, int nb, hipStream_t s);
+void launch_reduce_h(const double* hpart, int nv, int nvmax, int nblk, double* h, double* Hcol, int64_t hstride,
+                     double* wn2, int second, const int* flag, int nb, hipStream_t s);
+void launch_reorth_flag(const double* wn2, const double* part, int nblk, int nb, int* flag, int* count, hipStream_t s);
+void launch_update(const double* V, int64_t ldv, int nv, int nvmax, const double* h, double* w, int64_t n,
+                   double* part, const int* flag, int nb, hipStream_t s);   // w_b -= V_b h_b
+void launch_combine(double* x, int64_t ldx, const double* V, int64_t ldv, const int* cnt, int nvmax, const double* coef,
+                    int64_t n, int nb, hipStream_t s);                       // x_b += V_b coef_b
+void launch_norm2(const double* w, int64_t ldw, int64_t n, double* part, int nblk, int nb, hipStream_t s);
 void launch_axpby(double* y, const double* x, int64_t n, double a_re, double a_im, double b,
                   hipStream_t s);       // y = b*y + a*x (a complex, b real)
-void launch_scale_dev(double* y, const double* x, int64_t n, const double* part, int nblk, double* hsub,
-                      hipStream_t s);   // y = x / sqrt(sum parts); hsub (if set) = that norm
-void launch_combine(double* x, const double* V, int64_t ldv, int nv, const double* coef, int64_t n,
-                    hipStream_t s);     // x += V coef
+void launch_scale_dev(double* y, const double* x, int64_t ld, int64_t n, const double* part, int nblk, double* hsub,
+                      int64_t hstride, int nb, hipStream_t s);   // y_b = x_b / ||x_b||, hsub_b = ||x_b||
 
 void launch_far_field(const DomDesc* d0, const TriGeom* geom, const int32_t* tdof, const int8_t* tsign,
                       int32_t T0, double k0, double rho0, const double* x, int64_t ldx, int nrhs,
@@ -122,14 +124,15 @@ void launch_precond_finish(const DomDesc* doms, int ndom, const int32_t* dof_dom
 void launch_nonfinite_check(const float* A, int64_t n, int* flag, hipStream_t s);
 
 // Multi-RHS block products (gemm.hip).
+// mode 0: operator blocks [K_i | T_i]; mode 1: preconditioner blocks T_i^-1 (passed as T).
 void launch_split_A(const GemmDesc* descs, const DomDesc* doms, const int4* tiles, int64_t ntiles, const float* T,
-                    const float* K, uint16_t* A, hipStream_t s);
+                    const float* K, uint16_t* A, int mode, hipStream_t s);
 void launch_split_B(const GemmDesc* descs, const DomDesc* doms, int ndom, int64_t kp_max, int64_t np, const double* x,
-                    int64_t ld, int nrhs, uint16_t* B, hipStream_t s);
+                    int64_t ld, int nrhs, uint16_t* B, int mode, hipStream_t s);
 void launch_gemm_bf16x3(const GemmDesc* descs, const int4* tiles, int64_t ntiles, const uint16_t* A, const uint16_t* B,
                         float* C, hipStream_t s);
 void launch_gemm_finish(const DomDesc* doms, const GemmDesc* descs, const int32_t* dof_dom, int64_t ndof,
                         const int32_t* dplus, const int32_t* dminus, const double* gval, const int64_t* gcol,
-                        const float* C, const double* x, double* y, int64_t ld, int nrhs, hipStream_t s);
+                        const float* C, const double* x, double* y, int64_t ld, int nrhs, int mode, hipStream_t s);
 
 }  // namespace mtf

@@ -124,11 +124,13 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(const GemmDesc* __restrict_
             }
 }
 
-// A planes of subdomain i: A[r][k] = K_i[r, k] (k < E), T_i[r, k - E] (E <= k < 2E), 0 in the padding.
-// 64 x 64 tiles transposed through LDS: column-major reads and row-major writes both coalesced.
+// A planes of subdomain i.  mode 0 (operator): A[r][k] = K_i[r, k] (k < E), T_i[r, k - E]
+// (E <= k < 2E); mode 1 (preconditioner): A[r][k] = (T_i^-1)[r, k] (k < E), passed as T.
+// Zero in the padding.  64 x 64 tiles transposed through LDS: column-major reads and row-major
+// writes both coalesced.
 __global__ __launch_bounds__(256) void k_split_A(const GemmDesc* __restrict__ descs, const DomDesc* __restrict__ doms,
                                                  const int4* __restrict__ tiles, const float* __restrict__ T,
-                                                 const float* __restrict__ K, uint16_t* __restrict__ Abase) {
+                                                 const float* __restrict__ K, uint16_t* __restrict__ Abase, int mode) {
     __shared__ float2 tile[64][65];
     const int4 tl = tiles[blockIdx.x];     // (dom, r0, k0)
     const GemmDesc g = descs[tl.x];
@@ -141,7 +143,11 @@ __global__ __launch_bounds__(256) void k_split_A(const GemmDesc* __restrict__ de
         const int rr = e & 63, kk = e >> 6;
         const int r = r0 + rr, k = k0 + kk;
         float2 v = make_float2(0.f, 0.f);
-        if (r < E && k < 2 * E) v = (k < E) ? K2[r + (int64_t)k * E] : T2[r + (int64_t)(k - E) * E];
+        if (mode == 0) {
+            if (r < E && k < 2 * E) v = (k < E) ? K2[r + (int64_t)k * E] : T2[r + (int64_t)(k - E) * E];
+        } else if (r < E && k < E) {
+            v = T2[r + (int64_t)k * E];
+        }
         tile[rr][kk] = v;
     }
     __syncthreads();
@@ -164,10 +170,11 @@ __global__ __launch_bounds__(256) void k_split_A(const GemmDesc* __restrict__ de
 }
 
 // B planes of subdomain i for nrhs vectors x (complex128, column j at x + j*ld):
-//   column j       : [2 x_iD ; 2/rho x_iN]      column nrhs + j : [2 x_iN ; -2 rho x_iD]
+//   mode 0: column j : [2 x_iD ; 2/rho x_iN]    column nrhs + j : [2 x_iN ; -2 rho x_iD]
+//   mode 1: column j : -x_iN / (2 rho)           column nrhs + j : rho/2 x_iD
 __global__ __launch_bounds__(256) void k_split_B(const GemmDesc* __restrict__ descs, const DomDesc* __restrict__ doms,
                                                  int ndom, const double* __restrict__ x, int64_t ld, int nrhs,
-                                                 uint16_t* __restrict__ Bbase) {
+                                                 uint16_t* __restrict__ Bbase, int mode) {
     const int dom = blockIdx.z;
     const GemmDesc g = descs[dom];
     const DomDesc dd = doms[dom];
@@ -176,14 +183,19 @@ __global__ __launch_bounds__(256) void k_split_B(const GemmDesc* __restrict__ de
     if (k >= g.Kp || n >= g.Np) return;
     const int E = dd.E;
     double vr = 0.0, vi = 0.0;
-    if (n < 2 * nrhs && k < 2 * E) {
+    if (n < 2 * nrhs && k < (mode == 0 ? 2 * E : E)) {
         const int j = (int)(n % nrhs);
         const bool second = n >= nrhs;
         const double* xc = x + 2 * ((int64_t)j * ld + dd.off);
         double s;
         int64_t src;
-        if (!second) { if (k < E) { s = 2.0; src = k; } else { s = 2.0 / dd.rho; src = E + (k - E); } }
-        else { if (k < E) { s = 2.0; src = E + k; } else { s = -2.0 * dd.rho; src = k - E; } }
+        if (mode == 0) {
+            if (!second) { if (k < E) { s = 2.0; src = k; } else { s = 2.0 / dd.rho; src = E + (k - E); } }
+            else { if (k < E) { s = 2.0; src = E + k; } else { s = -2.0 * dd.rho; src = k - E; } }
+        } else {
+            if (!second) { s = -0.5 / dd.rho; src = E + k; }
+            else { s = 0.5 * dd.rho; src = k; }
+        }
         vr = s * xc[2 * src];
         vi = s * xc[2 * src + 1];
     }
@@ -199,13 +211,13 @@ __global__ __launch_bounds__(256) void k_split_B(const GemmDesc* __restrict__ de
     B[3 * pb + idx] = l;
 }
 
-// y = [C_D ; C_N] + transmission, one thread per (dof, right-hand side).
+// y = [C_D ; C_N] (+ transmission in mode 0), one thread per (dof, right-hand side).
 __global__ __launch_bounds__(256) void k_gemm_finish(const DomDesc* __restrict__ doms, const GemmDesc* __restrict__ descs,
                                                      const int32_t* __restrict__ dof_dom, int64_t ndof,
                                                      const int32_t* __restrict__ dplus, const int32_t* __restrict__ dminus,
                                                      const double* __restrict__ gval, const int64_t* __restrict__ gcol,
                                                      const float* __restrict__ Cbase, const double* __restrict__ x,
-                                                     double* __restrict__ y, int64_t ld, int nrhs) {
+                                                     double* __restrict__ y, int64_t ld, int nrhs, int mode) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (g >= ndof) return;
@@ -218,7 +230,7 @@ __global__ __launch_bounds__(256) void k_gemm_finish(const DomDesc* __restrict__
     double yD[2] = {C[2 * (m + (int64_t)j * gd.ldc)], C[2 * (m + (int64_t)j * gd.ldc) + 1]};
     double yN[2] = {C[2 * (m + (int64_t)(nrhs + j) * gd.ldc)], C[2 * (m + (int64_t)(nrhs + j) * gd.ldc) + 1]};
     const double* xj = x + 2 * (int64_t)j * ld;
-    for (int side = 0; side < 2; ++side) {
+    for (int side = 0; side < (mode == 0 ? 2 : 0); ++side) {
         const int32_t* pm = side == 0 ? dplus : dminus;
         const int64_t rec = dd.rec0 + pm[2 * g];
         const int a = pm[2 * g + 1];
@@ -248,22 +260,22 @@ void launch_gemm_bf16x3(const GemmDesc* descs, const int4* tiles, int64_t ntiles
 }
 
 void launch_split_A(const GemmDesc* descs, const DomDesc* doms, const int4* tiles, int64_t ntiles, const float* T,
-                    const float* K, uint16_t* A, hipStream_t s) {
+                    const float* K, uint16_t* A, int mode, hipStream_t s) {
     if (ntiles <= 0) return;
-    hipLaunchKernelGGL(k_split_A, dim3((unsigned)ntiles), dim3(256), 0, s, descs, doms, tiles, T, K, A);
+    hipLaunchKernelGGL(k_split_A, dim3((unsigned)ntiles), dim3(256), 0, s, descs, doms, tiles, T, K, A, mode);
 }
 
 void launch_split_B(const GemmDesc* descs, const DomDesc* doms, int ndom, int64_t kp_max, int64_t np, const double* x,
-                    int64_t ld, int nrhs, uint16_t* B, hipStream_t s) {
+                    int64_t ld, int nrhs, uint16_t* B, int mode, hipStream_t s) {
     hipLaunchKernelGGL(k_split_B, dim3(gridn(kp_max, 256), (unsigned)np, (unsigned)ndom), dim3(256), 0, s, descs, doms,
-                       ndom, x, ld, nrhs, B);
+                       ndom, x, ld, nrhs, B, mode);
 }
 
 void launch_gemm_finish(const DomDesc* doms, const GemmDesc* descs, const int32_t* dof_dom, int64_t ndof,
                         const int32_t* dplus, const int32_t* dminus, const double* gval, const int64_t* gcol,
-                        const float* C, const double* x, double* y, int64_t ld, int nrhs, hipStream_t s) {
+                        const float* C, const double* x, double* y, int64_t ld, int nrhs, int mode, hipStream_t s) {
     hipLaunchKernelGGL(k_gemm_finish, dim3(gridn(ndof, 256), (unsigned)nrhs), dim3(256), 0, s, doms, descs, dof_dom, ndof,
-                       dplus, dminus, gval, gcol, C, x, y, ld, nrhs);
+                       dplus, dminus, gval, gcol, C, x, y, ld, nrhs, mode);
 }
 
 }  // namespace mtf

@@ -165,17 +165,24 @@ __device__ inline double wsum(double v) {
     return v;
 }
 
-// hpart[i * nblk + blk] = sum_{n in chunk blk} conj(V_i[n]) w[n] for i < nv; with `self`, slot nv
-// receives w^H w.  Skipped entirely when `flag` is given and *flag == 0.
-__global__ __launch_bounds__(256) void k_multidot(const double* __restrict__ V, int64_t ldv, int nv,
-                                                  const double* __restrict__ w, int64_t n, double* __restrict__ hpart,
+// Batched Arnoldi kernels.  nb right-hand sides advance in lockstep: Krylov block j is an
+// n x nb column-major slab at V + j*ldv (ldv = nb*n), column b of every slab belongs to
+// right-hand side b (gridDim.z or blockIdx.z = b).  Per right-hand side b:
+//   hpart[(b*(nvmax+1) + i) * nblk + blk]  partial dots,   h[b*(nvmax+1) + i]  reduced dots,
+//   H + b*hstride + column j               Hessenberg column,   wn2[b], flag[b], npart[b*nblk + k].
+
+// conj(V_i) . w for i < nv (and w . w in slot nv when `self`); skipped where flag[b] == 0.
+__global__ __launch_bounds__(256) void k_multidot(const double* __restrict__ V, int64_t ldv, int nv, int nvmax,
+                                                  const double* __restrict__ W, int64_t n, double* __restrict__ hpart,
                                                   int nblk, const int* __restrict__ flag) {
-    if (flag && *flag == 0) return;
+    const int b = blockIdx.z;
+    if (flag && flag[b] == 0) return;
     const int i = blockIdx.y;
     const int blk = blockIdx.x;
     const int64_t chunk = (n + nblk - 1) / nblk;
     const int64_t lo = blk * chunk, hi = min(n, lo + chunk);
-    const double* v = (i == nv) ? w : V + 2 * (int64_t)i * ldv;
+    const double* w = W + 2 * (int64_t)b * n;
+    const double* v = (i == nv) ? w : V + 2 * ((int64_t)i * ldv + (int64_t)b * n);
     double re = 0, im = 0;
     for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
         const double vr = v[2 * e], vi = v[2 * e + 1], wr = w[2 * e], wi = w[2 * e + 1];
@@ -189,56 +196,64 @@ __global__ __launch_bounds__(256) void k_multidot(const double* __restrict__ V, 
     if (lane == 0) { red[0][wv] = re; red[1][wv] = im; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double a = 0, b = 0;
-        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { a += red[0][k]; b += red[1][k]; }
-        hpart[2 * ((int64_t)i * nblk + blk)] = a;
-        hpart[2 * ((int64_t)i * nblk + blk) + 1] = b;
+        double a = 0, c = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { a += red[0][k]; c += red[1][k]; }
+        const int64_t slot = ((int64_t)b * (nvmax + 1) + i) * nblk + blk;
+        hpart[2 * slot] = a;
+        hpart[2 * slot + 1] = c;
     }
 }
 
-// h[i] = sum of partials; Hcol[i] = h[i] (first pass) or Hcol[i] + h[i] (second pass);
-// slot nv (first pass only) gives wn2 = w^H w.
-__global__ void k_reduce_h(const double* __restrict__ hpart, int nv, int nblk, double* __restrict__ h,
-                           double* __restrict__ Hcol, double* __restrict__ wn2, int second,
+__global__ void k_reduce_h(const double* __restrict__ hpart, int nv, int nvmax, int nblk, double* __restrict__ h,
+                           double* __restrict__ Hcol, int64_t hstride, double* __restrict__ wn2, int second,
                            const int* __restrict__ flag) {
-    if (flag && *flag == 0) return;
+    const int b = blockIdx.y;
+    if (flag && flag[b] == 0) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int top = second ? nv : nv + 1;
     if (i >= top) return;
-    double a = 0, b = 0;
-    for (int k = 0; k < nblk; ++k) { a += hpart[2 * ((int64_t)i * nblk + k)]; b += hpart[2 * ((int64_t)i * nblk + k) + 1]; }
-    if (i == nv) { wn2[0] = a; return; }
-    h[2 * i] = a;
-    h[2 * i + 1] = b;
-    if (second) { Hcol[2 * i] += a; Hcol[2 * i + 1] += b; }
-    else { Hcol[2 * i] = a; Hcol[2 * i + 1] = b; }
+    double a = 0, c = 0;
+    const int64_t base = ((int64_t)b * (nvmax + 1) + i) * nblk;
+    for (int k = 0; k < nblk; ++k) { a += hpart[2 * (base + k)]; c += hpart[2 * (base + k) + 1]; }
+    if (i == nv) { wn2[b] = a; return; }
+    double* hb = h + 2 * ((int64_t)b * (nvmax + 1));
+    double* Hb = Hcol + 2 * (int64_t)b * hstride;
+    hb[2 * i] = a;
+    hb[2 * i + 1] = c;
+    if (second) { Hb[2 * i] += a; Hb[2 * i + 1] += c; }
+    else { Hb[2 * i] = a; Hb[2 * i + 1] = c; }
 }
 
 // Second Gram-Schmidt pass only when the first lost too much: ||w'||^2 < ||w||^2 / 2 (DGKS test).
-__global__ void k_reorth_flag(const double* __restrict__ wn2, const double* __restrict__ part, int nblk,
+__global__ void k_reorth_flag(const double* __restrict__ wn2, const double* __restrict__ part, int nblk, int nb,
                               int* __restrict__ flag, int* __restrict__ count) {
+    const int b = threadIdx.x;
+    if (b >= nb) return;
     double s = 0;
-    for (int k = 0; k < nblk; ++k) s += part[k];
-    const int f = s < 0.5 * wn2[0] ? 1 : 0;
-    flag[0] = f;
-    count[0] += f;
+    for (int k = 0; k < nblk; ++k) s += part[(int64_t)b * nblk + k];
+    const int f = s < 0.5 * wn2[b] ? 1 : 0;
+    flag[b] = f;
+    count[b] += f;
 }
 
-// part[c][e] = sum_{i in vector chunk c} V_i[e] h[i]   (64 vectors per chunk)
-__global__ __launch_bounds__(256) void k_update_part(const double* __restrict__ V, int64_t ldv, int nv,
+// part[(b*nch + c)][e] = sum_{i in vector chunk c} V_i[e] h[i]   (64 vectors per chunk)
+__global__ __launch_bounds__(256) void k_update_part(const double* __restrict__ V, int64_t ldv, int nv, int nvmax,
                                                      const double* __restrict__ h, double* __restrict__ part,
                                                      int64_t n, const int* __restrict__ flag) {
-    if (flag && *flag == 0) return;
+    const int b = blockIdx.z;
+    if (flag && flag[b] == 0) return;
     __shared__ double hs[2 * 64];
     const int c = blockIdx.y;
+    const int nch = gridDim.y;
     const int i0 = c * 64;
     const int cnt = min(64, nv - i0);
-    if ((int)threadIdx.x < cnt) { hs[2 * threadIdx.x] = h[2 * (i0 + threadIdx.x)]; hs[2 * threadIdx.x + 1] = h[2 * (i0 + threadIdx.x) + 1]; }
+    const double* hb = h + 2 * ((int64_t)b * (nvmax + 1));
+    if ((int)threadIdx.x < cnt) { hs[2 * threadIdx.x] = hb[2 * (i0 + threadIdx.x)]; hs[2 * threadIdx.x + 1] = hb[2 * (i0 + threadIdx.x) + 1]; }
     __syncthreads();
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     double re = 0, im = 0;
-    const double* v = V + 2 * ((int64_t)i0 * ldv + e);
+    const double* v = V + 2 * ((int64_t)i0 * ldv + (int64_t)b * n + e);
     int i = 0;
     for (; i + 8 <= cnt; i += 8) {
         double vr[8], vi[8];
@@ -257,67 +272,59 @@ __global__ __launch_bounds__(256) void k_update_part(const double* __restrict__ 
         re += vr * hr - vi * hi;
         im += vr * hi + vi * hr;
     }
-    part[2 * ((int64_t)c * n + e)] = re;
-    part[2 * ((int64_t)c * n + e) + 1] = im;
+    const int64_t slot = ((int64_t)b * nch + c) * n + e;
+    part[2 * slot] = re;
+    part[2 * slot + 1] = im;
 }
 
-__global__ __launch_bounds__(256) void k_update_apply(const double* __restrict__ part, int nchunk, double* __restrict__ w,
+__global__ __launch_bounds__(256) void k_update_apply(const double* __restrict__ part, int nchunk, double* __restrict__ W,
                                                       int64_t n, const int* __restrict__ flag) {
-    if (flag && *flag == 0) return;
+    const int b = blockIdx.y;
+    if (flag && flag[b] == 0) return;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     double re = 0, im = 0;
-    for (int c = 0; c < nchunk; ++c) { re += part[2 * ((int64_t)c * n + e)]; im += part[2 * ((int64_t)c * n + e) + 1]; }
+    for (int c = 0; c < nchunk; ++c) {
+        const int64_t slot = ((int64_t)b * nchunk + c) * n + e;
+        re += part[2 * slot];
+        im += part[2 * slot + 1];
+    }
+    double* w = W + 2 * (int64_t)b * n;
     w[2 * e] -= re;
     w[2 * e + 1] -= im;
 }
 
-// w -= V h
-__global__ __launch_bounds__(256) void k_update(const double* __restrict__ V, int64_t ldv, int nv,
-                                                const double* __restrict__ h, double* __restrict__ w, int64_t n) {
-    __shared__ double hs[2 * 256];
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double re = 0, im = 0;
-    for (int i0 = 0; i0 < nv; i0 += 256) {
-        const int cnt = min(256, nv - i0);
-        __syncthreads();
-        if ((int)threadIdx.x < cnt) { hs[2 * threadIdx.x] = h[2 * (i0 + threadIdx.x)]; hs[2 * threadIdx.x + 1] = h[2 * (i0 + threadIdx.x) + 1]; }
-        __syncthreads();
-        if (e < n) {
-            for (int i = 0; i < cnt; ++i) {
-                const double* v = V + 2 * ((int64_t)(i0 + i) * ldv + e);
-                const double vr = v[0], vi = v[1], hr = hs[2 * i], hi = hs[2 * i + 1];
-                re += vr * hr - vi * hi;
-                im += vr * hi + vi * hr;
-            }
-        }
-    }
-    if (e < n) { w[2 * e] -= re; w[2 * e + 1] -= im; }
-}
-
-// x += V coef
-__global__ __launch_bounds__(256) void k_combine(double* __restrict__ x, const double* __restrict__ V, int64_t ldv, int nv,
+// x_b += V_b coef_b over the first cnt[b] vectors (column b of each slab)
+__global__ __launch_bounds__(256) void k_combine(double* __restrict__ X, int64_t ldx, const double* __restrict__ V,
+                                                 int64_t ldv, const int* __restrict__ cnt, int nvmax,
                                                  const double* __restrict__ coef, int64_t n) {
+    const int b = blockIdx.y;
     __shared__ double hs[2 * 256];
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nv = cnt[b];
+    const double* cb = coef + 2 * ((int64_t)b * (nvmax + 1));
     double re = 0, im = 0;
     for (int i0 = 0; i0 < nv; i0 += 256) {
-        const int cnt = min(256, nv - i0);
+        const int m = min(256, nv - i0);
         __syncthreads();
-        if ((int)threadIdx.x < cnt) { hs[2 * threadIdx.x] = coef[2 * (i0 + threadIdx.x)]; hs[2 * threadIdx.x + 1] = coef[2 * (i0 + threadIdx.x) + 1]; }
+        if ((int)threadIdx.x < m) { hs[2 * threadIdx.x] = cb[2 * (i0 + threadIdx.x)]; hs[2 * threadIdx.x + 1] = cb[2 * (i0 + threadIdx.x) + 1]; }
         __syncthreads();
         if (e < n) {
-            for (int i = 0; i < cnt; ++i) {
-                const double* v = V + 2 * ((int64_t)(i0 + i) * ldv + e);
+            for (int i = 0; i < m; ++i) {
+                const double* v = V + 2 * ((int64_t)(i0 + i) * ldv + (int64_t)b * n + e);
                 re += v[0] * hs[2 * i] - v[1] * hs[2 * i + 1];
                 im += v[0] * hs[2 * i + 1] + v[1] * hs[2 * i];
             }
         }
     }
-    if (e < n) { x[2 * e] += re; x[2 * e + 1] += im; }
+    if (e < n) { X[2 * ((int64_t)b * ldx + e)] += re; X[2 * ((int64_t)b * ldx + e) + 1] += im; }
 }
 
-__global__ __launch_bounds__(256) void k_norm2(const double* __restrict__ w, int64_t n, double* __restrict__ part, int nblk) {
+// part[b*nblk + blk] = sum |w_b|^2 over chunk blk
+__global__ __launch_bounds__(256) void k_norm2(const double* __restrict__ W, int64_t ldw, int64_t n, double* __restrict__ part,
+                                               int nblk) {
+    const int b = blockIdx.y;
+    const double* w = W + 2 * (int64_t)b * ldw;
     const int64_t chunk = (n + nblk - 1) / nblk;
     const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
     double s = 0;
@@ -329,7 +336,7 @@ __global__ __launch_bounds__(256) void k_norm2(const double* __restrict__ w, int
     if (threadIdx.x == 0) {
         double a = 0;
         for (int k = 0; k < (int)(blockDim.x >> 6); ++k) a += red[k];
-        part[blockIdx.x] = a;
+        part[(int64_t)b * nblk + blockIdx.x] = a;
     }
 }
 
@@ -341,17 +348,19 @@ __global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, in
     y[2 * e + 1] = b * y[2 * e + 1] + ar * xi + ai * xr;
 }
 
-__global__ void k_scale_dev(double* __restrict__ y, const double* __restrict__ x, int64_t n,
-                            const double* __restrict__ part, int nblk, double* __restrict__ hsub) {
+// y_b = x_b / ||x_b|| (norm from the partial sums; 0 stays 0); hsub + b*hstride receives the norm.
+__global__ void k_scale_dev(double* __restrict__ Y, const double* __restrict__ X, int64_t ld, int64_t n,
+                            const double* __restrict__ part, int nblk, double* __restrict__ hsub, int64_t hstride) {
+    const int b = blockIdx.y;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double s = 0;
-    for (int k = 0; k < nblk; ++k) s += part[k];
+    for (int k = 0; k < nblk; ++k) s += part[(int64_t)b * nblk + k];
     const double nrm = sqrt(s);
-    if (e == 0 && hsub) { hsub[0] = nrm; hsub[1] = 0.0; }
+    if (e == 0 && hsub) { hsub[2 * (int64_t)b * hstride] = nrm; hsub[2 * (int64_t)b * hstride + 1] = 0.0; }
     if (e >= n) return;
     const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
-    y[2 * e] = x[2 * e] * inv;
-    y[2 * e + 1] = x[2 * e + 1] * inv;
+    Y[2 * ((int64_t)b * ld + e)] = X[2 * ((int64_t)b * ld + e)] * inv;
+    Y[2 * ((int64_t)b * ld + e) + 1] = X[2 * ((int64_t)b * ld + e) + 1] * inv;
 }
 
 // ---------------------------------------------------------------------------
@@ -539,43 +548,47 @@ void launch_precond_finish(const DomDesc* doms, int /*ndom*/, const int32_t* dof
     hipLaunchKernelGGL(k_pc_finish, dim3(gridn(ndof, 256)), dim3(256), 0, s, doms, dof_dom, ndof, part, z);
 }
 
-void launch_multidot(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* hpart, int nblk,
-                     int self, const int* flag, hipStream_t s) {
-    hipLaunchKernelGGL(k_multidot, dim3((unsigned)nblk, (unsigned)(nv + (self ? 1 : 0))), dim3(256), 0, s, V, ldv, nv, w,
-                       n, hpart, nblk, flag);
+void launch_multidot(const double* V, int64_t ldv, int nv, int nvmax, const double* w, int64_t n, double* hpart,
+                     int nblk, int self, const int* flag, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(k_multidot, dim3((unsigned)nblk, (unsigned)(nv + (self ? 1 : 0)), (unsigned)nb), dim3(256), 0, s,
+                       V, ldv, nv, nvmax, w, n, hpart, nblk, flag);
 }
 
-void launch_reduce_h(const double* hpart, int nv, int nblk, double* h, double* Hcol, double* wn2, int second,
-                     const int* flag, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_h, dim3(gridn(nv + 1, 128)), dim3(128), 0, s, hpart, nv, nblk, h, Hcol, wn2, second, flag);
+void launch_reduce_h(const double* hpart, int nv, int nvmax, int nblk, double* h, double* Hcol, int64_t hstride,
+                     double* wn2, int second, const int* flag, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_h, dim3(gridn(nv + 1, 128), (unsigned)nb), dim3(128), 0, s, hpart, nv, nvmax, nblk, h,
+                       Hcol, hstride, wn2, second, flag);
 }
 
-void launch_reorth_flag(const double* wn2, const double* part, int nblk, int* flag, int* count, hipStream_t s) {
-    hipLaunchKernelGGL(k_reorth_flag, dim3(1), dim3(1), 0, s, wn2, part, nblk, flag, count);
+void launch_reorth_flag(const double* wn2, const double* part, int nblk, int nb, int* flag, int* count, hipStream_t s) {
+    hipLaunchKernelGGL(k_reorth_flag, dim3(1), dim3(256), 0, s, wn2, part, nblk, nb, flag, count);
 }
 
-void launch_update(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n, double* part,
-                   const int* flag, hipStream_t s) {
+void launch_update(const double* V, int64_t ldv, int nv, int nvmax, const double* h, double* w, int64_t n,
+                   double* part, const int* flag, int nb, hipStream_t s) {
     const int nchunk = (nv + 63) / 64;
-    hipLaunchKernelGGL(k_update_part, dim3(gridn(n, 256), (unsigned)nchunk), dim3(256), 0, s, V, ldv, nv, h, part, n, flag);
-    hipLaunchKernelGGL(k_update_apply, dim3(gridn(n, 256)), dim3(256), 0, s, part, nchunk, w, n, flag);
+    hipLaunchKernelGGL(k_update_part, dim3(gridn(n, 256), (unsigned)nchunk, (unsigned)nb), dim3(256), 0, s, V, ldv, nv,
+                       nvmax, h, part, n, flag);
+    hipLaunchKernelGGL(k_update_apply, dim3(gridn(n, 256), (unsigned)nb), dim3(256), 0, s, part, nchunk, w, n, flag);
 }
 
-void launch_combine(double* x, const double* V, int64_t ldv, int nv, const double* coef, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_combine, dim3(gridn(n, 256)), dim3(256), 0, s, x, V, ldv, nv, coef, n);
+void launch_combine(double* x, int64_t ldx, const double* V, int64_t ldv, const int* cnt, int nvmax, const double* coef,
+                    int64_t n, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(k_combine, dim3(gridn(n, 256), (unsigned)nb), dim3(256), 0, s, x, ldx, V, ldv, cnt, nvmax, coef, n);
 }
 
-void launch_norm2(const double* w, int64_t n, double* part, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL(k_norm2, dim3((unsigned)nblk), dim3(256), 0, s, w, n, part, nblk);
+void launch_norm2(const double* w, int64_t ldw, int64_t n, double* part, int nblk, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(k_norm2, dim3((unsigned)nblk, (unsigned)nb), dim3(256), 0, s, w, ldw, n, part, nblk);
 }
 
 void launch_axpby(double* y, const double* x, int64_t n, double ar, double ai, double b, hipStream_t s) {
     hipLaunchKernelGGL(k_axpby, dim3(gridn(n, 256)), dim3(256), 0, s, y, x, n, ar, ai, b);
 }
 
-void launch_scale_dev(double* y, const double* x, int64_t n, const double* part, int nblk, double* hsub,
-                      hipStream_t s) {
-    hipLaunchKernelGGL(k_scale_dev, dim3(gridn(n, 256)), dim3(256), 0, s, y, x, n, part, nblk, hsub);
+void launch_scale_dev(double* y, const double* x, int64_t ld, int64_t n, const double* part, int nblk, double* hsub,
+                      int64_t hstride, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_dev, dim3(gridn(n, 256), (unsigned)nb), dim3(256), 0, s, y, x, ld, n, part, nblk, hsub,
+                       hstride);
 }
 
 void launch_copy_block_f64_to_f32(const double* src, float* dst, int64_t n, hipStream_t s) {

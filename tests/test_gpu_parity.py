@@ -207,3 +207,40 @@ def test_matvec_bf16_split_mfma(name, nrhs, request):
     y32 = torch.zeros_like(x)
     c.P.matvec(x, y32, mtf.FP32_MIXED)
     assert np.linalg.norm(got - y32.cpu().numpy()) / np.linalg.norm(got) < 1e-4
+
+
+def _multi_rhs(c, nrhs):
+    d = mi.fibonacci_directions(nrhs)
+    et, ep = mi.polarisations(d)
+    p = np.where(np.arange(nrhs)[:, None] % 2 == 0, et, ep).astype(np.complex128)
+    bo = sy.rhs(c.pb, d, p)                               # oracle right-hand sides [N, nrhs]
+    xo = np.linalg.solve(c.M, bo)
+    b = torch.zeros((nrhs, c.P.N), dtype=torch.complex128, device="cuda")
+    c.P.rhs_plane_waves(d, p, b)
+    assert _rel(b.cpu().numpy().T, bo) < 1e-13
+    return b, xo
+
+
+@pytest.mark.parametrize("name", ["sphere", "cube"])
+def test_solve_batched_bf16_lockstep(name, request):
+    """Right-hand sides in lockstep with MFMA block products (operator and preconditioner) inside
+    GMRES and FP64 residuals outside: every column reaches the FP64 tolerance and the LU solution."""
+    c = request.getfixturevalue(name)
+    b, xo = _multi_rhs(c, 5)
+    x = torch.zeros_like(b)
+    st = c.P.solve(b, x, rtol=1e-9, precision=mtf.BF16_SPLIT, max_iters=3000)
+    xs = x.cpu().numpy()
+    for j, s in enumerate(st):
+        print(f"[{name} bf16 rhs {j}] it {s.iterations} ref {s.refinements} res {s.rel_residual:.1e}", flush=True)
+        assert s.converged and s.rel_residual <= 1e-9
+        assert np.linalg.norm(xs[j] - xo[:, j]) / np.linalg.norm(xo[:, j]) < 1e-6
+
+
+def test_solve_many_rhs_fp64_sequential(cube):
+    b, xo = _multi_rhs(cube, 3)
+    x = torch.zeros_like(b)
+    st = cube.P.solve(b, x, rtol=1e-10)
+    xs = x.cpu().numpy()
+    for j, s in enumerate(st):
+        assert s.converged
+        assert np.linalg.norm(xs[j] - xo[:, j]) / np.linalg.norm(xo[:, j]) < 1e-7
