@@ -211,6 +211,61 @@ int mtf_far_field(mtf_problem p, int32_t nrhs, const void* x_dev, int64_t ld, in
  * seconds (HIP events).  Synchronises. */
 int mtf_assembly_stats(mtf_problem p, int64_t* counts, double* seconds);
 
+/* ---------------------------------------------------------------------------
+ * Learned warm start: a POD basis of MTF solutions and a small MLP mapping
+ * problem parameters to POD coefficients; GMRES then starts from x0 = Phi c.
+ * (Not in the paper: an addition that changes only the initial guess; the FP64
+ * residual of mtf_solve, relative to ||b||, still decides convergence.)
+ * ------------------------------------------------------------------------- */
+
+/* POD basis of nsnap solution snapshots U_dev (complex128 [nsnap][ldu], N rows
+ * each): the r leading left singular vectors Phi_dev (complex128 [r][ldphi])
+ * and singular values sv[r] (host), computed in complex64 from the snapshot
+ * Gram matrix U^H U by subspace iteration with Rayleigh-Ritz.  r <= nsnap,
+ * r <= 256.  Synchronises. */
+int mtf_pod_build(mtf_problem p, int32_t nsnap, const void* U_dev, int64_t ldu, int32_t r,
+                  void* Phi_dev, int64_t ldphi, double* sv);
+
+/* C = Phi^H X for n vectors X_dev (complex128 [n][ldx]) -> C_dev (complex128 [n][r]). */
+int mtf_pod_project(mtf_problem p, int32_t r, const void* Phi_dev, int64_t ldphi, int32_t n,
+                    const void* X_dev, int64_t ldx, void* C_dev);
+
+/* X = Phi C for n coefficient vectors C_dev (complex128 [n][r]) -> X_dev (complex128 [n][ldx]). */
+int mtf_pod_expand(mtf_problem p, int32_t r, const void* Phi_dev, int64_t ldphi, int32_t n,
+                   const void* C_dev, void* X_dev, int64_t ldx);
+
+/* Multilayer perceptron n_in -> width (tanh) -> width (tanh) -> n_out (linear), FP32,
+ * parameters packed (W1 [width][n_in], b1, W2 [width][width], b2, W3 [n_out][width], b3),
+ * Glorot-uniform initialisation from a SplitMix64 stream seeded with `seed`, zero biases.
+ * Activations are row-major [samples][features] float arrays on the device. */
+typedef struct mtf_mlp_s* mtf_mlp;
+int mtf_mlp_create(mtf_mlp* out, int device, void* stream, int32_t n_in, int32_t width,
+                   int32_t n_out, uint64_t seed);
+int mtf_mlp_destroy(mtf_mlp m);
+int mtf_mlp_num_params(mtf_mlp m, int64_t* n);
+int mtf_mlp_get_params(mtf_mlp m, float* host);           /* [num_params] */
+int mtf_mlp_set_params(mtf_mlp m, const float* host);
+/* Y_dev [n][n_out] = MLP(X_dev [n][n_in]). */
+int mtf_mlp_forward(mtf_mlp m, int32_t n, const float* X_dev, float* Y_dev);
+/* Mean squared error over all n x n_out outputs against targets T_dev and its gradient
+ * with respect to the packed parameters (grad_host [num_params], may be NULL). */
+int mtf_mlp_loss_grad(mtf_mlp m, int32_t n, const float* X_dev, const float* T_dev, float* loss,
+                      float* grad_host);
+
+typedef struct {
+    int32_t struct_size;     /* sizeof(mtf_train_opts)                          */
+    int32_t epochs;          /* passes over the data                            */
+    int32_t batch;           /* minibatch size                                  */
+    int32_t reserved;
+    float   lr, beta1, beta2, eps;   /* Adam (Kingma & Ba 2015)                 */
+    uint64_t seed;           /* SplitMix64 seed of the per-epoch shuffles       */
+} mtf_train_opts;
+
+/* Adam on the MSE loss with shuffled minibatches; loss_hist[epochs] (host, may be NULL)
+ * receives the full-data loss after each epoch.  Synchronises at epoch ends. */
+int mtf_mlp_train(mtf_mlp m, int32_t n, const float* X_dev, const float* T_dev,
+                  const mtf_train_opts* opts, float* loss_hist);
+
 #ifdef __cplusplus
 }
 #endif

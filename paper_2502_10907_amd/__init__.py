@@ -51,6 +51,12 @@ class SolveOpts(C.Structure):
                 ("rtol", C.c_double), ("inner_rtol", C.c_double), ("x0_dev", C.c_void_p)]
 
 
+class TrainOpts(C.Structure):
+    _fields_ = [("struct_size", C.c_int32), ("epochs", C.c_int32), ("batch", C.c_int32), ("reserved", C.c_int32),
+                ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("seed", C.c_uint64)]
+
+
 class SolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("refinements", C.c_int32), ("converged", C.c_int32),
                 ("reorthogonalizations", C.c_int32), ("rel_residual", C.c_double), ("t_precond_s", C.c_double),
@@ -78,6 +84,17 @@ _SIGS = {
     "mtf_solve": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
     "mtf_far_field": (C.c_int, [_P, C.c_int32, _P, C.c_int64, C.c_int32, _dp, _dp]),
     "mtf_assembly_stats": (C.c_int, [_P, _lp, _dp]),
+    "mtf_pod_build": (C.c_int, [_P, C.c_int32, _P, C.c_int64, C.c_int32, _P, C.c_int64, _dp]),
+    "mtf_pod_project": (C.c_int, [_P, C.c_int32, _P, C.c_int64, C.c_int32, _P, C.c_int64, _P]),
+    "mtf_pod_expand": (C.c_int, [_P, C.c_int32, _P, C.c_int64, C.c_int32, _P, _P, C.c_int64]),
+    "mtf_mlp_create": (C.c_int, [C.POINTER(_P), C.c_int, _P, C.c_int32, C.c_int32, C.c_int32, C.c_uint64]),
+    "mtf_mlp_destroy": (C.c_int, [_P]),
+    "mtf_mlp_num_params": (C.c_int, [_P, _lp]),
+    "mtf_mlp_get_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "mtf_mlp_set_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "mtf_mlp_forward": (C.c_int, [_P, C.c_int32, _P, _P]),
+    "mtf_mlp_loss_grad": (C.c_int, [_P, C.c_int32, _P, _P, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    "mtf_mlp_train": (C.c_int, [_P, C.c_int32, _P, _P, C.c_void_p, C.POINTER(C.c_float)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -267,3 +284,106 @@ class Problem:
         out = np.zeros(nrhs * dirs.shape[0] * 6)
         _check(_lib.mtf_far_field(self._h, nrhs, px, ld, dirs.shape[0], pd, out.ctypes.data_as(_dp)))
         return out.view(np.complex128).reshape(nrhs, dirs.shape[0], 3)
+
+
+    # -- POD basis (learned warm start) ------------------------------------------
+    def pod_build(self, U, r: int, Phi):
+        """Phi [r, N] (complex128, device) <- r leading POD modes of snapshots U [nsnap, N]; returns sv."""
+        pu, nsnap, ldu = _dev(U, self.N)
+        pp, r2, ldp = _dev(Phi, self.N)
+        if r2 < r:
+            raise ValueError("Phi needs r rows")
+        sv = np.zeros(r)
+        _check(_lib.mtf_pod_build(self._h, nsnap, pu, ldu, int(r), pp, ldp, sv.ctypes.data_as(_dp)))
+        return sv
+
+    def pod_project(self, Phi, X, Cout):
+        """Cout [n, r] = (Phi^H X) for X [n, N]."""
+        import torch
+        pp, r, ldp = _dev(Phi, self.N)
+        px, n, ldx = _dev(X, self.N)
+        if not (isinstance(Cout, torch.Tensor) and Cout.dtype == torch.complex128 and Cout.is_cuda and Cout.is_contiguous()
+                and tuple(Cout.shape) == (n, r)):
+            raise ValueError("Cout must be a contiguous complex128 GPU tensor of shape [n, r]")
+        _check(_lib.mtf_pod_project(self._h, r, pp, ldp, n, px, ldx, C.c_void_p(Cout.data_ptr())))
+
+    def pod_expand(self, Phi, Cin, X):
+        """X [n, N] = Phi C for coefficients Cin [n, r]."""
+        pp, r, ldp = _dev(Phi, self.N)
+        px, n, ldx = _dev(X, self.N)
+        if tuple(Cin.shape) != (n, r) or not Cin.is_contiguous():
+            raise ValueError("Cin must be contiguous [n, r]")
+        _check(_lib.mtf_pod_expand(self._h, r, pp, ldp, n, C.c_void_p(Cin.data_ptr()), px, ldx))
+
+
+def _fdev(t, cols):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError("MLP buffers must be contiguous float32 GPU tensors")
+    if t.dim() != 2 or t.shape[1] != cols:
+        raise ValueError(f"expected shape [n, {cols}]")
+    return C.c_void_p(t.data_ptr()), t.shape[0]
+
+
+class MLP:
+    """n_in -> width (tanh) -> width (tanh) -> n_out MLP trained by the library's own kernels."""
+
+    def __init__(self, n_in: int, width: int, n_out: int, seed: int = 0, device: int = 0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self._h = C.c_void_p()
+        _check(_lib.mtf_mlp_create(C.byref(self._h), int(device), C.c_void_p(stream), int(n_in), int(width),
+                                   int(n_out), C.c_uint64(seed)))
+        self.n_in, self.width, self.n_out = n_in, width, n_out
+        n = C.c_int64()
+        _check(_lib.mtf_mlp_num_params(self._h, C.byref(n)))
+        self.num_params = n.value
+
+    def close(self):
+        if self._h:
+            _lib.mtf_mlp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.num_params, dtype=np.float32)
+        _check(_lib.mtf_mlp_get_params(self._h, out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        _check(_lib.mtf_mlp_set_params(self._h, theta.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def forward(self, X, Y):
+        px, n = _fdev(X, self.n_in)
+        py, n2 = _fdev(Y, self.n_out)
+        if n != n2:
+            raise ValueError("row counts differ")
+        _check(_lib.mtf_mlp_forward(self._h, n, px, py))
+
+    def loss_grad(self, X, T):
+        px, n = _fdev(X, self.n_in)
+        pt, n2 = _fdev(T, self.n_out)
+        if n != n2:
+            raise ValueError("row counts differ")
+        loss = C.c_float()
+        g = np.zeros(self.num_params, dtype=np.float32)
+        _check(_lib.mtf_mlp_loss_grad(self._h, n, px, pt, C.byref(loss), g.ctypes.data_as(C.POINTER(C.c_float))))
+        return loss.value, g
+
+    def train(self, X, T, epochs=100, batch=128, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0):
+        px, n = _fdev(X, self.n_in)
+        pt, n2 = _fdev(T, self.n_out)
+        if n != n2:
+            raise ValueError("row counts differ")
+        o = TrainOpts(C.sizeof(TrainOpts), int(epochs), int(batch), 0, float(lr), float(beta1), float(beta2),
+                      float(eps), C.c_uint64(seed))
+        hist = np.zeros(epochs, dtype=np.float32)
+        _check(_lib.mtf_mlp_train(self._h, n, px, pt, C.byref(o), hist.ctypes.data_as(C.POINTER(C.c_float))))
+        return hist

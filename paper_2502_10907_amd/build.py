@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmtf.so")
-SOURCES = ["skeleton.cpp", "quadrature.cpp", "capi.cpp", "assembly.hip", "solver.hip", "gemm.hip"]
+SOURCES = ["skeleton.cpp", "quadrature.cpp", "capi.cpp", "learn_api.cpp", "assembly.hip", "solver.hip", "gemm.hip", "learn.hip"]
 ARCH = os.environ.get("MTF_OFFLOAD_ARCH", "gfx950")
 
 
@@ -31,7 +31,7 @@ def build(verbose: bool = False) -> str:
     procs = []
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") or src == "capi.cpp" else []
+        lang = ["-x", "hip"] if src.endswith(".hip") or src in ("capi.cpp", "learn_api.cpp") else []
         cmd = [hipcc()] + flags + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

@@ -136,3 +136,19 @@ void launch_gemm_finish(const DomDesc* doms, const GemmDesc* descs, const int32_
                         const float* C, const double* x, double* y, int64_t ld, int nrhs, int mode, hipStream_t s);
 
 }  // namespace mtf
+
+namespace mtf {
+// Learned warm start (learn.hip).
+void launch_sgemm(int M, int N, int K, const float* A, int lda, int ta, const float* B, int ldb, int tb, const float* bias,
+                  int act_tanh, float* C, int ldc, int accumulate, hipStream_t s);
+void launch_tanh_back(const float* A, const float* dA, float* dZ, int64_t n, hipStream_t s);
+int  launch_mse(const float* Y, const float* T, float* dY, int64_t n, float scale, float* loss_part, hipStream_t s);
+void launch_colsum(const float* dZ, int M, int N, float* db, hipStream_t s);
+void launch_adam(float* p, const float* g, float* m1, float* m2, int64_t n, float lr_t, float b1, float b2, float eps,
+                 hipStream_t s);
+void launch_gather_rows(const float* X, const int* idx, int B, int cols, float* Xb, hipStream_t s);
+void launch_cgemm_hn(int m, int n, int k, const float* A, int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc,
+                     hipStream_t s);
+void launch_c128_to_c64(const double* X, int64_t ld, int64_t n, int cols, float* Y, hipStream_t s);
+void launch_c64_to_c128(const float* X, int64_t n, int cols, double* Y, int64_t ld, hipStream_t s);
+}  // namespace mtf
