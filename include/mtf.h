@@ -212,6 +212,30 @@ int mtf_far_field(mtf_problem p, int32_t nrhs, const void* x_dev, int64_t ld, in
 int mtf_assembly_stats(mtf_problem p, int64_t* counts, double* seconds);
 
 /* ---------------------------------------------------------------------------
+ * Batches of independent problems (many scatterers of uneven size).
+ * ------------------------------------------------------------------------- */
+typedef struct mtf_batch_s* mtf_batch;
+
+/* A batch over n existing problems (each with mesh and materials set, all on one device
+ * and stream, each at most once).  The problems stay owned by the caller and must outlive
+ * the batch; the batch keeps its work list of the problems' current meshes. */
+int mtf_batch_create(mtf_batch* out, int32_t n, const mtf_problem* problems);
+int mtf_batch_destroy(mtf_batch b);
+
+/* Assembles T_i and K_i of every problem of the batch in ONE persistent launch: workgroups
+ * claim work items (16 x 16 tiles of separated triangle pairs and chunks of four touching
+ * pairs, across all problems, largest problems first) from an atomic counter until the list is
+ * exhausted.  On the first call per precision an autotuner times the launch with 1, 2, 4 and 8
+ * persistent workgroups per compute unit and keeps the fastest (grid_used, may be NULL);
+ * seconds (may be NULL) receives the device time of the kept launch.  Synchronises. */
+int mtf_batch_assemble(mtf_batch b, const mtf_assembly_opts* opts, int32_t* grid_used, double* seconds);
+
+/* mtf_solve of problem i on b_dev[i] -> x_dev[i] (one right-hand side each, ld = N_i) with
+ * common options; stats[n] may be NULL. */
+int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, const mtf_solve_opts* opts,
+                    mtf_solve_stats* stats);
+
+/* ---------------------------------------------------------------------------
  * Learned warm start: a POD basis of MTF solutions and a small MLP mapping
  * problem parameters to POD coefficients; GMRES then starts from x0 = Phi c.
  * (Not in the paper: an addition that changes only the initial guess; the FP64

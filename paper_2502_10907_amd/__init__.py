@@ -84,6 +84,10 @@ _SIGS = {
     "mtf_solve": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
     "mtf_far_field": (C.c_int, [_P, C.c_int32, _P, C.c_int64, C.c_int32, _dp, _dp]),
     "mtf_assembly_stats": (C.c_int, [_P, _lp, _dp]),
+    "mtf_batch_create": (C.c_int, [C.POINTER(_P), C.c_int32, C.POINTER(_P)]),
+    "mtf_batch_destroy": (C.c_int, [_P]),
+    "mtf_batch_assemble": (C.c_int, [_P, C.POINTER(AssemblyOpts), _ip, _dp]),
+    "mtf_batch_solve": (C.c_int, [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
     "mtf_pod_build": (C.c_int, [_P, C.c_int32, _P, C.c_int64, C.c_int32, _P, C.c_int64, _dp]),
     "mtf_pod_project": (C.c_int, [_P, C.c_int32, _P, C.c_int64, C.c_int32, _P, C.c_int64, _P]),
     "mtf_pod_expand": (C.c_int, [_P, C.c_int32, _P, C.c_int64, C.c_int32, _P, _P, C.c_int64]),
@@ -387,3 +391,42 @@ class MLP:
         hist = np.zeros(epochs, dtype=np.float32)
         _check(_lib.mtf_mlp_train(self._h, n, px, pt, C.byref(o), hist.ctypes.data_as(C.POINTER(C.c_float))))
         return hist
+
+
+class Batch:
+    """Independent problems assembled together in one persistent launch (the problems must outlive it)."""
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        arr = (_P * len(self.problems))(*[p._h.value for p in self.problems])
+        self._h = C.c_void_p()
+        _check(_lib.mtf_batch_create(C.byref(self._h), len(self.problems), arr))
+
+    def close(self):
+        if self._h:
+            _lib.mtf_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def assemble(self, precision: int = FP64, singular_order: int = 4):
+        """Returns (persistent workgroups chosen by the autotuner, device seconds of the launch)."""
+        o = AssemblyOpts(C.sizeof(AssemblyOpts), int(precision), int(singular_order), 0)
+        g = C.c_int32()
+        t = C.c_double()
+        _check(_lib.mtf_batch_assemble(self._h, C.byref(o), C.byref(g), C.byref(t)))
+        return g.value, t.value
+
+    def solve(self, bs, xs, rtol=1e-6, precision=FP64, preconditioner=PREC_BLOCK_TINV, max_iters=0):
+        n = len(self.problems)
+        pb = (_P * n)(*[_dev(b, p.N)[0].value for b, p in zip(bs, self.problems)])
+        px = (_P * n)(*[_dev(x, p.N)[0].value for x, p in zip(xs, self.problems)])
+        o = SolveOpts(C.sizeof(SolveOpts), int(precision), int(preconditioner), int(max_iters), 0, 0, float(rtol), 0.0, None)
+        st = (SolveStats * n)()
+        _check(_lib.mtf_batch_solve(self._h, pb, px, C.byref(o), st))
+        return [Stats(s.iterations, s.refinements, bool(s.converged), s.rel_residual, s.t_precond_s, s.t_solve_s,
+                      s.reorthogonalizations) for s in st]

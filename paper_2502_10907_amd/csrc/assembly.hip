@@ -205,13 +205,13 @@ __device__ inline void epilogue(const Moments<R>& m, const R* pa_all, const R* q
     }
 }
 
+// One 16 x 16 tile of separated pairs; all 256 threads of the workgroup must call it (it holds a
+// workgroup barrier); pairs outside Gamma_i or touching are skipped by predication.
 template <typename R>
-__global__ __launch_bounds__(256) void k_regular(const int4* __restrict__ tiles, const DomDesc* __restrict__ doms,
-                                                 const TriGeom* __restrict__ geom, const int32_t* __restrict__ verts,
-                                                 const int32_t* __restrict__ tdof, const int8_t* __restrict__ tsign,
-                                                 R* __restrict__ T, R* __restrict__ K) {
-    __shared__ LRec<R> rec[32];
-    const int4 tile = tiles[blockIdx.x];
+__device__ inline void regular_tile(const int4 tile, const DomDesc* __restrict__ doms, const TriGeom* __restrict__ geom,
+                                    const int32_t* __restrict__ verts, const int32_t* __restrict__ tdof,
+                                    const int8_t* __restrict__ tsign, R* __restrict__ T, R* __restrict__ K,
+                                    LRec<R>* rec) {
     const DomDesc dd = doms[tile.x];
     const int tid = threadIdx.x;
     if (tid < 32) {
@@ -235,61 +235,73 @@ __global__ __launch_bounds__(256) void k_regular(const int4* __restrict__ tiles,
     __syncthreads();
     const int ix = tid >> 4, iy = tid & 15;
     const int tx = tile.y + ix, ty = tile.z + iy;
-    if (tx >= dd.T || ty >= dd.T) return;
+    bool valid = tx < dd.T && ty < dd.T;
     const LRec<R>& X = rec[ix];
     const LRec<R>& Y = rec[16 + iy];
-    // touching pairs belong to the Sauter-Schwab kernel
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b)
-            if (X.v[a] == Y.v[b]) return;
-
-    const R k = (R)dd.k;
-    R D[3];
-    for (int i = 0; i < 3; ++i) D[i] = (R)(X.c[i] - Y.c[i]);
-    Moments<R> m;
-    zero_moments(m);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        const R x0 = X.q[3 * q], x1 = X.q[3 * q + 1], x2 = X.q[3 * q + 2];
-        const R wq = X.w[q];
-        const R dx0 = D[0] + x0, dx1 = D[1] + x1, dx2 = D[2] + x2;
-        R s0[2] = {0, 0}, sy[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-        R t0[2] = {0, 0}, ty[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-#pragma unroll
-        for (int r = 0; r < 6; ++r) {
-            const R y0 = Y.q[3 * r], y1 = Y.q[3 * r + 1], y2 = Y.q[3 * r + 2];
-            const R d0 = dx0 - y0, d1 = dx1 - y1, d2 = dx2 - y2;
-            const R r2 = d0 * d0 + d1 * d1 + d2 * d2;
-            const R rinv = rsqrt_r(r2);
-            const R kr = k * (r2 * rinv);
-            R Gre, Gim, gre, gim;
-            kernel_values<R>(kr, rinv, Y.w[r], Gre, Gim, gre, gim);
-            s0[0] += Gre; s0[1] += Gim;
-            t0[0] += gre; t0[1] += gim;
-            sy[0][0] += Gre * y0; sy[0][1] += Gim * y0;
-            sy[1][0] += Gre * y1; sy[1][1] += Gim * y1;
-            sy[2][0] += Gre * y2; sy[2][1] += Gim * y2;
-            ty[0][0] += gre * y0; ty[0][1] += gim * y0;
-            ty[1][0] += gre * y1; ty[1][1] += gim * y1;
-            ty[2][0] += gre * y2; ty[2][1] += gim * y2;
-        }
-        const R xv[3] = {x0, x1, x2};
-        for (int c = 0; c < 2; ++c) {
-            m.M0[c] += wq * s0[c];
-            m.N0[c] += wq * t0[c];
-            m.Mxy[c] += wq * (x0 * sy[0][c] + x1 * sy[1][c] + x2 * sy[2][c]);
-            for (int i = 0; i < 3; ++i) {
-                m.Mx[i][c] += wq * s0[c] * xv[i];
-                m.My[i][c] += wq * sy[i][c];
-                m.Nx[i][c] += wq * t0[c] * xv[i];
-                m.Ny[i][c] += wq * ty[i][c];
-            }
-            m.Nxy[0][c] += wq * (x1 * ty[2][c] - x2 * ty[1][c]);
-            m.Nxy[1][c] += wq * (x2 * ty[0][c] - x0 * ty[2][c]);
-            m.Nxy[2][c] += wq * (x0 * ty[1][c] - x1 * ty[0][c]);
-        }
+    if (valid) {
+        // touching pairs belong to the Sauter-Schwab path
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                if (X.v[a] == Y.v[b]) valid = false;
     }
-    epilogue<R, R>(m, X.p, Y.p, X.coef, Y.coef, D, k, X.dof, Y.dof, X.sg, Y.sg, dd.mat0, dd.E, T, K);
+    if (valid) {
+        const R k = (R)dd.k;
+        R D[3];
+        for (int i = 0; i < 3; ++i) D[i] = (R)(X.c[i] - Y.c[i]);
+        Moments<R> m;
+        zero_moments(m);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const R x0 = X.q[3 * q], x1 = X.q[3 * q + 1], x2 = X.q[3 * q + 2];
+            const R wq = X.w[q];
+            const R dx0 = D[0] + x0, dx1 = D[1] + x1, dx2 = D[2] + x2;
+            R s0[2] = {0, 0}, sy[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+            R t0[2] = {0, 0}, ty[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                const R y0 = Y.q[3 * r], y1 = Y.q[3 * r + 1], y2 = Y.q[3 * r + 2];
+                const R d0 = dx0 - y0, d1 = dx1 - y1, d2 = dx2 - y2;
+                const R r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                const R rinv = rsqrt_r(r2);
+                const R kr = k * (r2 * rinv);
+                R Gre, Gim, gre, gim;
+                kernel_values<R>(kr, rinv, Y.w[r], Gre, Gim, gre, gim);
+                s0[0] += Gre; s0[1] += Gim;
+                t0[0] += gre; t0[1] += gim;
+                sy[0][0] += Gre * y0; sy[0][1] += Gim * y0;
+                sy[1][0] += Gre * y1; sy[1][1] += Gim * y1;
+                sy[2][0] += Gre * y2; sy[2][1] += Gim * y2;
+                ty[0][0] += gre * y0; ty[0][1] += gim * y0;
+                ty[1][0] += gre * y1; ty[1][1] += gim * y1;
+                ty[2][0] += gre * y2; ty[2][1] += gim * y2;
+            }
+            const R xv[3] = {x0, x1, x2};
+            for (int c = 0; c < 2; ++c) {
+                m.M0[c] += wq * s0[c];
+                m.N0[c] += wq * t0[c];
+                m.Mxy[c] += wq * (x0 * sy[0][c] + x1 * sy[1][c] + x2 * sy[2][c]);
+                for (int i = 0; i < 3; ++i) {
+                    m.Mx[i][c] += wq * s0[c] * xv[i];
+                    m.My[i][c] += wq * sy[i][c];
+                    m.Nx[i][c] += wq * t0[c] * xv[i];
+                    m.Ny[i][c] += wq * ty[i][c];
+                }
+                m.Nxy[0][c] += wq * (x1 * ty[2][c] - x2 * ty[1][c]);
+                m.Nxy[1][c] += wq * (x2 * ty[0][c] - x0 * ty[2][c]);
+                m.Nxy[2][c] += wq * (x0 * ty[1][c] - x1 * ty[0][c]);
+            }
+        }
+        epilogue<R, R>(m, X.p, Y.p, X.coef, Y.coef, D, k, X.dof, Y.dof, X.sg, Y.sg, dd.mat0, dd.E, T, K);
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_regular(const int4* __restrict__ tiles, const DomDesc* __restrict__ doms,
+                                                 const TriGeom* __restrict__ geom, const int32_t* __restrict__ verts,
+                                                 const int32_t* __restrict__ tdof, const int8_t* __restrict__ tsign,
+                                                 R* __restrict__ T, R* __restrict__ K) {
+    __shared__ LRec<R> rec[32];
+    regular_tile<R>(tiles[blockIdx.x], doms, geom, verts, tdof, tsign, T, K, rec);
 }
 
 // ---------------------------------------------------------------------------
@@ -302,16 +314,13 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-__global__ __launch_bounds__(256) void k_singular(const SingPair* __restrict__ pairs, int64_t npairs,
-                                                  const DomDesc* __restrict__ doms, const TriGeom* __restrict__ geom,
-                                                  const int32_t* __restrict__ tdof, const int8_t* __restrict__ tsign,
-                                                  const double* __restrict__ ss_table, const int32_t* __restrict__ ss_off,
-                                                  const int32_t* __restrict__ ss_cnt, double* T64, double* K64,
-                                                  float* T32, float* K32) {
-    const int64_t pid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (pid >= npairs) return;   // uniform per wavefront; no block-level barrier below
-    const SingPair sp = pairs[pid];
+// One touching pair per wavefront (no workgroup barrier): Sauter-Schwab points split over the
+// 64 lanes, moments reduced with shuffles, lane 0 scatters the local blocks.
+__device__ inline void singular_pair(const SingPair sp, const DomDesc* __restrict__ doms, const TriGeom* __restrict__ geom,
+                                     const int32_t* __restrict__ tdof, const int8_t* __restrict__ tsign,
+                                     const double* __restrict__ ss_table, const int32_t* __restrict__ ss_off,
+                                     const int32_t* __restrict__ ss_cnt, double* T64, double* K64, float* T32,
+                                     float* K32, int lane) {
     const DomDesc dd = doms[sp.dom];
     const int64_t rx = dd.rec0 + sp.tx, ry = dd.rec0 + sp.ty;
     const TriGeom& gx = geom[rx];
@@ -369,16 +378,70 @@ __global__ __launch_bounds__(256) void k_singular(const SingPair* __restrict__ p
             m.Nxy[i][c] = wave_sum(m.Nxy[i][c]);
         }
     }
-    if (lane != 0) return;
-    int32_t dofx[3], dofy[3], sgx[3], sgy[3];
-    for (int a = 0; a < 3; ++a) {
-        dofx[a] = tdof[3 * rx + a];
-        dofy[a] = tdof[3 * ry + a];
-        sgx[a] = tsign[3 * rx + a];
-        sgy[a] = tsign[3 * ry + a];
+    if (lane == 0) {
+        int32_t dofx[3], dofy[3], sgx[3], sgy[3];
+        for (int a = 0; a < 3; ++a) {
+            dofx[a] = tdof[3 * rx + a];
+            dofy[a] = tdof[3 * ry + a];
+            sgx[a] = tsign[3 * rx + a];
+            sgy[a] = tsign[3 * ry + a];
+        }
+        if (T64) epilogue<double, double>(m, gx.p, gy.p, gx.coef, gy.coef, D, k, dofx, dofy, sgx, sgy, dd.mat0, dd.E, T64, K64);
+        if (T32) epilogue<double, float>(m, gx.p, gy.p, gx.coef, gy.coef, D, k, dofx, dofy, sgx, sgy, dd.mat0, dd.E, T32, K32);
     }
-    if (T64) epilogue<double, double>(m, gx.p, gy.p, gx.coef, gy.coef, D, k, dofx, dofy, sgx, sgy, dd.mat0, dd.E, T64, K64);
-    if (T32) epilogue<double, float>(m, gx.p, gy.p, gx.coef, gy.coef, D, k, dofx, dofy, sgx, sgy, dd.mat0, dd.E, T32, K32);
+}
+
+__global__ __launch_bounds__(256) void k_singular(const SingPair* __restrict__ pairs, int64_t npairs,
+                                                  const DomDesc* __restrict__ doms, const TriGeom* __restrict__ geom,
+                                                  const int32_t* __restrict__ tdof, const int8_t* __restrict__ tsign,
+                                                  const double* __restrict__ ss_table, const int32_t* __restrict__ ss_off,
+                                                  const int32_t* __restrict__ ss_cnt, double* T64, double* K64,
+                                                  float* T32, float* K32) {
+    const int64_t pid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (pid >= npairs) return;   // uniform per wavefront; no workgroup barrier in singular_pair
+    singular_pair(pairs[pid], doms, geom, tdof, tsign, ss_table, ss_off, ss_cnt, T64, K64, T32, K32, threadIdx.x & 63);
+}
+
+// ---------------------------------------------------------------------------
+// persistent assembly of a batch of problems (one launch, dynamic work queue)
+// ---------------------------------------------------------------------------
+// Work item (int4): x = problem | (kind << 24); kind 0 = separated tile (y, z, w = subdomain,
+// first test triangle, first trial triangle), kind 1 = up to four touching pairs (y = first pair,
+// z = count).  Each workgroup claims items through an atomic counter until the counter passes
+// `nitems`; every wave then leaves the loop.
+template <typename R>
+__global__ __launch_bounds__(256) void k_assemble_persistent(const int4* __restrict__ items, int64_t nitems,
+                                                             unsigned long long* counter, const BatchProb* __restrict__ probs,
+                                                             const double* __restrict__ ss_table,
+                                                             const int32_t* __restrict__ ss_off,
+                                                             const int32_t* __restrict__ ss_cnt) {
+    __shared__ LRec<R> rec[32];
+    __shared__ long long claimed;
+    for (;;) {
+        if (threadIdx.x == 0) claimed = (long long)atomicAdd(counter, 1ull);
+        __syncthreads();
+        const long long it = claimed;
+        __syncthreads();
+        if (it >= nitems) break;            // uniform across the workgroup
+        const int4 w = items[it];
+        const int prob = w.x & 0xffffff, kind = w.x >> 24;
+        const BatchProb bp = probs[prob];
+        if (kind == 0) {
+            regular_tile<R>(make_int4(w.y, w.z, w.w, 0), bp.doms, bp.geom, bp.verts, bp.tdof, bp.tsign,
+                            static_cast<R*>(bp.T), static_cast<R*>(bp.K), rec);
+        } else {
+            const int wave = threadIdx.x >> 6;
+            if (wave < w.z) {
+                double* T64 = sizeof(R) == 8 ? static_cast<double*>(bp.T) : nullptr;
+                double* K64 = sizeof(R) == 8 ? static_cast<double*>(bp.K) : nullptr;
+                float* T32 = sizeof(R) == 4 ? static_cast<float*>(bp.T) : nullptr;
+                float* K32 = sizeof(R) == 4 ? static_cast<float*>(bp.K) : nullptr;
+                singular_pair(bp.sing[w.y + wave], bp.doms, bp.geom, bp.tdof, bp.tsign, ss_table, ss_off, ss_cnt, T64, K64,
+                              T32, K32, threadIdx.x & 63);
+            }
+        }
+        __syncthreads();                    // LDS records are reused by the next item
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -604,6 +667,18 @@ void launch_far_field(const DomDesc* d0, const TriGeom* geom, const int32_t* tdo
     if (nrhs <= 0 || ndir <= 0) return;
     hipLaunchKernelGGL(k_far_field, dim3((unsigned)(nrhs * ndir)), dim3(256), 0, s, *d0, geom, tdof, tsign, T0, k0,
                        rho0, x, ldx, dirs, ndir, out);
+}
+
+void launch_assemble_persistent(int precision, const int4* items, int64_t nitems, unsigned long long* counter,
+                                const BatchProb* probs, const double* ss_table, const int32_t* ss_off,
+                                const int32_t* ss_cnt, int grid, hipStream_t s) {
+    if (nitems <= 0) return;
+    if (precision == 0)
+        hipLaunchKernelGGL(k_assemble_persistent<double>, dim3((unsigned)grid), dim3(256), 0, s, items, nitems, counter,
+                           probs, ss_table, ss_off, ss_cnt);
+    else
+        hipLaunchKernelGGL(k_assemble_persistent<float>, dim3((unsigned)grid), dim3(256), 0, s, items, nitems, counter,
+                           probs, ss_table, ss_off, ss_cnt);
 }
 
 void launch_tri_setup_rule(const double* xyz, const int32_t* verts, int64_t nrec, const double* bary18,

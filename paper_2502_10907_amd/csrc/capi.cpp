@@ -229,16 +229,42 @@ void ensure_ss(mtf_problem p, int order) {
     p->ss_order = order;
 }
 
-void assemble_impl(mtf_problem p, const mtf_assembly_opts* o) {
-    if (!p->has_mesh || !p->has_mat) throw StateError("mtf_assemble needs mtf_set_mesh and mtf_set_materials first");
-    int prec = MTF_FP64, order = 4;
+void parse_assembly_opts(const mtf_assembly_opts* o, int* prec, int* order) {
+    *prec = MTF_FP64;
+    *order = 4;
     if (o) {
         if (o->struct_size < (int)sizeof(mtf_assembly_opts)) throw ArgError("mtf_assembly_opts.struct_size too small");
-        prec = o->precision;
-        if (o->singular_order) order = o->singular_order;
+        *prec = o->precision;
+        if (o->singular_order) *order = o->singular_order;
     }
-    if (prec != MTF_FP64 && prec != MTF_FP32_MIXED) throw ArgError("unknown precision");
-    if (order < 1 || order > 8) throw ArgError("singular_order must be in 1..8");
+    if (*prec != MTF_FP64 && *prec != MTF_FP32_MIXED) throw ArgError("unknown precision");
+    if (*order < 1 || *order > 8) throw ArgError("singular_order must be in 1..8");
+}
+
+// Allocates and zeroes the blocks of one precision and marks them current (kernels launched by the caller).
+void assemble_prepare(mtf_problem p, int prec) {
+    hipStream_t s = p->stream;
+    const int64_t n2 = 2 * p->mat_entries;
+    if (prec == MTF_FP64) {
+        p->T64.alloc(n2); p->K64.alloc(n2);
+        launch_fill(p->T64.p, n2, 0.0, s);
+        launch_fill(p->K64.p, n2, 0.0, s);
+        p->have64 = true;
+    } else {
+        p->T32.alloc(n2); p->K32.alloc(n2);
+        launch_fill_f(p->T32.p, n2, 0.f, s);
+        launch_fill_f(p->K32.p, n2, 0.f, s);
+        p->have32 = true;
+        p->gm.haveA = false;
+    }
+    p->have_tinv = false;
+    p->gp.haveA = false;
+}
+
+void assemble_impl(mtf_problem p, const mtf_assembly_opts* o) {
+    if (!p->has_mesh || !p->has_mat) throw StateError("mtf_assemble needs mtf_set_mesh and mtf_set_materials first");
+    int prec, order;
+    parse_assembly_opts(o, &prec, &order);
     DeviceGuard g(p->device);
     ensure_ss(p, order);
     hipStream_t s = p->stream;
@@ -970,6 +996,176 @@ int mtf_assembly_stats(mtf_problem p, int64_t* counts, double* seconds) {
             }
         }
         return MTF_OK;
+    });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batches of independent problems: one persistent assembly launch
+// ---------------------------------------------------------------------------
+
+struct mtf_batch_s {
+    std::vector<mtf_problem> probs;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    DevBuf<BatchProb> d_probs;
+    DevBuf<int4> d_items;
+    DevBuf<unsigned long long> counter;
+    int64_t nitems = 0;
+    int tuned_grid[2] = {0, 0};       // per precision (0 FP64, 1 FP32)
+    double tuned_s[2] = {0.0, 0.0};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~mtf_batch_s() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
+namespace {
+
+void batch_items(mtf_batch b) {
+    // touching-pair chunks first, then separated tiles, problems by decreasing size
+    std::vector<int> order(b->probs.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return b->probs[x]->mat_entries > b->probs[y]->mat_entries; });
+    std::vector<int4> items;
+    for (int pi : order) {
+        const int64_t ns = (int64_t)b->probs[pi]->sk.singular.size();
+        for (int64_t f = 0; f < ns; f += 4) items.push_back(make_int4(pi | (1 << 24), (int)f, (int)std::min<int64_t>(4, ns - f), 0));
+    }
+    for (int pi : order) {
+        const mtf_problem p = b->probs[pi];
+        for (int i = 0; i <= p->sk.M; ++i) {
+            const int T = p->sk.dom[i].T;
+            for (int x0 = 0; x0 < T; x0 += kTile)
+                for (int y0 = 0; y0 < T; y0 += kTile) items.push_back(make_int4(pi, i, x0, y0));
+        }
+    }
+    b->d_items.upload(items, b->stream);
+    b->nitems = (int64_t)items.size();
+}
+
+// one persistent launch over every problem; returns the device time in seconds
+double batch_launch(mtf_batch b, int prec, int grid) {
+    hipStream_t s = b->stream;
+    std::vector<BatchProb> bp(b->probs.size());
+    for (size_t i = 0; i < b->probs.size(); ++i) {
+        mtf_problem p = b->probs[i];
+        assemble_prepare(p, prec);
+        BatchProb& q = bp[i];
+        q.doms = p->d_doms.p;
+        q.geom = p->d_geom.p;
+        q.verts = p->d_verts.p;
+        q.tdof = p->d_tdof.p;
+        q.tsign = p->d_tsign.p;
+        q.sing = p->d_sing.p;
+        q.T = prec == MTF_FP64 ? (void*)p->T64.p : (void*)p->T32.p;
+        q.K = prec == MTF_FP64 ? (void*)p->K64.p : (void*)p->K32.p;
+    }
+    b->d_probs.upload(bp, s);
+    HIPCHK(hipMemsetAsync(b->counter.p, 0, sizeof(unsigned long long), s));
+    mtf_problem p0 = b->probs[0];
+    const int32_t* meta = p0->d_ss_meta.p;
+    HIPCHK(hipEventRecord(b->e0, s));
+    launch_assemble_persistent(prec == MTF_FP64 ? 0 : 1, b->d_items.p, b->nitems, b->counter.p, b->d_probs.p, p0->d_ss.p,
+                               meta, meta + 4, grid, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(b->e1, s));
+    HIPCHK(hipEventSynchronize(b->e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, b->e0, b->e1));
+    return ms * 1e-3;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mtf_batch_create(mtf_batch* out, int32_t n, const mtf_problem* problems) {
+    return guarded([&] {
+        if (!out || !problems || n < 1) throw ArgError("bad arguments");
+        *out = nullptr;
+        auto b = std::make_unique<mtf_batch_s>();
+        for (int i = 0; i < n; ++i) {
+            mtf_problem p = problems[i];
+            if (!p) throw ArgError("NULL problem in batch");
+            if (!p->has_mesh || !p->has_mat) throw StateError("every problem of a batch needs mesh and materials");
+            if (i > 0 && (p->device != problems[0]->device || p->stream != problems[0]->stream))
+                throw ArgError("problems of a batch must share device and stream");
+            for (int k = 0; k < i; ++k)
+                if (problems[k] == p) throw ArgError("a problem appears twice in the batch");
+            b->probs.push_back(p);
+        }
+        if (n >= (1 << 24)) throw ArgError("too many problems");
+        b->device = problems[0]->device;
+        b->stream = problems[0]->stream;
+        DeviceGuard g(b->device);
+        b->counter.alloc(1);
+        HIPCHK(hipEventCreate(&b->e0));
+        HIPCHK(hipEventCreate(&b->e1));
+        batch_items(b.get());
+        sync(problems[0]);
+        *out = b.release();
+        return MTF_OK;
+    });
+}
+
+int mtf_batch_destroy(mtf_batch b) {
+    if (!b) return MTF_OK;
+    return guarded([&] {
+        DeviceGuard g(b->device);
+        (void)hipStreamSynchronize(b->stream);
+        delete b;
+        return MTF_OK;
+    });
+}
+
+int mtf_batch_assemble(mtf_batch b, const mtf_assembly_opts* opts, int32_t* grid_used, double* seconds) {
+    return guarded([&] {
+        if (!b) throw ArgError("batch is NULL");
+        int prec, order;
+        parse_assembly_opts(opts, &prec, &order);
+        DeviceGuard g(b->device);
+        for (mtf_problem p : b->probs) {
+            if (!p->has_mesh || !p->has_mat) throw StateError("problem lost its mesh or materials");
+            ensure_ss(p, order);
+        }
+        const int pi = prec == MTF_FP64 ? 0 : 1;
+        double t = 0;
+        if (b->tuned_grid[pi] == 0) {
+            // autotuner: persistent workgroups per CU, fastest of one trial launch each; the last
+            // trial is repeated with the winner so the stored blocks are a single clean assembly
+            hipDeviceProp_t prop;
+            HIPCHK(hipGetDeviceProperties(&prop, b->device));
+            const int cus = prop.multiProcessorCount;
+            double best = 1e30;
+            int bestg = cus;
+            for (int per : {1, 2, 4, 8}) {
+                const double tt = batch_launch(b, prec, cus * per);
+                if (tt < best) { best = tt; bestg = cus * per; }
+            }
+            b->tuned_grid[pi] = bestg;
+            b->tuned_s[pi] = best;
+        }
+        t = batch_launch(b, prec, b->tuned_grid[pi]);
+        if (grid_used) *grid_used = b->tuned_grid[pi];
+        if (seconds) *seconds = t;
+        return MTF_OK;
+    });
+}
+
+int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, const mtf_solve_opts* opts,
+                    mtf_solve_stats* stats) {
+    return guarded([&] {
+        if (!b || !b_dev || !x_dev) throw ArgError("bad arguments");
+        int status = MTF_OK;
+        for (size_t i = 0; i < b->probs.size(); ++i) {
+            mtf_problem p = b->probs[i];
+            const int r = solve_impl(p, 1, b_dev[i], x_dev[i], p->sk.N, opts, stats ? stats + i : nullptr);
+            if (r != MTF_OK) status = r;
+        }
+        return status;
     });
 }
 

@@ -46,6 +46,18 @@ struct SingPair {     // device copy of a touching pair
     int32_t px[3], py[3];
 };
 
+// Device pointers of one problem of a batch (persistent assembly).
+struct BatchProb {
+    const DomDesc* doms;
+    const TriGeom* geom;
+    const int32_t* verts;
+    const int32_t* tdof;
+    const int8_t* tsign;
+    const SingPair* sing;
+    void* T;          // double* or float* by precision
+    void* K;
+};
+
 // ---- launchers (all asynchronous on `s`) ----
 void launch_fill(double* p, int64_t n, double v, hipStream_t s);
 void launch_fill_f(float* p, int64_t n, float v, hipStream_t s);
@@ -66,6 +78,12 @@ void launch_singular(const SingPair* pairs, int64_t npairs, const DomDesc* doms,
                      const double* xyz, const int32_t* verts, const int32_t* tdof, const int8_t* tsign,
                      const double* ss_table, const int32_t* ss_off, const int32_t* ss_cnt,
                      double* T64, double* K64, float* T32, float* K32, hipStream_t s);
+
+// One persistent launch over the work items of a batch of problems (precision 0 = FP64, 1 = FP32
+// separated pairs); `counter` must be zero; grid = number of persistent workgroups.
+void launch_assemble_persistent(int precision, const int4* items, int64_t nitems, unsigned long long* counter,
+                                const BatchProb* probs, const double* ss_table, const int32_t* ss_off,
+                                const int32_t* ss_cnt, int grid, hipStream_t s);
 
 // Signed local transmission values and column indices per triangle record.
 void launch_gram_local(const DomDesc* doms, int ndom, int64_t nrec, const int32_t* rec_dom,

@@ -244,3 +244,68 @@ def test_solve_many_rhs_fp64_sequential(cube):
     for j, s in enumerate(st):
         assert s.converged
         assert np.linalg.norm(xs[j] - xo[:, j]) / np.linalg.norm(xo[:, j]) < 1e-7
+
+
+def _cluster_cfg():
+    rng = mi.SplitMix64(5)
+    mesh, eps = mi.sphere_cluster(rng, tmin=60, tmax=160, nmin=3, nmax=3)
+    return dict(mesh=mesh, k0=1.5, eps_r=eps, mu_r=np.ones(mesh.M + 1),
+                d=np.array([[0.0, 0.0, 1.0]]), p=np.array([[1.0, 0.0, 0.0]], dtype=np.complex128))
+
+
+@pytest.mark.parametrize("prec", [mtf.FP64, mtf.FP32_MIXED])
+def test_batch_persistent_assembly_matches_single(prec, sphere, ragged):
+    """Problems of different sizes assembled in one persistent launch give the blocks of their own
+    assembly (same sums, atomic order aside), hence the oracle's."""
+    cl = _cluster_cfg()
+    single = [sphere.P, ragged.P]
+    fresh = []
+    for cfg in (sphere.cfg, ragged.cfg, cl):
+        m = cfg["mesh"]
+        P = mtf.Problem(0)
+        P.set_mesh(m.xyz, m.tri, m.label, m.M)
+        P.set_materials(cfg["k0"], cfg["eps_r"], cfg["mu_r"])
+        fresh.append(P)
+    B = mtf.Batch(fresh)
+    grid, sec = B.assemble(prec)
+    assert grid > 0 and sec > 0
+    tol = 1e-13 if prec == mtf.FP64 else 1e-6
+    for Pb, Ps in zip(fresh[:2], single):
+        for i in range(Pb.M + 1):
+            for which in (mtf.BLOCK_T, mtf.BLOCK_K):
+                a, b = Pb.copy_block(i, which, prec), Ps.copy_block(i, which, prec)
+                assert np.abs(a - b).max() <= tol * np.abs(b).max() + 1e-300
+    # the cluster against the oracle
+    from oracle import system as osy
+    pb = osy.Problem.from_config(cl)
+    T, K, G = osy.assemble_blocks(pb)
+    for i in range(pb.M + 1):
+        bound = 1e-11 if prec == mtf.FP64 else 3e-5
+        assert np.abs(fresh[2].copy_block(i, mtf.BLOCK_T, prec) - T[i]).max() < bound * np.abs(T[i]).max()
+    B.close()
+
+
+def test_batch_solve(sphere):
+    cl = _cluster_cfg()
+    probs, bs, xs, refs = [], [], [], []
+    from oracle import system as osy
+    for cfg in (sphere.cfg, cl):
+        m = cfg["mesh"]
+        P = mtf.Problem(0)
+        P.set_mesh(m.xyz, m.tri, m.label, m.M)
+        P.set_materials(cfg["k0"], cfg["eps_r"], cfg["mu_r"])
+        probs.append(P)
+        b = torch.zeros((1, P.N), dtype=torch.complex128, device="cuda")
+        P.rhs_plane_waves(cfg["d"], cfg["p"], b)
+        bs.append(b)
+        xs.append(torch.zeros_like(b))
+        pb = osy.Problem.from_config(cfg)
+        T, K, G = osy.assemble_blocks(pb)
+        refs.append(osy.solve_direct(osy.dense_matrix(pb, T, K, G), osy.rhs(pb, cfg["d"], cfg["p"])[:, 0]))
+    B = mtf.Batch(probs)
+    B.assemble(mtf.FP64)
+    st = B.solve(bs, xs, rtol=1e-10, max_iters=3000)
+    for s, x, ref in zip(st, xs, refs):
+        assert s.converged
+        assert np.linalg.norm(x[0].cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-7
+    B.close()
