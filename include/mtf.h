@@ -65,7 +65,8 @@ extern "C" {
 #define MTF_BLOCK_K            1
 
 #define MTF_PREC_NONE          0
-#define MTF_PREC_BLOCK_TINV    1   /* right block preconditioner from T_i^-1 (see mtf_solve) */
+#define MTF_PREC_BLOCK_TINV    1   /* right block-Jacobi preconditioner from T_i^-1 (see mtf_solve) */
+#define MTF_PREC_BLOCK_TINV_GS 2   /* one block Gauss-Seidel sweep with the same blocks (see mtf_solve) */
 
 typedef struct mtf_problem_s* mtf_problem;
 
@@ -188,7 +189,11 @@ typedef struct {
  *     P_i = 1/2 [[0, -T_i^-1 / rho_i], [rho_i T_i^-1, 0]]
  * (the inverse of the off-diagonal part of 2 A_i; the block shape of the
  * block-OSRC preconditioner of Section 4.4 with the exact discrete T_i^-1),
- * T_i^-1 computed once per problem on the GPU in complex64.  Right
+ * T_i^-1 computed once per problem on the GPU in complex64.
+ * MTF_PREC_BLOCK_TINV_GS applies one block Gauss-Seidel sweep instead: Omega_0
+ * first, then the colour classes of the subdomain adjacency graph (subdomains
+ * of one class share no interface and are done together), each block solving
+ * with P_i after subtracting the transmission terms of the blocks already done.  Right
  * preconditioning leaves the judged residual ||b - M x|| unchanged.
  * MTF_FP32_MIXED runs the inner GMRES on the complex64 operator and corrects
  * with FP64 residuals (iterative refinement) until rtol holds for the FP64

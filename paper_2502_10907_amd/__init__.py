@@ -31,7 +31,7 @@ OK, NOT_CONVERGED = 0, 1
 ERR_NAMES = {-1: "ARG", -2: "MESH", -3: "NONFINITE", -4: "HIP", -5: "OOM", -6: "STATE", -7: "UNSUPPORTED"}
 FP64, FP32_MIXED, BF16_SPLIT = 0, 1, 2
 BLOCK_T, BLOCK_K = 0, 1
-PREC_NONE, PREC_BLOCK_TINV = 0, 1
+PREC_NONE, PREC_BLOCK_TINV, PREC_BLOCK_TINV_GS = 0, 1, 2
 
 
 class MTFError(RuntimeError):

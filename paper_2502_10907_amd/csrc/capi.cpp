@@ -42,7 +42,7 @@ struct GemmOp {
 struct GmresWork {
     int64_t n = 0;
     int maxit = 0, nb = 0;
-    DevBuf<double> V, tmp, tmp2, r, hpart, h, H, wn2, npart, upart, y;
+    DevBuf<double> V, tmp, tmp2, tmp3, r, hpart, h, H, wn2, npart, upart, y;
     DevBuf<int> flag;                // [0, nb) second-pass flags, [nb, 2nb) their counts
     DevBuf<int> cnt;                 // Arnoldi steps kept per right-hand side
     double* host = nullptr;          // pinned: nb x kSync Hessenberg columns + norm parts
@@ -82,6 +82,10 @@ struct mtf_problem_s {
     DevBuf<float> T32, K32, Tinv;
     bool have64 = false, have32 = false, have_tinv = false;
     GemmOp gm, gp;                   // multi-RHS MFMA products: operator blocks, preconditioner blocks
+    // block Gauss-Seidel stages: stage 0 = {Omega_0}, then colour classes of the subdomain graph
+    DevBuf<int4> d_stage_tiles;
+    DevBuf<int32_t> d_stage_dofs;
+    std::vector<int64_t> stage_tile0, stage_dof0;   // [nstage + 1] offsets
     double t_precond = 0;
     DevBuf<double> part;
     DevBuf<double> scratch_dirs;
@@ -167,6 +171,35 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
         for (int c = 0; c < doms[i].nchunk; ++c)
             for (int r0 = 0; r0 < E; r0 += kRows) mtiles.push_back(make_int4(i, r0, c, 0));
     }
+    // greedy colouring of subdomains 1..M (adjacent subdomains get different colours); stage 0 is Omega_0
+    std::vector<int> colour(M + 1, -1);
+    colour[0] = 0;
+    int ncol = 0;
+    for (int i = 1; i <= M; ++i) {
+        std::vector<char> used(M + 2, 0);
+        for (int lt = 0; lt < sk.dom[i].T; ++lt) {
+            const int j = sk.dom[i].other[lt];
+            if (j > 0 && colour[j] > 0) used[colour[j]] = 1;
+        }
+        int c = 1;
+        while (used[c]) ++c;
+        colour[i] = c;
+        ncol = std::max(ncol, c);
+    }
+    std::vector<int4> stiles;
+    std::vector<int32_t> sdofs;
+    std::vector<int64_t> st0{0}, sd0{0};
+    for (int c = 0; c <= ncol; ++c) {
+        for (int i = 0; i <= M; ++i) {
+            if (colour[i] != c) continue;
+            const int E = sk.dom[i].E;
+            for (int ch = 0; ch < doms[i].nchunk; ++ch)
+                for (int r0 = 0; r0 < E; r0 += kRows) stiles.push_back(make_int4(i, r0, ch, 0));
+            for (int m = 0; m < E; ++m) sdofs.push_back((int32_t)(doms[i].dof0 + m));
+        }
+        st0.push_back((int64_t)stiles.size());
+        sd0.push_back((int64_t)sdofs.size());
+    }
     std::vector<SingPair> sing(sk.singular.size());
     for (size_t q = 0; q < sk.singular.size(); ++q) {
         const auto& a = sk.singular[q];
@@ -188,6 +221,10 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
     p->d_tiles.upload(tiles, s);
     p->d_mtiles.upload(mtiles, s);
     p->d_sing.upload(sing, s);
+    p->d_stage_tiles.upload(stiles, s);
+    p->d_stage_dofs.upload(sdofs, s);
+    p->stage_tile0 = st0;
+    p->stage_dof0 = sd0;
     p->ntiles = (int64_t)tiles.size();
     p->nmtiles = (int64_t)mtiles.size();
     p->doms = doms;
@@ -387,6 +424,29 @@ void precond1(mtf_problem p, const double* x, double* z) {
     launch_precond_finish(p->d_doms.p, (int)p->doms.size(), p->d_dof_dom.p, p->ndof, p->part.p, z, p->stream);
 }
 
+// z = P_GS x: one block Gauss-Seidel sweep over the stages with the T_i^-1 block of each subdomain;
+// within a stage the subdomains are not adjacent and are processed together.
+void precond1_gs(mtf_problem p, const double* x, double* z, double* w) {
+    hipStream_t s = p->stream;
+    const int64_t n = p->sk.N;
+    launch_fill(z, 2 * n, 0.0, s);
+    const int nst = (int)p->stage_tile0.size() - 1;
+    for (int st = 0; st < nst; ++st) {
+        const int4* tiles = p->d_stage_tiles.p + p->stage_tile0[st];
+        const int64_t ntl = p->stage_tile0[st + 1] - p->stage_tile0[st];
+        const int32_t* dl = p->d_stage_dofs.p + p->stage_dof0[st];
+        const int64_t nd = p->stage_dof0[st + 1] - p->stage_dof0[st];
+        const double* in = x;
+        if (st > 0) {
+            launch_gs_residual(p->d_doms.p, p->d_dof_dom.p, dl, nd, p->d_dplus.p, p->d_dminus.p, p->d_gval.p, p->d_gcol.p,
+                               x, z, w, s);
+            in = w;
+        }
+        launch_precond_apply(p->d_doms.p, tiles, ntl, p->Tinv.p, in, p->part.p, s);
+        launch_precond_finish(p->d_doms.p, (int)p->doms.size(), p->d_dof_dom.p, nd, p->part.p, z, s, dl);
+    }
+}
+
 // X = inv(A) by recursive 2 x 2 Schur-complement splitting; A (complex64, ld lda) is overwritten.
 void inv_rec(float* A, int64_t lda, float* X, int64_t ldx, int n, float* work, int* info, hipStream_t s) {
     if (n <= 64) {
@@ -459,6 +519,7 @@ void gmres_alloc(mtf_problem p, int maxit, int nb) {
     w.V.alloc(2 * n * (int64_t)nb * (maxit + 1));
     w.tmp.alloc(2 * n * nb);
     w.tmp2.alloc(2 * n * nb);
+    w.tmp3.alloc(2 * n);
     w.r.alloc(2 * n * nb);
     w.hpart.alloc(2 * (int64_t)nb * (maxit + 2) * kNblk);
     w.h.alloc(2 * (int64_t)nb * (maxit + 1));
@@ -491,14 +552,23 @@ std::vector<double> norms_dev(mtf_problem p, const double* v, int64_t ld, int nb
 }
 
 // Inner operator A = M_prec P on the nb columns of slab src (ld n) into slab dst (ld n).
-void apply_inner(mtf_problem p, const double* src, double* dst, int nb, int prec, bool use_pc) {
+// z = P x for nb columns (ld n); pc: MTF_PREC_BLOCK_TINV (Jacobi) or MTF_PREC_BLOCK_TINV_GS.
+void apply_pc(mtf_problem p, int pc, int prec, int nb, const double* x, double* z) {
+    GmresWork& w = p->gw;
+    const int64_t n = w.n;
+    if (pc == MTF_PREC_BLOCK_TINV && prec == MTF_BF16_SPLIT) { apply_gemm(p, 1, nb, x, n, z); return; }
+    for (int b = 0; b < nb; ++b) {
+        if (pc == MTF_PREC_BLOCK_TINV_GS) precond1_gs(p, x + 2 * n * b, z + 2 * n * b, w.tmp3.p);
+        else precond1(p, x + 2 * n * b, z + 2 * n * b);
+    }
+}
+
+void apply_inner(mtf_problem p, const double* src, double* dst, int nb, int prec, int pc) {
     GmresWork& w = p->gw;
     const int64_t n = w.n;
     const double* in = src;
-    if (use_pc) {
-        if (prec == MTF_BF16_SPLIT) apply_gemm(p, 1, nb, src, n, w.tmp.p);
-        else
-            for (int b = 0; b < nb; ++b) precond1(p, src + 2 * n * b, w.tmp.p + 2 * n * b);
+    if (pc != MTF_PREC_NONE) {
+        apply_pc(p, pc, prec, nb, src, w.tmp.p);
         in = w.tmp.p;
     }
     if (prec == MTF_BF16_SPLIT) apply_gemm(p, 0, nb, in, n, dst);
@@ -511,7 +581,7 @@ void apply_inner(mtf_problem p, const double* src, double* dst, int nb, int prec
 // the DGKS test asks for it (decided on the device); Hessenberg columns stay on the device and the
 // host applies the Givens rotations every kSync steps.  Each right-hand side stops at its own step.
 // Returns the largest number of Arnoldi steps; it[b], est[b] (recurrence residual / ||r_b||) per column.
-int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, int prec, bool use_pc,
+int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, int prec, int pc,
                 const std::vector<double>& tol, int maxit, std::vector<int>& itv, std::vector<double>& est,
                 std::vector<int>& reorth) {
     GmresWork& w = p->gw;
@@ -541,7 +611,7 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
     int done_cols = 0, steps = 0;
     for (int j = 0; j < maxit && live > 0; ++j) {
         double* wv = Vs(j + 1);
-        apply_inner(p, Vs(j), wv, nb, prec, use_pc);
+        apply_inner(p, Vs(j), wv, nb, prec, pc);
         const int nv = j + 1;
         launch_multidot(V, ldv, nv, nvmax, wv, n, w.hpart.p, kNblk, 1, nullptr, nb, s);
         launch_reduce_h(w.hpart.p, nv, nvmax, kNblk, w.h.p, Hc(j), hstride, w.wn2.p, 0, nullptr, nb, s);
@@ -608,10 +678,8 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
     launch_fill(w.tmp2.p, 2 * n * nb, 0.0, s);
     launch_combine(w.tmp2.p, n, V, ldv, w.cnt.p, nvmax, w.y.p, n, nb, s);
     const double* corr = w.tmp2.p;
-    if (use_pc) {
-        if (prec == MTF_BF16_SPLIT) apply_gemm(p, 1, nb, w.tmp2.p, n, w.tmp.p);
-        else
-            for (int b = 0; b < nb; ++b) precond1(p, w.tmp2.p + 2 * n * b, w.tmp.p + 2 * n * b);
+    if (pc != MTF_PREC_NONE) {
+        apply_pc(p, pc, prec, nb, w.tmp2.p, w.tmp.p);
         corr = w.tmp.p;
     }
     for (int b = 0; b < nb; ++b) launch_axpby(X + 2 * ldx * (int64_t)b, corr + 2 * n * b, n, 1.0, 0.0, 1.0, s);
@@ -645,10 +713,12 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
     const int prec = opts.precision;
     check_prec_available(p, prec);
     if (!p->have64) throw StateError("mtf_solve checks residuals with the FP64 operator: assemble MTF_FP64 first");
-    if (opts.preconditioner != MTF_PREC_NONE && opts.preconditioner != MTF_PREC_BLOCK_TINV)
+    if (opts.preconditioner != MTF_PREC_NONE && opts.preconditioner != MTF_PREC_BLOCK_TINV &&
+        opts.preconditioner != MTF_PREC_BLOCK_TINV_GS)
         throw ArgError("unknown preconditioner");
     DeviceGuard g(p->device);
-    const bool use_pc = opts.preconditioner == MTF_PREC_BLOCK_TINV;
+    const int pc = opts.preconditioner;
+    const bool use_pc = pc != MTF_PREC_NONE;
     double t_pc = 0;
     if (use_pc && !p->have_tinv) { build_tinv(p); t_pc = p->t_precond; }
     // right-hand sides advance in lockstep batches when the products are GEMMs
@@ -696,7 +766,7 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
                 tol[b] = 0.9 * t;
             }
             if (all || outer == maxref || total >= maxit * (maxref + 1)) break;
-            total += gmres_cycle(p, w.r.p, X, ld, nb, prec, use_pc, tol, maxit, itv, est, reorth);
+            total += gmres_cycle(p, w.r.p, X, ld, nb, prec, pc, tol, maxit, itv, est, reorth);
             for (int b = 0; b < nb; ++b) iters[b] += itv[b];
         }
         const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

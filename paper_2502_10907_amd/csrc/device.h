@@ -138,7 +138,11 @@ int  launch_cinv_small_f32(float* A, int64_t lda, int n, int* info, hipStream_t 
 void launch_precond_apply(const DomDesc* doms, const int4* mtiles, int64_t nmt, const float* Tinv,
                           const double* x, double* part, hipStream_t s);
 void launch_precond_finish(const DomDesc* doms, int ndom, const int32_t* dof_dom, int64_t ndof_total,
-                           const double* part, double* y, hipStream_t s);
+                           const double* part, double* y, hipStream_t s, const int32_t* list = nullptr);
+// w_i = v_i - sum_j G^ij z_j for the dofs in `list` (one block Gauss-Seidel stage)
+void launch_gs_residual(const DomDesc* doms, const int32_t* dof_dom, const int32_t* list, int64_t nlist,
+                        const int32_t* dplus, const int32_t* dminus, const double* gval, const int64_t* gcol,
+                        const double* v, const double* z, double* w, hipStream_t s);
 void launch_nonfinite_check(const float* A, int64_t n, int* flag, hipStream_t s);
 
 // Multi-RHS block products (gemm.hip).

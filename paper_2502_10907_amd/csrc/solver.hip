@@ -133,11 +133,13 @@ __global__ __launch_bounds__(256) void k_pc_dense(const DomDesc* __restrict__ do
     pN[0] = aN[0]; pN[1] = aN[1];
 }
 
-// z_iD = -1/(2 rho) T^-1 x_iN,  z_iN = rho/2 T^-1 x_iD
+// z_iD = -1/(2 rho) T^-1 x_iN,  z_iN = rho/2 T^-1 x_iD  (all dofs, or the dofs of `list`)
 __global__ __launch_bounds__(256) void k_pc_finish(const DomDesc* __restrict__ doms, const int32_t* __restrict__ dof_dom,
-                                                   int64_t ndof, const double* __restrict__ part, double* __restrict__ z) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ndof) return;
+                                                   int64_t ndof, const double* __restrict__ part, double* __restrict__ z,
+                                                   const int32_t* __restrict__ list) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ndof) return;
+    const int64_t g = list ? list[t] : t;
     const DomDesc dd = doms[dof_dom[g]];
     const int64_t m = g - dd.dof0;
     const int E = dd.E;
@@ -153,6 +155,37 @@ __global__ __launch_bounds__(256) void k_pc_finish(const DomDesc* __restrict__ d
     double* oN = z + 2 * (dd.off + E + m);
     oD[0] = a * vN[0]; oD[1] = a * vN[1];
     oN[0] = b * vD[0]; oN[1] = b * vD[1];
+}
+
+// Block Gauss-Seidel stage input: w_i = v_i - sum_j G^ij z_j for the dofs of one stage (z holds
+// the already computed stages, zero elsewhere).
+__global__ __launch_bounds__(256) void k_gs_residual(const DomDesc* __restrict__ doms, const int32_t* __restrict__ dof_dom,
+                                                     const int32_t* __restrict__ list, int64_t nlist,
+                                                     const int32_t* __restrict__ dplus, const int32_t* __restrict__ dminus,
+                                                     const double* __restrict__ gval, const int64_t* __restrict__ gcol,
+                                                     const double* __restrict__ v, const double* __restrict__ z,
+                                                     double* __restrict__ w) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nlist) return;
+    const int64_t g = list[t];
+    const DomDesc dd = doms[dof_dom[g]];
+    const int64_t m = g - dd.dof0;
+    const int64_t iD = dd.off + m, iN = dd.off + dd.E + m;
+    double yD[2] = {v[2 * iD], v[2 * iD + 1]}, yN[2] = {v[2 * iN], v[2 * iN + 1]};
+    for (int side = 0; side < 2; ++side) {
+        const int32_t* pm = side == 0 ? dplus : dminus;
+        const int64_t rec = dd.rec0 + pm[2 * g];
+        const int a = pm[2 * g + 1];
+        for (int c = 0; c < 3; ++c) {
+            const double gv = gval[9 * rec + 3 * a + c];
+            const double* zd = z + 2 * gcol[6 * rec + c];
+            const double* zn = z + 2 * gcol[6 * rec + 3 + c];
+            yD[0] -= gv * zd[0]; yD[1] -= gv * zd[1];
+            yN[0] -= gv * zn[0]; yN[1] -= gv * zn[1];
+        }
+    }
+    w[2 * iD] = yD[0]; w[2 * iD + 1] = yD[1];
+    w[2 * iN] = yN[0]; w[2 * iN + 1] = yN[1];
 }
 
 // ---------------------------------------------------------------------------
@@ -540,12 +573,22 @@ void launch_matvec_finish(const DomDesc* doms, int /*ndom*/, const int32_t* dof_
 
 void launch_precond_apply(const DomDesc* doms, const int4* mtiles, int64_t nmt, const float* Tinv, const double* x,
                           double* part, hipStream_t s) {
+    if (nmt <= 0) return;
     hipLaunchKernelGGL(k_pc_dense, dim3((unsigned)nmt), dim3(256), 0, s, doms, mtiles, Tinv, x, part);
 }
 
 void launch_precond_finish(const DomDesc* doms, int /*ndom*/, const int32_t* dof_dom, int64_t ndof, const double* part,
-                           double* z, hipStream_t s) {
-    hipLaunchKernelGGL(k_pc_finish, dim3(gridn(ndof, 256)), dim3(256), 0, s, doms, dof_dom, ndof, part, z);
+                           double* z, hipStream_t s, const int32_t* list) {
+    if (ndof <= 0) return;
+    hipLaunchKernelGGL(k_pc_finish, dim3(gridn(ndof, 256)), dim3(256), 0, s, doms, dof_dom, ndof, part, z, list);
+}
+
+void launch_gs_residual(const DomDesc* doms, const int32_t* dof_dom, const int32_t* list, int64_t nlist,
+                        const int32_t* dplus, const int32_t* dminus, const double* gval, const int64_t* gcol,
+                        const double* v, const double* z, double* w, hipStream_t s) {
+    if (nlist <= 0) return;
+    hipLaunchKernelGGL(k_gs_residual, dim3(gridn(nlist, 256)), dim3(256), 0, s, doms, dof_dom, list, nlist, dplus, dminus,
+                       gval, gcol, v, z, w);
 }
 
 void launch_multidot(const double* V, int64_t ldv, int nv, int nvmax, const double* w, int64_t n, double* hpart,

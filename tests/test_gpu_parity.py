@@ -131,7 +131,7 @@ def test_matvec(name, request):
 
 
 @pytest.mark.parametrize("name", CASES)
-@pytest.mark.parametrize("pc", [mtf.PREC_NONE, mtf.PREC_BLOCK_TINV])
+@pytest.mark.parametrize("pc", [mtf.PREC_NONE, mtf.PREC_BLOCK_TINV, mtf.PREC_BLOCK_TINV_GS])
 def test_solve_fp64(name, pc, request):
     c = request.getfixturevalue(name)
     b = torch.tensor(c.b[None, :], device="cuda")
@@ -309,3 +309,12 @@ def test_batch_solve(sphere):
         assert s.converged
         assert np.linalg.norm(x[0].cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-7
     B.close()
+
+
+def test_gauss_seidel_needs_fewer_iterations(cube):
+    b = torch.tensor(cube.b[None, :], device="cuda")
+    its = {}
+    for pc in (mtf.PREC_BLOCK_TINV, mtf.PREC_BLOCK_TINV_GS):
+        x = torch.zeros_like(b)
+        its[pc] = cube.P.solve(b, x, rtol=1e-8, preconditioner=pc)[0].iterations
+    assert its[mtf.PREC_BLOCK_TINV_GS] < its[mtf.PREC_BLOCK_TINV]
