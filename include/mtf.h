@@ -136,6 +136,12 @@ int mtf_assemble(mtf_problem p, const mtf_assembly_opts* opts);
  * converted from complex64 for MTF_FP32_MIXED).  Synchronises. */
 int mtf_copy_block(mtf_problem p, int32_t i, int32_t which, int32_t precision, double* dst);
 
+/* Gather n entries (rows[k], cols[k]) of block `which` of subdomain i in the given
+ * precision into out (complex128 [n], host); indices must lie in [0, E_i).  For sampled
+ * checks of large blocks.  Synchronises. */
+int mtf_get_entries(mtf_problem p, int32_t i, int32_t which, int32_t precision, int32_t n,
+                    const int32_t* rows, const int32_t* cols, double* out);
+
 /* Copy the transmission block G^ij (row block i, column block j, j in
  * Lambda_i; real, dense E_i x E_j column-major) to host memory.  Zero if
  * Gamma_ij is empty.  Synchronises. */

@@ -79,6 +79,7 @@ _SIGS = {
     "mtf_assemble": (C.c_int, [_P, C.POINTER(AssemblyOpts)]),
     "mtf_copy_block": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, _dp]),
     "mtf_copy_transmission": (C.c_int, [_P, C.c_int32, C.c_int32, _dp]),
+    "mtf_get_entries": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _ip, _ip, _dp]),
     "mtf_rhs_plane_waves": (C.c_int, [_P, C.c_int32, _dp, _dp, _dp, _P, C.c_int64]),
     "mtf_matvec": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.c_int32]),
     "mtf_solve": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
@@ -239,6 +240,14 @@ class Problem:
         out = np.zeros(2 * E * E, dtype=np.float64)
         _check(_lib.mtf_copy_block(self._h, int(i), int(which), int(precision), out.ctypes.data_as(_dp)))
         return out.view(np.complex128).reshape(E, E, order="F")
+
+    def get_entries(self, i: int, which: int, rows, cols, precision: int = FP64) -> np.ndarray:
+        rows, pr = _i32(rows)
+        cols, pc = _i32(cols)
+        out = np.zeros(2 * rows.shape[0])
+        _check(_lib.mtf_get_entries(self._h, int(i), int(which), int(precision), rows.shape[0], pr, pc,
+                                    out.ctypes.data_as(_dp)))
+        return out.view(np.complex128)
 
     def copy_transmission(self, i: int, j: int) -> np.ndarray:
         out = np.zeros(int(self.E[i]) * int(self.E[j]), dtype=np.float64)

@@ -42,8 +42,7 @@ struct GemmOp {
 struct GmresWork {
     int64_t n = 0;
     int maxit = 0, nb = 0;
-    DevBuf<double> V, tmp, tmp2, tmp3, r, hpart, h, H, wn2, npart, upart, y;
-    DevBuf<int> flag;                // [0, nb) second-pass flags, [nb, 2nb) their counts
+    DevBuf<double> V, tmp, tmp2, tmp3, r, hpart, S, Z, hg, scal, H, npart, upart, y;
     DevBuf<int> cnt;                 // Arnoldi steps kept per right-hand side
     double* host = nullptr;          // pinned: nb x kSync Hessenberg columns + norm parts
     ~GmresWork() {
@@ -516,19 +515,21 @@ void gmres_alloc(mtf_problem p, int maxit, int nb) {
     w.maxit = maxit;
     w.nb = nb;
     const int64_t ldh = maxit + 1;
+    const int64_t nct = (maxit + 63) / 64;
     w.V.alloc(2 * n * (int64_t)nb * (maxit + 1));
     w.tmp.alloc(2 * n * nb);
     w.tmp2.alloc(2 * n * nb);
     w.tmp3.alloc(2 * n);
     w.r.alloc(2 * n * nb);
-    w.hpart.alloc(2 * (int64_t)nb * (maxit + 2) * kNblk);
-    w.h.alloc(2 * (int64_t)nb * (maxit + 1));
+    w.hpart.alloc(4 * (int64_t)nb * (maxit + 1) * kNblk);
+    w.S.alloc(2 * (int64_t)nb * (maxit + 1));
+    w.Z.alloc(2 * (int64_t)nb * (maxit + 1));
+    w.hg.alloc(2 * (int64_t)nb * nct * (maxit + 1));
+    w.scal.alloc(4 * (int64_t)nb);
     w.H.alloc(2 * ldh * (int64_t)maxit * nb);
-    w.wn2.alloc(nb);
     w.npart.alloc((int64_t)nb * kNblk);
-    w.upart.alloc(2 * n * (int64_t)nb * ((maxit + 63) / 64 + 1));
+    w.upart.alloc(4 * n * (int64_t)nb * std::max<int64_t>(nct, 1));
     w.y.alloc(2 * (int64_t)nb * (maxit + 1));
-    w.flag.alloc(2 * nb);
     w.cnt.alloc(nb);
     if (w.host) (void)hipHostFree(w.host);
     w.host = nullptr;
@@ -577,10 +578,12 @@ void apply_inner(mtf_problem p, const double* src, double* dst, int nb, int prec
 }
 
 // One GMRES cycle for nb right-hand sides in lockstep: residual slab R (ld n), corrections added to
-// the nb columns of X (ld ldx).  Arnoldi: one classical Gram-Schmidt pass, a second one only where
-// the DGKS test asks for it (decided on the device); Hessenberg columns stay on the device and the
-// host applies the Givens rotations every kSync steps.  Each right-hand side stops at its own step.
-// Returns the largest number of Arnoldi steps; it[b], est[b] (recurrence residual / ||r_b||) per column.
+// the nb columns of X (ld ldx).  Arnoldi with delayed classical Gram-Schmidt reorthogonalisation:
+// step j applies the operator to the once-projected candidate u_j, then one pass over the basis
+// gives the coefficients and a second pass forms q_j and u_{j+1}; Hessenberg column j-1 becomes
+// final at step j.  The Hessenberg matrix stays on the device; the host reads the final columns
+// every kSync steps and applies the Givens rotations.  Each right-hand side stops at its own step.
+// Returns the number of Arnoldi steps taken; it[b], est[b] (recurrence residual / ||r_b||) per column.
 int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, int prec, int pc,
                 const std::vector<double>& tol, int maxit, std::vector<int>& itv, std::vector<double>& est,
                 std::vector<int>& reorth) {
@@ -591,12 +594,12 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
     const int64_t hstride = ldh * (int64_t)w.maxit;
     const int64_t ldv = n * nb;
     const int nvmax = w.maxit;
+    const int nct = (w.maxit + 63) / 64;
     double* V = w.V.p;
     auto Vs = [&](int j) { return V + 2 * ldv * (int64_t)j; };
     auto Hc = [&](int j) { return w.H.p + 2 * ldh * (int64_t)j; };
     std::vector<double> beta = norms_dev(p, R, n, nb);
-    launch_scale_dev(Vs(0), R, n, n, w.npart.p, kNblk, nullptr, 0, nb, s);
-    HIPCHK(hipMemsetAsync(w.flag.p, 0, 2 * nb * sizeof(int), s));
+    HIPCHK(hipMemcpyAsync(Vs(0), R, (size_t)2 * n * nb * sizeof(double), hipMemcpyDeviceToDevice, s));   // u_0 = r
     std::vector<std::vector<cd>> H(nb, std::vector<cd>((size_t)ldh * maxit, cd(0)));
     std::vector<std::vector<double>> cs(nb, std::vector<double>(maxit, 0.0));
     std::vector<std::vector<cd>> sn(nb, std::vector<cd>(maxit, cd(0))), gv(nb, std::vector<cd>(maxit + 1, cd(0)));
@@ -609,23 +612,21 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
         if (beta[b] == 0.0) stop[b] = 1; else ++live;
     }
     int done_cols = 0, steps = 0;
-    for (int j = 0; j < maxit && live > 0; ++j) {
-        double* wv = Vs(j + 1);
-        apply_inner(p, Vs(j), wv, nb, prec, pc);
-        const int nv = j + 1;
-        launch_multidot(V, ldv, nv, nvmax, wv, n, w.hpart.p, kNblk, 1, nullptr, nb, s);
-        launch_reduce_h(w.hpart.p, nv, nvmax, kNblk, w.h.p, Hc(j), hstride, w.wn2.p, 0, nullptr, nb, s);
-        launch_update(V, ldv, nv, nvmax, w.h.p, wv, n, w.upart.p, nullptr, nb, s);
-        launch_norm2(wv, n, n, w.npart.p, kNblk, nb, s);
-        launch_reorth_flag(w.wn2.p, w.npart.p, kNblk, nb, w.flag.p, w.flag.p + nb, s);
-        launch_multidot(V, ldv, nv, nvmax, wv, n, w.hpart.p, kNblk, 0, w.flag.p, nb, s);
-        launch_reduce_h(w.hpart.p, nv, nvmax, kNblk, w.h.p, Hc(j), hstride, w.wn2.p, 1, w.flag.p, nb, s);
-        launch_update(V, ldv, nv, nvmax, w.h.p, wv, n, w.upart.p, w.flag.p, nb, s);
-        launch_norm2(wv, n, n, w.npart.p, kNblk, nb, s);
-        launch_scale_dev(wv, wv, n, n, w.npart.p, kNblk, Hc(j) + 2 * (j + 1), hstride, nb, s);
-        steps = j + 1;
-        if ((j + 1) % kSync != 0 && j + 1 != maxit) continue;
-        const int c0 = done_cols, nc = j + 1 - done_cols;
+    for (int j = 0; j <= maxit && live > 0; ++j) {
+        const bool last = j == maxit;      // only finalises column maxit-1
+        double* u = Vs(j);
+        double* t = last ? u : Vs(j + 1);
+        if (!last) apply_inner(p, u, t, nb, prec, pc);
+        launch_dot2(V, ldv, j, nvmax, u, t, n, w.hpart.p, kNblk, nb, s);
+        launch_reduce2(w.hpart.p, j, nvmax, kNblk, w.S.p, w.Z.p, nb, s);
+        if (!last) launch_hess_gemv(w.H.p, ldh, hstride, w.S.p, j, nvmax, nct, w.hg.p, nb, s);
+        launch_dcgs_col(w.H.p, ldh, hstride, w.S.p, w.Z.p, w.hg.p, nct, j, nvmax, w.scal.p, last ? 1 : 0, nb, s);
+        if (!last) launch_update2(V, ldv, j, nvmax, w.S.p, w.Z.p, u, t, n, w.upart.p, w.scal.p, nb, s);
+        steps = j;
+        if ((j % kSync != 0 || j == 0) && !last) continue;
+        // columns done_cols .. j-1 are final
+        const int c0 = done_cols, nc = j - done_cols;
+        if (nc <= 0) continue;
         HIPCHK(hipMemcpy2DAsync(w.host, (size_t)2 * ldh * nc * sizeof(double), Hc(c0), (size_t)2 * hstride * sizeof(double),
                                 (size_t)2 * ldh * nc * sizeof(double), nb, hipMemcpyDeviceToHost, s));
         sync(p);
@@ -638,9 +639,9 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
                 for (int i = 0; i <= jj + 1; ++i) col[i] = cd(hb[2 * (ldh * q + i)], hb[2 * (ldh * q + i) + 1]);
                 const double hn = col[jj + 1].real();
                 for (int i = 0; i < jj; ++i) {
-                    const cd t = cs[b][i] * col[i] + sn[b][i] * col[i + 1];
+                    const cd tq = cs[b][i] * col[i] + sn[b][i] * col[i + 1];
                     col[i + 1] = -std::conj(sn[b][i]) * col[i] + cs[b][i] * col[i + 1];
-                    col[i] = t;
+                    col[i] = tq;
                 }
                 const cd a = col[jj];
                 const double den = std::sqrt(std::norm(a) + hn * hn);
@@ -656,7 +657,7 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
                 if (resid[b] <= tol[b] * beta[b] || hn == 0.0) { stop[b] = 1; --live; }
             }
         }
-        done_cols = j + 1;
+        done_cols = j;
     }
     // back substitution per right-hand side, then X_b += P (V_b y_b)
     std::vector<double> yh((size_t)2 * nb * (nvmax + 1), 0.0);
@@ -683,12 +684,10 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
         corr = w.tmp.p;
     }
     for (int b = 0; b < nb; ++b) launch_axpby(X + 2 * ldx * (int64_t)b, corr + 2 * n * b, n, 1.0, 0.0, 1.0, s);
-    std::vector<int> cnt(2 * nb);
-    HIPCHK(hipMemcpyAsync(cnt.data(), w.flag.p, cnt.size() * sizeof(int), hipMemcpyDeviceToHost, s));
     sync(p);
     est.assign(nb, 0.0);
     for (int b = 0; b < nb; ++b) {
-        reorth[b] += cnt[nb + b];
+        reorth[b] += itv[b];          // every kept step was reorthogonalised
         est[b] = beta[b] > 0 ? resid[b] / beta[b] : 0.0;
     }
     return steps;
@@ -934,6 +933,38 @@ int mtf_copy_block(mtf_problem p, int32_t i, int32_t which, int32_t precision, d
             sync(p);
             for (int64_t e = 0; e < ne; ++e) dst[e] = tmp[e];
         }
+        return MTF_OK;
+    });
+}
+
+int mtf_get_entries(mtf_problem p, int32_t i, int32_t which, int32_t precision, int32_t n, const int32_t* rows,
+                    const int32_t* cols, double* out) {
+    return guarded([&] {
+        if (!p || !rows || !cols || !out || n < 0) throw ArgError("bad arguments");
+        if (!p->has_mesh) throw StateError("no mesh");
+        if (i < 0 || i > p->sk.M) throw ArgError("subdomain index out of range");
+        if (which != MTF_BLOCK_T && which != MTF_BLOCK_K) throw ArgError("which must be MTF_BLOCK_T or MTF_BLOCK_K");
+        if (precision != MTF_FP64 && precision != MTF_FP32_MIXED) throw ArgError("precision must be MTF_FP64 or MTF_FP32_MIXED");
+        check_prec_available(p, precision);
+        const DomDesc& d = p->doms[i];
+        for (int k = 0; k < n; ++k)
+            if (rows[k] < 0 || rows[k] >= d.E || cols[k] < 0 || cols[k] >= d.E) throw ArgError("entry index out of range");
+        DeviceGuard g(p->device);
+        for (int k = 0; k < n; ++k) {
+            const int64_t e = d.mat0 + rows[k] + (int64_t)cols[k] * d.E;
+            if (precision == MTF_FP64) {
+                const double* src = (which == MTF_BLOCK_T ? p->T64.p : p->K64.p) + 2 * e;
+                HIPCHK(hipMemcpyAsync(out + 2 * k, src, 2 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+            } else {
+                float tmp[2];
+                const float* src = (which == MTF_BLOCK_T ? p->T32.p : p->K32.p) + 2 * e;
+                HIPCHK(hipMemcpyAsync(tmp, src, 2 * sizeof(float), hipMemcpyDeviceToHost, p->stream));
+                sync(p);
+                out[2 * k] = tmp[0];
+                out[2 * k + 1] = tmp[1];
+            }
+        }
+        sync(p);
         return MTF_OK;
     });
 }

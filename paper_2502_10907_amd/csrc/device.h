@@ -109,20 +109,21 @@ void launch_matvec_finish(const DomDesc* doms, int ndom, const int32_t* dof_dom,
 // GMRES vector kernels (complex128, length n), batched over nb right-hand sides in lockstep
 // (Krylov slab j at V + j*ldv with ldv = nb*n; column b of each slab is right-hand side b).
 // Kernels taking `flag` skip right-hand side b when flag[b] == 0.
-void launch_multidot(const double* V, int64_t ldv, int nv, int nvmax, const double* w, int64_t n, double* hpart,
-                     int nblk, int self, const int* flag, int nb, hipStream_t s);
-void launch_reduce_h(const double* hpart, int nv, int nvmax, int nblk, double* h, double* Hcol, int64_t hstride,
-                     double* wn2, int second, const int* flag, int nb, hipStream_t s);
-void launch_reorth_flag(const double* wn2, const double* part, int nblk, int nb, int* flag, int* count, hipStream_t s);
-void launch_update(const double* V, int64_t ldv, int nv, int nvmax, const double* h, double* w, int64_t n,
-                   double* part, const int* flag, int nb, hipStream_t s);   // w_b -= V_b h_b
+// Arnoldi step with delayed reorthogonalisation (DCGS2), nb right-hand sides in lockstep
+void launch_dot2(const double* V, int64_t ldv, int nv, int nvmax, const double* u, const double* t, int64_t n,
+                 double* hpart, int nblk, int nb, hipStream_t s);           // partial Q^H [u t], u^H [u t]
+void launch_reduce2(const double* hpart, int nv, int nvmax, int nblk, double* S, double* Z, int nb, hipStream_t s);
+void launch_hess_gemv(const double* H, int64_t ldh, int64_t hstride, const double* S, int nv, int nvmax, int nct,
+                      double* hg, int nb, hipStream_t s);                   // partial Hbar s
+void launch_dcgs_col(double* H, int64_t ldh, int64_t hstride, const double* S, const double* Z, const double* hg, int nct,
+                     int nv, int nvmax, double* scal, int last, int nb, hipStream_t s);
+void launch_update2(const double* V, int64_t ldv, int nv, int nvmax, const double* S, const double* Z, double* u,
+                    double* t, int64_t n, double* part, const double* scal, int nb, hipStream_t s);
 void launch_combine(double* x, int64_t ldx, const double* V, int64_t ldv, const int* cnt, int nvmax, const double* coef,
                     int64_t n, int nb, hipStream_t s);                       // x_b += V_b coef_b
 void launch_norm2(const double* w, int64_t ldw, int64_t n, double* part, int nblk, int nb, hipStream_t s);
 void launch_axpby(double* y, const double* x, int64_t n, double a_re, double a_im, double b,
                   hipStream_t s);       // y = b*y + a*x (a complex, b real)
-void launch_scale_dev(double* y, const double* x, int64_t ld, int64_t n, const double* part, int nblk, double* hsub,
-                      int64_t hstride, int nb, hipStream_t s);   // y_b = x_b / ||x_b||, hsub_b = ||x_b||
 
 void launch_far_field(const DomDesc* d0, const TriGeom* geom, const int32_t* tdof, const int8_t* tsign,
                       int32_t T0, double k0, double rho0, const double* x, int64_t ldx, int nrhs,

@@ -65,39 +65,56 @@ __global__ __launch_bounds__(256) void k_mv_dense(const DomDesc* __restrict__ do
     pN[1] = -2.0 * rho * (double)tD[1] + 2.0 * (double)kN[1];
 }
 
+// Finishing kernels: 64 dofs per workgroup, the four wavefronts split the column chunks of the
+// partial sums (and the two transmission triangles) and meet in LDS.
+__device__ inline void finish_reduce(double (&acc)[4], double (*red)[64][4]) {
+    const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
+    for (int k = 0; k < 4; ++k) red[q][r][k] = acc[k];
+    __syncthreads();
+    if (q == 0)
+        for (int k = 0; k < 4; ++k) acc[k] = red[0][r][k] + red[1][r][k] + red[2][r][k] + red[3][r][k];
+}
+
 __global__ __launch_bounds__(256) void k_mv_finish(const DomDesc* __restrict__ doms, const int32_t* __restrict__ dof_dom,
                                                    int64_t ndof, const int32_t* __restrict__ dplus,
                                                    const int32_t* __restrict__ dminus, const double* __restrict__ gval,
                                                    const int64_t* __restrict__ gcol, const double* __restrict__ part,
                                                    const double* __restrict__ x, double* __restrict__ y) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ndof) return;
-    const DomDesc dd = doms[dof_dom[g]];
-    const int64_t m = g - dd.dof0;
-    const int E = dd.E;
-    double yD[2] = {0, 0}, yN[2] = {0, 0};
-    for (int c = 0; c < dd.nchunk; ++c) {
-        const double* pD = part + 2 * (dd.part0 + (int64_t)(2 * c) * E + m);
-        const double* pN = part + 2 * (dd.part0 + (int64_t)(2 * c + 1) * E + m);
-        yD[0] += pD[0]; yD[1] += pD[1];
-        yN[0] += pN[0]; yN[1] += pN[1];
-    }
-    for (int side = 0; side < 2; ++side) {
-        const int32_t* pm = side == 0 ? dplus : dminus;
-        const int64_t rec = dd.rec0 + pm[2 * g];
-        const int a = pm[2 * g + 1];
-        for (int c = 0; c < 3; ++c) {
-            const double v = gval[9 * rec + 3 * a + c];
-            const double* xd = x + 2 * gcol[6 * rec + c];
-            const double* xn = x + 2 * gcol[6 * rec + 3 + c];
-            yD[0] += v * xd[0]; yD[1] += v * xd[1];
-            yN[0] += v * xn[0]; yN[1] += v * xn[1];
+    __shared__ double red[4][64][4];
+    const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t g = (int64_t)blockIdx.x * 64 + r;
+    double acc[4] = {0, 0, 0, 0};     // yD re, im, yN re, im
+    DomDesc dd;
+    int64_t m = 0;
+    if (g < ndof) {
+        dd = doms[dof_dom[g]];
+        m = g - dd.dof0;
+        const int E = dd.E;
+        for (int c = q; c < dd.nchunk; c += 4) {
+            const double* pD = part + 2 * (dd.part0 + (int64_t)(2 * c) * E + m);
+            const double* pN = part + 2 * (dd.part0 + (int64_t)(2 * c + 1) * E + m);
+            acc[0] += pD[0]; acc[1] += pD[1];
+            acc[2] += pN[0]; acc[3] += pN[1];
+        }
+        if (q < 2) {
+            const int32_t* pm = q == 0 ? dplus : dminus;
+            const int64_t rec = dd.rec0 + pm[2 * g];
+            const int a = pm[2 * g + 1];
+            for (int c = 0; c < 3; ++c) {
+                const double v = gval[9 * rec + 3 * a + c];
+                const double* xd = x + 2 * gcol[6 * rec + c];
+                const double* xn = x + 2 * gcol[6 * rec + 3 + c];
+                acc[0] += v * xd[0]; acc[1] += v * xd[1];
+                acc[2] += v * xn[0]; acc[3] += v * xn[1];
+            }
         }
     }
+    finish_reduce(acc, red);
+    if (q != 0 || g >= ndof) return;
     double* oD = y + 2 * (dd.off + m);
-    double* oN = y + 2 * (dd.off + E + m);
-    oD[0] = yD[0]; oD[1] = yD[1];
-    oN[0] = yN[0]; oN[1] = yN[1];
+    double* oN = y + 2 * (dd.off + dd.E + m);
+    oD[0] = acc[0]; oD[1] = acc[1];
+    oN[0] = acc[2]; oN[1] = acc[3];
 }
 
 // u = T^-1 x_N and v = T^-1 x_D per subdomain (complex64 matrix, FP32 accumulation).
@@ -137,24 +154,31 @@ __global__ __launch_bounds__(256) void k_pc_dense(const DomDesc* __restrict__ do
 __global__ __launch_bounds__(256) void k_pc_finish(const DomDesc* __restrict__ doms, const int32_t* __restrict__ dof_dom,
                                                    int64_t ndof, const double* __restrict__ part, double* __restrict__ z,
                                                    const int32_t* __restrict__ list) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ndof) return;
-    const int64_t g = list ? list[t] : t;
-    const DomDesc dd = doms[dof_dom[g]];
-    const int64_t m = g - dd.dof0;
-    const int E = dd.E;
-    double vD[2] = {0, 0}, vN[2] = {0, 0};
-    for (int c = 0; c < dd.nchunk; ++c) {
-        const double* pD = part + 2 * (dd.part0 + (int64_t)(2 * c) * E + m);
-        const double* pN = part + 2 * (dd.part0 + (int64_t)(2 * c + 1) * E + m);
-        vD[0] += pD[0]; vD[1] += pD[1];
-        vN[0] += pN[0]; vN[1] += pN[1];
+    __shared__ double red[4][64][4];
+    const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t t = (int64_t)blockIdx.x * 64 + r;
+    double acc[4] = {0, 0, 0, 0};     // vD re, im, vN re, im
+    DomDesc dd;
+    int64_t m = 0;
+    if (t < ndof) {
+        const int64_t g = list ? list[t] : t;
+        dd = doms[dof_dom[g]];
+        m = g - dd.dof0;
+        const int E = dd.E;
+        for (int c = q; c < dd.nchunk; c += 4) {
+            const double* pD = part + 2 * (dd.part0 + (int64_t)(2 * c) * E + m);
+            const double* pN = part + 2 * (dd.part0 + (int64_t)(2 * c + 1) * E + m);
+            acc[0] += pD[0]; acc[1] += pD[1];
+            acc[2] += pN[0]; acc[3] += pN[1];
+        }
     }
+    finish_reduce(acc, red);
+    if (q != 0 || t >= ndof) return;
     const double a = -0.5 / dd.rho, b = 0.5 * dd.rho;
     double* oD = z + 2 * (dd.off + m);
-    double* oN = z + 2 * (dd.off + E + m);
-    oD[0] = a * vN[0]; oD[1] = a * vN[1];
-    oN[0] = b * vD[0]; oN[1] = b * vD[1];
+    double* oN = z + 2 * (dd.off + dd.E + m);
+    oD[0] = a * acc[2]; oD[1] = a * acc[3];
+    oN[0] = b * acc[0]; oN[1] = b * acc[1];
 }
 
 // Block Gauss-Seidel stage input: w_i = v_i - sum_j G^ij z_j for the dofs of one stage (z holds
@@ -198,133 +222,234 @@ __device__ inline double wsum(double v) {
     return v;
 }
 
-// Batched Arnoldi kernels.  nb right-hand sides advance in lockstep: Krylov block j is an
-// n x nb column-major slab at V + j*ldv (ldv = nb*n), column b of every slab belongs to
-// right-hand side b (gridDim.z or blockIdx.z = b).  Per right-hand side b:
-//   hpart[(b*(nvmax+1) + i) * nblk + blk]  partial dots,   h[b*(nvmax+1) + i]  reduced dots,
-//   H + b*hstride + column j               Hessenberg column,   wn2[b], flag[b], npart[b*nblk + k].
+// Batched Arnoldi with delayed classical Gram-Schmidt reorthogonalisation (DCGS2; Swirydowicz,
+// Thomas, Yamazaki and others, 2020/2022).  At step j the slot V_j holds u, the candidate for
+// q_j after ONE projection against Q_j = [q_0 .. q_{j-1}] (not yet normalised), and t = A u.  One
+// pass over Q_j forms s = Q_j^H u, z = Q_j^H t, alpha = u^H u, gamma = u^H t; then
+//   nu = sqrt(alpha - |s|^2),  q_j = (u - Q_j s) / nu,  c = (gamma - s^H z) / nu,
+//   Hessenberg column j-1 (final) = its first-pass value + s, subdiagonal nu,
+//   first-pass column j = ([z; c] - Hbar_j s) / nu   (A Q_j = Q_{j+1} Hbar_j),
+//   next candidate u' = (t - Q_j z - q_j c) / nu,
+// and a second pass over Q_j forms q_j and u' together: two reads of the basis per step instead
+// of four.  nb right-hand sides advance in lockstep: Krylov slot j is an n x nb column-major slab
+// at V + j*ldv (ldv = nb*n), column b belongs to right-hand side b (blockIdx.z or blockIdx.y).
+// Per right-hand side b:  S, Z + b*(nvmax+1)  the coefficients (slot j holds alpha and gamma),
+// H + b*hstride  the Hessenberg matrix (column-major, ld ldh),  scal + 4b  {nu, Re c, Im c}.
 
-// conj(V_i) . w for i < nv (and w . w in slot nv when `self`); skipped where flag[b] == 0.
-__global__ __launch_bounds__(256) void k_multidot(const double* __restrict__ V, int64_t ldv, int nv, int nvmax,
-                                                  const double* __restrict__ W, int64_t n, double* __restrict__ hpart,
-                                                  int nblk, const int* __restrict__ flag) {
+// hpart[((b*(nvmax+1) + i)*nblk + blk)*4 + {0,1,2,3}] = partial {conj(v_i).u, conj(v_i).t},
+// v_i = V_i for i < nv and v_nv = u.
+__global__ __launch_bounds__(256) void k_dot2(const double* __restrict__ V, int64_t ldv, int nv, int nvmax,
+                                              const double* __restrict__ U, const double* __restrict__ Tt, int64_t n,
+                                              double* __restrict__ hpart, int nblk) {
     const int b = blockIdx.z;
-    if (flag && flag[b] == 0) return;
     const int i = blockIdx.y;
     const int blk = blockIdx.x;
     const int64_t chunk = (n + nblk - 1) / nblk;
     const int64_t lo = blk * chunk, hi = min(n, lo + chunk);
-    const double* w = W + 2 * (int64_t)b * n;
-    const double* v = (i == nv) ? w : V + 2 * ((int64_t)i * ldv + (int64_t)b * n);
-    double re = 0, im = 0;
+    const double* u = U + 2 * (int64_t)b * n;
+    const double* t = Tt + 2 * (int64_t)b * n;
+    const double* v = (i == nv) ? u : V + 2 * ((int64_t)i * ldv + (int64_t)b * n);
+    double ur = 0, ui = 0, tr = 0, ti = 0;
     for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-        const double vr = v[2 * e], vi = v[2 * e + 1], wr = w[2 * e], wi = w[2 * e + 1];
-        re += vr * wr + vi * wi;
-        im += vr * wi - vi * wr;
+        const double vr = v[2 * e], vi = v[2 * e + 1];
+        const double a = u[2 * e], c = u[2 * e + 1], d = t[2 * e], f = t[2 * e + 1];
+        ur += vr * a + vi * c;
+        ui += vr * c - vi * a;
+        tr += vr * d + vi * f;
+        ti += vr * f - vi * d;
     }
-    __shared__ double red[2][4];
-    re = wsum(re);
-    im = wsum(im);
+    __shared__ double red[4][4];
+    ur = wsum(ur); ui = wsum(ui); tr = wsum(tr); ti = wsum(ti);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) { red[0][wv] = re; red[1][wv] = im; }
+    if (lane == 0) { red[0][wv] = ur; red[1][wv] = ui; red[2][wv] = tr; red[3][wv] = ti; }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double a = 0, c = 0;
-        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { a += red[0][k]; c += red[1][k]; }
-        const int64_t slot = ((int64_t)b * (nvmax + 1) + i) * nblk + blk;
-        hpart[2 * slot] = a;
-        hpart[2 * slot + 1] = c;
+    if (threadIdx.x < 4) {
+        double acc = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) acc += red[threadIdx.x][k];
+        hpart[(((int64_t)b * (nvmax + 1) + i) * nblk + blk) * 4 + threadIdx.x] = acc;
     }
 }
 
-__global__ void k_reduce_h(const double* __restrict__ hpart, int nv, int nvmax, int nblk, double* __restrict__ h,
-                           double* __restrict__ Hcol, int64_t hstride, double* __restrict__ wn2, int second,
-                           const int* __restrict__ flag) {
+// S_i, Z_i from the partial sums, i <= nv
+__global__ void k_reduce2(const double* __restrict__ hpart, int nv, int nvmax, int nblk, double* __restrict__ S,
+                          double* __restrict__ Z) {
     const int b = blockIdx.y;
-    if (flag && flag[b] == 0) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int top = second ? nv : nv + 1;
-    if (i >= top) return;
-    double a = 0, c = 0;
-    const int64_t base = ((int64_t)b * (nvmax + 1) + i) * nblk;
-    for (int k = 0; k < nblk; ++k) { a += hpart[2 * (base + k)]; c += hpart[2 * (base + k) + 1]; }
-    if (i == nv) { wn2[b] = a; return; }
-    double* hb = h + 2 * ((int64_t)b * (nvmax + 1));
-    double* Hb = Hcol + 2 * (int64_t)b * hstride;
-    hb[2 * i] = a;
-    hb[2 * i + 1] = c;
-    if (second) { Hb[2 * i] += a; Hb[2 * i + 1] += c; }
-    else { Hb[2 * i] = a; Hb[2 * i + 1] = c; }
+    if (i > nv) return;
+    double a[4] = {0, 0, 0, 0};
+    const double* p = hpart + ((int64_t)b * (nvmax + 1) + i) * nblk * 4;
+    for (int k = 0; k < nblk; ++k)
+        for (int q = 0; q < 4; ++q) a[q] += p[4 * k + q];
+    const int64_t o = (int64_t)b * (nvmax + 1) + i;
+    S[2 * o] = a[0]; S[2 * o + 1] = a[1];
+    Z[2 * o] = a[2]; Z[2 * o + 1] = a[3];
 }
 
-// Second Gram-Schmidt pass only when the first lost too much: ||w'||^2 < ||w||^2 / 2 (DGKS test).
-__global__ void k_reorth_flag(const double* __restrict__ wn2, const double* __restrict__ part, int nblk, int nb,
-                              int* __restrict__ flag, int* __restrict__ count) {
-    const int b = threadIdx.x;
-    if (b >= nb) return;
-    double s = 0;
-    for (int k = 0; k < nblk; ++k) s += part[(int64_t)b * nblk + k];
-    const int f = s < 0.5 * wn2[b] ? 1 : 0;
-    flag[b] = f;
-    count[b] += f;
-}
-
-// part[(b*nch + c)][e] = sum_{i in vector chunk c} V_i[e] h[i]   (64 vectors per chunk)
-__global__ __launch_bounds__(256) void k_update_part(const double* __restrict__ V, int64_t ldv, int nv, int nvmax,
-                                                     const double* __restrict__ h, double* __restrict__ part,
-                                                     int64_t n, const int* __restrict__ flag) {
+// Partial products of the stored Hessenberg columns 0..nv-1 with s: tile (row block rt of 64 rows,
+// column block kc of 64 columns) -> hg[(b*nct + kc)*(nvmax+1) + i].  Only entries i <= k+1 count;
+// row nv of column nv-1 is not final yet and is left out (k_dcgs_col adds its share).  Tiles with
+// rt > kc + 1 lie below the band: they are neither written nor read.
+__global__ __launch_bounds__(256) void k_hess_gemv(const double* __restrict__ H, int64_t ldh, int64_t hstride,
+                                                   const double* __restrict__ S, int nv, int nvmax, int nct,
+                                                   double* __restrict__ hg) {
     const int b = blockIdx.z;
-    if (flag && flag[b] == 0) return;
-    __shared__ double hs[2 * 64];
+    const int rt = blockIdx.x, kc = blockIdx.y;
+    if (rt > kc + 1) return;
+    const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int i = rt * 64 + r;
+    const double* Hb = H + 2 * (int64_t)b * hstride;
+    const double* sb = S + 2 * (int64_t)b * (nvmax + 1);
+    double re = 0, im = 0;
+    const int k0 = kc * 64 + q * 16;
+    if (i <= nv) {
+#pragma unroll 4
+        for (int kk = 0; kk < 16; ++kk) {
+            const int k = k0 + kk;
+            if (k >= nv || i > k + 1 || (k == nv - 1 && i == nv)) continue;
+            const double hr = Hb[2 * ((int64_t)k * ldh + i)], hi = Hb[2 * ((int64_t)k * ldh + i) + 1];
+            const double sr = sb[2 * k], si = sb[2 * k + 1];
+            re += hr * sr - hi * si;
+            im += hr * si + hi * sr;
+        }
+    }
+    __shared__ double red[4][64][2];
+    red[q][r][0] = re;
+    red[q][r][1] = im;
+    __syncthreads();
+    if (q == 0 && i <= nv) {
+        const double a = red[0][r][0] + red[1][r][0] + red[2][r][0] + red[3][r][0];
+        const double c = red[0][r][1] + red[1][r][1] + red[2][r][1] + red[3][r][1];
+        const int64_t o = ((int64_t)b * nct + kc) * (nvmax + 1) + i;
+        hg[2 * o] = a;
+        hg[2 * o + 1] = c;
+    }
+}
+
+// nu, c; finalise Hessenberg column nv-1; first-pass column nv (skipped when `last`).
+__global__ __launch_bounds__(256) void k_dcgs_col(double* __restrict__ H, int64_t ldh, int64_t hstride,
+                                                  const double* __restrict__ S, const double* __restrict__ Z,
+                                                  const double* __restrict__ hg, int nct, int nv, int nvmax,
+                                                  double* __restrict__ scal, int last) {
+    const int b = blockIdx.y;
+    const double* sb = S + 2 * (int64_t)b * (nvmax + 1);
+    const double* zb = Z + 2 * (int64_t)b * (nvmax + 1);
+    double ss = 0, pr = 0, pi = 0;
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+        const double sr = sb[2 * i], si = sb[2 * i + 1], zr = zb[2 * i], zi = zb[2 * i + 1];
+        ss += sr * sr + si * si;
+        pr += sr * zr + si * zi;
+        pi += sr * zi - si * zr;
+    }
+    __shared__ double red[3][4];
+    ss = wsum(ss); pr = wsum(pr); pi = wsum(pi);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) { red[0][wv] = ss; red[1][wv] = pr; red[2][wv] = pi; }
+    __syncthreads();
+    ss = pr = pi = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { ss += red[0][k]; pr += red[1][k]; pi += red[2][k]; }
+    const double alpha = sb[2 * nv];
+    const double nu2 = alpha - ss;
+    const double nu = nu2 > 0 ? sqrt(nu2) : 0.0;
+    const double inv = nu > 0 ? 1.0 / nu : 0.0;
+    const double cr = (zb[2 * nv] - pr) * inv, ci = (zb[2 * nv + 1] - pi) * inv;
+    if (blockIdx.x == 0 && threadIdx.x == 0) { scal[4 * b] = nu; scal[4 * b + 1] = cr; scal[4 * b + 2] = ci; }
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > nv) return;
+    double* Hb = H + 2 * (int64_t)b * hstride;
+    if (nv >= 1) {
+        double* Hc = Hb + 2 * (int64_t)(nv - 1) * ldh;
+        if (i < nv) { Hc[2 * i] += sb[2 * i]; Hc[2 * i + 1] += sb[2 * i + 1]; }
+        else { Hc[2 * i] = nu; Hc[2 * i + 1] = 0.0; }
+    }
+    if (last) return;
+    double hr = 0, hi = 0;
+    if (nv >= 1) {
+        const int kc0 = max(0, i / 64 - 1), kc1 = (nv + 63) / 64;    // the tiles this step wrote
+        for (int kc = kc0; kc < kc1; ++kc) {
+            const int64_t o = ((int64_t)b * nct + kc) * (nvmax + 1) + i;
+            hr += hg[2 * o];
+            hi += hg[2 * o + 1];
+        }
+        // column nv-1 changed after the partial products: + (s_i or nu) * s_{nv-1}
+        const double lr = sb[2 * (nv - 1)], li = sb[2 * (nv - 1) + 1];
+        const double fr = i < nv ? sb[2 * i] : nu, fi = i < nv ? sb[2 * i + 1] : 0.0;
+        hr += fr * lr - fi * li;
+        hi += fr * li + fi * lr;
+    }
+    const double zr = i < nv ? zb[2 * i] : cr, zi = i < nv ? zb[2 * i + 1] : ci;
+    double* Hn = Hb + 2 * (int64_t)nv * ldh;
+    Hn[2 * i] = (zr - hr) * inv;
+    Hn[2 * i + 1] = (zi - hi) * inv;
+}
+
+// part[((b*nch + c)*n + e)*4 + {0..3}] = sum over the 64 vectors of chunk c of {V_i s_i, V_i z_i}
+__global__ __launch_bounds__(256) void k_update2_part(const double* __restrict__ V, int64_t ldv, int nv, int nvmax,
+                                                      const double* __restrict__ S, const double* __restrict__ Z,
+                                                      double* __restrict__ part, int64_t n) {
+    const int b = blockIdx.z;
+    __shared__ double cs[4 * 64];
     const int c = blockIdx.y;
     const int nch = gridDim.y;
     const int i0 = c * 64;
     const int cnt = min(64, nv - i0);
-    const double* hb = h + 2 * ((int64_t)b * (nvmax + 1));
-    if ((int)threadIdx.x < cnt) { hs[2 * threadIdx.x] = hb[2 * (i0 + threadIdx.x)]; hs[2 * threadIdx.x + 1] = hb[2 * (i0 + threadIdx.x) + 1]; }
+    const int64_t cb = (int64_t)b * (nvmax + 1);
+    if ((int)threadIdx.x < cnt) {
+        const int64_t o = cb + i0 + threadIdx.x;
+        cs[4 * threadIdx.x] = S[2 * o]; cs[4 * threadIdx.x + 1] = S[2 * o + 1];
+        cs[4 * threadIdx.x + 2] = Z[2 * o]; cs[4 * threadIdx.x + 3] = Z[2 * o + 1];
+    }
     __syncthreads();
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
-    double re = 0, im = 0;
+    double ar = 0, ai = 0, br = 0, bi = 0;
     const double* v = V + 2 * ((int64_t)i0 * ldv + (int64_t)b * n + e);
     int i = 0;
     for (; i + 8 <= cnt; i += 8) {
         double vr[8], vi[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) { vr[u] = v[2 * (int64_t)(i + u) * ldv]; vi[u] = v[2 * (int64_t)(i + u) * ldv + 1]; }
+        for (int k = 0; k < 8; ++k) { vr[k] = v[2 * (int64_t)(i + k) * ldv]; vi[k] = v[2 * (int64_t)(i + k) * ldv + 1]; }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const double hr = hs[2 * (i + u)], hi = hs[2 * (i + u) + 1];
-            re += vr[u] * hr - vi[u] * hi;
-            im += vr[u] * hi + vi[u] * hr;
+        for (int k = 0; k < 8; ++k) {
+            const double* q = cs + 4 * (i + k);
+            ar += vr[k] * q[0] - vi[k] * q[1];
+            ai += vr[k] * q[1] + vi[k] * q[0];
+            br += vr[k] * q[2] - vi[k] * q[3];
+            bi += vr[k] * q[3] + vi[k] * q[2];
         }
     }
     for (; i < cnt; ++i) {
         const double vr = v[2 * (int64_t)i * ldv], vi = v[2 * (int64_t)i * ldv + 1];
-        const double hr = hs[2 * i], hi = hs[2 * i + 1];
-        re += vr * hr - vi * hi;
-        im += vr * hi + vi * hr;
+        const double* q = cs + 4 * i;
+        ar += vr * q[0] - vi * q[1];
+        ai += vr * q[1] + vi * q[0];
+        br += vr * q[2] - vi * q[3];
+        bi += vr * q[3] + vi * q[2];
     }
-    const int64_t slot = ((int64_t)b * nch + c) * n + e;
-    part[2 * slot] = re;
-    part[2 * slot + 1] = im;
+    double* o = part + (((int64_t)b * nch + c) * n + e) * 4;
+    o[0] = ar; o[1] = ai; o[2] = br; o[3] = bi;
 }
 
-__global__ __launch_bounds__(256) void k_update_apply(const double* __restrict__ part, int nchunk, double* __restrict__ W,
-                                                      int64_t n, const int* __restrict__ flag) {
+// q_j = (u - Q s)/nu into slot U, u' = (t - Q z - q_j c)/nu into slot Tt (in place over t)
+__global__ __launch_bounds__(256) void k_update2_apply(const double* __restrict__ part, int nch, double* __restrict__ U,
+                                                       double* __restrict__ Tt, int64_t n, const double* __restrict__ scal) {
     const int b = blockIdx.y;
-    if (flag && flag[b] == 0) return;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
-    double re = 0, im = 0;
-    for (int c = 0; c < nchunk; ++c) {
-        const int64_t slot = ((int64_t)b * nchunk + c) * n + e;
-        re += part[2 * slot];
-        im += part[2 * slot + 1];
+    double ar = 0, ai = 0, br = 0, bi = 0;
+    for (int c = 0; c < nch; ++c) {
+        const double* p = part + (((int64_t)b * nch + c) * n + e) * 4;
+        ar += p[0]; ai += p[1]; br += p[2]; bi += p[3];
     }
-    double* w = W + 2 * (int64_t)b * n;
-    w[2 * e] -= re;
-    w[2 * e + 1] -= im;
+    const double nu = scal[4 * b], cr = scal[4 * b + 1], ci = scal[4 * b + 2];
+    const double inv = nu > 0 ? 1.0 / nu : 0.0;
+    double* u = U + 2 * ((int64_t)b * n + e);
+    double* t = Tt + 2 * ((int64_t)b * n + e);
+    const double qr = (u[0] - ar) * inv, qi = (u[1] - ai) * inv;
+    u[0] = qr;
+    u[1] = qi;
+    const double tr = t[0] - br - (qr * cr - qi * ci), ti = t[1] - bi - (qr * ci + qi * cr);
+    t[0] = tr * inv;
+    t[1] = ti * inv;
 }
 
 // x_b += V_b coef_b over the first cnt[b] vectors (column b of each slab)
@@ -379,21 +504,6 @@ __global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, in
     const double xr = x[2 * e], xi = x[2 * e + 1];
     y[2 * e] = b * y[2 * e] + ar * xr - ai * xi;
     y[2 * e + 1] = b * y[2 * e + 1] + ar * xi + ai * xr;
-}
-
-// y_b = x_b / ||x_b|| (norm from the partial sums; 0 stays 0); hsub + b*hstride receives the norm.
-__global__ void k_scale_dev(double* __restrict__ Y, const double* __restrict__ X, int64_t ld, int64_t n,
-                            const double* __restrict__ part, int nblk, double* __restrict__ hsub, int64_t hstride) {
-    const int b = blockIdx.y;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double s = 0;
-    for (int k = 0; k < nblk; ++k) s += part[(int64_t)b * nblk + k];
-    const double nrm = sqrt(s);
-    if (e == 0 && hsub) { hsub[2 * (int64_t)b * hstride] = nrm; hsub[2 * (int64_t)b * hstride + 1] = 0.0; }
-    if (e >= n) return;
-    const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
-    Y[2 * ((int64_t)b * ld + e)] = X[2 * ((int64_t)b * ld + e)] * inv;
-    Y[2 * ((int64_t)b * ld + e) + 1] = X[2 * ((int64_t)b * ld + e) + 1] * inv;
 }
 
 // ---------------------------------------------------------------------------
@@ -567,7 +677,7 @@ void launch_matvec_dense_f32(const DomDesc* doms, const int4* mtiles, int64_t nm
 void launch_matvec_finish(const DomDesc* doms, int /*ndom*/, const int32_t* dof_dom, int64_t ndof, const int32_t* dplus,
                           const int32_t* dminus, const double* gval, const int64_t* gcol, const double* part,
                           const double* x, double* y, hipStream_t s) {
-    hipLaunchKernelGGL(k_mv_finish, dim3(gridn(ndof, 256)), dim3(256), 0, s, doms, dof_dom, ndof, dplus, dminus, gval,
+    hipLaunchKernelGGL(k_mv_finish, dim3(gridn(ndof, 64)), dim3(256), 0, s, doms, dof_dom, ndof, dplus, dminus, gval,
                        gcol, part, x, y);
 }
 
@@ -580,7 +690,7 @@ void launch_precond_apply(const DomDesc* doms, const int4* mtiles, int64_t nmt, 
 void launch_precond_finish(const DomDesc* doms, int /*ndom*/, const int32_t* dof_dom, int64_t ndof, const double* part,
                            double* z, hipStream_t s, const int32_t* list) {
     if (ndof <= 0) return;
-    hipLaunchKernelGGL(k_pc_finish, dim3(gridn(ndof, 256)), dim3(256), 0, s, doms, dof_dom, ndof, part, z, list);
+    hipLaunchKernelGGL(k_pc_finish, dim3(gridn(ndof, 64)), dim3(256), 0, s, doms, dof_dom, ndof, part, z, list);
 }
 
 void launch_gs_residual(const DomDesc* doms, const int32_t* dof_dom, const int32_t* list, int64_t nlist,
@@ -591,28 +701,37 @@ void launch_gs_residual(const DomDesc* doms, const int32_t* dof_dom, const int32
                        gval, gcol, v, z, w);
 }
 
-void launch_multidot(const double* V, int64_t ldv, int nv, int nvmax, const double* w, int64_t n, double* hpart,
-                     int nblk, int self, const int* flag, int nb, hipStream_t s) {
-    hipLaunchKernelGGL(k_multidot, dim3((unsigned)nblk, (unsigned)(nv + (self ? 1 : 0)), (unsigned)nb), dim3(256), 0, s,
-                       V, ldv, nv, nvmax, w, n, hpart, nblk, flag);
+void launch_dot2(const double* V, int64_t ldv, int nv, int nvmax, const double* u, const double* t, int64_t n,
+                 double* hpart, int nblk, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot2, dim3((unsigned)nblk, (unsigned)(nv + 1), (unsigned)nb), dim3(256), 0, s, V, ldv, nv, nvmax,
+                       u, t, n, hpart, nblk);
 }
 
-void launch_reduce_h(const double* hpart, int nv, int nvmax, int nblk, double* h, double* Hcol, int64_t hstride,
-                     double* wn2, int second, const int* flag, int nb, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_h, dim3(gridn(nv + 1, 128), (unsigned)nb), dim3(128), 0, s, hpart, nv, nvmax, nblk, h,
-                       Hcol, hstride, wn2, second, flag);
+void launch_reduce2(const double* hpart, int nv, int nvmax, int nblk, double* S, double* Z, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce2, dim3(gridn(nv + 1, 128), (unsigned)nb), dim3(128), 0, s, hpart, nv, nvmax, nblk, S, Z);
 }
 
-void launch_reorth_flag(const double* wn2, const double* part, int nblk, int nb, int* flag, int* count, hipStream_t s) {
-    hipLaunchKernelGGL(k_reorth_flag, dim3(1), dim3(256), 0, s, wn2, part, nblk, nb, flag, count);
+void launch_hess_gemv(const double* H, int64_t ldh, int64_t hstride, const double* S, int nv, int nvmax, int nct,
+                      double* hg, int nb, hipStream_t s) {
+    if (nv < 1) return;
+    const int nrt = (nv + 1 + 63) / 64, nkc = (nv + 63) / 64;
+    hipLaunchKernelGGL(k_hess_gemv, dim3((unsigned)nrt, (unsigned)nkc, (unsigned)nb), dim3(256), 0, s, H, ldh, hstride, S,
+                       nv, nvmax, nct, hg);
 }
 
-void launch_update(const double* V, int64_t ldv, int nv, int nvmax, const double* h, double* w, int64_t n,
-                   double* part, const int* flag, int nb, hipStream_t s) {
-    const int nchunk = (nv + 63) / 64;
-    hipLaunchKernelGGL(k_update_part, dim3(gridn(n, 256), (unsigned)nchunk, (unsigned)nb), dim3(256), 0, s, V, ldv, nv,
-                       nvmax, h, part, n, flag);
-    hipLaunchKernelGGL(k_update_apply, dim3(gridn(n, 256), (unsigned)nb), dim3(256), 0, s, part, nchunk, w, n, flag);
+void launch_dcgs_col(double* H, int64_t ldh, int64_t hstride, const double* S, const double* Z, const double* hg, int nct,
+                     int nv, int nvmax, double* scal, int last, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(k_dcgs_col, dim3(gridn(nv + 1, 256), (unsigned)nb), dim3(256), 0, s, H, ldh, hstride, S, Z, hg, nct,
+                       nv, nvmax, scal, last);
+}
+
+void launch_update2(const double* V, int64_t ldv, int nv, int nvmax, const double* S, const double* Z, double* u,
+                    double* t, int64_t n, double* part, const double* scal, int nb, hipStream_t s) {
+    const int nch = (nv + 63) / 64;
+    if (nch > 0)
+        hipLaunchKernelGGL(k_update2_part, dim3(gridn(n, 256), (unsigned)nch, (unsigned)nb), dim3(256), 0, s, V, ldv, nv,
+                           nvmax, S, Z, part, n);
+    hipLaunchKernelGGL(k_update2_apply, dim3(gridn(n, 256), (unsigned)nb), dim3(256), 0, s, part, nch, u, t, n, scal);
 }
 
 void launch_combine(double* x, int64_t ldx, const double* V, int64_t ldv, const int* cnt, int nvmax, const double* coef,
@@ -626,12 +745,6 @@ void launch_norm2(const double* w, int64_t ldw, int64_t n, double* part, int nbl
 
 void launch_axpby(double* y, const double* x, int64_t n, double ar, double ai, double b, hipStream_t s) {
     hipLaunchKernelGGL(k_axpby, dim3(gridn(n, 256)), dim3(256), 0, s, y, x, n, ar, ai, b);
-}
-
-void launch_scale_dev(double* y, const double* x, int64_t ld, int64_t n, const double* part, int nblk, double* hsub,
-                      int64_t hstride, int nb, hipStream_t s) {
-    hipLaunchKernelGGL(k_scale_dev, dim3(gridn(n, 256), (unsigned)nb), dim3(256), 0, s, y, x, ld, n, part, nblk, hsub,
-                       hstride);
 }
 
 void launch_copy_block_f64_to_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
