@@ -166,10 +166,19 @@ int mtf_rhs_plane_waves(mtf_problem p, int32_t nrhs, const double* d, const doub
 int mtf_matvec(mtf_problem p, int32_t nrhs, const void* x_dev, void* y_dev, int64_t ld,
                int32_t precision);
 
+/* Measurement of the product above for one vector (x_dev, y_dev: complex128 [N] on the device,
+ * precision MTF_FP64 or MTF_FP32_MIXED): `reps` products are launched on the problem's stream
+ * with HIP events around each launch of the dense block kernel (every T_i, K_i entry streamed
+ * once) and around each whole product (dense kernel + the kernel that sums the column-chunk
+ * partials and applies the transmission blocks).  dense_s, total_s receive the mean seconds per
+ * launch.  Synchronises; reps must be in [1, 10000]. */
+int mtf_time_matvec(mtf_problem p, int32_t precision, int32_t reps, const void* x_dev, void* y_dev,
+                    double* dense_s, double* total_s);
+
 typedef struct {
     int32_t struct_size;      /* sizeof(mtf_solve_opts)                                     */
     int32_t precision;        /* operator used by the inner iteration: MTF_FP64 or MTF_FP32_MIXED */
-    int32_t preconditioner;   /* MTF_PREC_NONE or MTF_PREC_BLOCK_TINV                        */
+    int32_t preconditioner;   /* MTF_PREC_NONE, MTF_PREC_BLOCK_TINV or MTF_PREC_BLOCK_TINV_GS */
     int32_t max_iters;        /* Arnoldi steps per GMRES cycle, 0 = 2000                     */
     int32_t max_refinements;  /* outer FP64 refinement steps (MTF_FP32_MIXED), 0 = 10        */
     int32_t reserved;
@@ -182,7 +191,7 @@ typedef struct {
     int32_t iterations;       /* total Arnoldi steps                                   */
     int32_t refinements;      /* FP64 residual evaluations after the first             */
     int32_t converged;        /* 1 if rtol was met                                     */
-    int32_t reorthogonalizations; /* Arnoldi steps that needed a second Gram-Schmidt pass */
+    int32_t reorthogonalizations; /* Arnoldi steps with a second Gram-Schmidt pass (all kept steps) */
     double  rel_residual;     /* final ||b - M x|| / ||b|| with the FP64 operator       */
     double  t_precond_s;      /* time to build the preconditioner (first call only)    */
     double  t_solve_s;        /* wall time of the solve                                */

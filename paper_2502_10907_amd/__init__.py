@@ -80,6 +80,7 @@ _SIGS = {
     "mtf_copy_block": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, _dp]),
     "mtf_copy_transmission": (C.c_int, [_P, C.c_int32, C.c_int32, _dp]),
     "mtf_get_entries": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _ip, _ip, _dp]),
+    "mtf_time_matvec": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _dp, _dp]),
     "mtf_rhs_plane_waves": (C.c_int, [_P, C.c_int32, _dp, _dp, _dp, _P, C.c_int64]),
     "mtf_matvec": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.c_int32]),
     "mtf_solve": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
@@ -271,6 +272,16 @@ class Problem:
         if (nrhs, ld) != (nrhs2, ld2):
             raise ValueError("x and y shapes differ")
         _check(_lib.mtf_matvec(self._h, nrhs, px, py, ld, int(precision)))
+
+    def time_matvec(self, x, y, reps: int = 20, precision: int = FP64):
+        """(mean seconds per dense block-kernel launch, mean seconds per whole product), HIP events."""
+        px, nrhs, _ = _dev(x, self.N)
+        py, nrhs2, _ = _dev(y, self.N)
+        if nrhs != 1 or nrhs2 != 1:
+            raise ValueError("time_matvec takes one vector")
+        d, t = C.c_double(), C.c_double()
+        _check(_lib.mtf_time_matvec(self._h, int(precision), int(reps), px, py, C.byref(d), C.byref(t)))
+        return d.value, t.value
 
     def solve(self, b, x, rtol: float = 1e-6, precision: int = FP64, preconditioner: int = PREC_BLOCK_TINV,
               max_iters: int = 0, max_refinements: int = 0, inner_rtol: float = 0.0, x0=None) -> list[Stats]:

@@ -42,7 +42,8 @@ struct GemmOp {
 struct GmresWork {
     int64_t n = 0;
     int maxit = 0, nb = 0;
-    DevBuf<double> V, tmp, tmp2, tmp3, r, hpart, S, Z, hg, scal, H, npart, upart, y;
+    DevBuf<double> V, Zt, Rf, tmp, tmp2, tmp3, r, hpart, S, Z, hg, scal, H, npart, upart, y;
+    int zslots = 0;                  // Krylov slots held by Zt (0: no preconditioned basis)
     DevBuf<int> cnt;                 // Arnoldi steps kept per right-hand side
     double* host = nullptr;          // pinned: nb x kSync Hessenberg columns + norm parts
     ~GmresWork() {
@@ -507,16 +508,31 @@ void build_tinv(mtf_problem p) {
     p->t_precond = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
-void gmres_alloc(mtf_problem p, int maxit, int nb) {
+void gmres_alloc(mtf_problem p, int maxit, int nb, bool flex) {
     GmresWork& w = p->gw;
     const int64_t n = p->sk.N;
-    if (w.n == n && w.maxit >= maxit && w.nb >= nb) return;
+    if (w.n == n && w.maxit >= maxit && w.nb >= nb) {
+        if (flex && w.zslots < w.maxit) {
+            w.Zt.alloc(2 * n * (int64_t)w.nb * w.maxit);
+            w.Rf.alloc(2 * (int64_t)(w.maxit + 1) * w.maxit * w.nb);
+            w.zslots = w.maxit;
+        }
+        return;
+    }
     w.n = n;
     w.maxit = maxit;
     w.nb = nb;
     const int64_t ldh = maxit + 1;
     const int64_t nct = (maxit + 63) / 64;
     w.V.alloc(2 * n * (int64_t)nb * (maxit + 1));
+    w.zslots = 0;
+    w.Zt.reset();
+    w.Rf.reset();
+    if (flex) {
+        w.Zt.alloc(2 * n * (int64_t)nb * maxit);
+        w.Rf.alloc(2 * ldh * (int64_t)maxit * nb);
+        w.zslots = maxit;
+    }
     w.tmp.alloc(2 * n * nb);
     w.tmp2.alloc(2 * n * nb);
     w.tmp3.alloc(2 * n);
@@ -564,13 +580,15 @@ void apply_pc(mtf_problem p, int pc, int prec, int nb, const double* x, double* 
     }
 }
 
-void apply_inner(mtf_problem p, const double* src, double* dst, int nb, int prec, int pc) {
+// dst = M P src; the preconditioned slab P src goes to zout (or to scratch when zout is null)
+void apply_inner(mtf_problem p, const double* src, double* dst, int nb, int prec, int pc, double* zout) {
     GmresWork& w = p->gw;
     const int64_t n = w.n;
     const double* in = src;
     if (pc != MTF_PREC_NONE) {
-        apply_pc(p, pc, prec, nb, src, w.tmp.p);
-        in = w.tmp.p;
+        double* z = zout ? zout : w.tmp.p;
+        apply_pc(p, pc, prec, nb, src, z);
+        in = z;
     }
     if (prec == MTF_BF16_SPLIT) apply_gemm(p, 0, nb, in, n, dst);
     else
@@ -583,6 +601,10 @@ void apply_inner(mtf_problem p, const double* src, double* dst, int nb, int prec
 // gives the coefficients and a second pass forms q_j and u_{j+1}; Hessenberg column j-1 becomes
 // final at step j.  The Hessenberg matrix stays on the device; the host reads the final columns
 // every kSync steps and applies the Givens rotations.  Each right-hand side stops at its own step.
+// With a preconditioner the iteration is flexible: the preconditioned candidates zt_j = P u_j are
+// kept, and since U = Q R (R upper triangular from the reorthogonalisation coefficients) the
+// correction is Zt R^-1 y, so M times the correction matches the Arnoldi relation exactly even
+// though P is applied in FP32.
 // Returns the number of Arnoldi steps taken; it[b], est[b] (recurrence residual / ||r_b||) per column.
 int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, int prec, int pc,
                 const std::vector<double>& tol, int maxit, std::vector<int>& itv, std::vector<double>& est,
@@ -595,32 +617,38 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
     const int64_t ldv = n * nb;
     const int nvmax = w.maxit;
     const int nct = (w.maxit + 63) / 64;
+    const bool flex = pc != MTF_PREC_NONE;
+    if (flex && w.zslots < maxit) throw StateError("flexible GMRES basis not allocated");
     double* V = w.V.p;
     auto Vs = [&](int j) { return V + 2 * ldv * (int64_t)j; };
+    auto Zs = [&](int j) { return w.Zt.p + 2 * ldv * (int64_t)j; };
     auto Hc = [&](int j) { return w.H.p + 2 * ldh * (int64_t)j; };
     std::vector<double> beta = norms_dev(p, R, n, nb);
     HIPCHK(hipMemcpyAsync(Vs(0), R, (size_t)2 * n * nb * sizeof(double), hipMemcpyDeviceToDevice, s));   // u_0 = r
-    std::vector<std::vector<cd>> H(nb, std::vector<cd>((size_t)ldh * maxit, cd(0)));
-    std::vector<std::vector<double>> cs(nb, std::vector<double>(maxit, 0.0));
-    std::vector<std::vector<cd>> sn(nb, std::vector<cd>(maxit, cd(0))), gv(nb, std::vector<cd>(maxit + 1, cd(0)));
+    // host copies of the final Hessenberg columns after the rotations (column jj has jj+1 entries)
+    std::vector<std::vector<std::vector<cd>>> H(nb);
+    std::vector<std::vector<double>> cs(nb);
+    std::vector<std::vector<cd>> sn(nb), gv(nb);
     std::vector<char> stop(nb, 0);
     std::vector<double> resid(beta);
     itv.assign(nb, 0);
     int live = 0;
     for (int b = 0; b < nb; ++b) {
-        gv[b][0] = beta[b];
+        gv[b].push_back(beta[b]);
         if (beta[b] == 0.0) stop[b] = 1; else ++live;
     }
     int done_cols = 0, steps = 0;
+    std::vector<cd> col;
     for (int j = 0; j <= maxit && live > 0; ++j) {
         const bool last = j == maxit;      // only finalises column maxit-1
         double* u = Vs(j);
         double* t = last ? u : Vs(j + 1);
-        if (!last) apply_inner(p, u, t, nb, prec, pc);
+        if (!last) apply_inner(p, u, t, nb, prec, pc, flex ? Zs(j) : nullptr);
         launch_dot2(V, ldv, j, nvmax, u, t, n, w.hpart.p, kNblk, nb, s);
         launch_reduce2(w.hpart.p, j, nvmax, kNblk, w.S.p, w.Z.p, nb, s);
         if (!last) launch_hess_gemv(w.H.p, ldh, hstride, w.S.p, j, nvmax, nct, w.hg.p, nb, s);
-        launch_dcgs_col(w.H.p, ldh, hstride, w.S.p, w.Z.p, w.hg.p, nct, j, nvmax, w.scal.p, last ? 1 : 0, nb, s);
+        launch_dcgs_col(w.H.p, ldh, hstride, w.S.p, w.Z.p, w.hg.p, nct, j, nvmax, w.scal.p, last ? 1 : 0,
+                        flex && !last ? w.Rf.p : nullptr, hstride, nb, s);
         if (!last) launch_update2(V, ldv, j, nvmax, w.S.p, w.Z.p, u, t, n, w.upart.p, w.scal.p, nb, s);
         steps = j;
         if ((j % kSync != 0 || j == 0) && !last) continue;
@@ -635,7 +663,7 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
             const double* hb = w.host + (size_t)2 * ldh * nc * b;
             for (int q = 0; q < nc && !stop[b]; ++q) {
                 const int jj = c0 + q;
-                cd* col = &H[b][(size_t)jj * ldh];
+                col.assign(jj + 2, cd(0));
                 for (int i = 0; i <= jj + 1; ++i) col[i] = cd(hb[2 * (ldh * q + i)], hb[2 * (ldh * q + i) + 1]);
                 const double hn = col[jj + 1].real();
                 for (int i = 0; i < jj; ++i) {
@@ -645,12 +673,17 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
                 }
                 const cd a = col[jj];
                 const double den = std::sqrt(std::norm(a) + hn * hn);
-                if (std::abs(a) == 0.0) { cs[b][jj] = 0.0; sn[b][jj] = 1.0; }
-                else { cs[b][jj] = std::abs(a) / den; sn[b][jj] = (a / std::abs(a)) * hn / den; }
-                col[jj] = cs[b][jj] * a + sn[b][jj] * hn;
-                col[jj + 1] = 0.0;
-                gv[b][jj + 1] = -std::conj(sn[b][jj]) * gv[b][jj];
-                gv[b][jj] = cs[b][jj] * gv[b][jj];
+                double c;
+                cd sj;
+                if (std::abs(a) == 0.0) { c = 0.0; sj = 1.0; }
+                else { c = std::abs(a) / den; sj = (a / std::abs(a)) * hn / den; }
+                cs[b].push_back(c);
+                sn[b].push_back(sj);
+                col[jj] = c * a + sj * hn;
+                col.resize(jj + 1);
+                H[b].push_back(col);
+                gv[b].push_back(-std::conj(sj) * gv[b][jj]);
+                gv[b][jj] = c * gv[b][jj];
                 itv[b] = jj + 1;
                 resid[b] = std::abs(gv[b][jj + 1]);
                 if (!std::isfinite(resid[b])) throw NonFiniteError("GMRES produced a non-finite residual");
@@ -659,15 +692,29 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
         }
         done_cols = j;
     }
-    // back substitution per right-hand side, then X_b += P (V_b y_b)
+    // back substitution per right-hand side; flexible: coefficients R^-1 y on the zt basis
     std::vector<double> yh((size_t)2 * nb * (nvmax + 1), 0.0);
+    std::vector<cd> Rh;
     for (int b = 0; b < nb; ++b) {
         const int it = itv[b];
         std::vector<cd> yv(it);
         for (int i = it - 1; i >= 0; --i) {
             cd acc = gv[b][i];
-            for (int k = i + 1; k < it; ++k) acc -= H[b][(size_t)k * ldh + i] * yv[k];
-            yv[i] = acc / H[b][(size_t)i * ldh + i];
+            for (int k = i + 1; k < it; ++k) acc -= H[b][k][i] * yv[k];
+            yv[i] = acc / H[b][i][i];
+        }
+        if (flex && it > 0) {
+            Rh.assign((size_t)it * it, cd(0));
+            HIPCHK(hipMemcpy2DAsync(Rh.data(), (size_t)it * sizeof(cd), w.Rf.p + 2 * (int64_t)b * hstride,
+                                    (size_t)ldh * sizeof(cd), (size_t)it * sizeof(cd), it, hipMemcpyDeviceToHost, s));
+            sync(p);
+            for (int i = it - 1; i >= 0; --i) {
+                cd acc = yv[i];
+                for (int k = i + 1; k < it; ++k) acc -= Rh[(size_t)k * it + i] * yv[k];
+                const cd d = Rh[(size_t)i * it + i];
+                if (d == cd(0)) throw NonFiniteError("GMRES: zero pivot in the reorthogonalisation factor");
+                yv[i] = acc / d;
+            }
         }
         for (int i = 0; i < it; ++i) {
             yh[(size_t)2 * b * (nvmax + 1) + 2 * i] = yv[i].real();
@@ -676,14 +723,7 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
     }
     HIPCHK(hipMemcpyAsync(w.y.p, yh.data(), yh.size() * sizeof(double), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(w.cnt.p, itv.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
-    launch_fill(w.tmp2.p, 2 * n * nb, 0.0, s);
-    launch_combine(w.tmp2.p, n, V, ldv, w.cnt.p, nvmax, w.y.p, n, nb, s);
-    const double* corr = w.tmp2.p;
-    if (pc != MTF_PREC_NONE) {
-        apply_pc(p, pc, prec, nb, w.tmp2.p, w.tmp.p);
-        corr = w.tmp.p;
-    }
-    for (int b = 0; b < nb; ++b) launch_axpby(X + 2 * ldx * (int64_t)b, corr + 2 * n * b, n, 1.0, 0.0, 1.0, s);
+    launch_combine(X, ldx, flex ? w.Zt.p : V, ldv, w.cnt.p, nvmax, w.y.p, n, nb, s);   // X_b += basis_b coef_b
     sync(p);
     est.assign(nb, 0.0);
     for (int b = 0; b < nb; ++b) {
@@ -722,7 +762,7 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
     if (use_pc && !p->have_tinv) { build_tinv(p); t_pc = p->t_precond; }
     // right-hand sides advance in lockstep batches when the products are GEMMs
     const int nbmax = prec == MTF_BF16_SPLIT ? std::min<int>(nrhs, kMaxBatch) : 1;
-    gmres_alloc(p, maxit, nbmax);
+    gmres_alloc(p, maxit, nbmax, use_pc);
     GmresWork& w = p->gw;
     hipStream_t s = p->stream;
     const int64_t n = p->sk.N;
@@ -1047,6 +1087,52 @@ int mtf_matvec(mtf_problem p, int32_t nrhs, const void* x_dev, void* y_dev, int6
                         static_cast<double*>(y_dev) + 2 * ld * (int64_t)r, precision);
         }
         HIPCHK(hipGetLastError());
+        return MTF_OK;
+    });
+}
+
+int mtf_time_matvec(mtf_problem p, int32_t precision, int32_t reps, const void* x_dev, void* y_dev, double* dense_s,
+                    double* total_s) {
+    return guarded([&] {
+        if (!p || !x_dev || !y_dev || !dense_s || !total_s) throw ArgError("bad arguments");
+        if (!p->has_mesh || !p->has_mat) throw StateError("mtf_time_matvec before mesh/materials");
+        if (reps < 1 || reps > 10000) throw ArgError("reps must be in [1, 10000]");
+        if (x_dev == y_dev) throw ArgError("x and y must not alias");
+        if (precision != MTF_FP64 && precision != MTF_FP32_MIXED) throw ArgError("precision must be MTF_FP64 or MTF_FP32_MIXED");
+        check_prec_available(p, precision);
+        DeviceGuard g(p->device);
+        hipStream_t s = p->stream;
+        const double* x = static_cast<const double*>(x_dev);
+        double* y = static_cast<double*>(y_dev);
+        std::vector<hipEvent_t> ev(3 * (size_t)reps, nullptr);
+        struct Cleanup {
+            std::vector<hipEvent_t>& e;
+            ~Cleanup() { for (auto v : e) if (v) (void)hipEventDestroy(v); }
+        } cleanup{ev};
+        for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+        for (int r = 0; r < reps; ++r) {
+            HIPCHK(hipEventRecord(ev[3 * r], s));
+            if (precision == MTF_FP64)
+                launch_matvec_dense_f64(p->d_doms.p, p->d_mtiles.p, p->nmtiles, p->T64.p, p->K64.p, x, p->part.p, s);
+            else
+                launch_matvec_dense_f32(p->d_doms.p, p->d_mtiles.p, p->nmtiles, p->T32.p, p->K32.p, x, p->part.p, s);
+            HIPCHK(hipEventRecord(ev[3 * r + 1], s));
+            launch_matvec_finish(p->d_doms.p, (int)p->doms.size(), p->d_dof_dom.p, p->ndof, p->d_dplus.p, p->d_dminus.p,
+                                 p->d_gval.p, p->d_gcol.p, p->part.p, x, y, s);
+            HIPCHK(hipEventRecord(ev[3 * r + 2], s));
+        }
+        HIPCHK(hipGetLastError());
+        sync(p);
+        double td = 0, tt = 0;
+        for (int r = 0; r < reps; ++r) {
+            float a = 0, b = 0;
+            HIPCHK(hipEventElapsedTime(&a, ev[3 * r], ev[3 * r + 1]));
+            HIPCHK(hipEventElapsedTime(&b, ev[3 * r], ev[3 * r + 2]));
+            td += a;
+            tt += b;
+        }
+        *dense_s = td * 1e-3 / reps;
+        *total_s = tt * 1e-3 / reps;
         return MTF_OK;
     });
 }

@@ -116,7 +116,7 @@ void launch_reduce2(const double* hpart, int nv, int nvmax, int nblk, double* S,
 void launch_hess_gemv(const double* H, int64_t ldh, int64_t hstride, const double* S, int nv, int nvmax, int nct,
                       double* hg, int nb, hipStream_t s);                   // partial Hbar s
 void launch_dcgs_col(double* H, int64_t ldh, int64_t hstride, const double* S, const double* Z, const double* hg, int nct,
-                     int nv, int nvmax, double* scal, int last, int nb, hipStream_t s);
+                     int nv, int nvmax, double* scal, int last, double* R, int64_t rstride, int nb, hipStream_t s);
 void launch_update2(const double* V, int64_t ldv, int nv, int nvmax, const double* S, const double* Z, double* u,
                     double* t, int64_t n, double* part, const double* scal, int nb, hipStream_t s);
 void launch_combine(double* x, int64_t ldx, const double* V, int64_t ldv, const int* cnt, int nvmax, const double* coef,

@@ -326,10 +326,13 @@ __global__ __launch_bounds__(256) void k_hess_gemv(const double* __restrict__ H,
 }
 
 // nu, c; finalise Hessenberg column nv-1; first-pass column nv (skipped when `last`).
+// When R is given, column nv of the triangular factor U = Q R of the candidates is stored too:
+// R[i, nv] = s_i (i < nv), R[nv, nv] = nu (per right-hand side at R + b*rstride, ld ldh).
 __global__ __launch_bounds__(256) void k_dcgs_col(double* __restrict__ H, int64_t ldh, int64_t hstride,
                                                   const double* __restrict__ S, const double* __restrict__ Z,
                                                   const double* __restrict__ hg, int nct, int nv, int nvmax,
-                                                  double* __restrict__ scal, int last) {
+                                                  double* __restrict__ scal, int last, double* __restrict__ R,
+                                                  int64_t rstride) {
     const int b = blockIdx.y;
     const double* sb = S + 2 * (int64_t)b * (nvmax + 1);
     const double* zb = Z + 2 * (int64_t)b * (nvmax + 1);
@@ -355,6 +358,11 @@ __global__ __launch_bounds__(256) void k_dcgs_col(double* __restrict__ H, int64_
     if (blockIdx.x == 0 && threadIdx.x == 0) { scal[4 * b] = nu; scal[4 * b + 1] = cr; scal[4 * b + 2] = ci; }
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i > nv) return;
+    if (R) {
+        double* Rc = R + 2 * ((int64_t)b * rstride + (int64_t)nv * ldh);
+        Rc[2 * i] = i < nv ? sb[2 * i] : nu;
+        Rc[2 * i + 1] = i < nv ? sb[2 * i + 1] : 0.0;
+    }
     double* Hb = H + 2 * (int64_t)b * hstride;
     if (nv >= 1) {
         double* Hc = Hb + 2 * (int64_t)(nv - 1) * ldh;
@@ -720,9 +728,9 @@ void launch_hess_gemv(const double* H, int64_t ldh, int64_t hstride, const doubl
 }
 
 void launch_dcgs_col(double* H, int64_t ldh, int64_t hstride, const double* S, const double* Z, const double* hg, int nct,
-                     int nv, int nvmax, double* scal, int last, int nb, hipStream_t s) {
+                     int nv, int nvmax, double* scal, int last, double* R, int64_t rstride, int nb, hipStream_t s) {
     hipLaunchKernelGGL(k_dcgs_col, dim3(gridn(nv + 1, 256), (unsigned)nb), dim3(256), 0, s, H, ldh, hstride, S, Z, hg, nct,
-                       nv, nvmax, scal, last);
+                       nv, nvmax, scal, last, R, rstride);
 }
 
 void launch_update2(const double* V, int64_t ldv, int nv, int nvmax, const double* S, const double* Z, double* u,
