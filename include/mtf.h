@@ -197,9 +197,11 @@ typedef struct {
     double  t_solve_s;        /* wall time of the solve                                */
 } mtf_solve_stats;
 
-/* Solve M x = b by GMRES (full; FP64 Arnoldi by classical Gram-Schmidt with a
- * second pass when the first loses more than half the norm) for each of nrhs right-hand sides (b_dev, x_dev: complex128
- * [nrhs][ld]).  With MTF_PREC_BLOCK_TINV the iteration runs on M P, with P the
+/* Solve M x = b by GMRES (full; FP64 Arnoldi by classical Gram-Schmidt with
+ * delayed reorthogonalisation, two passes over the basis per step) for each of nrhs
+ * right-hand sides (b_dev, x_dev: complex128 [nrhs][ld]).  A cycle ends when the
+ * recurrence residual meets rtol; the FP64 residual is then recomputed and a new
+ * cycle starts if it does not.  With MTF_PREC_BLOCK_TINV the iteration runs on M P, with P the
  * block-diagonal right preconditioner
  *     P_i = 1/2 [[0, -T_i^-1 / rho_i], [rho_i T_i^-1, 0]]
  * (the inverse of the off-diagonal part of 2 A_i; the block shape of the
@@ -209,13 +211,22 @@ typedef struct {
  * first, then the colour classes of the subdomain adjacency graph (subdomains
  * of one class share no interface and are done together), each block solving
  * with P_i after subtracting the transmission terms of the blocks already done.  Right
- * preconditioning leaves the judged residual ||b - M x|| unchanged.
+ * preconditioning leaves the judged residual ||b - M x|| unchanged.  With either
+ * preconditioner the iteration is flexible (the preconditioned vectors are kept),
+ * so the FP32 application of P does not limit the attainable FP64 residual.
  * MTF_FP32_MIXED runs the inner GMRES on the complex64 operator and corrects
  * with FP64 residuals (iterative refinement) until rtol holds for the FP64
  * operator, which must have been assembled too.  stats[nrhs] may be NULL.
  * Returns MTF_NOT_CONVERGED if some right-hand side missed rtol. */
 int mtf_solve(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int64_t ld,
               const mtf_solve_opts* opts, mtf_solve_stats* stats);
+
+/* z = P x for nrhs complex128 vectors (x_dev, z_dev: [nrhs][ld], ld >= N, no aliasing) with
+ * the right preconditioner `preconditioner` (MTF_PREC_BLOCK_TINV or MTF_PREC_BLOCK_TINV_GS, as
+ * defined for mtf_solve).  Builds T_i^-1 on first use (from the FP32 blocks if assembled, else
+ * from the FP64 ones).  Stream-ordered. */
+int mtf_apply_preconditioner(mtf_problem p, int32_t preconditioner, int32_t nrhs, const void* x_dev,
+                             void* z_dev, int64_t ld);
 
 /* Far field E_inf(xhat) (E_sc ~ exp(i k0 |x|)/|x| E_inf) of nrhs solutions
  * x_dev [nrhs][ld] in ndir unit directions dir[ndir][3] (host), written to host

@@ -81,6 +81,7 @@ _SIGS = {
     "mtf_copy_transmission": (C.c_int, [_P, C.c_int32, C.c_int32, _dp]),
     "mtf_get_entries": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _ip, _ip, _dp]),
     "mtf_time_matvec": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _dp, _dp]),
+    "mtf_apply_preconditioner": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, C.c_int64]),
     "mtf_rhs_plane_waves": (C.c_int, [_P, C.c_int32, _dp, _dp, _dp, _P, C.c_int64]),
     "mtf_matvec": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.c_int32]),
     "mtf_solve": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
@@ -272,6 +273,13 @@ class Problem:
         if (nrhs, ld) != (nrhs2, ld2):
             raise ValueError("x and y shapes differ")
         _check(_lib.mtf_matvec(self._h, nrhs, px, py, ld, int(precision)))
+
+    def apply_preconditioner(self, x, z, preconditioner: int = PREC_BLOCK_TINV):
+        px, nrhs, ld = _dev(x, self.N)
+        pz, nrhs2, ld2 = _dev(z, self.N)
+        if (nrhs, ld) != (nrhs2, ld2):
+            raise ValueError("x and z shapes differ")
+        _check(_lib.mtf_apply_preconditioner(self._h, int(preconditioner), nrhs, px, pz, ld))
 
     def time_matvec(self, x, y, reps: int = 20, precision: int = FP64):
         """(mean seconds per dense block-kernel launch, mean seconds per whole product), HIP events."""

@@ -447,35 +447,42 @@ void precond1_gs(mtf_problem p, const double* x, double* z, double* w) {
     }
 }
 
-// X = inv(A) by recursive 2 x 2 Schur-complement splitting; A (complex64, ld lda) is overwritten.
-void inv_rec(float* A, int64_t lda, float* X, int64_t ldx, int n, float* work, int* info, hipStream_t s) {
-    if (n <= 64) {
-        HIPCHK(hipMemcpy2DAsync(X, ldx * 8, A, lda * 8, (size_t)n * 8, n, hipMemcpyDeviceToDevice, s));
-        launch_cinv_small_f32(X, ldx, n, info, s);
-        return;
+// In-place inverse of `batch` n x n complex64 matrices X + z*stride (ld n) by blocked Gauss-Jordan
+// elimination over 64-wide diagonal blocks P (pivoting within each diagonal block):
+//   X_PP <- X_PP^-1;  X_Pj <- X_PP X_Pj;  X_ij <- X_ij - X_iP X_Pj;  X_iP <- -X_iP X_PP   (i, j not in P)
+// The rank-64 update is one batched matrix-core GEMM over the whole matrix minus the band P.
+void block_gj_inverse(float* X, int n, int64_t stride, int batch, int* info, hipStream_t s) {
+    const int64_t ld = n;
+    for (int p0 = 0; p0 < n; p0 += 64) {
+        const int w = std::min(64, n - p0);
+        float* Xpp = X + 2 * (p0 + (int64_t)p0 * ld);
+        float* Xrow = X + 2 * (int64_t)p0;            // row p0, column 0
+        float* Xcol = X + 2 * ((int64_t)p0 * ld);     // row 0, column p0
+        launch_cinv_small_f32(Xpp, ld, stride, w, batch, info, s);
+        if (w == n) break;
+        CGemm r;                                      // row panel, in place
+        r.m = w; r.n = n - w; r.k = w; r.batch = batch;
+        r.A = Xpp; r.lda = ld; r.sA = stride;
+        r.B = Xrow; r.ldb = ld; r.sB = stride;
+        r.D = Xrow; r.ldd = ld; r.sD = stride;
+        r.cg0 = p0; r.cgw = w;
+        launch_cgemm_f32(r, s);
+        CGemm t;                                      // rank-w update outside the band
+        t.m = n - w; t.n = n - w; t.k = w; t.batch = batch; t.ar = -1.f; t.beta = 1.f;
+        t.A = Xcol; t.lda = ld; t.sA = stride;
+        t.B = Xrow; t.ldb = ld; t.sB = stride;
+        t.C = X; t.ldc = ld; t.sC = stride;
+        t.D = X; t.ldd = ld; t.sD = stride;
+        t.rg0 = p0; t.rgw = w; t.cg0 = p0; t.cgw = w;
+        launch_cgemm_f32(t, s);
+        CGemm c;                                      // column panel, in place
+        c.m = n - w; c.n = w; c.k = w; c.batch = batch; c.ar = -1.f;
+        c.A = Xcol; c.lda = ld; c.sA = stride;
+        c.B = Xpp; c.ldb = ld; c.sB = stride;
+        c.D = Xcol; c.ldd = ld; c.sD = stride;
+        c.rg0 = p0; c.rgw = w;
+        launch_cgemm_f32(c, s);
     }
-    int n1 = ((n / 2 + 63) / 64) * 64;
-    if (n1 >= n) n1 = n - 64;
-    const int n2 = n - n1;
-    float* A11 = A;
-    float* A21 = A + 2 * (int64_t)n1;
-    float* A12 = A + 2 * (int64_t)n1 * lda;
-    float* A22 = A + 2 * ((int64_t)n1 + (int64_t)n1 * lda);
-    float* X11 = X;
-    float* X21 = X + 2 * (int64_t)n1;
-    float* X12 = X + 2 * (int64_t)n1 * ldx;
-    float* X22 = X + 2 * ((int64_t)n1 + (int64_t)n1 * ldx);
-    float* W = work;                          // n1 x n2
-    float* V = W + 2 * (int64_t)n1 * n2;      // n2 x n1
-    float* next = V + 2 * (int64_t)n2 * n1;
-    inv_rec(A11, lda, X11, ldx, n1, next, info, s);
-    launch_cgemm_f32(n1, n2, n1, 1.f, 0.f, X11, ldx, A12, lda, 0.f, nullptr, 0, W, n1, s);
-    launch_cgemm_f32(n2, n2, n1, -1.f, 0.f, A21, lda, W, n1, 1.f, A22, lda, A22, lda, s);
-    inv_rec(A22, lda, X22, ldx, n2, next, info, s);
-    launch_cgemm_f32(n1, n2, n2, -1.f, 0.f, W, n1, X22, ldx, 0.f, nullptr, 0, X12, ldx, s);
-    launch_cgemm_f32(n2, n1, n1, 1.f, 0.f, A21, lda, X11, ldx, 0.f, nullptr, 0, V, n2, s);
-    launch_cgemm_f32(n2, n1, n2, -1.f, 0.f, X22, ldx, V, n2, 0.f, nullptr, 0, X21, ldx, s);
-    launch_cgemm_f32(n1, n1, n2, -1.f, 0.f, X12, ldx, V, n2, 1.f, X11, ldx, X11, ldx, s);
 }
 
 void build_tinv(mtf_problem p) {
@@ -483,19 +490,21 @@ void build_tinv(mtf_problem p) {
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = p->stream;
     p->Tinv.alloc(2 * p->mat_entries);
-    int64_t emax = 0;
-    for (auto& d : p->doms) emax = std::max<int64_t>(emax, d.E);
-    DevBuf<float> A, work;
     DevBuf<int> info;
-    A.alloc(2 * emax * emax);
-    work.alloc(2 * emax * emax + 4096);
     info.alloc(2);
     HIPCHK(hipMemsetAsync(info.p, 0, 2 * sizeof(int), s));
-    for (auto& d : p->doms) {
-        const int64_t ne = 2 * (int64_t)d.E * d.E;
-        if (p->have32) HIPCHK(hipMemcpyAsync(A.p, p->T32.p + 2 * d.mat0, ne * sizeof(float), hipMemcpyDeviceToDevice, s));
-        else launch_copy_block_f64_to_f32(p->T64.p + 2 * d.mat0, A.p, ne, s);
-        inv_rec(A.p, d.E, p->Tinv.p + 2 * d.mat0, d.E, d.E, work.p, info.p, s);
+    if (p->have32)
+        HIPCHK(hipMemcpyAsync(p->Tinv.p, p->T32.p, 2 * p->mat_entries * sizeof(float), hipMemcpyDeviceToDevice, s));
+    else
+        launch_copy_block_f64_to_f32(p->T64.p, p->Tinv.p, 2 * p->mat_entries, s);
+    // consecutive subdomains of equal size are stored back to back and inverted as one batch
+    const auto& D = p->doms;
+    for (size_t a = 0; a < D.size();) {
+        size_t b = a + 1;
+        const int64_t E = D[a].E;
+        while (b < D.size() && D[b].E == E && D[b].mat0 == D[a].mat0 + (int64_t)(b - a) * E * E) ++b;
+        if (E > 0) block_gj_inverse(p->Tinv.p + 2 * D[a].mat0, (int)E, E * E, (int)(b - a), info.p, s);
+        a = b;
     }
     launch_nonfinite_check(p->Tinv.p, 2 * p->mat_entries, info.p + 1, s);
     HIPCHK(hipGetLastError());
@@ -1142,6 +1151,32 @@ int mtf_solve(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int64
     return guarded([&] {
         if (!p) throw ArgError("problem is NULL");
         return solve_impl(p, nrhs, b_dev, x_dev, ld, opts, stats);
+    });
+}
+
+int mtf_apply_preconditioner(mtf_problem p, int32_t preconditioner, int32_t nrhs, const void* x_dev, void* z_dev,
+                             int64_t ld) {
+    return guarded([&] {
+        if (!p) throw ArgError("problem is NULL");
+        if (!p->has_mesh || !p->has_mat) throw StateError("mtf_apply_preconditioner before mesh/materials");
+        if (nrhs < 1 || !x_dev || !z_dev || ld < p->sk.N) throw ArgError("bad arguments");
+        if (x_dev == z_dev) throw ArgError("x and z must not alias");
+        if (preconditioner != MTF_PREC_BLOCK_TINV && preconditioner != MTF_PREC_BLOCK_TINV_GS)
+            throw ArgError("preconditioner must be MTF_PREC_BLOCK_TINV or MTF_PREC_BLOCK_TINV_GS");
+        if (!p->have64 && !p->have32) throw StateError("mtf_apply_preconditioner before mtf_assemble");
+        DeviceGuard g(p->device);
+        if (!p->have_tinv) build_tinv(p);
+        DevBuf<double> w;
+        if (preconditioner == MTF_PREC_BLOCK_TINV_GS) w.alloc(2 * p->sk.N);
+        for (int r = 0; r < nrhs; ++r) {
+            const double* x = static_cast<const double*>(x_dev) + 2 * ld * (int64_t)r;
+            double* z = static_cast<double*>(z_dev) + 2 * ld * (int64_t)r;
+            if (preconditioner == MTF_PREC_BLOCK_TINV_GS) precond1_gs(p, x, z, w.p);
+            else precond1(p, x, z);
+        }
+        HIPCHK(hipGetLastError());
+        if (preconditioner == MTF_PREC_BLOCK_TINV_GS) sync(p);      // w is released on return
+        return MTF_OK;
     });
 }
 

@@ -131,11 +131,36 @@ void launch_far_field(const DomDesc* d0, const TriGeom* geom, const int32_t* tdo
 
 // Complex64 helpers for the preconditioner.
 void launch_copy_block_f64_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
-void launch_cgemm_f32(int m, int n, int k, float alpha_re, float alpha_im,
-                      const float* A, int64_t lda, const float* B, int64_t ldb,
-                      float beta_re, const float* C, int64_t ldc, float* D, int64_t ldd,
-                      hipStream_t s);          // D = alpha A B + beta C (beta real)
-int  launch_cinv_small_f32(float* A, int64_t lda, int n, int* info, hipStream_t s);   // n <= 64, in place
+// Batched complex64 GEMM on FP32 matrix cores, column-major: for z < batch,
+//   D_z = alpha A_z B_z + beta C_z   (X_z = X + z * sX complex entries; C may alias D).
+// Logical rows r of A, C, D map to physical rows r + (r >= rg0 ? rgw : 0) and logical columns c
+// of B, C, D to c + (c >= cg0 ? cgw : 0): a band of rows/columns can be skipped.
+struct CGemm {
+    int m = 0, n = 0, k = 0, batch = 1;
+    float ar = 1.f, ai = 0.f, beta = 0.f;
+    const float* A = nullptr;
+    int64_t lda = 0, sA = 0;
+    const float* B = nullptr;
+    int64_t ldb = 0, sB = 0;
+    const float* C = nullptr;
+    int64_t ldc = 0, sC = 0;
+    float* D = nullptr;
+    int64_t ldd = 0, sD = 0;
+    int rg0 = 0x7fffffff, rgw = 0, cg0 = 0x7fffffff, cgw = 0;
+};
+void launch_cgemm_f32(const CGemm& g, hipStream_t s);
+// single product D = alpha A B + beta C (beta real)
+inline void launch_cgemm_f32(int m, int n, int k, float alpha_re, float alpha_im, const float* A, int64_t lda,
+                             const float* B, int64_t ldb, float beta_re, const float* C, int64_t ldc, float* D,
+                             int64_t ldd, hipStream_t s) {
+    CGemm g;
+    g.m = m; g.n = n; g.k = k; g.ar = alpha_re; g.ai = alpha_im; g.beta = beta_re;
+    g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc; g.D = D; g.ldd = ldd;
+    launch_cgemm_f32(g, s);
+}
+// In-place inverse of the n x n (n <= 64) complex64 blocks A + z*stride (ld lda), z < batch;
+// info[0] is set to a nonzero value on a zero pivot.
+int  launch_cinv_small_f32(float* A, int64_t lda, int64_t stride, int n, int batch, int* info, hipStream_t s);
 void launch_precond_apply(const DomDesc* doms, const int4* mtiles, int64_t nmt, const float* Tinv,
                           const double* x, double* part, hipStream_t s);
 void launch_precond_finish(const DomDesc* doms, int ndom, const int32_t* dof_dom, int64_t ndof_total,

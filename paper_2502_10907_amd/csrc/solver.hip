@@ -514,148 +514,196 @@ __global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, in
     y[2 * e + 1] = b * y[2 * e + 1] + ar * xi + ai * xr;
 }
 
-// ---------------------------------------------------------------------------
-// complex64 GEMM: D = alpha A B + beta C (column-major; C may alias D)
-// 64 x 64 tile per workgroup, 4 x 4 complex outputs per thread, k-step 8.
-// ---------------------------------------------------------------------------
+// complex64 GEMM on FP32 matrix cores (v_mfma_f32_32x32x2f32), batched over blockIdx.z, with
+// optional skipped bands of rows and columns (see CGemm).  C may alias D: each output element is
+// read and written by the same lane.
+// Workgroup tile 128 x 64 complex, k-tile 16, four wavefronts in 2 x 2, each owning 64 x 32 as two
+// 32 x 32 MFMA tiles; per pair of k: re*re, im*(-im), re*im and im*re products, FP32 accumulation.
+// MFMA lane layout: A operand row l%32, k l/32; B operand k l/32, column l%32; result register i
+// holds row (i/4)*8 + (l/32)*4 + i%4, column l%32.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-__global__ __launch_bounds__(256) void k_cgemm(int m, int n, int k, float ar, float ai, const float* __restrict__ A,
-                                               int64_t lda, const float* __restrict__ B, int64_t ldb, float beta,
-                                               const float* C, int64_t ldc, float* D, int64_t ldd) {
-    __shared__ float2 As[8][64 + 1];
-    __shared__ float2 Bs[8][64 + 1];
-    const int tid = threadIdx.x;
-    const int tr = tid & 15, tc = tid >> 4;
-    const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
-    float acc[4][4][2];
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) acc[i][j][0] = acc[i][j][1] = 0.f;
-    const float2* A2 = reinterpret_cast<const float2*>(A);
-    const float2* B2 = reinterpret_cast<const float2*>(B);
-    for (int k0 = 0; k0 < k; k0 += 8) {
-        for (int e = tid; e < 512; e += 256) {
-            const int r = e & 63, kk = e >> 6;
-            const int gr = row0 + r, gk = k0 + kk;
-            As[kk][r] = (gr < m && gk < k) ? A2[gr + (int64_t)gk * lda] : make_float2(0.f, 0.f);
-            const int kb = e & 7, cc = e >> 3;
-            const int gkb = k0 + kb, gc = col0 + cc;
-            Bs[kb][cc] = (gkb < k && gc < n) ? B2[gkb + (int64_t)gc * ldb] : make_float2(0.f, 0.f);
+__global__ __launch_bounds__(256) void k_cgemm_mfma(const CGemm g) {
+    constexpr int TM = 128, TN = 64, BK = 16;
+    __shared__ float Ar[BK][TM], Ai[BK][TM];
+    __shared__ float Br[BK][TN + 1], Bi[BK][TN + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wm = wv & 1, wn = wv >> 1;
+    const int row0 = blockIdx.x * TM, col0 = blockIdx.y * TN;
+    const int64_t z = blockIdx.z;
+    const float2* A2 = reinterpret_cast<const float2*>(g.A) + z * g.sA;
+    const float2* B2 = reinterpret_cast<const float2*>(g.B) + z * g.sB;
+    const int m = g.m, n = g.n, k = g.k;
+    floatx16 cr0 = {}, cr1 = {}, ci0 = {}, ci1 = {};
+    const int ar_row = tid & 127, ar_k = (tid >> 7) * 8;     // A tile loader: one row, 8 k values
+    const int bk = tid & 15, bc = tid >> 4;                   // B tile loader: one k, columns bc + 16q
+    const int gr = row0 + ar_row;
+    const int64_t pr = gr + (gr >= g.rg0 ? g.rgw : 0);
+    int64_t pc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int gc = col0 + bc + 16 * q;
+        pc[q] = gc + (gc >= g.cg0 ? g.cgw : 0);
+    }
+    for (int k0 = 0; k0 < k; k0 += BK) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int gk = k0 + ar_k + q;
+            const float2 v = (gr < m && gk < k) ? A2[pr + (int64_t)gk * g.lda] : make_float2(0.f, 0.f);
+            Ar[ar_k + q][ar_row] = v.x;
+            Ai[ar_k + q][ar_row] = v.y;
+        }
+        const int gk = k0 + bk;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int gc = col0 + bc + 16 * q;
+            const float2 v = (gc < n && gk < k) ? B2[gk + pc[q] * g.ldb] : make_float2(0.f, 0.f);
+            Br[bk][bc + 16 * q] = v.x;
+            Bi[bk][bc + 16 * q] = v.y;
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < 8; ++kk) {
-            float2 a[4], b[4];
-            for (int i = 0; i < 4; ++i) a[i] = As[kk][tr + 16 * i];
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tc + 16 * j];
-            for (int i = 0; i < 4; ++i)
-                for (int j = 0; j < 4; ++j) {
-                    acc[i][j][0] += a[i].x * b[j].x - a[i].y * b[j].y;
-                    acc[i][j][1] += a[i].x * b[j].y + a[i].y * b[j].x;
-                }
+        for (int kp = 0; kp < BK; kp += 2) {
+            const int kk = kp + (lane >> 5);
+            const int cc = wn * 32 + (lane & 31);
+            const float b_r = Br[kk][cc], b_i = Bi[kk][cc];
+            const int r0 = wm * 64 + (lane & 31);
+            const float a0r = Ar[kk][r0], a0i = Ai[kk][r0];
+            const float a1r = Ar[kk][r0 + 32], a1i = Ai[kk][r0 + 32];
+            cr0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0r, b_r, cr0, 0, 0, 0);
+            ci0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0r, b_i, ci0, 0, 0, 0);
+            cr1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1r, b_r, cr1, 0, 0, 0);
+            ci1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1r, b_i, ci1, 0, 0, 0);
+            cr0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0i, -b_i, cr0, 0, 0, 0);
+            ci0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0i, b_r, ci0, 0, 0, 0);
+            cr1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1i, -b_i, cr1, 0, 0, 0);
+            ci1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1i, b_r, ci1, 0, 0, 0);
         }
         __syncthreads();
     }
-    for (int i = 0; i < 4; ++i) {
-        const int gr = row0 + tr + 16 * i;
-        if (gr >= m) continue;
-        for (int j = 0; j < 4; ++j) {
-            const int gc = col0 + tc + 16 * j;
-            if (gc >= n) continue;
-            float re = ar * acc[i][j][0] - ai * acc[i][j][1];
-            float im = ar * acc[i][j][1] + ai * acc[i][j][0];
-            if (beta != 0.f) {
-                const float* c = C + 2 * (gr + (int64_t)gc * ldc);
-                re += beta * c[0];
-                im += beta * c[1];
+    const int col = col0 + wn * 32 + (lane & 31);
+    if (col >= n) return;
+    const int64_t pcol = col + (col >= g.cg0 ? g.cgw : 0);
+    const float* Cz = g.C ? g.C + 2 * z * g.sC : nullptr;
+    float* Dz = g.D + 2 * z * g.sD;
+#pragma unroll
+    for (int sub = 0; sub < 2; ++sub) {
+        const floatx16& xr = sub == 0 ? cr0 : cr1;
+        const floatx16& xi = sub == 0 ? ci0 : ci1;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int row = row0 + wm * 64 + sub * 32 + (i / 4) * 8 + (lane >> 5) * 4 + (i % 4);
+            if (row >= m) continue;
+            const int64_t prow = row + (row >= g.rg0 ? g.rgw : 0);
+            float re = g.ar * xr[i] - g.ai * xi[i];
+            float im = g.ar * xi[i] + g.ai * xr[i];
+            if (g.beta != 0.f) {
+                const float* c = Cz + 2 * (prow + pcol * g.ldc);
+                re += g.beta * c[0];
+                im += g.beta * c[1];
             }
-            float* d = D + 2 * (gr + (int64_t)gc * ldd);
+            float* d = Dz + 2 * (prow + pcol * g.ldd);
             d[0] = re;
             d[1] = im;
         }
     }
 }
 
-// In-place inverse of an n x n (n <= 64) complex64 block by Gauss-Jordan elimination
-// with partial pivoting; one workgroup, the block held in LDS.
-__global__ __launch_bounds__(256) void k_cinv_small(float* A, int64_t lda, int n, int* info) {
+// In-place inverse of n x n (n <= 64) complex64 blocks by Gauss-Jordan elimination with partial
+// pivoting; one workgroup per block (blockIdx.x), the block held in LDS.  Per elimination step:
+// wavefront 0 finds the pivot row p (largest modulus in column k, smallest index on ties); the
+// scaled pivot row, the multipliers (rows k and p exchanged) and the old row k are staged in LDS;
+// every thread then updates one column over 16 rows (loads first, then stores).  The row
+// exchanges become one column permutation, composed in registers and applied on the store.
+__global__ __launch_bounds__(256) void k_cinv_small(float* A, int64_t lda, int64_t stride, int n, int* info) {
     __shared__ float2 M[64][65];
-    __shared__ int piv[64];
-    __shared__ float2 pvt;
-    __shared__ float2 colk[64];
-    const int tid = threadIdx.x;
-    float2* A2 = reinterpret_cast<float2*>(A);
-    for (int e = tid; e < n * n; e += blockDim.x) {
-        const int r = e % n, c = e / n;
-        M[r][c] = A2[r + (int64_t)c * lda];
-    }
+    __shared__ float2 prow[64], pcol[64], oldk[64];
+    __shared__ int piv[64], perm[64];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    float2* A2 = reinterpret_cast<float2*>(A) + stride * (int64_t)blockIdx.x;
+    for (int c = wv; c < n; c += 4)
+        if (lane < n) M[lane][c] = A2[lane + (int64_t)c * lda];
     __syncthreads();
     for (int k = 0; k < n; ++k) {
-        if (tid == 0) {
-            int p = k;
-            float best = -1.f;
-            for (int i = k; i < n; ++i) {
-                const float v = M[i][k].x * M[i][k].x + M[i][k].y * M[i][k].y;
-                if (v > best) { best = v; p = i; }
+        if (wv == 0) {
+            float v = -1.f;
+            int idx = lane;
+            if (lane >= k && lane < n) v = M[lane][k].x * M[lane][k].x + M[lane][k].y * M[lane][k].y;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const float ov = __shfl_xor(v, off, 64);
+                const int oi = __shfl_xor(idx, off, 64);
+                if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
             }
-            piv[k] = p;
-            if (!(best > 0.f)) info[0] = k + 1;
+            if (lane == 0) {
+                piv[k] = idx;
+                if (!(v > 0.f)) info[0] = k + 1;
+            }
         }
         __syncthreads();
         const int p = piv[k];
-        if (p != k) {
-            for (int c = tid; c < n; c += blockDim.x) {
-                const float2 t = M[k][c];
-                M[k][c] = M[p][c];
-                M[p][c] = t;
-            }
-        }
-        __syncthreads();
-        if (tid == 0) {
-            const float2 a = M[k][k];
+        {
+            const float2 a = M[p][k];
             const float den = a.x * a.x + a.y * a.y;
-            pvt = make_float2(a.x / den, -a.y / den);   // 1 / a
-            M[k][k] = make_float2(1.f, 0.f);
+            const float2 inv = make_float2(a.x / den, -a.y / den);
+            if (tid < 64) {
+                if (tid < n) {
+                    const float2 v = M[p][tid];
+                    prow[tid] = tid == k ? inv : make_float2(v.x * inv.x - v.y * inv.y, v.x * inv.y + v.y * inv.x);
+                }
+            } else if (tid < 128) {
+                const int i = tid - 64;
+                if (i < n) pcol[i] = M[i == k ? p : (i == p ? k : i)][k];
+            } else if (tid < 192) {
+                const int c = tid - 128;
+                if (c < n) oldk[c] = M[k][c];
+            }
         }
         __syncthreads();
-        for (int c = tid; c < n; c += blockDim.x) {
-            const float2 v = M[k][c];
-            M[k][c] = make_float2(v.x * pvt.x - v.y * pvt.y, v.x * pvt.y + v.y * pvt.x);
-        }
-        __syncthreads();
-        for (int i = tid; i < n; i += blockDim.x) {
-            colk[i] = M[i][k];
-        }
-        __syncthreads();
-        for (int i = tid; i < n; i += blockDim.x) {
-            if (i != k) M[i][k] = make_float2(0.f, 0.f);
-        }
-        __syncthreads();
-        for (int e = tid; e < n * n; e += blockDim.x) {
-            const int i = e % n, c = e / n;
-            if (i == k) continue;
-            const float2 f = colk[i];
-            const float2 r = M[k][c];
-            M[i][c].x -= f.x * r.x - f.y * r.y;
-            M[i][c].y -= f.x * r.y + f.y * r.x;
-        }
-        __syncthreads();
-    }
-    // undo the row interchanges as column interchanges, last first
-    for (int k = n - 1; k >= 0; --k) {
-        const int p = piv[k];
-        if (p != k) {
-            for (int r = tid; r < n; r += blockDim.x) {
-                const float2 t = M[r][k];
-                M[r][k] = M[r][p];
-                M[r][p] = t;
+        if (lane < n) {
+            const int c = lane;
+            const float2 r = prow[c];
+            float2 v[16], f[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int i = wv + 4 * q;
+                if (i < n) {
+                    v[q] = i == p ? oldk[c] : M[i][c];
+                    f[q] = pcol[i];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int i = wv + 4 * q;
+                if (i >= n) continue;
+                if (i == k) {
+                    M[k][c] = r;
+                } else if (c == k) {
+                    M[i][k] = make_float2(-(f[q].x * r.x - f[q].y * r.y), -(f[q].x * r.y + f[q].y * r.x));
+                } else {
+                    M[i][c] = make_float2(v[q].x - (f[q].x * r.x - f[q].y * r.y), v[q].y - (f[q].x * r.y + f[q].y * r.x));
+                }
             }
         }
         __syncthreads();
     }
-    for (int e = tid; e < n * n; e += blockDim.x) {
-        const int r = e % n, c = e / n;
-        A2[r + (int64_t)c * lda] = M[r][c];
+    // undoing the row exchanges, last first, as column exchanges: out[:, j] = M[:, perm[j]]
+    if (wv == 0) {
+        int pj = lane;
+        const int mypiv = lane < n ? piv[lane] : lane;
+        for (int k = n - 1; k >= 0; --k) {
+            const int pk = __shfl(mypiv, k, 64);
+            const int vk = __shfl(pj, k, 64), vp = __shfl(pj, pk, 64);
+            if (pk != k) {
+                if (lane == k) pj = vp;
+                if (lane == pk) pj = vk;
+            }
+        }
+        perm[lane] = pj;
     }
+    __syncthreads();
+    for (int c = wv; c < n; c += 4)
+        if (lane < n) A2[lane + (int64_t)c * lda] = M[lane][perm[c]];
 }
 
 __global__ void k_copy_d2f(const double* __restrict__ s, float* __restrict__ d, int64_t n) {
@@ -759,16 +807,14 @@ void launch_copy_block_f64_to_f32(const double* src, float* dst, int64_t n, hipS
     hipLaunchKernelGGL(k_copy_d2f, dim3(gridn(n, 256)), dim3(256), 0, s, src, dst, n);
 }
 
-void launch_cgemm_f32(int m, int n, int k, float ar, float ai, const float* A, int64_t lda, const float* B, int64_t ldb,
-                      float beta, const float* C, int64_t ldc, float* D, int64_t ldd, hipStream_t s) {
-    if (m <= 0 || n <= 0) return;
-    hipLaunchKernelGGL(k_cgemm, dim3(gridn(m, 64), gridn(n, 64)), dim3(256), 0, s, m, n, k, ar, ai, A, lda, B, ldb,
-                       beta, C, ldc, D, ldd);
+void launch_cgemm_f32(const CGemm& g, hipStream_t s) {
+    if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return;
+    hipLaunchKernelGGL(k_cgemm_mfma, dim3(gridn(g.m, 128), gridn(g.n, 64), (unsigned)g.batch), dim3(256), 0, s, g);
 }
 
-int launch_cinv_small_f32(float* A, int64_t lda, int n, int* info, hipStream_t s) {
-    if (n <= 0 || n > 64) return -1;
-    hipLaunchKernelGGL(k_cinv_small, dim3(1), dim3(256), 0, s, A, lda, n, info);
+int launch_cinv_small_f32(float* A, int64_t lda, int64_t stride, int n, int batch, int* info, hipStream_t s) {
+    if (n <= 0 || n > 64 || batch <= 0) return -1;
+    hipLaunchKernelGGL(k_cinv_small, dim3((unsigned)batch), dim3(256), 0, s, A, lda, stride, n, info);
     return 0;
 }
 
