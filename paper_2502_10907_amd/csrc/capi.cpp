@@ -44,10 +44,14 @@ struct GmresWork {
     int maxit = 0, nb = 0;
     DevBuf<double> V, Zt, Rf, tmp, tmp2, tmp3, r, hpart, S, Z, hg, scal, H, npart, upart, y;
     int zslots = 0;                  // Krylov slots held by Zt (0: no preconditioned basis)
-    DevBuf<int> cnt;                 // Arnoldi steps kept per right-hand side
+    DevBuf<int> cnt;                 // Arnoldi steps kept per right-hand side, then a zero-pivot flag
     double* host = nullptr;          // pinned: nb x kSync Hessenberg columns + norm parts
+    double* hosty = nullptr;         // pinned: nb x (maxit + 1) least-squares coefficients
+    int* hostcnt = nullptr;          // pinned: nb step counts + flag
     ~GmresWork() {
         if (host) (void)hipHostFree(host);
+        if (hosty) (void)hipHostFree(hosty);
+        if (hostcnt) (void)hipHostFree(hostcnt);
     }
 };
 
@@ -555,11 +559,17 @@ void gmres_alloc(mtf_problem p, int maxit, int nb, bool flex) {
     w.npart.alloc((int64_t)nb * kNblk);
     w.upart.alloc(4 * n * (int64_t)nb * std::max<int64_t>(nct, 1));
     w.y.alloc(2 * (int64_t)nb * (maxit + 1));
-    w.cnt.alloc(nb);
+    w.cnt.alloc(nb + 1);
     if (w.host) (void)hipHostFree(w.host);
+    if (w.hosty) (void)hipHostFree(w.hosty);
+    if (w.hostcnt) (void)hipHostFree(w.hostcnt);
     w.host = nullptr;
+    w.hosty = nullptr;
+    w.hostcnt = nullptr;
     HIPCHK(hipHostMalloc((void**)&w.host, ((size_t)2 * ldh * kSync * nb + (size_t)kNblk * nb) * sizeof(double),
                          hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&w.hosty, (size_t)2 * nb * ldh * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&w.hostcnt, (size_t)(nb + 1) * sizeof(int), hipHostMallocDefault));
 }
 
 // column norms of nb vectors (stride ld)
@@ -701,9 +711,9 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
         }
         done_cols = j;
     }
-    // back substitution per right-hand side; flexible: coefficients R^-1 y on the zt basis
-    std::vector<double> yh((size_t)2 * nb * (nvmax + 1), 0.0);
-    std::vector<cd> Rh;
+    // back substitution per right-hand side; flexible: coefficients R^-1 y on the zt basis (device)
+    double* yh = w.hosty;
+    std::fill(yh, yh + (size_t)2 * nb * (nvmax + 1), 0.0);
     for (int b = 0; b < nb; ++b) {
         const int it = itv[b];
         std::vector<cd> yv(it);
@@ -712,28 +722,20 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
             for (int k = i + 1; k < it; ++k) acc -= H[b][k][i] * yv[k];
             yv[i] = acc / H[b][i][i];
         }
-        if (flex && it > 0) {
-            Rh.assign((size_t)it * it, cd(0));
-            HIPCHK(hipMemcpy2DAsync(Rh.data(), (size_t)it * sizeof(cd), w.Rf.p + 2 * (int64_t)b * hstride,
-                                    (size_t)ldh * sizeof(cd), (size_t)it * sizeof(cd), it, hipMemcpyDeviceToHost, s));
-            sync(p);
-            for (int i = it - 1; i >= 0; --i) {
-                cd acc = yv[i];
-                for (int k = i + 1; k < it; ++k) acc -= Rh[(size_t)k * it + i] * yv[k];
-                const cd d = Rh[(size_t)i * it + i];
-                if (d == cd(0)) throw NonFiniteError("GMRES: zero pivot in the reorthogonalisation factor");
-                yv[i] = acc / d;
-            }
-        }
         for (int i = 0; i < it; ++i) {
             yh[(size_t)2 * b * (nvmax + 1) + 2 * i] = yv[i].real();
             yh[(size_t)2 * b * (nvmax + 1) + 2 * i + 1] = yv[i].imag();
         }
     }
-    HIPCHK(hipMemcpyAsync(w.y.p, yh.data(), yh.size() * sizeof(double), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(w.cnt.p, itv.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
+    for (int b = 0; b < nb; ++b) w.hostcnt[b] = itv[b];
+    w.hostcnt[nb] = 0;
+    HIPCHK(hipMemcpyAsync(w.y.p, yh, (size_t)2 * nb * (nvmax + 1) * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(w.cnt.p, w.hostcnt, (nb + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    if (flex) launch_trsv_upper(w.Rf.p, ldh, hstride, w.cnt.p, w.y.p, nvmax + 1, w.cnt.p + nb, nb, s);
     launch_combine(X, ldx, flex ? w.Zt.p : V, ldv, w.cnt.p, nvmax, w.y.p, n, nb, s);   // X_b += basis_b coef_b
+    HIPCHK(hipMemcpyAsync(w.hostcnt + nb, w.cnt.p + nb, sizeof(int), hipMemcpyDeviceToHost, s));
     sync(p);
+    if (w.hostcnt[nb]) throw NonFiniteError("GMRES: zero pivot in the reorthogonalisation factor");
     est.assign(nb, 0.0);
     for (int b = 0; b < nb; ++b) {
         reorth[b] += itv[b];          // every kept step was reorthogonalised

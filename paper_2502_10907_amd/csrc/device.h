@@ -119,6 +119,8 @@ void launch_dcgs_col(double* H, int64_t ldh, int64_t hstride, const double* S, c
                      int nv, int nvmax, double* scal, int last, double* R, int64_t rstride, int nb, hipStream_t s);
 void launch_update2(const double* V, int64_t ldv, int nv, int nvmax, const double* S, const double* Z, double* u,
                     double* t, int64_t n, double* part, const double* scal, int nb, hipStream_t s);
+void launch_trsv_upper(const double* R, int64_t ldh, int64_t rstride, const int* cnt, double* y, int64_t ystride,
+                       int* info, int nb, hipStream_t s);                  // y_b = R_b^-1 y_b (upper, cnt[b])
 void launch_combine(double* x, int64_t ldx, const double* V, int64_t ldv, const int* cnt, int nvmax, const double* coef,
                     int64_t n, int nb, hipStream_t s);                       // x_b += V_b coef_b
 void launch_norm2(const double* w, int64_t ldw, int64_t n, double* part, int nblk, int nb, hipStream_t s);

@@ -460,6 +460,48 @@ __global__ __launch_bounds__(256) void k_update2_apply(const double* __restrict_
     t[1] = ti * inv;
 }
 
+// Back substitution y_b <- R_b^-1 y_b with the upper triangular cnt[b] x cnt[b] factor R_b
+// (R + b*rstride, ld ldh), column by column; one workgroup per right-hand side.  A zero diagonal
+// sets info[0] and leaves y_b unchanged from that column on.
+__global__ __launch_bounds__(1024) void k_trsv_upper(const double* __restrict__ R, int64_t ldh, int64_t rstride,
+                                                     const int* __restrict__ cnt, double* __restrict__ Y,
+                                                     int64_t ystride, int* __restrict__ info) {
+    const int b = blockIdx.x;
+    const int it = cnt[b];
+    const double* Rb = R + 2 * (int64_t)b * rstride;
+    double* y = Y + 2 * (int64_t)b * ystride;
+    __shared__ double wv[2];
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    for (int i = it - 1; i >= 0; --i) {
+        if (threadIdx.x == 0) {
+            const double dr = Rb[2 * ((int64_t)i * ldh + i)], di = Rb[2 * ((int64_t)i * ldh + i) + 1];
+            const double den = dr * dr + di * di;
+            if (!(den > 0.0)) {
+                bad = 1;
+                info[0] = 1;
+            } else {
+                const double yr = y[2 * i], yi = y[2 * i + 1];
+                wv[0] = (yr * dr + yi * di) / den;
+                wv[1] = (yi * dr - yr * di) / den;
+                y[2 * i] = wv[0];
+                y[2 * i + 1] = wv[1];
+            }
+        }
+        __syncthreads();
+        if (bad) return;
+        const double ar = wv[0], ai = wv[1];
+        const double* col = Rb + 2 * (int64_t)i * ldh;
+        for (int k = threadIdx.x; k < i; k += blockDim.x) {
+            const double cr = col[2 * k], ci = col[2 * k + 1];
+            y[2 * k] -= cr * ar - ci * ai;
+            y[2 * k + 1] -= cr * ai + ci * ar;
+        }
+        __syncthreads();
+    }
+}
+
 // x_b += V_b coef_b over the first cnt[b] vectors (column b of each slab)
 __global__ __launch_bounds__(256) void k_combine(double* __restrict__ X, int64_t ldx, const double* __restrict__ V,
                                                  int64_t ldv, const int* __restrict__ cnt, int nvmax,
@@ -519,8 +561,10 @@ __global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, in
 // read and written by the same lane.
 // Workgroup tile 128 x 64 complex, k-tile 16, four wavefronts in 2 x 2, each owning 64 x 32 as two
 // 32 x 32 MFMA tiles; per pair of k: re*re, im*(-im), re*im and im*re products, FP32 accumulation.
-// MFMA lane layout: A operand row l%32, k l/32; B operand k l/32, column l%32; result register i
-// holds row (i/4)*8 + (l/32)*4 + i%4, column l%32.
+// MFMA lane layout: first operand row l%32, k l/32; second operand k l/32, column l%32; result
+// register i holds row (i/4)*8 + (l/32)*4 + i%4, column l%32.  Each tile is computed transposed
+// (first operand B^T, second A^T), so that lane l holds matrix row l%32: the epilogue's loads and
+// stores of C and D run down the columns (256 contiguous bytes per half-wavefront).
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 __global__ __launch_bounds__(256) void k_cgemm_mfma(const CGemm g) {
@@ -570,31 +614,31 @@ __global__ __launch_bounds__(256) void k_cgemm_mfma(const CGemm g) {
             const int r0 = wm * 64 + (lane & 31);
             const float a0r = Ar[kk][r0], a0i = Ai[kk][r0];
             const float a1r = Ar[kk][r0 + 32], a1i = Ai[kk][r0 + 32];
-            cr0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0r, b_r, cr0, 0, 0, 0);
-            ci0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0r, b_i, ci0, 0, 0, 0);
-            cr1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1r, b_r, cr1, 0, 0, 0);
-            ci1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1r, b_i, ci1, 0, 0, 0);
-            cr0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0i, -b_i, cr0, 0, 0, 0);
-            ci0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0i, b_r, ci0, 0, 0, 0);
-            cr1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1i, -b_i, cr1, 0, 0, 0);
-            ci1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1i, b_r, ci1, 0, 0, 0);
+            cr0 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_r, a0r, cr0, 0, 0, 0);
+            ci0 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_i, a0r, ci0, 0, 0, 0);
+            cr1 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_r, a1r, cr1, 0, 0, 0);
+            ci1 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_i, a1r, ci1, 0, 0, 0);
+            cr0 = __builtin_amdgcn_mfma_f32_32x32x2f32(-b_i, a0i, cr0, 0, 0, 0);
+            ci0 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_r, a0i, ci0, 0, 0, 0);
+            cr1 = __builtin_amdgcn_mfma_f32_32x32x2f32(-b_i, a1i, cr1, 0, 0, 0);
+            ci1 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_r, a1i, ci1, 0, 0, 0);
         }
         __syncthreads();
     }
-    const int col = col0 + wn * 32 + (lane & 31);
-    if (col >= n) return;
-    const int64_t pcol = col + (col >= g.cg0 ? g.cgw : 0);
     const float* Cz = g.C ? g.C + 2 * z * g.sC : nullptr;
     float* Dz = g.D + 2 * z * g.sD;
 #pragma unroll
     for (int sub = 0; sub < 2; ++sub) {
         const floatx16& xr = sub == 0 ? cr0 : cr1;
         const floatx16& xi = sub == 0 ? ci0 : ci1;
+        const int row = row0 + wm * 64 + sub * 32 + (lane & 31);
+        if (row >= m) continue;
+        const int64_t prow = row + (row >= g.rg0 ? g.rgw : 0);
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const int row = row0 + wm * 64 + sub * 32 + (i / 4) * 8 + (lane >> 5) * 4 + (i % 4);
-            if (row >= m) continue;
-            const int64_t prow = row + (row >= g.rg0 ? g.rgw : 0);
+            const int col = col0 + wn * 32 + (i / 4) * 8 + (lane >> 5) * 4 + (i % 4);
+            if (col >= n) continue;
+            const int64_t pcol = col + (col >= g.cg0 ? g.cgw : 0);
             float re = g.ar * xr[i] - g.ai * xi[i];
             float im = g.ar * xi[i] + g.ai * xr[i];
             if (g.beta != 0.f) {
@@ -610,38 +654,62 @@ __global__ __launch_bounds__(256) void k_cgemm_mfma(const CGemm g) {
 }
 
 // In-place inverse of n x n (n <= 64) complex64 blocks by Gauss-Jordan elimination with partial
-// pivoting; one workgroup per block (blockIdx.x), the block held in LDS.  Per elimination step:
-// wavefront 0 finds the pivot row p (largest modulus in column k, smallest index on ties); the
-// scaled pivot row, the multipliers (rows k and p exchanged) and the old row k are staged in LDS;
-// every thread then updates one column over 16 rows (loads first, then stores).  The row
-// exchanges become one column permutation, composed in registers and applied on the store.
-__global__ __launch_bounds__(256) void k_cinv_small(float* A, int64_t lda, int64_t stride, int n, int* info) {
+// pivoting; one workgroup of 1024 threads per block (blockIdx.x), the block held in LDS.  Thread
+// (lane c, wavefront w) owns column c of rows w, w+16, w+32, w+48.  Per elimination step k:
+//  A. every thread combines the 16 per-wavefront candidates for the pivot of column k (largest
+//     modulus, smallest row on ties) and the scaled pivot row, the multipliers (rows k and p
+//     exchanged) and the old row k are staged in LDS;
+//  B. every thread updates its four entries (loads first, then stores); the owners of column k+1
+//     leave their candidate for the next pivot.
+// Two barriers per step.  The row exchanges become one column permutation, composed in registers
+// and applied on the store.
+__global__ __launch_bounds__(1024) void k_cinv_small(float* A, int64_t lda, int64_t stride, int n, int* info) {
     __shared__ float2 M[64][65];
     __shared__ float2 prow[64], pcol[64], oldk[64];
+    __shared__ float cv[2][16];
+    __shared__ int ci[2][16];
     __shared__ int piv[64], perm[64];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     float2* A2 = reinterpret_cast<float2*>(A) + stride * (int64_t)blockIdx.x;
-    for (int c = wv; c < n; c += 4)
+    for (int c = wv; c < n; c += 16)
         if (lane < n) M[lane][c] = A2[lane + (int64_t)c * lda];
     __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        if (wv == 0) {
-            float v = -1.f;
-            int idx = lane;
-            if (lane >= k && lane < n) v = M[lane][k].x * M[lane][k].x + M[lane][k].y * M[lane][k].y;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const float ov = __shfl_xor(v, off, 64);
-                const int oi = __shfl_xor(idx, off, 64);
-                if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-            }
-            if (lane == 0) {
-                piv[k] = idx;
-                if (!(v > 0.f)) info[0] = k + 1;
+    // candidates for the first pivot (column 0)
+    if (lane == 0) {
+        float best = -1.f;
+        int bi = 0;
+        for (int q = 0; q < 4; ++q) {
+            const int i = wv + 16 * q;
+            if (i < n) {
+                const float v = M[i][0].x * M[i][0].x + M[i][0].y * M[i][0].y;
+                if (v > best) { best = v; bi = i; }
             }
         }
-        __syncthreads();
-        const int p = piv[k];
+        cv[0][wv] = best;
+        ci[0][wv] = bi;
+    }
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        const int sl = k & 1;
+        float cvals[16];
+        int cidx[16];
+#pragma unroll
+        for (int w = 0; w < 16; ++w) {      // all loads first, then branch-free selection
+            cvals[w] = cv[sl][w];
+            cidx[w] = ci[sl][w];
+        }
+        float best = cvals[0];
+        int p = cidx[0];
+#pragma unroll
+        for (int w = 1; w < 16; ++w) {
+            const bool better = (cvals[w] > best) | ((cvals[w] == best) & (cidx[w] < p));
+            best = better ? cvals[w] : best;
+            p = better ? cidx[w] : p;
+        }
+        if (tid == 0) {
+            piv[k] = p;
+            if (!(best > 0.f)) info[0] = k + 1;
+        }
         {
             const float2 a = M[p][k];
             const float den = a.x * a.x + a.y * a.y;
@@ -663,26 +731,38 @@ __global__ __launch_bounds__(256) void k_cinv_small(float* A, int64_t lda, int64
         if (lane < n) {
             const int c = lane;
             const float2 r = prow[c];
-            float2 v[16], f[16];
+            float2 v[4], f[4];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int i = wv + 4 * q;
+            for (int q = 0; q < 4; ++q) {
+                const int i = wv + 16 * q;
                 if (i < n) {
                     v[q] = i == p ? oldk[c] : M[i][c];
                     f[q] = pcol[i];
                 }
             }
+            float nb = -1.f;
+            int ni = 0;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int i = wv + 4 * q;
+            for (int q = 0; q < 4; ++q) {
+                const int i = wv + 16 * q;
                 if (i >= n) continue;
+                float2 o;
                 if (i == k) {
-                    M[k][c] = r;
+                    o = r;
                 } else if (c == k) {
-                    M[i][k] = make_float2(-(f[q].x * r.x - f[q].y * r.y), -(f[q].x * r.y + f[q].y * r.x));
+                    o = make_float2(-(f[q].x * r.x - f[q].y * r.y), -(f[q].x * r.y + f[q].y * r.x));
                 } else {
-                    M[i][c] = make_float2(v[q].x - (f[q].x * r.x - f[q].y * r.y), v[q].y - (f[q].x * r.y + f[q].y * r.x));
+                    o = make_float2(v[q].x - (f[q].x * r.x - f[q].y * r.y), v[q].y - (f[q].x * r.y + f[q].y * r.x));
                 }
+                M[i][c] = o;
+                const float m2 = o.x * o.x + o.y * o.y;
+                const bool better = (i > k) & (m2 > nb);
+                nb = better ? m2 : nb;
+                ni = better ? i : ni;
+            }
+            if (c == k + 1) {
+                cv[sl ^ 1][wv] = nb;
+                ci[sl ^ 1][wv] = ni;
             }
         }
         __syncthreads();
@@ -702,7 +782,7 @@ __global__ __launch_bounds__(256) void k_cinv_small(float* A, int64_t lda, int64
         perm[lane] = pj;
     }
     __syncthreads();
-    for (int c = wv; c < n; c += 4)
+    for (int c = wv; c < n; c += 16)
         if (lane < n) A2[lane + (int64_t)c * lda] = M[lane][perm[c]];
 }
 
@@ -790,6 +870,11 @@ void launch_update2(const double* V, int64_t ldv, int nv, int nvmax, const doubl
     hipLaunchKernelGGL(k_update2_apply, dim3(gridn(n, 256), (unsigned)nb), dim3(256), 0, s, part, nch, u, t, n, scal);
 }
 
+void launch_trsv_upper(const double* R, int64_t ldh, int64_t rstride, const int* cnt, double* y, int64_t ystride,
+                       int* info, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(k_trsv_upper, dim3((unsigned)nb), dim3(1024), 0, s, R, ldh, rstride, cnt, y, ystride, info);
+}
+
 void launch_combine(double* x, int64_t ldx, const double* V, int64_t ldv, const int* cnt, int nvmax, const double* coef,
                     int64_t n, int nb, hipStream_t s) {
     hipLaunchKernelGGL(k_combine, dim3(gridn(n, 256), (unsigned)nb), dim3(256), 0, s, x, ldx, V, ldv, cnt, nvmax, coef, n);
@@ -814,7 +899,7 @@ void launch_cgemm_f32(const CGemm& g, hipStream_t s) {
 
 int launch_cinv_small_f32(float* A, int64_t lda, int64_t stride, int n, int batch, int* info, hipStream_t s) {
     if (n <= 0 || n > 64 || batch <= 0) return -1;
-    hipLaunchKernelGGL(k_cinv_small, dim3((unsigned)batch), dim3(256), 0, s, A, lda, stride, n, info);
+    hipLaunchKernelGGL(k_cinv_small, dim3((unsigned)batch), dim3(1024), 0, s, A, lda, stride, n, info);
     return 0;
 }
 
