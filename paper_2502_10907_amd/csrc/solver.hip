@@ -65,6 +65,50 @@ __global__ __launch_bounds__(256) void k_mv_dense(const DomDesc* __restrict__ do
     pN[1] = -2.0 * rho * (double)tD[1] + 2.0 * (double)kN[1];
 }
 
+// Complex64 blocks, FP64 arithmetic: the entries are widened on load and the products and sums
+// are formed in FP64, so the only error against the stored operator is the FP32 rounding of
+// the entries themselves (the kernel is HBM-bound either way).
+__global__ __launch_bounds__(256) void k_mv_dense_f32w(const DomDesc* __restrict__ doms, const int4* __restrict__ mtiles,
+                                                       const float* __restrict__ T, const float* __restrict__ K,
+                                                       const double* __restrict__ x, double* __restrict__ part) {
+    const int4 t = mtiles[blockIdx.x];
+    const DomDesc dd = doms[t.x];
+    const int E = dd.E;
+    const int c0 = t.z * kChunk;
+    const int nc = min(kChunk, E - c0);
+    __shared__ double xs[kChunk][4];
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        const double* xd = x + 2 * (dd.off + c0 + c);
+        const double* xn = x + 2 * (dd.off + E + c0 + c);
+        xs[c][0] = xd[0]; xs[c][1] = xd[1];
+        xs[c][2] = xn[0]; xs[c][3] = xn[1];
+    }
+    __syncthreads();
+    const int row = t.y + threadIdx.x;
+    if (row >= E) return;
+    double tD[2] = {0, 0}, tN[2] = {0, 0}, kD[2] = {0, 0}, kN[2] = {0, 0};
+    const float2* Tc = reinterpret_cast<const float2*>(T) + dd.mat0 + row + (int64_t)c0 * E;
+    const float2* Kc = reinterpret_cast<const float2*>(K) + dd.mat0 + row + (int64_t)c0 * E;
+#pragma unroll 4
+    for (int c = 0; c < nc; ++c) {
+        const float2 af = Tc[(int64_t)c * E];
+        const float2 bf = Kc[(int64_t)c * E];
+        const double ar = af.x, ai = af.y, br = bf.x, bi = bf.y;
+        const double xdr = xs[c][0], xdi = xs[c][1], xnr = xs[c][2], xni = xs[c][3];
+        tD[0] += ar * xdr - ai * xdi; tD[1] += ar * xdi + ai * xdr;
+        tN[0] += ar * xnr - ai * xni; tN[1] += ar * xni + ai * xnr;
+        kD[0] += br * xdr - bi * xdi; kD[1] += br * xdi + bi * xdr;
+        kN[0] += br * xnr - bi * xni; kN[1] += br * xni + bi * xnr;
+    }
+    const double rho = dd.rho;
+    double* pD = part + 2 * (dd.part0 + (int64_t)(2 * t.z) * E + row);
+    double* pN = part + 2 * (dd.part0 + (int64_t)(2 * t.z + 1) * E + row);
+    pD[0] = 2.0 * kD[0] + (2.0 / rho) * tN[0];
+    pD[1] = 2.0 * kD[1] + (2.0 / rho) * tN[1];
+    pN[0] = -2.0 * rho * tD[0] + 2.0 * kN[0];
+    pN[1] = -2.0 * rho * tD[1] + 2.0 * kN[1];
+}
+
 // Finishing kernels: 64 dofs per workgroup, the four wavefronts split the column chunks of the
 // partial sums (and the two transmission triangles) and meet in LDS.
 __device__ inline void finish_reduce(double (&acc)[4], double (*red)[64][4]) {
@@ -807,7 +851,7 @@ void launch_matvec_dense_f64(const DomDesc* doms, const int4* mtiles, int64_t nm
 
 void launch_matvec_dense_f32(const DomDesc* doms, const int4* mtiles, int64_t nmt, const float* T, const float* K,
                              const double* x, double* part, hipStream_t s) {
-    hipLaunchKernelGGL(k_mv_dense<float>, dim3((unsigned)nmt), dim3(256), 0, s, doms, mtiles, T, K, x, part);
+    hipLaunchKernelGGL(k_mv_dense_f32w, dim3((unsigned)nmt), dim3(256), 0, s, doms, mtiles, T, K, x, part);
 }
 
 void launch_matvec_finish(const DomDesc* doms, int /*ndom*/, const int32_t* dof_dom, int64_t ndof, const int32_t* dplus,
