@@ -68,6 +68,11 @@ extern "C" {
 #define MTF_PREC_BLOCK_TINV    1   /* right block-Jacobi preconditioner from T_i^-1 (see mtf_solve) */
 #define MTF_PREC_BLOCK_TINV_GS 2   /* one block Gauss-Seidel sweep with the same blocks (see mtf_solve) */
 
+/* mtf_solve_opts.flags: by default the Arnoldi steps between two host reads of the Hessenberg
+ * columns are captured once per GMRES cycle as a HIP graph and replayed; MTF_SOLVE_EAGER launches
+ * the same kernels one by one instead (same results). */
+#define MTF_SOLVE_EAGER 1
+
 typedef struct mtf_problem_s* mtf_problem;
 
 /* Message of the last failing call on this thread (never NULL). */
@@ -181,7 +186,7 @@ typedef struct {
     int32_t preconditioner;   /* MTF_PREC_NONE, MTF_PREC_BLOCK_TINV or MTF_PREC_BLOCK_TINV_GS */
     int32_t max_iters;        /* Arnoldi steps per GMRES cycle, 0 = 2000                     */
     int32_t max_refinements;  /* outer FP64 refinement steps (MTF_FP32_MIXED), 0 = 10        */
-    int32_t reserved;
+    int32_t flags;            /* 0, or MTF_SOLVE_EAGER                                       */
     double  rtol;             /* ||b - M x||_2 <= rtol ||b||_2 with the FP64 operator        */
     double  inner_rtol;       /* inner GMRES tolerance of a refinement step, 0 = 1e-3*... */
     const void* x0_dev;       /* complex128 initial guess [nrhs][ld] or NULL (zero)          */

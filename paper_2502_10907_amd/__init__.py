@@ -32,6 +32,7 @@ ERR_NAMES = {-1: "ARG", -2: "MESH", -3: "NONFINITE", -4: "HIP", -5: "OOM", -6: "
 FP64, FP32_MIXED, BF16_SPLIT = 0, 1, 2
 BLOCK_T, BLOCK_K = 0, 1
 PREC_NONE, PREC_BLOCK_TINV, PREC_BLOCK_TINV_GS = 0, 1, 2
+SOLVE_EAGER = 1
 
 
 class MTFError(RuntimeError):
@@ -47,7 +48,7 @@ class AssemblyOpts(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("precision", C.c_int32), ("preconditioner", C.c_int32),
-                ("max_iters", C.c_int32), ("max_refinements", C.c_int32), ("reserved", C.c_int32),
+                ("max_iters", C.c_int32), ("max_refinements", C.c_int32), ("flags", C.c_int32),
                 ("rtol", C.c_double), ("inner_rtol", C.c_double), ("x0_dev", C.c_void_p)]
 
 
@@ -292,7 +293,8 @@ class Problem:
         return d.value, t.value
 
     def solve(self, b, x, rtol: float = 1e-6, precision: int = FP64, preconditioner: int = PREC_BLOCK_TINV,
-              max_iters: int = 0, max_refinements: int = 0, inner_rtol: float = 0.0, x0=None) -> list[Stats]:
+              max_iters: int = 0, max_refinements: int = 0, inner_rtol: float = 0.0, x0=None,
+              graph: bool = True) -> list[Stats]:
         pb, nrhs, ld = _dev(b, self.N)
         px, nrhs2, ld2 = _dev(x, self.N)
         if (nrhs, ld) != (nrhs2, ld2):
@@ -303,7 +305,7 @@ class Problem:
             if (n3, ld3) != (nrhs, ld):
                 raise ValueError("x0 shape differs")
         o = SolveOpts(C.sizeof(SolveOpts), int(precision), int(preconditioner), int(max_iters),
-                      int(max_refinements), 0, float(rtol), float(inner_rtol), x0p)
+                      int(max_refinements), 0 if graph else SOLVE_EAGER, float(rtol), float(inner_rtol), x0p)
         st = (SolveStats * nrhs)()
         code = _check(_lib.mtf_solve(self._h, nrhs, pb, px, ld, C.byref(o), st))
         self.last_status = code
@@ -449,11 +451,12 @@ class Batch:
         _check(_lib.mtf_batch_assemble(self._h, C.byref(o), C.byref(g), C.byref(t)))
         return g.value, t.value
 
-    def solve(self, bs, xs, rtol=1e-6, precision=FP64, preconditioner=PREC_BLOCK_TINV, max_iters=0):
+    def solve(self, bs, xs, rtol=1e-6, precision=FP64, preconditioner=PREC_BLOCK_TINV, max_iters=0, graph=True):
         n = len(self.problems)
         pb = (_P * n)(*[_dev(b, p.N)[0].value for b, p in zip(bs, self.problems)])
         px = (_P * n)(*[_dev(x, p.N)[0].value for x, p in zip(xs, self.problems)])
-        o = SolveOpts(C.sizeof(SolveOpts), int(precision), int(preconditioner), int(max_iters), 0, 0, float(rtol), 0.0, None)
+        o = SolveOpts(C.sizeof(SolveOpts), int(precision), int(preconditioner), int(max_iters), 0,
+                      0 if graph else SOLVE_EAGER, float(rtol), 0.0, None)
         st = (SolveStats * n)()
         _check(_lib.mtf_batch_solve(self._h, pb, px, C.byref(o), st))
         return [Stats(s.iterations, s.refinements, bool(s.converged), s.rel_residual, s.t_precond_s, s.t_solve_s,

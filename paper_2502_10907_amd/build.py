@@ -48,7 +48,7 @@ def build(verbose: bool = False) -> str:
         msg = "\n".join(f"--- {s} ---\n{o}" for s, o in failed)
         raise RuntimeError("HIP build failed:\n" + msg)
     tmp = OUT + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,-z,defs", "-o", tmp] + objs
     subprocess.run(cmd, check=True)
     os.replace(tmp, OUT)
     return OUT

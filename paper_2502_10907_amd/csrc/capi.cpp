@@ -28,6 +28,8 @@ constexpr int kChunk = 64;    // columns per dense-matvec workgroup (matches sol
 constexpr int kNblk = 32;     // partial sums of GMRES reductions
 constexpr int kSync = 8;      // Arnoldi steps between host reads of the Hessenberg columns
 constexpr int kMaxBatch = 64; // right-hand sides per lockstep GMRES batch (MFMA products)
+constexpr int kUpdGroups = 8; // partial-sum groups of the basis update
+constexpr int kEagerBatches = 2;   // Arnoldi batches of a cycle launched eagerly before a graph is captured
 
 struct GemmOp {
     DevBuf<uint16_t> A, B;
@@ -43,6 +45,8 @@ struct GmresWork {
     int64_t n = 0;
     int maxit = 0, nb = 0;
     DevBuf<double> V, Zt, Rf, tmp, tmp2, tmp3, r, hpart, S, Z, hg, scal, H, npart, upart, y;
+    DevBuf<double> ufix, tfix, zfix, Hst;   // step-invariant candidate, product, preconditioned slabs; staged columns
+    DevBuf<int> jdev;                // step index: step j reads slot j&1 and writes j+1 into the other slot
     int zslots = 0;                  // Krylov slots held by Zt (0: no preconditioned basis)
     DevBuf<int> cnt;                 // Arnoldi steps kept per right-hand side, then a zero-pivot flag
     double* host = nullptr;          // pinned: nb x kSync Hessenberg columns + norm parts
@@ -88,18 +92,20 @@ struct mtf_problem_s {
     GemmOp gm, gp;                   // multi-RHS MFMA products: operator blocks, preconditioner blocks
     // block Gauss-Seidel stages: stage 0 = {Omega_0}, then colour classes of the subdomain graph
     DevBuf<int4> d_stage_tiles;
-    DevBuf<int32_t> d_stage_dofs;
+    DevBuf<int32_t> d_stage_dofs, d_dom_stage;
     std::vector<int64_t> stage_tile0, stage_dof0;   // [nstage + 1] offsets
     double t_precond = 0;
     DevBuf<double> part;
     DevBuf<double> scratch_dirs;
     double t_assemble = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipStream_t capture = nullptr;   // private stream on which GMRES step graphs are captured (never run)
     GmresWork gw;
 
     ~mtf_problem_s() {
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
+        if (capture) (void)hipStreamDestroy(capture);
     }
 };
 
@@ -226,6 +232,7 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
     p->d_mtiles.upload(mtiles, s);
     p->d_sing.upload(sing, s);
     p->d_stage_tiles.upload(stiles, s);
+    p->d_dom_stage.upload(colour, s);
     p->d_stage_dofs.upload(sdofs, s);
     p->stage_tile0 = st0;
     p->stage_dof0 = sd0;
@@ -432,8 +439,6 @@ void precond1(mtf_problem p, const double* x, double* z) {
 // within a stage the subdomains are not adjacent and are processed together.
 void precond1_gs(mtf_problem p, const double* x, double* z, double* w) {
     hipStream_t s = p->stream;
-    const int64_t n = p->sk.N;
-    launch_fill(z, 2 * n, 0.0, s);
     const int nst = (int)p->stage_tile0.size() - 1;
     for (int st = 0; st < nst; ++st) {
         const int4* tiles = p->d_stage_tiles.p + p->stage_tile0[st];
@@ -443,7 +448,7 @@ void precond1_gs(mtf_problem p, const double* x, double* z, double* w) {
         const double* in = x;
         if (st > 0) {
             launch_gs_residual(p->d_doms.p, p->d_dof_dom.p, dl, nd, p->d_dplus.p, p->d_dminus.p, p->d_gval.p, p->d_gcol.p,
-                               x, z, w, s);
+                               p->d_other_dom.p, p->d_dom_stage.p, st, x, z, w, s);
             in = w;
         }
         launch_precond_apply(p->d_doms.p, tiles, ntl, p->Tinv.p, in, p->part.p, s);
@@ -557,7 +562,12 @@ void gmres_alloc(mtf_problem p, int maxit, int nb, bool flex) {
     w.scal.alloc(4 * (int64_t)nb);
     w.H.alloc(2 * ldh * (int64_t)maxit * nb);
     w.npart.alloc((int64_t)nb * kNblk);
-    w.upart.alloc(4 * n * (int64_t)nb * std::max<int64_t>(nct, 1));
+    w.upart.alloc(4 * n * (int64_t)nb * kUpdGroups);
+    w.ufix.alloc(2 * n * nb);
+    w.tfix.alloc(2 * n * nb);
+    w.zfix.alloc(2 * n * nb);
+    w.Hst.alloc(2 * ldh * (int64_t)kSync * nb);
+    w.jdev.alloc(2);
     w.y.alloc(2 * (int64_t)nb * (maxit + 1));
     w.cnt.alloc(nb + 1);
     if (w.host) (void)hipHostFree(w.host);
@@ -618,16 +628,20 @@ void apply_inner(mtf_problem p, const double* src, double* dst, int nb, int prec
 // the nb columns of X (ld ldx).  Arnoldi with delayed classical Gram-Schmidt reorthogonalisation:
 // step j applies the operator to the once-projected candidate u_j, then one pass over the basis
 // gives the coefficients and a second pass forms q_j and u_{j+1}; Hessenberg column j-1 becomes
-// final at step j.  The Hessenberg matrix stays on the device; the host reads the final columns
+// final at step j.  The Hessenberg matrix stays on the device; the host receives the final columns
 // every kSync steps and applies the Givens rotations.  Each right-hand side stops at its own step.
 // With a preconditioner the iteration is flexible: the preconditioned candidates zt_j = P u_j are
 // kept, and since U = Q R (R upper triangular from the reorthogonalisation coefficients) the
 // correction is Zt R^-1 y, so M times the correction matches the Arnoldi relation exactly even
 // though P is applied in FP32.
+// Every kernel of a step reads the step index from the device and works on step-invariant
+// buffers, so the kSync steps between two host reads (plus the staging of the final columns and
+// their copy to pinned host memory) are captured once as a HIP graph and replayed (`graph`), or
+// launched one by one; both run the same kernels.
 // Returns the number of Arnoldi steps taken; it[b], est[b] (recurrence residual / ||r_b||) per column.
 int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, int prec, int pc,
                 const std::vector<double>& tol, int maxit, std::vector<int>& itv, std::vector<double>& est,
-                std::vector<int>& reorth) {
+                std::vector<int>& reorth, bool graph) {
     GmresWork& w = p->gw;
     hipStream_t s = p->stream;
     const int64_t n = w.n;
@@ -639,11 +653,40 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
     const bool flex = pc != MTF_PREC_NONE;
     if (flex && w.zslots < maxit) throw StateError("flexible GMRES basis not allocated");
     double* V = w.V.p;
-    auto Vs = [&](int j) { return V + 2 * ldv * (int64_t)j; };
-    auto Zs = [&](int j) { return w.Zt.p + 2 * ldv * (int64_t)j; };
+    auto jslot = [&](int j) { return w.jdev.p + (j & 1); };
     auto Hc = [&](int j) { return w.H.p + 2 * ldh * (int64_t)j; };
     std::vector<double> beta = norms_dev(p, R, n, nb);
-    HIPCHK(hipMemcpyAsync(Vs(0), R, (size_t)2 * n * nb * sizeof(double), hipMemcpyDeviceToDevice, s));   // u_0 = r
+    // u_0 = r, step index 0
+    HIPCHK(hipMemcpyAsync(V, R, (size_t)2 * n * nb * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(w.ufix.p, R, (size_t)2 * n * nb * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_set_int(jslot(0), 0, s);
+    // one Arnoldi step with index jj (the kernels read jj from the device, so only its parity matters
+    // to the launch sequence)
+    auto step = [&](int jj) {
+        const int* jr = jslot(jj);
+        apply_inner(p, w.ufix.p, w.tfix.p, nb, prec, pc, flex ? w.zfix.p : nullptr);
+        launch_dot2(V, ldv, jr, nvmax, w.tfix.p, n, w.hpart.p, kNblk, nb, s);
+        launch_reduce2(w.hpart.p, jr, nvmax, kNblk, w.S.p, w.Z.p, nb, s);
+        launch_hess_gemv(w.H.p, ldh, hstride, w.S.p, jr, nvmax, nct, w.hg.p, nb, s);
+        launch_dcgs_col(w.H.p, ldh, hstride, w.S.p, w.Z.p, w.hg.p, nct, jr, nvmax, w.scal.p, 0,
+                        flex ? w.Rf.p : nullptr, hstride, nb, s);
+        launch_update2(V, ldv, jr, jslot(jj + 1), nvmax, w.S.p, w.Z.p, w.tfix.p, w.ufix.p, n, w.upart.p, kUpdGroups,
+                       w.scal.p, flex ? w.zfix.p : nullptr, flex ? w.Zt.p : nullptr, nb, s);
+    };
+    // kSync steps j0 .. j0+kSync-1 (j0 odd), then the final columns j0-1 .. j0+kSync-2 staged and
+    // copied to w.host
+    const size_t stage_bytes = (size_t)2 * ldh * kSync * nb * sizeof(double);
+    auto batch = [&](int j0) {
+        for (int q = 0; q < kSync; ++q) step(j0 + q);
+        launch_stage_cols(w.H.p, ldh, hstride, jslot(j0 + kSync), kSync + 1, kSync, w.Hst.p, nb, s);
+        HIPCHK(hipMemcpyAsync(w.host, w.Hst.p, stage_bytes, hipMemcpyDeviceToHost, s));
+    };
+    hipGraphExec_t exec = nullptr;
+    struct ExecGuard {
+        hipGraphExec_t& e;
+        ~ExecGuard() { if (e) (void)hipGraphExecDestroy(e); }
+    } exec_guard{exec};
+
     // host copies of the final Hessenberg columns after the rotations (column jj has jj+1 entries)
     std::vector<std::vector<std::vector<cd>>> H(nb);
     std::vector<std::vector<double>> cs(nb);
@@ -656,27 +699,9 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
         gv[b].push_back(beta[b]);
         if (beta[b] == 0.0) stop[b] = 1; else ++live;
     }
-    int done_cols = 0, steps = 0;
     std::vector<cd> col;
-    for (int j = 0; j <= maxit && live > 0; ++j) {
-        const bool last = j == maxit;      // only finalises column maxit-1
-        double* u = Vs(j);
-        double* t = last ? u : Vs(j + 1);
-        if (!last) apply_inner(p, u, t, nb, prec, pc, flex ? Zs(j) : nullptr);
-        launch_dot2(V, ldv, j, nvmax, u, t, n, w.hpart.p, kNblk, nb, s);
-        launch_reduce2(w.hpart.p, j, nvmax, kNblk, w.S.p, w.Z.p, nb, s);
-        if (!last) launch_hess_gemv(w.H.p, ldh, hstride, w.S.p, j, nvmax, nct, w.hg.p, nb, s);
-        launch_dcgs_col(w.H.p, ldh, hstride, w.S.p, w.Z.p, w.hg.p, nct, j, nvmax, w.scal.p, last ? 1 : 0,
-                        flex && !last ? w.Rf.p : nullptr, hstride, nb, s);
-        if (!last) launch_update2(V, ldv, j, nvmax, w.S.p, w.Z.p, u, t, n, w.upart.p, w.scal.p, nb, s);
-        steps = j;
-        if ((j % kSync != 0 || j == 0) && !last) continue;
-        // columns done_cols .. j-1 are final
-        const int c0 = done_cols, nc = j - done_cols;
-        if (nc <= 0) continue;
-        HIPCHK(hipMemcpy2DAsync(w.host, (size_t)2 * ldh * nc * sizeof(double), Hc(c0), (size_t)2 * hstride * sizeof(double),
-                                (size_t)2 * ldh * nc * sizeof(double), nb, hipMemcpyDeviceToHost, s));
-        sync(p);
+    // Givens rotations on final columns c0 .. c0+nc-1 held in w.host ([b][q][ldh] complex)
+    auto process = [&](int c0, int nc) {
         for (int b = 0; b < nb; ++b) {
             if (stop[b]) continue;
             const double* hb = w.host + (size_t)2 * ldh * nc * b;
@@ -709,8 +734,72 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
                 if (resid[b] <= tol[b] * beta[b] || hn == 0.0) { stop[b] = 1; --live; }
             }
         }
-        done_cols = j;
+    };
+
+    int j = 0, done_cols = 0;
+    if (live > 0) {
+        step(0);                           // step 0 (also makes every lazily allocated buffer exist)
+        j = 1;
     }
+    int batches = 0;
+    while (live > 0) {
+        if (j + kSync <= maxit) {
+            // short cycles never pay for the capture: the first kEagerBatches batches run eagerly
+            if (graph && batches++ >= kEagerBatches) {
+                if (!exec) {
+                    // capture on the private stream (the caller's may be the null stream, which cannot be
+                    // captured); every launch in batch() goes to p->stream and s, redirected meanwhile
+                    if (!p->capture) HIPCHK(hipStreamCreate(&p->capture));
+                    const hipStream_t caller = p->stream;
+                    struct Restore {
+                        mtf_problem p;
+                        hipStream_t& s;
+                        hipStream_t caller;
+                        ~Restore() { p->stream = caller; s = caller; }
+                    } restore{p, s, caller};
+                    p->stream = s = p->capture;
+                    hipGraph_t g = nullptr;
+                    HIPCHK(hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal));
+                    try {
+                        batch(j);
+                    } catch (...) {
+                        (void)hipStreamEndCapture(p->capture, &g);
+                        if (g) (void)hipGraphDestroy(g);
+                        throw;
+                    }
+                    HIPCHK(hipStreamEndCapture(p->capture, &g));
+                    const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(g);
+                    HIPCHK(e);
+                }
+                HIPCHK(hipGraphLaunch(exec, s));
+            } else {
+                batch(j);
+            }
+            j += kSync;
+            sync(p);
+            process(j - kSync - 1, kSync);
+            done_cols = j - 1;
+            continue;
+        }
+        // tail: the remaining steps one by one, then the step that only finalises column maxit-1
+        for (; j < maxit; ++j) step(j);
+        launch_dot2(V, ldv, jslot(maxit), nvmax, nullptr, n, w.hpart.p, kNblk, nb, s);
+        launch_reduce2(w.hpart.p, jslot(maxit), nvmax, kNblk, w.S.p, w.Z.p, nb, s);
+        launch_dcgs_col(w.H.p, ldh, hstride, w.S.p, w.Z.p, w.hg.p, nct, jslot(maxit), nvmax, w.scal.p, 1, nullptr,
+                        hstride, nb, s);
+        const int nc = maxit - done_cols;
+        if (nc > 0) {
+            HIPCHK(hipMemcpy2DAsync(w.host, (size_t)2 * ldh * nc * sizeof(double), Hc(done_cols),
+                                    (size_t)2 * hstride * sizeof(double), (size_t)2 * ldh * nc * sizeof(double), nb,
+                                    hipMemcpyDeviceToHost, s));
+            sync(p);
+            process(done_cols, nc);
+        }
+        done_cols = maxit;
+        break;
+    }
+    const int steps = j;
     // back substitution per right-hand side; flexible: coefficients R^-1 y on the zt basis (device)
     double* yh = w.hosty;
     std::fill(yh, yh + (size_t)2 * nb * (nvmax + 1), 0.0);
@@ -769,6 +858,8 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
     DeviceGuard g(p->device);
     const int pc = opts.preconditioner;
     const bool use_pc = pc != MTF_PREC_NONE;
+    if (opts.flags & ~MTF_SOLVE_EAGER) throw ArgError("unknown solve flags");
+    const bool graph = (opts.flags & MTF_SOLVE_EAGER) == 0;
     double t_pc = 0;
     if (use_pc && !p->have_tinv) { build_tinv(p); t_pc = p->t_precond; }
     // right-hand sides advance in lockstep batches when the products are GEMMs
@@ -816,7 +907,7 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
                 tol[b] = 0.9 * t;
             }
             if (all || outer == maxref || total >= maxit * (maxref + 1)) break;
-            total += gmres_cycle(p, w.r.p, X, ld, nb, prec, pc, tol, maxit, itv, est, reorth);
+            total += gmres_cycle(p, w.r.p, X, ld, nb, prec, pc, tol, maxit, itv, est, reorth, graph);
             for (int b = 0; b < nb; ++b) iters[b] += itv[b];
         }
         const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

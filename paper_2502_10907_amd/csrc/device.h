@@ -109,16 +109,22 @@ void launch_matvec_finish(const DomDesc* doms, int ndom, const int32_t* dof_dom,
 // GMRES vector kernels (complex128, length n), batched over nb right-hand sides in lockstep
 // (Krylov slab j at V + j*ldv with ldv = nb*n; column b of each slab is right-hand side b).
 // Kernels taking `flag` skip right-hand side b when flag[b] == 0.
-// Arnoldi step with delayed reorthogonalisation (DCGS2), nb right-hand sides in lockstep
-void launch_dot2(const double* V, int64_t ldv, int nv, int nvmax, const double* u, const double* t, int64_t n,
-                 double* hpart, int nblk, int nb, hipStream_t s);           // partial Q^H [u t], u^H [u t]
-void launch_reduce2(const double* hpart, int nv, int nvmax, int nblk, double* S, double* Z, int nb, hipStream_t s);
-void launch_hess_gemv(const double* H, int64_t ldh, int64_t hstride, const double* S, int nv, int nvmax, int nct,
+// Arnoldi step with delayed reorthogonalisation (DCGS2), nb right-hand sides in lockstep; the
+// step index j is read from jdev[0] on the device and the grids depend on nvmax only.
+void launch_dot2(const double* V, int64_t ldv, const int* jdev, int nvmax, const double* t, int64_t n, double* hpart,
+                 int nblk, int nb, hipStream_t s);                          // partial Q^H [u t], u^H [u t] (t null: t = u)
+void launch_reduce2(const double* hpart, const int* jdev, int nvmax, int nblk, double* S, double* Z, int nb,
+                    hipStream_t s);
+void launch_hess_gemv(const double* H, int64_t ldh, int64_t hstride, const double* S, const int* jdev, int nvmax, int nct,
                       double* hg, int nb, hipStream_t s);                   // partial Hbar s
 void launch_dcgs_col(double* H, int64_t ldh, int64_t hstride, const double* S, const double* Z, const double* hg, int nct,
-                     int nv, int nvmax, double* scal, int last, double* R, int64_t rstride, int nb, hipStream_t s);
-void launch_update2(const double* V, int64_t ldv, int nv, int nvmax, const double* S, const double* Z, double* u,
-                    double* t, int64_t n, double* part, const double* scal, int nb, hipStream_t s);
+                     const int* jdev, int nvmax, double* scal, int last, double* R, int64_t rstride, int nb, hipStream_t s);
+void launch_update2(const double* V, int64_t ldv, const int* jdev, int* jnext, int nvmax, const double* S,
+                    const double* Z, const double* t, double* unext, int64_t n, double* part, int ng, const double* scal,
+                    const double* zsrc, double* zdst, int nb, hipStream_t s);  // q_j, u_{j+1} (also unext); zsrc -> zdst slot j; *jnext = j+1
+void launch_set_int(int* p, int v, hipStream_t s);                         // p[0] = v
+void launch_stage_cols(const double* H, int64_t ldh, int64_t hstride, const int* jdev, int back, int cnt, double* Hst,
+                       int nb, hipStream_t s);                              // H columns j-back .. j-back+cnt-1
 void launch_trsv_upper(const double* R, int64_t ldh, int64_t rstride, const int* cnt, double* y, int64_t ystride,
                        int* info, int nb, hipStream_t s);                  // y_b = R_b^-1 y_b (upper, cnt[b])
 void launch_combine(double* x, int64_t ldx, const double* V, int64_t ldv, const int* cnt, int nvmax, const double* coef,
@@ -170,7 +176,8 @@ void launch_precond_finish(const DomDesc* doms, int ndom, const int32_t* dof_dom
 // w_i = v_i - sum_j G^ij z_j for the dofs in `list` (one block Gauss-Seidel stage)
 void launch_gs_residual(const DomDesc* doms, const int32_t* dof_dom, const int32_t* list, int64_t nlist,
                         const int32_t* dplus, const int32_t* dminus, const double* gval, const int64_t* gcol,
-                        const double* v, const double* z, double* w, hipStream_t s);
+                        const int32_t* other_dom, const int32_t* dom_stage, int stage, const double* v, const double* z,
+                        double* w, hipStream_t s);
 void launch_nonfinite_check(const float* A, int64_t n, int* flag, hipStream_t s);
 
 // Multi-RHS block products (gemm.hip).

@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_pc_dense(const DomDesc* __restrict__ do
     if (row >= E) return;
     float aD[2] = {0, 0}, aN[2] = {0, 0};
     const C2<float>* Tc = reinterpret_cast<const C2<float>*>(Ti) + dd.mat0 + row + (int64_t)c0 * E;
-#pragma unroll 4
+#pragma unroll 8
     for (int c = 0; c < nc; ++c) {
         const C2<float> a = Tc[(int64_t)c * E];
         aD[0] += a.re * xs[c][0] - a.im * xs[c][1]; aD[1] += a.re * xs[c][1] + a.im * xs[c][0];
@@ -231,6 +231,8 @@ __global__ __launch_bounds__(256) void k_gs_residual(const DomDesc* __restrict__
                                                      const int32_t* __restrict__ list, int64_t nlist,
                                                      const int32_t* __restrict__ dplus, const int32_t* __restrict__ dminus,
                                                      const double* __restrict__ gval, const int64_t* __restrict__ gcol,
+                                                     const int32_t* __restrict__ other_dom,
+                                                     const int32_t* __restrict__ dom_stage, int stage,
                                                      const double* __restrict__ v, const double* __restrict__ z,
                                                      double* __restrict__ w) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -243,6 +245,7 @@ __global__ __launch_bounds__(256) void k_gs_residual(const DomDesc* __restrict__
     for (int side = 0; side < 2; ++side) {
         const int32_t* pm = side == 0 ? dplus : dminus;
         const int64_t rec = dd.rec0 + pm[2 * g];
+        if (dom_stage[other_dom[rec]] >= stage) continue;      // neighbour not swept yet: its z is not set
         const int a = pm[2 * g + 1];
         for (int c = 0; c < 3; ++c) {
             const double gv = gval[9 * rec + 3 * a + c];
@@ -279,44 +282,51 @@ __device__ inline double wsum(double v) {
 // at V + j*ldv (ldv = nb*n), column b belongs to right-hand side b (blockIdx.z or blockIdx.y).
 // Per right-hand side b:  S, Z + b*(nvmax+1)  the coefficients (slot j holds alpha and gamma),
 // H + b*hstride  the Hessenberg matrix (column-major, ld ldh),  scal + 4b  {nu, Re c, Im c}.
+// The step index j is read from device memory (jdev[0]) by every kernel of a step, and the grids
+// do not depend on it, so a captured sequence of steps can be replayed.
 
 // hpart[((b*(nvmax+1) + i)*nblk + blk)*4 + {0,1,2,3}] = partial {conj(v_i).u, conj(v_i).t},
-// v_i = V_i for i < nv and v_nv = u.
-__global__ __launch_bounds__(256) void k_dot2(const double* __restrict__ V, int64_t ldv, int nv, int nvmax,
-                                              const double* __restrict__ U, const double* __restrict__ Tt, int64_t n,
+// v_i = V_i for i < j and v_j = u = V_j; t = Tt (slab, ld n), or u itself when Tt is null.
+// blockIdx.y strides over the vectors.
+__global__ __launch_bounds__(256) void k_dot2(const double* __restrict__ V, int64_t ldv, const int* __restrict__ jdev,
+                                              int nvmax, const double* __restrict__ Tt, int64_t n,
                                               double* __restrict__ hpart, int nblk) {
+    const int nv = jdev[0];
     const int b = blockIdx.z;
-    const int i = blockIdx.y;
     const int blk = blockIdx.x;
     const int64_t chunk = (n + nblk - 1) / nblk;
     const int64_t lo = blk * chunk, hi = min(n, lo + chunk);
-    const double* u = U + 2 * (int64_t)b * n;
-    const double* t = Tt + 2 * (int64_t)b * n;
-    const double* v = (i == nv) ? u : V + 2 * ((int64_t)i * ldv + (int64_t)b * n);
-    double ur = 0, ui = 0, tr = 0, ti = 0;
-    for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-        const double vr = v[2 * e], vi = v[2 * e + 1];
-        const double a = u[2 * e], c = u[2 * e + 1], d = t[2 * e], f = t[2 * e + 1];
-        ur += vr * a + vi * c;
-        ui += vr * c - vi * a;
-        tr += vr * d + vi * f;
-        ti += vr * f - vi * d;
-    }
+    const double* u = V + 2 * ((int64_t)nv * ldv + (int64_t)b * n);
+    const double* t = Tt ? Tt + 2 * (int64_t)b * n : u;
     __shared__ double red[4][4];
-    ur = wsum(ur); ui = wsum(ui); tr = wsum(tr); ti = wsum(ti);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) { red[0][wv] = ur; red[1][wv] = ui; red[2][wv] = tr; red[3][wv] = ti; }
-    __syncthreads();
-    if (threadIdx.x < 4) {
-        double acc = 0;
-        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) acc += red[threadIdx.x][k];
-        hpart[(((int64_t)b * (nvmax + 1) + i) * nblk + blk) * 4 + threadIdx.x] = acc;
+    for (int i = blockIdx.y; i <= nv; i += gridDim.y) {
+        const double* v = V + 2 * ((int64_t)i * ldv + (int64_t)b * n);
+        double ur = 0, ui = 0, tr = 0, ti = 0;
+        for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+            const double vr = v[2 * e], vi = v[2 * e + 1];
+            const double a = u[2 * e], c = u[2 * e + 1], d = t[2 * e], f = t[2 * e + 1];
+            ur += vr * a + vi * c;
+            ui += vr * c - vi * a;
+            tr += vr * d + vi * f;
+            ti += vr * f - vi * d;
+        }
+        ur = wsum(ur); ui = wsum(ui); tr = wsum(tr); ti = wsum(ti);
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        if (lane == 0) { red[0][wv] = ur; red[1][wv] = ui; red[2][wv] = tr; red[3][wv] = ti; }
+        __syncthreads();
+        if (threadIdx.x < 4) {
+            double acc = 0;
+            for (int k = 0; k < (int)(blockDim.x >> 6); ++k) acc += red[threadIdx.x][k];
+            hpart[(((int64_t)b * (nvmax + 1) + i) * nblk + blk) * 4 + threadIdx.x] = acc;
+        }
+        __syncthreads();
     }
 }
 
-// S_i, Z_i from the partial sums, i <= nv
-__global__ void k_reduce2(const double* __restrict__ hpart, int nv, int nvmax, int nblk, double* __restrict__ S,
-                          double* __restrict__ Z) {
+// S_i, Z_i from the partial sums, i <= j
+__global__ void k_reduce2(const double* __restrict__ hpart, const int* __restrict__ jdev, int nvmax, int nblk,
+                          double* __restrict__ S, double* __restrict__ Z) {
+    const int nv = jdev[0];
     const int b = blockIdx.y;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i > nv) return;
@@ -329,54 +339,62 @@ __global__ void k_reduce2(const double* __restrict__ hpart, int nv, int nvmax, i
     Z[2 * o] = a[2]; Z[2 * o + 1] = a[3];
 }
 
-// Partial products of the stored Hessenberg columns 0..nv-1 with s: tile (row block rt of 64 rows,
+// Partial products of the stored Hessenberg columns 0..j-1 with s: tile (row block rt of 64 rows,
 // column block kc of 64 columns) -> hg[(b*nct + kc)*(nvmax+1) + i].  Only entries i <= k+1 count;
-// row nv of column nv-1 is not final yet and is left out (k_dcgs_col adds its share).  Tiles with
-// rt > kc + 1 lie below the band: they are neither written nor read.
+// row j of column j-1 is not final yet and is left out (k_dcgs_col adds its share).  Tiles with
+// rt > kc + 1 lie below the band: they are neither written nor read.  blockIdx.x strides over the
+// tiles of the (rt, kc) grid.
 __global__ __launch_bounds__(256) void k_hess_gemv(const double* __restrict__ H, int64_t ldh, int64_t hstride,
-                                                   const double* __restrict__ S, int nv, int nvmax, int nct,
-                                                   double* __restrict__ hg) {
+                                                   const double* __restrict__ S, const int* __restrict__ jdev, int nvmax,
+                                                   int nct, double* __restrict__ hg) {
+    const int nv = jdev[0];
+    if (nv < 1) return;
     const int b = blockIdx.z;
-    const int rt = blockIdx.x, kc = blockIdx.y;
-    if (rt > kc + 1) return;
+    const int nrt = (nv + 1 + 63) / 64, nkc = (nv + 63) / 64;
     const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int i = rt * 64 + r;
     const double* Hb = H + 2 * (int64_t)b * hstride;
     const double* sb = S + 2 * (int64_t)b * (nvmax + 1);
-    double re = 0, im = 0;
-    const int k0 = kc * 64 + q * 16;
-    if (i <= nv) {
-#pragma unroll 4
-        for (int kk = 0; kk < 16; ++kk) {
-            const int k = k0 + kk;
-            if (k >= nv || i > k + 1 || (k == nv - 1 && i == nv)) continue;
-            const double hr = Hb[2 * ((int64_t)k * ldh + i)], hi = Hb[2 * ((int64_t)k * ldh + i) + 1];
-            const double sr = sb[2 * k], si = sb[2 * k + 1];
-            re += hr * sr - hi * si;
-            im += hr * si + hi * sr;
-        }
-    }
     __shared__ double red[4][64][2];
-    red[q][r][0] = re;
-    red[q][r][1] = im;
-    __syncthreads();
-    if (q == 0 && i <= nv) {
-        const double a = red[0][r][0] + red[1][r][0] + red[2][r][0] + red[3][r][0];
-        const double c = red[0][r][1] + red[1][r][1] + red[2][r][1] + red[3][r][1];
-        const int64_t o = ((int64_t)b * nct + kc) * (nvmax + 1) + i;
-        hg[2 * o] = a;
-        hg[2 * o + 1] = c;
+    for (int tile = blockIdx.x; tile < nrt * nkc; tile += gridDim.x) {
+        const int rt = tile % nrt, kc = tile / nrt;
+        if (rt > kc + 1) continue;
+        const int i = rt * 64 + r;
+        double re = 0, im = 0;
+        const int k0 = kc * 64 + q * 16;
+        if (i <= nv) {
+#pragma unroll 4
+            for (int kk = 0; kk < 16; ++kk) {
+                const int k = k0 + kk;
+                if (k >= nv || i > k + 1 || (k == nv - 1 && i == nv)) continue;
+                const double hr = Hb[2 * ((int64_t)k * ldh + i)], hi = Hb[2 * ((int64_t)k * ldh + i) + 1];
+                const double sr = sb[2 * k], si = sb[2 * k + 1];
+                re += hr * sr - hi * si;
+                im += hr * si + hi * sr;
+            }
+        }
+        red[q][r][0] = re;
+        red[q][r][1] = im;
+        __syncthreads();
+        if (q == 0 && i <= nv) {
+            const double a = red[0][r][0] + red[1][r][0] + red[2][r][0] + red[3][r][0];
+            const double c = red[0][r][1] + red[1][r][1] + red[2][r][1] + red[3][r][1];
+            const int64_t o = ((int64_t)b * nct + kc) * (nvmax + 1) + i;
+            hg[2 * o] = a;
+            hg[2 * o + 1] = c;
+        }
+        __syncthreads();
     }
 }
 
-// nu, c; finalise Hessenberg column nv-1; first-pass column nv (skipped when `last`).
-// When R is given, column nv of the triangular factor U = Q R of the candidates is stored too:
-// R[i, nv] = s_i (i < nv), R[nv, nv] = nu (per right-hand side at R + b*rstride, ld ldh).
+// nu, c; finalise Hessenberg column j-1; first-pass column j (skipped when `last`).
+// When R is given, column j of the triangular factor U = Q R of the candidates is stored too:
+// R[i, j] = s_i (i < j), R[j, j] = nu (per right-hand side at R + b*rstride, ld ldh).
 __global__ __launch_bounds__(256) void k_dcgs_col(double* __restrict__ H, int64_t ldh, int64_t hstride,
                                                   const double* __restrict__ S, const double* __restrict__ Z,
-                                                  const double* __restrict__ hg, int nct, int nv, int nvmax,
-                                                  double* __restrict__ scal, int last, double* __restrict__ R,
+                                                  const double* __restrict__ hg, int nct, const int* __restrict__ jdev,
+                                                  int nvmax, double* __restrict__ scal, int last, double* __restrict__ R,
                                                   int64_t rstride) {
+    const int nv = jdev[0];
     const int b = blockIdx.y;
     const double* sb = S + 2 * (int64_t)b * (nvmax + 1);
     const double* zb = Z + 2 * (int64_t)b * (nvmax + 1);
@@ -422,7 +440,7 @@ __global__ __launch_bounds__(256) void k_dcgs_col(double* __restrict__ H, int64_
             hr += hg[2 * o];
             hi += hg[2 * o + 1];
         }
-        // column nv-1 changed after the partial products: + (s_i or nu) * s_{nv-1}
+        // column j-1 changed after the partial products: + (s_i or nu) * s_{j-1}
         const double lr = sb[2 * (nv - 1)], li = sb[2 * (nv - 1) + 1];
         const double fr = i < nv ? sb[2 * i] : nu, fi = i < nv ? sb[2 * i + 1] : 0.0;
         hr += fr * lr - fi * li;
@@ -434,74 +452,109 @@ __global__ __launch_bounds__(256) void k_dcgs_col(double* __restrict__ H, int64_
     Hn[2 * i + 1] = (zi - hi) * inv;
 }
 
-// part[((b*nch + c)*n + e)*4 + {0..3}] = sum over the 64 vectors of chunk c of {V_i s_i, V_i z_i}
-__global__ __launch_bounds__(256) void k_update2_part(const double* __restrict__ V, int64_t ldv, int nv, int nvmax,
+// part[((b*ng + g)*n + e)*4 + {0..3}] = sum over the chunks c = g, g+ng, ... of 64 vectors of
+// {V_i s_i, V_i z_i}, i < j (zero when a group has no chunk).
+__global__ __launch_bounds__(256) void k_update2_part(const double* __restrict__ V, int64_t ldv,
+                                                      const int* __restrict__ jdev, int nvmax,
                                                       const double* __restrict__ S, const double* __restrict__ Z,
                                                       double* __restrict__ part, int64_t n) {
+    const int nv = jdev[0];
     const int b = blockIdx.z;
     __shared__ double cs[4 * 64];
-    const int c = blockIdx.y;
-    const int nch = gridDim.y;
-    const int i0 = c * 64;
-    const int cnt = min(64, nv - i0);
-    const int64_t cb = (int64_t)b * (nvmax + 1);
-    if ((int)threadIdx.x < cnt) {
-        const int64_t o = cb + i0 + threadIdx.x;
-        cs[4 * threadIdx.x] = S[2 * o]; cs[4 * threadIdx.x + 1] = S[2 * o + 1];
-        cs[4 * threadIdx.x + 2] = Z[2 * o]; cs[4 * threadIdx.x + 3] = Z[2 * o + 1];
-    }
-    __syncthreads();
+    const int g = blockIdx.y, ng = gridDim.y;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
+    const int64_t cb = (int64_t)b * (nvmax + 1);
     double ar = 0, ai = 0, br = 0, bi = 0;
-    const double* v = V + 2 * ((int64_t)i0 * ldv + (int64_t)b * n + e);
-    int i = 0;
-    for (; i + 8 <= cnt; i += 8) {
-        double vr[8], vi[8];
+    for (int i0 = g * 64; i0 < nv; i0 += ng * 64) {
+        const int cnt = min(64, nv - i0);
+        __syncthreads();
+        if ((int)threadIdx.x < cnt) {
+            const int64_t o = cb + i0 + threadIdx.x;
+            cs[4 * threadIdx.x] = S[2 * o]; cs[4 * threadIdx.x + 1] = S[2 * o + 1];
+            cs[4 * threadIdx.x + 2] = Z[2 * o]; cs[4 * threadIdx.x + 3] = Z[2 * o + 1];
+        }
+        __syncthreads();
+        if (e >= n) continue;
+        const double* v = V + 2 * ((int64_t)i0 * ldv + (int64_t)b * n + e);
+        int i = 0;
+        for (; i + 8 <= cnt; i += 8) {
+            double vr[8], vi[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) { vr[k] = v[2 * (int64_t)(i + k) * ldv]; vi[k] = v[2 * (int64_t)(i + k) * ldv + 1]; }
+            for (int k = 0; k < 8; ++k) { vr[k] = v[2 * (int64_t)(i + k) * ldv]; vi[k] = v[2 * (int64_t)(i + k) * ldv + 1]; }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const double* q = cs + 4 * (i + k);
-            ar += vr[k] * q[0] - vi[k] * q[1];
-            ai += vr[k] * q[1] + vi[k] * q[0];
-            br += vr[k] * q[2] - vi[k] * q[3];
-            bi += vr[k] * q[3] + vi[k] * q[2];
+            for (int k = 0; k < 8; ++k) {
+                const double* q = cs + 4 * (i + k);
+                ar += vr[k] * q[0] - vi[k] * q[1];
+                ai += vr[k] * q[1] + vi[k] * q[0];
+                br += vr[k] * q[2] - vi[k] * q[3];
+                bi += vr[k] * q[3] + vi[k] * q[2];
+            }
+        }
+        for (; i < cnt; ++i) {
+            const double vr = v[2 * (int64_t)i * ldv], vi = v[2 * (int64_t)i * ldv + 1];
+            const double* q = cs + 4 * i;
+            ar += vr * q[0] - vi * q[1];
+            ai += vr * q[1] + vi * q[0];
+            br += vr * q[2] - vi * q[3];
+            bi += vr * q[3] + vi * q[2];
         }
     }
-    for (; i < cnt; ++i) {
-        const double vr = v[2 * (int64_t)i * ldv], vi = v[2 * (int64_t)i * ldv + 1];
-        const double* q = cs + 4 * i;
-        ar += vr * q[0] - vi * q[1];
-        ai += vr * q[1] + vi * q[0];
-        br += vr * q[2] - vi * q[3];
-        bi += vr * q[3] + vi * q[2];
-    }
-    double* o = part + (((int64_t)b * nch + c) * n + e) * 4;
+    if (e >= n) return;
+    double* o = part + (((int64_t)b * ng + g) * n + e) * 4;
     o[0] = ar; o[1] = ai; o[2] = br; o[3] = bi;
 }
 
-// q_j = (u - Q s)/nu into slot U, u' = (t - Q z - q_j c)/nu into slot Tt (in place over t)
-__global__ __launch_bounds__(256) void k_update2_apply(const double* __restrict__ part, int nch, double* __restrict__ U,
-                                                       double* __restrict__ Tt, int64_t n, const double* __restrict__ scal) {
+// q_j = (u - Q s)/nu into slot j, u' = (t - Q z - q_j c)/nu into slot j+1 and into Unext; when Zsrc
+// is given it is also copied into slot j of Zdst (the preconditioned candidate of flexible GMRES).
+__global__ __launch_bounds__(256) void k_update2_apply(const double* __restrict__ part, int ng, double* __restrict__ V,
+                                                       int64_t ldv, const int* __restrict__ jdev, int* __restrict__ jnext,
+                                                       const double* __restrict__ Tt, double* __restrict__ Unext,
+                                                       int64_t n, const double* __restrict__ scal,
+                                                       const double* __restrict__ Zsrc, double* __restrict__ Zdst) {
+    const int nv = jdev[0];
     const int b = blockIdx.y;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0 && b == 0) jnext[0] = nv + 1;      // the other slot: read by the next step only
     if (e >= n) return;
     double ar = 0, ai = 0, br = 0, bi = 0;
-    for (int c = 0; c < nch; ++c) {
-        const double* p = part + (((int64_t)b * nch + c) * n + e) * 4;
+    for (int g = 0; g < ng; ++g) {
+        const double* p = part + (((int64_t)b * ng + g) * n + e) * 4;
         ar += p[0]; ai += p[1]; br += p[2]; bi += p[3];
     }
     const double nu = scal[4 * b], cr = scal[4 * b + 1], ci = scal[4 * b + 2];
     const double inv = nu > 0 ? 1.0 / nu : 0.0;
-    double* u = U + 2 * ((int64_t)b * n + e);
-    double* t = Tt + 2 * ((int64_t)b * n + e);
+    double* u = V + 2 * ((int64_t)nv * ldv + (int64_t)b * n + e);
+    double* un = V + 2 * ((int64_t)(nv + 1) * ldv + (int64_t)b * n + e);
+    const double* t = Tt + 2 * ((int64_t)b * n + e);
     const double qr = (u[0] - ar) * inv, qi = (u[1] - ai) * inv;
     u[0] = qr;
     u[1] = qi;
-    const double tr = t[0] - br - (qr * cr - qi * ci), ti = t[1] - bi - (qr * ci + qi * cr);
-    t[0] = tr * inv;
-    t[1] = ti * inv;
+    const double tr = (t[0] - br - (qr * cr - qi * ci)) * inv, ti = (t[1] - bi - (qr * ci + qi * cr)) * inv;
+    un[0] = tr;
+    un[1] = ti;
+    Unext[2 * ((int64_t)b * n + e)] = tr;
+    Unext[2 * ((int64_t)b * n + e) + 1] = ti;
+    if (Zsrc) {
+        const double* zs = Zsrc + 2 * ((int64_t)b * n + e);
+        double* zd = Zdst + 2 * ((int64_t)nv * ldv + (int64_t)b * n + e);
+        zd[0] = zs[0];
+        zd[1] = zs[1];
+    }
+}
+
+// p[0] = v
+__global__ void k_set_int(int* p, int v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
+}
+
+// Hst[(b*cnt + q)*ldh + i] = H column (jdev[0] - back + q) of right-hand side b, rows 0..ldh-1
+__global__ void k_stage_cols(const double* __restrict__ H, int64_t ldh, int64_t hstride, const int* __restrict__ jdev,
+                             int back, int cnt, double* __restrict__ Hst) {
+    const int b = blockIdx.y;
+    const int64_t c0 = jdev[0] - back;
+    const int64_t tot = 2 * ldh * cnt;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x)
+        Hst[(int64_t)b * tot + e] = H[2 * ((int64_t)b * hstride + c0 * ldh) + e];
 }
 
 // Back substitution y_b <- R_b^-1 y_b with the upper triangular cnt[b] x cnt[b] factor R_b
@@ -875,44 +928,58 @@ void launch_precond_finish(const DomDesc* doms, int /*ndom*/, const int32_t* dof
 
 void launch_gs_residual(const DomDesc* doms, const int32_t* dof_dom, const int32_t* list, int64_t nlist,
                         const int32_t* dplus, const int32_t* dminus, const double* gval, const int64_t* gcol,
-                        const double* v, const double* z, double* w, hipStream_t s) {
+                        const int32_t* other_dom, const int32_t* dom_stage, int stage, const double* v, const double* z,
+                        double* w, hipStream_t s) {
     if (nlist <= 0) return;
     hipLaunchKernelGGL(k_gs_residual, dim3(gridn(nlist, 256)), dim3(256), 0, s, doms, dof_dom, list, nlist, dplus, dminus,
-                       gval, gcol, v, z, w);
+                       gval, gcol, other_dom, dom_stage, stage, v, z, w);
 }
 
-void launch_dot2(const double* V, int64_t ldv, int nv, int nvmax, const double* u, const double* t, int64_t n,
-                 double* hpart, int nblk, int nb, hipStream_t s) {
-    hipLaunchKernelGGL(k_dot2, dim3((unsigned)nblk, (unsigned)(nv + 1), (unsigned)nb), dim3(256), 0, s, V, ldv, nv, nvmax,
-                       u, t, n, hpart, nblk);
+void launch_dot2(const double* V, int64_t ldv, const int* jdev, int nvmax, const double* t, int64_t n, double* hpart,
+                 int nblk, int nb, hipStream_t s) {
+    const int gy = std::min(nvmax + 1, 512);
+    hipLaunchKernelGGL(k_dot2, dim3((unsigned)nblk, (unsigned)gy, (unsigned)nb), dim3(256), 0, s, V, ldv, jdev, nvmax, t,
+                       n, hpart, nblk);
 }
 
-void launch_reduce2(const double* hpart, int nv, int nvmax, int nblk, double* S, double* Z, int nb, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce2, dim3(gridn(nv + 1, 128), (unsigned)nb), dim3(128), 0, s, hpart, nv, nvmax, nblk, S, Z);
+void launch_reduce2(const double* hpart, const int* jdev, int nvmax, int nblk, double* S, double* Z, int nb,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce2, dim3(gridn(nvmax + 1, 128), (unsigned)nb), dim3(128), 0, s, hpart, jdev, nvmax, nblk,
+                       S, Z);
 }
 
-void launch_hess_gemv(const double* H, int64_t ldh, int64_t hstride, const double* S, int nv, int nvmax, int nct,
+void launch_hess_gemv(const double* H, int64_t ldh, int64_t hstride, const double* S, const int* jdev, int nvmax, int nct,
                       double* hg, int nb, hipStream_t s) {
-    if (nv < 1) return;
-    const int nrt = (nv + 1 + 63) / 64, nkc = (nv + 63) / 64;
-    hipLaunchKernelGGL(k_hess_gemv, dim3((unsigned)nrt, (unsigned)nkc, (unsigned)nb), dim3(256), 0, s, H, ldh, hstride, S,
-                       nv, nvmax, nct, hg);
+    const int tiles = ((nvmax + 1 + 63) / 64) * ((nvmax + 63) / 64);
+    const int gx = std::max(1, std::min(tiles, 256));
+    hipLaunchKernelGGL(k_hess_gemv, dim3((unsigned)gx, 1, (unsigned)nb), dim3(256), 0, s, H, ldh, hstride, S, jdev, nvmax,
+                       nct, hg);
 }
 
 void launch_dcgs_col(double* H, int64_t ldh, int64_t hstride, const double* S, const double* Z, const double* hg, int nct,
-                     int nv, int nvmax, double* scal, int last, double* R, int64_t rstride, int nb, hipStream_t s) {
-    hipLaunchKernelGGL(k_dcgs_col, dim3(gridn(nv + 1, 256), (unsigned)nb), dim3(256), 0, s, H, ldh, hstride, S, Z, hg, nct,
-                       nv, nvmax, scal, last, R, rstride);
+                     const int* jdev, int nvmax, double* scal, int last, double* R, int64_t rstride, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(k_dcgs_col, dim3(gridn(nvmax + 1, 256), (unsigned)nb), dim3(256), 0, s, H, ldh, hstride, S, Z, hg,
+                       nct, jdev, nvmax, scal, last, R, rstride);
 }
 
-void launch_update2(const double* V, int64_t ldv, int nv, int nvmax, const double* S, const double* Z, double* u,
-                    double* t, int64_t n, double* part, const double* scal, int nb, hipStream_t s) {
-    const int nch = (nv + 63) / 64;
-    if (nch > 0)
-        hipLaunchKernelGGL(k_update2_part, dim3(gridn(n, 256), (unsigned)nch, (unsigned)nb), dim3(256), 0, s, V, ldv, nv,
-                           nvmax, S, Z, part, n);
-    hipLaunchKernelGGL(k_update2_apply, dim3(gridn(n, 256), (unsigned)nb), dim3(256), 0, s, part, nch, u, t, n, scal);
+void launch_update2(const double* V_, int64_t ldv, const int* jdev, int* jnext, int nvmax, const double* S,
+                    const double* Z, const double* t, double* unext, int64_t n, double* part, int ng, const double* scal,
+                    const double* zsrc, double* zdst, int nb, hipStream_t s) {
+    double* V = const_cast<double*>(V_);
+    hipLaunchKernelGGL(k_update2_part, dim3(gridn(n, 256), (unsigned)ng, (unsigned)nb), dim3(256), 0, s, V, ldv, jdev,
+                       nvmax, S, Z, part, n);
+    hipLaunchKernelGGL(k_update2_apply, dim3(gridn(n, 256), (unsigned)nb), dim3(256), 0, s, part, ng, V, ldv, jdev,
+                       jnext, t, unext, n, scal, zsrc, zdst);
 }
+
+void launch_set_int(int* p, int v, hipStream_t s) { hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, p, v); }
+
+void launch_stage_cols(const double* H, int64_t ldh, int64_t hstride, const int* jdev, int back, int cnt, double* Hst,
+                       int nb, hipStream_t s) {
+    hipLaunchKernelGGL(k_stage_cols, dim3(gridn(2 * ldh * cnt, 256), (unsigned)nb), dim3(256), 0, s, H, ldh, hstride, jdev,
+                       back, cnt, Hst);
+}
+
 
 void launch_trsv_upper(const double* R, int64_t ldh, int64_t rstride, const int* cnt, double* y, int64_t ystride,
                        int* info, int nb, hipStream_t s) {
