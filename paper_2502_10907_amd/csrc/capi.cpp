@@ -10,6 +10,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "device.h"
@@ -79,8 +80,12 @@ struct mtf_problem_s {
     DevBuf<DomDesc> d_doms;
     DevBuf<double> d_gval;
     DevBuf<int64_t> d_gcol;
-    DevBuf<int4> d_tiles, d_mtiles;
-    int64_t ntiles = 0, nmtiles = 0;
+    DevBuf<int4> d_tiles, d_mtiles, d_symtiles;
+    int64_t ntiles = 0, nmtiles = 0, nsymtiles = 0;
+    DevBuf<int64_t> d_near_ptr;      // touching-pair lower-triangle pattern (CSR over dofs)
+    DevBuf<int32_t> d_near_col;
+    DevBuf<double> near64, near32;   // corrections A[m,n] - A[n,m] for T, K from the FP64 / FP32 blocks
+    int64_t near_nnz = 0;
     DevBuf<SingPair> d_sing;
     DevBuf<double> d_ss;
     DevBuf<int32_t> d_ss_meta;   // off[4], cnt[4]
@@ -145,7 +150,7 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
         rec += d.T;
         dof += d.E;
         mat += (int64_t)d.E * d.E;
-        part += (int64_t)dd.nchunk * 2 * d.E;
+        part += (int64_t)(dd.nchunk + 1) * 2 * d.E;    // nchunk + 1 slots: symmetric-read product
     }
     std::vector<int32_t> verts(3 * rec), tdof(3 * rec), other_rec(rec), other_dom(rec), rec_dom(rec);
     std::vector<int8_t> tsign(3 * rec);
@@ -172,7 +177,7 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
             dof_dom[f0 + m] = i;
         }
     }
-    std::vector<int4> tiles, mtiles;
+    std::vector<int4> tiles, mtiles, symtiles;
     for (int i = 0; i <= M; ++i) {
         const int T = sk.dom[i].T;
         for (int x0 = 0; x0 < T; x0 += kTile)
@@ -180,6 +185,35 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
         const int E = sk.dom[i].E;
         for (int c = 0; c < doms[i].nchunk; ++c)
             for (int r0 = 0; r0 < E; r0 += kRows) mtiles.push_back(make_int4(i, r0, c, 0));
+        for (int bi = 0; bi < doms[i].nchunk; ++bi)
+            for (int bj = bi; bj < doms[i].nchunk; ++bj) symtiles.push_back(make_int4(i, bi, bj, 0));
+    }
+    // touching-pair pattern of the strictly lower triangle: (m, n), n < m, whose supports share a
+    // vertex (CSR over the global dof index, local column n)
+    std::vector<int64_t> nearptr(dof + 1, 0);
+    std::vector<int32_t> nearcol;
+    for (int i = 0; i <= M; ++i) {
+        const Domain& d = sk.dom[i];
+        std::unordered_map<int32_t, std::vector<int32_t>> vtri;        // global vertex -> local triangles
+        for (int lt = 0; lt < d.T; ++lt)
+            for (int a = 0; a < 3; ++a) vtri[d.verts[3 * lt + a]].push_back(lt);
+        std::vector<int32_t> cols;
+        for (int m = 0; m < d.E; ++m) {
+            cols.clear();
+            for (int side = 0; side < 2; ++side) {
+                const int lt = side == 0 ? d.plus[2 * m] : d.minus[2 * m];
+                for (int a = 0; a < 3; ++a)
+                    for (int t2 : vtri[d.verts[3 * lt + a]])
+                        for (int b = 0; b < 3; ++b) {
+                            const int n = d.tri_dof[3 * t2 + b];
+                            if (n < m) cols.push_back(n);
+                        }
+            }
+            std::sort(cols.begin(), cols.end());
+            cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+            nearcol.insert(nearcol.end(), cols.begin(), cols.end());
+            nearptr[doms[i].dof0 + m + 1] = (int64_t)nearcol.size();
+        }
     }
     // greedy colouring of subdomains 1..M (adjacent subdomains get different colours); stage 0 is Omega_0
     std::vector<int> colour(M + 1, -1);
@@ -230,6 +264,13 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
     p->d_dof_dom.upload(dof_dom, s);
     p->d_tiles.upload(tiles, s);
     p->d_mtiles.upload(mtiles, s);
+    p->d_symtiles.upload(symtiles, s);
+    p->nsymtiles = (int64_t)symtiles.size();
+    p->d_near_ptr.upload(nearptr, s);
+    p->d_near_col.upload(nearcol, s);
+    p->near_nnz = (int64_t)nearcol.size();
+    p->near64.reset();
+    p->near32.reset();
     p->d_sing.upload(sing, s);
     p->d_stage_tiles.upload(stiles, s);
     p->d_dom_stage.upload(colour, s);
@@ -309,6 +350,18 @@ void assemble_prepare(mtf_problem p, int prec) {
     p->gp.haveA = false;
 }
 
+// Touching-pair corrections of the lower triangle for the blocks of `prec` (after their assembly).
+void near_corrections(mtf_problem p, int prec) {
+    DevBuf<double>& out = prec == MTF_FP64 ? p->near64 : p->near32;
+    out.alloc(4 * std::max<int64_t>(p->near_nnz, 1));
+    if (prec == MTF_FP64)
+        launch_near_diff_f64(p->d_doms.p, p->d_dof_dom.p, p->ndof, p->d_near_ptr.p, p->d_near_col.p, p->T64.p, p->K64.p,
+                             out.p, p->stream);
+    else
+        launch_near_diff_f32(p->d_doms.p, p->d_dof_dom.p, p->ndof, p->d_near_ptr.p, p->d_near_col.p, p->T32.p, p->K32.p,
+                             out.p, p->stream);
+}
+
 void assemble_impl(mtf_problem p, const mtf_assembly_opts* o) {
     if (!p->has_mesh || !p->has_mat) throw StateError("mtf_assemble needs mtf_set_mesh and mtf_set_materials first");
     int prec, order;
@@ -337,6 +390,7 @@ void assemble_impl(mtf_problem p, const mtf_assembly_opts* o) {
         launch_singular(p->d_sing.p, (int64_t)p->d_sing.n, p->d_doms.p, p->d_geom.p, p->d_xyz.p, p->d_verts.p,
                         p->d_tdof.p, p->d_tsign.p, p->d_ss.p, meta, meta + 4, nullptr, nullptr, p->T32.p, p->K32.p, s);
     }
+    near_corrections(p, prec);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(p->ev1, s));
     if (prec == MTF_FP64) p->have64 = true; else { p->have32 = true; p->gm.haveA = false; }
@@ -423,11 +477,12 @@ void matvec_gemm(mtf_problem p, int nrhs, const double* x, int64_t ld, double* y
 void matvec1(mtf_problem p, const double* x, double* y, int prec) {
     hipStream_t s = p->stream;
     if (prec == MTF_FP64)
-        launch_matvec_dense_f64(p->d_doms.p, p->d_mtiles.p, p->nmtiles, p->T64.p, p->K64.p, x, p->part.p, s);
+        launch_matvec_sym_f64(p->d_doms.p, p->d_symtiles.p, p->nsymtiles, p->T64.p, p->K64.p, x, p->part.p, s);
     else
-        launch_matvec_dense_f32(p->d_doms.p, p->d_mtiles.p, p->nmtiles, p->T32.p, p->K32.p, x, p->part.p, s);
-    launch_matvec_finish(p->d_doms.p, (int)p->doms.size(), p->d_dof_dom.p, p->ndof, p->d_dplus.p, p->d_dminus.p,
-                         p->d_gval.p, p->d_gcol.p, p->part.p, x, y, s);
+        launch_matvec_sym_f32(p->d_doms.p, p->d_symtiles.p, p->nsymtiles, p->T32.p, p->K32.p, x, p->part.p, s);
+    launch_matvec_sym_finish(p->d_doms.p, p->d_dof_dom.p, p->ndof, p->d_dplus.p, p->d_dminus.p, p->d_gval.p,
+                             p->d_gcol.p, p->d_near_ptr.p, p->d_near_col.p,
+                             prec == MTF_FP64 ? p->near64.p : p->near32.p, p->part.p, x, y, s);
 }
 
 void precond1(mtf_problem p, const double* x, double* z) {
@@ -1215,12 +1270,13 @@ int mtf_time_matvec(mtf_problem p, int32_t precision, int32_t reps, const void* 
         for (int r = 0; r < reps; ++r) {
             HIPCHK(hipEventRecord(ev[3 * r], s));
             if (precision == MTF_FP64)
-                launch_matvec_dense_f64(p->d_doms.p, p->d_mtiles.p, p->nmtiles, p->T64.p, p->K64.p, x, p->part.p, s);
+                launch_matvec_sym_f64(p->d_doms.p, p->d_symtiles.p, p->nsymtiles, p->T64.p, p->K64.p, x, p->part.p, s);
             else
-                launch_matvec_dense_f32(p->d_doms.p, p->d_mtiles.p, p->nmtiles, p->T32.p, p->K32.p, x, p->part.p, s);
+                launch_matvec_sym_f32(p->d_doms.p, p->d_symtiles.p, p->nsymtiles, p->T32.p, p->K32.p, x, p->part.p, s);
             HIPCHK(hipEventRecord(ev[3 * r + 1], s));
-            launch_matvec_finish(p->d_doms.p, (int)p->doms.size(), p->d_dof_dom.p, p->ndof, p->d_dplus.p, p->d_dminus.p,
-                                 p->d_gval.p, p->d_gcol.p, p->part.p, x, y, s);
+            launch_matvec_sym_finish(p->d_doms.p, p->d_dof_dom.p, p->ndof, p->d_dplus.p, p->d_dminus.p, p->d_gval.p,
+                                     p->d_gcol.p, p->d_near_ptr.p, p->d_near_col.p,
+                                     precision == MTF_FP64 ? p->near64.p : p->near32.p, p->part.p, x, y, s);
             HIPCHK(hipEventRecord(ev[3 * r + 2], s));
         }
         HIPCHK(hipGetLastError());
@@ -1387,7 +1443,9 @@ double batch_launch(mtf_batch b, int prec, int grid) {
                                meta, meta + 4, grid, s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(b->e1, s));
-    HIPCHK(hipEventSynchronize(b->e1));
+    for (mtf_problem p : b->probs) near_corrections(p, prec);    // same stream, after the blocks
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, b->e0, b->e1));
     return ms * 1e-3;

@@ -169,6 +169,20 @@ inline void launch_cgemm_f32(int m, int n, int k, float alpha_re, float alpha_im
 // In-place inverse of the n x n (n <= 64) complex64 blocks A + z*stride (ld lda), z < batch;
 // info[0] is set to a nonzero value on a zero pivot.
 int  launch_cinv_small_f32(float* A, int64_t lda, int64_t stride, int n, int batch, int* info, hipStream_t s);
+// Symmetric-read block matvec (tiles I <= J of 64 x 64; stiles: int4(domain, I, J, 0)), the
+// touching-pair corrections of the lower triangle, and the finishing kernel.
+void launch_matvec_sym_f64(const DomDesc* doms, const int4* stiles, int64_t ntiles, const double* T, const double* K,
+                           const double* x, double* part, hipStream_t s);
+void launch_matvec_sym_f32(const DomDesc* doms, const int4* stiles, int64_t ntiles, const float* T, const float* K,
+                           const double* x, double* part, hipStream_t s);
+void launch_near_diff_f64(const DomDesc* doms, const int32_t* dof_dom, int64_t ndof, const int64_t* ptr, const int32_t* col,
+                          const double* T, const double* K, double* out, hipStream_t s);
+void launch_near_diff_f32(const DomDesc* doms, const int32_t* dof_dom, int64_t ndof, const int64_t* ptr, const int32_t* col,
+                          const float* T, const float* K, double* out, hipStream_t s);
+void launch_matvec_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int64_t ndof, const int32_t* dplus,
+                              const int32_t* dminus, const double* gval, const int64_t* gcol, const int64_t* nptr,
+                              const int32_t* ncol, const double* nval, const double* part, const double* x, double* y,
+                              hipStream_t s);
 void launch_precond_apply(const DomDesc* doms, const int4* mtiles, int64_t nmt, const float* Tinv,
                           const double* x, double* part, hipStream_t s);
 void launch_precond_finish(const DomDesc* doms, int ndom, const int32_t* dof_dom, int64_t ndof_total,

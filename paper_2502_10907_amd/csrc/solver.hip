@@ -161,6 +161,256 @@ __global__ __launch_bounds__(256) void k_mv_finish(const DomDesc* __restrict__ d
     oN[0] = acc[2]; oN[1] = acc[3];
 }
 
+// Symmetric-read block matvec.  The separated-pair part of T_i and K_i is complex symmetric (the
+// quadrature of a separated pair is the same in both orders), so a wavefront reads only the tiles
+// (I, J), I <= J, of 64 x 64 entries and applies each entry twice: as (row r, column c) and, off
+// the diagonal, as (row c, column r).  Diagonal tiles use the upper triangle only (the diagonal
+// once).  The touching-pair entries differ between the two orders by the quadrature error of the
+// singular rules; the exact lower entries are restored by the sparse correction applied in the
+// finishing kernel.
+// Lane (rg = l % 16, cg = l / 16) owns rows r0 + rg + 16 i (i < 4) and columns c0 + 4k + cg
+// (k < 16): each load instruction reads 16 consecutive rows.  Direct sums stay in registers and
+// are reduced over the four column phases at the end; the transposed sums of each column are
+// reduced over the 16 row lanes at once.  Partial slots per row (nb = ceil(E/64) blocks): the
+// direct part of tile (B, J) goes to slot J+1, the transposed part of tile (I, B) to slot I, so
+// every row has nb + 1 slots, each written once.
+template <typename RM>
+__global__ __launch_bounds__(256) void k_mv_sym(const DomDesc* __restrict__ doms, const int4* __restrict__ stiles,
+                                                int64_t ntiles, const RM* __restrict__ T, const RM* __restrict__ K,
+                                                const double* __restrict__ x, double* __restrict__ part) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t tix = (int64_t)blockIdx.x * 4 + wv;
+    if (tix >= ntiles) return;                          // no workgroup barrier in this kernel
+    const int4 t = stiles[tix];
+    const DomDesc dd = doms[t.x];
+    const int E = dd.E;
+    const int I = t.y, J = t.z;
+    const int r0 = I * 64, c0 = J * 64;
+    const int rg = lane & 15, cg = lane >> 4;
+    const bool diag = I == J;
+    const double rho = dd.rho, q2 = 2.0 / rho;
+    const double* xD = x + 2 * dd.off;
+    const double* xN = x + 2 * (dd.off + E);
+    // With A = 2 x_D, B = (2/rho) x_N, C = 2 x_N the 2x2 Calderon block of a row is
+    //   y_D += K A + T B,   y_N += K C - rho T A.
+    // Indices past the block edge are clamped into it and the loaded values masked by selects, so
+    // that every load is unconditional and the loads of a column issue back to back.
+    double ra[4][2], rb[4][2], rc[4][2];                // A, B, C of this lane's rows (transposed part)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = r0 + rg + 16 * i;
+        const bool ok = r < E;
+        const int rs = ok ? r : E - 1;
+        const double2 d = reinterpret_cast<const double2*>(xD)[rs], nn = reinterpret_cast<const double2*>(xN)[rs];
+        const double dr = ok ? d.x : 0.0, di = ok ? d.y : 0.0, nr = ok ? nn.x : 0.0, ni = ok ? nn.y : 0.0;
+        ra[i][0] = 2.0 * dr; ra[i][1] = 2.0 * di;
+        rb[i][0] = q2 * nr; rb[i][1] = q2 * ni;
+        rc[i][0] = 2.0 * nr; rc[i][1] = 2.0 * ni;
+    }
+    double acc[4][4];                                   // per row: y_D (re, im), y_N without -rho T A, T A
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[i][q] = 0.0;
+    double accTA[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) accTA[i][0] = accTA[i][1] = 0.0;
+    const C2<RM>* Tb = reinterpret_cast<const C2<RM>*>(T) + dd.mat0;
+    const C2<RM>* Kb = reinterpret_cast<const C2<RM>*>(K) + dd.mat0;
+    double* pbase = part + 2 * dd.part0;
+    int rsafe[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = r0 + rg + 16 * i;
+        rsafe[i] = r < E ? r : E - 1;
+    }
+    // software pipeline: the entries and x values of column k+1 are loaded while column k is used
+    C2<RM> av[4], bv[4];
+    double2 d, nn;
+    {
+        const int c = c0 + cg;
+        const int cs = c < E ? c : E - 1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            av[i] = Tb[rsafe[i] + (int64_t)cs * E];
+            bv[i] = Kb[rsafe[i] + (int64_t)cs * E];
+        }
+        d = reinterpret_cast<const double2*>(xD)[cs];
+        nn = reinterpret_cast<const double2*>(xN)[cs];
+    }
+    for (int k = 0; k < 16; ++k) {
+        const int c = c0 + 4 * k + cg;
+        const bool cok = c < E;
+        C2<RM> an[4], bn[4];
+        double2 dn, nnn;
+        {
+            const int c1 = c + 4;
+            const int cs1 = c1 < E ? c1 : E - 1;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                an[i] = Tb[rsafe[i] + (int64_t)cs1 * E];
+                bn[i] = Kb[rsafe[i] + (int64_t)cs1 * E];
+            }
+            dn = reinterpret_cast<const double2*>(xD)[cs1];
+            nnn = reinterpret_cast<const double2*>(xN)[cs1];
+        }
+        const double dr = cok ? d.x : 0.0, di = cok ? d.y : 0.0, nr = cok ? nn.x : 0.0, ni = cok ? nn.y : 0.0;
+        const double Ar = 2.0 * dr, Ai = 2.0 * di, Br = q2 * nr, Bi = q2 * ni, Cr = 2.0 * nr, Ci = 2.0 * ni;
+        double sD[2] = {0, 0}, sN[2] = {0, 0}, sTA[2] = {0, 0};   // transposed sums of row c
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = r0 + rg + 16 * i;
+            const bool dok = cok && r < E && (!diag || r <= c);
+            const double ar = dok ? (double)av[i].re : 0.0, ai = dok ? (double)av[i].im : 0.0;
+            const double br = dok ? (double)bv[i].re : 0.0, bi = dok ? (double)bv[i].im : 0.0;
+            // direct, row r
+            acc[i][0] += br * Ar - bi * Ai + ar * Br - ai * Bi;
+            acc[i][1] += br * Ai + bi * Ar + ar * Bi + ai * Br;
+            acc[i][2] += br * Cr - bi * Ci;
+            acc[i][3] += br * Ci + bi * Cr;
+            accTA[i][0] += ar * Ar - ai * Ai;
+            accTA[i][1] += ar * Ai + ai * Ar;
+            // transposed, row c (strictly upper on the diagonal)
+            const bool tok = !diag || r < c;
+            const double tr = tok ? ar : 0.0, ti = tok ? ai : 0.0, kr = tok ? br : 0.0, ki = tok ? bi : 0.0;
+            sD[0] += kr * ra[i][0] - ki * ra[i][1] + tr * rb[i][0] - ti * rb[i][1];
+            sD[1] += kr * ra[i][1] + ki * ra[i][0] + tr * rb[i][1] + ti * rb[i][0];
+            sN[0] += kr * rc[i][0] - ki * rc[i][1];
+            sN[1] += kr * rc[i][1] + ki * rc[i][0];
+            sTA[0] += tr * ra[i][0] - ti * ra[i][1];
+            sTA[1] += tr * ra[i][1] + ti * ra[i][0];
+        }
+        double v[4] = {sD[0], sD[1], sN[0] - rho * sTA[0], sN[1] - rho * sTA[1]};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) v[q] += __shfl_xor(v[q], off, 64);
+        }
+        if (rg == 0 && cok) {
+            double* pD = pbase + 2 * ((int64_t)(2 * I) * E + c);
+            double* pN = pbase + 2 * ((int64_t)(2 * I + 1) * E + c);
+            pD[0] = v[0]; pD[1] = v[1];
+            pN[0] = v[2]; pN[1] = v[3];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { av[i] = an[i]; bv[i] = bn[i]; }
+        d = dn;
+        nn = nnn;
+    }
+    double o[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        o[i][0] = acc[i][0];
+        o[i][1] = acc[i][1];
+        o[i][2] = acc[i][2] - rho * accTA[i][0];
+        o[i][3] = acc[i][3] - rho * accTA[i][1];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            o[i][q] += __shfl_xor(o[i][q], 16, 64);
+            o[i][q] += __shfl_xor(o[i][q], 32, 64);
+        }
+    }
+    if (cg != 0) return;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = r0 + rg + 16 * i;
+        if (r >= E) continue;
+        double* pD = pbase + 2 * ((int64_t)(2 * (J + 1)) * E + r);
+        double* pN = pbase + 2 * ((int64_t)(2 * (J + 1) + 1) * E + r);
+        pD[0] = o[i][0]; pD[1] = o[i][1];
+        pN[0] = o[i][2]; pN[1] = o[i][3];
+    }
+}
+
+// Touching-pair corrections of the lower triangle: for each stored position (m, n), n < m, of the
+// sparse pattern, D = A[m, n] - A[n, m] for A = T and K (complex, FP64), so that the symmetric-read
+// product plus D x reproduces the stored blocks exactly.
+template <typename RM>
+__global__ void k_near_diff(const DomDesc* __restrict__ doms, const int32_t* __restrict__ dof_dom, int64_t ndof,
+                            const int64_t* __restrict__ ptr, const int32_t* __restrict__ col, const RM* __restrict__ T,
+                            const RM* __restrict__ K, double* __restrict__ out) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ndof) return;
+    const DomDesc dd = doms[dof_dom[g]];
+    const int64_t m = g - dd.dof0;
+    const int64_t E = dd.E;
+    const C2<RM>* Tb = reinterpret_cast<const C2<RM>*>(T) + dd.mat0;
+    const C2<RM>* Kb = reinterpret_cast<const C2<RM>*>(K) + dd.mat0;
+    for (int64_t q = ptr[g]; q < ptr[g + 1]; ++q) {
+        const int64_t n = col[q];
+        const C2<RM> a = Tb[m + n * E], at = Tb[n + m * E];
+        const C2<RM> b = Kb[m + n * E], bt = Kb[n + m * E];
+        double* o = out + 4 * q;
+        o[0] = (double)a.re - (double)at.re;
+        o[1] = (double)a.im - (double)at.im;
+        o[2] = (double)b.re - (double)bt.re;
+        o[3] = (double)b.im - (double)bt.im;
+    }
+}
+
+// Finishing kernel of the symmetric-read product: nb + 1 partial slots per row, the touching-pair
+// correction of the lower triangle and the transmission part.  16 rows per workgroup; the 16 lanes
+// of a row split the slots, the correction terms and the two transmission triangles and are
+// reduced with shuffles.
+__global__ __launch_bounds__(256) void k_mv_sym_finish(const DomDesc* __restrict__ doms,
+                                                       const int32_t* __restrict__ dof_dom, int64_t ndof,
+                                                       const int32_t* __restrict__ dplus,
+                                                       const int32_t* __restrict__ dminus,
+                                                       const double* __restrict__ gval, const int64_t* __restrict__ gcol,
+                                                       const int64_t* __restrict__ nptr, const int32_t* __restrict__ ncol,
+                                                       const double* __restrict__ nval, const double* __restrict__ part,
+                                                       const double* __restrict__ x, double* __restrict__ y) {
+    const int sl = threadIdx.x & 15;
+    const int64_t g = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    const bool live = g < ndof;
+    const int64_t gs = live ? g : ndof - 1;
+    double acc[4] = {0, 0, 0, 0};     // yD re, im, yN re, im
+    const DomDesc dd = doms[dof_dom[gs]];
+    const int64_t m = gs - dd.dof0;
+    const int E = dd.E;
+    const int nslot = dd.nchunk + 1;
+    for (int c = sl; c < nslot; c += 16) {
+        const double* pD = part + 2 * (dd.part0 + (int64_t)(2 * c) * E + m);
+        const double* pN = part + 2 * (dd.part0 + (int64_t)(2 * c + 1) * E + m);
+        acc[0] += pD[0]; acc[1] += pD[1];
+        acc[2] += pN[0]; acc[3] += pN[1];
+    }
+    const double rho = dd.rho;
+    const double* xD = x + 2 * dd.off;
+    const double* xN = x + 2 * (dd.off + E);
+    for (int64_t k = nptr[gs] + sl; k < nptr[gs + 1]; k += 16) {
+        const int64_t n = ncol[k];
+        const double* v = nval + 4 * k;
+        const double tr = v[0], ti = v[1], kr = v[2], ki = v[3];
+        const double dr = xD[2 * n], di = xD[2 * n + 1], nr = xN[2 * n], ni = xN[2 * n + 1];
+        acc[0] += 2.0 * (kr * dr - ki * di) + (2.0 / rho) * (tr * nr - ti * ni);
+        acc[1] += 2.0 * (kr * di + ki * dr) + (2.0 / rho) * (tr * ni + ti * nr);
+        acc[2] += -2.0 * rho * (tr * dr - ti * di) + 2.0 * (kr * nr - ki * ni);
+        acc[3] += -2.0 * rho * (tr * di + ti * dr) + 2.0 * (kr * ni + ki * nr);
+    }
+    if (sl < 6) {
+        const int side = sl / 3, c = sl % 3;
+        const int32_t* pm = side == 0 ? dplus : dminus;
+        const int64_t rec = dd.rec0 + pm[2 * gs];
+        const int a = pm[2 * gs + 1];
+        const double v = gval[9 * rec + 3 * a + c];
+        const double* xd = x + 2 * gcol[6 * rec + c];
+        const double* xn = x + 2 * gcol[6 * rec + 3 + c];
+        acc[0] += v * xd[0]; acc[1] += v * xd[1];
+        acc[2] += v * xn[0]; acc[3] += v * xn[1];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) acc[q] += __shfl_xor(acc[q], off, 64);
+    }
+    if (sl != 0 || !live) return;
+    double* oD = y + 2 * (dd.off + m);
+    double* oN = y + 2 * (dd.off + E + m);
+    oD[0] = acc[0]; oD[1] = acc[1];
+    oN[0] = acc[2]; oN[1] = acc[3];
+}
+
 // u = T^-1 x_N and v = T^-1 x_D per subdomain (complex64 matrix, FP32 accumulation).
 __global__ __launch_bounds__(256) void k_pc_dense(const DomDesc* __restrict__ doms, const int4* __restrict__ mtiles,
                                                   const float* __restrict__ Ti, const double* __restrict__ x,
@@ -905,6 +1155,36 @@ void launch_matvec_dense_f64(const DomDesc* doms, const int4* mtiles, int64_t nm
 void launch_matvec_dense_f32(const DomDesc* doms, const int4* mtiles, int64_t nmt, const float* T, const float* K,
                              const double* x, double* part, hipStream_t s) {
     hipLaunchKernelGGL(k_mv_dense_f32w, dim3((unsigned)nmt), dim3(256), 0, s, doms, mtiles, T, K, x, part);
+}
+
+void launch_matvec_sym_f64(const DomDesc* doms, const int4* stiles, int64_t ntiles, const double* T, const double* K,
+                           const double* x, double* part, hipStream_t s) {
+    hipLaunchKernelGGL(k_mv_sym<double>, dim3(gridn(ntiles, 4)), dim3(256), 0, s, doms, stiles, ntiles, T, K, x, part);
+}
+
+void launch_matvec_sym_f32(const DomDesc* doms, const int4* stiles, int64_t ntiles, const float* T, const float* K,
+                           const double* x, double* part, hipStream_t s) {
+    hipLaunchKernelGGL(k_mv_sym<float>, dim3(gridn(ntiles, 4)), dim3(256), 0, s, doms, stiles, ntiles, T, K, x, part);
+}
+
+void launch_near_diff_f64(const DomDesc* doms, const int32_t* dof_dom, int64_t ndof, const int64_t* ptr, const int32_t* col,
+                          const double* T, const double* K, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_near_diff<double>, dim3(gridn(ndof, 256)), dim3(256), 0, s, doms, dof_dom, ndof, ptr, col, T, K,
+                       out);
+}
+
+void launch_near_diff_f32(const DomDesc* doms, const int32_t* dof_dom, int64_t ndof, const int64_t* ptr, const int32_t* col,
+                          const float* T, const float* K, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_near_diff<float>, dim3(gridn(ndof, 256)), dim3(256), 0, s, doms, dof_dom, ndof, ptr, col, T, K,
+                       out);
+}
+
+void launch_matvec_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int64_t ndof, const int32_t* dplus,
+                              const int32_t* dminus, const double* gval, const int64_t* gcol, const int64_t* nptr,
+                              const int32_t* ncol, const double* nval, const double* part, const double* x, double* y,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_mv_sym_finish, dim3(gridn(ndof, 16)), dim3(256), 0, s, doms, dof_dom, ndof, dplus, dminus, gval,
+                       gcol, nptr, ncol, nval, part, x, y);
 }
 
 void launch_matvec_finish(const DomDesc* doms, int /*ndom*/, const int32_t* dof_dom, int64_t ndof, const int32_t* dplus,
