@@ -96,15 +96,7 @@ void launch_rhs(const DomDesc* d0, const TriGeom* geom, const int32_t* dplus, co
                 double* b, int64_t ldb, hipStream_t s);
 
 // Dense part of y = M x: partial sums of the 2x2 block products per column chunk.
-void launch_matvec_dense_f64(const DomDesc* doms, const int4* mtiles, int64_t nmt, const double* T,
-                             const double* K, const double* x, double* part, hipStream_t s);
-void launch_matvec_dense_f32(const DomDesc* doms, const int4* mtiles, int64_t nmt, const float* T,
-                             const float* K, const double* x, double* part, hipStream_t s);
 // y = sum of partials + transmission; one thread per unknown pair (D, N) of a dof.
-void launch_matvec_finish(const DomDesc* doms, int ndom, const int32_t* dof_dom, int64_t ndof_total,
-                          const int32_t* dplus, const int32_t* dminus, const double* gval,
-                          const int64_t* gcol, const double* part, const double* x, double* y,
-                          hipStream_t s);
 
 // GMRES vector kernels (complex128, length n), batched over nb right-hand sides in lockstep
 // (Krylov slab j at V + j*ldv with ldv = nb*n; column b of each slab is right-hand side b).

@@ -4,11 +4,11 @@
 // Block matvec (Problem 2, Section 3.2): for every subdomain i
 //   y_iD =  2 K_i x_iD + 2/rho_i T_i x_iN + sum_j G^ij x_jD
 //   y_iN = -2 rho_i T_i x_iD + 2 K_i x_iN + sum_j G^ij x_jN
-// The dense part streams each T_i and K_i from HBM exactly once per product
-// (coalesced columns, 64 consecutive rows per wavefront, 16-byte loads) and
-// applies it to both x_iD and x_iN; column chunks give the grid enough
-// workgroups, their partial sums are reduced in the finishing kernel that also
-// applies the sparse transmission part (six terms per row).
+// The dense part streams the upper-triangle tiles of each T_i and K_i from HBM
+// once per product and applies every entry in both positions (the blocks are
+// complex symmetric up to the touching-pair entries, which a sparse correction
+// restores); per-tile partial sums are reduced in the finishing kernel that also
+// applies the correction and the sparse transmission part (six terms per row).
 #include "device.h"
 
 #include <algorithm>
@@ -17,97 +17,12 @@ namespace mtf {
 
 namespace {
 
-constexpr int kChunk = 64;    // columns per dense-matvec workgroup (must match the host tiling)
+constexpr int kChunk = 64;    // columns per preconditioner workgroup and tile size of the product (host tiling)
 
 template <typename RM>
 struct C2 {
     RM re, im;
 };
-
-template <typename RM>
-__global__ __launch_bounds__(256) void k_mv_dense(const DomDesc* __restrict__ doms, const int4* __restrict__ mtiles,
-                                                  const RM* __restrict__ T, const RM* __restrict__ K,
-                                                  const double* __restrict__ x, double* __restrict__ part) {
-    const int4 t = mtiles[blockIdx.x];
-    const DomDesc dd = doms[t.x];
-    const int E = dd.E;
-    const int c0 = t.z * kChunk;
-    const int nc = min(kChunk, E - c0);
-    __shared__ RM xs[kChunk][4];
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-        const double* xd = x + 2 * (dd.off + c0 + c);
-        const double* xn = x + 2 * (dd.off + E + c0 + c);
-        xs[c][0] = (RM)xd[0]; xs[c][1] = (RM)xd[1];
-        xs[c][2] = (RM)xn[0]; xs[c][3] = (RM)xn[1];
-    }
-    __syncthreads();
-    const int row = t.y + threadIdx.x;
-    if (row >= E) return;
-    RM tD[2] = {0, 0}, tN[2] = {0, 0}, kD[2] = {0, 0}, kN[2] = {0, 0};
-    const C2<RM>* Tc = reinterpret_cast<const C2<RM>*>(T) + dd.mat0 + row + (int64_t)c0 * E;
-    const C2<RM>* Kc = reinterpret_cast<const C2<RM>*>(K) + dd.mat0 + row + (int64_t)c0 * E;
-#pragma unroll 4
-    for (int c = 0; c < nc; ++c) {
-        const C2<RM> a = Tc[(int64_t)c * E];
-        const C2<RM> b = Kc[(int64_t)c * E];
-        const RM xdr = xs[c][0], xdi = xs[c][1], xnr = xs[c][2], xni = xs[c][3];
-        tD[0] += a.re * xdr - a.im * xdi; tD[1] += a.re * xdi + a.im * xdr;
-        tN[0] += a.re * xnr - a.im * xni; tN[1] += a.re * xni + a.im * xnr;
-        kD[0] += b.re * xdr - b.im * xdi; kD[1] += b.re * xdi + b.im * xdr;
-        kN[0] += b.re * xnr - b.im * xni; kN[1] += b.re * xni + b.im * xnr;
-    }
-    const double rho = dd.rho;
-    double* pD = part + 2 * (dd.part0 + (int64_t)(2 * t.z) * E + row);
-    double* pN = part + 2 * (dd.part0 + (int64_t)(2 * t.z + 1) * E + row);
-    pD[0] = 2.0 * (double)kD[0] + (2.0 / rho) * (double)tN[0];
-    pD[1] = 2.0 * (double)kD[1] + (2.0 / rho) * (double)tN[1];
-    pN[0] = -2.0 * rho * (double)tD[0] + 2.0 * (double)kN[0];
-    pN[1] = -2.0 * rho * (double)tD[1] + 2.0 * (double)kN[1];
-}
-
-// Complex64 blocks, FP64 arithmetic: the entries are widened on load and the products and sums
-// are formed in FP64, so the only error against the stored operator is the FP32 rounding of
-// the entries themselves (the kernel is HBM-bound either way).
-__global__ __launch_bounds__(256) void k_mv_dense_f32w(const DomDesc* __restrict__ doms, const int4* __restrict__ mtiles,
-                                                       const float* __restrict__ T, const float* __restrict__ K,
-                                                       const double* __restrict__ x, double* __restrict__ part) {
-    const int4 t = mtiles[blockIdx.x];
-    const DomDesc dd = doms[t.x];
-    const int E = dd.E;
-    const int c0 = t.z * kChunk;
-    const int nc = min(kChunk, E - c0);
-    __shared__ double xs[kChunk][4];
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-        const double* xd = x + 2 * (dd.off + c0 + c);
-        const double* xn = x + 2 * (dd.off + E + c0 + c);
-        xs[c][0] = xd[0]; xs[c][1] = xd[1];
-        xs[c][2] = xn[0]; xs[c][3] = xn[1];
-    }
-    __syncthreads();
-    const int row = t.y + threadIdx.x;
-    if (row >= E) return;
-    double tD[2] = {0, 0}, tN[2] = {0, 0}, kD[2] = {0, 0}, kN[2] = {0, 0};
-    const float2* Tc = reinterpret_cast<const float2*>(T) + dd.mat0 + row + (int64_t)c0 * E;
-    const float2* Kc = reinterpret_cast<const float2*>(K) + dd.mat0 + row + (int64_t)c0 * E;
-#pragma unroll 4
-    for (int c = 0; c < nc; ++c) {
-        const float2 af = Tc[(int64_t)c * E];
-        const float2 bf = Kc[(int64_t)c * E];
-        const double ar = af.x, ai = af.y, br = bf.x, bi = bf.y;
-        const double xdr = xs[c][0], xdi = xs[c][1], xnr = xs[c][2], xni = xs[c][3];
-        tD[0] += ar * xdr - ai * xdi; tD[1] += ar * xdi + ai * xdr;
-        tN[0] += ar * xnr - ai * xni; tN[1] += ar * xni + ai * xnr;
-        kD[0] += br * xdr - bi * xdi; kD[1] += br * xdi + bi * xdr;
-        kN[0] += br * xnr - bi * xni; kN[1] += br * xni + bi * xnr;
-    }
-    const double rho = dd.rho;
-    double* pD = part + 2 * (dd.part0 + (int64_t)(2 * t.z) * E + row);
-    double* pN = part + 2 * (dd.part0 + (int64_t)(2 * t.z + 1) * E + row);
-    pD[0] = 2.0 * kD[0] + (2.0 / rho) * tN[0];
-    pD[1] = 2.0 * kD[1] + (2.0 / rho) * tN[1];
-    pN[0] = -2.0 * rho * tD[0] + 2.0 * kN[0];
-    pN[1] = -2.0 * rho * tD[1] + 2.0 * kN[1];
-}
 
 // Finishing kernels: 64 dofs per workgroup, the four wavefronts split the column chunks of the
 // partial sums (and the two transmission triangles) and meet in LDS.
@@ -117,48 +32,6 @@ __device__ inline void finish_reduce(double (&acc)[4], double (*red)[64][4]) {
     __syncthreads();
     if (q == 0)
         for (int k = 0; k < 4; ++k) acc[k] = red[0][r][k] + red[1][r][k] + red[2][r][k] + red[3][r][k];
-}
-
-__global__ __launch_bounds__(256) void k_mv_finish(const DomDesc* __restrict__ doms, const int32_t* __restrict__ dof_dom,
-                                                   int64_t ndof, const int32_t* __restrict__ dplus,
-                                                   const int32_t* __restrict__ dminus, const double* __restrict__ gval,
-                                                   const int64_t* __restrict__ gcol, const double* __restrict__ part,
-                                                   const double* __restrict__ x, double* __restrict__ y) {
-    __shared__ double red[4][64][4];
-    const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int64_t g = (int64_t)blockIdx.x * 64 + r;
-    double acc[4] = {0, 0, 0, 0};     // yD re, im, yN re, im
-    DomDesc dd;
-    int64_t m = 0;
-    if (g < ndof) {
-        dd = doms[dof_dom[g]];
-        m = g - dd.dof0;
-        const int E = dd.E;
-        for (int c = q; c < dd.nchunk; c += 4) {
-            const double* pD = part + 2 * (dd.part0 + (int64_t)(2 * c) * E + m);
-            const double* pN = part + 2 * (dd.part0 + (int64_t)(2 * c + 1) * E + m);
-            acc[0] += pD[0]; acc[1] += pD[1];
-            acc[2] += pN[0]; acc[3] += pN[1];
-        }
-        if (q < 2) {
-            const int32_t* pm = q == 0 ? dplus : dminus;
-            const int64_t rec = dd.rec0 + pm[2 * g];
-            const int a = pm[2 * g + 1];
-            for (int c = 0; c < 3; ++c) {
-                const double v = gval[9 * rec + 3 * a + c];
-                const double* xd = x + 2 * gcol[6 * rec + c];
-                const double* xn = x + 2 * gcol[6 * rec + 3 + c];
-                acc[0] += v * xd[0]; acc[1] += v * xd[1];
-                acc[2] += v * xn[0]; acc[3] += v * xn[1];
-            }
-        }
-    }
-    finish_reduce(acc, red);
-    if (q != 0 || g >= ndof) return;
-    double* oD = y + 2 * (dd.off + m);
-    double* oN = y + 2 * (dd.off + dd.E + m);
-    oD[0] = acc[0]; oD[1] = acc[1];
-    oN[0] = acc[2]; oN[1] = acc[3];
 }
 
 // Symmetric-read block matvec.  The separated-pair part of T_i and K_i is complex symmetric (the
@@ -1147,16 +1020,6 @@ inline unsigned gridn(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs);
 
 }  // namespace
 
-void launch_matvec_dense_f64(const DomDesc* doms, const int4* mtiles, int64_t nmt, const double* T, const double* K,
-                             const double* x, double* part, hipStream_t s) {
-    hipLaunchKernelGGL(k_mv_dense<double>, dim3((unsigned)nmt), dim3(256), 0, s, doms, mtiles, T, K, x, part);
-}
-
-void launch_matvec_dense_f32(const DomDesc* doms, const int4* mtiles, int64_t nmt, const float* T, const float* K,
-                             const double* x, double* part, hipStream_t s) {
-    hipLaunchKernelGGL(k_mv_dense_f32w, dim3((unsigned)nmt), dim3(256), 0, s, doms, mtiles, T, K, x, part);
-}
-
 void launch_matvec_sym_f64(const DomDesc* doms, const int4* stiles, int64_t ntiles, const double* T, const double* K,
                            const double* x, double* part, hipStream_t s) {
     hipLaunchKernelGGL(k_mv_sym<double>, dim3(gridn(ntiles, 4)), dim3(256), 0, s, doms, stiles, ntiles, T, K, x, part);
@@ -1185,13 +1048,6 @@ void launch_matvec_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int64
                               hipStream_t s) {
     hipLaunchKernelGGL(k_mv_sym_finish, dim3(gridn(ndof, 16)), dim3(256), 0, s, doms, dof_dom, ndof, dplus, dminus, gval,
                        gcol, nptr, ncol, nval, part, x, y);
-}
-
-void launch_matvec_finish(const DomDesc* doms, int /*ndom*/, const int32_t* dof_dom, int64_t ndof, const int32_t* dplus,
-                          const int32_t* dminus, const double* gval, const int64_t* gcol, const double* part,
-                          const double* x, double* y, hipStream_t s) {
-    hipLaunchKernelGGL(k_mv_finish, dim3(gridn(ndof, 64)), dim3(256), 0, s, doms, dof_dom, ndof, dplus, dminus, gval,
-                       gcol, part, x, y);
 }
 
 void launch_precond_apply(const DomDesc* doms, const int4* mtiles, int64_t nmt, const float* Tinv, const double* x,
