@@ -184,7 +184,8 @@ typedef struct {
     int32_t struct_size;      /* sizeof(mtf_solve_opts)                                     */
     int32_t precision;        /* operator used by the inner iteration: MTF_FP64 or MTF_FP32_MIXED */
     int32_t preconditioner;   /* MTF_PREC_NONE, MTF_PREC_BLOCK_TINV or MTF_PREC_BLOCK_TINV_GS */
-    int32_t max_iters;        /* Arnoldi steps per GMRES cycle, 0 = 2000                     */
+    int32_t max_iters;        /* Arnoldi steps per GMRES cycle; 0: as many as half the free
+                                 device memory holds, at most 8000 (2000 for lockstep batches) */
     int32_t max_refinements;  /* outer FP64 refinement steps (MTF_FP32_MIXED), 0 = 10        */
     int32_t flags;            /* 0, or MTF_SOLVE_EAGER                                       */
     double  rtol;             /* ||b - M x||_2 <= rtol ||b||_2 with the FP64 operator        */

@@ -902,7 +902,7 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
     }
     if (!(opts.rtol > 0.0) || !(opts.rtol < 1.0)) throw ArgError("rtol must be in (0, 1)");
     if (opts.max_iters < 0 || opts.max_refinements < 0) throw ArgError("negative iteration limits");
-    const int maxit = opts.max_iters ? opts.max_iters : 2000;
+    int maxit = opts.max_iters;
     const int maxref = opts.max_refinements ? opts.max_refinements : 10;
     const int prec = opts.precision;
     check_prec_available(p, prec);
@@ -919,6 +919,21 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
     if (use_pc && !p->have_tinv) { build_tinv(p); t_pc = p->t_precond; }
     // right-hand sides advance in lockstep batches when the products are GEMMs
     const int nbmax = prec == MTF_BF16_SPLIT ? std::min<int>(nrhs, kMaxBatch) : 1;
+    if (maxit == 0) {
+        // cycle length from memory: the Krylov slabs (basis, and the preconditioned candidates when
+        // flexible: 16 N nb bytes per step each) and the Hessenberg matrix and triangular factor
+        // (16 nb m^2 bytes each) may take half of the free device memory plus what this problem
+        // already holds; at most 8000 steps for one right-hand side, 2000 for lockstep batches
+        size_t freeb = 0, totalb = 0;
+        HIPCHK(hipMemGetInfo(&freeb, &totalb));
+        const GmresWork& w = p->gw;
+        const double held = (double)(w.V.n + w.Zt.n + w.H.n + w.Rf.n) * sizeof(double);
+        const double budget = 0.5 * ((double)freeb + held);
+        const double f = use_pc ? 2.0 : 1.0;
+        const double a = 16.0 * nbmax * f, bcoef = 16.0 * (double)p->sk.N * nbmax * f;
+        const double m = (-bcoef + std::sqrt(bcoef * bcoef + 4.0 * a * budget)) / (2.0 * a);
+        maxit = (int)std::min(nbmax > 1 ? 2000.0 : 8000.0, std::max(100.0, m));
+    }
     gmres_alloc(p, maxit, nbmax, use_pc);
     GmresWork& w = p->gw;
     hipStream_t s = p->stream;

@@ -1073,7 +1073,7 @@ void launch_gs_residual(const DomDesc* doms, const int32_t* dof_dom, const int32
 
 void launch_dot2(const double* V, int64_t ldv, const int* jdev, int nvmax, const double* t, int64_t n, double* hpart,
                  int nblk, int nb, hipStream_t s) {
-    const int gy = std::min(nvmax + 1, 512);
+    const int gy = std::max(8, std::min(nvmax + 1, 16384 / (nblk * nb)));   // about 16k workgroups
     hipLaunchKernelGGL(k_dot2, dim3((unsigned)nblk, (unsigned)gy, (unsigned)nb), dim3(256), 0, s, V, ldv, jdev, nvmax, t,
                        n, hpart, nblk);
 }
