@@ -268,7 +268,10 @@ int mtf_batch_destroy(mtf_batch b);
 int mtf_batch_assemble(mtf_batch b, const mtf_assembly_opts* opts, int32_t* grid_used, double* seconds);
 
 /* mtf_solve of problem i on b_dev[i] -> x_dev[i] (one right-hand side each, ld = N_i) with
- * common options; stats[n] may be NULL. */
+ * common options, problem after problem; stats[n] may be NULL.  A problem without FP64 blocks
+ * gets them assembled (default options) for its residual checks and released after its solve;
+ * its T_i^-1 blocks and GMRES work buffers are released too when they did not exist before, so
+ * the batch needs device memory for one problem's solve at a time beyond the blocks it holds. */
 int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, const mtf_solve_opts* opts,
                     mtf_solve_stats* stats);
 

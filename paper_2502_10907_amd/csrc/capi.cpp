@@ -53,10 +53,21 @@ struct GmresWork {
     double* host = nullptr;          // pinned: nb x kSync Hessenberg columns + norm parts
     double* hosty = nullptr;         // pinned: nb x (maxit + 1) least-squares coefficients
     int* hostcnt = nullptr;          // pinned: nb step counts + flag
-    ~GmresWork() {
+    ~GmresWork() { release(); }
+    // frees every buffer; the next solve allocates again
+    void release() {
+        for (DevBuf<double>* b : {&V, &Zt, &Rf, &tmp, &tmp2, &tmp3, &r, &hpart, &S, &Z, &hg, &scal, &H, &npart, &upart,
+                                  &y, &ufix, &tfix, &zfix, &Hst})
+            b->reset();
+        jdev.reset();
+        cnt.reset();
         if (host) (void)hipHostFree(host);
         if (hosty) (void)hipHostFree(hosty);
         if (hostcnt) (void)hipHostFree(hostcnt);
+        host = hosty = nullptr;
+        hostcnt = nullptr;
+        n = 0;
+        maxit = nb = zslots = 0;
     }
 };
 
@@ -932,7 +943,7 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
         const double f = use_pc ? 2.0 : 1.0;
         const double a = 16.0 * nbmax * f, bcoef = 16.0 * (double)p->sk.N * nbmax * f;
         const double m = (-bcoef + std::sqrt(bcoef * bcoef + 4.0 * a * budget)) / (2.0 * a);
-        maxit = (int)std::min(nbmax > 1 ? 2000.0 : 8000.0, std::max(100.0, m));
+        maxit = (int)std::min({nbmax > 1 ? 2000.0 : 8000.0, (double)p->sk.N, std::max(100.0, m)});
     }
     gmres_alloc(p, maxit, nbmax, use_pc);
     GmresWork& w = p->gw;
@@ -1550,8 +1561,21 @@ int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, c
         int status = MTF_OK;
         for (size_t i = 0; i < b->probs.size(); ++i) {
             mtf_problem p = b->probs[i];
+            if (!b_dev[i] || !x_dev[i]) throw ArgError("NULL right-hand side or solution");
+            const bool tmp64 = !p->have64, tmpinv = !p->have_tinv, tmpwork = p->gw.V.n == 0;
+            if (tmp64) {
+                mtf_assembly_opts ao{};
+                ao.struct_size = sizeof(ao);
+                ao.precision = MTF_FP64;
+                ao.singular_order = 4;
+                assemble_impl(p, &ao);
+            }
             const int r = solve_impl(p, 1, b_dev[i], x_dev[i], p->sk.N, opts, stats ? stats + i : nullptr);
             if (r != MTF_OK) status = r;
+            sync(p);
+            if (tmp64) { p->T64.reset(); p->K64.reset(); p->near64.reset(); p->have64 = false; }
+            if (tmpinv) { p->Tinv.reset(); p->have_tinv = false; p->gp.haveA = false; }
+            if (tmpwork) p->gw.release();
         }
         return status;
     });
