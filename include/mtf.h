@@ -209,10 +209,11 @@ typedef struct {
  * recurrence residual meets rtol; the FP64 residual is then recomputed and a new
  * cycle starts if it does not.  With MTF_PREC_BLOCK_TINV the iteration runs on M P, with P the
  * block-diagonal right preconditioner
- *     P_i = 1/2 [[0, -T_i^-1 / rho_i], [rho_i T_i^-1, 0]]
- * (the inverse of the off-diagonal part of 2 A_i; the block shape of the
- * block-OSRC preconditioner of Section 4.4 with the exact discrete T_i^-1),
- * T_i^-1 computed once per problem on the GPU in complex64.
+ *     P_i = 1/2 [[0, -S_i^-1 / rho_i], [rho_i S_i^-1, 0]],  S_i = (T_i + T_i^T) / 2
+ * (the inverse of the off-diagonal part of 2 A_i with T_i replaced by its symmetric
+ * part, which differs from T_i only by the quadrature asymmetry of touching pairs; the
+ * block shape of the block-OSRC preconditioner of Section 4.4), S_i^-1 computed once
+ * per problem on the GPU in complex64 and applied reading its upper triangle only.
  * MTF_PREC_BLOCK_TINV_GS applies one block Gauss-Seidel sweep instead: Omega_0
  * first, then the colour classes of the subdomain adjacency graph (subdomains
  * of one class share no interface and are done together), each block solving
@@ -229,7 +230,7 @@ int mtf_solve(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int64
 
 /* z = P x for nrhs complex128 vectors (x_dev, z_dev: [nrhs][ld], ld >= N, no aliasing) with
  * the right preconditioner `preconditioner` (MTF_PREC_BLOCK_TINV or MTF_PREC_BLOCK_TINV_GS, as
- * defined for mtf_solve).  Builds T_i^-1 on first use (from the FP32 blocks if assembled, else
+ * defined for mtf_solve).  Builds S_i^-1 on first use (from the FP32 blocks if assembled, else
  * from the FP64 ones).  Stream-ordered. */
 int mtf_apply_preconditioner(mtf_problem p, int32_t preconditioner, int32_t nrhs, const void* x_dev,
                              void* z_dev, int64_t ld);
@@ -270,7 +271,7 @@ int mtf_batch_assemble(mtf_batch b, const mtf_assembly_opts* opts, int32_t* grid
 /* mtf_solve of problem i on b_dev[i] -> x_dev[i] (one right-hand side each, ld = N_i) with
  * common options, problem after problem; stats[n] may be NULL.  A problem without FP64 blocks
  * gets them assembled (default options) for its residual checks and released after its solve;
- * its T_i^-1 blocks and GMRES work buffers are released too when they did not exist before, so
+ * its preconditioner blocks and GMRES work buffers are released too when they did not exist before, so
  * the batch needs device memory for one problem's solve at a time beyond the blocks it holds. */
 int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, const mtf_solve_opts* opts,
                     mtf_solve_stats* stats);

@@ -24,7 +24,6 @@ using namespace mtf;
 using cd = std::complex<double>;
 
 constexpr int kTile = 16;     // triangles per side of a separated-pair tile
-constexpr int kRows = 256;    // rows per dense-matvec workgroup
 constexpr int kChunk = 64;    // columns per dense-matvec workgroup (matches solver.hip)
 constexpr int kNblk = 32;     // partial sums of GMRES reductions
 constexpr int kSync = 8;      // Arnoldi steps between host reads of the Hessenberg columns
@@ -91,8 +90,8 @@ struct mtf_problem_s {
     DevBuf<DomDesc> d_doms;
     DevBuf<double> d_gval;
     DevBuf<int64_t> d_gcol;
-    DevBuf<int4> d_tiles, d_mtiles, d_symtiles;
-    int64_t ntiles = 0, nmtiles = 0, nsymtiles = 0;
+    DevBuf<int4> d_tiles, d_symtiles;
+    int64_t ntiles = 0, nsymtiles = 0;
     DevBuf<int64_t> d_near_ptr;      // touching-pair lower-triangle pattern (CSR over dofs)
     DevBuf<int32_t> d_near_col;
     DevBuf<double> near64, near32;   // corrections A[m,n] - A[n,m] for T, K from the FP64 / FP32 blocks
@@ -188,14 +187,11 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
             dof_dom[f0 + m] = i;
         }
     }
-    std::vector<int4> tiles, mtiles, symtiles;
+    std::vector<int4> tiles, symtiles;
     for (int i = 0; i <= M; ++i) {
         const int T = sk.dom[i].T;
         for (int x0 = 0; x0 < T; x0 += kTile)
             for (int y0 = 0; y0 < T; y0 += kTile) tiles.push_back(make_int4(i, x0, y0, 0));
-        const int E = sk.dom[i].E;
-        for (int c = 0; c < doms[i].nchunk; ++c)
-            for (int r0 = 0; r0 < E; r0 += kRows) mtiles.push_back(make_int4(i, r0, c, 0));
         for (int bi = 0; bi < doms[i].nchunk; ++bi)
             for (int bj = bi; bj < doms[i].nchunk; ++bj) symtiles.push_back(make_int4(i, bi, bj, 0));
     }
@@ -248,8 +244,8 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
         for (int i = 0; i <= M; ++i) {
             if (colour[i] != c) continue;
             const int E = sk.dom[i].E;
-            for (int ch = 0; ch < doms[i].nchunk; ++ch)
-                for (int r0 = 0; r0 < E; r0 += kRows) stiles.push_back(make_int4(i, r0, ch, 0));
+            for (int bi = 0; bi < doms[i].nchunk; ++bi)
+                for (int bj = bi; bj < doms[i].nchunk; ++bj) stiles.push_back(make_int4(i, bi, bj, 0));
             for (int m = 0; m < E; ++m) sdofs.push_back((int32_t)(doms[i].dof0 + m));
         }
         st0.push_back((int64_t)stiles.size());
@@ -274,7 +270,6 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
     p->d_dminus.upload(dminus, s);
     p->d_dof_dom.upload(dof_dom, s);
     p->d_tiles.upload(tiles, s);
-    p->d_mtiles.upload(mtiles, s);
     p->d_symtiles.upload(symtiles, s);
     p->nsymtiles = (int64_t)symtiles.size();
     p->d_near_ptr.upload(nearptr, s);
@@ -289,7 +284,6 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
     p->stage_tile0 = st0;
     p->stage_dof0 = sd0;
     p->ntiles = (int64_t)tiles.size();
-    p->nmtiles = (int64_t)mtiles.size();
     p->doms = doms;
     p->nrec = rec;
     p->ndof = dof;
@@ -341,10 +335,14 @@ void parse_assembly_opts(const mtf_assembly_opts* o, int* prec, int* order) {
     if (*order < 1 || *order > 8) throw ArgError("singular_order must be in 1..8");
 }
 
+// Allocation of the T_i, K_i arrays (real numbers): the blocks and 64 complex entries of zero
+// padding, which the symmetric-read product may read past the last block (masked rows).
+int64_t mat_alloc_reals(mtf_problem p) { return 2 * (p->mat_entries + 64); }
+
 // Allocates and zeroes the blocks of one precision and marks them current (kernels launched by the caller).
 void assemble_prepare(mtf_problem p, int prec) {
     hipStream_t s = p->stream;
-    const int64_t n2 = 2 * p->mat_entries;
+    const int64_t n2 = mat_alloc_reals(p);
     if (prec == MTF_FP64) {
         p->T64.alloc(n2); p->K64.alloc(n2);
         launch_fill(p->T64.p, n2, 0.0, s);
@@ -381,7 +379,7 @@ void assemble_impl(mtf_problem p, const mtf_assembly_opts* o) {
     ensure_ss(p, order);
     hipStream_t s = p->stream;
     if (!p->ev0) { HIPCHK(hipEventCreate(&p->ev0)); HIPCHK(hipEventCreate(&p->ev1)); }
-    const int64_t n2 = 2 * p->mat_entries;
+    const int64_t n2 = mat_alloc_reals(p);
     if (prec == MTF_FP64) { p->T64.alloc(n2); p->K64.alloc(n2); }
     else { p->T32.alloc(n2); p->K32.alloc(n2); }
     HIPCHK(hipEventRecord(p->ev0, s));
@@ -497,8 +495,8 @@ void matvec1(mtf_problem p, const double* x, double* y, int prec) {
 }
 
 void precond1(mtf_problem p, const double* x, double* z) {
-    launch_precond_apply(p->d_doms.p, p->d_mtiles.p, p->nmtiles, p->Tinv.p, x, p->part.p, p->stream);
-    launch_precond_finish(p->d_doms.p, (int)p->doms.size(), p->d_dof_dom.p, p->ndof, p->part.p, z, p->stream);
+    launch_precond_sym(p->d_doms.p, p->d_symtiles.p, p->nsymtiles, p->Tinv.p, x, p->part.p, p->stream);
+    launch_precond_sym_finish(p->d_doms.p, p->d_dof_dom.p, p->ndof, p->part.p, z, nullptr, p->stream);
 }
 
 // z = P_GS x: one block Gauss-Seidel sweep over the stages with the T_i^-1 block of each subdomain;
@@ -517,8 +515,8 @@ void precond1_gs(mtf_problem p, const double* x, double* z, double* w) {
                                p->d_other_dom.p, p->d_dom_stage.p, st, x, z, w, s);
             in = w;
         }
-        launch_precond_apply(p->d_doms.p, tiles, ntl, p->Tinv.p, in, p->part.p, s);
-        launch_precond_finish(p->d_doms.p, (int)p->doms.size(), p->d_dof_dom.p, nd, p->part.p, z, s, dl);
+        launch_precond_sym(p->d_doms.p, tiles, ntl, p->Tinv.p, in, p->part.p, s);
+        launch_precond_sym_finish(p->d_doms.p, p->d_dof_dom.p, nd, p->part.p, z, dl, s);
     }
 }
 
@@ -564,7 +562,10 @@ void build_tinv(mtf_problem p) {
     if (p->have_tinv) return;
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = p->stream;
-    p->Tinv.alloc(2 * p->mat_entries);
+    // 64 complex entries of padding: the symmetric-read apply may read up to 63 entries past the
+    // last block (masked rows of its last column)
+    p->Tinv.alloc(2 * (p->mat_entries + 64));
+    HIPCHK(hipMemsetAsync(p->Tinv.p + 2 * p->mat_entries, 0, 2 * 64 * sizeof(float), s));
     DevBuf<int> info;
     info.alloc(2);
     HIPCHK(hipMemsetAsync(info.p, 0, 2 * sizeof(int), s));
@@ -572,6 +573,11 @@ void build_tinv(mtf_problem p) {
         HIPCHK(hipMemcpyAsync(p->Tinv.p, p->T32.p, 2 * p->mat_entries * sizeof(float), hipMemcpyDeviceToDevice, s));
     else
         launch_copy_block_f64_to_f32(p->T64.p, p->Tinv.p, 2 * p->mat_entries, s);
+    // the preconditioner inverts the symmetric part (T_i + T_i^T)/2: T_i differs from it only by
+    // the quadrature asymmetry of touching pairs, and a symmetric inverse is applied reading half
+    // of its entries
+    for (const DomDesc& d : p->doms)
+        if (d.E > 0) launch_symmetrize_f32(p->Tinv.p + 2 * d.mat0, d.E, s);
     // consecutive subdomains of equal size are stored back to back and inverted as one batch
     const auto& D = p->doms;
     for (size_t a = 0; a < D.size();) {

@@ -175,10 +175,13 @@ void launch_matvec_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int64
                               const int32_t* dminus, const double* gval, const int64_t* gcol, const int64_t* nptr,
                               const int32_t* ncol, const double* nval, const double* part, const double* x, double* y,
                               hipStream_t s);
-void launch_precond_apply(const DomDesc* doms, const int4* mtiles, int64_t nmt, const float* Tinv,
-                          const double* x, double* part, hipStream_t s);
-void launch_precond_finish(const DomDesc* doms, int ndom, const int32_t* dof_dom, int64_t ndof_total,
-                           const double* part, double* y, hipStream_t s, const int32_t* list = nullptr);
+// Symmetric-read preconditioner product (tiles I <= J of the complex64 inverse of the symmetric
+// part of T_i), its finishing kernel, and the in-place symmetrisation A <- (A + A^T)/2.
+void launch_precond_sym(const DomDesc* doms, const int4* stiles, int64_t ntiles, const float* Tinv, const double* x,
+                        double* part, hipStream_t s);
+void launch_precond_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int64_t ndof, const double* part, double* z,
+                               const int32_t* list, hipStream_t s);
+void launch_symmetrize_f32(float* A, int n, hipStream_t s);
 // w_i = v_i - sum_j G^ij z_j for the dofs in `list` (one block Gauss-Seidel stage)
 void launch_gs_residual(const DomDesc* doms, const int32_t* dof_dom, const int32_t* list, int64_t nlist,
                         const int32_t* dplus, const int32_t* dminus, const double* gval, const int64_t* gcol,

@@ -12,46 +12,231 @@
 #include "device.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace mtf {
 
 namespace {
-
-constexpr int kChunk = 64;    // columns per preconditioner workgroup and tile size of the product (host tiling)
 
 template <typename RM>
 struct C2 {
     RM re, im;
 };
 
-// Finishing kernels: 64 dofs per workgroup, the four wavefronts split the column chunks of the
-// partial sums (and the two transmission triangles) and meet in LDS.
-__device__ inline void finish_reduce(double (&acc)[4], double (*red)[64][4]) {
-    const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
-    for (int k = 0; k < 4; ++k) red[q][r][k] = acc[k];
-    __syncthreads();
-    if (q == 0)
-        for (int k = 0; k < 4; ++k) acc[k] = red[0][r][k] + red[1][r][k] + red[2][r][k] + red[3][r][k];
+// Cross-lane moves within rows of 16 lanes (DPP): quad_perm [1,0,3,2], quad_perm [2,3,0,1],
+// row_half_mirror, row_mirror.  After the four steps of row16_sum every lane of a row holds the
+// sum over its row.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+template <int CTRL>
+__device__ inline float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+template <typename F>
+__device__ inline F row16_sum(F v) {
+    if constexpr (std::is_same<F, double>::value) {
+        v += dpp_d<kDppXor1>(v);
+        v += dpp_d<kDppXor2>(v);
+        v += dpp_d<kDppHalfMirror>(v);
+        v += dpp_d<kDppMirror>(v);
+    } else {
+        v += dpp_f<kDppXor1>(v);
+        v += dpp_f<kDppXor2>(v);
+        v += dpp_f<kDppHalfMirror>(v);
+        v += dpp_f<kDppMirror>(v);
+    }
+    return v;
+}
+
+// acc += a * b for complex a = (ar, ai), b = (br, bi) as four FMAs
+__device__ inline void cfma(double& re, double& im, double ar, double ai, double br, double bi) {
+    re = fma(ar, br, re);
+    re = fma(-ai, bi, re);
+    im = fma(ar, bi, im);
+    im = fma(ai, br, im);
 }
 
 // Symmetric-read block matvec.  The separated-pair part of T_i and K_i is complex symmetric (the
 // quadrature of a separated pair is the same in both orders), so a wavefront reads only the tiles
 // (I, J), I <= J, of 64 x 64 entries and applies each entry twice: as (row r, column c) and, off
-// the diagonal, as (row c, column r).  Diagonal tiles use the upper triangle only (the diagonal
-// once).  The touching-pair entries differ between the two orders by the quadrature error of the
-// singular rules; the exact lower entries are restored by the sparse correction applied in the
-// finishing kernel.
+// the diagonal, as (row c, column r).  In a diagonal tile the strict lower triangle is dropped and
+// the diagonal entries are halved, so that both uses together apply each entry once.  The
+// touching-pair entries differ between the two orders by the quadrature error of the singular
+// rules; the exact lower entries are restored by the sparse correction applied in the finishing
+// kernel.
 // Lane (rg = l % 16, cg = l / 16) owns rows r0 + rg + 16 i (i < 4) and columns c0 + 4k + cg
-// (k < 16): each load instruction reads 16 consecutive rows.  Direct sums stay in registers and
-// are reduced over the four column phases at the end; the transposed sums of each column are
-// reduced over the 16 row lanes at once.  Partial slots per row (nb = ceil(E/64) blocks): the
-// direct part of tile (B, J) goes to slot J+1, the transposed part of tile (I, B) to slot I, so
-// every row has nb + 1 slots, each written once.
+// (k < 16): each load instruction reads 16 consecutive rows.  The tile and domain descriptors are
+// wave-uniform (scalar loads); a column's eight loads share one 32-bit byte offset from the tile
+// base.  Rows past E are not clamped: they read the next column (or at most 63 entries into the
+// padding behind the blocks) and meet zero row values or unwritten outputs.  The loads of the
+// next column group are issued before the arithmetic of the current one.  The wavefront's 64 column values of x are staged in
+// LDS.  Direct sums stay in registers and are reduced over the four column phases at the end; the
+// transposed sums of each column are reduced over the 16 row lanes at once (DPP).  Partial slots
+// per row (nb = ceil(E/64) blocks): the direct part of tile (B, J) goes to slot J+1, the
+// transposed part of tile (I, B) to slot I, so every row has nb + 1 slots, each written once.
 template <typename RM>
-__global__ __launch_bounds__(256) void k_mv_sym(const DomDesc* __restrict__ doms, const int4* __restrict__ stiles,
-                                                int64_t ntiles, const RM* __restrict__ T, const RM* __restrict__ K,
+__global__ __launch_bounds__(256, 2) void k_mv_sym(const DomDesc* __restrict__ doms, const int4* __restrict__ stiles,
+                                                   int64_t ntiles, const RM* __restrict__ T, const RM* __restrict__ K,
+                                                   const double* __restrict__ x, double* __restrict__ part) {
+    using V2 = typename std::conditional<std::is_same<RM, double>::value, double2, float2>::type;
+    __shared__ double4 xs[4][64];                       // per wavefront: x_D, x_N at column c0 + l
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t tix = (int64_t)blockIdx.x * 4 + wv;
+    const bool live = tix < ntiles;
+    const int4 t = stiles[live ? tix : ntiles - 1];
+    const DomDesc dd = doms[t.x];
+    const int E = dd.E;
+    const int I = t.y, J = t.z;
+    const int r0 = I * 64, c0 = J * 64;
+    const int rg = lane & 15, cg = lane >> 4;
+    const bool diag = I == J;
+    const double rho = dd.rho, irho = 1.0 / rho;
+    const double2* xD = reinterpret_cast<const double2*>(x) + dd.off;
+    const double2* xN = xD + E;
+    {
+        const int c = c0 + lane;
+        const bool ok = c < E;
+        const int cs = ok ? c : E - 1;
+        const double2 d = xD[cs], nn = xN[cs];
+        xs[wv][lane] = make_double4(ok ? d.x : 0.0, ok ? d.y : 0.0, ok ? nn.x : 0.0, ok ? nn.y : 0.0);
+    }
+    __syncthreads();
+    if (!live) return;                                  // no workgroup barrier below
+    // With A = 2 x_D, B = (2/rho) x_N = C / rho, C = 2 x_N and P = -rho A the 2x2 Calderon
+    // block of a row is  y_D += K A + T B,  y_N += K C + T P.
+    double ra[4][2], rc[4][2];                          // A and C of this lane's rows (transposed part)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = r0 + rg + 16 * i;
+        const bool ok = r < E;
+        const int rs = ok ? r : E - 1;
+        const double2 d = xD[rs], nn = xN[rs];
+        ra[i][0] = ok ? 2.0 * d.x : 0.0; ra[i][1] = ok ? 2.0 * d.y : 0.0;
+        rc[i][0] = ok ? 2.0 * nn.x : 0.0; rc[i][1] = ok ? 2.0 * nn.y : 0.0;
+    }
+    const int64_t tile0 = dd.mat0 + r0 + (int64_t)c0 * E;
+    const char* Tt = reinterpret_cast<const char*>(reinterpret_cast<const V2*>(T) + tile0);
+    const char* Kt = reinterpret_cast<const char*>(reinterpret_cast<const V2*>(K) + tile0);
+    double acc[4][4];                                   // per row: y_D (re, im), y_N (re, im)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[i][q] = 0.0;
+    double* pbase = part + 2 * dd.part0;
+    V2 tv[2][4], kv[2][4];
+    auto load = [&](int k, int slot) {
+        const int c = c0 + 4 * k + cg;
+        const int cs = c < E ? c : E - 1;
+        const uint32_t boff = ((uint32_t)rg + (uint32_t)(cs - c0) * (uint32_t)E) * (uint32_t)sizeof(V2);
+        const V2* tp = reinterpret_cast<const V2*>(Tt + boff);
+        const V2* kp = reinterpret_cast<const V2*>(Kt + boff);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            tv[slot][i] = tp[16 * i];
+            kv[slot][i] = kp[16 * i];
+        }
+    };
+    // column group k computes from slot k % 2 while group k + 1 is in flight (the slot and
+    // whether a load is issued are compile-time, so no register set is kept alive across a branch)
+    auto step = [&](int k, auto slot, auto issue) {
+        constexpr int sl = decltype(slot)::value;
+        if constexpr (decltype(issue)::value) load(k + 1, (sl + 1) % 2);
+        const int c = c0 + 4 * k + cg;
+        const double4 xv = xs[wv][4 * k + cg];
+        const double Ar = 2.0 * xv.x, Ai = 2.0 * xv.y, Cr = 2.0 * xv.z, Ci = 2.0 * xv.w;
+        const double Br = irho * Cr, Bi = irho * Ci, Pr = -rho * Ar, Pi = -rho * Ai;
+        double e[4][4];                                 // T re, T im, K re, K im
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            e[i][0] = (double)tv[sl][i].x; e[i][1] = (double)tv[sl][i].y;
+            e[i][2] = (double)kv[sl][i].x; e[i][3] = (double)kv[sl][i].y;
+        }
+        if (diag) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = r0 + rg + 16 * i;
+                const double w = r < c ? 1.0 : (r == c ? 0.5 : 0.0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) e[i][q] *= w;
+            }
+        }
+        double vD[2] = {0, 0}, vN[2] = {0, 0}, tr[2] = {0, 0}, tp[2] = {0, 0};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double ar = e[i][0], ai = e[i][1], br = e[i][2], bi = e[i][3];
+            // direct, row r
+            cfma(acc[i][0], acc[i][1], br, bi, Ar, Ai);
+            cfma(acc[i][0], acc[i][1], ar, ai, Br, Bi);
+            cfma(acc[i][2], acc[i][3], br, bi, Cr, Ci);
+            cfma(acc[i][2], acc[i][3], ar, ai, Pr, Pi);
+            // transposed, row c: K A_r and K C_r directly, T C_r and T A_r scaled after the sum
+            cfma(vD[0], vD[1], br, bi, ra[i][0], ra[i][1]);
+            cfma(vN[0], vN[1], br, bi, rc[i][0], rc[i][1]);
+            cfma(tr[0], tr[1], ar, ai, rc[i][0], rc[i][1]);
+            cfma(tp[0], tp[1], ar, ai, ra[i][0], ra[i][1]);
+        }
+        double v[4] = {fma(irho, tr[0], vD[0]), fma(irho, tr[1], vD[1]), fma(-rho, tp[0], vN[0]),
+                       fma(-rho, tp[1], vN[1])};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = row16_sum(v[q]);
+        if (rg == 0 && c < E) {
+            double* pD = pbase + 2 * ((int64_t)(2 * I) * E + c);
+            double* pN = pbase + 2 * ((int64_t)(2 * I + 1) * E + c);
+            *reinterpret_cast<double2*>(pD) = make_double2(v[0], v[1]);
+            *reinterpret_cast<double2*>(pN) = make_double2(v[2], v[3]);
+        }
+    };
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, 1>;
+    load(0, 0);
+#pragma unroll 1
+    for (int k = 0; k < 14; k += 2) {
+        step(k, S0{}, std::true_type{});
+        step(k + 1, S1{}, std::true_type{});
+    }
+    step(14, S0{}, std::true_type{});
+    step(15, S1{}, std::false_type{});
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            acc[i][q] += __shfl_xor(acc[i][q], 16, 64);
+            acc[i][q] += __shfl_xor(acc[i][q], 32, 64);
+        }
+    if (cg != 0) return;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = r0 + rg + 16 * i;
+        if (r >= E) continue;
+        double* pD = pbase + 2 * ((int64_t)(2 * (J + 1)) * E + r);
+        double* pN = pbase + 2 * ((int64_t)(2 * (J + 1) + 1) * E + r);
+        *reinterpret_cast<double2*>(pD) = make_double2(acc[i][0], acc[i][1]);
+        *reinterpret_cast<double2*>(pN) = make_double2(acc[i][2], acc[i][3]);
+    }
+}
+
+// Symmetric-read preconditioner product: v_D = S x_D, v_N = S x_N per subdomain with S the
+// complex64 inverse of the symmetric part of T_i (symmetric up to the rounding of the inversion;
+// only its tiles I <= J are read, each entry used as (r, c) and, off the diagonal, as (c, r)).
+// Same lane layout and partial-slot layout as k_mv_sym; FP32 arithmetic.  A tile is only 32 KB
+// and the Gauss-Seidel stages launch few of them, so each wavefront issues all of its tile's
+// loads (64 per lane) before the first use: latency is paid once per tile, not per column
+// group.  Lane l holds x at column c0 + l and hands it to the lanes of column 4k + cg by
+// cross-lane reads.
+__global__ __launch_bounds__(256) void k_pc_sym(const DomDesc* __restrict__ doms, const int4* __restrict__ stiles,
+                                                int64_t ntiles, const float* __restrict__ Ti,
                                                 const double* __restrict__ x, double* __restrict__ part) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t tix = (int64_t)blockIdx.x * 4 + wv;
     if (tix >= ntiles) return;                          // no workgroup barrier in this kernel
     const int4 t = stiles[tix];
@@ -61,128 +246,85 @@ __global__ __launch_bounds__(256) void k_mv_sym(const DomDesc* __restrict__ doms
     const int r0 = I * 64, c0 = J * 64;
     const int rg = lane & 15, cg = lane >> 4;
     const bool diag = I == J;
-    const double rho = dd.rho, q2 = 2.0 / rho;
-    const double* xD = x + 2 * dd.off;
-    const double* xN = x + 2 * (dd.off + E);
-    // With A = 2 x_D, B = (2/rho) x_N, C = 2 x_N the 2x2 Calderon block of a row is
-    //   y_D += K A + T B,   y_N += K C - rho T A.
-    // Indices past the block edge are clamped into it and the loaded values masked by selects, so
-    // that every load is unconditional and the loads of a column issue back to back.
-    double ra[4][2], rb[4][2], rc[4][2];                // A, B, C of this lane's rows (transposed part)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = r0 + rg + 16 * i;
-        const bool ok = r < E;
-        const int rs = ok ? r : E - 1;
-        const double2 d = reinterpret_cast<const double2*>(xD)[rs], nn = reinterpret_cast<const double2*>(xN)[rs];
-        const double dr = ok ? d.x : 0.0, di = ok ? d.y : 0.0, nr = ok ? nn.x : 0.0, ni = ok ? nn.y : 0.0;
-        ra[i][0] = 2.0 * dr; ra[i][1] = 2.0 * di;
-        rb[i][0] = q2 * nr; rb[i][1] = q2 * ni;
-        rc[i][0] = 2.0 * nr; rc[i][1] = 2.0 * ni;
-    }
-    double acc[4][4];                                   // per row: y_D (re, im), y_N without -rho T A, T A
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[i][q] = 0.0;
-    double accTA[4][2];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) accTA[i][0] = accTA[i][1] = 0.0;
-    const C2<RM>* Tb = reinterpret_cast<const C2<RM>*>(T) + dd.mat0;
-    const C2<RM>* Kb = reinterpret_cast<const C2<RM>*>(K) + dd.mat0;
-    double* pbase = part + 2 * dd.part0;
+    // rows past E are not clamped: they read the next column (or, after the last column, at most
+    // 63 entries into the 64-entry padding behind the inverse blocks) and are masked below, so the
+    // four loads of a column share one address
+    const float2* Tb = reinterpret_cast<const float2*>(Ti) + dd.mat0 + r0 + rg;
     int rsafe[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int r = r0 + rg + 16 * i;
         rsafe[i] = r < E ? r : E - 1;
     }
-    // software pipeline: the entries and x values of column k+1 are loaded while column k is used
-    C2<RM> av[4], bv[4];
-    double2 d, nn;
-    {
-        const int c = c0 + cg;
-        const int cs = c < E ? c : E - 1;
+    float2 a[16][4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            av[i] = Tb[rsafe[i] + (int64_t)cs * E];
-            bv[i] = Kb[rsafe[i] + (int64_t)cs * E];
-        }
-        d = reinterpret_cast<const double2*>(xD)[cs];
-        nn = reinterpret_cast<const double2*>(xN)[cs];
+    for (int k = 0; k < 16; ++k) {
+        const int c = c0 + 4 * k + cg;
+        const int cs = c < E ? c : E - 1;
+        const float2* pc = Tb + (int64_t)cs * E;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[k][i] = pc[16 * i];
     }
+    const double2* xD = reinterpret_cast<const double2*>(x) + dd.off;
+    const double2* xN = reinterpret_cast<const double2*>(x) + dd.off + E;
+    float xr[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const bool ok = r0 + rg + 16 * i < E;
+        const double2 d = xD[rsafe[i]], nn = xN[rsafe[i]];
+        xr[i][0] = ok ? (float)d.x : 0.f; xr[i][1] = ok ? (float)d.y : 0.f;
+        xr[i][2] = ok ? (float)nn.x : 0.f; xr[i][3] = ok ? (float)nn.y : 0.f;
+    }
+    float xc[4];
+    {
+        const int c = c0 + lane;
+        const bool ok = c < E;
+        const int cs = ok ? c : E - 1;
+        const double2 d = xD[cs], nn = xN[cs];
+        xc[0] = ok ? (float)d.x : 0.f; xc[1] = ok ? (float)d.y : 0.f;
+        xc[2] = ok ? (float)nn.x : 0.f; xc[3] = ok ? (float)nn.y : 0.f;
+    }
+    float acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[i][q] = 0.f;
+    double* pbase = part + 2 * dd.part0;
+#pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int c = c0 + 4 * k + cg;
         const bool cok = c < E;
-        C2<RM> an[4], bn[4];
-        double2 dn, nnn;
-        {
-            const int c1 = c + 4;
-            const int cs1 = c1 < E ? c1 : E - 1;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                an[i] = Tb[rsafe[i] + (int64_t)cs1 * E];
-                bn[i] = Kb[rsafe[i] + (int64_t)cs1 * E];
-            }
-            dn = reinterpret_cast<const double2*>(xD)[cs1];
-            nnn = reinterpret_cast<const double2*>(xN)[cs1];
-        }
-        const double dr = cok ? d.x : 0.0, di = cok ? d.y : 0.0, nr = cok ? nn.x : 0.0, ni = cok ? nn.y : 0.0;
-        const double Ar = 2.0 * dr, Ai = 2.0 * di, Br = q2 * nr, Bi = q2 * ni, Cr = 2.0 * nr, Ci = 2.0 * ni;
-        double sD[2] = {0, 0}, sN[2] = {0, 0}, sTA[2] = {0, 0};   // transposed sums of row c
+        const float dr = __shfl(xc[0], 4 * k + cg, 64), di = __shfl(xc[1], 4 * k + cg, 64);
+        const float nr = __shfl(xc[2], 4 * k + cg, 64), ni = __shfl(xc[3], 4 * k + cg, 64);
+        float s[4] = {0.f, 0.f, 0.f, 0.f};             // transposed: S x_D, S x_N of row c
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int r = r0 + rg + 16 * i;
             const bool dok = cok && r < E && (!diag || r <= c);
-            const double ar = dok ? (double)av[i].re : 0.0, ai = dok ? (double)av[i].im : 0.0;
-            const double br = dok ? (double)bv[i].re : 0.0, bi = dok ? (double)bv[i].im : 0.0;
-            // direct, row r
-            acc[i][0] += br * Ar - bi * Ai + ar * Br - ai * Bi;
-            acc[i][1] += br * Ai + bi * Ar + ar * Bi + ai * Br;
-            acc[i][2] += br * Cr - bi * Ci;
-            acc[i][3] += br * Ci + bi * Cr;
-            accTA[i][0] += ar * Ar - ai * Ai;
-            accTA[i][1] += ar * Ai + ai * Ar;
-            // transposed, row c (strictly upper on the diagonal)
+            const float ar = dok ? a[k][i].x : 0.f, ai = dok ? a[k][i].y : 0.f;
+            acc[i][0] += ar * dr - ai * di; acc[i][1] += ar * di + ai * dr;
+            acc[i][2] += ar * nr - ai * ni; acc[i][3] += ar * ni + ai * nr;
             const bool tok = !diag || r < c;
-            const double tr = tok ? ar : 0.0, ti = tok ? ai : 0.0, kr = tok ? br : 0.0, ki = tok ? bi : 0.0;
-            sD[0] += kr * ra[i][0] - ki * ra[i][1] + tr * rb[i][0] - ti * rb[i][1];
-            sD[1] += kr * ra[i][1] + ki * ra[i][0] + tr * rb[i][1] + ti * rb[i][0];
-            sN[0] += kr * rc[i][0] - ki * rc[i][1];
-            sN[1] += kr * rc[i][1] + ki * rc[i][0];
-            sTA[0] += tr * ra[i][0] - ti * ra[i][1];
-            sTA[1] += tr * ra[i][1] + ti * ra[i][0];
+            const float tr = tok ? ar : 0.f, ti = tok ? ai : 0.f;
+            s[0] += tr * xr[i][0] - ti * xr[i][1]; s[1] += tr * xr[i][1] + ti * xr[i][0];
+            s[2] += tr * xr[i][2] - ti * xr[i][3]; s[3] += tr * xr[i][3] + ti * xr[i][2];
         }
-        double v[4] = {sD[0], sD[1], sN[0] - rho * sTA[0], sN[1] - rho * sTA[1]};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-#pragma unroll
-            for (int off = 1; off < 16; off <<= 1) v[q] += __shfl_xor(v[q], off, 64);
-        }
+        for (int q = 0; q < 4; ++q) s[q] = row16_sum(s[q]);
         if (rg == 0 && cok) {
             double* pD = pbase + 2 * ((int64_t)(2 * I) * E + c);
             double* pN = pbase + 2 * ((int64_t)(2 * I + 1) * E + c);
-            pD[0] = v[0]; pD[1] = v[1];
-            pN[0] = v[2]; pN[1] = v[3];
+            pD[0] = s[0]; pD[1] = s[1];
+            pN[0] = s[2]; pN[1] = s[3];
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) { av[i] = an[i]; bv[i] = bn[i]; }
-        d = dn;
-        nn = nnn;
     }
-    double o[4][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        o[i][0] = acc[i][0];
-        o[i][1] = acc[i][1];
-        o[i][2] = acc[i][2] - rho * accTA[i][0];
-        o[i][3] = acc[i][3] - rho * accTA[i][1];
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            o[i][q] += __shfl_xor(o[i][q], 16, 64);
-            o[i][q] += __shfl_xor(o[i][q], 32, 64);
+            acc[i][q] += __shfl_xor(acc[i][q], 16, 64);
+            acc[i][q] += __shfl_xor(acc[i][q], 32, 64);
         }
-    }
     if (cg != 0) return;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -190,9 +332,53 @@ __global__ __launch_bounds__(256) void k_mv_sym(const DomDesc* __restrict__ doms
         if (r >= E) continue;
         double* pD = pbase + 2 * ((int64_t)(2 * (J + 1)) * E + r);
         double* pN = pbase + 2 * ((int64_t)(2 * (J + 1) + 1) * E + r);
-        pD[0] = o[i][0]; pD[1] = o[i][1];
-        pN[0] = o[i][2]; pN[1] = o[i][3];
+        pD[0] = acc[i][0]; pD[1] = acc[i][1];
+        pN[0] = acc[i][2]; pN[1] = acc[i][3];
     }
+}
+
+// z_iD = -1/(2 rho) v_N, z_iN = rho/2 v_D from the nb + 1 slots of k_pc_sym (all dofs, or the dofs
+// of `list`); 16 rows per workgroup, 16 lanes per row.
+__global__ __launch_bounds__(256) void k_pc_sym_finish(const DomDesc* __restrict__ doms,
+                                                       const int32_t* __restrict__ dof_dom, int64_t ndof,
+                                                       const double* __restrict__ part, double* __restrict__ z,
+                                                       const int32_t* __restrict__ list) {
+    const int sl = threadIdx.x & 15;
+    const int64_t t = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    const bool live = t < ndof;
+    const int64_t ts = live ? t : ndof - 1;
+    const int64_t g = list ? list[ts] : ts;
+    const DomDesc dd = doms[dof_dom[g]];
+    const int64_t m = g - dd.dof0;
+    const int E = dd.E;
+    double acc[4] = {0, 0, 0, 0};
+    for (int c = sl; c < dd.nchunk + 1; c += 16) {
+        const double* pD = part + 2 * (dd.part0 + (int64_t)(2 * c) * E + m);
+        const double* pN = part + 2 * (dd.part0 + (int64_t)(2 * c + 1) * E + m);
+        acc[0] += pD[0]; acc[1] += pD[1];
+        acc[2] += pN[0]; acc[3] += pN[1];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = row16_sum(acc[q]);
+    if (sl != 0 || !live) return;
+    const double a = -0.5 / dd.rho, b = 0.5 * dd.rho;
+    double* oD = z + 2 * (dd.off + m);
+    double* oN = z + 2 * (dd.off + E + m);
+    oD[0] = a * acc[2]; oD[1] = a * acc[3];
+    oN[0] = b * acc[0]; oN[1] = b * acc[1];
+}
+
+// A <- (A + A^T) / 2 for the n x n complex64 block A (ld n), in place
+__global__ void k_symmetrize_f32(float* __restrict__ A, int n) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * n) return;
+    const int r = (int)(e % n), c = (int)(e / n);
+    if (r >= c) return;
+    float2* A2 = reinterpret_cast<float2*>(A);
+    const float2 u = A2[r + (int64_t)c * n], l = A2[c + (int64_t)r * n];
+    const float2 m = make_float2(0.5f * (u.x + l.x), 0.5f * (u.y + l.y));
+    A2[r + (int64_t)c * n] = m;
+    A2[c + (int64_t)r * n] = m;
 }
 
 // Touching-pair corrections of the lower triangle: for each stored position (m, n), n < m, of the
@@ -273,79 +459,12 @@ __global__ __launch_bounds__(256) void k_mv_sym_finish(const DomDesc* __restrict
         acc[2] += v * xn[0]; acc[3] += v * xn[1];
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-#pragma unroll
-        for (int off = 1; off < 16; off <<= 1) acc[q] += __shfl_xor(acc[q], off, 64);
-    }
+    for (int q = 0; q < 4; ++q) acc[q] = row16_sum(acc[q]);
     if (sl != 0 || !live) return;
     double* oD = y + 2 * (dd.off + m);
     double* oN = y + 2 * (dd.off + E + m);
     oD[0] = acc[0]; oD[1] = acc[1];
     oN[0] = acc[2]; oN[1] = acc[3];
-}
-
-// u = T^-1 x_N and v = T^-1 x_D per subdomain (complex64 matrix, FP32 accumulation).
-__global__ __launch_bounds__(256) void k_pc_dense(const DomDesc* __restrict__ doms, const int4* __restrict__ mtiles,
-                                                  const float* __restrict__ Ti, const double* __restrict__ x,
-                                                  double* __restrict__ part) {
-    const int4 t = mtiles[blockIdx.x];
-    const DomDesc dd = doms[t.x];
-    const int E = dd.E;
-    const int c0 = t.z * kChunk;
-    const int nc = min(kChunk, E - c0);
-    __shared__ float xs[kChunk][4];
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-        const double* xd = x + 2 * (dd.off + c0 + c);
-        const double* xn = x + 2 * (dd.off + E + c0 + c);
-        xs[c][0] = (float)xd[0]; xs[c][1] = (float)xd[1];
-        xs[c][2] = (float)xn[0]; xs[c][3] = (float)xn[1];
-    }
-    __syncthreads();
-    const int row = t.y + threadIdx.x;
-    if (row >= E) return;
-    float aD[2] = {0, 0}, aN[2] = {0, 0};
-    const C2<float>* Tc = reinterpret_cast<const C2<float>*>(Ti) + dd.mat0 + row + (int64_t)c0 * E;
-#pragma unroll 8
-    for (int c = 0; c < nc; ++c) {
-        const C2<float> a = Tc[(int64_t)c * E];
-        aD[0] += a.re * xs[c][0] - a.im * xs[c][1]; aD[1] += a.re * xs[c][1] + a.im * xs[c][0];
-        aN[0] += a.re * xs[c][2] - a.im * xs[c][3]; aN[1] += a.re * xs[c][3] + a.im * xs[c][2];
-    }
-    double* pD = part + 2 * (dd.part0 + (int64_t)(2 * t.z) * E + row);
-    double* pN = part + 2 * (dd.part0 + (int64_t)(2 * t.z + 1) * E + row);
-    pD[0] = aD[0]; pD[1] = aD[1];
-    pN[0] = aN[0]; pN[1] = aN[1];
-}
-
-// z_iD = -1/(2 rho) T^-1 x_iN,  z_iN = rho/2 T^-1 x_iD  (all dofs, or the dofs of `list`)
-__global__ __launch_bounds__(256) void k_pc_finish(const DomDesc* __restrict__ doms, const int32_t* __restrict__ dof_dom,
-                                                   int64_t ndof, const double* __restrict__ part, double* __restrict__ z,
-                                                   const int32_t* __restrict__ list) {
-    __shared__ double red[4][64][4];
-    const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int64_t t = (int64_t)blockIdx.x * 64 + r;
-    double acc[4] = {0, 0, 0, 0};     // vD re, im, vN re, im
-    DomDesc dd;
-    int64_t m = 0;
-    if (t < ndof) {
-        const int64_t g = list ? list[t] : t;
-        dd = doms[dof_dom[g]];
-        m = g - dd.dof0;
-        const int E = dd.E;
-        for (int c = q; c < dd.nchunk; c += 4) {
-            const double* pD = part + 2 * (dd.part0 + (int64_t)(2 * c) * E + m);
-            const double* pN = part + 2 * (dd.part0 + (int64_t)(2 * c + 1) * E + m);
-            acc[0] += pD[0]; acc[1] += pD[1];
-            acc[2] += pN[0]; acc[3] += pN[1];
-        }
-    }
-    finish_reduce(acc, red);
-    if (q != 0 || t >= ndof) return;
-    const double a = -0.5 / dd.rho, b = 0.5 * dd.rho;
-    double* oD = z + 2 * (dd.off + m);
-    double* oN = z + 2 * (dd.off + dd.E + m);
-    oD[0] = a * acc[2]; oD[1] = a * acc[3];
-    oN[0] = b * acc[0]; oN[1] = b * acc[1];
 }
 
 // Block Gauss-Seidel stage input: w_i = v_i - sum_j G^ij z_j for the dofs of one stage (z holds
@@ -1050,16 +1169,20 @@ void launch_matvec_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int64
                        gcol, nptr, ncol, nval, part, x, y);
 }
 
-void launch_precond_apply(const DomDesc* doms, const int4* mtiles, int64_t nmt, const float* Tinv, const double* x,
-                          double* part, hipStream_t s) {
-    if (nmt <= 0) return;
-    hipLaunchKernelGGL(k_pc_dense, dim3((unsigned)nmt), dim3(256), 0, s, doms, mtiles, Tinv, x, part);
+void launch_precond_sym(const DomDesc* doms, const int4* stiles, int64_t ntiles, const float* Tinv, const double* x,
+                        double* part, hipStream_t s) {
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL(k_pc_sym, dim3(gridn(ntiles, 4)), dim3(256), 0, s, doms, stiles, ntiles, Tinv, x, part);
 }
 
-void launch_precond_finish(const DomDesc* doms, int /*ndom*/, const int32_t* dof_dom, int64_t ndof, const double* part,
-                           double* z, hipStream_t s, const int32_t* list) {
+void launch_precond_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int64_t ndof, const double* part, double* z,
+                               const int32_t* list, hipStream_t s) {
     if (ndof <= 0) return;
-    hipLaunchKernelGGL(k_pc_finish, dim3(gridn(ndof, 64)), dim3(256), 0, s, doms, dof_dom, ndof, part, z, list);
+    hipLaunchKernelGGL(k_pc_sym_finish, dim3(gridn(ndof, 16)), dim3(256), 0, s, doms, dof_dom, ndof, part, z, list);
+}
+
+void launch_symmetrize_f32(float* A, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_symmetrize_f32, dim3(gridn((int64_t)n * n, 256)), dim3(256), 0, s, A, n);
 }
 
 void launch_gs_residual(const DomDesc* doms, const int32_t* dof_dom, const int32_t* list, int64_t nlist,

@@ -129,10 +129,11 @@ def test_full_size_entries_fp32_c3():
 
 
 def test_full_size_tinv_residual(c2):
-    """T_i^-1 from the complex64 inversion at full size (E_0 = 4,608, E_1 = 1,152): the block-Jacobi
-    preconditioner applied to a random vector, checked through ||T_i z - v|| / ||v|| with the
-    library's FP64 T_i.  cond(T_1) = 27 (oracle); the inverse is built from the FP64 blocks
-    rounded to complex64, so the residual is a few hundred FP32 roundings at most."""
+    """S_i^-1, S_i = (T_i + T_i^T)/2, from the complex64 inversion at full size (E_0 = 4,608,
+    E_1 = 1,152): the block-Jacobi preconditioner applied to a random vector, checked through
+    ||S_i z - v|| / ||v|| with the library's FP64 T_i symmetrised.  cond(T_1) = 27 (oracle); the
+    inverse is built from the FP64 blocks rounded to complex64, so the residual is a few hundred
+    FP32 roundings at most."""
     cfg, P, pb = c2
     rng = np.random.default_rng(11)
     x = rng.standard_normal(P.N) + 1j * rng.standard_normal(P.N)
@@ -143,7 +144,8 @@ def test_full_size_tinv_residual(c2):
     for i in (0, 1, 8):
         o, E, rho = pb.offsets[i], pb.E[i], pb.rho[i]
         T = P.copy_block(i, mtf.BLOCK_T)
+        S = 0.5 * (T + T.T)
         vN = x[o + E:o + 2 * E]
-        r = np.linalg.norm(T @ (z[o:o + E] * (-2 * rho)) - vN) / np.linalg.norm(vN)
+        r = np.linalg.norm(S @ (z[o:o + E] * (-2 * rho)) - vN) / np.linalg.norm(vN)
         print(f"[T_{i}^-1 full size] E={E} residual {r:.2e}", flush=True)
         assert r < 1e-4
