@@ -56,6 +56,29 @@ __device__ inline F row16_sum(F v) {
     return v;
 }
 
+constexpr int kDppRor4 = 0x124, kDppRor8 = 0x128;     // row_ror:4, row_ror:8
+
+template <int CTRL, typename F>
+__device__ inline F dpp(F v) {
+    if constexpr (std::is_same<F, double>::value) return dpp_d<CTRL>(v);
+    else return dpp_f<CTRL>(v);
+}
+
+// Sums four values over the 16 lanes of a row with five cross-lane moves: the lanes of a pair
+// trade half of their values, those of a quad half of the rest, and the four quads their one
+// remaining value.  On return lane l holds the row sum of value q = 2 (l & 1) + ((l >> 1) & 1).
+template <typename F>
+__device__ inline F row16_sum4(const F (&v)[4], int rg) {
+    const bool odd = rg & 1, hi = (rg >> 1) & 1;
+    const F s0 = odd ? v[0] : v[2], s1 = odd ? v[1] : v[3];
+    const F w0 = (odd ? v[2] : v[0]) + dpp<kDppXor1>(s0);
+    const F w1 = (odd ? v[3] : v[1]) + dpp<kDppXor1>(s1);
+    F u = (hi ? w1 : w0) + dpp<kDppXor2>(hi ? w0 : w1);
+    u += dpp<kDppRor4>(u);
+    u += dpp<kDppRor8>(u);
+    return u;
+}
+
 // acc += a * b for complex a = (ar, ai), b = (br, bi) as four FMAs
 __device__ inline void cfma(double& re, double& im, double ar, double ai, double br, double bi) {
     re = fma(ar, br, re);
@@ -184,16 +207,11 @@ __global__ __launch_bounds__(256, 2) void k_mv_sym(const DomDesc* __restrict__ d
             cfma(tr[0], tr[1], ar, ai, rc[i][0], rc[i][1]);
             cfma(tp[0], tp[1], ar, ai, ra[i][0], ra[i][1]);
         }
-        double v[4] = {fma(irho, tr[0], vD[0]), fma(irho, tr[1], vD[1]), fma(-rho, tp[0], vN[0]),
-                       fma(-rho, tp[1], vN[1])};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = row16_sum(v[q]);
-        if (rg == 0 && c < E) {
-            double* pD = pbase + 2 * ((int64_t)(2 * I) * E + c);
-            double* pN = pbase + 2 * ((int64_t)(2 * I + 1) * E + c);
-            *reinterpret_cast<double2*>(pD) = make_double2(v[0], v[1]);
-            *reinterpret_cast<double2*>(pN) = make_double2(v[2], v[3]);
-        }
+        const double v[4] = {fma(irho, tr[0], vD[0]), fma(irho, tr[1], vD[1]), fma(-rho, tp[0], vN[0]),
+                             fma(-rho, tp[1], vN[1])};
+        // lanes rg = 0, 1, 2, 3 hold the sums of y_D re, y_N re, y_D im, y_N im of row c
+        const double u = row16_sum4(v, rg);
+        if (rg < 4 && c < E) pbase[2 * ((int64_t)(2 * I + (rg & 1)) * E + c) + (rg >> 1)] = u;
     };
     using S0 = std::integral_constant<int, 0>;
     using S1 = std::integral_constant<int, 1>;
@@ -224,65 +242,83 @@ __global__ __launch_bounds__(256, 2) void k_mv_sym(const DomDesc* __restrict__ d
     }
 }
 
+__device__ inline void cfmaf(float& re, float& im, float ar, float ai, float br, float bi) {
+    re = fmaf(ar, br, re);
+    re = fmaf(-ai, bi, re);
+    im = fmaf(ar, bi, im);
+    im = fmaf(ai, br, im);
+}
+
 // Symmetric-read preconditioner product: v_D = S x_D, v_N = S x_N per subdomain with S the
 // complex64 inverse of the symmetric part of T_i (symmetric up to the rounding of the inversion;
-// only its tiles I <= J are read, each entry used as (r, c) and, off the diagonal, as (c, r)).
-// Same lane layout and partial-slot layout as k_mv_sym; FP32 arithmetic.  A tile is only 32 KB
-// and the Gauss-Seidel stages launch few of them, so each wavefront issues all of its tile's
-// loads (64 per lane) before the first use: latency is paid once per tile, not per column
-// group.  Lane l holds x at column c0 + l and hands it to the lanes of column 4k + cg by
-// cross-lane reads.
+// only its tiles I <= J are read, each entry used as (r, c) and, off the diagonal, as (c, r); in
+// a diagonal tile the strict lower triangle is dropped and the diagonal halved).  Same lane
+// layout, addressing and partial-slot layout as k_mv_sym; FP32 arithmetic.  A column group is
+// only 2 KB per wavefront, so the loads run D groups ahead through a ring of D + 1 register
+// slots (D = 3 measured fastest on the Gauss-Seidel stages, large and small: three wavefronts
+// per SIMD with three groups in flight each).
+constexpr int kPcDepth = 3;
+
+// Steps k + j (j < NS) of a register-slot ring, slot j, each issuing the load D groups ahead.
+template <int NS, typename Step, int... j>
+__device__ inline void ring_round(Step& step, int k, std::integer_sequence<int, j...>) {
+    (step(k + j, std::integral_constant<int, j>{}, std::true_type{}), ...);
+}
+
+// The remaining steps K0 + j of a ring over KN groups: slot (K0 + j) % NS, a load issued only
+// while group K0 + j + D exists.
+template <int NS, int K0, int D, int KN, typename Step, int... j>
+__device__ inline void ring_tail(Step& step, std::integer_sequence<int, j...>) {
+    (step(K0 + j, std::integral_constant<int, (K0 + j) % NS>{}, std::bool_constant<(K0 + j + D < KN)>{}), ...);
+}
+
+template <int D>
 __global__ __launch_bounds__(256) void k_pc_sym(const DomDesc* __restrict__ doms, const int4* __restrict__ stiles,
                                                 int64_t ntiles, const float* __restrict__ Ti,
                                                 const double* __restrict__ x, double* __restrict__ part) {
+    __shared__ float4 xs[4][64];                        // per wavefront: x_D, x_N at column c0 + l
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t tix = (int64_t)blockIdx.x * 4 + wv;
-    if (tix >= ntiles) return;                          // no workgroup barrier in this kernel
-    const int4 t = stiles[tix];
+    const bool live = tix < ntiles;
+    const int4 t = stiles[live ? tix : ntiles - 1];
     const DomDesc dd = doms[t.x];
     const int E = dd.E;
     const int I = t.y, J = t.z;
     const int r0 = I * 64, c0 = J * 64;
     const int rg = lane & 15, cg = lane >> 4;
     const bool diag = I == J;
-    // rows past E are not clamped: they read the next column (or, after the last column, at most
-    // 63 entries into the 64-entry padding behind the inverse blocks) and are masked below, so the
-    // four loads of a column share one address
-    const float2* Tb = reinterpret_cast<const float2*>(Ti) + dd.mat0 + r0 + rg;
-    int rsafe[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = r0 + rg + 16 * i;
-        rsafe[i] = r < E ? r : E - 1;
-    }
-    float2 a[16][4];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const int c = c0 + 4 * k + cg;
-        const int cs = c < E ? c : E - 1;
-        const float2* pc = Tb + (int64_t)cs * E;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) a[k][i] = pc[16 * i];
-    }
     const double2* xD = reinterpret_cast<const double2*>(x) + dd.off;
-    const double2* xN = reinterpret_cast<const double2*>(x) + dd.off + E;
-    float xr[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const bool ok = r0 + rg + 16 * i < E;
-        const double2 d = xD[rsafe[i]], nn = xN[rsafe[i]];
-        xr[i][0] = ok ? (float)d.x : 0.f; xr[i][1] = ok ? (float)d.y : 0.f;
-        xr[i][2] = ok ? (float)nn.x : 0.f; xr[i][3] = ok ? (float)nn.y : 0.f;
-    }
-    float xc[4];
+    const double2* xN = xD + E;
     {
         const int c = c0 + lane;
         const bool ok = c < E;
         const int cs = ok ? c : E - 1;
         const double2 d = xD[cs], nn = xN[cs];
-        xc[0] = ok ? (float)d.x : 0.f; xc[1] = ok ? (float)d.y : 0.f;
-        xc[2] = ok ? (float)nn.x : 0.f; xc[3] = ok ? (float)nn.y : 0.f;
+        xs[wv][lane] = ok ? make_float4((float)d.x, (float)d.y, (float)nn.x, (float)nn.y) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    __syncthreads();
+    if (!live) return;                                  // no workgroup barrier below
+    const char* Tt = reinterpret_cast<const char*>(reinterpret_cast<const float2*>(Ti) + dd.mat0 + r0 + (int64_t)c0 * E);
+    constexpr int NS = D + 1;                           // ring of column-group register slots
+    float2 a[NS][4];
+    auto load = [&](int k, int slot) {
+        const int c = c0 + 4 * k + cg;
+        const int cs = c < E ? c : E - 1;
+        const uint32_t boff = ((uint32_t)rg + (uint32_t)(cs - c0) * (uint32_t)E) * (uint32_t)sizeof(float2);
+        const float2* tp = reinterpret_cast<const float2*>(Tt + boff);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[slot][i] = tp[16 * i];
+    };
+    float xr[4][4];                                     // x_D, x_N of this lane's rows (0 past E)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = r0 + rg + 16 * i;
+        const bool ok = r < E;
+        const int rs = ok ? r : E - 1;
+        const double2 d = xD[rs], nn = xN[rs];
+        xr[i][0] = ok ? (float)d.x : 0.f; xr[i][1] = ok ? (float)d.y : 0.f;
+        xr[i][2] = ok ? (float)nn.x : 0.f; xr[i][3] = ok ? (float)nn.y : 0.f;
     }
     float acc[4][4];
 #pragma unroll
@@ -290,34 +326,43 @@ __global__ __launch_bounds__(256) void k_pc_sym(const DomDesc* __restrict__ doms
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[i][q] = 0.f;
     double* pbase = part + 2 * dd.part0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
+    auto step = [&](int k, auto slot, auto issue) {
+        constexpr int sl = decltype(slot)::value;
+        if constexpr (decltype(issue)::value) load(k + D, (sl + D) % NS);
         const int c = c0 + 4 * k + cg;
-        const bool cok = c < E;
-        const float dr = __shfl(xc[0], 4 * k + cg, 64), di = __shfl(xc[1], 4 * k + cg, 64);
-        const float nr = __shfl(xc[2], 4 * k + cg, 64), ni = __shfl(xc[3], 4 * k + cg, 64);
-        float s[4] = {0.f, 0.f, 0.f, 0.f};             // transposed: S x_D, S x_N of row c
+        const float4 xv = xs[wv][4 * k + cg];
+        float e[4][2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { e[i][0] = a[sl][i].x; e[i][1] = a[sl][i].y; }
+        if (diag) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = r0 + rg + 16 * i;
+                const float w = r < c ? 1.f : (r == c ? 0.5f : 0.f);
+                e[i][0] *= w;
+                e[i][1] *= w;
+            }
+        }
+        float v[4] = {0.f, 0.f, 0.f, 0.f};              // transposed: S x_D, S x_N of row c
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int r = r0 + rg + 16 * i;
-            const bool dok = cok && r < E && (!diag || r <= c);
-            const float ar = dok ? a[k][i].x : 0.f, ai = dok ? a[k][i].y : 0.f;
-            acc[i][0] += ar * dr - ai * di; acc[i][1] += ar * di + ai * dr;
-            acc[i][2] += ar * nr - ai * ni; acc[i][3] += ar * ni + ai * nr;
-            const bool tok = !diag || r < c;
-            const float tr = tok ? ar : 0.f, ti = tok ? ai : 0.f;
-            s[0] += tr * xr[i][0] - ti * xr[i][1]; s[1] += tr * xr[i][1] + ti * xr[i][0];
-            s[2] += tr * xr[i][2] - ti * xr[i][3]; s[3] += tr * xr[i][3] + ti * xr[i][2];
+            cfmaf(acc[i][0], acc[i][1], e[i][0], e[i][1], xv.x, xv.y);
+            cfmaf(acc[i][2], acc[i][3], e[i][0], e[i][1], xv.z, xv.w);
+            cfmaf(v[0], v[1], e[i][0], e[i][1], xr[i][0], xr[i][1]);
+            cfmaf(v[2], v[3], e[i][0], e[i][1], xr[i][2], xr[i][3]);
         }
+        // lanes rg = 0, 1, 2, 3 hold the sums of v_D re, v_N re, v_D im, v_N im of row c
+        const float u = row16_sum4(v, rg);
+        if (rg < 4 && c < E) pbase[2 * ((int64_t)(2 * I + (rg & 1)) * E + c) + (rg >> 1)] = (double)u;
+    };
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s[q] = row16_sum(s[q]);
-        if (rg == 0 && cok) {
-            double* pD = pbase + 2 * ((int64_t)(2 * I) * E + c);
-            double* pN = pbase + 2 * ((int64_t)(2 * I + 1) * E + c);
-            pD[0] = s[0]; pD[1] = s[1];
-            pN[0] = s[2]; pN[1] = s[3];
-        }
-    }
+    for (int k = 0; k < D; ++k) load(k, k);
+    // full rounds of NS steps keep every slot index compile-time; the last steps, some of which
+    // issue no load, follow
+    constexpr int kFull = ((16 - D) / NS) * NS;
+#pragma unroll 1
+    for (int k = 0; k < kFull; k += NS) ring_round<NS>(step, k, std::make_integer_sequence<int, NS>{});
+    ring_tail<NS, kFull, D, 16>(step, std::make_integer_sequence<int, 16 - kFull>{});
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -332,8 +377,8 @@ __global__ __launch_bounds__(256) void k_pc_sym(const DomDesc* __restrict__ doms
         if (r >= E) continue;
         double* pD = pbase + 2 * ((int64_t)(2 * (J + 1)) * E + r);
         double* pN = pbase + 2 * ((int64_t)(2 * (J + 1) + 1) * E + r);
-        pD[0] = acc[i][0]; pD[1] = acc[i][1];
-        pN[0] = acc[i][2]; pN[1] = acc[i][3];
+        *reinterpret_cast<double2*>(pD) = make_double2(acc[i][0], acc[i][1]);
+        *reinterpret_cast<double2*>(pN) = make_double2(acc[i][2], acc[i][3]);
     }
 }
 
@@ -529,39 +574,40 @@ __device__ inline double wsum(double v) {
 
 // hpart[((b*(nvmax+1) + i)*nblk + blk)*4 + {0,1,2,3}] = partial {conj(v_i).u, conj(v_i).t},
 // v_i = V_i for i < j and v_j = u = V_j; t = Tt (slab, ld n), or u itself when Tt is null.
-// blockIdx.y strides over the vectors.
+// blockIdx.y strides over groups of 16 vectors.
 __global__ __launch_bounds__(256) void k_dot2(const double* __restrict__ V, int64_t ldv, const int* __restrict__ jdev,
                                               int nvmax, const double* __restrict__ Tt, int64_t n,
                                               double* __restrict__ hpart, int nblk) {
+    // Row chunk blockIdx.x of the basis against 16 vectors per workgroup: lane (rg = l % 16,
+    // g = l / 16) of wavefront w takes vector 16 vg + 4 w + g and rows lo + rg + 16 m, so that a
+    // load instruction reads 16 consecutive rows of four vectors and the 16 row lanes of a vector
+    // meet in one cross-lane reduction at the end of the chunk.
     const int nv = jdev[0];
     const int b = blockIdx.z;
     const int blk = blockIdx.x;
     const int64_t chunk = (n + nblk - 1) / nblk;
     const int64_t lo = blk * chunk, hi = min(n, lo + chunk);
-    const double* u = V + 2 * ((int64_t)nv * ldv + (int64_t)b * n);
-    const double* t = Tt ? Tt + 2 * (int64_t)b * n : u;
-    __shared__ double red[4][4];
-    for (int i = blockIdx.y; i <= nv; i += gridDim.y) {
-        const double* v = V + 2 * ((int64_t)i * ldv + (int64_t)b * n);
-        double ur = 0, ui = 0, tr = 0, ti = 0;
-        for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-            const double vr = v[2 * e], vi = v[2 * e + 1];
-            const double a = u[2 * e], c = u[2 * e + 1], d = t[2 * e], f = t[2 * e + 1];
-            ur += vr * a + vi * c;
-            ui += vr * c - vi * a;
-            tr += vr * d + vi * f;
-            ti += vr * f - vi * d;
+    const double2* u = reinterpret_cast<const double2*>(V + 2 * ((int64_t)nv * ldv + (int64_t)b * n));
+    const double2* t = Tt ? reinterpret_cast<const double2*>(Tt + 2 * (int64_t)b * n) : u;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int rg = lane & 15, g = lane >> 4;
+    for (int vg = blockIdx.y; vg * 16 <= nv; vg += gridDim.y) {
+        const int i = vg * 16 + w * 4 + g;
+        const int is = i <= nv ? i : nv;
+        const double2* v = reinterpret_cast<const double2*>(V + 2 * ((int64_t)is * ldv + (int64_t)b * n));
+        double a[4] = {0, 0, 0, 0};                     // conj(v) u (re, im), conj(v) t (re, im)
+#pragma unroll 4
+        for (int64_t e = lo + rg; e < hi; e += 16) {
+            const double2 x = v[e], uu = u[e], tt = t[e];
+            a[0] = fma(x.x, uu.x, fma(x.y, uu.y, a[0]));
+            a[1] = fma(x.x, uu.y, fma(-x.y, uu.x, a[1]));
+            a[2] = fma(x.x, tt.x, fma(x.y, tt.y, a[2]));
+            a[3] = fma(x.x, tt.y, fma(-x.y, tt.x, a[3]));
         }
-        ur = wsum(ur); ui = wsum(ui); tr = wsum(tr); ti = wsum(ti);
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        if (lane == 0) { red[0][wv] = ur; red[1][wv] = ui; red[2][wv] = tr; red[3][wv] = ti; }
-        __syncthreads();
-        if (threadIdx.x < 4) {
-            double acc = 0;
-            for (int k = 0; k < (int)(blockDim.x >> 6); ++k) acc += red[threadIdx.x][k];
-            hpart[(((int64_t)b * (nvmax + 1) + i) * nblk + blk) * 4 + threadIdx.x] = acc;
-        }
-        __syncthreads();
+        // lanes rg = 0, 1, 2, 3 hold the sums of a[0], a[2], a[1], a[3]
+        const double sum = row16_sum4(a, rg);
+        if (i <= nv && rg < 4)
+            hpart[(((int64_t)b * (nvmax + 1) + i) * nblk + blk) * 4 + 2 * (rg & 1) + (rg >> 1)] = sum;
     }
 }
 
@@ -1172,7 +1218,7 @@ void launch_matvec_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int64
 void launch_precond_sym(const DomDesc* doms, const int4* stiles, int64_t ntiles, const float* Tinv, const double* x,
                         double* part, hipStream_t s) {
     if (ntiles <= 0) return;
-    hipLaunchKernelGGL(k_pc_sym, dim3(gridn(ntiles, 4)), dim3(256), 0, s, doms, stiles, ntiles, Tinv, x, part);
+    hipLaunchKernelGGL(k_pc_sym<kPcDepth>, dim3(gridn(ntiles, 4)), dim3(256), 0, s, doms, stiles, ntiles, Tinv, x, part);
 }
 
 void launch_precond_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int64_t ndof, const double* part, double* z,
@@ -1196,7 +1242,7 @@ void launch_gs_residual(const DomDesc* doms, const int32_t* dof_dom, const int32
 
 void launch_dot2(const double* V, int64_t ldv, const int* jdev, int nvmax, const double* t, int64_t n, double* hpart,
                  int nblk, int nb, hipStream_t s) {
-    const int gy = std::max(8, std::min(nvmax + 1, 16384 / (nblk * nb)));   // about 16k workgroups
+    const int gy = std::max(1, std::min((nvmax + 16) / 16, 4096 / (nblk * nb)));   // 16 vectors per workgroup
     hipLaunchKernelGGL(k_dot2, dim3((unsigned)nblk, (unsigned)gy, (unsigned)nb), dim3(256), 0, s, V, ldv, jdev, nvmax, t,
                        n, hpart, nblk);
 }
