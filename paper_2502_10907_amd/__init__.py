@@ -33,6 +33,7 @@ FP64, FP32_MIXED, BF16_SPLIT = 0, 1, 2
 BLOCK_T, BLOCK_K = 0, 1
 PREC_NONE, PREC_BLOCK_TINV, PREC_BLOCK_TINV_GS = 0, 1, 2
 SOLVE_EAGER = 1
+ASSEMBLE_ROUND_FP64 = 1
 
 
 class MTFError(RuntimeError):
@@ -228,8 +229,8 @@ class Problem:
         return ev, pt
 
     # -- assembly ------------------------------------------------------------
-    def assemble(self, precision: int = FP64, singular_order: int = 4):
-        o = AssemblyOpts(C.sizeof(AssemblyOpts), int(precision), int(singular_order), 0)
+    def assemble(self, precision: int = FP64, singular_order: int = 4, flags: int = 0):
+        o = AssemblyOpts(C.sizeof(AssemblyOpts), int(precision), int(singular_order), int(flags))
         _check(_lib.mtf_assemble(self._h, C.byref(o)))
 
     def assembly_stats(self):

@@ -323,14 +323,20 @@ void ensure_ss(mtf_problem p, int order) {
     p->ss_order = order;
 }
 
-void parse_assembly_opts(const mtf_assembly_opts* o, int* prec, int* order) {
+void parse_assembly_opts(const mtf_assembly_opts* o, int* prec, int* order, int* flags = nullptr) {
     *prec = MTF_FP64;
     *order = 4;
+    int fl = 0;
     if (o) {
         if (o->struct_size < (int)sizeof(mtf_assembly_opts)) throw ArgError("mtf_assembly_opts.struct_size too small");
         *prec = o->precision;
         if (o->singular_order) *order = o->singular_order;
+        fl = o->flags;
     }
+    if (fl & ~MTF_ASSEMBLE_ROUND_FP64) throw ArgError("unknown assembly flags");
+    if (fl && !flags) throw ArgError("MTF_ASSEMBLE_ROUND_FP64 applies to mtf_assemble only");
+    if (fl && *prec != MTF_FP32_MIXED) throw ArgError("MTF_ASSEMBLE_ROUND_FP64 applies to MTF_FP32_MIXED");
+    if (flags) *flags = fl;
     if (*prec != MTF_FP64 && *prec != MTF_FP32_MIXED) throw ArgError("unknown precision");
     if (*order < 1 || *order > 8) throw ArgError("singular_order must be in 1..8");
 }
@@ -373,13 +379,29 @@ void near_corrections(mtf_problem p, int prec) {
 
 void assemble_impl(mtf_problem p, const mtf_assembly_opts* o) {
     if (!p->has_mesh || !p->has_mat) throw StateError("mtf_assemble needs mtf_set_mesh and mtf_set_materials first");
-    int prec, order;
-    parse_assembly_opts(o, &prec, &order);
+    int prec, order, flags;
+    parse_assembly_opts(o, &prec, &order, &flags);
     DeviceGuard g(p->device);
-    ensure_ss(p, order);
     hipStream_t s = p->stream;
     if (!p->ev0) { HIPCHK(hipEventCreate(&p->ev0)); HIPCHK(hipEventCreate(&p->ev1)); }
     const int64_t n2 = mat_alloc_reals(p);
+    if (flags & MTF_ASSEMBLE_ROUND_FP64) {
+        // complex64 blocks rounded from the FP64 ones (padding included)
+        if (!p->have64) throw StateError("MTF_ASSEMBLE_ROUND_FP64 needs the FP64 blocks: assemble MTF_FP64 first");
+        p->T32.alloc(n2); p->K32.alloc(n2);
+        HIPCHK(hipEventRecord(p->ev0, s));
+        launch_copy_block_f64_to_f32(p->T64.p, p->T32.p, n2, s);
+        launch_copy_block_f64_to_f32(p->K64.p, p->K32.p, n2, s);
+        near_corrections(p, MTF_FP32_MIXED);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipEventRecord(p->ev1, s));
+        p->have32 = true;
+        p->gm.haveA = false;
+        p->have_tinv = false;
+        p->gp.haveA = false;
+        return;
+    }
+    ensure_ss(p, order);
     if (prec == MTF_FP64) { p->T64.alloc(n2); p->K64.alloc(n2); }
     else { p->T32.alloc(n2); p->K32.alloc(n2); }
     HIPCHK(hipEventRecord(p->ev0, s));
@@ -681,6 +703,18 @@ void apply_pc(mtf_problem p, int pc, int prec, int nb, const double* x, double* 
     }
 }
 
+// ||(M_32 - M_64) v|| / ||M_64 v|| for one vector v (device, length N): the relative accuracy of
+// the complex64 operator, which sets where a mixed solve may switch to it.
+double operator_gap(mtf_problem p, const double* v) {
+    GmresWork& w = p->gw;
+    matvec1(p, v, w.tmp.p, MTF_FP64);
+    matvec1(p, v, w.tmp2.p, MTF_FP32_MIXED);
+    const double n64 = norms_dev(p, w.tmp.p, w.n, 1)[0];
+    launch_axpby(w.tmp2.p, w.tmp.p, w.n, 1.0, 0.0, -1.0, p->stream);   // tmp2 = tmp - tmp2
+    const double nd = norms_dev(p, w.tmp2.p, w.n, 1)[0];
+    return n64 > 0.0 ? nd / n64 : 0.0;
+}
+
 // dst = M P src; the preconditioned slab P src goes to zout (or to scratch when zout is null)
 void apply_inner(mtf_problem p, const double* src, double* dst, int nb, int prec, int pc, double* zout) {
     GmresWork& w = p->gw;
@@ -713,7 +747,7 @@ void apply_inner(mtf_problem p, const double* src, double* dst, int nb, int prec
 // Returns the number of Arnoldi steps taken; it[b], est[b] (recurrence residual / ||r_b||) per column.
 int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, int prec, int pc,
                 const std::vector<double>& tol, int maxit, std::vector<int>& itv, std::vector<double>& est,
-                std::vector<int>& reorth, bool graph) {
+                std::vector<int>& reorth, bool graph, double relax) {
     GmresWork& w = p->gw;
     hipStream_t s = p->stream;
     const int64_t n = w.n;
@@ -732,11 +766,14 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
     HIPCHK(hipMemcpyAsync(V, R, (size_t)2 * n * nb * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(w.ufix.p, R, (size_t)2 * n * nb * sizeof(double), hipMemcpyDeviceToDevice, s));
     launch_set_int(jslot(0), 0, s);
+    // Relaxed products (complex64 operator only): the steps use the FP64 operator until every
+    // live recurrence residual is at most relax times its initial value, the complex64 one after.
+    int cur_prec = prec == MTF_FP32_MIXED && relax < 1.0 ? MTF_FP64 : prec;
     // one Arnoldi step with index jj (the kernels read jj from the device, so only its parity matters
     // to the launch sequence)
     auto step = [&](int jj) {
         const int* jr = jslot(jj);
-        apply_inner(p, w.ufix.p, w.tfix.p, nb, prec, pc, flex ? w.zfix.p : nullptr);
+        apply_inner(p, w.ufix.p, w.tfix.p, nb, cur_prec, pc, flex ? w.zfix.p : nullptr);
         launch_dot2(V, ldv, jr, nvmax, w.tfix.p, n, w.hpart.p, kNblk, nb, s);
         launch_reduce2(w.hpart.p, jr, nvmax, kNblk, w.S.p, w.Z.p, nb, s);
         launch_hess_gemv(w.H.p, ldh, hstride, w.S.p, jr, nvmax, nct, w.hg.p, nb, s);
@@ -852,6 +889,15 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
             sync(p);
             process(j - kSync - 1, kSync);
             done_cols = j - 1;
+            if (cur_prec != prec) {
+                bool below = true;
+                for (int b = 0; b < nb; ++b)
+                    if (!stop[b] && resid[b] > relax * beta[b]) below = false;
+                if (below) {
+                    cur_prec = prec;                 // the captured batch holds the FP64 product
+                    if (exec) { HIPCHK(hipGraphExecDestroy(exec)); exec = nullptr; }
+                }
+            }
             continue;
         }
         // tail: the remaining steps one by one, then the step that only finalises column maxit-1
@@ -972,6 +1018,7 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
         std::vector<double> rel(nb, 1.0), est;
         std::vector<char> conv(nb, 0);
         int total = 0;
+        double delta = -1.0;
         for (int outer = 0; outer <= maxref; ++outer) {
             // true residuals with the FP64 operator
             for (int b = 0; b < nb; ++b) {
@@ -991,10 +1038,19 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
                 double t = opts.rtol * bn[b] / rn[b];
                 if (prec != MTF_FP64) t = std::max(t, opts.inner_rtol > 0 ? opts.inner_rtol : 1e-6);
                 else if (opts.inner_rtol > 0) t = std::max(t, opts.inner_rtol);
-                tol[b] = 0.9 * t;
+                // the complex64 cycle leaves room for the gap its products open between the
+                // recurrence and the FP64 residual
+                tol[b] = (prec == MTF_FP32_MIXED ? 0.5 : 0.9) * t;
             }
             if (all || outer == maxref || total >= maxit * (maxref + 1)) break;
-            total += gmres_cycle(p, w.r.p, X, ld, nb, prec, pc, tol, maxit, itv, est, reorth, graph);
+            double relax = 1.0;
+            if (prec == MTF_FP32_MIXED && nb == 1) {
+                // relative difference of the two operators on this residual; the complex64 products
+                // are admitted once the recurrence residual has fallen to 1% of tol / delta
+                if (delta < 0.0) delta = operator_gap(p, w.r.p);
+                if (delta > 0.0) relax = std::min(1.0, 0.01 * tol[0] / delta);
+            }
+            total += gmres_cycle(p, w.r.p, X, ld, nb, prec, pc, tol, maxit, itv, est, reorth, graph, relax);
             for (int b = 0; b < nb; ++b) iters[b] += itv[b];
         }
         const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

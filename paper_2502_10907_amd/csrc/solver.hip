@@ -79,12 +79,30 @@ __device__ inline F row16_sum4(const F (&v)[4], int rg) {
     return u;
 }
 
+// a * b + c in the precision of the operands
+__device__ inline float fmat(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ inline double fmat(double a, double b, double c) { return fma(a, b, c); }
+
 // acc += a * b for complex a = (ar, ai), b = (br, bi) as four FMAs
-__device__ inline void cfma(double& re, double& im, double ar, double ai, double br, double bi) {
-    re = fma(ar, br, re);
-    re = fma(-ai, bi, re);
-    im = fma(ar, bi, im);
-    im = fma(ai, br, im);
+template <typename F>
+__device__ inline void cfma(F& re, F& im, F ar, F ai, F br, F bi) {
+    re = fmat(ar, br, re);
+    re = fmat(-ai, bi, re);
+    im = fmat(ar, bi, im);
+    im = fmat(ai, br, im);
+}
+
+// Steps k + j (j < NS) of a register-slot ring, slot j, each issuing the load D groups ahead.
+template <int NS, typename Step, int... j>
+__device__ inline void ring_round(Step& step, int k, std::integer_sequence<int, j...>) {
+    (step(k + j, std::integral_constant<int, j>{}, std::true_type{}), ...);
+}
+
+// The remaining steps K0 + j of a ring over KN groups: slot (K0 + j) % NS, a load issued only
+// while group K0 + j + D exists.
+template <int NS, int K0, int D, int KN, typename Step, int... j>
+__device__ inline void ring_tail(Step& step, std::integer_sequence<int, j...>) {
+    (step(K0 + j, std::integral_constant<int, (K0 + j) % NS>{}, std::bool_constant<(K0 + j + D < KN)>{}), ...);
 }
 
 // Symmetric-read block matvec.  The separated-pair part of T_i and K_i is complex symmetric (the
@@ -110,7 +128,8 @@ __global__ __launch_bounds__(256, 2) void k_mv_sym(const DomDesc* __restrict__ d
                                                    int64_t ntiles, const RM* __restrict__ T, const RM* __restrict__ K,
                                                    const double* __restrict__ x, double* __restrict__ part) {
     using V2 = typename std::conditional<std::is_same<RM, double>::value, double2, float2>::type;
-    __shared__ double4 xs[4][64];                       // per wavefront: x_D, x_N at column c0 + l
+    using V4 = typename std::conditional<std::is_same<RM, double>::value, double4, float4>::type;
+    __shared__ V4 xs[4][64];                            // per wavefront: x_D, x_N at column c0 + l
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t tix = (int64_t)blockIdx.x * 4 + wv;
@@ -122,7 +141,7 @@ __global__ __launch_bounds__(256, 2) void k_mv_sym(const DomDesc* __restrict__ d
     const int r0 = I * 64, c0 = J * 64;
     const int rg = lane & 15, cg = lane >> 4;
     const bool diag = I == J;
-    const double rho = dd.rho, irho = 1.0 / rho;
+    const RM rho = (RM)dd.rho, irho = (RM)(1.0 / dd.rho);
     const double2* xD = reinterpret_cast<const double2*>(x) + dd.off;
     const double2* xN = xD + E;
     {
@@ -130,32 +149,34 @@ __global__ __launch_bounds__(256, 2) void k_mv_sym(const DomDesc* __restrict__ d
         const bool ok = c < E;
         const int cs = ok ? c : E - 1;
         const double2 d = xD[cs], nn = xN[cs];
-        xs[wv][lane] = make_double4(ok ? d.x : 0.0, ok ? d.y : 0.0, ok ? nn.x : 0.0, ok ? nn.y : 0.0);
+        xs[wv][lane] = V4{(RM)(ok ? d.x : 0.0), (RM)(ok ? d.y : 0.0), (RM)(ok ? nn.x : 0.0), (RM)(ok ? nn.y : 0.0)};
     }
     __syncthreads();
     if (!live) return;                                  // no workgroup barrier below
     // With A = 2 x_D, B = (2/rho) x_N = C / rho, C = 2 x_N and P = -rho A the 2x2 Calderon
     // block of a row is  y_D += K A + T B,  y_N += K C + T P.
-    double ra[4][2], rc[4][2];                          // A and C of this lane's rows (transposed part)
+    RM ra[4][2], rc[4][2];                              // A and C of this lane's rows (transposed part)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int r = r0 + rg + 16 * i;
         const bool ok = r < E;
         const int rs = ok ? r : E - 1;
         const double2 d = xD[rs], nn = xN[rs];
-        ra[i][0] = ok ? 2.0 * d.x : 0.0; ra[i][1] = ok ? 2.0 * d.y : 0.0;
-        rc[i][0] = ok ? 2.0 * nn.x : 0.0; rc[i][1] = ok ? 2.0 * nn.y : 0.0;
+        ra[i][0] = (RM)(ok ? 2.0 * d.x : 0.0); ra[i][1] = (RM)(ok ? 2.0 * d.y : 0.0);
+        rc[i][0] = (RM)(ok ? 2.0 * nn.x : 0.0); rc[i][1] = (RM)(ok ? 2.0 * nn.y : 0.0);
     }
     const int64_t tile0 = dd.mat0 + r0 + (int64_t)c0 * E;
     const char* Tt = reinterpret_cast<const char*>(reinterpret_cast<const V2*>(T) + tile0);
     const char* Kt = reinterpret_cast<const char*>(reinterpret_cast<const V2*>(K) + tile0);
-    double acc[4][4];                                   // per row: y_D (re, im), y_N (re, im)
+    RM acc[4][4];                                       // per row: y_D (re, im), y_N (re, im)
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[i][q] = 0.0;
+        for (int q = 0; q < 4; ++q) acc[i][q] = 0;
     double* pbase = part + 2 * dd.part0;
-    V2 tv[2][4], kv[2][4];
+    // ring of register slots: one column group ahead in FP64 (register bound), three in FP32
+    constexpr int D = std::is_same<RM, double>::value ? 1 : 3, NS = D + 1;
+    V2 tv[NS][4], kv[NS][4];
     auto load = [&](int k, int slot) {
         const int c = c0 + 4 * k + cg;
         const int cs = c < E ? c : E - 1;
@@ -172,30 +193,30 @@ __global__ __launch_bounds__(256, 2) void k_mv_sym(const DomDesc* __restrict__ d
     // whether a load is issued are compile-time, so no register set is kept alive across a branch)
     auto step = [&](int k, auto slot, auto issue) {
         constexpr int sl = decltype(slot)::value;
-        if constexpr (decltype(issue)::value) load(k + 1, (sl + 1) % 2);
+        if constexpr (decltype(issue)::value) load(k + D, (sl + D) % NS);
         const int c = c0 + 4 * k + cg;
-        const double4 xv = xs[wv][4 * k + cg];
-        const double Ar = 2.0 * xv.x, Ai = 2.0 * xv.y, Cr = 2.0 * xv.z, Ci = 2.0 * xv.w;
-        const double Br = irho * Cr, Bi = irho * Ci, Pr = -rho * Ar, Pi = -rho * Ai;
-        double e[4][4];                                 // T re, T im, K re, K im
+        const V4 xv = xs[wv][4 * k + cg];
+        const RM Ar = 2 * xv.x, Ai = 2 * xv.y, Cr = 2 * xv.z, Ci = 2 * xv.w;
+        const RM Br = irho * Cr, Bi = irho * Ci, Pr = -rho * Ar, Pi = -rho * Ai;
+        RM e[4][4];                                     // T re, T im, K re, K im
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            e[i][0] = (double)tv[sl][i].x; e[i][1] = (double)tv[sl][i].y;
-            e[i][2] = (double)kv[sl][i].x; e[i][3] = (double)kv[sl][i].y;
+            e[i][0] = tv[sl][i].x; e[i][1] = tv[sl][i].y;
+            e[i][2] = kv[sl][i].x; e[i][3] = kv[sl][i].y;
         }
         if (diag) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = r0 + rg + 16 * i;
-                const double w = r < c ? 1.0 : (r == c ? 0.5 : 0.0);
+                const RM w = r < c ? RM(1) : (r == c ? RM(0.5) : RM(0));
 #pragma unroll
                 for (int q = 0; q < 4; ++q) e[i][q] *= w;
             }
         }
-        double vD[2] = {0, 0}, vN[2] = {0, 0}, tr[2] = {0, 0}, tp[2] = {0, 0};
+        RM vD[2] = {0, 0}, vN[2] = {0, 0}, tr[2] = {0, 0}, tp[2] = {0, 0};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const double ar = e[i][0], ai = e[i][1], br = e[i][2], bi = e[i][3];
+            const RM ar = e[i][0], ai = e[i][1], br = e[i][2], bi = e[i][3];
             // direct, row r
             cfma(acc[i][0], acc[i][1], br, bi, Ar, Ai);
             cfma(acc[i][0], acc[i][1], ar, ai, Br, Bi);
@@ -207,22 +228,18 @@ __global__ __launch_bounds__(256, 2) void k_mv_sym(const DomDesc* __restrict__ d
             cfma(tr[0], tr[1], ar, ai, rc[i][0], rc[i][1]);
             cfma(tp[0], tp[1], ar, ai, ra[i][0], ra[i][1]);
         }
-        const double v[4] = {fma(irho, tr[0], vD[0]), fma(irho, tr[1], vD[1]), fma(-rho, tp[0], vN[0]),
-                             fma(-rho, tp[1], vN[1])};
+        const RM v[4] = {fmat(irho, tr[0], vD[0]), fmat(irho, tr[1], vD[1]), fmat(-rho, tp[0], vN[0]),
+                         fmat(-rho, tp[1], vN[1])};
         // lanes rg = 0, 1, 2, 3 hold the sums of y_D re, y_N re, y_D im, y_N im of row c
-        const double u = row16_sum4(v, rg);
-        if (rg < 4 && c < E) pbase[2 * ((int64_t)(2 * I + (rg & 1)) * E + c) + (rg >> 1)] = u;
+        const RM u = row16_sum4(v, rg);
+        if (rg < 4 && c < E) pbase[2 * ((int64_t)(2 * I + (rg & 1)) * E + c) + (rg >> 1)] = (double)u;
     };
-    using S0 = std::integral_constant<int, 0>;
-    using S1 = std::integral_constant<int, 1>;
-    load(0, 0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) load(k, k);
+    constexpr int kFull = ((16 - D) / NS) * NS;
 #pragma unroll 1
-    for (int k = 0; k < 14; k += 2) {
-        step(k, S0{}, std::true_type{});
-        step(k + 1, S1{}, std::true_type{});
-    }
-    step(14, S0{}, std::true_type{});
-    step(15, S1{}, std::false_type{});
+    for (int k = 0; k < kFull; k += NS) ring_round<NS>(step, k, std::make_integer_sequence<int, NS>{});
+    ring_tail<NS, kFull, D, 16>(step, std::make_integer_sequence<int, 16 - kFull>{});
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -237,16 +254,9 @@ __global__ __launch_bounds__(256, 2) void k_mv_sym(const DomDesc* __restrict__ d
         if (r >= E) continue;
         double* pD = pbase + 2 * ((int64_t)(2 * (J + 1)) * E + r);
         double* pN = pbase + 2 * ((int64_t)(2 * (J + 1) + 1) * E + r);
-        *reinterpret_cast<double2*>(pD) = make_double2(acc[i][0], acc[i][1]);
-        *reinterpret_cast<double2*>(pN) = make_double2(acc[i][2], acc[i][3]);
+        *reinterpret_cast<double2*>(pD) = make_double2((double)acc[i][0], (double)acc[i][1]);
+        *reinterpret_cast<double2*>(pN) = make_double2((double)acc[i][2], (double)acc[i][3]);
     }
-}
-
-__device__ inline void cfmaf(float& re, float& im, float ar, float ai, float br, float bi) {
-    re = fmaf(ar, br, re);
-    re = fmaf(-ai, bi, re);
-    im = fmaf(ar, bi, im);
-    im = fmaf(ai, br, im);
 }
 
 // Symmetric-read preconditioner product: v_D = S x_D, v_N = S x_N per subdomain with S the
@@ -258,19 +268,6 @@ __device__ inline void cfmaf(float& re, float& im, float ar, float ai, float br,
 // slots (D = 3 measured fastest on the Gauss-Seidel stages, large and small: three wavefronts
 // per SIMD with three groups in flight each).
 constexpr int kPcDepth = 3;
-
-// Steps k + j (j < NS) of a register-slot ring, slot j, each issuing the load D groups ahead.
-template <int NS, typename Step, int... j>
-__device__ inline void ring_round(Step& step, int k, std::integer_sequence<int, j...>) {
-    (step(k + j, std::integral_constant<int, j>{}, std::true_type{}), ...);
-}
-
-// The remaining steps K0 + j of a ring over KN groups: slot (K0 + j) % NS, a load issued only
-// while group K0 + j + D exists.
-template <int NS, int K0, int D, int KN, typename Step, int... j>
-__device__ inline void ring_tail(Step& step, std::integer_sequence<int, j...>) {
-    (step(K0 + j, std::integral_constant<int, (K0 + j) % NS>{}, std::bool_constant<(K0 + j + D < KN)>{}), ...);
-}
 
 template <int D>
 __global__ __launch_bounds__(256) void k_pc_sym(const DomDesc* __restrict__ doms, const int4* __restrict__ stiles,
@@ -346,10 +343,10 @@ __global__ __launch_bounds__(256) void k_pc_sym(const DomDesc* __restrict__ doms
         float v[4] = {0.f, 0.f, 0.f, 0.f};              // transposed: S x_D, S x_N of row c
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            cfmaf(acc[i][0], acc[i][1], e[i][0], e[i][1], xv.x, xv.y);
-            cfmaf(acc[i][2], acc[i][3], e[i][0], e[i][1], xv.z, xv.w);
-            cfmaf(v[0], v[1], e[i][0], e[i][1], xr[i][0], xr[i][1]);
-            cfmaf(v[2], v[3], e[i][0], e[i][1], xr[i][2], xr[i][3]);
+            cfma(acc[i][0], acc[i][1], e[i][0], e[i][1], xv.x, xv.y);
+            cfma(acc[i][2], acc[i][3], e[i][0], e[i][1], xv.z, xv.w);
+            cfma(v[0], v[1], e[i][0], e[i][1], xr[i][0], xr[i][1]);
+            cfma(v[2], v[3], e[i][0], e[i][1], xr[i][2], xr[i][3]);
         }
         // lanes rg = 0, 1, 2, 3 hold the sums of v_D re, v_N re, v_D im, v_N im of row c
         const float u = row16_sum4(v, rg);

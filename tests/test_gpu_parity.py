@@ -144,6 +144,38 @@ def test_solve_fp64(name, pc, request):
     assert np.linalg.norm(xs - c.x) / np.linalg.norm(c.x) < 1e-7
 
 
+def test_assemble_round_fp64_blocks_and_solve(cube):
+    """MTF_ASSEMBLE_ROUND_FP64: the complex64 blocks are the FP64 blocks rounded (bit for bit), and
+    the mixed solve on them (FP64 products first, complex64 once the recurrence residual is low,
+    FP64 residuals outside) reaches the FP64 tolerance and the LU solution."""
+    P = _gpu_problem(cube.cfg)
+    with pytest.raises(RuntimeError):
+        P.assemble(mtf.FP64, flags=mtf.ASSEMBLE_ROUND_FP64)      # the flag is for complex64 blocks
+    P.assemble(mtf.FP32_MIXED, flags=mtf.ASSEMBLE_ROUND_FP64)
+    for i in range(cube.pb.M + 1):
+        for which in (mtf.BLOCK_T, mtf.BLOCK_K):
+            b64 = P.copy_block(i, which)
+            b32 = P.copy_block(i, which, mtf.FP32_MIXED)
+            assert np.array_equal(b32, b64.astype(np.complex64).astype(np.complex128))
+    b = torch.tensor(cube.b[None, :], device="cuda")
+    x = torch.zeros_like(b)
+    st = P.solve(b, x, rtol=1e-9, precision=mtf.FP32_MIXED, preconditioner=mtf.PREC_BLOCK_TINV_GS)[0]
+    print(f"[cube rounded mixed] iterations {st.iterations} refinements {st.refinements} residual {st.rel_residual:.2e}",
+          flush=True)
+    assert st.converged and st.rel_residual <= 1e-9
+    xs = x[0].cpu().numpy()
+    assert np.linalg.norm(xs - cube.x) / np.linalg.norm(cube.x) < 1e-6
+
+
+def test_assemble_round_fp64_needs_fp64_blocks(cube):
+    m = cube.cfg["mesh"]
+    P = mtf.Problem(0)
+    P.set_mesh(m.xyz, m.tri, m.label, m.M)
+    P.set_materials(cube.cfg["k0"], cube.cfg["eps_r"], cube.cfg["mu_r"])
+    with pytest.raises(RuntimeError):
+        P.assemble(mtf.FP32_MIXED, flags=mtf.ASSEMBLE_ROUND_FP64)
+
+
 @pytest.mark.parametrize("name", CASES)
 def test_solve_mixed_refinement(name, request):
     """complex64 operator inside GMRES, FP64 residuals outside: reaches the FP64 tolerance."""
