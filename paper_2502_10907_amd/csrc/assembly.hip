@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace mtf {
 
@@ -154,7 +155,7 @@ __device__ inline void zero_moments(Moments<R>& m) {
 
 // Local blocks from the moments and their scatter (with RWG signs) into T and K.
 template <typename R, typename RO>
-__device__ inline void epilogue(const Moments<R>& m, const R* pa_all, const R* qb_all, const R* ca, const R* cb,
+__device__ __attribute__((always_inline)) inline void epilogue(const Moments<R>& m, const R* pa_all, const R* qb_all, const R* ca, const R* cb,
                                 const R* D, R k, const int32_t* dofx, const int32_t* dofy, const int32_t* sgx,
                                 const int32_t* sgy, int64_t mat0, int32_t E, RO* T, RO* K) {
     const R four_over_k2 = R(4) / (k * k);
@@ -208,7 +209,7 @@ __device__ inline void epilogue(const Moments<R>& m, const R* pa_all, const R* q
 // One 16 x 16 tile of separated pairs; all 256 threads of the workgroup must call it (it holds a
 // workgroup barrier); pairs outside Gamma_i or touching are skipped by predication.
 template <typename R>
-__device__ inline void regular_tile(const int4 tile, const DomDesc* __restrict__ doms, const TriGeom* __restrict__ geom,
+__device__ __attribute__((always_inline)) inline void regular_tile(const int4 tile, const DomDesc* __restrict__ doms, const TriGeom* __restrict__ geom,
                                     const int32_t* __restrict__ verts, const int32_t* __restrict__ tdof,
                                     const int8_t* __restrict__ tsign, R* __restrict__ T, R* __restrict__ K,
                                     LRec<R>* rec) {
@@ -250,7 +251,9 @@ __device__ inline void regular_tile(const int4 tile, const DomDesc* __restrict__
         for (int i = 0; i < 3; ++i) D[i] = (R)(X.c[i] - Y.c[i]);
         Moments<R> m;
         zero_moments(m);
-#pragma unroll
+        // FP64: one outer quadrature point at a time (the FP64 phase evaluations would otherwise spill)
+        constexpr int kUnrollQ = std::is_same<R, double>::value ? 1 : 6;
+#pragma unroll kUnrollQ
         for (int q = 0; q < 6; ++q) {
             const R x0 = X.q[3 * q], x1 = X.q[3 * q + 1], x2 = X.q[3 * q + 2];
             const R wq = X.w[q];
@@ -316,7 +319,7 @@ __device__ inline double wave_sum(double v) {
 
 // One touching pair per wavefront (no workgroup barrier): Sauter-Schwab points split over the
 // 64 lanes, moments reduced with shuffles, lane 0 scatters the local blocks.
-__device__ inline void singular_pair(const SingPair sp, const DomDesc* __restrict__ doms, const TriGeom* __restrict__ geom,
+__device__ __attribute__((always_inline)) inline void singular_pair(const SingPair sp, const DomDesc* __restrict__ doms, const TriGeom* __restrict__ geom,
                                      const int32_t* __restrict__ tdof, const int8_t* __restrict__ tsign,
                                      const double* __restrict__ ss_table, const int32_t* __restrict__ ss_off,
                                      const int32_t* __restrict__ ss_cnt, double* T64, double* K64, float* T32,

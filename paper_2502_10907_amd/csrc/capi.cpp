@@ -26,6 +26,7 @@ using cd = std::complex<double>;
 constexpr int kTile = 16;     // triangles per side of a separated-pair tile
 constexpr int kChunk = 64;    // columns per dense-matvec workgroup (matches solver.hip)
 constexpr int kNblk = 32;     // partial sums of GMRES reductions
+constexpr int kGjPanel = 256; // block width of the Gauss-Jordan inversion (64-wide leaves inside)
 constexpr int kSync = 8;      // Arnoldi steps between host reads of the Hessenberg columns
 constexpr int kMaxBatch = 64; // right-hand sides per lockstep GMRES batch (MFMA products)
 constexpr int kUpdGroups = 8; // partial-sum groups of the basis update
@@ -542,26 +543,39 @@ void precond1_gs(mtf_problem p, const double* x, double* z, double* w) {
     }
 }
 
-// In-place inverse of `batch` n x n complex64 matrices X + z*stride (ld n) by blocked Gauss-Jordan
-// elimination over 64-wide diagonal blocks P (pivoting within each diagonal block):
+// In-place inverse of `batch` n x n complex64 matrices X + z*stride (leading dimension ld) by
+// blocked Gauss-Jordan elimination over diagonal blocks P of width w <= W:
 //   X_PP <- X_PP^-1;  X_Pj <- X_PP X_Pj;  X_ij <- X_ij - X_iP X_Pj;  X_iP <- -X_iP X_PP   (i, j not in P)
-// The rank-64 update is one batched matrix-core GEMM over the whole matrix minus the band P.
-void block_gj_inverse(float* X, int n, int64_t stride, int batch, int* info, hipStream_t s) {
-    const int64_t ld = n;
-    for (int p0 = 0; p0 < n; p0 += 64) {
-        const int w = std::min(64, n - p0);
+// The rank-w update is one batched matrix-core GEMM over the whole matrix minus the band P; it
+// reads and writes the matrix once per block, so wider blocks cut the traffic.  X_PP is inverted
+// by the same elimination with 64-wide blocks (pivoting within each 64 x 64 leaf).  A panel is
+// updated in place when one workgroup tile spans its reduced dimension (128 rows, 64 columns);
+// otherwise through `tmp` (W * n complex entries per matrix) and a copy back.
+void block_gj_inverse(float* X, int n, int64_t ld, int64_t stride, int batch, int* info, hipStream_t s, int W,
+                      float* tmp) {
+    constexpr int kTileRows = 128, kTileCols = 64;
+    const int64_t ts = (int64_t)W * n;                 // tmp stride per matrix (complex entries)
+    for (int p0 = 0; p0 < n; p0 += W) {
+        const int w = std::min(W, n - p0);
         float* Xpp = X + 2 * (p0 + (int64_t)p0 * ld);
         float* Xrow = X + 2 * (int64_t)p0;            // row p0, column 0
         float* Xcol = X + 2 * ((int64_t)p0 * ld);     // row 0, column p0
-        launch_cinv_small_f32(Xpp, ld, stride, w, batch, info, s);
+        if (w <= 64) launch_cinv_small_f32(Xpp, ld, stride, w, batch, info, s);
+        else block_gj_inverse(Xpp, w, ld, stride, batch, info, s, 64, tmp);
         if (w == n) break;
-        CGemm r;                                      // row panel, in place
+        CGemm r;                                      // row panel
         r.m = w; r.n = n - w; r.k = w; r.batch = batch;
         r.A = Xpp; r.lda = ld; r.sA = stride;
         r.B = Xrow; r.ldb = ld; r.sB = stride;
-        r.D = Xrow; r.ldd = ld; r.sD = stride;
         r.cg0 = p0; r.cgw = w;
-        launch_cgemm_f32(r, s);
+        if (w <= kTileRows) {
+            r.D = Xrow; r.ldd = ld; r.sD = stride;
+            launch_cgemm_f32(r, s);
+        } else {
+            r.D = tmp; r.ldd = w; r.sD = ts; r.band_cd = 0;
+            launch_cgemm_f32(r, s);
+            launch_band_copy_f32(tmp, w, ts, Xrow, ld, stride, w, n - w, w, 0, p0, w, batch, s);
+        }
         CGemm t;                                      // rank-w update outside the band
         t.m = n - w; t.n = n - w; t.k = w; t.batch = batch; t.ar = -1.f; t.beta = 1.f;
         t.A = Xcol; t.lda = ld; t.sA = stride;
@@ -570,13 +584,19 @@ void block_gj_inverse(float* X, int n, int64_t stride, int batch, int* info, hip
         t.D = X; t.ldd = ld; t.sD = stride;
         t.rg0 = p0; t.rgw = w; t.cg0 = p0; t.cgw = w;
         launch_cgemm_f32(t, s);
-        CGemm c;                                      // column panel, in place
+        CGemm c;                                      // column panel
         c.m = n - w; c.n = w; c.k = w; c.batch = batch; c.ar = -1.f;
         c.A = Xcol; c.lda = ld; c.sA = stride;
         c.B = Xpp; c.ldb = ld; c.sB = stride;
-        c.D = Xcol; c.ldd = ld; c.sD = stride;
         c.rg0 = p0; c.rgw = w;
-        launch_cgemm_f32(c, s);
+        if (w <= kTileCols) {
+            c.D = Xcol; c.ldd = ld; c.sD = stride;
+            launch_cgemm_f32(c, s);
+        } else {
+            c.D = tmp; c.ldd = n - w; c.sD = ts; c.band_cd = 0;
+            launch_cgemm_f32(c, s);
+            launch_band_copy_f32(tmp, n - w, ts, Xcol, ld, stride, n - w, w, p0, w, w, 0, batch, s);
+        }
     }
 }
 
@@ -602,11 +622,21 @@ void build_tinv(mtf_problem p) {
         if (d.E > 0) launch_symmetrize_f32(p->Tinv.p + 2 * d.mat0, d.E, s);
     // consecutive subdomains of equal size are stored back to back and inverted as one batch
     const auto& D = p->doms;
+    int64_t tmp_entries = 0;                           // out-of-place panels: W * E per matrix of a batch
+    for (size_t a = 0; a < D.size();) {
+        size_t b = a + 1;
+        while (b < D.size() && D[b].E == D[a].E && D[b].mat0 == D[a].mat0 + (int64_t)(b - a) * D[a].E * D[a].E) ++b;
+        tmp_entries = std::max(tmp_entries, (int64_t)(b - a) * kGjPanel * D[a].E);
+        a = b;
+    }
+    DevBuf<float> gjtmp;
+    gjtmp.alloc(2 * std::max<int64_t>(tmp_entries, 1));
     for (size_t a = 0; a < D.size();) {
         size_t b = a + 1;
         const int64_t E = D[a].E;
         while (b < D.size() && D[b].E == E && D[b].mat0 == D[a].mat0 + (int64_t)(b - a) * E * E) ++b;
-        if (E > 0) block_gj_inverse(p->Tinv.p + 2 * D[a].mat0, (int)E, E * E, (int)(b - a), info.p, s);
+        if (E > 0) block_gj_inverse(p->Tinv.p + 2 * D[a].mat0, (int)E, E, E * E, (int)(b - a), info.p, s, kGjPanel,
+                                    gjtmp.p);
         a = b;
     }
     launch_nonfinite_check(p->Tinv.p, 2 * p->mat_entries, info.p + 1, s);

@@ -147,7 +147,12 @@ struct CGemm {
     float* D = nullptr;
     int64_t ldd = 0, sD = 0;
     int rg0 = 0x7fffffff, rgw = 0, cg0 = 0x7fffffff, cgw = 0;
+    int band_cd = 1;     // 0: C and D are compact (the skipped bands apply to A's rows and B's columns only)
 };
+// dst[(r + (r >= r0 ? rw : 0)) + (c + (c >= c0 ? cw : 0)) * ldd] = src[r + c * lds] for a rows x cols
+// complex64 block, batched (strides ss, sd)
+void launch_band_copy_f32(const float* src, int64_t lds, int64_t ss, float* dst, int64_t ldd, int64_t sd, int rows,
+                          int cols, int r0, int rw, int c0, int cw, int batch, hipStream_t s);
 void launch_cgemm_f32(const CGemm& g, hipStream_t s);
 // single product D = alpha A B + beta C (beta real)
 inline void launch_cgemm_f32(int m, int n, int k, float alpha_re, float alpha_im, const float* A, int64_t lda,

@@ -971,23 +971,35 @@ __global__ __launch_bounds__(256) void k_cgemm_mfma(const CGemm g) {
         const int gc = col0 + bc + 16 * q;
         pc[q] = gc + (gc >= g.cg0 ? g.cgw : 0);
     }
-    for (int k0 = 0; k0 < k; k0 += BK) {
+    // the next k-tile's global loads are issued before the matrix-core work on the current one
+    float2 va[8], vb[4];
+    auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int gk = k0 + ar_k + q;
-            const float2 v = (gr < m && gk < k) ? A2[pr + (int64_t)gk * g.lda] : make_float2(0.f, 0.f);
-            Ar[ar_k + q][ar_row] = v.x;
-            Ai[ar_k + q][ar_row] = v.y;
+            va[q] = (gr < m && gk < k) ? A2[pr + (int64_t)gk * g.lda] : make_float2(0.f, 0.f);
         }
         const int gk = k0 + bk;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int gc = col0 + bc + 16 * q;
-            const float2 v = (gc < n && gk < k) ? B2[gk + pc[q] * g.ldb] : make_float2(0.f, 0.f);
-            Br[bk][bc + 16 * q] = v.x;
-            Bi[bk][bc + 16 * q] = v.y;
+            vb[q] = (gc < n && gk < k) ? B2[gk + pc[q] * g.ldb] : make_float2(0.f, 0.f);
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < k; k0 += BK) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            Ar[ar_k + q][ar_row] = va[q].x;
+            Ai[ar_k + q][ar_row] = va[q].y;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            Br[bk][bc + 16 * q] = vb[q].x;
+            Bi[bk][bc + 16 * q] = vb[q].y;
         }
         __syncthreads();
+        if (k0 + BK < k) fetch(k0 + BK);
 #pragma unroll
         for (int kp = 0; kp < BK; kp += 2) {
             const int kk = kp + (lane >> 5);
@@ -1015,12 +1027,12 @@ __global__ __launch_bounds__(256) void k_cgemm_mfma(const CGemm g) {
         const floatx16& xi = sub == 0 ? ci0 : ci1;
         const int row = row0 + wm * 64 + sub * 32 + (lane & 31);
         if (row >= m) continue;
-        const int64_t prow = row + (row >= g.rg0 ? g.rgw : 0);
+        const int64_t prow = row + (g.band_cd && row >= g.rg0 ? g.rgw : 0);
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int col = col0 + wn * 32 + (i / 4) * 8 + (lane >> 5) * 4 + (i % 4);
             if (col >= n) continue;
-            const int64_t pcol = col + (col >= g.cg0 ? g.cgw : 0);
+            const int64_t pcol = col + (g.band_cd && col >= g.cg0 ? g.cgw : 0);
             float re = g.ar * xr[i] - g.ai * xi[i];
             float im = g.ar * xi[i] + g.ai * xr[i];
             if (g.beta != 0.f) {
@@ -1035,12 +1047,22 @@ __global__ __launch_bounds__(256) void k_cgemm_mfma(const CGemm g) {
     }
 }
 
+// (value, index) <- the better of its own and the DPP partner's: larger value, smaller index on ties
+template <int CTRL>
+__device__ inline void argmax_step(float& v, int& i) {
+    const float ov = dpp_f<CTRL>(v);
+    const int oi = __builtin_amdgcn_mov_dpp(i, CTRL, 0xF, 0xF, false);
+    const bool better = (ov > v) | ((ov == v) & (oi < i));
+    v = better ? ov : v;
+    i = better ? oi : i;
+}
+
 // In-place inverse of n x n (n <= 64) complex64 blocks by Gauss-Jordan elimination with partial
 // pivoting; one workgroup of 1024 threads per block (blockIdx.x), the block held in LDS.  Thread
 // (lane c, wavefront w) owns column c of rows w, w+16, w+32, w+48.  Per elimination step k:
-//  A. every thread combines the 16 per-wavefront candidates for the pivot of column k (largest
-//     modulus, smallest row on ties) and the scaled pivot row, the multipliers (rows k and p
-//     exchanged) and the old row k are staged in LDS;
+//  A. every wavefront reduces the 16 per-wavefront candidates for the pivot of column k (largest
+//     modulus, smallest row on ties) across one row of lanes, and the scaled pivot row, the
+//     multipliers (rows k and p exchanged) and the old row k are staged in LDS;
 //  B. every thread updates its four entries (loads first, then stores); the owners of column k+1
 //     leave their candidate for the next pivot.
 // Two barriers per step.  The row exchanges become one column permutation, composed in registers
@@ -1073,21 +1095,16 @@ __global__ __launch_bounds__(1024) void k_cinv_small(float* A, int64_t lda, int6
     __syncthreads();
     for (int k = 0; k < n; ++k) {
         const int sl = k & 1;
-        float cvals[16];
-        int cidx[16];
-#pragma unroll
-        for (int w = 0; w < 16; ++w) {      // all loads first, then branch-free selection
-            cvals[w] = cv[sl][w];
-            cidx[w] = ci[sl][w];
-        }
-        float best = cvals[0];
-        int p = cidx[0];
-#pragma unroll
-        for (int w = 1; w < 16; ++w) {
-            const bool better = (cvals[w] > best) | ((cvals[w] == best) & (cidx[w] < p));
-            best = better ? cvals[w] : best;
-            p = better ? cidx[w] : p;
-        }
+        // lanes 0..15 of every wavefront take one candidate each and reduce them across the row of
+        // 16 lanes (DPP); lane 0's result is the pivot
+        float bv = lane < 16 ? cv[sl][lane] : -2.f;
+        int bi = lane < 16 ? ci[sl][lane] : 0x7fffffff;
+        argmax_step<kDppXor1>(bv, bi);
+        argmax_step<kDppXor2>(bv, bi);
+        argmax_step<kDppHalfMirror>(bv, bi);
+        argmax_step<kDppMirror>(bv, bi);
+        const float best = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(bv)));
+        const int p = __builtin_amdgcn_readfirstlane(bi);
         if (tid == 0) {
             piv[k] = p;
             if (!(best > 0.f)) info[0] = k + 1;
@@ -1166,6 +1183,16 @@ __global__ __launch_bounds__(1024) void k_cinv_small(float* A, int64_t lda, int6
     __syncthreads();
     for (int c = wv; c < n; c += 16)
         if (lane < n) A2[lane + (int64_t)c * lda] = M[lane][perm[c]];
+}
+
+__global__ void k_band_copy(const float2* __restrict__ src, int64_t lds, int64_t ss, float2* __restrict__ dst,
+                            int64_t ldd, int64_t sd, int rows, int cols, int r0, int rw, int c0, int cw) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)rows * cols) return;
+    const int r = (int)(e % rows), c = (int)(e / rows);
+    const int64_t z = blockIdx.y;
+    const int64_t pr = r + (r >= r0 ? rw : 0), pc = c + (c >= c0 ? cw : 0);
+    dst[z * sd + pr + pc * ldd] = src[z * ss + r + (int64_t)c * lds];
 }
 
 __global__ void k_copy_d2f(const double* __restrict__ s, float* __restrict__ d, int64_t n) {
@@ -1308,6 +1335,14 @@ void launch_copy_block_f64_to_f32(const double* src, float* dst, int64_t n, hipS
 void launch_cgemm_f32(const CGemm& g, hipStream_t s) {
     if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return;
     hipLaunchKernelGGL(k_cgemm_mfma, dim3(gridn(g.m, 128), gridn(g.n, 64), (unsigned)g.batch), dim3(256), 0, s, g);
+}
+
+void launch_band_copy_f32(const float* src, int64_t lds, int64_t ss, float* dst, int64_t ldd, int64_t sd, int rows,
+                          int cols, int r0, int rw, int c0, int cw, int batch, hipStream_t s) {
+    if (rows <= 0 || cols <= 0 || batch <= 0) return;
+    hipLaunchKernelGGL(k_band_copy, dim3(gridn((int64_t)rows * cols, 256), (unsigned)batch), dim3(256), 0, s,
+                       reinterpret_cast<const float2*>(src), lds, ss, reinterpret_cast<float2*>(dst), ldd, sd, rows,
+                       cols, r0, rw, c0, cw);
 }
 
 int launch_cinv_small_f32(float* A, int64_t lda, int64_t stride, int n, int batch, int* info, hipStream_t s) {
