@@ -72,6 +72,10 @@ extern "C" {
  * columns are captured once per GMRES cycle as a HIP graph and replayed; MTF_SOLVE_EAGER launches
  * the same kernels one by one instead (same results). */
 #define MTF_SOLVE_EAGER 1
+/* Build every block of the T_i^-1 preconditioners from T_i itself (read whole when applied)
+ * instead of from its symmetric part; see mtf_solve.  Rebuilds the blocks when the last build
+ * used the other kind. */
+#define MTF_SOLVE_PC_FULL 2
 
 typedef struct mtf_problem_s* mtf_problem;
 
@@ -194,7 +198,7 @@ typedef struct {
     int32_t max_iters;        /* Arnoldi steps per GMRES cycle; 0: as many as half the free
                                  device memory holds, at most 8000 (2000 for lockstep batches) */
     int32_t max_refinements;  /* outer FP64 refinement steps (MTF_FP32_MIXED), 0 = 10        */
-    int32_t flags;            /* 0, or MTF_SOLVE_EAGER                                       */
+    int32_t flags;            /* 0, or MTF_SOLVE_EAGER and/or MTF_SOLVE_PC_FULL              */
     double  rtol;             /* ||b - M x||_2 <= rtol ||b||_2 with the FP64 operator        */
     double  inner_rtol;       /* inner GMRES tolerance of a refinement step, 0 = 1e-3*... */
     const void* x0_dev;       /* complex128 initial guess [nrhs][ld] or NULL (zero)          */
@@ -221,6 +225,8 @@ typedef struct {
  * part, which differs from T_i only by the quadrature asymmetry of touching pairs; the
  * block shape of the block-OSRC preconditioner of Section 4.4), S_i^-1 computed once
  * per problem on the GPU in complex64 and applied reading its upper triangle only.
+ * A block whose T_i is ill-conditioned enough that ||T_i S_i^-1 v - v|| > 1e-3 ||v|| on a
+ * fixed vector v is rebuilt as T_i^-1 and read whole (every block with MTF_SOLVE_PC_FULL).
  * MTF_PREC_BLOCK_TINV_GS applies one block Gauss-Seidel sweep instead: Omega_0
  * first, then the colour classes of the subdomain adjacency graph (subdomains
  * of one class share no interface and are done together), each block solving

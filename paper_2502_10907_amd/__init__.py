@@ -33,6 +33,7 @@ FP64, FP32_MIXED, BF16_SPLIT = 0, 1, 2
 BLOCK_T, BLOCK_K = 0, 1
 PREC_NONE, PREC_BLOCK_TINV, PREC_BLOCK_TINV_GS = 0, 1, 2
 SOLVE_EAGER = 1
+SOLVE_PC_FULL = 2
 ASSEMBLE_ROUND_FP64 = 1
 
 
@@ -295,7 +296,7 @@ class Problem:
 
     def solve(self, b, x, rtol: float = 1e-6, precision: int = FP64, preconditioner: int = PREC_BLOCK_TINV,
               max_iters: int = 0, max_refinements: int = 0, inner_rtol: float = 0.0, x0=None,
-              graph: bool = True) -> list[Stats]:
+              graph: bool = True, pc_full: bool = False) -> list[Stats]:
         pb, nrhs, ld = _dev(b, self.N)
         px, nrhs2, ld2 = _dev(x, self.N)
         if (nrhs, ld) != (nrhs2, ld2):
@@ -306,7 +307,8 @@ class Problem:
             if (n3, ld3) != (nrhs, ld):
                 raise ValueError("x0 shape differs")
         o = SolveOpts(C.sizeof(SolveOpts), int(precision), int(preconditioner), int(max_iters),
-                      int(max_refinements), 0 if graph else SOLVE_EAGER, float(rtol), float(inner_rtol), x0p)
+                      int(max_refinements), (0 if graph else SOLVE_EAGER) | (SOLVE_PC_FULL if pc_full else 0),
+                      float(rtol), float(inner_rtol), x0p)
         st = (SolveStats * nrhs)()
         code = _check(_lib.mtf_solve(self._h, nrhs, pb, px, ld, C.byref(o), st))
         self.last_status = code

@@ -27,6 +27,7 @@ constexpr int kTile = 16;     // triangles per side of a separated-pair tile
 constexpr int kChunk = 64;    // columns per dense-matvec workgroup (matches solver.hip)
 constexpr int kNblk = 32;     // partial sums of GMRES reductions
 constexpr int kGjPanel = 256; // block width of the Gauss-Jordan inversion (64-wide leaves inside)
+constexpr double kPcSymTol = 1e-3;   // largest ||T_i S_i^-1 v - v|| / ||v|| of a symmetric-part block
 constexpr int kSync = 8;      // Arnoldi steps between host reads of the Hessenberg columns
 constexpr int kMaxBatch = 64; // right-hand sides per lockstep GMRES batch (MFMA products)
 constexpr int kUpdGroups = 8; // partial-sum groups of the basis update
@@ -107,7 +108,11 @@ struct mtf_problem_s {
     bool have64 = false, have32 = false, have_tinv = false;
     GemmOp gm, gp;                   // multi-RHS MFMA products: operator blocks, preconditioner blocks
     // block Gauss-Seidel stages: stage 0 = {Omega_0}, then colour classes of the subdomain graph
-    DevBuf<int4> d_stage_tiles;
+    DevBuf<int4> d_stage_tiles, d_pctiles;    // preconditioner tiles per Gauss-Seidel stage, and all of them
+    int64_t npctiles = 0;
+    std::vector<int> dom_colour;              // Gauss-Seidel stage of each subdomain (Omega_0: 0)
+    std::vector<char> pc_full;                // 1: the block is T_i^-1 itself, read whole
+    bool pc_force_full = false;               // the blocks were built with MTF_SOLVE_PC_FULL
     DevBuf<int32_t> d_stage_dofs, d_dom_stage;
     std::vector<int64_t> stage_tile0, stage_dof0;   // [nstage + 1] offsets
     double t_precond = 0;
@@ -193,8 +198,10 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
         const int T = sk.dom[i].T;
         for (int x0 = 0; x0 < T; x0 += kTile)
             for (int y0 = 0; y0 < T; y0 += kTile) tiles.push_back(make_int4(i, x0, y0, 0));
-        for (int bi = 0; bi < doms[i].nchunk; ++bi)
-            for (int bj = bi; bj < doms[i].nchunk; ++bj) symtiles.push_back(make_int4(i, bi, bj, 0));
+        // column block by column block: the four tiles of a workgroup are vertically adjacent, so
+        // their column segments are contiguous in memory
+        for (int bj = 0; bj < doms[i].nchunk; ++bj)
+            for (int bi = 0; bi <= bj; ++bi) symtiles.push_back(make_int4(i, bi, bj, 0));
     }
     // touching-pair pattern of the strictly lower triangle: (m, n), n < m, whose supports share a
     // vertex (CSR over the global dof index, local column n)
@@ -238,18 +245,14 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
         colour[i] = c;
         ncol = std::max(ncol, c);
     }
-    std::vector<int4> stiles;
     std::vector<int32_t> sdofs;
-    std::vector<int64_t> st0{0}, sd0{0};
+    std::vector<int64_t> sd0{0};
     for (int c = 0; c <= ncol; ++c) {
         for (int i = 0; i <= M; ++i) {
             if (colour[i] != c) continue;
             const int E = sk.dom[i].E;
-            for (int bi = 0; bi < doms[i].nchunk; ++bi)
-                for (int bj = bi; bj < doms[i].nchunk; ++bj) stiles.push_back(make_int4(i, bi, bj, 0));
             for (int m = 0; m < E; ++m) sdofs.push_back((int32_t)(doms[i].dof0 + m));
         }
-        st0.push_back((int64_t)stiles.size());
         sd0.push_back((int64_t)sdofs.size());
     }
     std::vector<SingPair> sing(sk.singular.size());
@@ -279,10 +282,9 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
     p->near64.reset();
     p->near32.reset();
     p->d_sing.upload(sing, s);
-    p->d_stage_tiles.upload(stiles, s);
     p->d_dom_stage.upload(colour, s);
     p->d_stage_dofs.upload(sdofs, s);
-    p->stage_tile0 = st0;
+    p->dom_colour = colour;
     p->stage_dof0 = sd0;
     p->ntiles = (int64_t)tiles.size();
     p->doms = doms;
@@ -518,7 +520,7 @@ void matvec1(mtf_problem p, const double* x, double* y, int prec) {
 }
 
 void precond1(mtf_problem p, const double* x, double* z) {
-    launch_precond_sym(p->d_doms.p, p->d_symtiles.p, p->nsymtiles, p->Tinv.p, x, p->part.p, p->stream);
+    launch_precond_sym(p->d_doms.p, p->d_pctiles.p, p->npctiles, p->Tinv.p, x, p->part.p, p->stream);
     launch_precond_sym_finish(p->d_doms.p, p->d_dof_dom.p, p->ndof, p->part.p, z, nullptr, p->stream);
 }
 
@@ -600,10 +602,43 @@ void block_gj_inverse(float* X, int n, int64_t ld, int64_t stride, int batch, in
     }
 }
 
-void build_tinv(mtf_problem p) {
-    if (p->have_tinv) return;
+// Preconditioner tile lists from the per-subdomain kind: upper tiles (w = 0) of a symmetric block,
+// every tile (w = 1) of a whole one; all subdomains, and per Gauss-Seidel stage.
+void build_pc_tiles(mtf_problem p) {
+    const auto& D = p->doms;
+    auto tiles_of = [&](int i, std::vector<int4>& out) {
+        const int nb = D[i].nchunk;
+        for (int bj = 0; bj < nb; ++bj)
+            for (int bi = 0; bi < nb; ++bi)
+                if (p->pc_full[i] || bi <= bj) out.push_back(make_int4(i, bi, bj, p->pc_full[i] ? 1 : 0));
+    };
+    std::vector<int4> all, st;
+    std::vector<int64_t> st0{0};
+    for (int i = 0; i < (int)D.size(); ++i) tiles_of(i, all);
+    const int ncol = *std::max_element(p->dom_colour.begin(), p->dom_colour.end());
+    for (int c = 0; c <= ncol; ++c) {
+        for (int i = 0; i < (int)D.size(); ++i)
+            if (p->dom_colour[i] == c) tiles_of(i, st);
+        st0.push_back((int64_t)st.size());
+    }
+    p->d_pctiles.upload(all, p->stream);
+    p->npctiles = (int64_t)all.size();
+    p->d_stage_tiles.upload(st, p->stream);
+    p->stage_tile0 = st0;
+}
+
+// Blocks of the T_i^-1 preconditioner, complex64.  Each block is first the inverse of the
+// symmetric part S_i = (T_i + T_i^T)/2, applied reading half of its entries.  S_i differs from T_i
+// by the two-order quadrature difference of touching pairs; where T_i is ill-conditioned that
+// difference is amplified in the inverse.  So every block is checked on a fixed vector v: when
+// ||T_i (S_i^-1 v) - v|| > kPcSymTol ||v|| (or when `force_full`), the block is rebuilt as the
+// inverse of T_i itself and read whole.
+void build_tinv(mtf_problem p, bool force_full) {
+    if (p->have_tinv && p->pc_force_full == force_full) return;
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = p->stream;
+    const auto& D = p->doms;
+    const int nd = (int)D.size();
     // 64 complex entries of padding: the symmetric-read apply may read up to 63 entries past the
     // last block (masked rows of its last column)
     p->Tinv.alloc(2 * (p->mat_entries + 64));
@@ -611,33 +646,85 @@ void build_tinv(mtf_problem p) {
     DevBuf<int> info;
     info.alloc(2);
     HIPCHK(hipMemsetAsync(info.p, 0, 2 * sizeof(int), s));
-    if (p->have32)
-        HIPCHK(hipMemcpyAsync(p->Tinv.p, p->T32.p, 2 * p->mat_entries * sizeof(float), hipMemcpyDeviceToDevice, s));
-    else
-        launch_copy_block_f64_to_f32(p->T64.p, p->Tinv.p, 2 * p->mat_entries, s);
-    // the preconditioner inverts the symmetric part (T_i + T_i^T)/2: T_i differs from it only by
-    // the quadrature asymmetry of touching pairs, and a symmetric inverse is applied reading half
-    // of its entries
-    for (const DomDesc& d : p->doms)
-        if (d.E > 0) launch_symmetrize_f32(p->Tinv.p + 2 * d.mat0, d.E, s);
-    // consecutive subdomains of equal size are stored back to back and inverted as one batch
-    const auto& D = p->doms;
-    int64_t tmp_entries = 0;                           // out-of-place panels: W * E per matrix of a batch
-    for (size_t a = 0; a < D.size();) {
-        size_t b = a + 1;
-        while (b < D.size() && D[b].E == D[a].E && D[b].mat0 == D[a].mat0 + (int64_t)(b - a) * D[a].E * D[a].E) ++b;
+    // T_i in complex64 (kept for the check and the rebuilt blocks)
+    DevBuf<float> tcopy;
+    const float* T32 = p->T32.p;
+    if (!p->have32) {
+        tcopy.alloc(2 * p->mat_entries);
+        launch_copy_block_f64_to_f32(p->T64.p, tcopy.p, 2 * p->mat_entries, s);
+        T32 = tcopy.p;
+    }
+    HIPCHK(hipMemcpyAsync(p->Tinv.p, T32, 2 * p->mat_entries * sizeof(float), hipMemcpyDeviceToDevice, s));
+    p->pc_full.assign(nd, force_full ? 1 : 0);
+    for (int i = 0; i < nd; ++i)
+        if (D[i].E > 0 && !p->pc_full[i]) launch_symmetrize_f32(p->Tinv.p + 2 * D[i].mat0, D[i].E, s);
+    int64_t tmp_entries = 0, emax = 0;                 // out-of-place panels: W * E per matrix of a batch
+    for (int a = 0; a < nd;) {
+        int b = a + 1;
+        while (b < nd && D[b].E == D[a].E && D[b].mat0 == D[a].mat0 + (int64_t)(b - a) * D[a].E * D[a].E) ++b;
         tmp_entries = std::max(tmp_entries, (int64_t)(b - a) * kGjPanel * D[a].E);
+        emax = std::max<int64_t>(emax, D[a].E);
         a = b;
     }
     DevBuf<float> gjtmp;
     gjtmp.alloc(2 * std::max<int64_t>(tmp_entries, 1));
-    for (size_t a = 0; a < D.size();) {
-        size_t b = a + 1;
+    // consecutive subdomains of equal size are stored back to back and inverted as one batch
+    for (int a = 0; a < nd;) {
+        int b = a + 1;
         const int64_t E = D[a].E;
-        while (b < D.size() && D[b].E == E && D[b].mat0 == D[a].mat0 + (int64_t)(b - a) * E * E) ++b;
-        if (E > 0) block_gj_inverse(p->Tinv.p + 2 * D[a].mat0, (int)E, E, E * E, (int)(b - a), info.p, s, kGjPanel,
-                                    gjtmp.p);
+        while (b < nd && D[b].E == E && D[b].mat0 == D[a].mat0 + (int64_t)(b - a) * E * E) ++b;
+        if (E > 0) block_gj_inverse(p->Tinv.p + 2 * D[a].mat0, (int)E, E, E * E, b - a, info.p, s, kGjPanel, gjtmp.p);
         a = b;
+    }
+    if (!force_full && emax > 0) {
+        // check ||T_i (X_i v) - v|| / ||v|| with v_m = (cos m, sin 2m) per block
+        std::vector<float> vh(2 * emax);
+        for (int64_t m = 0; m < emax; ++m) { vh[2 * m] = (float)std::cos((double)m); vh[2 * m + 1] = (float)std::sin(2.0 * m); }
+        std::vector<int64_t> uoff(nd + 1, 0);          // T_i X_i v of every block, back to back
+        for (int i = 0; i < nd; ++i) uoff[i + 1] = uoff[i] + D[i].E;
+        int64_t part_entries = 0;
+        for (int a = 0; a < nd;) {                      // groups of equal size, as for the inversion
+            int b = a + 1;
+            while (b < nd && D[b].E == D[a].E && D[b].mat0 == D[a].mat0 + (int64_t)(b - a) * D[a].E * D[a].E) ++b;
+            part_entries = std::max(part_entries, (int64_t)(b - a) * ((D[a].E + 255) / 256) * D[a].E);
+            a = b;
+        }
+        DevBuf<float> v, w, u, part;
+        v.alloc(2 * emax); w.alloc(2 * uoff[nd]); u.alloc(2 * uoff[nd]); part.alloc(2 * std::max<int64_t>(part_entries, 1));
+        HIPCHK(hipMemcpyAsync(v.p, vh.data(), vh.size() * sizeof(float), hipMemcpyHostToDevice, s));
+        for (int a = 0; a < nd;) {
+            int b = a + 1;
+            const int64_t E = D[a].E;
+            while (b < nd && D[b].E == E && D[b].mat0 == D[a].mat0 + (int64_t)(b - a) * E * E) ++b;
+            if (E > 0) {
+                // blocks a..b-1 are back to back (stride E^2), as are their slices of w and u (stride E)
+                launch_cgemv_f32(p->Tinv.p + 2 * D[a].mat0, E, E * E, v.p, 0, (int)E, b - a, part.p, w.p + 2 * uoff[a], E, s);
+                launch_cgemv_f32(T32 + 2 * D[a].mat0, E, E * E, w.p + 2 * uoff[a], E, (int)E, b - a, part.p,
+                                 u.p + 2 * uoff[a], E, s);
+            }
+            a = b;
+        }
+        std::vector<float> uh(2 * uoff[nd]);
+        HIPCHK(hipMemcpyAsync(uh.data(), u.p, uh.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+        sync(p);
+        std::vector<int> redo;
+        for (int i = 0; i < nd; ++i) {
+            double num = 0, den = 0;
+            for (int64_t m = 0; m < D[i].E; ++m) {
+                const float* ui = uh.data() + 2 * (uoff[i] + m);
+                const double dr = ui[0] - vh[2 * m], di = ui[1] - vh[2 * m + 1];
+                num += dr * dr + di * di;
+                den += (double)vh[2 * m] * vh[2 * m] + (double)vh[2 * m + 1] * vh[2 * m + 1];
+            }
+            if (D[i].E > 0 && !(std::sqrt(num / den) <= kPcSymTol)) redo.push_back(i);
+        }
+        for (int i : redo) {
+            const int64_t E = D[i].E;
+            HIPCHK(hipMemcpyAsync(p->Tinv.p + 2 * D[i].mat0, T32 + 2 * D[i].mat0, 2 * E * E * sizeof(float),
+                                  hipMemcpyDeviceToDevice, s));
+            block_gj_inverse(p->Tinv.p + 2 * D[i].mat0, (int)E, E, E * E, 1, info.p, s, kGjPanel, gjtmp.p);
+            p->pc_full[i] = 1;
+        }
     }
     launch_nonfinite_check(p->Tinv.p, 2 * p->mat_entries, info.p + 1, s);
     HIPCHK(hipGetLastError());
@@ -645,7 +732,10 @@ void build_tinv(mtf_problem p) {
     HIPCHK(hipMemcpyAsync(h, info.p, sizeof(h), hipMemcpyDeviceToHost, s));
     sync(p);
     if (h[0] || h[1]) throw NonFiniteError("block preconditioner: singular pivot or non-finite inverse of T_i");
+    build_pc_tiles(p);
+    sync(p);
     p->have_tinv = true;
+    p->pc_force_full = force_full;
     p->gp.haveA = false;
     p->t_precond = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -1006,10 +1096,11 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
     DeviceGuard g(p->device);
     const int pc = opts.preconditioner;
     const bool use_pc = pc != MTF_PREC_NONE;
-    if (opts.flags & ~MTF_SOLVE_EAGER) throw ArgError("unknown solve flags");
+    if (opts.flags & ~(MTF_SOLVE_EAGER | MTF_SOLVE_PC_FULL)) throw ArgError("unknown solve flags");
     const bool graph = (opts.flags & MTF_SOLVE_EAGER) == 0;
+    const bool pc_full = (opts.flags & MTF_SOLVE_PC_FULL) != 0;
     double t_pc = 0;
-    if (use_pc && !p->have_tinv) { build_tinv(p); t_pc = p->t_precond; }
+    if (use_pc && (!p->have_tinv || p->pc_force_full != pc_full)) { build_tinv(p, pc_full); t_pc = p->t_precond; }
     // right-hand sides advance in lockstep batches when the products are GEMMs
     const int nbmax = prec == MTF_BF16_SPLIT ? std::min<int>(nrhs, kMaxBatch) : 1;
     if (maxit == 0) {
@@ -1432,7 +1523,7 @@ int mtf_apply_preconditioner(mtf_problem p, int32_t preconditioner, int32_t nrhs
             throw ArgError("preconditioner must be MTF_PREC_BLOCK_TINV or MTF_PREC_BLOCK_TINV_GS");
         if (!p->have64 && !p->have32) throw StateError("mtf_apply_preconditioner before mtf_assemble");
         DeviceGuard g(p->device);
-        if (!p->have_tinv) build_tinv(p);
+        if (!p->have_tinv) build_tinv(p, false);
         DevBuf<double> w;
         if (preconditioner == MTF_PREC_BLOCK_TINV_GS) w.alloc(2 * p->sk.N);
         for (int r = 0; r < nrhs; ++r) {

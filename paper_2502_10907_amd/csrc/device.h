@@ -165,6 +165,10 @@ inline void launch_cgemm_f32(int m, int n, int k, float alpha_re, float alpha_im
 }
 // In-place inverse of the n x n (n <= 64) complex64 blocks A + z*stride (ld lda), z < batch;
 // info[0] is set to a nonzero value on a zero pivot.
+// y_z = A_z x_z for `batch` n x n complex64 matrices A_z = A + z sA (ld lda), x_z = x + z sx,
+// y_z = y + z sy (strides in complex entries); part: batch * ceil(n / 256) * n complex scratch
+void launch_cgemv_f32(const float* A, int64_t lda, int64_t sA, const float* x, int64_t sx, int n, int batch, float* part,
+                      float* y, int64_t sy, hipStream_t s);
 int  launch_cinv_small_f32(float* A, int64_t lda, int64_t stride, int n, int batch, int* info, hipStream_t s);
 // Symmetric-read block matvec (tiles I <= J of 64 x 64; stiles: int4(domain, I, J, 0)), the
 // touching-pair corrections of the lower triangle, and the finishing kernel.

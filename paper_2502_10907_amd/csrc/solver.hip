@@ -259,10 +259,12 @@ __global__ __launch_bounds__(256, 2) void k_mv_sym(const DomDesc* __restrict__ d
     }
 }
 
-// Symmetric-read preconditioner product: v_D = S x_D, v_N = S x_N per subdomain with S the
-// complex64 inverse of the symmetric part of T_i (symmetric up to the rounding of the inversion;
-// only its tiles I <= J are read, each entry used as (r, c) and, off the diagonal, as (c, r); in
-// a diagonal tile the strict lower triangle is dropped and the diagonal halved).  Same lane
+// Preconditioner product: v_D = S x_D, v_N = S x_N per subdomain with S the complex64 inverse of
+// the symmetric part of T_i (symmetric up to the rounding of the inversion; only its tiles
+// I <= J are read, each entry used as (r, c) and, off the diagonal, as (c, r); in a diagonal tile
+// the strict lower triangle is dropped and the diagonal halved).  Tiles flagged in their fourth
+// component belong to a subdomain whose block is the inverse of T_i itself: every tile (I, J) is
+// listed and used directly only, and the tiles J = 0 clear the transposed slot of their rows.  Same lane
 // layout, addressing and partial-slot layout as k_mv_sym; FP32 arithmetic.  A column group is
 // only 2 KB per wavefront, so the loads run D groups ahead through a ring of D + 1 register
 // slots (D = 3 measured fastest on the Gauss-Seidel stages, large and small: three wavefronts
@@ -284,7 +286,8 @@ __global__ __launch_bounds__(256) void k_pc_sym(const DomDesc* __restrict__ doms
     const int I = t.y, J = t.z;
     const int r0 = I * 64, c0 = J * 64;
     const int rg = lane & 15, cg = lane >> 4;
-    const bool diag = I == J;
+    const bool full = t.w != 0;                         // all tiles of the block, direct use only
+    const bool diag = I == J && !full;
     const double2* xD = reinterpret_cast<const double2*>(x) + dd.off;
     const double2* xN = xD + E;
     {
@@ -340,17 +343,22 @@ __global__ __launch_bounds__(256) void k_pc_sym(const DomDesc* __restrict__ doms
                 e[i][1] *= w;
             }
         }
-        float v[4] = {0.f, 0.f, 0.f, 0.f};              // transposed: S x_D, S x_N of row c
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             cfma(acc[i][0], acc[i][1], e[i][0], e[i][1], xv.x, xv.y);
             cfma(acc[i][2], acc[i][3], e[i][0], e[i][1], xv.z, xv.w);
-            cfma(v[0], v[1], e[i][0], e[i][1], xr[i][0], xr[i][1]);
-            cfma(v[2], v[3], e[i][0], e[i][1], xr[i][2], xr[i][3]);
         }
-        // lanes rg = 0, 1, 2, 3 hold the sums of v_D re, v_N re, v_D im, v_N im of row c
-        const float u = row16_sum4(v, rg);
-        if (rg < 4 && c < E) pbase[2 * ((int64_t)(2 * I + (rg & 1)) * E + c) + (rg >> 1)] = (double)u;
+        if (!full) {
+            float v[4] = {0.f, 0.f, 0.f, 0.f};          // transposed: S x_D, S x_N of row c
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                cfma(v[0], v[1], e[i][0], e[i][1], xr[i][0], xr[i][1]);
+                cfma(v[2], v[3], e[i][0], e[i][1], xr[i][2], xr[i][3]);
+            }
+            // lanes rg = 0, 1, 2, 3 hold the sums of v_D re, v_N re, v_D im, v_N im of row c
+            const float u = row16_sum4(v, rg);
+            if (rg < 4 && c < E) pbase[2 * ((int64_t)(2 * I + (rg & 1)) * E + c) + (rg >> 1)] = (double)u;
+        }
     };
 #pragma unroll
     for (int k = 0; k < D; ++k) load(k, k);
@@ -376,6 +384,12 @@ __global__ __launch_bounds__(256) void k_pc_sym(const DomDesc* __restrict__ doms
         double* pN = pbase + 2 * ((int64_t)(2 * (J + 1) + 1) * E + r);
         *reinterpret_cast<double2*>(pD) = make_double2(acc[i][0], acc[i][1]);
         *reinterpret_cast<double2*>(pN) = make_double2(acc[i][2], acc[i][3]);
+        if (full && J == 0) {                           // slot 0 (the transposed slot) is unused
+            double* zD = pbase + 2 * ((int64_t)0 * E + r);
+            double* zN = pbase + 2 * ((int64_t)E + r);
+            *reinterpret_cast<double2*>(zD) = make_double2(0.0, 0.0);
+            *reinterpret_cast<double2*>(zN) = make_double2(0.0, 0.0);
+        }
     }
 }
 
@@ -1195,6 +1209,40 @@ __global__ void k_band_copy(const float2* __restrict__ src, int64_t lds, int64_t
     dst[z * sd + pr + pc * ldd] = src[z * ss + r + (int64_t)c * lds];
 }
 
+// y = A x for batched n x n complex64 A (column-major, lda; matrix z at A + z sA, x at x + z sx):
+// workgroup (row block, column chunk of 256) sums its chunk, then the chunks are added.
+__global__ __launch_bounds__(256) void k_cgemv_part(const float2* __restrict__ A, int64_t lda, int64_t sA,
+                                                    const float2* __restrict__ x, int64_t sx, int n,
+                                                    float2* __restrict__ part, int64_t sp) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    const int c0 = blockIdx.y * 256, c1 = min(n, c0 + 256);
+    const int64_t z = blockIdx.z;
+    if (r >= n) return;
+    const float2* Az = A + z * sA + r;
+    const float2* xz = x + z * sx;
+    float re = 0.f, im = 0.f;
+    for (int k = c0; k < c1; ++k) {
+        const float2 a = Az[(int64_t)k * lda], b = xz[k];
+        re = fmaf(a.x, b.x, fmaf(-a.y, b.y, re));
+        im = fmaf(a.x, b.y, fmaf(a.y, b.x, im));
+    }
+    part[z * sp + (int64_t)blockIdx.y * n + r] = make_float2(re, im);
+}
+
+__global__ void k_cgemv_sum(const float2* __restrict__ part, int n, int nch, int64_t sp, float2* __restrict__ y,
+                            int64_t sy) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t z = blockIdx.y;
+    if (r >= n) return;
+    float re = 0.f, im = 0.f;
+    for (int c = 0; c < nch; ++c) {
+        const float2 v = part[z * sp + (int64_t)c * n + r];
+        re += v.x;
+        im += v.y;
+    }
+    y[z * sy + r] = make_float2(re, im);
+}
+
 __global__ void k_copy_d2f(const double* __restrict__ s, float* __restrict__ d, int64_t n) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < n) d[e] = (float)s[e];
@@ -1343,6 +1391,18 @@ void launch_band_copy_f32(const float* src, int64_t lds, int64_t ss, float* dst,
     hipLaunchKernelGGL(k_band_copy, dim3(gridn((int64_t)rows * cols, 256), (unsigned)batch), dim3(256), 0, s,
                        reinterpret_cast<const float2*>(src), lds, ss, reinterpret_cast<float2*>(dst), ldd, sd, rows,
                        cols, r0, rw, c0, cw);
+}
+
+void launch_cgemv_f32(const float* A, int64_t lda, int64_t sA, const float* x, int64_t sx, int n, int batch, float* part,
+                      float* y, int64_t sy, hipStream_t s) {
+    if (n <= 0 || batch <= 0) return;
+    const int nch = (n + 255) / 256;
+    const int64_t sp = (int64_t)nch * n;
+    hipLaunchKernelGGL(k_cgemv_part, dim3((unsigned)nch, (unsigned)nch, (unsigned)batch), dim3(256), 0, s,
+                       reinterpret_cast<const float2*>(A), lda, sA, reinterpret_cast<const float2*>(x), sx, n,
+                       reinterpret_cast<float2*>(part), sp);
+    hipLaunchKernelGGL(k_cgemv_sum, dim3(gridn(n, 256), (unsigned)batch), dim3(256), 0, s,
+                       reinterpret_cast<const float2*>(part), n, nch, sp, reinterpret_cast<float2*>(y), sy);
 }
 
 int launch_cinv_small_f32(float* A, int64_t lda, int64_t stride, int n, int batch, int* info, hipStream_t s) {
