@@ -153,11 +153,11 @@ __device__ inline void zero_moments(Moments<R>& m) {
         for (int c = 0; c < 2; ++c) m.Mx[k][c] = m.My[k][c] = m.Nx[k][c] = m.Ny[k][c] = m.Nxy[k][c] = R(0);
 }
 
-// Local blocks from the moments and their scatter (with RWG signs) into T and K.
-template <typename R, typename RO>
-__device__ __attribute__((always_inline)) inline void epilogue(const Moments<R>& m, const R* pa_all, const R* qb_all, const R* ca, const R* cb,
-                                const R* D, R k, const int32_t* dofx, const int32_t* dofy, const int32_t* sgx,
-                                const int32_t* sgy, int64_t mat0, int32_t E, RO* T, RO* K) {
+// Local blocks from the moments, with RWG signs, handed to sink(a, b, T re, T im, K re, K im).
+template <typename R, typename Sink>
+__device__ __attribute__((always_inline)) inline void epilogue(const Moments<R>& m, const R* pa_all, const R* qb_all,
+                                                               const R* ca, const R* cb, const R* D, R k,
+                                                               const int32_t* sgx, const int32_t* sgy, Sink sink) {
     const R four_over_k2 = R(4) / (k * k);
     for (int a = 0; a < 3; ++a) {
         const R* Pa = pa_all + 3 * a;
@@ -197,22 +197,61 @@ __device__ __attribute__((always_inline)) inline void epilogue(const Moments<R>&
             const R Tim = -k * f * t[0];
             const R Kre = -f * s[0];
             const R Kim = -f * s[1];
-            const int64_t idx = 2 * (mat0 + (int64_t)dofx[a] + (int64_t)dofy[b] * E);
-            atomic_add(T + idx, (RO)Tre);
-            atomic_add(T + idx + 1, (RO)Tim);
-            atomic_add(K + idx, (RO)Kre);
-            atomic_add(K + idx + 1, (RO)Kim);
+            sink(a, b, Tre, Tim, Kre, Kim);
         }
     }
 }
 
-// One 16 x 16 tile of separated pairs; all 256 threads of the workgroup must call it (it holds a
-// workgroup barrier); pairs outside Gamma_i or touching are skipped by predication.
+// Scatter of one pair's local blocks straight into T and K (global atomics).
+template <typename RO>
+struct GlobalSink {
+    const int32_t* dofx;
+    const int32_t* dofy;
+    int64_t mat0;
+    int32_t E;
+    RO* T;
+    RO* K;
+    template <typename R>
+    __device__ void operator()(int a, int b, R Tre, R Tim, R Kre, R Kim) const {
+        const int64_t idx = 2 * (mat0 + (int64_t)dofx[a] + (int64_t)dofy[b] * E);
+        atomic_add(T + idx, (RO)Tre);
+        atomic_add(T + idx + 1, (RO)Tim);
+        atomic_add(K + idx, (RO)Kre);
+        atomic_add(K + idx + 1, (RO)Kim);
+    }
+};
+
+// Local accumulator of a 16 x 16 tile of separated pairs: slot 3 t + a is local dof a of tile
+// triangle t (48 per side); a dof that appears in several slots is kept in the first of them, so
+// the tile's pairs add into LDS and only its distinct (test dof, trial dof) entries reach T and K.
+constexpr int kTileSlots = 48;
+template <typename R>
+struct TileAcc {
+    R v[2][kTileSlots][kTileSlots][2];   // [T, K][test slot][trial slot][re, im]
+    int first[2][kTileSlots];            // [test, trial]: first slot of the same dof, -1 when unused
+};
+
+template <typename R>
+struct LdsSink {
+    TileAcc<R>* acc;
+    int sx, sy;                          // 3 * tile triangle of the pair, test and trial side
+    __device__ void operator()(int a, int b, R Tre, R Tim, R Kre, R Kim) const {
+        const int x = acc->first[0][sx + a], y = acc->first[1][sy + b];
+        atomicAdd(&acc->v[0][x][y][0], Tre);
+        atomicAdd(&acc->v[0][x][y][1], Tim);
+        atomicAdd(&acc->v[1][x][y][0], Kre);
+        atomicAdd(&acc->v[1][x][y][1], Kim);
+    }
+};
+
+// One 16 x 16 tile of separated pairs; all 256 threads of the workgroup must call it (it holds
+// workgroup barriers); pairs outside Gamma_i or touching are skipped by predication.  The pairs
+// add into the tile's LDS accumulator, which is then scattered into T and K.
 template <typename R>
 __device__ __attribute__((always_inline)) inline void regular_tile(const int4 tile, const DomDesc* __restrict__ doms, const TriGeom* __restrict__ geom,
                                     const int32_t* __restrict__ verts, const int32_t* __restrict__ tdof,
                                     const int8_t* __restrict__ tsign, R* __restrict__ T, R* __restrict__ K,
-                                    LRec<R>* rec) {
+                                    LRec<R>* rec, TileAcc<R>* acc) {
     const DomDesc dd = doms[tile.x];
     const int tid = threadIdx.x;
     if (tid < 32) {
@@ -232,6 +271,24 @@ __device__ __attribute__((always_inline)) inline void regular_tile(const int4 ti
                 L.sg[i] = tsign[3 * r + i];
             }
         }
+    }
+    {
+        R* z = &acc->v[0][0][0][0];
+        for (int e = tid; e < 2 * kTileSlots * kTileSlots * 2; e += 256) z[e] = R(0);
+    }
+    __syncthreads();
+    if (tid < 2 * kTileSlots) {
+        // first slot holding the same dof (slots of triangles past the end of Gamma_i: -1)
+        const int side = tid / kTileSlots, sl = tid % kTileSlots;
+        const int t0 = side == 0 ? tile.y : tile.z;
+        int f = -1;
+        if (t0 + sl / 3 < dd.T) {
+            const int d = rec[16 * side + sl / 3].dof[sl % 3];
+            f = sl;
+            for (int q = 0; q < sl; ++q)
+                if (rec[16 * side + q / 3].dof[q % 3] == d) { f = q; break; }
+        }
+        acc->first[side][sl] = f;
     }
     __syncthreads();
     const int ix = tid >> 4, iy = tid & 15;
@@ -294,7 +351,20 @@ __device__ __attribute__((always_inline)) inline void regular_tile(const int4 ti
                 m.Nxy[2][c] += wq * (x0 * ty[1][c] - x1 * ty[0][c]);
             }
         }
-        epilogue<R, R>(m, X.p, Y.p, X.coef, Y.coef, D, k, X.dof, Y.dof, X.sg, Y.sg, dd.mat0, dd.E, T, K);
+        epilogue<R>(m, X.p, Y.p, X.coef, Y.coef, D, k, X.sg, Y.sg, LdsSink<R>{acc, 3 * ix, 3 * iy});
+    }
+    __syncthreads();
+    // distinct (test dof, trial dof) entries of the tile into T and K
+    for (int e = tid; e < kTileSlots * kTileSlots; e += 256) {
+        const int x = e % kTileSlots, y = e / kTileSlots;
+        if (acc->first[0][x] != x || acc->first[1][y] != y) continue;
+        const R tr = acc->v[0][x][y][0], ti = acc->v[0][x][y][1], kr = acc->v[1][x][y][0], ki = acc->v[1][x][y][1];
+        if (tr == R(0) && ti == R(0) && kr == R(0) && ki == R(0)) continue;
+        const int64_t idx = 2 * (dd.mat0 + (int64_t)rec[x / 3].dof[x % 3] + (int64_t)rec[16 + y / 3].dof[y % 3] * dd.E);
+        atomic_add(T + idx, tr);
+        atomic_add(T + idx + 1, ti);
+        atomic_add(K + idx, kr);
+        atomic_add(K + idx + 1, ki);
     }
 }
 
@@ -304,7 +374,8 @@ __global__ __launch_bounds__(256) void k_regular(const int4* __restrict__ tiles,
                                                  const int32_t* __restrict__ tdof, const int8_t* __restrict__ tsign,
                                                  R* __restrict__ T, R* __restrict__ K) {
     __shared__ LRec<R> rec[32];
-    regular_tile<R>(tiles[blockIdx.x], doms, geom, verts, tdof, tsign, T, K, rec);
+    __shared__ TileAcc<R> acc;
+    regular_tile<R>(tiles[blockIdx.x], doms, geom, verts, tdof, tsign, T, K, rec, &acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -389,8 +460,10 @@ __device__ __attribute__((always_inline)) inline void singular_pair(const SingPa
             sgx[a] = tsign[3 * rx + a];
             sgy[a] = tsign[3 * ry + a];
         }
-        if (T64) epilogue<double, double>(m, gx.p, gy.p, gx.coef, gy.coef, D, k, dofx, dofy, sgx, sgy, dd.mat0, dd.E, T64, K64);
-        if (T32) epilogue<double, float>(m, gx.p, gy.p, gx.coef, gy.coef, D, k, dofx, dofy, sgx, sgy, dd.mat0, dd.E, T32, K32);
+        if (T64) epilogue<double>(m, gx.p, gy.p, gx.coef, gy.coef, D, k, sgx, sgy,
+                                  GlobalSink<double>{dofx, dofy, dd.mat0, dd.E, T64, K64});
+        if (T32) epilogue<double>(m, gx.p, gy.p, gx.coef, gy.coef, D, k, sgx, sgy,
+                                  GlobalSink<float>{dofx, dofy, dd.mat0, dd.E, T32, K32});
     }
 }
 
@@ -419,6 +492,7 @@ __global__ __launch_bounds__(256) void k_assemble_persistent(const int4* __restr
                                                              const int32_t* __restrict__ ss_off,
                                                              const int32_t* __restrict__ ss_cnt) {
     __shared__ LRec<R> rec[32];
+    __shared__ TileAcc<R> acc;
     __shared__ long long claimed;
     for (;;) {
         if (threadIdx.x == 0) claimed = (long long)atomicAdd(counter, 1ull);
@@ -431,7 +505,7 @@ __global__ __launch_bounds__(256) void k_assemble_persistent(const int4* __restr
         const BatchProb bp = probs[prob];
         if (kind == 0) {
             regular_tile<R>(make_int4(w.y, w.z, w.w, 0), bp.doms, bp.geom, bp.verts, bp.tdof, bp.tsign,
-                            static_cast<R*>(bp.T), static_cast<R*>(bp.K), rec);
+                            static_cast<R*>(bp.T), static_cast<R*>(bp.K), rec, &acc);
         } else {
             const int wave = threadIdx.x >> 6;
             if (wave < w.z) {

@@ -607,7 +607,7 @@ __global__ __launch_bounds__(256) void k_dot2(const double* __restrict__ V, int6
         const int is = i <= nv ? i : nv;
         const double2* v = reinterpret_cast<const double2*>(V + 2 * ((int64_t)is * ldv + (int64_t)b * n));
         double a[4] = {0, 0, 0, 0};                     // conj(v) u (re, im), conj(v) t (re, im)
-#pragma unroll 4
+#pragma unroll 8
         for (int64_t e = lo + rg; e < hi; e += 16) {
             const double2 x = v[e], uu = u[e], tt = t[e];
             a[0] = fma(x.x, uu.x, fma(x.y, uu.y, a[0]));
