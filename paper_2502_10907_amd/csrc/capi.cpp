@@ -25,7 +25,7 @@ using cd = std::complex<double>;
 
 constexpr int kTile = 16;     // triangles per side of a separated-pair tile
 constexpr int kChunk = 64;    // columns per dense-matvec workgroup (matches solver.hip)
-constexpr int kNblk = 32;     // partial sums of GMRES reductions
+constexpr int kNblk = 32;     // partial sums of GMRES norms
 constexpr int kGjPanel = 256; // block width of the Gauss-Jordan inversion (64-wide leaves inside)
 constexpr double kPcSymTol = 1e-3;   // largest ||T_i S_i^-1 v - v|| / ||v|| of a symmetric-part block
 constexpr int kSync = 8;      // Arnoldi steps between host reads of the Hessenberg columns
@@ -769,7 +769,7 @@ void gmres_alloc(mtf_problem p, int maxit, int nb, bool flex) {
     w.tmp2.alloc(2 * n * nb);
     w.tmp3.alloc(2 * n);
     w.r.alloc(2 * n * nb);
-    w.hpart.alloc(4 * (int64_t)nb * (maxit + 1) * kNblk);
+    w.hpart.alloc(4 * (int64_t)nb * (maxit + 1) * dot_plan(nb).kmax);
     w.S.alloc(2 * (int64_t)nb * (maxit + 1));
     w.Z.alloc(2 * (int64_t)nb * (maxit + 1));
     w.hg.alloc(2 * (int64_t)nb * nct * (maxit + 1));
@@ -894,13 +894,11 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
     auto step = [&](int jj) {
         const int* jr = jslot(jj);
         apply_inner(p, w.ufix.p, w.tfix.p, nb, cur_prec, pc, flex ? w.zfix.p : nullptr);
-        launch_dot2(V, ldv, jr, nvmax, w.tfix.p, n, w.hpart.p, kNblk, nb, s);
-        launch_reduce2(w.hpart.p, jr, nvmax, kNblk, w.S.p, w.Z.p, nb, s);
-        launch_hess_gemv(w.H.p, ldh, hstride, w.S.p, jr, nvmax, nct, w.hg.p, nb, s);
-        launch_dcgs_col(w.H.p, ldh, hstride, w.S.p, w.Z.p, w.hg.p, nct, jr, nvmax, w.scal.p, 0,
-                        flex ? w.Rf.p : nullptr, hstride, nb, s);
+        launch_dot2(V, ldv, jr, nvmax, w.tfix.p, n, w.hpart.p, dot_plan(nb), nb, s);
+        launch_reduce2(w.hpart.p, jr, nvmax, dot_plan(nb), w.S.p, w.Z.p, nb, s);
         launch_update2(V, ldv, jr, jslot(jj + 1), nvmax, w.S.p, w.Z.p, w.tfix.p, w.ufix.p, n, w.upart.p, kUpdGroups,
-                       w.scal.p, flex ? w.zfix.p : nullptr, flex ? w.Zt.p : nullptr, nb, s);
+                       flex ? w.zfix.p : nullptr, flex ? w.Zt.p : nullptr, w.H.p, ldh, hstride, w.hg.p, nct,
+                       flex ? w.Rf.p : nullptr, hstride, nb, s);
     };
     // kSync steps j0 .. j0+kSync-1 (j0 odd), then the final columns j0-1 .. j0+kSync-2 staged and
     // copied to w.host
@@ -1022,8 +1020,8 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
         }
         // tail: the remaining steps one by one, then the step that only finalises column maxit-1
         for (; j < maxit; ++j) step(j);
-        launch_dot2(V, ldv, jslot(maxit), nvmax, nullptr, n, w.hpart.p, kNblk, nb, s);
-        launch_reduce2(w.hpart.p, jslot(maxit), nvmax, kNblk, w.S.p, w.Z.p, nb, s);
+        launch_dot2(V, ldv, jslot(maxit), nvmax, nullptr, n, w.hpart.p, dot_plan(nb), nb, s);
+        launch_reduce2(w.hpart.p, jslot(maxit), nvmax, dot_plan(nb), w.S.p, w.Z.p, nb, s);
         launch_dcgs_col(w.H.p, ldh, hstride, w.S.p, w.Z.p, w.hg.p, nct, jslot(maxit), nvmax, w.scal.p, 1, nullptr,
                         hstride, nb, s);
         const int nc = maxit - done_cols;

@@ -103,17 +103,34 @@ void launch_rhs(const DomDesc* d0, const TriGeom* geom, const int32_t* dplus, co
 // Kernels taking `flag` skip right-hand side b when flag[b] == 0.
 // Arnoldi step with delayed reorthogonalisation (DCGS2), nb right-hand sides in lockstep; the
 // step index j is read from jdev[0] on the device and the grids depend on nvmax only.
+// Reductions over the basis at step j: `grid` workgroups per right-hand side; at step j each
+// vector is split into clamp(units / (j / 16 + 1), cmin, kmax) row chunks, and hpart holds
+// 4 * nb * (nvmax + 1) * kmax doubles.
+struct DotPlan {
+    int grid, units, cmin, kmax;
+};
+inline DotPlan dot_plan(int nb) {
+    nb = nb < 1 ? 1 : nb;
+    DotPlan d;
+    d.grid = 2048 / nb < 32 ? 32 : 2048 / nb;
+    d.units = 1280 / nb < 32 ? 32 : 1280 / nb;
+    d.cmin = 32;
+    d.kmax = d.units < 512 ? (d.units < 32 ? 32 : d.units) : 512;
+    return d;
+}
 void launch_dot2(const double* V, int64_t ldv, const int* jdev, int nvmax, const double* t, int64_t n, double* hpart,
-                 int nblk, int nb, hipStream_t s);                          // partial Q^H [u t], u^H [u t] (t null: t = u)
-void launch_reduce2(const double* hpart, const int* jdev, int nvmax, int nblk, double* S, double* Z, int nb,
+                 const DotPlan& d, int nb, hipStream_t s);                  // partial Q^H [u t], u^H [u t] (t null: t = u)
+void launch_reduce2(const double* hpart, const int* jdev, int nvmax, const DotPlan& d, double* S, double* Z, int nb,
                     hipStream_t s);
-void launch_hess_gemv(const double* H, int64_t ldh, int64_t hstride, const double* S, const int* jdev, int nvmax, int nct,
-                      double* hg, int nb, hipStream_t s);                   // partial Hbar s
 void launch_dcgs_col(double* H, int64_t ldh, int64_t hstride, const double* S, const double* Z, const double* hg, int nct,
                      const int* jdev, int nvmax, double* scal, int last, double* R, int64_t rstride, int nb, hipStream_t s);
+// q_j, u_{j+1} (also unext); zsrc -> zdst slot j; *jnext = j+1.  The same two launches also form
+// the partial products Hbar s (into hg), finalise Hessenberg column j-1, write the first-pass
+// column j and, when R is given, column j of R.
 void launch_update2(const double* V, int64_t ldv, const int* jdev, int* jnext, int nvmax, const double* S,
-                    const double* Z, const double* t, double* unext, int64_t n, double* part, int ng, const double* scal,
-                    const double* zsrc, double* zdst, int nb, hipStream_t s);  // q_j, u_{j+1} (also unext); zsrc -> zdst slot j; *jnext = j+1
+                    const double* Z, const double* t, double* unext, int64_t n, double* part, int ng,
+                    const double* zsrc, double* zdst, double* H, int64_t ldh, int64_t hstride, double* hg, int nct,
+                    double* R, int64_t rstride, int nb, hipStream_t s);
 void launch_set_int(int* p, int v, hipStream_t s);                         // p[0] = v
 void launch_stage_cols(const double* H, int64_t ldh, int64_t hstride, const int* jdev, int back, int cnt, double* Hst,
                        int nb, hipStream_t s);                              // H columns j-back .. j-back+cnt-1

@@ -264,23 +264,21 @@ __global__ __launch_bounds__(256, 2) void k_mv_sym(const DomDesc* __restrict__ d
 // I <= J are read, each entry used as (r, c) and, off the diagonal, as (c, r); in a diagonal tile
 // the strict lower triangle is dropped and the diagonal halved).  Tiles flagged in their fourth
 // component belong to a subdomain whose block is the inverse of T_i itself: every tile (I, J) is
-// listed and used directly only, and the tiles J = 0 clear the transposed slot of their rows.  Same lane
-// layout, addressing and partial-slot layout as k_mv_sym; FP32 arithmetic.  A column group is
-// only 2 KB per wavefront, so the loads run D groups ahead through a ring of D + 1 register
-// slots (D = 3 measured fastest on the Gauss-Seidel stages, large and small: three wavefronts
-// per SIMD with three groups in flight each).
-constexpr int kPcDepth = 3;
-
-template <int D>
+// listed and used directly only, and the tiles J = 0 clear the transposed slot of their rows.  Same
+// lane layout within a column group, addressing and partial-slot layout as k_mv_sym; FP32
+// arithmetic.  One workgroup per tile: wavefront w takes the four column groups of columns
+// c0 + 16 w .. c0 + 16 w + 15 and issues all of its loads (8 KB) at once, so that a Gauss-Seidel
+// stage with few tiles still has its whole block in flight; the row sums of the four wavefronts
+// meet in LDS.
 __global__ __launch_bounds__(256) void k_pc_sym(const DomDesc* __restrict__ doms, const int4* __restrict__ stiles,
-                                                int64_t ntiles, const float* __restrict__ Ti,
-                                                const double* __restrict__ x, double* __restrict__ part) {
-    __shared__ float4 xs[4][64];                        // per wavefront: x_D, x_N at column c0 + l
+                                                const float* __restrict__ Ti, const double* __restrict__ x,
+                                                double* __restrict__ part) {
+    __shared__ float4 xs[64];                           // x_D, x_N at column c0 + l
+    __shared__ float4 xrs[64];                          // x_D, x_N at row r0 + l (0 past E)
+    __shared__ float4 red[4][64];                       // per wavefront: direct sums of row r0 + l
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t tix = (int64_t)blockIdx.x * 4 + wv;
-    const bool live = tix < ntiles;
-    const int4 t = stiles[live ? tix : ntiles - 1];
+    const int4 t = stiles[blockIdx.x];
     const DomDesc dd = doms[t.x];
     const int E = dd.E;
     const int I = t.y, J = t.z;
@@ -290,35 +288,31 @@ __global__ __launch_bounds__(256) void k_pc_sym(const DomDesc* __restrict__ doms
     const bool diag = I == J && !full;
     const double2* xD = reinterpret_cast<const double2*>(x) + dd.off;
     const double2* xN = xD + E;
-    {
-        const int c = c0 + lane;
+    if (wv < 2) {
+        const int c = (wv == 0 ? c0 : r0) + lane;
         const bool ok = c < E;
         const int cs = ok ? c : E - 1;
         const double2 d = xD[cs], nn = xN[cs];
-        xs[wv][lane] = ok ? make_float4((float)d.x, (float)d.y, (float)nn.x, (float)nn.y) : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 v = ok ? make_float4((float)d.x, (float)d.y, (float)nn.x, (float)nn.y) : make_float4(0.f, 0.f, 0.f, 0.f);
+        if (wv == 0) xs[lane] = v; else xrs[lane] = v;
     }
-    __syncthreads();
-    if (!live) return;                                  // no workgroup barrier below
     const char* Tt = reinterpret_cast<const char*>(reinterpret_cast<const float2*>(Ti) + dd.mat0 + r0 + (int64_t)c0 * E);
-    constexpr int NS = D + 1;                           // ring of column-group register slots
-    float2 a[NS][4];
-    auto load = [&](int k, int slot) {
-        const int c = c0 + 4 * k + cg;
+    float2 a[4][4];                                     // [column group][row i]
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c = c0 + 16 * wv + 4 * k + cg;
         const int cs = c < E ? c : E - 1;
         const uint32_t boff = ((uint32_t)rg + (uint32_t)(cs - c0) * (uint32_t)E) * (uint32_t)sizeof(float2);
         const float2* tp = reinterpret_cast<const float2*>(Tt + boff);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[slot][i] = tp[16 * i];
-    };
-    float xr[4][4];                                     // x_D, x_N of this lane's rows (0 past E)
+        for (int i = 0; i < 4; ++i) a[k][i] = tp[16 * i];
+    }
+    __syncthreads();
+    float xr[4][4];                                     // x_D, x_N of this lane's rows
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int r = r0 + rg + 16 * i;
-        const bool ok = r < E;
-        const int rs = ok ? r : E - 1;
-        const double2 d = xD[rs], nn = xN[rs];
-        xr[i][0] = ok ? (float)d.x : 0.f; xr[i][1] = ok ? (float)d.y : 0.f;
-        xr[i][2] = ok ? (float)nn.x : 0.f; xr[i][3] = ok ? (float)nn.y : 0.f;
+        const float4 v = xrs[rg + 16 * i];
+        xr[i][0] = v.x; xr[i][1] = v.y; xr[i][2] = v.z; xr[i][3] = v.w;
     }
     float acc[4][4];
 #pragma unroll
@@ -326,14 +320,14 @@ __global__ __launch_bounds__(256) void k_pc_sym(const DomDesc* __restrict__ doms
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[i][q] = 0.f;
     double* pbase = part + 2 * dd.part0;
-    auto step = [&](int k, auto slot, auto issue) {
-        constexpr int sl = decltype(slot)::value;
-        if constexpr (decltype(issue)::value) load(k + D, (sl + D) % NS);
-        const int c = c0 + 4 * k + cg;
-        const float4 xv = xs[wv][4 * k + cg];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int cl = 16 * wv + 4 * k + cg;            // column within the tile
+        const int c = c0 + cl;
+        const float4 xv = xs[cl];
         float e[4][2];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) { e[i][0] = a[sl][i].x; e[i][1] = a[sl][i].y; }
+        for (int i = 0; i < 4; ++i) { e[i][0] = a[k][i].x; e[i][1] = a[k][i].y; }
         if (diag) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -359,15 +353,7 @@ __global__ __launch_bounds__(256) void k_pc_sym(const DomDesc* __restrict__ doms
             const float u = row16_sum4(v, rg);
             if (rg < 4 && c < E) pbase[2 * ((int64_t)(2 * I + (rg & 1)) * E + c) + (rg >> 1)] = (double)u;
         }
-    };
-#pragma unroll
-    for (int k = 0; k < D; ++k) load(k, k);
-    // full rounds of NS steps keep every slot index compile-time; the last steps, some of which
-    // issue no load, follow
-    constexpr int kFull = ((16 - D) / NS) * NS;
-#pragma unroll 1
-    for (int k = 0; k < kFull; k += NS) ring_round<NS>(step, k, std::make_integer_sequence<int, NS>{});
-    ring_tail<NS, kFull, D, 16>(step, std::make_integer_sequence<int, 16 - kFull>{});
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -375,21 +361,27 @@ __global__ __launch_bounds__(256) void k_pc_sym(const DomDesc* __restrict__ doms
             acc[i][q] += __shfl_xor(acc[i][q], 16, 64);
             acc[i][q] += __shfl_xor(acc[i][q], 32, 64);
         }
-    if (cg != 0) return;
+    if (cg == 0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = r0 + rg + 16 * i;
-        if (r >= E) continue;
-        double* pD = pbase + 2 * ((int64_t)(2 * (J + 1)) * E + r);
-        double* pN = pbase + 2 * ((int64_t)(2 * (J + 1) + 1) * E + r);
-        *reinterpret_cast<double2*>(pD) = make_double2(acc[i][0], acc[i][1]);
-        *reinterpret_cast<double2*>(pN) = make_double2(acc[i][2], acc[i][3]);
-        if (full && J == 0) {                           // slot 0 (the transposed slot) is unused
-            double* zD = pbase + 2 * ((int64_t)0 * E + r);
-            double* zN = pbase + 2 * ((int64_t)E + r);
-            *reinterpret_cast<double2*>(zD) = make_double2(0.0, 0.0);
-            *reinterpret_cast<double2*>(zN) = make_double2(0.0, 0.0);
-        }
+        for (int i = 0; i < 4; ++i) red[wv][rg + 16 * i] = make_float4(acc[i][0], acc[i][1], acc[i][2], acc[i][3]);
+    }
+    __syncthreads();
+    // threads 0..63 write the D part of row r0 + l, threads 64..127 the N part
+    if (wv >= 2) return;
+    const int r = r0 + lane;
+    if (r >= E) return;
+    float sr = 0.f, si = 0.f;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const float4 v = red[w][lane];
+        sr += wv == 0 ? v.x : v.z;
+        si += wv == 0 ? v.y : v.w;
+    }
+    double* p = pbase + 2 * ((int64_t)(2 * (J + 1) + wv) * E + r);
+    *reinterpret_cast<double2*>(p) = make_double2(sr, si);
+    if (full && J == 0) {                               // slot 0 (the transposed slot) is unused
+        double* z0 = pbase + 2 * ((int64_t)wv * E + r);
+        *reinterpret_cast<double2*>(z0) = make_double2(0.0, 0.0);
     }
 }
 
@@ -583,26 +575,39 @@ __device__ inline double wsum(double v) {
 // The step index j is read from device memory (jdev[0]) by every kernel of a step, and the grids
 // do not depend on it, so a captured sequence of steps can be replayed.
 
-// hpart[((b*(nvmax+1) + i)*nblk + blk)*4 + {0,1,2,3}] = partial {conj(v_i).u, conj(v_i).t},
-// v_i = V_i for i < j and v_j = u = V_j; t = Tt (slab, ld n), or u itself when Tt is null.
-// blockIdx.y strides over groups of 16 vectors.
+// Row chunks of the basis reductions at step j: about T work units (16 vectors x one chunk) per
+// right-hand side, between cmin and kmax chunks.  Measured on the 27,648-row basis, about 1,300
+// units in flight read fastest from the first step (512 chunks of 64 rows) to the last (32 chunks
+// of 864 rows); fewer, longer chunks win once there are many vectors.  k_dot2 and k_reduce2 agree
+// on it.
+__device__ inline int dot_chunks(int nv, int T, int cmin, int kmax) {
+    const int c = T / (nv / 16 + 1);
+    return c < cmin ? cmin : min(c, kmax);
+}
+
+// hpart[((b*(nvmax+1) + i)*kmax + blk)*4 + {0,1,2,3}] = partial {conj(v_i).u, conj(v_i).t} over row
+// chunk blk, v_i = V_i for i < j and v_j = u = V_j; t = Tt (slab, ld n), or u itself when Tt is null.
+// Work unit k of a right-hand side is vector group k / nch, row chunk k % nch (nch = dot_chunks);
+// the workgroups stride over the units.
 __global__ __launch_bounds__(256) void k_dot2(const double* __restrict__ V, int64_t ldv, const int* __restrict__ jdev,
                                               int nvmax, const double* __restrict__ Tt, int64_t n,
-                                              double* __restrict__ hpart, int nblk) {
-    // Row chunk blockIdx.x of the basis against 16 vectors per workgroup: lane (rg = l % 16,
-    // g = l / 16) of wavefront w takes vector 16 vg + 4 w + g and rows lo + rg + 16 m, so that a
-    // load instruction reads 16 consecutive rows of four vectors and the 16 row lanes of a vector
-    // meet in one cross-lane reduction at the end of the chunk.
+                                              double* __restrict__ hpart, int T, int cmin, int kmax) {
+    // Row chunk of the basis against 16 vectors per work unit: lane (rg = l % 16, g = l / 16) of
+    // wavefront w takes vector 16 vg + 4 w + g and rows lo + rg + 16 m, so that a load instruction
+    // reads 16 consecutive rows of four vectors and the 16 row lanes of a vector meet in one
+    // cross-lane reduction at the end of the chunk.
     const int nv = jdev[0];
     const int b = blockIdx.z;
-    const int blk = blockIdx.x;
-    const int64_t chunk = (n + nblk - 1) / nblk;
-    const int64_t lo = blk * chunk, hi = min(n, lo + chunk);
+    const int nch = dot_chunks(nv, T, cmin, kmax);
+    const int64_t chunk = ((n + nch - 1) / nch + 15) / 16 * 16;
     const double2* u = reinterpret_cast<const double2*>(V + 2 * ((int64_t)nv * ldv + (int64_t)b * n));
     const double2* t = Tt ? reinterpret_cast<const double2*>(Tt + 2 * (int64_t)b * n) : u;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int rg = lane & 15, g = lane >> 4;
-    for (int vg = blockIdx.y; vg * 16 <= nv; vg += gridDim.y) {
+    const int units = (nv / 16 + 1) * nch;
+    for (int unit = blockIdx.x; unit < units; unit += gridDim.x) {
+        const int vg = unit / nch, blk = unit - vg * nch;
+        const int64_t lo = blk * chunk, hi = min(n, lo + chunk);
         const int i = vg * 16 + w * 4 + g;
         const int is = i <= nv ? i : nv;
         const double2* v = reinterpret_cast<const double2*>(V + 2 * ((int64_t)is * ldv + (int64_t)b * n));
@@ -618,21 +623,29 @@ __global__ __launch_bounds__(256) void k_dot2(const double* __restrict__ V, int6
         // lanes rg = 0, 1, 2, 3 hold the sums of a[0], a[2], a[1], a[3]
         const double sum = row16_sum4(a, rg);
         if (i <= nv && rg < 4)
-            hpart[(((int64_t)b * (nvmax + 1) + i) * nblk + blk) * 4 + 2 * (rg & 1) + (rg >> 1)] = sum;
+            hpart[(((int64_t)b * (nvmax + 1) + i) * kmax + blk) * 4 + 2 * (rg & 1) + (rg >> 1)] = sum;
     }
 }
 
-// S_i, Z_i from the partial sums, i <= j
-__global__ void k_reduce2(const double* __restrict__ hpart, const int* __restrict__ jdev, int nvmax, int nblk,
-                          double* __restrict__ S, double* __restrict__ Z) {
+// S_i, Z_i from the partial sums, i <= j: one wavefront per vector
+__global__ __launch_bounds__(256) void k_reduce2(const double* __restrict__ hpart, const int* __restrict__ jdev,
+                                                 int nvmax, int T, int cmin, int kmax, double* __restrict__ S,
+                                                 double* __restrict__ Z) {
     const int nv = jdev[0];
     const int b = blockIdx.y;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i > nv) return;
+    const int nch = dot_chunks(nv, T, cmin, kmax);
     double a[4] = {0, 0, 0, 0};
-    const double* p = hpart + ((int64_t)b * (nvmax + 1) + i) * nblk * 4;
-    for (int k = 0; k < nblk; ++k)
-        for (int q = 0; q < 4; ++q) a[q] += p[4 * k + q];
+    const double* p = hpart + ((int64_t)b * (nvmax + 1) + i) * kmax * 4;
+    for (int k = lane; k < nch; k += 64) {
+        const double4 q = *reinterpret_cast<const double4*>(p + 4 * k);
+        a[0] += q.x; a[1] += q.y; a[2] += q.z; a[3] += q.w;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = wsum(a[q]);
+    if (lane != 0) return;
     const int64_t o = (int64_t)b * (nvmax + 1) + i;
     S[2 * o] = a[0]; S[2 * o + 1] = a[1];
     Z[2 * o] = a[2]; Z[2 * o + 1] = a[3];
@@ -643,18 +656,16 @@ __global__ void k_reduce2(const double* __restrict__ hpart, const int* __restric
 // row j of column j-1 is not final yet and is left out (k_dcgs_col adds its share).  Tiles with
 // rt > kc + 1 lie below the band: they are neither written nor read.  blockIdx.x strides over the
 // tiles of the (rt, kc) grid.
-__global__ __launch_bounds__(256) void k_hess_gemv(const double* __restrict__ H, int64_t ldh, int64_t hstride,
-                                                   const double* __restrict__ S, const int* __restrict__ jdev, int nvmax,
-                                                   int nct, double* __restrict__ hg) {
-    const int nv = jdev[0];
+__device__ inline void hess_gemv_body(const double* __restrict__ H, int64_t ldh, int64_t hstride,
+                                      const double* __restrict__ S, int nv, int nvmax, int nct,
+                                      double* __restrict__ hg, int b, int tile0, int tstride) {
     if (nv < 1) return;
-    const int b = blockIdx.z;
     const int nrt = (nv + 1 + 63) / 64, nkc = (nv + 63) / 64;
     const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
     const double* Hb = H + 2 * (int64_t)b * hstride;
     const double* sb = S + 2 * (int64_t)b * (nvmax + 1);
     __shared__ double red[4][64][2];
-    for (int tile = blockIdx.x; tile < nrt * nkc; tile += gridDim.x) {
+    for (int tile = tile0; tile < nrt * nkc; tile += tstride) {
         const int rt = tile % nrt, kc = tile / nrt;
         if (rt > kc + 1) continue;
         const int i = rt * 64 + r;
@@ -685,20 +696,13 @@ __global__ __launch_bounds__(256) void k_hess_gemv(const double* __restrict__ H,
     }
 }
 
-// nu, c; finalise Hessenberg column j-1; first-pass column j (skipped when `last`).
-// When R is given, column j of the triangular factor U = Q R of the candidates is stored too:
-// R[i, j] = s_i (i < j), R[j, j] = nu (per right-hand side at R + b*rstride, ld ldh).
-__global__ __launch_bounds__(256) void k_dcgs_col(double* __restrict__ H, int64_t ldh, int64_t hstride,
-                                                  const double* __restrict__ S, const double* __restrict__ Z,
-                                                  const double* __restrict__ hg, int nct, const int* __restrict__ jdev,
-                                                  int nvmax, double* __restrict__ scal, int last, double* __restrict__ R,
-                                                  int64_t rstride) {
-    const int nv = jdev[0];
-    const int b = blockIdx.y;
-    const double* sb = S + 2 * (int64_t)b * (nvmax + 1);
-    const double* zb = Z + 2 * (int64_t)b * (nvmax + 1);
+// nu = sqrt(alpha - |s|^2) and c = (gamma - s^H z) / nu of right-hand side b (alpha, gamma in
+// slot j of S, Z).  Every workgroup of 256 threads that calls this sums in the same order, so all
+// of them get the same values.
+__device__ inline void dcgs_scalars(const double* __restrict__ sb, const double* __restrict__ zb, int nv,
+                                    double& nu, double& cr, double& ci) {
     double ss = 0, pr = 0, pi = 0;
-    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+    for (int i = threadIdx.x; i < nv; i += 256) {
         const double sr = sb[2 * i], si = sb[2 * i + 1], zr = zb[2 * i], zi = zb[2 * i + 1];
         ss += sr * sr + si * si;
         pr += sr * zr + si * zi;
@@ -710,14 +714,31 @@ __global__ __launch_bounds__(256) void k_dcgs_col(double* __restrict__ H, int64_
     if (lane == 0) { red[0][wv] = ss; red[1][wv] = pr; red[2][wv] = pi; }
     __syncthreads();
     ss = pr = pi = 0;
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { ss += red[0][k]; pr += red[1][k]; pi += red[2][k]; }
+    for (int k = 0; k < 4; ++k) { ss += red[0][k]; pr += red[1][k]; pi += red[2][k]; }
     const double alpha = sb[2 * nv];
     const double nu2 = alpha - ss;
-    const double nu = nu2 > 0 ? sqrt(nu2) : 0.0;
+    nu = nu2 > 0 ? sqrt(nu2) : 0.0;
     const double inv = nu > 0 ? 1.0 / nu : 0.0;
-    const double cr = (zb[2 * nv] - pr) * inv, ci = (zb[2 * nv + 1] - pi) * inv;
-    if (blockIdx.x == 0 && threadIdx.x == 0) { scal[4 * b] = nu; scal[4 * b + 1] = cr; scal[4 * b + 2] = ci; }
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    cr = (zb[2 * nv] - pr) * inv;
+    ci = (zb[2 * nv + 1] - pi) * inv;
+}
+
+// Finalise Hessenberg column j-1 and write the first-pass column j (skipped when `last`) for rows
+// bx*256 .. bx*256+255.  When R is given, column j of the triangular factor U = Q R of the
+// candidates is stored too: R[i, j] = s_i (i < j), R[j, j] = nu (per right-hand side at
+// R + b*rstride, ld ldh).  When scal is given, {nu, Re c, Im c} go to scal + 4b.
+__device__ inline void dcgs_col_body(double* __restrict__ H, int64_t ldh, int64_t hstride,
+                                     const double* __restrict__ S, const double* __restrict__ Z,
+                                     const double* __restrict__ hg, int nct, int nv, int nvmax,
+                                     double* __restrict__ scal, int last, double* __restrict__ R, int64_t rstride,
+                                     int b, int bx) {
+    const double* sb = S + 2 * (int64_t)b * (nvmax + 1);
+    const double* zb = Z + 2 * (int64_t)b * (nvmax + 1);
+    double nu, cr, ci;
+    dcgs_scalars(sb, zb, nv, nu, cr, ci);
+    const double inv = nu > 0 ? 1.0 / nu : 0.0;
+    if (scal && bx == 0 && threadIdx.x == 0) { scal[4 * b] = nu; scal[4 * b + 1] = cr; scal[4 * b + 2] = ci; }
+    const int i = bx * 256 + threadIdx.x;
     if (i > nv) return;
     if (R) {
         double* Rc = R + 2 * ((int64_t)b * rstride + (int64_t)nv * ldh);
@@ -751,21 +772,43 @@ __global__ __launch_bounds__(256) void k_dcgs_col(double* __restrict__ H, int64_
     Hn[2 * i + 1] = (zi - hi) * inv;
 }
 
-// part[((b*ng + g)*n + e)*4 + {0..3}] = sum over the chunks c = g, g+ng, ... of 64 vectors of
-// {V_i s_i, V_i z_i}, i < j (zero when a group has no chunk).
+// nu, c into scal; finalise Hessenberg column j-1; first-pass column j (skipped when `last`).
+__global__ __launch_bounds__(256) void k_dcgs_col(double* __restrict__ H, int64_t ldh, int64_t hstride,
+                                                  const double* __restrict__ S, const double* __restrict__ Z,
+                                                  const double* __restrict__ hg, int nct, const int* __restrict__ jdev,
+                                                  int nvmax, double* __restrict__ scal, int last, double* __restrict__ R,
+                                                  int64_t rstride) {
+    dcgs_col_body(H, ldh, hstride, S, Z, hg, nct, jdev[0], nvmax, scal, last, R, rstride, blockIdx.y, blockIdx.x);
+}
+
+// part[((b*ng + g)*n + e)*4 + {0..3}] = sum over the vectors i < j of group g of {V_i s_i, V_i z_i}
+// (zero when a group has none).  The workgroups with
+// blockIdx.x >= nxp instead form the partial products of the Hessenberg matrix with s
+// (hess_gemv_body), which need nothing but S: the two independent parts of a step share a launch.
 __global__ __launch_bounds__(256) void k_update2_part(const double* __restrict__ V, int64_t ldv,
                                                       const int* __restrict__ jdev, int nvmax,
                                                       const double* __restrict__ S, const double* __restrict__ Z,
-                                                      double* __restrict__ part, int64_t n) {
+                                                      double* __restrict__ part, int64_t n, int nxp,
+                                                      const double* __restrict__ H, int64_t ldh, int64_t hstride,
+                                                      int nct, double* __restrict__ hg) {
     const int nv = jdev[0];
     const int b = blockIdx.z;
+    if ((int)blockIdx.x >= nxp) {
+        const int nhx = gridDim.x - nxp;
+        hess_gemv_body(H, ldh, hstride, S, nv, nvmax, nct, hg, b, (blockIdx.x - nxp) + nhx * blockIdx.y,
+                       nhx * gridDim.y);
+        return;
+    }
     __shared__ double cs[4 * 64];
     const int g = blockIdx.y, ng = gridDim.y;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t cb = (int64_t)b * (nvmax + 1);
     double ar = 0, ai = 0, br = 0, bi = 0;
-    for (int i0 = g * 64; i0 < nv; i0 += ng * 64) {
-        const int cnt = min(64, nv - i0);
+    // group g takes vectors [g cv, (g + 1) cv), cv = ceil(j / ng) rounded up to 8, in LDS batches of 64
+    const int cv = ((nv + ng - 1) / ng + 7) / 8 * 8;
+    const int vend = min(nv, (g + 1) * cv);
+    for (int i0 = g * cv; i0 < vend; i0 += 64) {
+        const int cnt = min(64, vend - i0);
         __syncthreads();
         if ((int)threadIdx.x < cnt) {
             const int64_t o = cb + i0 + threadIdx.x;
@@ -805,13 +848,26 @@ __global__ __launch_bounds__(256) void k_update2_part(const double* __restrict__
 
 // q_j = (u - Q s)/nu into slot j, u' = (t - Q z - q_j c)/nu into slot j+1 and into Unext; when Zsrc
 // is given it is also copied into slot j of Zdst (the preconditioned candidate of flexible GMRES).
+// Each workgroup forms nu and c itself from S and Z (dcgs_scalars).  The workgroups with
+// blockIdx.x >= nxa finalise the Hessenberg columns instead (dcgs_col_body, rows 256 (blockIdx.x -
+// nxa) onwards), which needs the partial products hg of the previous launch.
 __global__ __launch_bounds__(256) void k_update2_apply(const double* __restrict__ part, int ng, double* __restrict__ V,
                                                        int64_t ldv, const int* __restrict__ jdev, int* __restrict__ jnext,
                                                        const double* __restrict__ Tt, double* __restrict__ Unext,
-                                                       int64_t n, const double* __restrict__ scal,
-                                                       const double* __restrict__ Zsrc, double* __restrict__ Zdst) {
+                                                       int64_t n, const double* __restrict__ Zsrc,
+                                                       double* __restrict__ Zdst, int nxa, int nvmax,
+                                                       const double* __restrict__ S, const double* __restrict__ Z,
+                                                       double* __restrict__ H, int64_t ldh, int64_t hstride,
+                                                       const double* __restrict__ hg, int nct, double* __restrict__ R,
+                                                       int64_t rstride) {
     const int nv = jdev[0];
     const int b = blockIdx.y;
+    if ((int)blockIdx.x >= nxa) {
+        dcgs_col_body(H, ldh, hstride, S, Z, hg, nct, nv, nvmax, nullptr, 0, R, rstride, b, blockIdx.x - nxa);
+        return;
+    }
+    double nu, cr, ci;
+    dcgs_scalars(S + 2 * (int64_t)b * (nvmax + 1), Z + 2 * (int64_t)b * (nvmax + 1), nv, nu, cr, ci);
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e == 0 && b == 0) jnext[0] = nv + 1;      // the other slot: read by the next step only
     if (e >= n) return;
@@ -820,7 +876,6 @@ __global__ __launch_bounds__(256) void k_update2_apply(const double* __restrict_
         const double* p = part + (((int64_t)b * ng + g) * n + e) * 4;
         ar += p[0]; ai += p[1]; br += p[2]; bi += p[3];
     }
-    const double nu = scal[4 * b], cr = scal[4 * b + 1], ci = scal[4 * b + 2];
     const double inv = nu > 0 ? 1.0 / nu : 0.0;
     double* u = V + 2 * ((int64_t)nv * ldv + (int64_t)b * n + e);
     double* un = V + 2 * ((int64_t)(nv + 1) * ldv + (int64_t)b * n + e);
@@ -1290,7 +1345,7 @@ void launch_matvec_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int64
 void launch_precond_sym(const DomDesc* doms, const int4* stiles, int64_t ntiles, const float* Tinv, const double* x,
                         double* part, hipStream_t s) {
     if (ntiles <= 0) return;
-    hipLaunchKernelGGL(k_pc_sym<kPcDepth>, dim3(gridn(ntiles, 4)), dim3(256), 0, s, doms, stiles, ntiles, Tinv, x, part);
+    hipLaunchKernelGGL(k_pc_sym, dim3((unsigned)ntiles), dim3(256), 0, s, doms, stiles, Tinv, x, part);
 }
 
 void launch_precond_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int64_t ndof, const double* part, double* z,
@@ -1313,24 +1368,15 @@ void launch_gs_residual(const DomDesc* doms, const int32_t* dof_dom, const int32
 }
 
 void launch_dot2(const double* V, int64_t ldv, const int* jdev, int nvmax, const double* t, int64_t n, double* hpart,
-                 int nblk, int nb, hipStream_t s) {
-    const int gy = std::max(1, std::min((nvmax + 16) / 16, 4096 / (nblk * nb)));   // 16 vectors per workgroup
-    hipLaunchKernelGGL(k_dot2, dim3((unsigned)nblk, (unsigned)gy, (unsigned)nb), dim3(256), 0, s, V, ldv, jdev, nvmax, t,
-                       n, hpart, nblk);
+                 const DotPlan& d, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot2, dim3((unsigned)d.grid, 1, (unsigned)nb), dim3(256), 0, s, V, ldv, jdev, nvmax, t, n, hpart,
+                       d.units, d.cmin, d.kmax);
 }
 
-void launch_reduce2(const double* hpart, const int* jdev, int nvmax, int nblk, double* S, double* Z, int nb,
+void launch_reduce2(const double* hpart, const int* jdev, int nvmax, const DotPlan& d, double* S, double* Z, int nb,
                     hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce2, dim3(gridn(nvmax + 1, 128), (unsigned)nb), dim3(128), 0, s, hpart, jdev, nvmax, nblk,
-                       S, Z);
-}
-
-void launch_hess_gemv(const double* H, int64_t ldh, int64_t hstride, const double* S, const int* jdev, int nvmax, int nct,
-                      double* hg, int nb, hipStream_t s) {
-    const int tiles = ((nvmax + 1 + 63) / 64) * ((nvmax + 63) / 64);
-    const int gx = std::max(1, std::min(tiles, 256));
-    hipLaunchKernelGGL(k_hess_gemv, dim3((unsigned)gx, 1, (unsigned)nb), dim3(256), 0, s, H, ldh, hstride, S, jdev, nvmax,
-                       nct, hg);
+    hipLaunchKernelGGL(k_reduce2, dim3(gridn(nvmax + 1, 4), (unsigned)nb), dim3(256), 0, s, hpart, jdev, nvmax, d.units,
+                       d.cmin, d.kmax, S, Z);
 }
 
 void launch_dcgs_col(double* H, int64_t ldh, int64_t hstride, const double* S, const double* Z, const double* hg, int nct,
@@ -1340,13 +1386,19 @@ void launch_dcgs_col(double* H, int64_t ldh, int64_t hstride, const double* S, c
 }
 
 void launch_update2(const double* V_, int64_t ldv, const int* jdev, int* jnext, int nvmax, const double* S,
-                    const double* Z, const double* t, double* unext, int64_t n, double* part, int ng, const double* scal,
-                    const double* zsrc, double* zdst, int nb, hipStream_t s) {
+                    const double* Z, const double* t, double* unext, int64_t n, double* part, int ng,
+                    const double* zsrc, double* zdst, double* H, int64_t ldh, int64_t hstride, double* hg, int nct,
+                    double* R, int64_t rstride, int nb, hipStream_t s) {
     double* V = const_cast<double*>(V_);
-    hipLaunchKernelGGL(k_update2_part, dim3(gridn(n, 256), (unsigned)ng, (unsigned)nb), dim3(256), 0, s, V, ldv, jdev,
-                       nvmax, S, Z, part, n);
-    hipLaunchKernelGGL(k_update2_apply, dim3(gridn(n, 256), (unsigned)nb), dim3(256), 0, s, part, ng, V, ldv, jdev,
-                       jnext, t, unext, n, scal, zsrc, zdst);
+    const int nxp = (int)gridn(n, 256);
+    const int tiles = ((nvmax + 1 + 63) / 64) * ((nvmax + 63) / 64);
+    const int nhx = std::max(1, (std::min(tiles, 256) + ng - 1) / ng);
+    hipLaunchKernelGGL(k_update2_part, dim3((unsigned)(nxp + nhx), (unsigned)ng, (unsigned)nb), dim3(256), 0, s, V, ldv,
+                       jdev, nvmax, S, Z, part, n, nxp, H, ldh, hstride, nct, hg);
+    const int nxa = (int)gridn(n, 256);
+    const int ncx = (int)gridn(nvmax + 1, 256);
+    hipLaunchKernelGGL(k_update2_apply, dim3((unsigned)(nxa + ncx), (unsigned)nb), dim3(256), 0, s, part, ng, V, ldv,
+                       jdev, jnext, t, unext, n, zsrc, zdst, nxa, nvmax, S, Z, H, ldh, hstride, hg, nct, R, rstride);
 }
 
 void launch_set_int(int* p, int v, hipStream_t s) { hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, p, v); }
