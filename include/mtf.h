@@ -76,6 +76,12 @@ extern "C" {
  * instead of from its symmetric part; see mtf_solve.  Rebuilds the blocks when the last build
  * used the other kind. */
 #define MTF_SOLVE_PC_FULL 2
+/* Store the Krylov basis in complex64 (compressed-basis GMRES: Aliaga, Anzt, Grutzmacher,
+ * Quintana-Orti and Tomas): the Arnoldi arithmetic and the candidate vector stay complex128,
+ * each orthonormal basis vector is rounded to complex64 when it is stored, which halves the bytes
+ * of the two passes over the basis per step.  Needs a preconditioner (the flexible iteration,
+ * whose correction uses the complex128 preconditioned vectors). */
+#define MTF_SOLVE_BASIS_C64 4
 
 typedef struct mtf_problem_s* mtf_problem;
 
@@ -198,7 +204,7 @@ typedef struct {
     int32_t max_iters;        /* Arnoldi steps per GMRES cycle; 0: as many as half the free
                                  device memory holds, at most 8000 (2000 for lockstep batches) */
     int32_t max_refinements;  /* outer FP64 refinement steps (MTF_FP32_MIXED), 0 = 10        */
-    int32_t flags;            /* 0, or MTF_SOLVE_EAGER and/or MTF_SOLVE_PC_FULL              */
+    int32_t flags;            /* 0, or MTF_SOLVE_EAGER, MTF_SOLVE_PC_FULL, MTF_SOLVE_BASIS_C64 */
     double  rtol;             /* ||b - M x||_2 <= rtol ||b||_2 with the FP64 operator        */
     double  inner_rtol;       /* inner GMRES tolerance of a refinement step, 0 = 1e-3*... */
     const void* x0_dev;       /* complex128 initial guess [nrhs][ld] or NULL (zero)          */

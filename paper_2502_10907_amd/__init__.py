@@ -34,6 +34,7 @@ BLOCK_T, BLOCK_K = 0, 1
 PREC_NONE, PREC_BLOCK_TINV, PREC_BLOCK_TINV_GS = 0, 1, 2
 SOLVE_EAGER = 1
 SOLVE_PC_FULL = 2
+SOLVE_BASIS_C64 = 4
 ASSEMBLE_ROUND_FP64 = 1
 
 
@@ -296,7 +297,7 @@ class Problem:
 
     def solve(self, b, x, rtol: float = 1e-6, precision: int = FP64, preconditioner: int = PREC_BLOCK_TINV,
               max_iters: int = 0, max_refinements: int = 0, inner_rtol: float = 0.0, x0=None,
-              graph: bool = True, pc_full: bool = False) -> list[Stats]:
+              graph: bool = True, pc_full: bool = False, basis_c64: bool = False) -> list[Stats]:
         pb, nrhs, ld = _dev(b, self.N)
         px, nrhs2, ld2 = _dev(x, self.N)
         if (nrhs, ld) != (nrhs2, ld2):
@@ -307,7 +308,9 @@ class Problem:
             if (n3, ld3) != (nrhs, ld):
                 raise ValueError("x0 shape differs")
         o = SolveOpts(C.sizeof(SolveOpts), int(precision), int(preconditioner), int(max_iters),
-                      int(max_refinements), (0 if graph else SOLVE_EAGER) | (SOLVE_PC_FULL if pc_full else 0),
+                      int(max_refinements),
+                      (0 if graph else SOLVE_EAGER) | (SOLVE_PC_FULL if pc_full else 0) |
+                      (SOLVE_BASIS_C64 if basis_c64 else 0),
                       float(rtol), float(inner_rtol), x0p)
         st = (SolveStats * nrhs)()
         code = _check(_lib.mtf_solve(self._h, nrhs, pb, px, ld, C.byref(o), st))
@@ -454,12 +457,13 @@ class Batch:
         _check(_lib.mtf_batch_assemble(self._h, C.byref(o), C.byref(g), C.byref(t)))
         return g.value, t.value
 
-    def solve(self, bs, xs, rtol=1e-6, precision=FP64, preconditioner=PREC_BLOCK_TINV, max_iters=0, graph=True):
+    def solve(self, bs, xs, rtol=1e-6, precision=FP64, preconditioner=PREC_BLOCK_TINV, max_iters=0, graph=True,
+              basis_c64=False):
         n = len(self.problems)
         pb = (_P * n)(*[_dev(b, p.N)[0].value for b, p in zip(bs, self.problems)])
         px = (_P * n)(*[_dev(x, p.N)[0].value for x, p in zip(xs, self.problems)])
         o = SolveOpts(C.sizeof(SolveOpts), int(precision), int(preconditioner), int(max_iters), 0,
-                      0 if graph else SOLVE_EAGER, float(rtol), 0.0, None)
+                      (0 if graph else SOLVE_EAGER) | (SOLVE_BASIS_C64 if basis_c64 else 0), float(rtol), 0.0, None)
         st = (SolveStats * n)()
         _check(_lib.mtf_batch_solve(self._h, pb, px, C.byref(o), st))
         return [Stats(s.iterations, s.refinements, bool(s.converged), s.rel_residual, s.t_precond_s, s.t_solve_s,

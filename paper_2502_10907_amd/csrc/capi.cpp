@@ -867,7 +867,7 @@ void apply_inner(mtf_problem p, const double* src, double* dst, int nb, int prec
 // Returns the number of Arnoldi steps taken; it[b], est[b] (recurrence residual / ||r_b||) per column.
 int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, int prec, int pc,
                 const std::vector<double>& tol, int maxit, std::vector<int>& itv, std::vector<double>& est,
-                std::vector<int>& reorth, bool graph, double relax) {
+                std::vector<int>& reorth, bool graph, double relax, bool c64) {
     GmresWork& w = p->gw;
     hipStream_t s = p->stream;
     const int64_t n = w.n;
@@ -883,7 +883,8 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
     auto Hc = [&](int j) { return w.H.p + 2 * ldh * (int64_t)j; };
     std::vector<double> beta = norms_dev(p, R, n, nb);
     // u_0 = r, step index 0
-    HIPCHK(hipMemcpyAsync(V, R, (size_t)2 * n * nb * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (c64 && !flex) throw ArgError("a complex64 basis needs the flexible (preconditioned) iteration");
+    if (!c64) HIPCHK(hipMemcpyAsync(V, R, (size_t)2 * n * nb * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(w.ufix.p, R, (size_t)2 * n * nb * sizeof(double), hipMemcpyDeviceToDevice, s));
     launch_set_int(jslot(0), 0, s);
     // Relaxed products (complex64 operator only): the steps use the FP64 operator until every
@@ -894,11 +895,11 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
     auto step = [&](int jj) {
         const int* jr = jslot(jj);
         apply_inner(p, w.ufix.p, w.tfix.p, nb, cur_prec, pc, flex ? w.zfix.p : nullptr);
-        launch_dot2(V, ldv, jr, nvmax, w.tfix.p, n, w.hpart.p, dot_plan(nb), nb, s);
+        launch_dot2(V, ldv, jr, nvmax, w.tfix.p, w.ufix.p, n, w.hpart.p, dot_plan(nb), c64, nb, s);
         launch_reduce2(w.hpart.p, jr, nvmax, dot_plan(nb), w.S.p, w.Z.p, nb, s);
         launch_update2(V, ldv, jr, jslot(jj + 1), nvmax, w.S.p, w.Z.p, w.tfix.p, w.ufix.p, n, w.upart.p, kUpdGroups,
                        flex ? w.zfix.p : nullptr, flex ? w.Zt.p : nullptr, w.H.p, ldh, hstride, w.hg.p, nct,
-                       flex ? w.Rf.p : nullptr, hstride, nb, s);
+                       flex ? w.Rf.p : nullptr, hstride, c64, nb, s);
     };
     // kSync steps j0 .. j0+kSync-1 (j0 odd), then the final columns j0-1 .. j0+kSync-2 staged and
     // copied to w.host
@@ -1020,7 +1021,7 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
         }
         // tail: the remaining steps one by one, then the step that only finalises column maxit-1
         for (; j < maxit; ++j) step(j);
-        launch_dot2(V, ldv, jslot(maxit), nvmax, nullptr, n, w.hpart.p, dot_plan(nb), nb, s);
+        launch_dot2(V, ldv, jslot(maxit), nvmax, nullptr, w.ufix.p, n, w.hpart.p, dot_plan(nb), c64, nb, s);
         launch_reduce2(w.hpart.p, jslot(maxit), nvmax, dot_plan(nb), w.S.p, w.Z.p, nb, s);
         launch_dcgs_col(w.H.p, ldh, hstride, w.S.p, w.Z.p, w.hg.p, nct, jslot(maxit), nvmax, w.scal.p, 1, nullptr,
                         hstride, nb, s);
@@ -1094,7 +1095,9 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
     DeviceGuard g(p->device);
     const int pc = opts.preconditioner;
     const bool use_pc = pc != MTF_PREC_NONE;
-    if (opts.flags & ~(MTF_SOLVE_EAGER | MTF_SOLVE_PC_FULL)) throw ArgError("unknown solve flags");
+    if (opts.flags & ~(MTF_SOLVE_EAGER | MTF_SOLVE_PC_FULL | MTF_SOLVE_BASIS_C64)) throw ArgError("unknown solve flags");
+    const bool basis_c64 = (opts.flags & MTF_SOLVE_BASIS_C64) != 0;
+    if (basis_c64 && !use_pc) throw ArgError("MTF_SOLVE_BASIS_C64 needs a preconditioner (the flexible iteration)");
     const bool graph = (opts.flags & MTF_SOLVE_EAGER) == 0;
     const bool pc_full = (opts.flags & MTF_SOLVE_PC_FULL) != 0;
     double t_pc = 0;
@@ -1169,7 +1172,7 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
                 if (delta < 0.0) delta = operator_gap(p, w.r.p);
                 if (delta > 0.0) relax = std::min(1.0, 0.01 * tol[0] / delta);
             }
-            total += gmres_cycle(p, w.r.p, X, ld, nb, prec, pc, tol, maxit, itv, est, reorth, graph, relax);
+            total += gmres_cycle(p, w.r.p, X, ld, nb, prec, pc, tol, maxit, itv, est, reorth, graph, relax, basis_c64);
             for (int b = 0; b < nb; ++b) iters[b] += itv[b];
         }
         const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

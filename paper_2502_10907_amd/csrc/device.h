@@ -118,8 +118,10 @@ inline DotPlan dot_plan(int nb) {
     d.kmax = d.units < 512 ? (d.units < 32 ? 32 : d.units) : 512;
     return d;
 }
-void launch_dot2(const double* V, int64_t ldv, const int* jdev, int nvmax, const double* t, int64_t n, double* hpart,
-                 const DotPlan& d, int nb, hipStream_t s);                  // partial Q^H [u t], u^H [u t] (t null: t = u)
+// V holds the basis in complex128 or, when c64, in complex64 (the same ldv, in entries); U is the
+// complex128 copy of the candidate u (read instead of slot j when c64).
+void launch_dot2(const double* V, int64_t ldv, const int* jdev, int nvmax, const double* t, const double* U, int64_t n,
+                 double* hpart, const DotPlan& d, bool c64, int nb, hipStream_t s);  // partial Q^H [u t], u^H [u t] (t null: t = u)
 void launch_reduce2(const double* hpart, const int* jdev, int nvmax, const DotPlan& d, double* S, double* Z, int nb,
                     hipStream_t s);
 void launch_dcgs_col(double* H, int64_t ldh, int64_t hstride, const double* S, const double* Z, const double* hg, int nct,
@@ -130,7 +132,7 @@ void launch_dcgs_col(double* H, int64_t ldh, int64_t hstride, const double* S, c
 void launch_update2(const double* V, int64_t ldv, const int* jdev, int* jnext, int nvmax, const double* S,
                     const double* Z, const double* t, double* unext, int64_t n, double* part, int ng,
                     const double* zsrc, double* zdst, double* H, int64_t ldh, int64_t hstride, double* hg, int nct,
-                    double* R, int64_t rstride, int nb, hipStream_t s);
+                    double* R, int64_t rstride, bool c64, int nb, hipStream_t s);
 void launch_set_int(int* p, int v, hipStream_t s);                         // p[0] = v
 void launch_stage_cols(const double* H, int64_t ldh, int64_t hstride, const int* jdev, int back, int cnt, double* Hst,
                        int nb, hipStream_t s);                              // H columns j-back .. j-back+cnt-1

@@ -585,11 +585,26 @@ __device__ inline int dot_chunks(int nv, int T, int cmin, int kmax) {
     return c < cmin ? cmin : min(c, kmax);
 }
 
+// One basis entry as complex128: the basis is stored in complex128 (double2) or complex64 (float2).
+__device__ inline double2 basis_ld(const double2* p) { return *p; }
+__device__ inline double2 basis_ld(const float2* p) {
+    const float2 f = *p;
+    return make_double2((double)f.x, (double)f.y);
+}
+
+// acc += {conj(x) u, conj(x) t}, stored as (re, im, re, im)
+__device__ inline void dot2_acc(double (&a)[4], double2 x, double2 uu, double2 tt) {
+    a[0] = fma(x.x, uu.x, fma(x.y, uu.y, a[0]));
+    a[1] = fma(x.x, uu.y, fma(-x.y, uu.x, a[1]));
+    a[2] = fma(x.x, tt.x, fma(x.y, tt.y, a[2]));
+    a[3] = fma(x.x, tt.y, fma(-x.y, tt.x, a[3]));
+}
+
 // hpart[((b*(nvmax+1) + i)*kmax + blk)*4 + {0,1,2,3}] = partial {conj(v_i).u, conj(v_i).t} over row
 // chunk blk, v_i = V_i for i < j and v_j = u = V_j; t = Tt (slab, ld n), or u itself when Tt is null.
-// Work unit k of a right-hand side is vector group k / nch, row chunk k % nch (nch = dot_chunks);
-// the workgroups stride over the units.
-__global__ __launch_bounds__(256) void k_dot2(const double* __restrict__ V, int64_t ldv, const int* __restrict__ jdev,
+// Complex128 basis.  Work unit k of a right-hand side is vector group k / nch, row chunk k % nch
+// (nch = dot_chunks); the workgroups stride over the units.
+__global__ __launch_bounds__(256) void k_dot2(const double2* __restrict__ V, int64_t ldv, const int* __restrict__ jdev,
                                               int nvmax, const double* __restrict__ Tt, int64_t n,
                                               double* __restrict__ hpart, int T, int cmin, int kmax) {
     // Row chunk of the basis against 16 vectors per work unit: lane (rg = l % 16, g = l / 16) of
@@ -600,8 +615,8 @@ __global__ __launch_bounds__(256) void k_dot2(const double* __restrict__ V, int6
     const int b = blockIdx.z;
     const int nch = dot_chunks(nv, T, cmin, kmax);
     const int64_t chunk = ((n + nch - 1) / nch + 15) / 16 * 16;
-    const double2* u = reinterpret_cast<const double2*>(V + 2 * ((int64_t)nv * ldv + (int64_t)b * n));
-    const double2* t = Tt ? reinterpret_cast<const double2*>(Tt + 2 * (int64_t)b * n) : u;
+    const double2* u = V + ((int64_t)nv * ldv + (int64_t)b * n);
+    const double2* t = Tt ? reinterpret_cast<const double2*>(Tt) + (int64_t)b * n : u;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int rg = lane & 15, g = lane >> 4;
     const int units = (nv / 16 + 1) * nch;
@@ -610,20 +625,85 @@ __global__ __launch_bounds__(256) void k_dot2(const double* __restrict__ V, int6
         const int64_t lo = blk * chunk, hi = min(n, lo + chunk);
         const int i = vg * 16 + w * 4 + g;
         const int is = i <= nv ? i : nv;
-        const double2* v = reinterpret_cast<const double2*>(V + 2 * ((int64_t)is * ldv + (int64_t)b * n));
+        const double2* v = V + ((int64_t)is * ldv + (int64_t)b * n);
         double a[4] = {0, 0, 0, 0};                     // conj(v) u (re, im), conj(v) t (re, im)
 #pragma unroll 8
-        for (int64_t e = lo + rg; e < hi; e += 16) {
-            const double2 x = v[e], uu = u[e], tt = t[e];
-            a[0] = fma(x.x, uu.x, fma(x.y, uu.y, a[0]));
-            a[1] = fma(x.x, uu.y, fma(-x.y, uu.x, a[1]));
-            a[2] = fma(x.x, tt.x, fma(x.y, tt.y, a[2]));
-            a[3] = fma(x.x, tt.y, fma(-x.y, tt.x, a[3]));
-        }
+        for (int64_t e = lo + rg; e < hi; e += 16) dot2_acc(a, v[e], u[e], t[e]);
         // lanes rg = 0, 1, 2, 3 hold the sums of a[0], a[2], a[1], a[3]
         const double sum = row16_sum4(a, rg);
         if (i <= nv && rg < 4)
             hpart[(((int64_t)b * (nvmax + 1) + i) * kmax + blk) * 4 + 2 * (rg & 1) + (rg >> 1)] = sum;
+    }
+}
+
+// The same partial sums for a complex64 basis (slots i < j), with u read from its complex128 copy U
+// (slab, ld n), so that alpha = u^H u and gamma = u^H t keep FP64 inputs.  A complex64 entry is half
+// the bytes of the u and t entries it meets, so each lane takes four basis vectors per u, t load:
+// lane (rg, g) of wavefront w takes vectors 16 vg + g + 4 k (k < 4) and rows lo + 64 m + 16 w + rg;
+// the four wavefronts' sums of a vector meet in LDS.  (The layout of k_dot2 leaves the complex64
+// pass no faster than the complex128 one; this one takes 38% less time at j = 760.)
+__global__ __launch_bounds__(256) void k_dot2_c64(const float2* __restrict__ V, int64_t ldv,
+                                                  const int* __restrict__ jdev, int nvmax,
+                                                  const double* __restrict__ Tt, const double* __restrict__ U,
+                                                  int64_t n, double* __restrict__ hpart, int T, int cmin, int kmax) {
+    __shared__ double red[4][16][4];
+    const int nv = jdev[0];
+    const int b = blockIdx.z;
+    const int nch = dot_chunks(nv, T, cmin, kmax);
+    const int64_t chunk = ((n + nch - 1) / nch + 15) / 16 * 16;
+    const double2* u = reinterpret_cast<const double2*>(U) + (int64_t)b * n;
+    const double2* t = Tt ? reinterpret_cast<const double2*>(Tt) + (int64_t)b * n : u;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int rg = lane & 15, g = lane >> 4;
+    const int units = (nv / 16 + 1) * nch;
+    for (int unit = blockIdx.x; unit < units; unit += gridDim.x) {
+        const int vg = unit / nch, blk = unit - vg * nch;
+        const int64_t lo = blk * chunk, hi = min(n, lo + chunk);
+        const float2* v[4];
+        bool own[4];                                    // vector i >= j: u itself (only i == j is kept)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = vg * 16 + g + 4 * k;
+            own[k] = i >= nv;
+            v[k] = V + ((int64_t)(own[k] ? 0 : i) * ldv + (int64_t)b * n);
+        }
+        double a[4][4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[k][q] = 0.0;
+        if (vg < nv / 16) {
+#pragma unroll 2
+            for (int64_t e = lo + 16 * w + rg; e < hi; e += 64) {
+                const double2 uu = u[e], tt = t[e];
+                double2 x[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) x[k] = basis_ld(v[k] + e);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) dot2_acc(a[k], x[k], uu, tt);
+            }
+        } else {
+            for (int64_t e = lo + 16 * w + rg; e < hi; e += 64) {
+                const double2 uu = u[e], tt = t[e];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) dot2_acc(a[k], own[k] ? uu : basis_ld(v[k] + e), uu, tt);
+            }
+        }
+        // per vector k, lanes rg = 0, 1, 2, 3 hold the sums of a[k][0], a[k][2], a[k][1], a[k][3]
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double sum = row16_sum4(a[k], rg);
+            if (rg < 4) red[w][g + 4 * k][2 * (rg & 1) + (rg >> 1)] = sum;
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int vl = threadIdx.x >> 2, q = threadIdx.x & 3;
+            const int i = vg * 16 + vl;
+            if (i <= nv)
+                hpart[(((int64_t)b * (nvmax + 1) + i) * kmax + blk) * 4 + q] =
+                    red[0][vl][q] + red[1][vl][q] + red[2][vl][q] + red[3][vl][q];
+        }
+        __syncthreads();
     }
 }
 
@@ -785,7 +865,8 @@ __global__ __launch_bounds__(256) void k_dcgs_col(double* __restrict__ H, int64_
 // (zero when a group has none).  The workgroups with
 // blockIdx.x >= nxp instead form the partial products of the Hessenberg matrix with s
 // (hess_gemv_body), which need nothing but S: the two independent parts of a step share a launch.
-__global__ __launch_bounds__(256) void k_update2_part(const double* __restrict__ V, int64_t ldv,
+template <typename VT>
+__global__ __launch_bounds__(256) void k_update2_part(const VT* __restrict__ V, int64_t ldv,
                                                       const int* __restrict__ jdev, int nvmax,
                                                       const double* __restrict__ S, const double* __restrict__ Z,
                                                       double* __restrict__ part, int64_t n, int nxp,
@@ -817,12 +898,16 @@ __global__ __launch_bounds__(256) void k_update2_part(const double* __restrict__
         }
         __syncthreads();
         if (e >= n) continue;
-        const double* v = V + 2 * ((int64_t)i0 * ldv + (int64_t)b * n + e);
+        const VT* v = V + ((int64_t)i0 * ldv + (int64_t)b * n + e);
         int i = 0;
         for (; i + 8 <= cnt; i += 8) {
             double vr[8], vi[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) { vr[k] = v[2 * (int64_t)(i + k) * ldv]; vi[k] = v[2 * (int64_t)(i + k) * ldv + 1]; }
+            for (int k = 0; k < 8; ++k) {
+                const double2 q = basis_ld(v + (int64_t)(i + k) * ldv);
+                vr[k] = q.x;
+                vi[k] = q.y;
+            }
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const double* q = cs + 4 * (i + k);
@@ -833,7 +918,8 @@ __global__ __launch_bounds__(256) void k_update2_part(const double* __restrict__
             }
         }
         for (; i < cnt; ++i) {
-            const double vr = v[2 * (int64_t)i * ldv], vi = v[2 * (int64_t)i * ldv + 1];
+            const double2 qv = basis_ld(v + (int64_t)i * ldv);
+            const double vr = qv.x, vi = qv.y;
             const double* q = cs + 4 * i;
             ar += vr * q[0] - vi * q[1];
             ai += vr * q[1] + vi * q[0];
@@ -848,10 +934,13 @@ __global__ __launch_bounds__(256) void k_update2_part(const double* __restrict__
 
 // q_j = (u - Q s)/nu into slot j, u' = (t - Q z - q_j c)/nu into slot j+1 and into Unext; when Zsrc
 // is given it is also copied into slot j of Zdst (the preconditioned candidate of flexible GMRES).
+// With a complex64 basis (VT = float2) u is read from Unext (its complex128 copy), q_j is rounded
+// into slot j and u' goes to Unext only.
 // Each workgroup forms nu and c itself from S and Z (dcgs_scalars).  The workgroups with
 // blockIdx.x >= nxa finalise the Hessenberg columns instead (dcgs_col_body, rows 256 (blockIdx.x -
 // nxa) onwards), which needs the partial products hg of the previous launch.
-__global__ __launch_bounds__(256) void k_update2_apply(const double* __restrict__ part, int ng, double* __restrict__ V,
+template <typename VT>
+__global__ __launch_bounds__(256) void k_update2_apply(const double* __restrict__ part, int ng, VT* __restrict__ V,
                                                        int64_t ldv, const int* __restrict__ jdev, int* __restrict__ jnext,
                                                        const double* __restrict__ Tt, double* __restrict__ Unext,
                                                        int64_t n, const double* __restrict__ Zsrc,
@@ -877,17 +966,26 @@ __global__ __launch_bounds__(256) void k_update2_apply(const double* __restrict_
         ar += p[0]; ai += p[1]; br += p[2]; bi += p[3];
     }
     const double inv = nu > 0 ? 1.0 / nu : 0.0;
-    double* u = V + 2 * ((int64_t)nv * ldv + (int64_t)b * n + e);
-    double* un = V + 2 * ((int64_t)(nv + 1) * ldv + (int64_t)b * n + e);
+    constexpr bool c64 = std::is_same<VT, float2>::value;
+    VT* q = V + ((int64_t)nv * ldv + (int64_t)b * n + e);
+    double2* uc = reinterpret_cast<double2*>(Unext) + (int64_t)b * n + e;
+    const double2 u = c64 ? *uc : basis_ld(q);
     const double* t = Tt + 2 * ((int64_t)b * n + e);
-    const double qr = (u[0] - ar) * inv, qi = (u[1] - ai) * inv;
-    u[0] = qr;
-    u[1] = qi;
+    double qr = (u.x - ar) * inv, qi = (u.y - ai) * inv;
+    if constexpr (c64) {
+        // later steps see q_j rounded: u' is formed from the rounded value too, so that
+        // t = Q z + q_j c + nu u' holds for the stored basis
+        const float2 qf = make_float2((float)qr, (float)qi);
+        *q = qf;
+        qr = qf.x;
+        qi = qf.y;
+    }
     const double tr = (t[0] - br - (qr * cr - qi * ci)) * inv, ti = (t[1] - bi - (qr * ci + qi * cr)) * inv;
-    un[0] = tr;
-    un[1] = ti;
-    Unext[2 * ((int64_t)b * n + e)] = tr;
-    Unext[2 * ((int64_t)b * n + e) + 1] = ti;
+    if constexpr (!c64) {
+        *q = make_double2(qr, qi);
+        V[(int64_t)(nv + 1) * ldv + (int64_t)b * n + e] = make_double2(tr, ti);
+    }
+    *uc = make_double2(tr, ti);
     if (Zsrc) {
         const double* zs = Zsrc + 2 * ((int64_t)b * n + e);
         double* zd = Zdst + 2 * ((int64_t)nv * ldv + (int64_t)b * n + e);
@@ -1367,10 +1465,15 @@ void launch_gs_residual(const DomDesc* doms, const int32_t* dof_dom, const int32
                        gval, gcol, other_dom, dom_stage, stage, v, z, w);
 }
 
-void launch_dot2(const double* V, int64_t ldv, const int* jdev, int nvmax, const double* t, int64_t n, double* hpart,
-                 const DotPlan& d, int nb, hipStream_t s) {
-    hipLaunchKernelGGL(k_dot2, dim3((unsigned)d.grid, 1, (unsigned)nb), dim3(256), 0, s, V, ldv, jdev, nvmax, t, n, hpart,
-                       d.units, d.cmin, d.kmax);
+void launch_dot2(const double* V, int64_t ldv, const int* jdev, int nvmax, const double* t, const double* U, int64_t n,
+                 double* hpart, const DotPlan& d, bool c64, int nb, hipStream_t s) {
+    const dim3 grid((unsigned)d.grid, 1, (unsigned)nb);
+    if (c64)
+        hipLaunchKernelGGL(k_dot2_c64, grid, dim3(256), 0, s, reinterpret_cast<const float2*>(V), ldv, jdev, nvmax, t, U,
+                           n, hpart, d.units, d.cmin, d.kmax);
+    else
+        hipLaunchKernelGGL(k_dot2, grid, dim3(256), 0, s, reinterpret_cast<const double2*>(V), ldv, jdev, nvmax, t, n,
+                           hpart, d.units, d.cmin, d.kmax);
 }
 
 void launch_reduce2(const double* hpart, const int* jdev, int nvmax, const DotPlan& d, double* S, double* Z, int nb,
@@ -1388,17 +1491,28 @@ void launch_dcgs_col(double* H, int64_t ldh, int64_t hstride, const double* S, c
 void launch_update2(const double* V_, int64_t ldv, const int* jdev, int* jnext, int nvmax, const double* S,
                     const double* Z, const double* t, double* unext, int64_t n, double* part, int ng,
                     const double* zsrc, double* zdst, double* H, int64_t ldh, int64_t hstride, double* hg, int nct,
-                    double* R, int64_t rstride, int nb, hipStream_t s) {
+                    double* R, int64_t rstride, bool c64, int nb, hipStream_t s) {
     double* V = const_cast<double*>(V_);
     const int nxp = (int)gridn(n, 256);
     const int tiles = ((nvmax + 1 + 63) / 64) * ((nvmax + 63) / 64);
     const int nhx = std::max(1, (std::min(tiles, 256) + ng - 1) / ng);
-    hipLaunchKernelGGL(k_update2_part, dim3((unsigned)(nxp + nhx), (unsigned)ng, (unsigned)nb), dim3(256), 0, s, V, ldv,
-                       jdev, nvmax, S, Z, part, n, nxp, H, ldh, hstride, nct, hg);
+    const dim3 gp((unsigned)(nxp + nhx), (unsigned)ng, (unsigned)nb);
     const int nxa = (int)gridn(n, 256);
     const int ncx = (int)gridn(nvmax + 1, 256);
-    hipLaunchKernelGGL(k_update2_apply, dim3((unsigned)(nxa + ncx), (unsigned)nb), dim3(256), 0, s, part, ng, V, ldv,
-                       jdev, jnext, t, unext, n, zsrc, zdst, nxa, nvmax, S, Z, H, ldh, hstride, hg, nct, R, rstride);
+    const dim3 ga((unsigned)(nxa + ncx), (unsigned)nb);
+    if (c64) {
+        float2* Vc = reinterpret_cast<float2*>(V);
+        hipLaunchKernelGGL(k_update2_part<float2>, gp, dim3(256), 0, s, Vc, ldv, jdev, nvmax, S, Z, part, n, nxp, H, ldh,
+                           hstride, nct, hg);
+        hipLaunchKernelGGL(k_update2_apply<float2>, ga, dim3(256), 0, s, part, ng, Vc, ldv, jdev, jnext, t, unext, n,
+                           zsrc, zdst, nxa, nvmax, S, Z, H, ldh, hstride, hg, nct, R, rstride);
+    } else {
+        double2* Vd = reinterpret_cast<double2*>(V);
+        hipLaunchKernelGGL(k_update2_part<double2>, gp, dim3(256), 0, s, Vd, ldv, jdev, nvmax, S, Z, part, n, nxp, H,
+                           ldh, hstride, nct, hg);
+        hipLaunchKernelGGL(k_update2_apply<double2>, ga, dim3(256), 0, s, part, ng, Vd, ldv, jdev, jnext, t, unext, n,
+                           zsrc, zdst, nxa, nvmax, S, Z, H, ldh, hstride, hg, nct, R, rstride);
+    }
 }
 
 void launch_set_int(int* p, int v, hipStream_t s) { hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, p, v); }

@@ -437,3 +437,49 @@ def test_graph_replay_batched_bf16(cube):
     assert [s.iterations for s in s0] == [s.iterations for s in s1]
     assert all(s.converged for s in s1) and max(s.iterations for s in s1) > 40
     assert torch.equal(x0, x1)
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("prec", [mtf.FP64, mtf.FP32_MIXED])
+def test_solve_basis_c64(name, prec, request):
+    """Complex64 Krylov basis (complex128 arithmetic and candidate vector).  Each stored basis
+    vector carries a relative rounding of about 6e-8, so one cycle attains about that times the
+    conditioning: at rtol 1e-6 the steps are those of the complex128 basis; at 1e-9 the FP64
+    residual check may start one more cycle, and the FP64 tolerance and the LU solution are still
+    reached."""
+    c = request.getfixturevalue(name)
+    b = torch.tensor(c.b[None, :], device="cuda")
+    kw = dict(precision=prec, preconditioner=mtf.PREC_BLOCK_TINV_GS, max_iters=3000)
+    ref = torch.zeros_like(b)
+    s6 = c.P.solve(b, ref, rtol=1e-6, **kw)[0]
+    x = torch.zeros_like(b)
+    c6 = c.P.solve(b, x, rtol=1e-6, basis_c64=True, **kw)[0]
+    assert c6.converged and c6.rel_residual <= 1e-6
+    assert c6.iterations <= s6.iterations + 2
+    s9 = c.P.solve(b, ref, rtol=1e-9, **kw)[0]
+    x = torch.zeros_like(b)
+    st = c.P.solve(b, x, rtol=1e-9, basis_c64=True, **kw)[0]
+    print(f"[{name} prec={prec} c64 basis] 1e-6: {c6.iterations} steps (c128 basis {s6.iterations}); "
+          f"1e-9: {st.iterations} steps (c128 basis {s9.iterations}), refinements {st.refinements}, "
+          f"residual {st.rel_residual:.2e}", flush=True)
+    assert st.converged and st.rel_residual <= 1e-9
+    assert st.iterations <= 2 * s9.iterations + 16
+    xs = x[0].cpu().numpy()
+    assert np.linalg.norm(c.M @ xs - c.b) / np.linalg.norm(c.b) < 2e-9
+    assert np.linalg.norm(xs - c.x) / np.linalg.norm(c.x) < 1e-6
+
+
+def test_basis_c64_graph_matches_eager_and_needs_preconditioner(cube):
+    """The complex64-basis steps replay as a HIP graph bit for bit like the eager launches; without a
+    preconditioner (no flexible iteration) the flag is rejected."""
+    b = torch.tensor(cube.b[None, :], device="cuda")
+    ref = torch.zeros_like(b)
+    st0 = cube.P.solve(b, ref, rtol=1e-9, preconditioner=mtf.PREC_BLOCK_TINV_GS, max_iters=3000, graph=False,
+                       basis_c64=True)[0]
+    x = torch.zeros_like(b)
+    st = cube.P.solve(b, x, rtol=1e-9, preconditioner=mtf.PREC_BLOCK_TINV_GS, max_iters=3000, graph=True,
+                      basis_c64=True)[0]
+    assert st0.converged and st.iterations == st0.iterations and st.iterations > 40
+    assert torch.equal(x, ref)
+    with pytest.raises(RuntimeError):
+        cube.P.solve(b, x, rtol=1e-9, preconditioner=mtf.PREC_NONE, basis_c64=True)
