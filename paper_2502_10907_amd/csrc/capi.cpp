@@ -32,6 +32,7 @@ constexpr int kSync = 8;      // Arnoldi steps between host reads of the Hessenb
 constexpr int kMaxBatch = 64; // right-hand sides per lockstep GMRES batch (MFMA products)
 constexpr int kUpdGroups = 8; // partial-sum groups of the basis update
 constexpr int kEagerBatches = 2;   // Arnoldi batches of a cycle launched eagerly before a graph is captured
+constexpr double kLookaheadFactor = 30.0;   // a second batch is queued while every residual exceeds this x target
 
 struct GemmOp {
     DevBuf<uint16_t> A, B;
@@ -51,7 +52,9 @@ struct GmresWork {
     DevBuf<int> jdev;                // step index: step j reads slot j&1 and writes j+1 into the other slot
     int zslots = 0;                  // Krylov slots held by Zt (0: no preconditioned basis)
     DevBuf<int> cnt;                 // Arnoldi steps kept per right-hand side, then a zero-pivot flag
-    double* host = nullptr;          // pinned: nb x kSync Hessenberg columns + norm parts
+    double* host = nullptr;          // pinned: two areas of nb x kSync Hessenberg columns (the first also
+                                     // takes the norm parts)
+    hipEvent_t ev[2] = {nullptr, nullptr};   // completion of the copy into each area
     double* hosty = nullptr;         // pinned: nb x (maxit + 1) least-squares coefficients
     int* hostcnt = nullptr;          // pinned: nb step counts + flag
     ~GmresWork() { release(); }
@@ -65,6 +68,10 @@ struct GmresWork {
         if (host) (void)hipHostFree(host);
         if (hosty) (void)hipHostFree(hosty);
         if (hostcnt) (void)hipHostFree(hostcnt);
+        for (hipEvent_t& e : ev) {
+            if (e) (void)hipEventDestroy(e);
+            e = nullptr;
+        }
         host = hosty = nullptr;
         hostcnt = nullptr;
         n = 0;
@@ -790,7 +797,7 @@ void gmres_alloc(mtf_problem p, int maxit, int nb, bool flex) {
     w.host = nullptr;
     w.hosty = nullptr;
     w.hostcnt = nullptr;
-    HIPCHK(hipHostMalloc((void**)&w.host, ((size_t)2 * ldh * kSync * nb + (size_t)kNblk * nb) * sizeof(double),
+    HIPCHK(hipHostMalloc((void**)&w.host, ((size_t)4 * ldh * kSync * nb + (size_t)kNblk * nb) * sizeof(double),
                          hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&w.hosty, (size_t)2 * nb * ldh * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&w.hostcnt, (size_t)(nb + 1) * sizeof(int), hipHostMallocDefault));
@@ -901,19 +908,27 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
                        flex ? w.zfix.p : nullptr, flex ? w.Zt.p : nullptr, w.H.p, ldh, hstride, w.hg.p, nct,
                        flex ? w.Rf.p : nullptr, hstride, c64, nb, s);
     };
-    // kSync steps j0 .. j0+kSync-1 (j0 odd), then the final columns j0-1 .. j0+kSync-2 staged and
-    // copied to w.host
-    const size_t stage_bytes = (size_t)2 * ldh * kSync * nb * sizeof(double);
+    // kSync steps j0 .. j0+kSync-1 (j0 odd), then the final columns j0-1 .. j0+kSync-2 staged in Hst
+    // (the caller copies them to one of the two host areas)
+    const size_t stage_doubles = (size_t)2 * ldh * kSync * nb;
+    const size_t stage_bytes = stage_doubles * sizeof(double);
     auto batch = [&](int j0) {
         for (int q = 0; q < kSync; ++q) step(j0 + q);
         launch_stage_cols(w.H.p, ldh, hstride, jslot(j0 + kSync), kSync + 1, kSync, w.Hst.p, nb, s);
-        HIPCHK(hipMemcpyAsync(w.host, w.Hst.p, stage_bytes, hipMemcpyDeviceToHost, s));
     };
+    for (hipEvent_t& e : w.ev)
+        if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     hipGraphExec_t exec = nullptr;
     struct ExecGuard {
         hipGraphExec_t& e;
-        ~ExecGuard() { if (e) (void)hipGraphExecDestroy(e); }
-    } exec_guard{exec};
+        hipStream_t s;
+        ~ExecGuard() {
+            if (e) {
+                (void)hipStreamSynchronize(s);     // no replay of it may still be queued
+                (void)hipGraphExecDestroy(e);
+            }
+        }
+    } exec_guard{exec, s};
 
     // host copies of the final Hessenberg columns after the rotations (column jj has jj+1 entries)
     std::vector<std::vector<std::vector<cd>>> H(nb);
@@ -928,11 +943,11 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
         if (beta[b] == 0.0) stop[b] = 1; else ++live;
     }
     std::vector<cd> col;
-    // Givens rotations on final columns c0 .. c0+nc-1 held in w.host ([b][q][ldh] complex)
-    auto process = [&](int c0, int nc) {
+    // Givens rotations on final columns c0 .. c0+nc-1 held in hbuf ([b][q][ldh] complex)
+    auto process = [&](int c0, int nc, const double* hbuf) {
         for (int b = 0; b < nb; ++b) {
             if (stop[b]) continue;
-            const double* hb = w.host + (size_t)2 * ldh * nc * b;
+            const double* hb = hbuf + (size_t)2 * ldh * nc * b;
             for (int q = 0; q < nc && !stop[b]; ++q) {
                 const int jj = c0 + q;
                 col.assign(jj + 2, cd(0));
@@ -970,51 +985,86 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
         j = 1;
     }
     int batches = 0;
-    while (live > 0) {
-        if (j + kSync <= maxit) {
-            // short cycles never pay for the capture: the first kEagerBatches batches run eagerly
-            if (graph && batches++ >= kEagerBatches) {
-                if (!exec) {
-                    // capture on the private stream (the caller's may be the null stream, which cannot be
-                    // captured); every launch in batch() goes to p->stream and s, redirected meanwhile
-                    if (!p->capture) HIPCHK(hipStreamCreate(&p->capture));
-                    const hipStream_t caller = p->stream;
-                    struct Restore {
-                        mtf_problem p;
-                        hipStream_t& s;
-                        hipStream_t caller;
-                        ~Restore() { p->stream = caller; s = caller; }
-                    } restore{p, s, caller};
-                    p->stream = s = p->capture;
-                    hipGraph_t g = nullptr;
-                    HIPCHK(hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal));
-                    try {
-                        batch(j);
-                    } catch (...) {
-                        (void)hipStreamEndCapture(p->capture, &g);
-                        if (g) (void)hipGraphDestroy(g);
-                        throw;
-                    }
-                    HIPCHK(hipStreamEndCapture(p->capture, &g));
-                    const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-                    (void)hipGraphDestroy(g);
-                    HIPCHK(e);
+    // Batches launched and not yet processed (at most two): while the host applies the rotations to
+    // one batch's columns, the next batch already runs.  Near convergence only one is launched at a
+    // time, so that at most the steps of one batch are spent past the converging step.
+    struct Pending {
+        int c0, area;
+    };
+    Pending pend[2];
+    int npend = 0, area = 0;
+    auto launch_batch = [&](int j0) {
+        // short cycles never pay for the capture: the first kEagerBatches batches run eagerly
+        if (graph && batches++ >= kEagerBatches) {
+            if (!exec) {
+                // capture on the private stream (the caller's may be the null stream, which cannot be
+                // captured); every launch in batch() goes to p->stream and s, redirected meanwhile
+                if (!p->capture) HIPCHK(hipStreamCreate(&p->capture));
+                const hipStream_t caller = p->stream;
+                struct Restore {
+                    mtf_problem p;
+                    hipStream_t& s;
+                    hipStream_t caller;
+                    ~Restore() { p->stream = caller; s = caller; }
+                } restore{p, s, caller};
+                p->stream = s = p->capture;
+                hipGraph_t g = nullptr;
+                HIPCHK(hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal));
+                try {
+                    batch(j0);
+                } catch (...) {
+                    (void)hipStreamEndCapture(p->capture, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    throw;
                 }
-                HIPCHK(hipGraphLaunch(exec, s));
-            } else {
-                batch(j);
+                HIPCHK(hipStreamEndCapture(p->capture, &g));
+                const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                HIPCHK(e);
             }
+            HIPCHK(hipGraphLaunch(exec, s));
+        } else {
+            batch(j0);
+        }
+        HIPCHK(hipMemcpyAsync(w.host + area * stage_doubles, w.Hst.p, stage_bytes, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(w.ev[area], s));
+        pend[npend++] = Pending{j0 - 1, area};
+        area ^= 1;
+    };
+    auto finish_oldest = [&]() {
+        const Pending q = pend[0];
+        pend[0] = pend[1];
+        --npend;
+        HIPCHK(hipEventSynchronize(w.ev[q.area]));
+        process(q.c0, kSync, w.host + q.area * stage_doubles);
+        done_cols = q.c0 + kSync;
+    };
+    auto far = [&]() {
+        for (int b = 0; b < nb; ++b)
+            if (!stop[b] && !(resid[b] > kLookaheadFactor * tol[b] * beta[b])) return false;
+        return true;
+    };
+    while (live > 0) {
+        const int want = far() ? 2 : 1;
+        while (npend < want && j + kSync <= maxit) {
+            launch_batch(j);
             j += kSync;
-            sync(p);
-            process(j - kSync - 1, kSync);
-            done_cols = j - 1;
+        }
+        if (npend > 0) {
+            finish_oldest();
             if (cur_prec != prec) {
                 bool below = true;
                 for (int b = 0; b < nb; ++b)
                     if (!stop[b] && resid[b] > relax * beta[b]) below = false;
                 if (below) {
+                    while (npend > 0 && live > 0) finish_oldest();   // the queued batch used the FP64 product
+                    npend = 0;
                     cur_prec = prec;                 // the captured batch holds the FP64 product
-                    if (exec) { HIPCHK(hipGraphExecDestroy(exec)); exec = nullptr; }
+                    if (exec) {
+                        sync(p);
+                        HIPCHK(hipGraphExecDestroy(exec));
+                        exec = nullptr;
+                    }
                 }
             }
             continue;
@@ -1031,7 +1081,7 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
                                     (size_t)2 * hstride * sizeof(double), (size_t)2 * ldh * nc * sizeof(double), nb,
                                     hipMemcpyDeviceToHost, s));
             sync(p);
-            process(done_cols, nc);
+            process(done_cols, nc, w.host);
         }
         done_cols = maxit;
         break;
