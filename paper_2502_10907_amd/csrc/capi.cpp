@@ -128,11 +128,16 @@ struct mtf_problem_s {
     double t_assemble = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipStream_t capture = nullptr;   // private stream on which GMRES step graphs are captured (never run)
+    hipStream_t gj_stream = nullptr; // private stream of the inversion lookahead (default priority)
+    hipEvent_t gj_fork = nullptr, gj_join = nullptr;
     GmresWork gw;
 
     ~mtf_problem_s() {
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
+        if (gj_fork) (void)hipEventDestroy(gj_fork);
+        if (gj_join) (void)hipEventDestroy(gj_join);
+        if (gj_stream) (void)hipStreamDestroy(gj_stream);
         if (capture) (void)hipStreamDestroy(capture);
     }
 };
@@ -552,6 +557,13 @@ void precond1_gs(mtf_problem p, const double* x, double* z, double* w) {
     }
 }
 
+// Second stream and events for the lookahead of block_gj_inverse (default priority, like every
+// stream here).
+struct GjLookahead {
+    hipStream_t s2 = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
 // In-place inverse of `batch` n x n complex64 matrices X + z*stride (leading dimension ld) by
 // blocked Gauss-Jordan elimination over diagonal blocks P of width w <= W:
 //   X_PP <- X_PP^-1;  X_Pj <- X_PP X_Pj;  X_ij <- X_ij - X_iP X_Pj;  X_iP <- -X_iP X_PP   (i, j not in P)
@@ -560,17 +572,40 @@ void precond1_gs(mtf_problem p, const double* x, double* z, double* w) {
 // by the same elimination with 64-wide blocks (pivoting within each 64 x 64 leaf).  A panel is
 // updated in place when one workgroup tile spans its reduced dimension (128 rows, 64 columns);
 // otherwise through `tmp` (W * n complex entries per matrix) and a copy back.
+// With `la` (lookahead), the rank-w update first forms the next diagonal block X_P'P' (P' the block
+// after P), which is then inverted on la->s2 while s carries on with the rest of the update and
+// the column panel; s waits for it before the next row panel.  The leaf inversions, which occupy
+// one CU each, then overlap the large update instead of following it.  P and P' are adjacent, so
+// every piece of the update is a GEMM with one skipped band of rows and one of columns:
+//   rows P', columns P' (first);  rows outside P u P', columns outside P;
+//   rows P', columns outside P u P'.
 void block_gj_inverse(float* X, int n, int64_t ld, int64_t stride, int batch, int* info, hipStream_t s, int W,
-                      float* tmp) {
+                      float* tmp, const GjLookahead* la = nullptr) {
     constexpr int kTileRows = 128, kTileCols = 64;
     const int64_t ts = (int64_t)W * n;                 // tmp stride per matrix (complex entries)
+    auto invert_diag = [&](int q0, int w, hipStream_t st) {
+        float* Xqq = X + 2 * (q0 + (int64_t)q0 * ld);
+        if (w <= 64) launch_cinv_small_f32(Xqq, ld, stride, w, batch, info, st);
+        else block_gj_inverse(Xqq, w, ld, stride, batch, info, st, 64, tmp);
+    };
+    // D(rows, cols) -= X(rows, P) X(P, cols): compact rows r -> r + (r >= rg0 ? rgw : 0), likewise cols
+    auto update = [&](int p0, int w, int m, int rg0, int rgw, int nn, int cg0, int cgw) {
+        if (m <= 0 || nn <= 0) return;
+        CGemm t;
+        t.m = m; t.n = nn; t.k = w; t.batch = batch; t.ar = -1.f; t.beta = 1.f;
+        t.A = X + 2 * ((int64_t)p0 * ld); t.lda = ld; t.sA = stride;
+        t.B = X + 2 * (int64_t)p0; t.ldb = ld; t.sB = stride;
+        t.C = X; t.ldc = ld; t.sC = stride;
+        t.D = X; t.ldd = ld; t.sD = stride;
+        t.rg0 = rg0; t.rgw = rgw; t.cg0 = cg0; t.cgw = cgw;
+        launch_cgemm_f32(t, s);
+    };
+    invert_diag(0, std::min(W, n), s);
     for (int p0 = 0; p0 < n; p0 += W) {
         const int w = std::min(W, n - p0);
         float* Xpp = X + 2 * (p0 + (int64_t)p0 * ld);
         float* Xrow = X + 2 * (int64_t)p0;            // row p0, column 0
         float* Xcol = X + 2 * ((int64_t)p0 * ld);     // row 0, column p0
-        if (w <= 64) launch_cinv_small_f32(Xpp, ld, stride, w, batch, info, s);
-        else block_gj_inverse(Xpp, w, ld, stride, batch, info, s, 64, tmp);
         if (w == n) break;
         CGemm r;                                      // row panel
         r.m = w; r.n = n - w; r.k = w; r.batch = batch;
@@ -585,14 +620,18 @@ void block_gj_inverse(float* X, int n, int64_t ld, int64_t stride, int batch, in
             launch_cgemm_f32(r, s);
             launch_band_copy_f32(tmp, w, ts, Xrow, ld, stride, w, n - w, w, 0, p0, w, batch, s);
         }
-        CGemm t;                                      // rank-w update outside the band
-        t.m = n - w; t.n = n - w; t.k = w; t.batch = batch; t.ar = -1.f; t.beta = 1.f;
-        t.A = Xcol; t.lda = ld; t.sA = stride;
-        t.B = Xrow; t.ldb = ld; t.sB = stride;
-        t.C = X; t.ldc = ld; t.sC = stride;
-        t.D = X; t.ldd = ld; t.sD = stride;
-        t.rg0 = p0; t.rgw = w; t.cg0 = p0; t.cgw = w;
-        launch_cgemm_f32(t, s);
+        const int q0 = p0 + w, w2 = std::min(W, n - q0);   // the next block P' (w2 <= 0: none)
+        if (la && w2 > 0) {
+            update(p0, w, w2, 0, q0, w2, 0, q0);                          // rows P', columns P'
+            HIPCHK(hipEventRecord(la->fork, s));
+            HIPCHK(hipStreamWaitEvent(la->s2, la->fork, 0));
+            invert_diag(q0, w2, la->s2);
+            HIPCHK(hipEventRecord(la->join, la->s2));
+            update(p0, w, n - w - w2, p0, w + w2, n - w, p0, w);          // rows outside P u P'
+            update(p0, w, w2, 0, q0, n - w - w2, p0, w + w2);             // rows P', columns outside P u P'
+        } else {
+            update(p0, w, n - w, p0, w, n - w, p0, w);                    // everything outside P
+        }
         CGemm c;                                      // column panel
         c.m = n - w; c.n = w; c.k = w; c.batch = batch; c.ar = -1.f;
         c.A = Xcol; c.lda = ld; c.sA = stride;
@@ -605,6 +644,10 @@ void block_gj_inverse(float* X, int n, int64_t ld, int64_t stride, int batch, in
             c.D = tmp; c.ldd = n - w; c.sD = ts; c.band_cd = 0;
             launch_cgemm_f32(c, s);
             launch_band_copy_f32(tmp, n - w, ts, Xcol, ld, stride, n - w, w, p0, w, w, 0, batch, s);
+        }
+        if (w2 > 0) {
+            if (la) HIPCHK(hipStreamWaitEvent(s, la->join, 0));
+            else invert_diag(q0, w2, s);
         }
     }
 }
@@ -653,6 +696,15 @@ void build_tinv(mtf_problem p, bool force_full) {
     DevBuf<int> info;
     info.alloc(2);
     HIPCHK(hipMemsetAsync(info.p, 0, 2 * sizeof(int), s));
+    // lookahead stream of the inversions: non-blocking, so that it also overlaps work on a caller's
+    // null stream; ordered by events only
+    if (!p->gj_stream) HIPCHK(hipStreamCreateWithFlags(&p->gj_stream, hipStreamNonBlocking));
+    if (!p->gj_fork) HIPCHK(hipEventCreateWithFlags(&p->gj_fork, hipEventDisableTiming));
+    if (!p->gj_join) HIPCHK(hipEventCreateWithFlags(&p->gj_join, hipEventDisableTiming));
+    GjLookahead la;
+    la.s2 = p->gj_stream;
+    la.fork = p->gj_fork;
+    la.join = p->gj_join;
     // T_i in complex64 (kept for the check and the rebuilt blocks)
     DevBuf<float> tcopy;
     const float* T32 = p->T32.p;
@@ -680,7 +732,8 @@ void build_tinv(mtf_problem p, bool force_full) {
         int b = a + 1;
         const int64_t E = D[a].E;
         while (b < nd && D[b].E == E && D[b].mat0 == D[a].mat0 + (int64_t)(b - a) * E * E) ++b;
-        if (E > 0) block_gj_inverse(p->Tinv.p + 2 * D[a].mat0, (int)E, E, E * E, b - a, info.p, s, kGjPanel, gjtmp.p);
+        if (E > 0)
+            block_gj_inverse(p->Tinv.p + 2 * D[a].mat0, (int)E, E, E * E, b - a, info.p, s, kGjPanel, gjtmp.p, &la);
         a = b;
     }
     if (!force_full && emax > 0) {
@@ -729,7 +782,7 @@ void build_tinv(mtf_problem p, bool force_full) {
             const int64_t E = D[i].E;
             HIPCHK(hipMemcpyAsync(p->Tinv.p + 2 * D[i].mat0, T32 + 2 * D[i].mat0, 2 * E * E * sizeof(float),
                                   hipMemcpyDeviceToDevice, s));
-            block_gj_inverse(p->Tinv.p + 2 * D[i].mat0, (int)E, E, E * E, 1, info.p, s, kGjPanel, gjtmp.p);
+            block_gj_inverse(p->Tinv.p + 2 * D[i].mat0, (int)E, E, E * E, 1, info.p, s, kGjPanel, gjtmp.p, &la);
             p->pc_full[i] = 1;
         }
     }
