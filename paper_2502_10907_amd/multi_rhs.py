@@ -6,6 +6,7 @@ polarisations e_theta, e_phi each (2 ndir right-hand sides).  Reported:
   * the MFMA block product Y = M X for all right-hand sides (BF16-split complex GEMM);
   * solves of a sample of the right-hand sides to ||b - M x|| <= rtol ||b|| (FP64 residual):
     `fp64`  one at a time, FP64 operator, block Gauss-Seidel preconditioner;
+    `fp64c64` the same with the Krylov basis stored in complex64 (MTF_SOLVE_BASIS_C64);
     `bf16`  lockstep batches on the MFMA products, block-Jacobi preconditioner (MFMA too);
     `bf16gs` lockstep batches on the MFMA products, block Gauss-Seidel per right-hand side;
   * the time per right-hand side and its extrapolation to all of them.
@@ -63,10 +64,11 @@ def run(n=4, h_inv=24, ndir=128, nsample=8, batch=8, modes="fp64,bf16,bf16gs", r
         Bs = B[sel].contiguous()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        if mode == "fp64":
+        if mode in ("fp64", "fp64c64"):
             sts = []
             for r in range(nsample):
-                sts += P.solve(Bs[r:r + 1], X[r:r + 1], rtol=rtol, preconditioner=mtf.PREC_BLOCK_TINV_GS)
+                sts += P.solve(Bs[r:r + 1], X[r:r + 1], rtol=rtol, preconditioner=mtf.PREC_BLOCK_TINV_GS,
+                               basis_c64=mode == "fp64c64")
         else:
             pc = mtf.PREC_BLOCK_TINV if mode == "bf16" else mtf.PREC_BLOCK_TINV_GS
             sts = []
