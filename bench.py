@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 # what the same counter reads for a 1 GiB device-to-device copy.  Valid only for the kernel source
 # the counters were taken on (digest below) and for h = 1/16; otherwise traffic is reported null.
 MV_COUNTERS = {
-    "kernel_digest": "522d9dc6bab9748f",
+    "kernel_digest": "37425098dd7ff8dd",
     "h_inv": 16,
-    "fetch_kib": 257780.35, "write_kib": 16987.02,
+    "fetch_kib": 251701.76, "write_kib": 17786.72,
     "copy_bytes": 1 << 30, "copy_fetch_kib": 524301.80, "copy_write_kib": 1048576.0,
     "summary": "profiles/k_mv_sym_counters_cube2x2x2_h16.md",
 }

@@ -177,6 +177,8 @@ __global__ __launch_bounds__(256, 2) void k_mv_sym(const DomDesc* __restrict__ d
     // ring of register slots: one column group ahead in FP64 (register bound), three in FP32
     constexpr int D = std::is_same<RM, double>::value ? 1 : 3, NS = D + 1;
     V2 tv[NS][4], kv[NS][4];
+    // In a diagonal tile the lanes below the diagonal (row > column) issue no load: those entries
+    // are dropped anyway, and the masked lanes' lines are not fetched.
     auto load = [&](int k, int slot) {
         const int c = c0 + 4 * k + cg;
         const int cs = c < E ? c : E - 1;
@@ -185,8 +187,13 @@ __global__ __launch_bounds__(256, 2) void k_mv_sym(const DomDesc* __restrict__ d
         const V2* kp = reinterpret_cast<const V2*>(Kt + boff);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            tv[slot][i] = tp[16 * i];
-            kv[slot][i] = kp[16 * i];
+            V2 a{}, b{};
+            if (!diag || rg + 16 * i <= 4 * k + cg) {
+                a = tp[16 * i];
+                b = kp[16 * i];
+            }
+            tv[slot][i] = a;
+            kv[slot][i] = b;
         }
     };
     // column group k computes from slot k % 2 while group k + 1 is in flight (the slot and
