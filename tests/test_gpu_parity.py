@@ -483,3 +483,27 @@ def test_basis_c64_graph_matches_eager_and_needs_preconditioner(cube):
     assert torch.equal(x, ref)
     with pytest.raises(RuntimeError):
         cube.P.solve(b, x, rtol=1e-9, preconditioner=mtf.PREC_NONE, basis_c64=True)
+
+
+@pytest.mark.parametrize("name", ["sphere", "ragged"])
+@pytest.mark.parametrize("maxit", [9, 12, 17])
+@pytest.mark.parametrize("pc", [mtf.PREC_BLOCK_TINV, mtf.PREC_BLOCK_TINV_GS])
+def test_short_cycles_restart(name, maxit, pc, request):
+    """Cycles of 9, 12 or 17 Arnoldi steps (step 0, batches of 8 steps, possibly two queued at
+    once, then the remaining steps one by one) restart from the FP64 residual until the tolerance
+    is met; graph replay and eager launches agree bit for bit, and the solution is the LU one.
+    (Without a preconditioner such short cycles stagnate on these cases, as MTF GMRES does.)"""
+    c = request.getfixturevalue(name)
+    b = torch.tensor(c.b[None, :], device="cuda")
+    kw = dict(rtol=1e-9, preconditioner=pc, max_iters=maxit, max_refinements=200)
+    x0 = torch.zeros_like(b)
+    s0 = c.P.solve(b, x0, graph=False, **kw)[0]
+    x1 = torch.zeros_like(b)
+    s1 = c.P.solve(b, x1, graph=True, **kw)[0]
+    print(f"[{name} maxit={maxit} pc={pc}] iterations {s1.iterations} refinements {s1.refinements} "
+          f"residual {s1.rel_residual:.2e}", flush=True)
+    assert s0.converged and s1.converged and s1.rel_residual <= 1e-9
+    assert s1.refinements >= 1 and s1.iterations == s0.iterations
+    assert torch.equal(x0, x1)
+    xs = x1[0].cpu().numpy()
+    assert np.linalg.norm(xs - c.x) / np.linalg.norm(c.x) < 1e-6
