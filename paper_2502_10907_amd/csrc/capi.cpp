@@ -972,14 +972,14 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
     for (hipEvent_t& e : w.ev)
         if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     hipGraphExec_t exec = nullptr;
+    // On every exit (an exception included) the queued batches finish first: no replay of the
+    // graph, and no copy into the pinned staging areas, may still be pending.
     struct ExecGuard {
         hipGraphExec_t& e;
         hipStream_t s;
         ~ExecGuard() {
-            if (e) {
-                (void)hipStreamSynchronize(s);     // no replay of it may still be queued
-                (void)hipGraphExecDestroy(e);
-            }
+            (void)hipStreamSynchronize(s);
+            if (e) (void)hipGraphExecDestroy(e);
         }
     } exec_guard{exec, s};
 
