@@ -128,16 +128,24 @@ struct mtf_problem_s {
     double t_assemble = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipStream_t capture = nullptr;   // private stream on which GMRES step graphs are captured (never run)
-    hipStream_t gj_stream = nullptr; // private stream of the inversion lookahead (default priority)
-    hipEvent_t gj_fork = nullptr, gj_join = nullptr;
+    // private streams of the preconditioner build (default priority, non-blocking): two lanes that
+    // invert subdomain groups concurrently, each with a lookahead stream
+    hipStream_t gj_lane[2] = {nullptr, nullptr}, gj_aux[2] = {nullptr, nullptr};
+    hipEvent_t gj_fork[2] = {nullptr, nullptr}, gj_join[2] = {nullptr, nullptr};
+    hipEvent_t gj_start = nullptr, gj_done[2] = {nullptr, nullptr};
     GmresWork gw;
 
     ~mtf_problem_s() {
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
-        if (gj_fork) (void)hipEventDestroy(gj_fork);
-        if (gj_join) (void)hipEventDestroy(gj_join);
-        if (gj_stream) (void)hipStreamDestroy(gj_stream);
+        for (int l = 0; l < 2; ++l) {
+            if (gj_fork[l]) (void)hipEventDestroy(gj_fork[l]);
+            if (gj_join[l]) (void)hipEventDestroy(gj_join[l]);
+            if (gj_done[l]) (void)hipEventDestroy(gj_done[l]);
+            if (gj_lane[l]) (void)hipStreamDestroy(gj_lane[l]);
+            if (gj_aux[l]) (void)hipStreamDestroy(gj_aux[l]);
+        }
+        if (gj_start) (void)hipEventDestroy(gj_start);
         if (capture) (void)hipStreamDestroy(capture);
     }
 };
@@ -696,15 +704,22 @@ void build_tinv(mtf_problem p, bool force_full) {
     DevBuf<int> info;
     info.alloc(2);
     HIPCHK(hipMemsetAsync(info.p, 0, 2 * sizeof(int), s));
-    // lookahead stream of the inversions: non-blocking, so that it also overlaps work on a caller's
-    // null stream; ordered by events only
-    if (!p->gj_stream) HIPCHK(hipStreamCreateWithFlags(&p->gj_stream, hipStreamNonBlocking));
-    if (!p->gj_fork) HIPCHK(hipEventCreateWithFlags(&p->gj_fork, hipEventDisableTiming));
-    if (!p->gj_join) HIPCHK(hipEventCreateWithFlags(&p->gj_join, hipEventDisableTiming));
-    GjLookahead la;
-    la.s2 = p->gj_stream;
-    la.fork = p->gj_fork;
-    la.join = p->gj_join;
+    // streams of the inversions: non-blocking, so that they also overlap work on a caller's null
+    // stream; ordered by events only
+    for (int l = 0; l < 2; ++l) {
+        if (!p->gj_lane[l]) HIPCHK(hipStreamCreateWithFlags(&p->gj_lane[l], hipStreamNonBlocking));
+        if (!p->gj_aux[l]) HIPCHK(hipStreamCreateWithFlags(&p->gj_aux[l], hipStreamNonBlocking));
+        if (!p->gj_fork[l]) HIPCHK(hipEventCreateWithFlags(&p->gj_fork[l], hipEventDisableTiming));
+        if (!p->gj_join[l]) HIPCHK(hipEventCreateWithFlags(&p->gj_join[l], hipEventDisableTiming));
+        if (!p->gj_done[l]) HIPCHK(hipEventCreateWithFlags(&p->gj_done[l], hipEventDisableTiming));
+    }
+    if (!p->gj_start) HIPCHK(hipEventCreateWithFlags(&p->gj_start, hipEventDisableTiming));
+    GjLookahead la[2];
+    for (int l = 0; l < 2; ++l) {
+        la[l].s2 = p->gj_aux[l];
+        la[l].fork = p->gj_fork[l];
+        la[l].join = p->gj_join[l];
+    }
     // T_i in complex64 (kept for the check and the rebuilt blocks)
     DevBuf<float> tcopy;
     const float* T32 = p->T32.p;
@@ -717,24 +732,44 @@ void build_tinv(mtf_problem p, bool force_full) {
     p->pc_full.assign(nd, force_full ? 1 : 0);
     for (int i = 0; i < nd; ++i)
         if (D[i].E > 0 && !p->pc_full[i]) launch_symmetrize_f32(p->Tinv.p + 2 * D[i].mat0, D[i].E, s);
-    int64_t tmp_entries = 0, emax = 0;                 // out-of-place panels: W * E per matrix of a batch
-    for (int a = 0; a < nd;) {
-        int b = a + 1;
-        while (b < nd && D[b].E == D[a].E && D[b].mat0 == D[a].mat0 + (int64_t)(b - a) * D[a].E * D[a].E) ++b;
-        tmp_entries = std::max(tmp_entries, (int64_t)(b - a) * kGjPanel * D[a].E);
-        emax = std::max<int64_t>(emax, D[a].E);
-        a = b;
-    }
-    DevBuf<float> gjtmp;
-    gjtmp.alloc(2 * std::max<int64_t>(tmp_entries, 1));
-    // consecutive subdomains of equal size are stored back to back and inverted as one batch
+    // consecutive subdomains of equal size are stored back to back and inverted as one batch; the
+    // groups are independent, so the one with the most work (the largest order) runs on lane 0 and
+    // all others, one after another, on lane 1, each lane with its own scratch for the panels
+    struct Group {
+        int a, b;
+        int64_t E;
+    };
+    std::vector<Group> groups;
+    int64_t emax = 0;
     for (int a = 0; a < nd;) {
         int b = a + 1;
         const int64_t E = D[a].E;
         while (b < nd && D[b].E == E && D[b].mat0 == D[a].mat0 + (int64_t)(b - a) * E * E) ++b;
-        if (E > 0)
-            block_gj_inverse(p->Tinv.p + 2 * D[a].mat0, (int)E, E, E * E, b - a, info.p, s, kGjPanel, gjtmp.p, &la);
+        if (E > 0) groups.push_back(Group{a, b, E});
+        emax = std::max<int64_t>(emax, E);
         a = b;
+    }
+    size_t big = 0;
+    for (size_t g = 1; g < groups.size(); ++g)
+        if (groups[g].E > groups[big].E) big = g;
+    int64_t tmp_entries[2] = {1, 1};                   // out-of-place panels: W * E per matrix of a batch
+    for (size_t g = 0; g < groups.size(); ++g) {
+        const int l = g == big ? 0 : 1;
+        tmp_entries[l] = std::max(tmp_entries[l], (int64_t)(groups[g].b - groups[g].a) * kGjPanel * groups[g].E);
+    }
+    DevBuf<float> gjtmp[2];
+    for (int l = 0; l < 2; ++l) gjtmp[l].alloc(2 * tmp_entries[l]);
+    HIPCHK(hipEventRecord(p->gj_start, s));
+    for (int l = 0; l < 2; ++l) HIPCHK(hipStreamWaitEvent(p->gj_lane[l], p->gj_start, 0));
+    for (size_t g = 0; g < groups.size(); ++g) {
+        const int l = g == big ? 0 : 1;
+        const Group& q = groups[g];
+        block_gj_inverse(p->Tinv.p + 2 * D[q.a].mat0, (int)q.E, q.E, q.E * q.E, q.b - q.a, info.p, p->gj_lane[l],
+                         kGjPanel, gjtmp[l].p, &la[l]);
+    }
+    for (int l = 0; l < 2; ++l) {
+        HIPCHK(hipEventRecord(p->gj_done[l], p->gj_lane[l]));
+        HIPCHK(hipStreamWaitEvent(s, p->gj_done[l], 0));
     }
     if (!force_full && emax > 0) {
         // check ||T_i (X_i v) - v|| / ||v|| with v_m = (cos m, sin 2m) per block
@@ -782,7 +817,8 @@ void build_tinv(mtf_problem p, bool force_full) {
             const int64_t E = D[i].E;
             HIPCHK(hipMemcpyAsync(p->Tinv.p + 2 * D[i].mat0, T32 + 2 * D[i].mat0, 2 * E * E * sizeof(float),
                                   hipMemcpyDeviceToDevice, s));
-            block_gj_inverse(p->Tinv.p + 2 * D[i].mat0, (int)E, E, E * E, 1, info.p, s, kGjPanel, gjtmp.p, &la);
+            // lane 0's scratch holds W * E for the largest E, so it serves any single block
+            block_gj_inverse(p->Tinv.p + 2 * D[i].mat0, (int)E, E, E * E, 1, info.p, s, kGjPanel, gjtmp[0].p, &la[0]);
             p->pc_full[i] = 1;
         }
     }
