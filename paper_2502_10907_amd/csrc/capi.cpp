@@ -685,8 +685,44 @@ void build_pc_tiles(mtf_problem p) {
     p->stage_tile0 = st0;
 }
 
+// Connected components of Gamma_i (its triangles joined through shared dofs) as dof ranges
+// [lo, hi), in dof order.  Empty when Gamma_i is connected, or when a component's dofs do not form
+// one contiguous range (then the block is treated whole).
+std::vector<std::pair<int, int>> dof_components(const Domain& d) {
+    const int E = d.E;
+    std::vector<int> par(E);
+    for (int m = 0; m < E; ++m) par[m] = m;
+    auto root = [&](int m) {
+        while (par[m] != m) m = par[m] = par[par[m]];
+        return m;
+    };
+    for (int lt = 0; lt < d.T; ++lt) {
+        const int a = root(d.tri_dof[3 * lt]);
+        for (int q = 1; q < 3; ++q) {
+            const int b = root(d.tri_dof[3 * lt + q]);
+            if (a != b) par[b] = a;
+        }
+    }
+    std::vector<std::pair<int, int>> runs;
+    std::vector<char> seen(E, 0);
+    for (int m = 0; m < E;) {
+        const int r = root(m);
+        if (seen[r]) return {};                        // the component comes back: not contiguous
+        seen[r] = 1;
+        int n = m + 1;
+        while (n < E && root(n) == r) ++n;
+        runs.emplace_back(m, n);
+        m = n;
+    }
+    if (runs.size() < 2) return {};
+    return runs;
+}
+
 // Blocks of the T_i^-1 preconditioner, complex64.  Each block is first the inverse of the
-// symmetric part S_i = (T_i + T_i^T)/2, applied reading half of its entries.  S_i differs from T_i
+// symmetric part S_i = (T_i + T_i^T)/2, applied reading half of its entries.  Where Gamma_i has
+// several connected components (the exterior of disjoint scatterers), S_i is replaced by its
+// block diagonal over the components, each block inverted on its own: the cost of the inverse
+// falls from the cube of the whole order to the sum of the components' cubes.  S_i differs from T_i
 // by the two-order quadrature difference of touching pairs; where T_i is ill-conditioned that
 // difference is amplified in the inverse.  So every block is checked on a fixed vector v: when
 // ||T_i (S_i^-1 v) - v|| > kPcSymTol ||v|| (or when `force_full`), the block is rebuilt as the
@@ -732,6 +768,21 @@ void build_tinv(mtf_problem p, bool force_full) {
     p->pc_full.assign(nd, force_full ? 1 : 0);
     for (int i = 0; i < nd; ++i)
         if (D[i].E > 0 && !p->pc_full[i]) launch_symmetrize_f32(p->Tinv.p + 2 * D[i].mat0, D[i].E, s);
+    // several components: block diagonal over them (entries between components cleared)
+    std::vector<std::vector<std::pair<int, int>>> comps(nd);
+    std::vector<std::vector<int32_t>> cidh(nd);        // kept until the build synchronises
+    std::vector<DevBuf<int32_t>> cids(nd);
+    for (int i = 0; i < nd; ++i) {
+        if (D[i].E == 0 || p->pc_full[i]) continue;
+        comps[i] = dof_components(p->sk.dom[i]);
+        if (comps[i].empty()) continue;
+        std::vector<int32_t>& cid = cidh[i];
+        cid.resize(D[i].E);
+        for (size_t q = 0; q < comps[i].size(); ++q)
+            for (int m = comps[i][q].first; m < comps[i][q].second; ++m) cid[m] = (int32_t)q;
+        cids[i].upload(cid, s);
+        launch_zero_offdiag_f32(p->Tinv.p + 2 * D[i].mat0, D[i].E, cids[i].p, s);
+    }
     // consecutive subdomains of equal size are stored back to back and inverted as one batch; the
     // groups are independent, so the one with the most work (the largest order) runs on lane 0 and
     // all others, one after another, on lane 1, each lane with its own scratch for the panels
@@ -764,6 +815,14 @@ void build_tinv(mtf_problem p, bool force_full) {
     for (size_t g = 0; g < groups.size(); ++g) {
         const int l = g == big ? 0 : 1;
         const Group& q = groups[g];
+        if (q.b - q.a == 1 && !comps[q.a].empty()) {
+            for (const auto& c : comps[q.a]) {          // each component's diagonal block, in place
+                const int64_t o = c.first + (int64_t)c.first * q.E;
+                block_gj_inverse(p->Tinv.p + 2 * (D[q.a].mat0 + o), c.second - c.first, q.E, q.E * q.E, 1, info.p,
+                                 p->gj_lane[l], kGjPanel, gjtmp[l].p, &la[l]);
+            }
+            continue;
+        }
         block_gj_inverse(p->Tinv.p + 2 * D[q.a].mat0, (int)q.E, q.E, q.E * q.E, q.b - q.a, info.p, p->gj_lane[l],
                          kGjPanel, gjtmp[l].p, &la[l]);
     }
@@ -791,7 +850,17 @@ void build_tinv(mtf_problem p, bool force_full) {
             int b = a + 1;
             const int64_t E = D[a].E;
             while (b < nd && D[b].E == E && D[b].mat0 == D[a].mat0 + (int64_t)(b - a) * E * E) ++b;
-            if (E > 0) {
+            if (E > 0 && b - a == 1 && !comps[a].empty()) {
+                // block diagonal over the components: each component's diagonal blocks of X_i and T_i
+                for (const auto& c : comps[a]) {
+                    const int64_t o = c.first + (int64_t)c.first * E;
+                    const int nc = c.second - c.first;
+                    launch_cgemv_f32(p->Tinv.p + 2 * (D[a].mat0 + o), E, E * E, v.p + 2 * c.first, 0, nc, 1, part.p,
+                                     w.p + 2 * (uoff[a] + c.first), E, s);
+                    launch_cgemv_f32(T32 + 2 * (D[a].mat0 + o), E, E * E, w.p + 2 * (uoff[a] + c.first), E, nc, 1,
+                                     part.p, u.p + 2 * (uoff[a] + c.first), E, s);
+                }
+            } else if (E > 0) {
                 // blocks a..b-1 are back to back (stride E^2), as are their slices of w and u (stride E)
                 launch_cgemv_f32(p->Tinv.p + 2 * D[a].mat0, E, E * E, v.p, 0, (int)E, b - a, part.p, w.p + 2 * uoff[a], E, s);
                 launch_cgemv_f32(T32 + 2 * D[a].mat0, E, E * E, w.p + 2 * uoff[a], E, (int)E, b - a, part.p,

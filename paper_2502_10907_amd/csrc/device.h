@@ -209,6 +209,7 @@ void launch_precond_sym(const DomDesc* doms, const int4* stiles, int64_t ntiles,
                         double* part, hipStream_t s);
 void launch_precond_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int64_t ndof, const double* part, double* z,
                                const int32_t* list, hipStream_t s);
+void launch_zero_offdiag_f32(float* A, int E, const int32_t* cid, hipStream_t s);   // A[r,c] = 0 where cid[r] != cid[c]
 void launch_symmetrize_f32(float* A, int n, hipStream_t s);
 // w_i = v_i - sum_j G^ij z_j for the dofs in `list` (one block Gauss-Seidel stage)
 void launch_gs_residual(const DomDesc* doms, const int32_t* dof_dom, const int32_t* list, int64_t nlist,

@@ -423,6 +423,15 @@ __global__ __launch_bounds__(256) void k_pc_sym_finish(const DomDesc* __restrict
     oN[0] = b * acc[0]; oN[1] = b * acc[1];
 }
 
+// A[r, c] <- 0 where the dofs r and c lie in different connected components (cid[r] != cid[c]) of the
+// E x E complex64 block A (ld E)
+__global__ void k_zero_offdiag_f32(float2* __restrict__ A, int E, const int32_t* __restrict__ cid) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)E * E) return;
+    const int r = (int)(e % E), c = (int)(e / E);
+    if (cid[r] != cid[c]) A[e] = make_float2(0.f, 0.f);
+}
+
 // A <- (A + A^T) / 2 for the n x n complex64 block A (ld n), in place
 __global__ void k_symmetrize_f32(float* __restrict__ A, int n) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1457,6 +1466,11 @@ void launch_precond_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int6
                                const int32_t* list, hipStream_t s) {
     if (ndof <= 0) return;
     hipLaunchKernelGGL(k_pc_sym_finish, dim3(gridn(ndof, 16)), dim3(256), 0, s, doms, dof_dom, ndof, part, z, list);
+}
+
+void launch_zero_offdiag_f32(float* A, int E, const int32_t* cid, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_offdiag_f32, dim3(gridn((int64_t)E * E, 256)), dim3(256), 0, s, reinterpret_cast<float2*>(A),
+                       E, cid);
 }
 
 void launch_symmetrize_f32(float* A, int n, hipStream_t s) {
