@@ -296,7 +296,10 @@ int mtf_batch_assemble(mtf_batch b, const mtf_assembly_opts* opts, int32_t* grid
  * common options, problem after problem; stats[n] may be NULL.  A problem without FP64 blocks
  * gets them assembled (default options) for its residual checks and released after its solve;
  * its preconditioner blocks and GMRES work buffers are released too when they did not exist before, so
- * the batch needs device memory for one problem's solve at a time beyond the blocks it holds. */
+ * the batch needs device memory for one problem's solve at a time beyond the blocks it holds.
+ * max_iters 0 here means cycles of at most 1,000 Arnoldi steps (not the free-memory length of
+ * mtf_solve): a batch is many small solves, and Krylov storage sized from free memory would be
+ * allocated and released for each of them. */
 int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, const mtf_solve_opts* opts,
                     mtf_solve_stats* stats);
 

@@ -31,6 +31,7 @@ constexpr double kPcSymTol = 1e-3;   // largest ||T_i S_i^-1 v - v|| / ||v|| of 
 constexpr int kSync = 8;      // Arnoldi steps between host reads of the Hessenberg columns
 constexpr int kMaxBatch = 64; // right-hand sides per lockstep GMRES batch (MFMA products)
 constexpr int kUpdGroups = 8; // partial-sum groups of the basis update
+constexpr int kBatchCycle = 1000;  // Arnoldi steps per cycle in mtf_batch_solve when max_iters is 0
 constexpr int kEagerBatches = 2;   // Arnoldi batches of a cycle launched eagerly before a graph is captured
 constexpr double kLookaheadFactor = 30.0;   // a second batch is queued while every residual exceeds this x target
 
@@ -887,7 +888,16 @@ void build_tinv(mtf_problem p, bool force_full) {
             HIPCHK(hipMemcpyAsync(p->Tinv.p + 2 * D[i].mat0, T32 + 2 * D[i].mat0, 2 * E * E * sizeof(float),
                                   hipMemcpyDeviceToDevice, s));
             // lane 0's scratch holds W * E for the largest E, so it serves any single block
-            block_gj_inverse(p->Tinv.p + 2 * D[i].mat0, (int)E, E, E * E, 1, info.p, s, kGjPanel, gjtmp[0].p, &la[0]);
+            if (!comps[i].empty()) {
+                // several components: T_i's own component blocks, each inverted on its own
+                launch_zero_offdiag_f32(p->Tinv.p + 2 * D[i].mat0, (int)E, cids[i].p, s);
+                for (const auto& c : comps[i])
+                    block_gj_inverse(p->Tinv.p + 2 * (D[i].mat0 + c.first + (int64_t)c.first * E), c.second - c.first,
+                                     E, E * E, 1, info.p, s, kGjPanel, gjtmp[0].p, &la[0]);
+            } else {
+                block_gj_inverse(p->Tinv.p + 2 * D[i].mat0, (int)E, E, E * E, 1, info.p, s, kGjPanel, gjtmp[0].p,
+                                 &la[0]);
+            }
             p->pc_full[i] = 1;
         }
     }
@@ -1962,7 +1972,18 @@ int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, c
                 ao.singular_order = 4;
                 assemble_impl(p, &ao);
             }
-            const int r = solve_impl(p, 1, b_dev[i], x_dev[i], p->sk.N, opts, stats ? stats + i : nullptr);
+            // max_iters 0: cycles of at most kBatchCycle steps.  The Krylov storage of a cycle is
+            // allocated per problem; sized from free memory it would be gigabytes per problem for
+            // solves that take tens of steps, and allocating it would dominate the batch.
+            mtf_solve_opts o{};
+            o.struct_size = sizeof(o);
+            o.rtol = 1e-6;
+            if (opts) {
+                if (opts->struct_size < (int)sizeof(mtf_solve_opts)) throw ArgError("mtf_solve_opts.struct_size too small");
+                o = *opts;
+            }
+            if (o.max_iters == 0) o.max_iters = kBatchCycle;
+            const int r = solve_impl(p, 1, b_dev[i], x_dev[i], p->sk.N, &o, stats ? stats + i : nullptr);
             if (r != MTF_OK) status = r;
             sync(p);
             if (tmp64) { p->T64.reset(); p->K64.reset(); p->near64.reset(); p->have64 = false; }
