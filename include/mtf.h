@@ -230,7 +230,9 @@ typedef struct {
  * (the inverse of the off-diagonal part of 2 A_i with T_i replaced by its symmetric
  * part, which differs from T_i only by the quadrature asymmetry of touching pairs; the
  * block shape of the block-OSRC preconditioner of Section 4.4), S_i^-1 computed once
- * per problem on the GPU in complex64 and applied reading its upper triangle only.
+ * per problem on the GPU in complex64 and applied reading its upper triangle only.  Where Gamma_i
+ * has several connected components (the exterior of disjoint scatterers), S_i is taken block
+ * diagonal over them, each component's block inverted on its own.
  * A block whose T_i is ill-conditioned enough that ||T_i S_i^-1 v - v|| > 1e-3 ||v|| on a
  * fixed vector v is rebuilt as T_i^-1 and read whole (every block with MTF_SOLVE_PC_FULL).
  * MTF_PREC_BLOCK_TINV_GS applies one block Gauss-Seidel sweep instead: Omega_0
