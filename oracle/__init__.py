@@ -25,7 +25,9 @@ Preconditioning"):
                     LU and plain GMRES.
 * ``mie``        -- Mie series of a dielectric sphere (Bohren & Huffman
                     1983, Chapter 4), an external check.
-* ``closed_forms`` -- textbook closed forms used only to pin the oracle.
+
+Textbook closed forms that pin the oracle live with the tests
+(``tests/_closed_forms.py``), not here.
 
 Readings where the paper is silent or inconsistent are documented in
 the design doc of the repository and restated at the function that takes them.

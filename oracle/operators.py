@@ -288,21 +288,6 @@ def gram_twisted(xyz, sp_test: RWGSpace, sp_trial: RWGSpace):
     return G
 
 
-def gram_untwisted(xyz, sp: RWGSpace):
-    """SPD mass matrix  int phi_n . phi_m  on Gamma_i (used only for projections in tests)."""
-    E = sp.ndof
-    Mm = np.zeros((E, E))
-    P, A, _, l = tri_geometry(xyz, sp.verts)
-    x, w = regular_points(P)
-    phi, _ = rwg_local(P, A, l, x)
-    loc = np.einsum("bq,bqai,bqci->bac", w, phi, phi)
-    for a in range(3):
-        for c in range(3):
-            s = sp.tri_sign[:, a] * sp.tri_sign[:, c]
-            np.add.at(Mm, (sp.tri_dof[:, a], sp.tri_dof[:, c]), s * loc[:, a, c])
-    return Mm
-
-
 # ---------------------------------------------------------------------------
 # incident plane wave, right-hand side, far field
 # ---------------------------------------------------------------------------

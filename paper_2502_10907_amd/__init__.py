@@ -4,8 +4,8 @@ Maxwell scattering: thin Python binding over the C ABI of ``libmtf.so``.
 Every operation runs in the HIP library; this module only marshals arguments.
 Device buffers are torch tensors on a HIP device (complex128, contiguous, shape
 [nrhs, N] so that right-hand side r starts at r * N); host arrays are numpy.
-The library is built in-tree by ``paper_2502_10907_amd.build.build()``; importing
-this module without it raises ImportError.
+The library is built in-tree by ``python paper_2502_10907_amd/build.py`` (or
+``__graft_entry__.build()``); importing this module without it raises ImportError.
 """
 from __future__ import annotations
 
@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libmtf.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "mtf.h")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2502_10907_amd.build`")
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2502_10907_amd/build.py` "
+                      "or __graft_entry__.build()")
 # torch first: its HIP runtime is then the one libmtf.so binds to (same soname), so the
 # process holds a single runtime and torch streams and pointers are valid in the library.
 import torch  # noqa: E402,F401

@@ -29,3 +29,30 @@ def plane_wave_traces(k, d, p, rho=1.0):
     def uN(x, n):
         return rho * np.cross(np.cross(d, p)[None] * np.exp(1j * k * x @ d)[:, None], n[None])
     return uD, uN
+
+
+def dipole_traces(k, xs, p, rho=1.0):
+    """(gamma_D U, rho gamma_N U) of the radiating field U = curl(p G_k(x - xs)) = grad G x p
+    (a magnetic dipole at xs; curl curl U = k^2 U away from xs), with G_k = exp(i k r)/(4 pi r).
+    curl U = grad(p . grad G) + k^2 p G; gamma_N U = (1/(i k)) curl U x n, as for the plane wave."""
+    xs = np.asarray(xs, float)
+    p = np.asarray(p, float)
+
+    def parts(x):
+        d = x - xs[None]
+        r = np.linalg.norm(d, axis=1)
+        e = np.exp(1j * k * r) / (4 * np.pi)
+        G = e / r
+        g = e * (1j * k * r - 1.0) / r ** 3                 # grad G = g d
+        dg_r = e * (3.0 - 3j * k * r - k * k * r * r) / r ** 5   # g'(r) / r
+        U = np.cross(g[:, None] * d, p[None])
+        pd = d @ p
+        cU = g[:, None] * p[None] + (pd * dg_r)[:, None] * d + (k * k * G)[:, None] * p[None]
+        return U, cU
+
+    def uD(x, n):
+        return np.cross(parts(x)[0], n[None])
+
+    def uN(x, n):
+        return rho / (1j * k) * np.cross(parts(x)[1], n[None])
+    return uD, uN

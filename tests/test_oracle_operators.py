@@ -120,3 +120,84 @@ def test_calderon_projector(i, sign):
         wrong = np.linalg.norm(np.concatenate([AD + sign * hD, AN + sign * hN])) / nrm
         assert wrong > 1.5
     assert errs[0] < 0.2 and errs[1] < 0.07 and errs[1] < 0.5 * errs[0]
+
+
+def _calderon_weak(h, i, k, rho, data):
+    m = mi.box_skeleton((1, 1, 1), (h, h, h))
+    sp = sk.rwg_space(m.tri, m.label, i)
+    T, K = op.assemble_TK(m.xyz, sp, k)
+    G = op.gram_twisted(m.xyz, sp, sp)
+    cs = []
+    for uD, uN in data:
+        cs.append(np.concatenate([_interp.rwg_interpolant(m.xyz, sp, uD), _interp.rwg_interpolant(m.xyz, sp, uN)]))
+    E = sp.ndof
+
+    def A(c):
+        return np.concatenate([K @ c[:E] + T @ c[E:] / rho, -rho * T @ c[:E] + K @ c[E:]])
+
+    def Gx(c):
+        return np.concatenate([G @ c[:E], G @ c[E:]])
+    return A, Gx, cs, G
+
+
+@pytest.mark.parametrize("i,sign", [(1, -0.5), (0, +0.5)])
+def test_calderon_projector_radiating_data(i, sign):
+    """Cauchy data of a field radiating from a source inside the scatterer (a dipole) lie in the
+    other eigenspace of the Calderon operator: A_1 u = -u/2 on Gamma_1 and, with Gamma_0's opposite
+    normal, A_0 u = +u/2 (Section 2.4).  Weak form, shrinking under refinement."""
+    k, rho = 2.0, 1.5
+    data = [_interp.dipole_traces(k, (0.45, 0.52, 0.5), (0.3, -0.5, 0.8), rho)]
+    errs = []
+    for h in (2, 4):
+        A, Gx, (c,), _ = _calderon_weak(h, i, k, rho, data)
+        ref = sign * Gx(c)
+        errs.append(np.linalg.norm(A(c) - ref) / np.linalg.norm(ref))
+        assert np.linalg.norm(A(c) + ref) / np.linalg.norm(ref) > 1.5
+    assert errs[1] < 0.1 and errs[1] < 0.6 * errs[0], errs
+
+
+def test_calderon_identity_square():
+    """(2A)^2 = I (Section 1, the Calderon identity): for u = u_int + u_ext (Cauchy data of a plane
+    wave, regular inside, plus those of a dipole inside Gamma_1, radiating), A u = (u_int - u_ext)/2
+    and A (u_int - u_ext) = u/2, so A(A u) = u/4.  Both steps are checked in the weak (Galerkin)
+    form on Gamma_1, with defects shrinking under refinement, while the sign-flipped steps stay O(1).
+    The literal product A_h A_h with A_h = G^-1 A_w is not formed: the twisted Gram G of RWG
+    against RWG is singular (checked here), so only the weak steps are well defined."""
+    k, rho = 2.0, 1.5
+    d = np.array([0.36, 0.48, 0.8])
+    p = np.array([0.8, 0.0, -0.36])
+    p /= np.linalg.norm(p)
+    data = [_interp.plane_wave_traces(k, d, p, rho),
+            _interp.dipole_traces(k, (0.45, 0.52, 0.5), (0.3, -0.5, 0.8), rho)]
+    e1, e2 = [], []
+    for h in (2, 4):
+        A, Gx, (ci, ce), G = _calderon_weak(h, 1, k, rho, data)
+        s, dlt = ci + ce, ci - ce
+        r1, r2 = 0.5 * Gx(dlt), 0.5 * Gx(s)
+        e1.append(np.linalg.norm(A(s) - r1) / np.linalg.norm(r1))
+        e2.append(np.linalg.norm(A(dlt) - r2) / np.linalg.norm(r2))
+        assert np.linalg.norm(A(s) - 0.5 * Gx(s)) / np.linalg.norm(r2) > 0.3    # u alone is no eigenvector
+        sv = np.linalg.svd(G, compute_uv=False)
+        assert sv[-1] < 1e-12 * sv[0]                                            # singular twisted Gram
+    assert max(e1[1], e2[1]) < 0.1, (e1, e2)
+    assert e1[1] < 0.6 * e1[0] and e2[1] < 0.6 * e2[0], (e1, e2)
+
+
+def test_single_entries_and_rows_equal_whole_blocks(cube_ops):
+    """entry_TK and rows_TK (the sampled-entry checkers of the full-size tests) equal the whole
+    assembled blocks, for separated and touching (coincident, edge, vertex) supports."""
+    m, sp, T, K = cube_ops
+    rng = np.random.default_rng(5)
+    pairs = [(int(rng.integers(sp.ndof)), int(rng.integers(sp.ndof))) for _ in range(6)]
+    for mm in rng.integers(sp.ndof, size=6):
+        lt = int(sp.plus[mm, 0])
+        pairs.append((int(mm), int(sp.tri_dof[lt, int(rng.integers(3))])))   # shared triangle
+        pairs.append((int(mm), int(mm)))
+    scale = np.abs(T).max()
+    for mm, nn in pairs:
+        t, kk = op.entry_TK(m.xyz, sp, mm, nn, 2.0)
+        assert abs(t - T[mm, nn]) < 1e-14 * scale and abs(kk - K[mm, nn]) < 1e-14 * scale, (mm, nn)
+    rows = rng.choice(sp.ndof, 5, replace=False)
+    Tr, Kr = op.rows_TK(m.xyz, sp, rows, 2.0)
+    assert np.abs(Tr - T[rows]).max() < 1e-14 * scale
+    assert np.abs(Kr - K[rows]).max() < 1e-14 * scale

@@ -117,3 +117,25 @@ def test_block_jacobi_gmres_matches_lu(small_cube):
     assert np.linalg.norm(Mx @ xg - b) / np.linalg.norm(b) < 2e-10
     assert np.linalg.norm(xg - x) / np.linalg.norm(x) < 1e-8
     assert it < 400
+
+
+@pytest.mark.parametrize("x", [1.0, 2.0, 3.5, 5.0])
+def test_mie_optical_theorem(x):
+    """For a non-absorbing sphere (real m) extinction equals scattering (Bohren & Huffman eqs.
+    4.61-4.62): Q_ext = (2/x^2) sum (2n+1) Re(a_n + b_n) = Q_sca = (2/x^2) sum (2n+1)(|a_n|^2 + |b_n|^2),
+    which fails for a wrong sign or index in any coefficient that matters at this size, and the
+    forward amplitude gives Q_ext = (4/x^2) Re S(0) (eq. 4.76), which pins the angular sums."""
+    m = np.sqrt(2.0)
+    nmax = int(np.ceil(x + 4 * x ** (1 / 3) + 2)) + 10
+    a, b = mie.mie_coefficients(x, m, nmax)
+    n = np.arange(1, nmax + 1)
+    qext = 2 / x ** 2 * np.sum((2 * n + 1) * (a + b).real)
+    qsca = 2 / x ** 2 * np.sum((2 * n + 1) * (abs(a) ** 2 + abs(b) ** 2))
+    assert abs(qext - qsca) < 1e-12 * qext
+    S1, S2 = mie.amplitudes(x, m, np.array([1.0]))
+    assert abs(S1[0] - S2[0]) < 1e-12 * abs(S1[0])
+    assert abs(4 / x ** 2 * S1[0].real - qext) < 1e-12 * qext
+    # a single-coefficient slip breaks the balance
+    a2 = a.copy()
+    a2[1] = -a2[1]
+    assert abs(2 / x ** 2 * np.sum((2 * n + 1) * (a2 + b).real) - qsca) > 1e-3 * qsca
