@@ -188,6 +188,20 @@ int mtf_rhs_plane_waves(mtf_problem p, int32_t nrhs, const double* d, const doub
 int mtf_matvec(mtf_problem p, int32_t nrhs, const void* x_dev, void* y_dev, int64_t ld,
                int32_t precision);
 
+/* The product of mtf_matvec (precision MTF_FP64 or MTF_FP32_MIXED only), for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  It calls no hipMalloc, hipFree or other allocating routine; the partial sums that
+ * mtf_matvec keeps in a buffer of the problem go to a fixed 64 MiB array in device memory instead
+ * (one per GPU, held until the process ends), so a problem whose product needs more than
+ * 64 MiB of partial sums (16 bytes x sum_i 2 E_i (ceil(E_i/64) + 1); about 16 MB for N = 27,648)
+ * is rejected with MTF_ERR_ARG before any device work.  Same kernels and results as mtf_matvec.
+ * The array is shared by every call on that GPU and keeps the last call's contents (it needs no
+ * clearing: every entry a call reads, that call wrote first): calls that overlap on one GPU, from
+ * two streams or two threads, race and give wrong results.  The blocks of `precision` must have
+ * been assembled (mtf_assemble allocates; this call does not). */
+int mtf_matvec_noalloc(mtf_problem p, int32_t nrhs, const void* x_dev, void* y_dev, int64_t ld,
+                       int32_t precision);
+
 /* Measurement of the product above for one vector (x_dev, y_dev: complex128 [N] on the device,
  * precision MTF_FP64 or MTF_FP32_MIXED): `reps` products are launched on the problem's stream
  * with HIP events around each launch of the dense block kernel (every T_i, K_i entry streamed

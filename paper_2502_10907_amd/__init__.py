@@ -89,6 +89,7 @@ _SIGS = {
     "mtf_apply_preconditioner": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, C.c_int64]),
     "mtf_rhs_plane_waves": (C.c_int, [_P, C.c_int32, _dp, _dp, _dp, _P, C.c_int64]),
     "mtf_matvec": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.c_int32]),
+    "mtf_matvec_noalloc": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.c_int32]),
     "mtf_solve": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
     "mtf_far_field": (C.c_int, [_P, C.c_int32, _P, C.c_int64, C.c_int32, _dp, _dp]),
     "mtf_assembly_stats": (C.c_int, [_P, _lp, _dp]),
@@ -278,6 +279,14 @@ class Problem:
         if (nrhs, ld) != (nrhs2, ld2):
             raise ValueError("x and y shapes differ")
         _check(_lib.mtf_matvec(self._h, nrhs, px, py, ld, int(precision)))
+
+    def matvec_noalloc(self, x, y, precision: int = FP64):
+        """y = M x through the allocation-free entry point (static device scratch)."""
+        px, nrhs, ld = _dev(x, self.N)
+        py, nrhs2, ld2 = _dev(y, self.N)
+        if (nrhs, ld) != (nrhs2, ld2):
+            raise ValueError("x and y shapes differ")
+        _check(_lib.mtf_matvec_noalloc(self._h, nrhs, px, py, ld, int(precision)))
 
     def apply_preconditioner(self, x, z, preconditioner: int = PREC_BLOCK_TINV):
         px, nrhs, ld = _dev(x, self.N)

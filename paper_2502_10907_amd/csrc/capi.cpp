@@ -9,6 +9,7 @@
 #include <complex>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -528,16 +529,43 @@ void apply_gemm(mtf_problem p, int mode, int nrhs, const double* x, int64_t ld, 
 
 void matvec_gemm(mtf_problem p, int nrhs, const double* x, int64_t ld, double* y) { apply_gemm(p, 0, nrhs, x, ld, y); }
 
-// y = M x for one vector (device pointers, complex128 length N)
-void matvec1(mtf_problem p, const double* x, double* y, int prec) {
+// y = M x for one vector (device pointers, complex128 length N); the column-chunk partial sums go
+// to `part` (the problem's own buffer unless given: 2 * part_entries doubles, every slot written
+// before it is read, so it needs no clearing)
+void matvec1(mtf_problem p, const double* x, double* y, int prec, double* part = nullptr) {
     hipStream_t s = p->stream;
+    if (!part) part = p->part.p;
     if (prec == MTF_FP64)
-        launch_matvec_sym_f64(p->d_doms.p, p->d_symtiles.p, p->nsymtiles, p->T64.p, p->K64.p, x, p->part.p, s);
+        launch_matvec_sym_f64(p->d_doms.p, p->d_symtiles.p, p->nsymtiles, p->T64.p, p->K64.p, x, part, s);
     else
-        launch_matvec_sym_f32(p->d_doms.p, p->d_symtiles.p, p->nsymtiles, p->T32.p, p->K32.p, x, p->part.p, s);
+        launch_matvec_sym_f32(p->d_doms.p, p->d_symtiles.p, p->nsymtiles, p->T32.p, p->K32.p, x, part, s);
     launch_matvec_sym_finish(p->d_doms.p, p->d_dof_dom.p, p->ndof, p->d_dplus.p, p->d_dminus.p, p->d_gval.p,
                              p->d_gcol.p, p->d_near_ptr.p, p->d_near_col.p,
-                             prec == MTF_FP64 ? p->near64.p : p->near32.p, p->part.p, x, y, s);
+                             prec == MTF_FP64 ? p->near64.p : p->near32.p, part, x, y, s);
+}
+
+// Partial sums of the allocation-free product (mtf_matvec_noalloc): a fixed array in device
+// memory, one copy per GPU that the library runs on, held until the process ends.  Host code never
+// passes `scratch` itself to a kernel (on the host that name is only a stand-in for the symbol):
+// the device address of each GPU's copy is looked up once per device with hipGetSymbolAddress,
+// with that device current, and that address is what the kernels receive.
+constexpr int64_t kScratchReals = int64_t(8) << 20;     // 64 MiB of doubles = 4 Mi complex partial sums
+static __device__ __align__(256) double scratch[kScratchReals];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch` (the device must be current).
+double* scratch_on(int device) {
+    if (device < 0 || device >= kMaxDevices) throw ArgError("device id out of range for the static scratch");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void* ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) throw HipError("hipGetSymbolAddress returned no address for the static scratch");
+        g_scratch_dev[device] = static_cast<double*>(ptr);
+    }
+    return g_scratch_dev[device];
 }
 
 void precond1(mtf_problem p, const double* x, double* z) {
@@ -1671,6 +1699,29 @@ int mtf_matvec(mtf_problem p, int32_t nrhs, const void* x_dev, void* y_dev, int6
                 matvec1(p, static_cast<const double*>(x_dev) + 2 * ld * (int64_t)r,
                         static_cast<double*>(y_dev) + 2 * ld * (int64_t)r, precision);
         }
+        HIPCHK(hipGetLastError());
+        return MTF_OK;
+    });
+}
+
+int mtf_matvec_noalloc(mtf_problem p, int32_t nrhs, const void* x_dev, void* y_dev, int64_t ld, int32_t precision) {
+    return guarded([&] {
+        if (!p) throw ArgError("problem is NULL");
+        if (!p->has_mesh || !p->has_mat) throw StateError("mtf_matvec_noalloc before mesh/materials");
+        if (nrhs < 1 || !x_dev || !y_dev || ld < p->sk.N) throw ArgError("bad arguments");
+        if (x_dev == y_dev) throw ArgError("x and y must not alias");
+        if (precision != MTF_FP64 && precision != MTF_FP32_MIXED)
+            throw ArgError("mtf_matvec_noalloc: precision must be MTF_FP64 or MTF_FP32_MIXED");
+        if (2 * p->part_entries > kScratchReals)
+            throw ArgError("mtf_matvec_noalloc: the product needs " + std::to_string(16 * p->part_entries) +
+                           " bytes of partial sums, more than the static scratch of " +
+                           std::to_string(8 * kScratchReals) + " bytes");
+        check_prec_available(p, precision);
+        DeviceGuard g(p->device);
+        double* ws = scratch_on(p->device);
+        for (int r = 0; r < nrhs; ++r)
+            matvec1(p, static_cast<const double*>(x_dev) + 2 * ld * (int64_t)r,
+                    static_cast<double*>(y_dev) + 2 * ld * (int64_t)r, precision, ws);
         HIPCHK(hipGetLastError());
         return MTF_OK;
     });
