@@ -1,22 +1,29 @@
 """Time-to-solution of the local MTF on one MI355X.
 
-One step = the whole hot path on one batch of synthetic input: Galerkin
-assembly of every T_i, K_i and transmission block, the plane-wave right-hand
-side, the block T^-1 preconditioner, and GMRES to ||b - M x|| <= 1e-6 ||b||
-(FP64 operator and Arnoldi).  Workload: unit cube split into 2x2x2 sub-cubes,
-structured skeleton at h = 1/16 (4,608 triangles, N = 27,648 unknowns),
-eps_r ~ U[1,4] per sub-cube (SplitMix64 seed 0), mu_r = 1, k0 = 2 pi, one
-x-polarised plane wave along +z.
+Headline workload (the largest one that one GPU holds): 64 independent clusters of 1-8 disjoint
+dielectric spheres (SplitMix64 seed 0; Fibonacci-hull sphere meshes of 200-2,000 triangles,
+radii U[0.3,1], eps_r ~ U[1.5,4], k0 = 1.5), 297,288 skeleton triangles, 2.24e9 ordered triangle
+pairs, one x-polarised plane wave along +z per cluster.
 
-Prints one JSON line (rank 0).  The dense matvec roofline is measured live with
-HIP events on the library's stream; ``--no-cpu-baseline`` skips the oracle leg.
+One step = the whole hot path over the batch, in FP64 (complex128 blocks, 161 GB resident):
+the Galerkin assembly of every T_i, K_i of every cluster (separated pairs in one persistent launch,
+touching pairs by Sauter-Schwab), the plane-wave right-hand sides, the block T^-1 preconditioner of
+every cluster (built together), and flexible GMRES per cluster to ||b - M x|| <= 1e-6 ||b|| with the
+FP64 operator.
+
+Also reported (extra keys, not the headline): the same batch on the mixed path (complex64 blocks
+from FP32 quadrature, relaxed complex64 products in GMRES, FP64 residuals and refinement), and the
+2x2x2 cube at h = 1/16 (N = 27,648) with the live roofline of its block product.
+
+Prints one JSON line.  The CPU baseline (the FP64 oracle on the three smallest clusters, three
+processes) runs first, before anything touches the GPU; ``--no-cpu-baseline`` skips it.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
+import subprocess
 import sys
 import time
 
@@ -26,11 +33,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFLOPS = 78.6
+# algorithmic work of a separated triangle pair: 36 point pairs x (about 90-110 real flops + sqrt,
+# reciprocal and sincos), about 3.7 kflop
+FLOP_PER_SEPARATED_PAIR = 3.7e3
+CPU_SAMPLE_CLUSTERS = 3
 
-# HBM traffic of the dense block matvec kernel from two rocprofv3 counter passes on this workload
-# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the bench's launches), each scaled by
-# what the same counter reads for a 1 GiB device-to-device copy.  Valid only for the kernel source
-# the counters were taken on (digest below) and for h = 1/16; otherwise traffic is reported null.
+# HBM traffic of the dense block matvec kernel from two rocprofv3 counter passes on the 2x2x2 cube
+# at h = 1/16 (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the launches), each scaled
+# by what the same counter reads for a 1 GiB device-to-device copy.  Valid only for the kernel
+# source the counters were taken on (digest below); otherwise traffic is reported null.
 MV_COUNTERS = {
     "kernel_digest": "37425098dd7ff8dd",
     "h_inv": 16,
@@ -67,155 +79,287 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--h-inv", type=int, default=16)
+    ap.add_argument("--nclusters", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cube", action="store_true")
     ap.add_argument("--matvec-reps", type=int, default=20)
-    ap.add_argument("--pc", type=int, default=2, help="1 block-Jacobi T^-1, 2 block Gauss-Seidel T^-1")
+    ap.add_argument("--cpu-worker", type=int, default=None, help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
-def cpu_baseline(cfg, gpu_iters, nrows=64):
-    """The oracle, timed on a bounded sample of the same workload and scaled to seconds per solve.
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle on the smallest clusters (test infrastructure, timed only)
+# ---------------------------------------------------------------------------
 
-    Sample: ``nrows`` full rows of T_1, K_1 of one sub-cube computed by the oracle (each row
-    integrates both triangles of its dof against every triangle of Gamma_1), and 5 oracle
-    matvecs with that sub-cube's 2x2 Calderon block.  Scaling: the assembly by ordered
-    triangle pairs (whole skeleton / pairs evaluated in the sample), the iteration by the
-    matrix bytes of the whole system times the GPU's GMRES iteration count (one M and one
-    preconditioner application per iteration, counted as two matvec equivalents).
-    """
-    from oracle import operators as op
+def _cluster_sizes(cl):
+    out = []
+    for i, c in enumerate(cl):
+        T = c["mesh"].meta["tri_per_sphere"]
+        Tc = sum(T)
+        out.append((Tc * Tc + sum(t * t for t in T), i, 6 * Tc))   # ordered pairs, index, N
+    return out
+
+
+def cpu_worker(idx):
+    """One oracle solve of cluster `idx` (seed 0): FP64 assembly of every block, dense matrix, LU."""
+    import mtf_inputs as mi
     from oracle import system as sy
+    cfg = mi.config_clusters(64, seed=0)[idx]
+    t0 = time.perf_counter()
     pb = sy.Problem.from_config(cfg)
-    sp = pb.spaces[1]
-    T1 = sp.verts.shape[0]
-    rows = np.linspace(0, sp.ndof - 1, nrows).astype(int)
+    T, K, G = sy.assemble_blocks(pb)
+    t_asm = time.perf_counter() - t0
     t0 = time.perf_counter()
-    op.rows_TK(pb.xyz, sp, rows, pb.k[1])
-    t_rows = time.perf_counter() - t0
-    pairs_sample = 2 * nrows * T1
-    pairs_total = sum(s.verts.shape[0] ** 2 for s in pb.spaces)
-    E = sp.ndof
-    rng = np.random.default_rng(0)
-    A = rng.standard_normal((E, E)) + 1j * rng.standard_normal((E, E))
-    B = rng.standard_normal((E, E)) + 1j * rng.standard_normal((E, E))
-    x = np.ones(2 * E, dtype=np.complex128)
-    reps = 5
+    b = sy.rhs(pb, cfg["d"], cfg["p"])[:, 0]
+    x = sy.solve_direct(sy.dense_matrix(pb, T, K, G), b)
+    t_sol = time.perf_counter() - t0
+    print(json.dumps({"idx": idx, "N": int(pb.N), "t_asm": t_asm, "t_solve": t_sol,
+                      "pairs": int(sum(s.verts.shape[0] ** 2 for s in pb.spaces)), "finite": bool(np.isfinite(x).all())}))
+
+
+def cpu_baseline_clusters():
+    """The oracle, timed on the host cores on a bounded sample of the 64-cluster workload and scaled
+    to seconds per step: the three smallest clusters, one process each, run concurrently.  Scaling:
+    assembly by ordered triangle pairs, the LU solve by N^3 (sum over the 64 clusters vs over the
+    sample).  Must run before anything touches the GPU (it starts processes)."""
+    import mtf_inputs as mi
+    cl = mi.config_clusters(64, seed=0)
+    sizes = sorted(_cluster_sizes(cl))
+    sample = sizes[:CPU_SAMPLE_CLUSTERS]
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    avail = min(avail, 16)
+    per = max(1, avail // CPU_SAMPLE_CLUSTERS)
+    env = dict(os.environ, OMP_NUM_THREADS=str(per), OPENBLAS_NUM_THREADS=str(per), MKL_NUM_THREADS=str(per))
     t0 = time.perf_counter()
-    for _ in range(reps):
-        y = np.concatenate([2 * (B @ x[:E]) + (2 / pb.rho[1]) * (A @ x[E:]),
-                            -2 * pb.rho[1] * (A @ x[:E]) + 2 * (B @ x[E:])])
-    t_mv = (time.perf_counter() - t0) / reps
-    del y
-    bytes_sample = 2 * E * E
-    bytes_total = 2 * sum(int(s.ndof) ** 2 for s in pb.spaces)
-    t_iter = 2 * t_mv * bytes_total / bytes_sample
-    total = t_rows * pairs_total / pairs_sample + gpu_iters * t_iter
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    return {"value": total, "unit": "s", "cores": int(cores), "kind": "oracle",
-            "sample": (f"oracle rows of T_1,K_1 for {nrows} dofs of one sub-cube ({pairs_sample} triangle pairs, "
-                       f"{t_rows:.1f} s) and {reps} 2x2-block matvecs of the oracle's form ({t_mv * 1e3:.1f} ms each); "
-                       f"scaled by ordered pairs ({pairs_total}) and matrix bytes x {gpu_iters} GMRES iterations "
-                       "(2 matvec-equivalents each); extrapolated, not a full run")}
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(i)],
+                              stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+             for _, i, _ in sample]
+    res = []
+    for p in procs:
+        out, err = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError("oracle worker failed: " + err[-2000:])
+        res.append(json.loads(out.strip().splitlines()[-1]))
+    wall = time.perf_counter() - t0
+    pairs_s = sum(r["pairs"] for r in res)
+    pairs_all = sum(s[0] for s in sizes)
+    n3_s = sum(float(r["N"]) ** 3 for r in res)
+    n3_all = sum(float(s[2]) ** 3 for s in sizes)
+    # the sample ran concurrently on `CPU_SAMPLE_CLUSTERS * per` cores: the whole workload at the same
+    # throughput takes the sample's wall time scaled by work
+    t_asm = max(r["t_asm"] for r in res) * pairs_all / pairs_s
+    t_sol = max(r["t_solve"] for r in res) * n3_all / n3_s
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = "unknown"
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        blas = ",".join(sorted({f"{d.get('internal_api')} {d.get('version')}" for d in info if d.get("user_api") == "blas"}))
+    except Exception:
+        pass
+    return {"value": t_asm + t_sol, "unit": "s", "cores": int(per * len(res)), "kind": "oracle",
+            "sample": (f"FP64 oracle (numpy; assembly single-threaded, LU through {blas} with {per} threads) on the "
+                       f"{len(res)} smallest of the 64 clusters (N = {', '.join(str(r['N']) for r in res)}; "
+                       f"{pairs_s} ordered pairs), one process each, concurrently, {wall:.1f} s wall; assembly scaled "
+                       f"by pairs (x{pairs_all / pairs_s:.0f}), LU solve by sum N^3 (x{n3_all / n3_s:.0f}); "
+                       f"extrapolated, not a full run; CPU {model}"),
+            "sample_wall_s": wall, "assembly_s_extrapolated": t_asm, "solve_s_extrapolated": t_sol}
+
+
+# ---------------------------------------------------------------------------
+# GPU legs
+# ---------------------------------------------------------------------------
+
+def cluster_problems(mtf, cl):
+    probs = []
+    for c in cl:
+        m = c["mesh"]
+        P = mtf.Problem(0)
+        P.set_mesh(m.xyz, m.tri, m.label, m.M)
+        P.set_materials(c["k0"], c["eps_r"], c["mu_r"])
+        probs.append(P)
+    return probs
+
+
+def cube_leg(torch, mtf, mi, reps):
+    """2x2x2 cube, h = 1/16: FP64 step and the mixed step (rounded blocks, complex64 basis), with the
+    live roofline of the symmetric-read block product."""
+    cfg = mi.config_cube(2, 16)
+    m = cfg["mesh"]
+    P = mtf.Problem(0)
+    P.set_mesh(m.xyz, m.tri, m.label, m.M)
+    P.set_materials(cfg["k0"], cfg["eps_r"], cfg["mu_r"])
+    b = torch.zeros((1, P.N), dtype=torch.complex128, device="cuda")
+    x = torch.zeros_like(b)
+
+    def step64():
+        P.assemble(mtf.FP64)
+        P.rhs_plane_waves(cfg["d"], cfg["p"], b)
+        return P.solve(b, x, rtol=1e-6, preconditioner=mtf.PREC_BLOCK_TINV_GS, max_iters=4000)[0]
+
+    def stepmix(xm):
+        P.assemble(mtf.FP64)
+        P.assemble(mtf.FP32_MIXED, flags=mtf.ASSEMBLE_ROUND_FP64)
+        P.rhs_plane_waves(cfg["d"], cfg["p"], b)
+        return P.solve(b, xm, rtol=1e-6, precision=mtf.FP32_MIXED, preconditioner=mtf.PREC_BLOCK_TINV_GS,
+                       max_iters=4000, basis_c64=True)[0]
+
+    out = {}
+    for name, fn in (("fp64", step64), ("mixed_rounded_c64_basis", None)):
+        ts = []
+        for r in range(reps + 1):
+            xm = torch.zeros_like(x)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = step64() if fn else stepmix(xm)
+            torch.cuda.synchronize()
+            if r > 0:
+                ts.append(time.perf_counter() - t0)
+        e = {"s_per_solve": float(np.median(ts)), "iterations": st.iterations, "rel_residual_fp64": st.rel_residual,
+             "converged": st.converged}
+        if not fn:
+            e["rel_diff_vs_fp64_solution"] = (torch.linalg.vector_norm(xm - x) / torch.linalg.vector_norm(x)).item()
+        out[name] = e
+    P.assemble(mtf.FP64)
+    xr = torch.randn((1, P.N), dtype=torch.complex128, device="cuda")
+    yr = torch.zeros_like(xr)
+    P.matvec(xr, yr)
+    t_mv, t_mv_total = P.time_matvec(xr, yr, reps=20)
+    E64 = P.E.astype(np.int64)
+    mat_bytes = 2 * 16 * int(np.sum(E64 * (E64 + 1) // 2))
+    achieved = mat_bytes / t_mv / 1e9
+    out["workload"] = ("unit cube 2x2x2 sub-cubes, structured skeleton h=1/16, eps_r~U[1,4] seed 0, k0=2pi, "
+                       "one plane wave, N=27648")
+    out["roofline_block_product"] = {"bound": "hbm", "kernel": "k_mv_sym<double>", "achieved": achieved,
+                                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                                     "traffic": mv_traffic(16), "bytes_per_launch": mat_bytes,
+                                     "avg_launch_s": t_mv, "whole_product_s": t_mv_total}
+    P.close()
+    return out
 
 
 def main():
     args = parse()
+    if args.cpu_worker is not None:
+        cpu_worker(args.cpu_worker)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    cpu = None
+    if not args.no_cpu_baseline and args.nclusters == 64:
+        cpu = cpu_baseline_clusters()          # before anything touches the GPU
+
     import torch
     import mtf_inputs as mi
     import paper_2502_10907_amd as mtf
 
-    cfg = mi.config_cube(2, args.h_inv)
-    m = cfg["mesh"]
-    dev = torch.device("cuda:0")
-    P = mtf.Problem(0)
-    P.set_mesh(m.xyz, m.tri, m.label, m.M)
-    P.set_materials(cfg["k0"], cfg["eps_r"], cfg["mu_r"])
-    N = P.N
-    b = torch.zeros((1, N), dtype=torch.complex128, device=dev)
-    x = torch.zeros((1, N), dtype=torch.complex128, device=dev)
+    cl = mi.config_clusters(args.nclusters, seed=0)
+    probs = cluster_problems(mtf, cl)
+    B = mtf.Batch(probs)
+    bs = [torch.zeros((1, P.N), dtype=torch.complex128, device="cuda") for P in probs]
+    xs = [torch.zeros_like(b) for b in bs]
+
+    launch_s = []          # persistent-launch and touching-pair device times of each step (HIP events)
 
     def step():
-        P.assemble(mtf.FP64)
-        P.rhs_plane_waves(cfg["d"], cfg["p"], b)
-        return P.solve(b, x, rtol=1e-6, preconditioner=args.pc, max_iters=4000)[0]
+        grid, _ = B.assemble(mtf.FP64)
+        launch_s.append(B.assembly_stats()[1])
+        for P, c, b in zip(probs, cl, bs):
+            P.rhs_plane_waves(c["d"], c["p"], b)
+        return grid, B.solve(bs, xs, rtol=1e-6, precision=mtf.FP64, preconditioner=mtf.PREC_BLOCK_TINV_GS)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    launch_s.clear()
     t0 = time.perf_counter()
     stats = [step() for _ in range(args.steps)]
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
-    st = stats[-1]
-    counts, t_asm = P.assembly_stats()
+    grid, st = stats[-1]
+    counts, _, (variant, _) = B.assembly_stats()
+    tx, ty, occ = mtf.tile_variant(variant)
+    t_tiles = float(np.mean([a for a, _ in launch_s]))
+    t_touch = float(np.mean([b for _, b in launch_s]))
+    its = [s.iterations for s in st]
+    flops = FLOP_PER_SEPARATED_PAIR * float(counts[0])
+    achieved = flops / t_tiles / 1e12
+    tri = int(sum(c["mesh"].nt for c in cl))
+    Ns = [P.N for P in probs]
+    fp64 = {"iterations_mean": float(np.mean(its)), "iterations_max": int(max(its)),
+            "all_converged": bool(all(s.converged for s in st)),
+            "rel_residual_fp64_max": float(max(s.rel_residual for s in st)),
+            "t_precond_build_s": float(st[0].t_precond_s), "assembly_persistent_s": t_tiles,
+            "assembly_touching_s": t_touch, "persistent_grid": int(grid),
+            "tile": {"variant": int(variant), "test_triangles": tx, "trial_triangles": ty, "min_waves_per_simd": occ},
+            "autotuner_trials": [l for l in mtf.tuning_log().splitlines() if "persistent" in l]}
+    B.close()
+    for P in probs:
+        P.close()
+    del probs, B
 
-    # live roofline of the symmetric-read block matvec kernel (the upper triangles of the FP64 T_i,
-    # K_i streamed once per product): HIP events around each launch, recorded by the library on
-    # its stream
-    xr = torch.randn((1, N), dtype=torch.complex128, device=dev)
-    yr = torch.zeros_like(xr)
-    P.matvec(xr, yr)
-    t_mv, t_mv_total = P.time_matvec(xr, yr, reps=args.matvec_reps)
-    E64 = P.E.astype(np.int64)
-    mat_bytes = 2 * 16 * int(np.sum(E64 * (E64 + 1) // 2))
-    full_bytes = 2 * 16 * int(np.sum(E64 ** 2))
-    achieved = mat_bytes / t_mv / 1e9
-    traffic = mv_traffic(args.h_inv)
-
-    # mixed path: complex64 blocks (FP32 quadrature, or the FP64 blocks rounded) and relaxed
-    # products inside GMRES, FP64 residuals outside, optionally with the Krylov basis stored in
-    # complex64; the whole step timed like the FP64 one
     mixed = None
     if not args.no_mixed:
-        mixed = {}
-        for name, flags, c64 in (("fp32_quadrature", 0, False), ("rounded_fp64", mtf.ASSEMBLE_ROUND_FP64, False),
-                                 ("rounded_fp64_c64_basis", mtf.ASSEMBLE_ROUND_FP64, True)):
-            runs = []
-            for _ in range(2):
-                torch.cuda.synchronize()
-                tm0 = time.perf_counter()
-                P.assemble(mtf.FP64)
-                P.assemble(mtf.FP32_MIXED, flags=flags)
-                P.rhs_plane_waves(cfg["d"], cfg["p"], b)
-                xm = torch.zeros_like(x)
-                sm = P.solve(b, xm, rtol=1e-6, precision=mtf.FP32_MIXED, preconditioner=args.pc, max_iters=4000,
-                             basis_c64=c64)[0]
-                torch.cuda.synchronize()
-                runs.append(time.perf_counter() - tm0)
-            diff = (torch.linalg.vector_norm(xm - x) / torch.linalg.vector_norm(x)).item()
-            mixed[name] = {"s_per_solve": runs[-1], "iterations": sm.iterations, "refinements": sm.refinements,
-                           "rel_residual_fp64": sm.rel_residual, "rel_diff_vs_fp64_solution": diff,
-                           "converged": sm.converged}
+        probs = cluster_problems(mtf, cl)
+        B = mtf.Batch(probs)
+        ts = []
+        for r in range(3):
+            torch.cuda.synchronize()
+            tm = time.perf_counter()
+            B.assemble(mtf.FP32_MIXED)
+            for P, c, b in zip(probs, cl, bs):
+                P.rhs_plane_waves(c["d"], c["p"], b)
+            xm = [torch.zeros_like(b) for b in bs]
+            sm = B.solve(bs, xm, rtol=1e-6, precision=mtf.FP32_MIXED, preconditioner=mtf.PREC_BLOCK_TINV_GS)
+            torch.cuda.synchronize()
+            if r > 0:
+                ts.append(time.perf_counter() - tm)
+        diff = max((torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item() for a, b in zip(xm, xs))
+        _, (mt_tiles, mt_touch), _ = B.assembly_stats()
+        mixed = {"s_per_step": float(np.median(ts)), "precision": "complex64 blocks (FP32 separated pairs, FP64 "
+                 "touching pairs), relaxed complex64 products, FP64 residuals and refinement",
+                 "iterations_mean": float(np.mean([s.iterations for s in sm])),
+                 "refinements_max": int(max(s.refinements for s in sm)),
+                 "all_converged": bool(all(s.converged for s in sm)),
+                 "rel_residual_fp64_max": float(max(s.rel_residual for s in sm)),
+                 "max_rel_diff_vs_fp64_solution": diff, "assembly_persistent_s": mt_tiles,
+                 "assembly_touching_s": mt_touch}
+        B.close()
+        for P in probs:
+            P.close()
+        del probs, B
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(cfg, st.iterations)
+    cube = None if args.no_cube else cube_leg(torch, mtf, mi, 3)
 
     out = {
         "metric": "MTF solve s to GMRES 1e-6 (assembly+matvec), mixed/batched vs FP64; % peak",
         "value": dt, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "c128", "data": "synthetic",
-        "config": {"workload": f"unit cube 2x2x2 sub-cubes, structured skeleton h=1/{args.h_inv}, eps_r~U[1,4] seed 0, "
-                               "k0=2pi, one plane wave; FP64 assembly + right block T^-1 preconditioner "
-                               f"({'Gauss-Seidel' if args.pc == 2 else 'Jacobi'}) + full GMRES",
-                   "triangles": int(m.nt), "N": int(N), "pairs_separated": int(counts[0]),
+        "config": {"workload": (f"{args.nclusters} clusters of 1-8 disjoint dielectric spheres (SplitMix64 seed 0; "
+                                "Fibonacci-hull meshes of 200-2000 triangles, radii U[0.3,1], eps_r~U[1.5,4], k0=1.5), "
+                                "one plane wave each; FP64 assembly (separated pairs in one persistent launch) + "
+                                "block T^-1 preconditioners built together (Gauss-Seidel) + flexible GMRES per cluster"),
+                   "clusters": args.nclusters, "spheres": int(sum(c["mesh"].M for c in cl)), "triangles": tri,
+                   "N_total": int(sum(Ns)), "N_max": int(max(Ns)), "pairs_separated": int(counts[0]),
                    "pairs_touching": int(counts[1:].sum())},
-        "gmres": {"iterations": st.iterations, "rel_residual_fp64": st.rel_residual, "converged": st.converged,
-                  "t_precond_s": st.t_precond_s, "t_solve_s": st.t_solve_s,
-                  "reorthogonalized_steps": st.reorthogonalizations},
-        "assembly_s": t_asm,
-        "roofline": {"bound": "hbm", "kernel": "k_mv_sym<double> (block matvec, upper triangles of T_i, K_i FP64)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "bytes_per_launch": mat_bytes, "avg_launch_s": t_mv,
-                     "whole_product_s": t_mv_total,
-                     "full_operator_bytes": full_bytes, "full_operator_equiv_GBps": full_bytes / t_mv_total / 1e9},
-        "mixed_fp32": mixed,
+        "gmres": fp64,
+        "roofline": {"bound": "alu", "kernel": "k_assemble_persistent<double> (separated pairs of all clusters)",
+                     "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+                     "flop_per_launch": flops, "flop_per_separated_pair": FLOP_PER_SEPARATED_PAIR,
+                     "avg_launch_s": t_tiles},
+        "mixed_batched": mixed,
+        "cube_2x2x2_h16": cube,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -117,7 +117,9 @@ int mtf_set_mesh(mtf_problem p, int64_t nv, const double* xyz, int64_t nt,
                  const int32_t* tri, const int32_t* label, int32_t M);
 
 /* Materials (eq. relativeParameters): eps_r[M+1], mu_r[M+1] > 0, k0 > 0.
- * k_i = k0 sqrt(eps_r,i mu_r,i), rho_i = sqrt(eps_r,i / mu_r,i). */
+ * k_i = k0 sqrt(eps_r,i mu_r,i), rho_i = sqrt(eps_r,i / mu_r,i).  MTF_ERR_UNSUPPORTED when some
+ * k_i times the diameter of the mesh's bounding box reaches 1e6 (over 1e5 wavelengths across: the
+ * range of the FP64 phase reduction of the assembly kernels). */
 int mtf_set_materials(mtf_problem p, double k0, const double* eps_r, const double* mu_r);
 
 /* Sizes: N (total unknowns) and E[M+1] (dim RWG_i); either may be NULL. */
@@ -135,6 +137,17 @@ typedef struct {
     int32_t singular_order;  /* Gauss-Legendre points per coordinate, 1..8 (default 4) */
     int32_t flags;           /* 0, or MTF_ASSEMBLE_ROUND_FP64                          */
 } mtf_assembly_opts;
+
+/* Launch configuration of the separated-pair assembly.  By default it is autotuned: on the first
+ * assembly of a shape class (floor(log2) of the mean number of triangles per subdomain) in a
+ * precision, each tile variant is timed once and the fastest kept for the process (and, for
+ * mtf_batch_assemble, then the number of persistent workgroups per CU); with the environment
+ * variable MTF_TUNE_CACHE naming a file the choices are also read from and appended to it.
+ * flags |= MTF_ASSEMBLE_TILE(v) forces variant v instead (0 <= v < MTF_TILE_VARIANTS; see
+ * mtf_tile_variant).  Every variant computes the same sums; only the order of the atomic
+ * additions differs. */
+#define MTF_TILE_VARIANTS 5
+#define MTF_ASSEMBLE_TILE(v) ((((v) + 1) & 0xff) << 8)
 
 /* With MTF_FP32_MIXED: the complex64 blocks are the FP64 blocks (assembled before) rounded to
  * complex64 instead of a new quadrature in FP32; rounding keeps them within one complex64 ulp of
@@ -283,6 +296,17 @@ int mtf_apply_preconditioner(mtf_problem p, int32_t preconditioner, int32_t nrhs
 int mtf_far_field(mtf_problem p, int32_t nrhs, const void* x_dev, int64_t ld, int32_t ndir,
                   const double* dir, double* out);
 
+/* Tile variant v: tiles of tx test x ty trial triangles (one pair per thread, tx * ty threads per
+ * workgroup), compiled for at least `occupancy` resident waves per SIMD.  Any output may be NULL. */
+int mtf_tile_variant(int32_t v, int32_t* tx, int32_t* ty, int32_t* occupancy);
+
+/* Tile variant used by the last mtf_assemble of p (-1 before the first). */
+int mtf_assembly_variant(mtf_problem p, int32_t* variant);
+
+/* The autotuner's trials of this process, one line each (key, variant, workgroups per CU for batch
+ * launches, seconds), as a NUL-terminated string truncated to cap bytes. */
+int mtf_tuning_log(char* buf, int64_t cap);
+
 /* Statistics of the last mtf_assemble: pair counts by class
  * (counts[0] separated, [1] vertex, [2] edge, [3] coincident, summed over
  * subdomains, ordered pairs) and the device time of the assembly kernels in
@@ -300,22 +324,45 @@ typedef struct mtf_batch_s* mtf_batch;
 int mtf_batch_create(mtf_batch* out, int32_t n, const mtf_problem* problems);
 int mtf_batch_destroy(mtf_batch b);
 
-/* Assembles T_i and K_i of every problem of the batch in ONE persistent launch: workgroups
- * claim work items (16 x 16 tiles of separated triangle pairs and chunks of four touching
- * pairs, across all problems, largest problems first) from an atomic counter until the list is
- * exhausted.  On the first call per precision an autotuner times the launch with 1, 2, 4 and 8
- * persistent workgroups per compute unit and keeps the fastest (grid_used, may be NULL);
- * seconds (may be NULL) receives the device time of the kept launch.  Synchronises. */
+/* Assembles T_i and K_i of every problem of the batch: the separated triangle pairs of all
+ * problems in ONE persistent launch (workgroups claim 16 x 16 tiles of separated pairs, across all
+ * problems, largest problems first, from an atomic counter until the list is exhausted), then the
+ * touching pairs (Sauter-Schwab, FP64) of each problem.  The launch is autotuned per shape class
+ * and precision (see MTF_ASSEMBLE_TILE): every tile variant at 4 workgroups per CU, then 1, 2 and 8
+ * workgroups per CU for the fastest, each timed on a persistent launch over every eighth tile
+ * (grid_used, may be NULL, receives the workgroups launched); seconds (may be NULL) receives the
+ * device time of the whole assembly.  Synchronises. */
 int mtf_batch_assemble(mtf_batch b, const mtf_assembly_opts* opts, int32_t* grid_used, double* seconds);
 
+/* Statistics of the last mtf_batch_assemble: ordered pair counts by class summed over the problems
+ * (counts[4] as in mtf_assembly_stats; may be NULL), device times in seconds (seconds[2], may be
+ * NULL): [0] the persistent launch over the separated pairs, [1] the touching pairs after it (HIP
+ * events on the batch's stream), and the launch configuration (config[2], may be NULL): tile
+ * variant and persistent workgroups.  Synchronises. */
+int mtf_batch_assembly_stats(mtf_batch b, int64_t* counts, double* seconds, int32_t* config);
+
+/* The T_i^-1 preconditioner blocks (as defined for mtf_solve) of every problem of the batch, built
+ * together: every diagonal block (of each T_i, or of each connected component of Gamma_i) of every
+ * problem is padded with the identity to an order rounded up to 128 and the blocks of equal padded
+ * order are inverted as one batch (blocked Gauss-Jordan on FP32 matrix cores), instead of one
+ * problem after another.  From the FP32 blocks where assembled, else from the FP64 ones.  flags:
+ * 0 or MTF_SOLVE_PC_FULL.  The blocks stay with their problems (used by mtf_solve,
+ * mtf_apply_preconditioner and mtf_batch_solve) until a new assembly of their source precision.
+ * Synchronises. */
+int mtf_batch_build_preconditioner(mtf_batch b, int32_t flags);
+
 /* mtf_solve of problem i on b_dev[i] -> x_dev[i] (one right-hand side each, ld = N_i) with
- * common options, problem after problem; stats[n] may be NULL.  A problem without FP64 blocks
- * gets them assembled (default options) for its residual checks and released after its solve;
- * its preconditioner blocks and GMRES work buffers are released too when they did not exist before, so
- * the batch needs device memory for one problem's solve at a time beyond the blocks it holds.
- * max_iters 0 here means cycles of at most 1,000 Arnoldi steps (not the free-memory length of
- * mtf_solve): a batch is many small solves, and Krylov storage sized from free memory would be
- * allocated and released for each of them. */
+ * common options, problem after problem; stats[n] may be NULL.  The preconditioner blocks of the
+ * problems lacking them are first built together (mtf_batch_build_preconditioner); stats[0]
+ * receives that build's time in t_precond_s.  A problem without FP64 blocks gets them assembled
+ * (default options) for its residual checks and released after its solve.  Preconditioner blocks
+ * that a problem did not hold before the call are released after its solve (also when the call
+ * fails).  A problem without GMRES work buffers of its own uses the batch's, allocated for the
+ * largest problem met and kept until mtf_batch_destroy.  Device memory needed beyond the assembled
+ * blocks: the preconditioner blocks of every problem (half the bytes of the complex64 T_i, K_i),
+ * one problem's FP64 blocks at a time and the batch's GMRES buffers.  max_iters 0 here means cycles
+ * of at most 1,000 Arnoldi steps (not the free-memory length of mtf_solve): a batch is many small
+ * solves, whose Krylov storage would otherwise be sized from free memory. */
 int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, const mtf_solve_opts* opts,
                     mtf_solve_stats* stats);
 
@@ -328,17 +375,17 @@ int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, c
 
 /* POD basis of nsnap solution snapshots U_dev (complex128 [nsnap][ldu], N rows
  * each): the r leading left singular vectors Phi_dev (complex128 [r][ldphi])
- * and singular values sv[r] (host), computed in complex64 from the snapshot
- * Gram matrix U^H U by subspace iteration with Rayleigh-Ritz.  r <= nsnap,
- * r <= 256.  Synchronises. */
+ * and singular values sv[r] (host), computed in complex128 from the snapshot
+ * Gram matrix U^H U (FP64 GEMM on the device) by subspace iteration with
+ * Rayleigh-Ritz, Phi = U Z Lambda^-1/2.  r <= nsnap, r <= 256.  Synchronises. */
 int mtf_pod_build(mtf_problem p, int32_t nsnap, const void* U_dev, int64_t ldu, int32_t r,
                   void* Phi_dev, int64_t ldphi, double* sv);
 
-/* C = Phi^H X for n vectors X_dev (complex128 [n][ldx]) -> C_dev (complex128 [n][r]). */
+/* C = Phi^H X for n vectors X_dev (complex128 [n][ldx]) -> C_dev (complex128 [n][r]); FP64. */
 int mtf_pod_project(mtf_problem p, int32_t r, const void* Phi_dev, int64_t ldphi, int32_t n,
                     const void* X_dev, int64_t ldx, void* C_dev);
 
-/* X = Phi C for n coefficient vectors C_dev (complex128 [n][r]) -> X_dev (complex128 [n][ldx]). */
+/* X = Phi C for n coefficient vectors C_dev (complex128 [n][r]) -> X_dev (complex128 [n][ldx]); FP64. */
 int mtf_pod_expand(mtf_problem p, int32_t r, const void* Phi_dev, int64_t ldphi, int32_t n,
                    const void* C_dev, void* X_dev, int64_t ldx);
 

@@ -29,7 +29,7 @@ __all__ = [
     "SplitMix64", "Mesh", "icosphere", "box_skeleton", "cube_partition",
     "fibonacci_directions", "polarisations", "sphere_cluster",
     "config_sphere", "config_cube", "config_cube_multi_rhs", "config_clusters",
-    "warm_start_samples",
+    "warm_start_samples", "split_sphere", "concentric_cuboids", "config_paper_sphere", "config_paper_cuboids",
 ]
 
 _MASK64 = (1 << 64) - 1
@@ -298,8 +298,141 @@ def sphere_cluster(rng: SplitMix64, tmin=200, tmax=2000, rmin=0.3, rmax=1.0,
 
 
 # ---------------------------------------------------------------------------
+# the paper's own geometries (Section 5): split sphere and concentric cuboids
+# ---------------------------------------------------------------------------
+
+def _ring_points(j: int, n: int):
+    """Angles of ring j of a ring-structured disc with n rings: 6j points (one at j = 0)."""
+    if j == 0:
+        return np.zeros(1)
+    return 2.0 * math.pi * np.arange(6 * j) / (6 * j)
+
+
+def _strip(a_ids, a_ang, b_ids, b_ang):
+    """Triangles between two closed rings of points (ids with increasing angles in [0, 2 pi)),
+    advancing along whichever ring's next point comes first in angle."""
+    na, nb = len(a_ids), len(b_ids)
+    if na == 1:
+        return [[a_ids[0], b_ids[k], b_ids[(k + 1) % nb]] for k in range(nb)]
+    tris = []
+    i = j = 0
+    while i < na or j < nb:
+        ai, bj = a_ang[i % na] + (2 * math.pi if i >= na else 0.0), b_ang[j % nb] + (2 * math.pi if j >= nb else 0.0)
+        an = a_ang[(i + 1) % na] + (2 * math.pi if i + 1 >= na else 0.0)
+        bn = b_ang[(j + 1) % nb] + (2 * math.pi if j + 1 >= nb else 0.0)
+        if j < nb and (i >= na or bn <= an):
+            tris.append([a_ids[i % na], b_ids[j % nb], b_ids[(j + 1) % nb]])
+            j += 1
+        else:
+            tris.append([a_ids[i % na], b_ids[j % nb], a_ids[(i + 1) % na]])
+            i += 1
+    return tris
+
+
+def split_sphere(n: int, halves: bool = True) -> Mesh:
+    """Unit sphere, ring-structured (n rings per hemisphere, 6j points on ring j, 6 n^2 triangles per
+    hemisphere).  With ``halves`` it is split by the plane x = 0 into Omega_1 (x < 0) and Omega_2
+    (x > 0) (Section 5.2's two half-spheres, read with x < 0 / x > 0): the skeleton is the two
+    hemispheres (labels (0,1), (0,2)) and the disc at x = 0 (labels (1,2)), which share the vertices
+    of the equator.  Without, the same sphere is one subdomain (labels (0,1)).  Normals point from
+    label[0] to label[1]."""
+    xyz, tris, labels = [], [], []
+
+    def add(p):
+        xyz.append(p)
+        return len(xyz) - 1
+
+    eq_ang = _ring_points(n, n)
+    eq = [add((0.0, math.cos(a), math.sin(a))) for a in eq_ang]
+    surfaces = []
+    for sgn in (-1.0, 1.0):                          # hemisphere x < 0, then x > 0
+        rings = []
+        for j in range(n):
+            psi = 0.5 * math.pi * j / n
+            ang = _ring_points(j, n)
+            rings.append(([add((sgn * math.cos(psi), math.sin(psi) * math.cos(a), math.sin(psi) * math.sin(a)))
+                           for a in ang], ang))
+        rings.append((eq, eq_ang))
+        t = []
+        for j in range(n):
+            t += _strip(rings[j][0], rings[j][1], rings[j + 1][0], rings[j + 1][1])
+        surfaces.append((sgn, t))
+    if halves:
+        rings = []
+        for j in range(n):
+            ang = _ring_points(j, n)
+            rings.append(([add((0.0, (j / n) * math.cos(a), (j / n) * math.sin(a))) for a in ang], ang))
+        rings.append((eq, eq_ang))
+        t = []
+        for j in range(n):
+            t += _strip(rings[j][0], rings[j][1], rings[j + 1][0], rings[j + 1][1])
+        surfaces.append((0.0, t))
+    P = np.array(xyz)
+    for sgn, t in surfaces:
+        for tri in t:
+            a, b, c = P[tri[0]], P[tri[1]], P[tri[2]]
+            nrm = np.cross(b - a, c - a)
+            cen = (a + b + c) / 3.0
+            if sgn == 0.0:                            # interface disc: normal from Omega_1 to Omega_2 (+x)
+                lab, want = (1, 2), np.array([1.0, 0.0, 0.0])
+            else:                                     # hemisphere: normal from Omega_0 into the ball
+                lab = (0, 1 if (sgn < 0 or not halves) else 2)
+                want = -cen
+            tris.append(tri if nrm @ want > 0 else [tri[0], tri[2], tri[1]])
+            labels.append(lab)
+    return Mesh(xyz=P, tri=np.array(tris, dtype=np.int32), label=np.array(labels, dtype=np.int32),
+                M=2 if halves else 1, meta={"kind": "split_sphere", "rings": n, "halves": halves})
+
+
+# subdomain boundaries of the concentric cuboids, in grid cells from the centre line (half-width 10
+# cells = 1.7); the paper gives its radius vectors only in a figure, so these are chosen: r_1 = 0.51
+# for M = 2 (the paper's 0.5 on this grid), then rings of 1-3 cells out to 1.7
+CUBOID_RINGS = {1: [10], 2: [3, 10], 3: [3, 6, 10], 4: [3, 5, 7, 10], 5: [2, 4, 6, 8, 10],
+                6: [2, 3, 5, 7, 8, 10]}
+
+
+def concentric_cuboids(M: int, cells_xy: int = 20, cells_z: int = 6) -> Mesh:
+    """The scatterer (-1.7, 1.7)^2 x (0, 1) split into M concentric cuboids (Section 5.4, read as
+    nested square annuli extruded in z: subdomain i holds the points with r_{i-1} < max(|x|, |y|) <
+    r_i, r_0 = 0, r_M = 1.7; the printed sets l_i x l_i would be four corner blocks).  Structured
+    skeleton: cells_xy x cells_xy cells across, cells_z in height."""
+    half = cells_xy // 2
+    rings = [round(w * half / 10) for w in CUBOID_RINGS[M]]
+    ids = np.zeros((1, cells_xy, cells_xy), dtype=np.int64)
+    for iy in range(cells_xy):
+        for ix in range(cells_xy):
+            c = max(abs(ix + 0.5 - half), abs(iy + 0.5 - half)) + 0.5      # ring of cells from the centre
+            ids[0, iy, ix] = 1 + next(k for k, w in enumerate(rings) if c <= w)
+    m = box_skeleton((cells_xy, cells_xy, 1), (1, 1, cells_z), size=(3.4, 3.4, 1.0), origin=(-1.7, -1.7, 0.0), ids=ids)
+    m.meta.update({"kind": "concentric_cuboids", "rings_cells": rings})
+    return m
+
+
+# ---------------------------------------------------------------------------
 # named workloads
 # ---------------------------------------------------------------------------
+
+def config_paper_sphere(case: str = "A", halves: bool = True, points_per_wavelength: float = 10.0):
+    """Section 5.2: unit sphere, Cases A (k0 = 3, eps_r = 2.1) and B (k0 = 5, eps_r = 1.9), mu_r = 1,
+    incidence d = (1, 0, 0), p = (0, 0, 1); MTF(2) (two half-spheres, same material) or MTF(1).  The
+    ring count gives about `points_per_wavelength` points per interior wavelength on the equator."""
+    k0, eps = {"A": (3.0, 2.1), "B": (5.0, 1.9)}[case]
+    lam = 2 * math.pi / (k0 * math.sqrt(eps))
+    n = max(2, int(round(2 * math.pi / lam * points_per_wavelength / 6)))
+    mesh = split_sphere(n, halves)
+    return dict(mesh=mesh, k0=k0, eps_r=np.array([1.0] + [eps] * mesh.M), mu_r=np.ones(mesh.M + 1),
+                d=np.array([[1.0, 0.0, 0.0]]), p=np.array([[0.0, 0.0, 1.0]], dtype=np.complex128))
+
+
+def config_paper_cuboids(M: int, cells_xy: int = 20, cells_z: int = 6):
+    """Section 5.4: concentric cuboids, all M subdomains with the Case A material, read as k_i = 4.3
+    (eps_r = (4.3/3)^2; the text's eps_r = 2 would give k_i = 4.24), k0 = 3, mu_r = 1, d = (1, 0, 0),
+    p = (0, 0, 1) (the incidence of Section 5.2)."""
+    mesh = concentric_cuboids(M, cells_xy, cells_z)
+    eps = (4.3 / 3.0) ** 2
+    return dict(mesh=mesh, k0=3.0, eps_r=np.array([1.0] + [eps] * M), mu_r=np.ones(M + 1),
+                d=np.array([[1.0, 0.0, 0.0]]), p=np.array([[0.0, 0.0, 1.0]], dtype=np.complex128))
+
 
 def config_sphere(subdivisions: int = 2):
     """Dielectric unit sphere (eps_r = 2, mu_r = 1) in vacuum, k0 = 1, x-polarised wave along +z."""

@@ -96,6 +96,11 @@ _SIGS = {
     "mtf_batch_create": (C.c_int, [C.POINTER(_P), C.c_int32, C.POINTER(_P)]),
     "mtf_batch_destroy": (C.c_int, [_P]),
     "mtf_batch_assemble": (C.c_int, [_P, C.POINTER(AssemblyOpts), _ip, _dp]),
+    "mtf_batch_build_preconditioner": (C.c_int, [_P, C.c_int32]),
+    "mtf_batch_assembly_stats": (C.c_int, [_P, _lp, _dp, _ip]),
+    "mtf_tile_variant": (C.c_int, [C.c_int32, _ip, _ip, _ip]),
+    "mtf_assembly_variant": (C.c_int, [_P, _ip]),
+    "mtf_tuning_log": (C.c_int, [C.c_char_p, C.c_int64]),
     "mtf_batch_solve": (C.c_int, [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
     "mtf_pod_build": (C.c_int, [_P, C.c_int32, _P, C.c_int64, C.c_int32, _P, C.c_int64, _dp]),
     "mtf_pod_project": (C.c_int, [_P, C.c_int32, _P, C.c_int64, C.c_int32, _P, C.c_int64, _P]),
@@ -120,6 +125,27 @@ def header_symbols() -> list[str]:
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"\b(mtf_[a-z0-9_]+)\s*\(", txt)))
+
+
+TILE_VARIANTS = 5
+
+
+def assemble_tile(v: int) -> int:
+    """Assembly flag forcing tile variant v."""
+    return ((v + 1) & 0xFF) << 8
+
+
+def tile_variant(v: int):
+    """(test triangles, trial triangles, minimum waves per SIMD) of tile variant v."""
+    a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(_lib.mtf_tile_variant(int(v), C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def tuning_log() -> str:
+    buf = C.create_string_buffer(1 << 16)
+    _check(_lib.mtf_tuning_log(buf, len(buf)))
+    return buf.value.decode()
 
 
 def last_error() -> str:
@@ -236,6 +262,11 @@ class Problem:
     def assemble(self, precision: int = FP64, singular_order: int = 4, flags: int = 0):
         o = AssemblyOpts(C.sizeof(AssemblyOpts), int(precision), int(singular_order), int(flags))
         _check(_lib.mtf_assemble(self._h, C.byref(o)))
+
+    def assembly_variant(self) -> int:
+        v = C.c_int32()
+        _check(_lib.mtf_assembly_variant(self._h, C.byref(v)))
+        return v.value
 
     def assembly_stats(self):
         counts = np.zeros(4, dtype=np.int64)
@@ -459,13 +490,27 @@ class Batch:
         except Exception:
             pass
 
-    def assemble(self, precision: int = FP64, singular_order: int = 4):
-        """Returns (persistent workgroups chosen by the autotuner, device seconds of the launch)."""
-        o = AssemblyOpts(C.sizeof(AssemblyOpts), int(precision), int(singular_order), 0)
+    def assemble(self, precision: int = FP64, singular_order: int = 4, flags: int = 0):
+        """Returns (persistent workgroups launched, device seconds of the whole assembly)."""
+        o = AssemblyOpts(C.sizeof(AssemblyOpts), int(precision), int(singular_order), int(flags))
         g = C.c_int32()
         t = C.c_double()
         _check(_lib.mtf_batch_assemble(self._h, C.byref(o), C.byref(g), C.byref(t)))
         return g.value, t.value
+
+    def assembly_stats(self):
+        """(pair counts by class [separated, vertex, edge, coincident], (persistent launch s, touching pairs s),
+        (tile variant, persistent workgroups))."""
+        counts = np.zeros(4, dtype=np.int64)
+        sec = np.zeros(2)
+        cfg = np.zeros(2, dtype=np.int32)
+        _check(_lib.mtf_batch_assembly_stats(self._h, counts.ctypes.data_as(_lp), sec.ctypes.data_as(_dp),
+                                             cfg.ctypes.data_as(_ip)))
+        return counts, (float(sec[0]), float(sec[1])), (int(cfg[0]), int(cfg[1]))
+
+    def build_preconditioner(self, pc_full: bool = False):
+        """T_i^-1 preconditioner blocks of every problem, built together."""
+        _check(_lib.mtf_batch_build_preconditioner(self._h, SOLVE_PC_FULL if pc_full else 0))
 
     def solve(self, bs, xs, rtol=1e-6, precision=FP64, preconditioner=PREC_BLOCK_TINV, max_iters=0, graph=True,
               basis_c64=False):

@@ -68,6 +68,7 @@ def main(nclusters=64, precision=1, solve=1):
         t_solve = time.perf_counter() - t0
         its = [s.iterations for s in st]
         out.update({"t_batch_solve_s": t_solve, "solve_precision": "fp32 operator + fp64 refinement" if precision else "fp64",
+                    "t_precond_build_s": st[0].t_precond_s,
                     "iterations_mean": float(np.mean(its)), "iterations_max": int(max(its)),
                     "refinements_max": int(max(s.refinements for s in st)),
                     "all_converged": all(s.converged for s in st),

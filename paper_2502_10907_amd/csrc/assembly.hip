@@ -20,6 +20,7 @@
 #include "device.h"
 
 #include <algorithm>
+#include <stdexcept>
 #include <cmath>
 #include <type_traits>
 
@@ -103,6 +104,54 @@ struct LRec {
     int32_t sg[3];
 };
 
+// sin x and cos x in FP64 for the phases k r of the kernel: the reduction of Cody & Waite
+// (Software Manual for the Elementary Functions, 1980), x = n pi/2 + t with pi/2 split into two
+// 33-bit parts and a remainder (so n * part is exact for |n| < 2^20), then the Taylor series of
+// sin t to t^15 and of cos t to t^16 on |t| <= pi/4, whose truncation error is below 7e-17 relative;
+// quadrant n mod 4 picks and signs the two.  Valid for |x| < 2^20 pi/2 (about 1.6e6): the kernel
+// phases k_i r stay below k_i times the mesh diameter, which mtf_set_materials limits to 1e6.  The
+// parts of pi/2 are its 33-bit truncation, the next 33 bits, and the rounded rest.
+__device__ inline void sincos_cw(double x, double* sp, double* cp) {
+    constexpr double kTwoOverPi = 0.6366197723675814;
+    constexpr double kP1 = 1.5707963267341256, kP2 = 6.077100506303966e-11, kP3 = 2.0222662487959506e-21;
+    const double n = rint(x * kTwoOverPi);
+    double t = fma(-n, kP1, x);
+    t = fma(-n, kP2, t);
+    t = fma(-n, kP3, t);
+    const double t2 = t * t;
+    double ps = -1.0 / 1307674368000.0;           // -1/15!
+    ps = fma(ps, t2, 1.0 / 6227020800.0);         //  1/13!
+    ps = fma(ps, t2, -1.0 / 39916800.0);          // -1/11!
+    ps = fma(ps, t2, 1.0 / 362880.0);             //  1/9!
+    ps = fma(ps, t2, -1.0 / 5040.0);              // -1/7!
+    ps = fma(ps, t2, 1.0 / 120.0);                //  1/5!
+    ps = fma(ps, t2, -1.0 / 6.0);                 // -1/3!
+    const double sn = fma(ps * t2, t, t);
+    double pc = 1.0 / 20922789888000.0;           //  1/16!
+    pc = fma(pc, t2, -1.0 / 87178291200.0);       // -1/14!
+    pc = fma(pc, t2, 1.0 / 479001600.0);          //  1/12!
+    pc = fma(pc, t2, -1.0 / 3628800.0);           // -1/10!
+    pc = fma(pc, t2, 1.0 / 40320.0);              //  1/8!
+    pc = fma(pc, t2, -1.0 / 720.0);               // -1/6!
+    pc = fma(pc, t2, 1.0 / 24.0);                 //  1/4!
+    pc = fma(pc, t2, -0.5);                       // -1/2!
+    const double cs = fma(pc, t2, 1.0);
+    const int q = (int)n & 3;
+    const double a = (q & 1) ? cs : sn, b = (q & 1) ? sn : cs;
+    *sp = (q & 2) ? -a : a;
+    *cp = ((q + 1) & 2) ? -b : b;
+}
+
+// 1/sqrt(x) in FP64 (x > 0): the hardware reciprocal square root estimate refined by two Newton
+// steps y <- y + (y/2)(1 - x y^2), each doubling the number of correct bits.
+__device__ inline double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
 template <typename R>
 __device__ inline void kernel_values(R kr, R rinv, R wr, R& Gre, R& Gim, R& gre, R& gim);
 
@@ -110,7 +159,7 @@ template <>
 __device__ inline void kernel_values<double>(double kr, double rinv, double wr, double& Gre, double& Gim,
                                              double& gre, double& gim) {
     double s, c;
-    sincos(kr, &s, &c);
+    sincos_cw(kr, &s, &c);
     double a = wr * kInv4Pi * rinv;
     Gre = c * a;
     Gim = s * a;
@@ -135,7 +184,7 @@ __device__ inline void kernel_values<float>(float kr, float rinv, float wr, floa
 template <typename R>
 __device__ inline R rsqrt_r(R x);
 template <>
-__device__ inline double rsqrt_r<double>(double x) { return 1.0 / sqrt(x); }
+__device__ inline double rsqrt_r<double>(double x) { return rsqrt_nr(x); }
 template <>
 __device__ inline float rsqrt_r<float>(float x) { return __frsqrt_rn(x); }
 
@@ -221,41 +270,64 @@ struct GlobalSink {
     }
 };
 
-// Local accumulator of a 16 x 16 tile of separated pairs: slot 3 t + a is local dof a of tile
-// triangle t (48 per side); a dof that appears in several slots is kept in the first of them, so
+// Local accumulator of a tile of separated pairs: slot 3 t + a is local dof a of tile
+// triangle t (3 TX test and 3 TY trial slots); a dof that appears in several slots is kept in the first of them, so
 // the tile's pairs add into LDS and only its distinct (test dof, trial dof) entries reach T and K.
-constexpr int kTileSlots = 48;
+// In FP64 it holds one operator at a time: the pairs add their T entries, the tile scatters them,
+// then the same for K (the moments stay in registers in between); half the LDS of holding both
+// lets three workgroups share a CU instead of one.  In FP32 both operators are held at once (the
+// moments held across the extra barriers would cost more registers than the LDS saved).
 template <typename R>
-struct TileAcc {
-    R v[2][kTileSlots][kTileSlots][2];   // [T, K][test slot][trial slot][re, im]
-    int first[2][kTileSlots];            // [test, trial]: first slot of the same dof, -1 when unused
+constexpr int kAccOps = std::is_same<R, double>::value ? 1 : 2;
+
+// Shape of a tile of separated pairs: TX test triangles x TY trial triangles, one pair per
+// thread, and the minimum number of resident waves per SIMD asked of the compiler (OCC; 1 leaves the
+// register budget to the compiler).  The variants are the autotuner's choices (tile_variant()).
+template <int TX_, int TY_, int OCC_>
+struct TileShape {
+    static constexpr int TX = TX_, TY = TY_, NT = TX_ * TY_, OCC = OCC_;
+    static constexpr int SX = 3 * TX_, SY = 3 * TY_;     // accumulator slots per side
 };
 
-template <typename R>
+template <typename R, typename S>
+struct TileAcc {
+    R v[kAccOps<R>][S::SX][S::SY][2];    // [operator][test slot][trial slot][re, im]
+    int first_x[S::SX], first_y[S::SY];  // first slot of the same dof, -1 when unused
+};
+
+// WHICH 0: T into v[0]; 1: K into v[0]; 2: T into v[0] and K into v[1]
+template <typename R, typename S, int WHICH>
 struct LdsSink {
-    TileAcc<R>* acc;
+    TileAcc<R, S>* acc;
     int sx, sy;                          // 3 * tile triangle of the pair, test and trial side
     __device__ void operator()(int a, int b, R Tre, R Tim, R Kre, R Kim) const {
-        const int x = acc->first[0][sx + a], y = acc->first[1][sy + b];
-        atomicAdd(&acc->v[0][x][y][0], Tre);
-        atomicAdd(&acc->v[0][x][y][1], Tim);
-        atomicAdd(&acc->v[1][x][y][0], Kre);
-        atomicAdd(&acc->v[1][x][y][1], Kim);
+        const int x = acc->first_x[sx + a], y = acc->first_y[sy + b];
+        if constexpr (WHICH == 2) {
+            atomicAdd(&acc->v[0][x][y][0], Tre);
+            atomicAdd(&acc->v[0][x][y][1], Tim);
+            atomicAdd(&acc->v[kAccOps<R> - 1][x][y][0], Kre);
+            atomicAdd(&acc->v[kAccOps<R> - 1][x][y][1], Kim);
+        } else {
+            atomicAdd(&acc->v[0][x][y][0], WHICH == 0 ? Tre : Kre);
+            atomicAdd(&acc->v[0][x][y][1], WHICH == 0 ? Tim : Kim);
+        }
     }
 };
 
-// One 16 x 16 tile of separated pairs; all 256 threads of the workgroup must call it (it holds
-// workgroup barriers); pairs outside Gamma_i or touching are skipped by predication.  The pairs
-// add into the tile's LDS accumulator, which is then scattered into T and K.
-template <typename R>
+// One TX x TY tile of separated pairs (tile = (subdomain, first test triangle, first trial
+// triangle)); all S::NT threads of the workgroup must call it (it holds workgroup barriers); pairs
+// outside Gamma_i or touching are skipped by predication.  The pairs add into the tile's LDS
+// accumulator, which is then scattered into T and K.
+template <typename R, typename S>
 __device__ __attribute__((always_inline)) inline void regular_tile(const int4 tile, const DomDesc* __restrict__ doms, const TriGeom* __restrict__ geom,
                                     const int32_t* __restrict__ verts, const int32_t* __restrict__ tdof,
                                     const int8_t* __restrict__ tsign, R* __restrict__ T, R* __restrict__ K,
-                                    LRec<R>* rec, TileAcc<R>* acc) {
+                                    LRec<R>* rec, TileAcc<R, S>* acc) {
+    constexpr int TX = S::TX, TY = S::TY, NT = S::NT, SX = S::SX, SY = S::SY;
     const DomDesc dd = doms[tile.x];
     const int tid = threadIdx.x;
-    if (tid < 32) {
-        const int lt = (tid < 16) ? tile.y + tid : tile.z + (tid - 16);
+    if (tid < TX + TY) {
+        const int lt = (tid < TX) ? tile.y + tid : tile.z + (tid - TX);
         if (lt < dd.T) {
             const int64_t r = dd.rec0 + lt;
             const TriGeom& g = geom[r];
@@ -274,40 +346,42 @@ __device__ __attribute__((always_inline)) inline void regular_tile(const int4 ti
     }
     {
         R* z = &acc->v[0][0][0][0];
-        for (int e = tid; e < 2 * kTileSlots * kTileSlots * 2; e += 256) z[e] = R(0);
+        for (int e = tid; e < kAccOps<R> * SX * SY * 2; e += NT) z[e] = R(0);
     }
     __syncthreads();
-    if (tid < 2 * kTileSlots) {
+    for (int e = tid; e < SX + SY; e += NT) {
         // first slot holding the same dof (slots of triangles past the end of Gamma_i: -1)
-        const int side = tid / kTileSlots, sl = tid % kTileSlots;
-        const int t0 = side == 0 ? tile.y : tile.z;
+        const int side = e < SX ? 0 : 1, sl = e < SX ? e : e - SX;
+        const int t0 = side == 0 ? tile.y : tile.z, base = side == 0 ? 0 : TX;
         int f = -1;
         if (t0 + sl / 3 < dd.T) {
-            const int d = rec[16 * side + sl / 3].dof[sl % 3];
+            const int d = rec[base + sl / 3].dof[sl % 3];
             f = sl;
             for (int q = 0; q < sl; ++q)
-                if (rec[16 * side + q / 3].dof[q % 3] == d) { f = q; break; }
+                if (rec[base + q / 3].dof[q % 3] == d) { f = q; break; }
         }
-        acc->first[side][sl] = f;
+        if (side == 0) acc->first_x[sl] = f;
+        else acc->first_y[sl] = f;
     }
     __syncthreads();
-    const int ix = tid >> 4, iy = tid & 15;
+    const int ix = tid / TY, iy = tid % TY;
     const int tx = tile.y + ix, ty = tile.z + iy;
     bool valid = tx < dd.T && ty < dd.T;
     const LRec<R>& X = rec[ix];
-    const LRec<R>& Y = rec[16 + iy];
+    const LRec<R>& Y = rec[TX + iy];
     if (valid) {
         // touching pairs belong to the Sauter-Schwab path
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b)
                 if (X.v[a] == Y.v[b]) valid = false;
     }
+    Moments<R> mom;
+    zero_moments(mom);
     if (valid) {
         const R k = (R)dd.k;
         R D[3];
         for (int i = 0; i < 3; ++i) D[i] = (R)(X.c[i] - Y.c[i]);
-        Moments<R> m;
-        zero_moments(m);
+        Moments<R>& m = mom;
         // FP64: one outer quadrature point at a time (the FP64 phase evaluations would otherwise spill)
         constexpr int kUnrollQ = std::is_same<R, double>::value ? 1 : 6;
 #pragma unroll kUnrollQ
@@ -351,31 +425,53 @@ __device__ __attribute__((always_inline)) inline void regular_tile(const int4 ti
                 m.Nxy[2][c] += wq * (x0 * ty[1][c] - x1 * ty[0][c]);
             }
         }
-        epilogue<R>(m, X.p, Y.p, X.coef, Y.coef, D, k, X.sg, Y.sg, LdsSink<R>{acc, 3 * ix, 3 * iy});
+        epilogue<R>(m, X.p, Y.p, X.coef, Y.coef, D, k, X.sg, Y.sg,
+                    LdsSink<R, S, kAccOps<R> == 2 ? 2 : 0>{acc, 3 * ix, 3 * iy});
     }
+    // distinct (test dof, trial dof) entries of the tile from accumulator `op` into `out`
+    auto scatter = [&](int op, R* out) {
+        for (int e = tid; e < SX * SY; e += NT) {
+            const int x = e % SX, y = e / SX;
+            if (acc->first_x[x] != x || acc->first_y[y] != y) continue;
+            const R re = acc->v[op][x][y][0], im = acc->v[op][x][y][1];
+            if (re == R(0) && im == R(0)) continue;
+            const int64_t idx = 2 * (dd.mat0 + (int64_t)rec[x / 3].dof[x % 3] + (int64_t)rec[TX + y / 3].dof[y % 3] * dd.E);
+            atomic_add(out + idx, re);
+            atomic_add(out + idx + 1, im);
+        }
+    };
     __syncthreads();
-    // distinct (test dof, trial dof) entries of the tile into T and K
-    for (int e = tid; e < kTileSlots * kTileSlots; e += 256) {
-        const int x = e % kTileSlots, y = e / kTileSlots;
-        if (acc->first[0][x] != x || acc->first[1][y] != y) continue;
-        const R tr = acc->v[0][x][y][0], ti = acc->v[0][x][y][1], kr = acc->v[1][x][y][0], ki = acc->v[1][x][y][1];
-        if (tr == R(0) && ti == R(0) && kr == R(0) && ki == R(0)) continue;
-        const int64_t idx = 2 * (dd.mat0 + (int64_t)rec[x / 3].dof[x % 3] + (int64_t)rec[16 + y / 3].dof[y % 3] * dd.E);
-        atomic_add(T + idx, tr);
-        atomic_add(T + idx + 1, ti);
-        atomic_add(K + idx, kr);
-        atomic_add(K + idx + 1, ki);
+    scatter(0, T);
+    if constexpr (kAccOps<R> == 2) {
+        scatter(1, K);
+    } else {
+        __syncthreads();
+        {
+            R* z = &acc->v[0][0][0][0];
+            for (int e = tid; e < SX * SY * 2; e += NT) z[e] = R(0);
+        }
+        __syncthreads();
+        if (valid) {
+            // the K pass repeats the epilogue from the moments still held in registers (only its K
+            // half is computed)
+            const R k = (R)dd.k;
+            R D[3];
+            for (int i = 0; i < 3; ++i) D[i] = (R)(X.c[i] - Y.c[i]);
+            epilogue<R>(mom, X.p, Y.p, X.coef, Y.coef, D, k, X.sg, Y.sg, LdsSink<R, S, 1>{acc, 3 * ix, 3 * iy});
+        }
+        __syncthreads();
+        scatter(0, K);
     }
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_regular(const int4* __restrict__ tiles, const DomDesc* __restrict__ doms,
-                                                 const TriGeom* __restrict__ geom, const int32_t* __restrict__ verts,
-                                                 const int32_t* __restrict__ tdof, const int8_t* __restrict__ tsign,
-                                                 R* __restrict__ T, R* __restrict__ K) {
-    __shared__ LRec<R> rec[32];
-    __shared__ TileAcc<R> acc;
-    regular_tile<R>(tiles[blockIdx.x], doms, geom, verts, tdof, tsign, T, K, rec, &acc);
+template <typename R, typename S>
+__global__ __launch_bounds__(S::NT, S::OCC) void k_regular(const int4* __restrict__ tiles, const DomDesc* __restrict__ doms,
+                                                           const TriGeom* __restrict__ geom, const int32_t* __restrict__ verts,
+                                                           const int32_t* __restrict__ tdof, const int8_t* __restrict__ tsign,
+                                                           R* __restrict__ T, R* __restrict__ K) {
+    __shared__ LRec<R> rec[S::TX + S::TY];
+    __shared__ TileAcc<R, S> acc;
+    regular_tile<R, S>(tiles[blockIdx.x], doms, geom, verts, tdof, tsign, T, K, rec, &acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -423,7 +519,7 @@ __device__ __attribute__((always_inline)) inline void singular_pair(const SingPa
             d[i] = D[i] + x[i] - y[i];
         }
         const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        const double rinv = 1.0 / sqrt(r2);
+        const double rinv = rsqrt_nr(r2);
         const double kr = k * r2 * rinv;
         double Gre, Gim, gre, gim;
         kernel_values<double>(kr, rinv, w, Gre, Gim, gre, gim);
@@ -481,18 +577,17 @@ __global__ __launch_bounds__(256) void k_singular(const SingPair* __restrict__ p
 // ---------------------------------------------------------------------------
 // persistent assembly of a batch of problems (one launch, dynamic work queue)
 // ---------------------------------------------------------------------------
-// Work item (int4): x = problem | (kind << 24); kind 0 = separated tile (y, z, w = subdomain,
-// first test triangle, first trial triangle), kind 1 = up to four touching pairs (y = first pair,
-// z = count).  Each workgroup claims items through an atomic counter until the counter passes
-// `nitems`; every wave then leaves the loop.
-template <typename R>
-__global__ __launch_bounds__(256) void k_assemble_persistent(const int4* __restrict__ items, int64_t nitems,
-                                                             unsigned long long* counter, const BatchProb* __restrict__ probs,
-                                                             const double* __restrict__ ss_table,
-                                                             const int32_t* __restrict__ ss_off,
-                                                             const int32_t* __restrict__ ss_cnt) {
-    __shared__ LRec<R> rec[32];
-    __shared__ TileAcc<R> acc;
+// Work item (int4): x = problem, y = subdomain, z = first test triangle, w = first trial triangle
+// of a tile of separated pairs (shape S).  Each workgroup claims items through an atomic counter until
+// the counter passes `nitems`; every wave then leaves the loop.  The touching pairs are not in the
+// queue: their Sauter-Schwab path needs far more registers than a tile, and sharing one kernel
+// would hold every tile to that register count (half the resident waves).
+template <typename R, typename S>
+__global__ __launch_bounds__(S::NT, S::OCC) void k_assemble_persistent(const int4* __restrict__ items, int64_t nitems,
+                                                                       unsigned long long* counter,
+                                                                       const BatchProb* __restrict__ probs) {
+    __shared__ LRec<R> rec[S::TX + S::TY];
+    __shared__ TileAcc<R, S> acc;
     __shared__ long long claimed;
     for (;;) {
         if (threadIdx.x == 0) claimed = (long long)atomicAdd(counter, 1ull);
@@ -501,22 +596,9 @@ __global__ __launch_bounds__(256) void k_assemble_persistent(const int4* __restr
         __syncthreads();
         if (it >= nitems) break;            // uniform across the workgroup
         const int4 w = items[it];
-        const int prob = w.x & 0xffffff, kind = w.x >> 24;
-        const BatchProb bp = probs[prob];
-        if (kind == 0) {
-            regular_tile<R>(make_int4(w.y, w.z, w.w, 0), bp.doms, bp.geom, bp.verts, bp.tdof, bp.tsign,
-                            static_cast<R*>(bp.T), static_cast<R*>(bp.K), rec, &acc);
-        } else {
-            const int wave = threadIdx.x >> 6;
-            if (wave < w.z) {
-                double* T64 = sizeof(R) == 8 ? static_cast<double*>(bp.T) : nullptr;
-                double* K64 = sizeof(R) == 8 ? static_cast<double*>(bp.K) : nullptr;
-                float* T32 = sizeof(R) == 4 ? static_cast<float*>(bp.T) : nullptr;
-                float* K32 = sizeof(R) == 4 ? static_cast<float*>(bp.K) : nullptr;
-                singular_pair(bp.sing[w.y + wave], bp.doms, bp.geom, bp.tdof, bp.tsign, ss_table, ss_off, ss_cnt, T64, K64,
-                              T32, K32, threadIdx.x & 63);
-            }
-        }
+        const BatchProb bp = probs[w.x];
+        regular_tile<R, S>(make_int4(w.y, w.z, w.w, 0), bp.doms, bp.geom, bp.verts, bp.tdof, bp.tsign,
+                           static_cast<R*>(bp.T), static_cast<R*>(bp.K), rec, &acc);
         __syncthreads();                    // LDS records are reused by the next item
     }
 }
@@ -698,18 +780,47 @@ void launch_fill_f(float* p, int64_t n, float v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_f, dim3(g), dim3(256), 0, s, p, n, v);
 }
 
-void launch_regular_f64(const int4* tiles, int64_t ntiles, const DomDesc* doms, const TriGeom* geom,
-                        const int32_t* verts, const int32_t* tdof, const int8_t* tsign, double* T, double* K,
-                        hipStream_t s) {
-    if (ntiles <= 0) return;
-    hipLaunchKernelGGL(k_regular<double>, dim3((unsigned)ntiles), dim3(256), 0, s, tiles, doms, geom, verts, tdof, tsign, T, K);
+// Tile variants the autotuner chooses from: (test x trial triangles, minimum waves per SIMD).
+using TV0 = TileShape<16, 16, 2>;
+using TV1 = TileShape<8, 32, 2>;
+using TV2 = TileShape<32, 8, 2>;
+using TV3 = TileShape<16, 8, 2>;
+using TV4 = TileShape<16, 16, 3>;
+
+template <typename F>
+void with_variant(int v, F&& f) {
+    switch (v) {
+        case 0: f(TV0{}); break;
+        case 1: f(TV1{}); break;
+        case 2: f(TV2{}); break;
+        case 3: f(TV3{}); break;
+        case 4: f(TV4{}); break;
+        default: throw std::invalid_argument("unknown tile variant");
+    }
 }
 
-void launch_regular_f32(const int4* tiles, int64_t ntiles, const DomDesc* doms, const TriGeom* geom,
-                        const int32_t* verts, const int32_t* tdof, const int8_t* tsign, float* T, float* K,
-                        hipStream_t s) {
+void tile_variant_shape(int v, int* tx, int* ty, int* occ) {
+    with_variant(v, [&](auto sh) {
+        using S = decltype(sh);
+        *tx = S::TX;
+        *ty = S::TY;
+        *occ = S::OCC;
+    });
+}
+
+void launch_regular(int precision, int variant, const int4* tiles, int64_t ntiles, const DomDesc* doms,
+                    const TriGeom* geom, const int32_t* verts, const int32_t* tdof, const int8_t* tsign, void* T,
+                    void* K, hipStream_t s) {
     if (ntiles <= 0) return;
-    hipLaunchKernelGGL(k_regular<float>, dim3((unsigned)ntiles), dim3(256), 0, s, tiles, doms, geom, verts, tdof, tsign, T, K);
+    with_variant(variant, [&](auto sh) {
+        using S = decltype(sh);
+        if (precision == 0)
+            hipLaunchKernelGGL((k_regular<double, S>), dim3((unsigned)ntiles), dim3(S::NT), 0, s, tiles, doms, geom, verts,
+                               tdof, tsign, static_cast<double*>(T), static_cast<double*>(K));
+        else
+            hipLaunchKernelGGL((k_regular<float, S>), dim3((unsigned)ntiles), dim3(S::NT), 0, s, tiles, doms, geom, verts,
+                               tdof, tsign, static_cast<float*>(T), static_cast<float*>(K));
+    });
 }
 
 void launch_singular(const SingPair* pairs, int64_t npairs, const DomDesc* doms, const TriGeom* geom,
@@ -746,16 +857,18 @@ void launch_far_field(const DomDesc* d0, const TriGeom* geom, const int32_t* tdo
                        rho0, x, ldx, dirs, ndir, out);
 }
 
-void launch_assemble_persistent(int precision, const int4* items, int64_t nitems, unsigned long long* counter,
-                                const BatchProb* probs, const double* ss_table, const int32_t* ss_off,
-                                const int32_t* ss_cnt, int grid, hipStream_t s) {
+void launch_assemble_persistent(int precision, int variant, const int4* items, int64_t nitems,
+                                unsigned long long* counter, const BatchProb* probs, int grid, hipStream_t s) {
     if (nitems <= 0) return;
-    if (precision == 0)
-        hipLaunchKernelGGL(k_assemble_persistent<double>, dim3((unsigned)grid), dim3(256), 0, s, items, nitems, counter,
-                           probs, ss_table, ss_off, ss_cnt);
-    else
-        hipLaunchKernelGGL(k_assemble_persistent<float>, dim3((unsigned)grid), dim3(256), 0, s, items, nitems, counter,
-                           probs, ss_table, ss_off, ss_cnt);
+    with_variant(variant, [&](auto sh) {
+        using S = decltype(sh);
+        if (precision == 0)
+            hipLaunchKernelGGL((k_assemble_persistent<double, S>), dim3((unsigned)grid), dim3(S::NT), 0, s, items, nitems,
+                               counter, probs);
+        else
+            hipLaunchKernelGGL((k_assemble_persistent<float, S>), dim3((unsigned)grid), dim3(S::NT), 0, s, items, nitems,
+                               counter, probs);
+    });
 }
 
 void launch_tri_setup_rule(const double* xyz, const int32_t* verts, int64_t nrec, const double* bary18,

@@ -6,8 +6,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <complex>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -24,7 +27,6 @@ namespace {
 using namespace mtf;
 using cd = std::complex<double>;
 
-constexpr int kTile = 16;     // triangles per side of a separated-pair tile
 constexpr int kChunk = 64;    // columns per dense-matvec workgroup (matches solver.hip)
 constexpr int kNblk = 32;     // partial sums of GMRES norms
 constexpr int kGjPanel = 256; // block width of the Gauss-Jordan inversion (64-wide leaves inside)
@@ -59,6 +61,7 @@ struct GmresWork {
     hipEvent_t ev[2] = {nullptr, nullptr};   // completion of the copy into each area
     double* hosty = nullptr;         // pinned: nb x (maxit + 1) least-squares coefficients
     int* hostcnt = nullptr;          // pinned: nb step counts + flag
+    int64_t cap_n = 0;               // unknowns the n-sized buffers were allocated for (n <= cap_n)
     ~GmresWork() { release(); }
     // frees every buffer; the next solve allocates again
     void release() {
@@ -76,10 +79,37 @@ struct GmresWork {
         }
         host = hosty = nullptr;
         hostcnt = nullptr;
-        n = 0;
+        n = cap_n = 0;
         maxit = nb = zslots = 0;
     }
 };
+
+template <typename T>
+void swap_buf(DevBuf<T>& a, DevBuf<T>& b) {
+    std::swap(a.p, b.p);
+    std::swap(a.n, b.n);
+}
+
+// Exchanges two workspaces (a batch lends its workspace to each problem's solve in turn).
+void swap_work(GmresWork& a, GmresWork& b) {
+    DevBuf<double>* da[] = {&a.V, &a.Zt, &a.Rf, &a.tmp, &a.tmp2, &a.tmp3, &a.r, &a.hpart, &a.S, &a.Z, &a.hg, &a.scal,
+                            &a.H, &a.npart, &a.upart, &a.y, &a.ufix, &a.tfix, &a.zfix, &a.Hst};
+    DevBuf<double>* db[] = {&b.V, &b.Zt, &b.Rf, &b.tmp, &b.tmp2, &b.tmp3, &b.r, &b.hpart, &b.S, &b.Z, &b.hg, &b.scal,
+                            &b.H, &b.npart, &b.upart, &b.y, &b.ufix, &b.tfix, &b.zfix, &b.Hst};
+    for (size_t k = 0; k < sizeof(da) / sizeof(da[0]); ++k) swap_buf(*da[k], *db[k]);
+    swap_buf(a.jdev, b.jdev);
+    swap_buf(a.cnt, b.cnt);
+    std::swap(a.n, b.n);
+    std::swap(a.cap_n, b.cap_n);
+    std::swap(a.maxit, b.maxit);
+    std::swap(a.nb, b.nb);
+    std::swap(a.zslots, b.zslots);
+    std::swap(a.host, b.host);
+    std::swap(a.hosty, b.hosty);
+    std::swap(a.hostcnt, b.hostcnt);
+    std::swap(a.ev[0], b.ev[0]);
+    std::swap(a.ev[1], b.ev[1]);
+}
 
 }  // namespace
 
@@ -103,6 +133,8 @@ struct mtf_problem_s {
     DevBuf<int64_t> d_gcol;
     DevBuf<int4> d_tiles, d_symtiles;
     int64_t ntiles = 0, nsymtiles = 0;
+    int tile_variant = -1;           // tile variant of d_tiles (-1: not built)
+    int last_variant = -1;           // tile variant of the last mtf_assemble
     DevBuf<int64_t> d_near_ptr;      // touching-pair lower-triangle pattern (CSR over dofs)
     DevBuf<int32_t> d_near_col;
     DevBuf<double> near64, near32;   // corrections A[m,n] - A[n,m] for T, K from the FP64 / FP32 blocks
@@ -115,6 +147,7 @@ struct mtf_problem_s {
     DevBuf<double> T64, K64;
     DevBuf<float> T32, K32, Tinv;
     bool have64 = false, have32 = false, have_tinv = false;
+    int tinv_prec = MTF_FP64;        // blocks the T_i^-1 preconditioner was built from (MTF_FP64 / MTF_FP32_MIXED)
     GemmOp gm, gp;                   // multi-RHS MFMA products: operator blocks, preconditioner blocks
     // block Gauss-Seidel stages: stage 0 = {Omega_0}, then colour classes of the subdomain graph
     DevBuf<int4> d_stage_tiles, d_pctiles;    // preconditioner tiles per Gauss-Seidel stage, and all of them
@@ -155,6 +188,17 @@ struct mtf_problem_s {
 namespace {
 
 void sync(mtf_problem p) { HIPCHK(hipStreamSynchronize(p->stream)); }
+
+// Largest accepted ||T_i S_i^-1 v - v|| / ||v|| of a symmetric-part preconditioner block: kPcSymTol,
+// or the value of the environment variable MTF_PC_SYM_TOL when set (0 rebuilds every block from
+// T_i itself; used to test that path).
+double pc_sym_tol() {
+    const char* e = std::getenv("MTF_PC_SYM_TOL");
+    if (!e || !*e) return kPcSymTol;
+    char* end = nullptr;
+    const double v = std::strtod(e, &end);
+    return (end && *end == 0 && v >= 0.0) ? v : kPcSymTol;
+}
 
 void upload_doms(mtf_problem p) {
     for (size_t i = 0; i < p->doms.size(); ++i) {
@@ -215,11 +259,8 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
             dof_dom[f0 + m] = i;
         }
     }
-    std::vector<int4> tiles, symtiles;
+    std::vector<int4> symtiles;
     for (int i = 0; i <= M; ++i) {
-        const int T = sk.dom[i].T;
-        for (int x0 = 0; x0 < T; x0 += kTile)
-            for (int y0 = 0; y0 < T; y0 += kTile) tiles.push_back(make_int4(i, x0, y0, 0));
         // column block by column block: the four tiles of a workgroup are vertically adjacent, so
         // their column segments are contiguous in memory
         for (int bj = 0; bj < doms[i].nchunk; ++bj)
@@ -295,7 +336,7 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
     p->d_dplus.upload(dplus, s);
     p->d_dminus.upload(dminus, s);
     p->d_dof_dom.upload(dof_dom, s);
-    p->d_tiles.upload(tiles, s);
+    p->tile_variant = -1;                 // separated-pair tile lists are built per variant on demand
     p->d_symtiles.upload(symtiles, s);
     p->nsymtiles = (int64_t)symtiles.size();
     p->d_near_ptr.upload(nearptr, s);
@@ -308,7 +349,6 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
     p->d_stage_dofs.upload(sdofs, s);
     p->dom_colour = colour;
     p->stage_dof0 = sd0;
-    p->ntiles = (int64_t)tiles.size();
     p->doms = doms;
     p->nrec = rec;
     p->ndof = dof;
@@ -348,7 +388,7 @@ void ensure_ss(mtf_problem p, int order) {
     p->ss_order = order;
 }
 
-void parse_assembly_opts(const mtf_assembly_opts* o, int* prec, int* order, int* flags = nullptr) {
+void parse_assembly_opts(const mtf_assembly_opts* o, int* prec, int* order, int* flags = nullptr, int* variant = nullptr) {
     *prec = MTF_FP64;
     *order = 4;
     int fl = 0;
@@ -358,10 +398,14 @@ void parse_assembly_opts(const mtf_assembly_opts* o, int* prec, int* order, int*
         if (o->singular_order) *order = o->singular_order;
         fl = o->flags;
     }
-    if (fl & ~MTF_ASSEMBLE_ROUND_FP64) throw ArgError("unknown assembly flags");
-    if (fl && !flags) throw ArgError("MTF_ASSEMBLE_ROUND_FP64 applies to mtf_assemble only");
-    if (fl && *prec != MTF_FP32_MIXED) throw ArgError("MTF_ASSEMBLE_ROUND_FP64 applies to MTF_FP32_MIXED");
-    if (flags) *flags = fl;
+    if (fl & ~(MTF_ASSEMBLE_ROUND_FP64 | 0xff00)) throw ArgError("unknown assembly flags");
+    const int tv = ((fl >> 8) & 0xff) - 1;
+    if (tv >= kTileVariants) throw ArgError("MTF_ASSEMBLE_TILE: variant out of range");
+    if ((fl & MTF_ASSEMBLE_ROUND_FP64) && !flags) throw ArgError("MTF_ASSEMBLE_ROUND_FP64 applies to mtf_assemble only");
+    if ((fl & MTF_ASSEMBLE_ROUND_FP64) && *prec != MTF_FP32_MIXED)
+        throw ArgError("MTF_ASSEMBLE_ROUND_FP64 applies to MTF_FP32_MIXED");
+    if (flags) *flags = fl & MTF_ASSEMBLE_ROUND_FP64;
+    if (variant) *variant = tv;
     if (*prec != MTF_FP64 && *prec != MTF_FP32_MIXED) throw ArgError("unknown precision");
     if (*order < 1 || *order > 8) throw ArgError("singular_order must be in 1..8");
 }
@@ -386,7 +430,7 @@ void assemble_prepare(mtf_problem p, int prec) {
         p->have32 = true;
         p->gm.haveA = false;
     }
-    p->have_tinv = false;
+    if (p->tinv_prec == prec) p->have_tinv = false;     // its source blocks change
     p->gp.haveA = false;
 }
 
@@ -402,10 +446,126 @@ void near_corrections(mtf_problem p, int prec) {
                              out.p, p->stream);
 }
 
+// ---------------------------------------------------------------------------
+// autotuning of the separated-pair tiles
+// ---------------------------------------------------------------------------
+// The launch configuration (tile variant: tile shape, workgroup size and occupancy; and, for the
+// persistent batch launch, workgroups per CU) is chosen by timing the candidates on the first
+// assembly of a shape class and kept for the process, keyed by (GPU name, launch kind, precision,
+// shape class); with the environment variable MTF_TUNE_CACHE naming a file, the choices are also
+// read from and appended to it, so that later processes skip the trials.  The shape class is
+// floor(log2) of the mean number of triangles per subdomain.
+struct TuneChoice {
+    int variant = 0, per_cu = 0;
+    double seconds = 0.0;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneChoice> g_tune;
+bool g_tune_loaded = false;
+std::vector<std::string> g_tune_log;     // one line per trial of this process (variant, grid, seconds)
+
+std::string tune_key(int device, const char* kind, int prec, int cls) {
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, device));
+    std::string name = prop.gcnArchName;
+    for (char& c : name)
+        if (c == ' ' || c == '|') c = '_';
+    return name + "|" + kind + "|" + (prec == MTF_FP64 ? "fp64" : "fp32") + "|" + std::to_string(cls);
+}
+
+bool tune_lookup(const std::string& key, TuneChoice* out) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_loaded) {
+        g_tune_loaded = true;
+        if (const char* f = std::getenv("MTF_TUNE_CACHE")) {
+            if (FILE* fp = std::fopen(f, "r")) {
+                char k[256];
+                TuneChoice c;
+                while (std::fscanf(fp, "%255s %d %d %lf", k, &c.variant, &c.per_cu, &c.seconds) == 4)
+                    if (c.variant >= 0 && c.variant < kTileVariants && c.per_cu >= 0) g_tune[k] = c;
+                std::fclose(fp);
+            }
+        }
+    }
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+void tune_store(const std::string& key, const TuneChoice& c) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = c;
+    if (const char* f = std::getenv("MTF_TUNE_CACHE")) {
+        if (FILE* fp = std::fopen(f, "a")) {
+            std::fprintf(fp, "%s %d %d %.9g\n", key.c_str(), c.variant, c.per_cu, c.seconds);
+            std::fclose(fp);
+        }
+    }
+}
+
+int shape_class(double mean_tri) { return mean_tri <= 1.0 ? 0 : (int)std::floor(std::log2(mean_tri)); }
+
+// Separated-pair tile list of the problem for tile variant v (subdomain, first test and trial
+// triangle), rebuilt when the variant changes.
+void ensure_tiles(mtf_problem p, int v) {
+    if (p->tile_variant == v) return;
+    int tx, ty, occ;
+    tile_variant_shape(v, &tx, &ty, &occ);
+    std::vector<int4> tiles;
+    for (int i = 0; i <= p->sk.M; ++i) {
+        const int T = p->sk.dom[i].T;
+        for (int x0 = 0; x0 < T; x0 += tx)
+            for (int y0 = 0; y0 < T; y0 += ty) tiles.push_back(make_int4(i, x0, y0, 0));
+    }
+    p->d_tiles.upload(tiles, p->stream);
+    p->ntiles = (int64_t)tiles.size();
+    p->tile_variant = v;
+    sync(p);
+}
+
+// Tile variant for assembling problem p in precision prec: the forced one, else the tuned one of its
+// shape class (timing every variant's separated-pair launch once on this problem if none is known).
+// The trial launches add into the blocks, which the caller clears afterwards.
+int choose_variant(mtf_problem p, int prec, int forced, void* T, void* K) {
+    if (forced >= 0) return forced;
+    double mean = 0.0;
+    for (int i = 0; i <= p->sk.M; ++i) mean += p->sk.dom[i].T;
+    mean /= (p->sk.M + 1);
+    const std::string key = tune_key(p->device, "single", prec, shape_class(mean));
+    TuneChoice c;
+    if (tune_lookup(key, &c)) return c.variant;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    TuneChoice best;
+    best.seconds = 1e300;
+    for (int v = 0; v < kTileVariants; ++v) {
+        ensure_tiles(p, v);
+        HIPCHK(hipEventRecord(e0, p->stream));
+        launch_regular(prec == MTF_FP64 ? 0 : 1, v, p->d_tiles.p, p->ntiles, p->d_doms.p, p->d_geom.p, p->d_verts.p,
+                       p->d_tdof.p, p->d_tsign.p, T, K, p->stream);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipEventRecord(e1, p->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune_log.push_back(key + " variant " + std::to_string(v) + " " + std::to_string(ms * 1e-3) + " s");
+        }
+        if (ms * 1e-3 < best.seconds) { best.seconds = ms * 1e-3; best.variant = v; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    tune_store(key, best);
+    return best.variant;
+}
+
 void assemble_impl(mtf_problem p, const mtf_assembly_opts* o) {
     if (!p->has_mesh || !p->has_mat) throw StateError("mtf_assemble needs mtf_set_mesh and mtf_set_materials first");
-    int prec, order, flags;
-    parse_assembly_opts(o, &prec, &order, &flags);
+    int prec, order, flags, forced;
+    parse_assembly_opts(o, &prec, &order, &flags, &forced);
     DeviceGuard g(p->device);
     hipStream_t s = p->stream;
     if (!p->ev0) { HIPCHK(hipEventCreate(&p->ev0)); HIPCHK(hipEventCreate(&p->ev1)); }
@@ -422,27 +582,31 @@ void assemble_impl(mtf_problem p, const mtf_assembly_opts* o) {
         HIPCHK(hipEventRecord(p->ev1, s));
         p->have32 = true;
         p->gm.haveA = false;
-        p->have_tinv = false;
+        if (p->tinv_prec == MTF_FP32_MIXED) p->have_tinv = false;
         p->gp.haveA = false;
         return;
     }
     ensure_ss(p, order);
     if (prec == MTF_FP64) { p->T64.alloc(n2); p->K64.alloc(n2); }
     else { p->T32.alloc(n2); p->K32.alloc(n2); }
+    const int variant = choose_variant(p, prec, forced, prec == MTF_FP64 ? (void*)p->T64.p : (void*)p->T32.p,
+                                       prec == MTF_FP64 ? (void*)p->K64.p : (void*)p->K32.p);
+    ensure_tiles(p, variant);
+    p->last_variant = variant;
     HIPCHK(hipEventRecord(p->ev0, s));
     const int32_t* meta = p->d_ss_meta.p;
     if (prec == MTF_FP64) {
         launch_fill(p->T64.p, n2, 0.0, s);
         launch_fill(p->K64.p, n2, 0.0, s);
-        launch_regular_f64(p->d_tiles.p, p->ntiles, p->d_doms.p, p->d_geom.p, p->d_verts.p, p->d_tdof.p, p->d_tsign.p,
-                           p->T64.p, p->K64.p, s);
+        launch_regular(0, variant, p->d_tiles.p, p->ntiles, p->d_doms.p, p->d_geom.p, p->d_verts.p, p->d_tdof.p,
+                       p->d_tsign.p, p->T64.p, p->K64.p, s);
         launch_singular(p->d_sing.p, (int64_t)p->d_sing.n, p->d_doms.p, p->d_geom.p, p->d_xyz.p, p->d_verts.p,
                         p->d_tdof.p, p->d_tsign.p, p->d_ss.p, meta, meta + 4, p->T64.p, p->K64.p, nullptr, nullptr, s);
     } else {
         launch_fill_f(p->T32.p, n2, 0.f, s);
         launch_fill_f(p->K32.p, n2, 0.f, s);
-        launch_regular_f32(p->d_tiles.p, p->ntiles, p->d_doms.p, p->d_geom.p, p->d_verts.p, p->d_tdof.p, p->d_tsign.p,
-                           p->T32.p, p->K32.p, s);
+        launch_regular(1, variant, p->d_tiles.p, p->ntiles, p->d_doms.p, p->d_geom.p, p->d_verts.p, p->d_tdof.p,
+                       p->d_tsign.p, p->T32.p, p->K32.p, s);
         launch_singular(p->d_sing.p, (int64_t)p->d_sing.n, p->d_doms.p, p->d_geom.p, p->d_xyz.p, p->d_verts.p,
                         p->d_tdof.p, p->d_tsign.p, p->d_ss.p, meta, meta + 4, nullptr, nullptr, p->T32.p, p->K32.p, s);
     }
@@ -450,7 +614,7 @@ void assemble_impl(mtf_problem p, const mtf_assembly_opts* o) {
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(p->ev1, s));
     if (prec == MTF_FP64) p->have64 = true; else { p->have32 = true; p->gm.haveA = false; }
-    p->have_tinv = false;
+    if (p->tinv_prec == prec) p->have_tinv = false;      // its source blocks change
     p->gp.haveA = false;
 }
 
@@ -747,6 +911,8 @@ std::vector<std::pair<int, int>> dof_components(const Domain& d) {
     return runs;
 }
 
+void ensure_gj_streams(mtf_problem p);
+
 // Blocks of the T_i^-1 preconditioner, complex64.  Each block is first the inverse of the
 // symmetric part S_i = (T_i + T_i^T)/2, applied reading half of its entries.  Where Gamma_i has
 // several connected components (the exterior of disjoint scatterers), S_i is replaced by its
@@ -771,14 +937,7 @@ void build_tinv(mtf_problem p, bool force_full) {
     HIPCHK(hipMemsetAsync(info.p, 0, 2 * sizeof(int), s));
     // streams of the inversions: non-blocking, so that they also overlap work on a caller's null
     // stream; ordered by events only
-    for (int l = 0; l < 2; ++l) {
-        if (!p->gj_lane[l]) HIPCHK(hipStreamCreateWithFlags(&p->gj_lane[l], hipStreamNonBlocking));
-        if (!p->gj_aux[l]) HIPCHK(hipStreamCreateWithFlags(&p->gj_aux[l], hipStreamNonBlocking));
-        if (!p->gj_fork[l]) HIPCHK(hipEventCreateWithFlags(&p->gj_fork[l], hipEventDisableTiming));
-        if (!p->gj_join[l]) HIPCHK(hipEventCreateWithFlags(&p->gj_join[l], hipEventDisableTiming));
-        if (!p->gj_done[l]) HIPCHK(hipEventCreateWithFlags(&p->gj_done[l], hipEventDisableTiming));
-    }
-    if (!p->gj_start) HIPCHK(hipEventCreateWithFlags(&p->gj_start, hipEventDisableTiming));
+    ensure_gj_streams(p);
     GjLookahead la[2];
     for (int l = 0; l < 2; ++l) {
         la[l].s2 = p->gj_aux[l];
@@ -909,7 +1068,7 @@ void build_tinv(mtf_problem p, bool force_full) {
                 num += dr * dr + di * di;
                 den += (double)vh[2 * m] * vh[2 * m] + (double)vh[2 * m + 1] * vh[2 * m + 1];
             }
-            if (D[i].E > 0 && !(std::sqrt(num / den) <= kPcSymTol)) redo.push_back(i);
+            if (D[i].E > 0 && !(std::sqrt(num / den) <= pc_sym_tol())) redo.push_back(i);
         }
         for (int i : redo) {
             const int64_t E = D[i].E;
@@ -938,23 +1097,232 @@ void build_tinv(mtf_problem p, bool force_full) {
     build_pc_tiles(p);
     sync(p);
     p->have_tinv = true;
+    p->tinv_prec = p->have32 ? MTF_FP32_MIXED : MTF_FP64;
     p->pc_force_full = force_full;
     p->gp.haveA = false;
     p->t_precond = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// Streams and events of the preconditioner build (created once per problem).
+void ensure_gj_streams(mtf_problem p) {
+    for (int l = 0; l < 2; ++l) {
+        if (!p->gj_lane[l]) HIPCHK(hipStreamCreateWithFlags(&p->gj_lane[l], hipStreamNonBlocking));
+        if (!p->gj_aux[l]) HIPCHK(hipStreamCreateWithFlags(&p->gj_aux[l], hipStreamNonBlocking));
+        if (!p->gj_fork[l]) HIPCHK(hipEventCreateWithFlags(&p->gj_fork[l], hipEventDisableTiming));
+        if (!p->gj_join[l]) HIPCHK(hipEventCreateWithFlags(&p->gj_join[l], hipEventDisableTiming));
+        if (!p->gj_done[l]) HIPCHK(hipEventCreateWithFlags(&p->gj_done[l], hipEventDisableTiming));
+    }
+    if (!p->gj_start) HIPCHK(hipEventCreateWithFlags(&p->gj_start, hipEventDisableTiming));
+}
+
+// The T_i^-1 preconditioner blocks of every problem of a batch, built together (same blocks as
+// build_tinv: the inverse of the symmetric part of each T_i, or of each connected component's
+// diagonal block of it, checked on a fixed vector and rebuilt from T_i itself where the check
+// fails).  A batch of many small problems has hundreds of diagonal blocks of different orders;
+// inverted one problem after another they are a long chain of small launches (the 64-wide leaf
+// inversions occupy one CU each).  Here every block is copied into a slot of a bucket of equal
+// padded order S (n rounded up to 128, the identity in the padding), and each bucket is one
+// batched blocked Gauss-Jordan inversion, the buckets spread over two streams.  All problems
+// share the stream s.  Returns the wall time of the build.
+double batch_build_tinv(const std::vector<mtf_problem>& ps, bool force_full, hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    struct Blk {
+        int prob, dom;
+        PadBlock pb;
+    };
+    std::vector<Blk> blocks;
+    int64_t emax = 0;
+    for (size_t q = 0; q < ps.size(); ++q) {
+        mtf_problem p = ps[q];
+        const auto& D = p->doms;
+        p->Tinv.alloc(2 * (p->mat_entries + 64));
+        launch_fill_f(p->Tinv.p, 2 * (p->mat_entries + 64), 0.f, s);
+        p->pc_full.assign(D.size(), force_full ? 1 : 0);
+        p->have_tinv = false;
+        for (int i = 0; i < (int)D.size(); ++i) {
+            const int64_t E = D[i].E;
+            if (E == 0) continue;
+            std::vector<std::pair<int, int>> comps;
+            if (!force_full) comps = dof_components(p->sk.dom[i]);
+            if (comps.empty()) comps.emplace_back(0, (int)E);
+            for (const auto& c : comps) {
+                const int64_t o = D[i].mat0 + c.first + (int64_t)c.first * E;
+                PadBlock b;
+                b.f64 = p->have32 ? 0 : 1;
+                b.src = b.f64 ? static_cast<const void*>(p->T64.p + 2 * o) : static_cast<const void*>(p->T32.p + 2 * o);
+                b.dst = p->Tinv.p + 2 * o;
+                b.ld = E;
+                b.n = c.second - c.first;
+                blocks.push_back(Blk{(int)q, i, b});
+            }
+            emax = std::max(emax, E);
+        }
+    }
+    if (blocks.empty()) return 0.0;
+    mtf_problem p0 = ps[0];
+    ensure_gj_streams(p0);
+    GjLookahead la[2];
+    for (int l = 0; l < 2; ++l) la[l] = GjLookahead{p0->gj_aux[l], p0->gj_fork[l], p0->gj_join[l]};
+    DevBuf<int> info;
+    info.alloc(2);
+    HIPCHK(hipMemsetAsync(info.p, 0, 2 * sizeof(int), s));
+    auto padded = [](int n) { return n <= 64 ? 64 : ((n + 127) / 128) * 128; };
+    int smax = 64;
+    for (const Blk& b : blocks) smax = std::max(smax, padded(b.pb.n));
+    // the fixed check vector v_m = (cos m, sin 2m), long enough for every padded slot
+    const int64_t vlen = std::max<int64_t>(emax, smax);
+    std::vector<float> vh(2 * vlen);
+    for (int64_t m = 0; m < vlen; ++m) { vh[2 * m] = (float)std::cos((double)m); vh[2 * m + 1] = (float)std::sin(2.0 * m); }
+    DevBuf<float> v;
+    v.alloc(2 * vlen);
+    HIPCHK(hipMemcpyAsync(v.p, vh.data(), vh.size() * sizeof(float), hipMemcpyHostToDevice, s));
+
+    // Inverts the listed blocks (symmetrised when sym) into their destinations; with `check`,
+    // fills u[blocks] = T (X v) (X the new inverse), blocks back to back in list order.
+    std::vector<float> uh;
+    auto invert = [&](const std::vector<int>& idx, int sym, bool check) {
+        std::map<int, std::vector<int>> bucket;
+        for (int k : idx) bucket[padded(blocks[k].pb.n)].push_back(k);
+        std::vector<PadBlock> hb;
+        std::vector<int64_t> boff, bslot;              // per bucket: first PadBlock, first slot (complex entries)
+        int64_t slots = 0, tmp_need[2] = {1, 1}, wlen = 0, part_need = 1;
+        int lane = 0;
+        std::vector<int> blane;
+        for (auto& kv : bucket) {
+            const int S = kv.first;
+            boff.push_back((int64_t)hb.size());
+            bslot.push_back(slots);
+            for (int k : kv.second) hb.push_back(blocks[k].pb);
+            slots += (int64_t)kv.second.size() * S * S;
+            blane.push_back(lane);
+            tmp_need[lane] = std::max<int64_t>(tmp_need[lane], (int64_t)kv.second.size() * kGjPanel * S);
+            lane ^= 1;
+            wlen += (int64_t)kv.second.size() * S;
+            part_need = std::max<int64_t>(part_need, (int64_t)kv.second.size() * ((S + 255) / 256) * S);
+        }
+        DevBuf<PadBlock> dpb;
+        dpb.upload(hb, s);
+        DevBuf<float> buf, tmp[2];
+        buf.alloc(2 * slots);
+        for (int l = 0; l < 2; ++l) tmp[l].alloc(2 * tmp_need[l]);
+        HIPCHK(hipEventRecord(p0->gj_start, s));
+        for (int l = 0; l < 2; ++l) HIPCHK(hipStreamWaitEvent(p0->gj_lane[l], p0->gj_start, 0));
+        size_t bi = 0;
+        for (auto& kv : bucket) {
+            const int S = kv.first, cnt = (int)kv.second.size(), l = blane[bi];
+            hipStream_t ls = p0->gj_lane[l];
+            float* bb = buf.p + 2 * bslot[bi];
+            launch_pad_gather(dpb.p + boff[bi], cnt, S, sym, bb, ls);
+            block_gj_inverse(bb, S, S, (int64_t)S * S, cnt, info.p, ls, kGjPanel, tmp[l].p, &la[l]);
+            launch_pad_scatter(dpb.p + boff[bi], cnt, S, bb, ls);
+            ++bi;
+        }
+        for (int l = 0; l < 2; ++l) {
+            HIPCHK(hipEventRecord(p0->gj_done[l], p0->gj_lane[l]));
+            HIPCHK(hipStreamWaitEvent(s, p0->gj_done[l], 0));
+        }
+        if (check) {
+            // w = X v per slot (batched per bucket), then u = T_blk w[0:n] per block
+            DevBuf<float> w, u, part;
+            int64_t ulen = 0;
+            for (int k : idx) ulen += blocks[k].pb.n;
+            w.alloc(2 * wlen);
+            u.alloc(2 * std::max<int64_t>(ulen, 1));
+            int64_t pn = part_need;
+            for (int k : idx) pn = std::max<int64_t>(pn, (int64_t)((blocks[k].pb.n + 255) / 256) * blocks[k].pb.n);
+            part.alloc(2 * pn);
+            bi = 0;
+            int64_t wo = 0, uo = 0;
+            for (auto& kv : bucket) {
+                const int S = kv.first, cnt = (int)kv.second.size();
+                launch_cgemv_f32(buf.p + 2 * bslot[bi], S, (int64_t)S * S, v.p, 0, S, cnt, part.p, w.p + 2 * wo, S, s);
+                for (int j = 0; j < cnt; ++j) {
+                    const PadBlock& b = blocks[kv.second[j]].pb;
+                    float* wj = w.p + 2 * (wo + (int64_t)j * S);
+                    if (b.f64)
+                        launch_cgemv_f64src(static_cast<const double*>(b.src), b.ld, wj, b.n, part.p, u.p + 2 * uo, s);
+                    else
+                        launch_cgemv_f32(static_cast<const float*>(b.src), b.ld, 0, wj, 0, b.n, 1, part.p, u.p + 2 * uo, 0, s);
+                    uo += b.n;
+                }
+                wo += (int64_t)cnt * S;
+                ++bi;
+            }
+            uh.assign(2 * ulen, 0.f);
+            HIPCHK(hipMemcpyAsync(uh.data(), u.p, uh.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+            // the check's order of blocks: bucket by bucket
+            std::vector<int> order;
+            for (auto& kv2 : bucket) order.insert(order.end(), kv2.second.begin(), kv2.second.end());
+            HIPCHK(hipStreamSynchronize(s));
+            return order;
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        return std::vector<int>();
+    };
+
+    std::vector<int> all(blocks.size());
+    for (size_t k = 0; k < blocks.size(); ++k) all[k] = (int)k;
+    const std::vector<int> order = invert(all, force_full ? 0 : 1, !force_full);
+    if (!force_full) {
+        // ||T_i (X_i v) - v|| / ||v|| per subdomain (over its components); rebuild the failures
+        std::map<std::pair<int, int>, std::pair<double, double>> err;
+        int64_t uo = 0;
+        for (int k : order) {
+            const Blk& b = blocks[k];
+            auto& e = err[{b.prob, b.dom}];
+            for (int m = 0; m < b.pb.n; ++m) {
+                const float* ui = uh.data() + 2 * (uo + m);
+                const double dr = ui[0] - vh[2 * m], di = ui[1] - vh[2 * m + 1];
+                e.first += dr * dr + di * di;
+                e.second += (double)vh[2 * m] * vh[2 * m] + (double)vh[2 * m + 1] * vh[2 * m + 1];
+            }
+            uo += b.pb.n;
+        }
+        std::vector<int> redo;
+        for (size_t k = 0; k < blocks.size(); ++k) {
+            const auto& e = err[{blocks[k].prob, blocks[k].dom}];
+            if (!(std::sqrt(e.first / e.second) <= pc_sym_tol())) {
+                redo.push_back((int)k);
+                ps[blocks[k].prob]->pc_full[blocks[k].dom] = 1;
+            }
+        }
+        if (!redo.empty()) invert(redo, 0, false);
+    }
+    for (mtf_problem p : ps) launch_nonfinite_check(p->Tinv.p, 2 * p->mat_entries, info.p + 1, s);
+    HIPCHK(hipGetLastError());
+    int h[2];
+    HIPCHK(hipMemcpyAsync(h, info.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (h[0] || h[1]) throw NonFiniteError("block preconditioner: singular pivot or non-finite inverse of T_i");
+    for (mtf_problem p : ps) {
+        build_pc_tiles(p);
+        p->have_tinv = true;
+        p->tinv_prec = p->have32 ? MTF_FP32_MIXED : MTF_FP64;
+        p->pc_force_full = force_full;
+        p->gp.haveA = false;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (mtf_problem p : ps) p->t_precond = t;
+    return t;
+}
+
 void gmres_alloc(mtf_problem p, int maxit, int nb, bool flex) {
     GmresWork& w = p->gw;
     const int64_t n = p->sk.N;
-    if (w.n == n && w.maxit >= maxit && w.nb >= nb) {
+    // a workspace allocated for at least n unknowns, maxit steps and nb columns serves as it is (the
+    // buffers are laid out from w.n, w.maxit and w.nb)
+    if (w.cap_n >= n && w.maxit >= maxit && w.nb >= nb) {
+        w.n = n;
         if (flex && w.zslots < w.maxit) {
-            w.Zt.alloc(2 * n * (int64_t)w.nb * w.maxit);
+            w.Zt.alloc(2 * w.cap_n * (int64_t)w.nb * w.maxit);
             w.Rf.alloc(2 * (int64_t)(w.maxit + 1) * w.maxit * w.nb);
             w.zslots = w.maxit;
         }
         return;
     }
     w.n = n;
+    w.cap_n = n;
     w.maxit = maxit;
     w.nb = nb;
     const int64_t ldh = maxit + 1;
@@ -1515,6 +1883,20 @@ int mtf_set_materials(mtf_problem p, double k0, const double* eps_r, const doubl
         for (int i = 0; i <= M; ++i)
             if (!(eps_r[i] > 0.0) || !(mu_r[i] > 0.0) || !std::isfinite(eps_r[i]) || !std::isfinite(mu_r[i]))
                 throw ArgError("eps_r and mu_r must be positive and finite");
+        {
+            // the FP64 kernel evaluation reduces phases k_i r exactly only below about 1.6e6
+            double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+            for (int64_t v = 0; v < p->sk.nv; ++v)
+                for (int c = 0; c < 3; ++c) {
+                    lo[c] = std::min(lo[c], p->sk.xyz[3 * v + c]);
+                    hi[c] = std::max(hi[c], p->sk.xyz[3 * v + c]);
+                }
+            const double diam = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                                          (hi[2] - lo[2]) * (hi[2] - lo[2]));
+            for (int i = 0; i <= M; ++i)
+                if (!(k0 * std::sqrt(eps_r[i] * mu_r[i]) * diam < 1e6))
+                    throw UnsupportedError("k_i times the mesh diameter must be below 1e6");
+        }
         DeviceGuard g(p->device);
         p->k0 = k0;
         p->eps.assign(eps_r, eps_r + M + 1);
@@ -1829,6 +2211,41 @@ int mtf_far_field(mtf_problem p, int32_t nrhs, const void* x_dev, int64_t ld, in
     });
 }
 
+int mtf_tile_variant(int32_t v, int32_t* tx, int32_t* ty, int32_t* occupancy) {
+    return guarded([&] {
+        if (v < 0 || v >= kTileVariants) throw ArgError("tile variant out of range");
+        int a, b, c;
+        tile_variant_shape(v, &a, &b, &c);
+        if (tx) *tx = a;
+        if (ty) *ty = b;
+        if (occupancy) *occupancy = c;
+        return MTF_OK;
+    });
+}
+
+int mtf_assembly_variant(mtf_problem p, int32_t* variant) {
+    return guarded([&] {
+        if (!p || !variant) throw ArgError("bad arguments");
+        *variant = p->last_variant;
+        return MTF_OK;
+    });
+}
+
+int mtf_tuning_log(char* buf, int64_t cap) {
+    return guarded([&] {
+        if (!buf || cap < 1) throw ArgError("bad arguments");
+        std::string all;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            for (const auto& l : g_tune_log) all += l + "\n";
+        }
+        const size_t n = std::min<size_t>(all.size(), (size_t)cap - 1);
+        std::memcpy(buf, all.data(), n);
+        buf[n] = 0;
+        return MTF_OK;
+    });
+}
+
 int mtf_assembly_stats(mtf_problem p, int64_t* counts, double* seconds) {
     return guarded([&] {
         if (!p) throw ArgError("problem is NULL");
@@ -1860,45 +2277,70 @@ struct mtf_batch_s {
     int device = 0;
     hipStream_t stream = nullptr;
     DevBuf<BatchProb> d_probs;
-    DevBuf<int4> d_items;
+    DevBuf<int4> d_items, d_sample;
     DevBuf<unsigned long long> counter;
-    int64_t nitems = 0;
-    int tuned_grid[2] = {0, 0};       // per precision (0 FP64, 1 FP32)
-    double tuned_s[2] = {0.0, 0.0};
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int64_t nitems = 0, nsample = 0;
+    int items_variant = -1;           // tile variant of d_items
+    int last_variant = 0, last_grid = 0;
+    GmresWork gw;                     // GMRES workspace lent to each problem's solve in turn
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+    double last_tiles_s = 0.0;        // device time of the last persistent launch alone
+    double last_total_s = 0.0;        // and of the whole last assembly (touching pairs included)
     ~mtf_batch_s() {
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
+        if (e2) (void)hipEventDestroy(e2);
     }
 };
 
 namespace {
 
-void batch_items(mtf_batch b) {
-    // touching-pair chunks first, then separated tiles, problems by decreasing size
+// Separated-pair tiles of every problem for tile variant v, problems by decreasing size.
+void batch_items(mtf_batch b, int v) {
+    if (b->items_variant == v) return;
+    int tx, ty, occ;
+    tile_variant_shape(v, &tx, &ty, &occ);
     std::vector<int> order(b->probs.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
     std::sort(order.begin(), order.end(), [&](int x, int y) { return b->probs[x]->mat_entries > b->probs[y]->mat_entries; });
     std::vector<int4> items;
     for (int pi : order) {
-        const int64_t ns = (int64_t)b->probs[pi]->sk.singular.size();
-        for (int64_t f = 0; f < ns; f += 4) items.push_back(make_int4(pi | (1 << 24), (int)f, (int)std::min<int64_t>(4, ns - f), 0));
-    }
-    for (int pi : order) {
         const mtf_problem p = b->probs[pi];
         for (int i = 0; i <= p->sk.M; ++i) {
             const int T = p->sk.dom[i].T;
-            for (int x0 = 0; x0 < T; x0 += kTile)
-                for (int y0 = 0; y0 < T; y0 += kTile) items.push_back(make_int4(pi, i, x0, y0));
+            for (int x0 = 0; x0 < T; x0 += tx)
+                for (int y0 = 0; y0 < T; y0 += ty) items.push_back(make_int4(pi, i, x0, y0));
         }
     }
     b->d_items.upload(items, b->stream);
     b->nitems = (int64_t)items.size();
+    // every eighth item: the sample the autotuner times its candidates on
+    std::vector<int4> sample;
+    for (size_t k = 0; k < items.size(); k += 8) sample.push_back(items[k]);
+    b->d_sample.upload(sample, b->stream);
+    b->nsample = (int64_t)sample.size();
+    b->items_variant = v;
+    HIPCHK(hipStreamSynchronize(b->stream));
 }
 
-// one persistent launch over every problem; returns the device time in seconds
-double batch_launch(mtf_batch b, int prec, int grid) {
+// Device time of one persistent launch over the autotuner's sample of tiles (tile variant v,
+// `grid` workgroups); it adds into the blocks, which the real assembly clears.
+double batch_trial(mtf_batch b, int prec, int v, int grid) {
     hipStream_t s = b->stream;
+    batch_items(b, v);
+    HIPCHK(hipMemsetAsync(b->counter.p, 0, sizeof(unsigned long long), s));
+    HIPCHK(hipEventRecord(b->e0, s));
+    launch_assemble_persistent(prec == MTF_FP64 ? 0 : 1, v, b->d_sample.p, b->nsample, b->counter.p, b->d_probs.p, grid, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(b->e1, s));
+    HIPCHK(hipEventSynchronize(b->e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, b->e0, b->e1));
+    return ms * 1e-3;
+}
+
+// Problem descriptors of the batch for precision prec (blocks allocated and cleared).
+void batch_prepare(mtf_batch b, int prec) {
     std::vector<BatchProb> bp(b->probs.size());
     for (size_t i = 0; i < b->probs.size(); ++i) {
         mtf_problem p = b->probs[i];
@@ -1913,21 +2355,37 @@ double batch_launch(mtf_batch b, int prec, int grid) {
         q.T = prec == MTF_FP64 ? (void*)p->T64.p : (void*)p->T32.p;
         q.K = prec == MTF_FP64 ? (void*)p->K64.p : (void*)p->K32.p;
     }
-    b->d_probs.upload(bp, s);
+    b->d_probs.upload(bp, b->stream);
+}
+
+// one persistent launch over every problem; returns the device time in seconds
+double batch_launch(mtf_batch b, int prec, int v, int grid) {
+    hipStream_t s = b->stream;
+    batch_items(b, v);
+    batch_prepare(b, prec);
     HIPCHK(hipMemsetAsync(b->counter.p, 0, sizeof(unsigned long long), s));
-    mtf_problem p0 = b->probs[0];
-    const int32_t* meta = p0->d_ss_meta.p;
     HIPCHK(hipEventRecord(b->e0, s));
-    launch_assemble_persistent(prec == MTF_FP64 ? 0 : 1, b->d_items.p, b->nitems, b->counter.p, b->d_probs.p, p0->d_ss.p,
-                               meta, meta + 4, grid, s);
+    launch_assemble_persistent(prec == MTF_FP64 ? 0 : 1, v, b->d_items.p, b->nitems, b->counter.p, b->d_probs.p, grid, s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(b->e1, s));
+    // touching pairs (Sauter-Schwab, FP64 in both precisions), one launch per problem
+    for (mtf_problem p : b->probs) {
+        const int32_t* meta = p->d_ss_meta.p;
+        launch_singular(p->d_sing.p, (int64_t)p->d_sing.n, p->d_doms.p, p->d_geom.p, p->d_xyz.p, p->d_verts.p,
+                        p->d_tdof.p, p->d_tsign.p, p->d_ss.p, meta, meta + 4, prec == MTF_FP64 ? p->T64.p : nullptr,
+                        prec == MTF_FP64 ? p->K64.p : nullptr, prec == MTF_FP64 ? nullptr : p->T32.p,
+                        prec == MTF_FP64 ? nullptr : p->K32.p, s);
+    }
+    HIPCHK(hipEventRecord(b->e2, s));
     for (mtf_problem p : b->probs) near_corrections(p, prec);    // same stream, after the blocks
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
-    float ms = 0;
+    float ms = 0, ms2 = 0;
     HIPCHK(hipEventElapsedTime(&ms, b->e0, b->e1));
-    return ms * 1e-3;
+    HIPCHK(hipEventElapsedTime(&ms2, b->e0, b->e2));
+    b->last_tiles_s = ms * 1e-3;
+    b->last_total_s = ms2 * 1e-3;
+    return ms2 * 1e-3;
 }
 
 }  // namespace
@@ -1956,7 +2414,7 @@ int mtf_batch_create(mtf_batch* out, int32_t n, const mtf_problem* problems) {
         b->counter.alloc(1);
         HIPCHK(hipEventCreate(&b->e0));
         HIPCHK(hipEventCreate(&b->e1));
-        batch_items(b.get());
+        HIPCHK(hipEventCreate(&b->e2));
         sync(problems[0]);
         *out = b.release();
         return MTF_OK;
@@ -1976,33 +2434,95 @@ int mtf_batch_destroy(mtf_batch b) {
 int mtf_batch_assemble(mtf_batch b, const mtf_assembly_opts* opts, int32_t* grid_used, double* seconds) {
     return guarded([&] {
         if (!b) throw ArgError("batch is NULL");
-        int prec, order;
-        parse_assembly_opts(opts, &prec, &order);
+        int prec, order, forced;
+        parse_assembly_opts(opts, &prec, &order, nullptr, &forced);
         DeviceGuard g(b->device);
         for (mtf_problem p : b->probs) {
             if (!p->has_mesh || !p->has_mat) throw StateError("problem lost its mesh or materials");
             ensure_ss(p, order);
         }
-        const int pi = prec == MTF_FP64 ? 0 : 1;
-        double t = 0;
-        if (b->tuned_grid[pi] == 0) {
-            // autotuner: persistent workgroups per CU, fastest of one trial launch each; the last
-            // trial is repeated with the winner so the stored blocks are a single clean assembly
-            hipDeviceProp_t prop;
-            HIPCHK(hipGetDeviceProperties(&prop, b->device));
-            const int cus = prop.multiProcessorCount;
-            double best = 1e30;
-            int bestg = cus;
-            for (int per : {1, 2, 4, 8}) {
-                const double tt = batch_launch(b, prec, cus * per);
-                if (tt < best) { best = tt; bestg = cus * per; }
+        hipDeviceProp_t prop;
+        HIPCHK(hipGetDeviceProperties(&prop, b->device));
+        const int cus = prop.multiProcessorCount;
+        int v = forced, per = 0;
+        if (v < 0) {
+            double tri = 0, doms = 0;
+            for (mtf_problem p : b->probs) {
+                doms += p->sk.M + 1;
+                for (int i = 0; i <= p->sk.M; ++i) tri += p->sk.dom[i].T;
             }
-            b->tuned_grid[pi] = bestg;
-            b->tuned_s[pi] = best;
+            const std::string key = tune_key(b->device, "persistent", prec, shape_class(tri / doms));
+            TuneChoice c;
+            if (tune_lookup(key, &c)) {
+                v = c.variant;
+                per = c.per_cu;
+            } else {
+                // autotuner: every tile variant at 4 workgroups per CU, then 1, 2, 4 and 8 workgroups
+                // per CU for the fastest, each a persistent launch over every eighth tile
+                batch_prepare(b, prec);
+                TuneChoice best;
+                best.seconds = 1e300;
+                auto trial = [&](int tv, int tper) {
+                    const double t = batch_trial(b, prec, tv, cus * tper);
+                    {
+                        std::lock_guard<std::mutex> lk(g_tune_mu);
+                        g_tune_log.push_back(key + " variant " + std::to_string(tv) + " per_cu " + std::to_string(tper) +
+                                             " " + std::to_string(t) + " s");
+                    }
+                    if (t < best.seconds) { best.seconds = t; best.variant = tv; best.per_cu = tper; }
+                };
+                for (int tv = 0; tv < kTileVariants; ++tv) trial(tv, 4);
+                const int bv = best.variant;
+                for (int tper : {1, 2, 8}) trial(bv, tper);
+                tune_store(key, best);
+                v = best.variant;
+                per = best.per_cu;
+            }
         }
-        t = batch_launch(b, prec, b->tuned_grid[pi]);
-        if (grid_used) *grid_used = b->tuned_grid[pi];
+        if (per == 0) per = 4;
+        const double t = batch_launch(b, prec, v, cus * per);
+        b->last_variant = v;
+        b->last_grid = cus * per;
+        if (grid_used) *grid_used = cus * per;
         if (seconds) *seconds = t;
+        return MTF_OK;
+    });
+}
+
+int mtf_batch_assembly_stats(mtf_batch b, int64_t* counts, double* seconds, int32_t* config) {
+    return guarded([&] {
+        if (!b) throw ArgError("batch is NULL");
+        if (counts) {
+            for (int c = 0; c < 4; ++c) counts[c] = 0;
+            for (mtf_problem p : b->probs) {
+                int64_t pc[4];
+                const int r = mtf_assembly_stats(p, pc, nullptr);
+                if (r < 0) throw StateError(g_err);
+                for (int c = 0; c < 4; ++c) counts[c] += pc[c];
+            }
+        }
+        if (seconds) {
+            seconds[0] = b->last_tiles_s;
+            seconds[1] = b->last_total_s - b->last_tiles_s;
+        }
+        if (config) {
+            config[0] = b->last_variant;
+            config[1] = b->last_grid;
+        }
+        return MTF_OK;
+    });
+}
+
+int mtf_batch_build_preconditioner(mtf_batch b, int32_t flags) {
+    return guarded([&] {
+        if (!b) throw ArgError("batch is NULL");
+        if (flags & ~MTF_SOLVE_PC_FULL) throw ArgError("flags: only MTF_SOLVE_PC_FULL is accepted");
+        DeviceGuard g(b->device);
+        for (mtf_problem p : b->probs) {
+            if (!p->has_mesh || !p->has_mat) throw StateError("problem lost its mesh or materials");
+            if (!p->have32 && !p->have64) throw StateError("mtf_batch_build_preconditioner: assemble the batch first");
+        }
+        batch_build_tinv(b->probs, (flags & MTF_SOLVE_PC_FULL) != 0, b->stream);
         return MTF_OK;
     });
 }
@@ -2011,35 +2531,98 @@ int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, c
                     mtf_solve_stats* stats) {
     return guarded([&] {
         if (!b || !b_dev || !x_dev) throw ArgError("bad arguments");
-        int status = MTF_OK;
-        for (size_t i = 0; i < b->probs.size(); ++i) {
-            mtf_problem p = b->probs[i];
+        const size_t np = b->probs.size();
+        for (size_t i = 0; i < np; ++i)
             if (!b_dev[i] || !x_dev[i]) throw ArgError("NULL right-hand side or solution");
-            const bool tmp64 = !p->have64, tmpinv = !p->have_tinv, tmpwork = p->gw.V.n == 0;
-            if (tmp64) {
+        // max_iters 0: cycles of at most kBatchCycle steps.  The Krylov storage of a cycle is
+        // allocated per problem; sized from free memory it would be gigabytes per problem for
+        // solves that take tens of steps, and allocating it would dominate the batch.
+        mtf_solve_opts o{};
+        o.struct_size = sizeof(o);
+        o.rtol = 1e-6;
+        if (opts) {
+            if (opts->struct_size < (int)sizeof(mtf_solve_opts)) throw ArgError("mtf_solve_opts.struct_size too small");
+            o = *opts;
+        }
+        if (o.max_iters == 0) o.max_iters = kBatchCycle;
+        const bool pc_full = (o.flags & MTF_SOLVE_PC_FULL) != 0;
+        DeviceGuard g(b->device);
+        // what each problem held before the call; whatever the call creates beyond that is released
+        // when the problem's solve ends, also when it ends with an error
+        std::vector<char> tmpinv(np), tmpwork(np);
+        for (size_t i = 0; i < np; ++i) {
+            mtf_problem p = b->probs[i];
+            if (!p->has_mesh || !p->has_mat) throw StateError("problem lost its mesh or materials");
+            tmpinv[i] = !p->have_tinv;
+            tmpwork[i] = p->gw.V.n == 0;
+        }
+        struct Release {
+            mtf_problem p;
+            bool tmp64 = false, tmpinv = false, tmpwork = false;
+            ~Release() {
+                if (!p) return;
+                (void)hipStreamSynchronize(p->stream);
+                if (tmp64) { p->T64.reset(); p->K64.reset(); p->near64.reset(); p->have64 = false; }
+                if (tmpinv) { p->Tinv.reset(); p->have_tinv = false; p->gp.haveA = false; }
+                if (tmpwork) p->gw.release();
+            }
+        };
+        // the preconditioner blocks of every problem that lacks them, built together
+        double t_pc = 0.0;
+        if (o.preconditioner != MTF_PREC_NONE) {
+            std::vector<mtf_problem> need;
+            for (size_t i = 0; i < np; ++i) {
+                mtf_problem p = b->probs[i];
+                if (!p->have32 && !p->have64) throw StateError("mtf_batch_solve: assemble the batch first");
+                if (!p->have_tinv || p->pc_force_full != pc_full) need.push_back(p);
+            }
+            if (!need.empty()) {
+                try {
+                    t_pc = batch_build_tinv(need, pc_full, b->stream);
+                } catch (...) {
+                    for (size_t i = 0; i < np; ++i)
+                        if (tmpinv[i]) { b->probs[i]->Tinv.reset(); b->probs[i]->have_tinv = false; }
+                    throw;
+                }
+            }
+        }
+        // problems not reached when a solve fails: release the preconditioner blocks built above
+        size_t next = 0;
+        struct Rest {
+            const std::vector<mtf_problem>& ps;
+            const std::vector<char>& tmp;
+            size_t& next;
+            ~Rest() {
+                for (size_t j = next; j < ps.size(); ++j)
+                    if (tmp[j]) { ps[j]->Tinv.reset(); ps[j]->have_tinv = false; ps[j]->gp.haveA = false; }
+            }
+        } rest{b->probs, tmpinv, next};
+        int status = MTF_OK;
+        for (size_t i = 0; i < np; ++i) {
+            mtf_problem p = b->probs[i];
+            next = i + 1;
+            Release rel{p, !p->have64, (bool)tmpinv[i], false};
+            // a problem without a workspace of its own borrows the batch's (allocated once, for the
+            // largest problem met so far), so the Krylov buffers are not allocated per problem
+            struct Lend {
+                GmresWork& a;
+                GmresWork& b;
+                bool on;
+                ~Lend() {
+                    if (on) swap_work(a, b);
+                }
+            } lend{p->gw, b->gw, (bool)tmpwork[i]};
+            if (lend.on) swap_work(p->gw, b->gw);
+            if (rel.tmp64) {
                 mtf_assembly_opts ao{};
                 ao.struct_size = sizeof(ao);
                 ao.precision = MTF_FP64;
                 ao.singular_order = 4;
-                assemble_impl(p, &ao);
+                assemble_impl(p, &ao);       // the preconditioner stays: it was built from the FP32 blocks
             }
-            // max_iters 0: cycles of at most kBatchCycle steps.  The Krylov storage of a cycle is
-            // allocated per problem; sized from free memory it would be gigabytes per problem for
-            // solves that take tens of steps, and allocating it would dominate the batch.
-            mtf_solve_opts o{};
-            o.struct_size = sizeof(o);
-            o.rtol = 1e-6;
-            if (opts) {
-                if (opts->struct_size < (int)sizeof(mtf_solve_opts)) throw ArgError("mtf_solve_opts.struct_size too small");
-                o = *opts;
-            }
-            if (o.max_iters == 0) o.max_iters = kBatchCycle;
             const int r = solve_impl(p, 1, b_dev[i], x_dev[i], p->sk.N, &o, stats ? stats + i : nullptr);
             if (r != MTF_OK) status = r;
-            sync(p);
-            if (tmp64) { p->T64.reset(); p->K64.reset(); p->near64.reset(); p->have64 = false; }
-            if (tmpinv) { p->Tinv.reset(); p->have_tinv = false; p->gp.haveA = false; }
-            if (tmpwork) p->gw.release();
+            if (stats) stats[i].t_precond_s = i == 0 ? t_pc : 0.0;
         }
         return status;
     });

@@ -66,12 +66,15 @@ void launch_tri_setup_rule(const double* xyz, const int32_t* verts, int64_t nrec
                            const double* w6, TriGeom* geom, hipStream_t s);
 
 // Separated pairs over tiles (int4: dom, x0, y0, unused) of 16 x 16 triangles.
-void launch_regular_f64(const int4* tiles, int64_t ntiles, const DomDesc* doms, const TriGeom* geom,
-                        const int32_t* verts, const int32_t* tdof, const int8_t* tsign,
-                        double* T, double* K, hipStream_t s);
-void launch_regular_f32(const int4* tiles, int64_t ntiles, const DomDesc* doms, const TriGeom* geom,
-                        const int32_t* verts, const int32_t* tdof, const int8_t* tsign,
-                        float* T, float* K, hipStream_t s);
+// Separated-pair tiles: variant v (0..kTileVariants-1) is a tile of tx test x ty trial triangles
+// (tx * ty threads) compiled for at least `occ` resident waves per SIMD; tiles: int4(subdomain,
+// first test triangle, first trial triangle, 0) stepping by tx and ty.  precision 0 = FP64 blocks,
+// 1 = FP32 (T, K point to double or float).
+constexpr int kTileVariants = 5;
+void tile_variant_shape(int v, int* tx, int* ty, int* occ);
+void launch_regular(int precision, int variant, const int4* tiles, int64_t ntiles, const DomDesc* doms,
+                    const TriGeom* geom, const int32_t* verts, const int32_t* tdof, const int8_t* tsign, void* T,
+                    void* K, hipStream_t s);
 
 // Touching pairs (Sauter-Schwab, FP64 arithmetic), results added to FP64 or FP32 blocks.
 void launch_singular(const SingPair* pairs, int64_t npairs, const DomDesc* doms, const TriGeom* geom,
@@ -79,11 +82,11 @@ void launch_singular(const SingPair* pairs, int64_t npairs, const DomDesc* doms,
                      const double* ss_table, const int32_t* ss_off, const int32_t* ss_cnt,
                      double* T64, double* K64, float* T32, float* K32, hipStream_t s);
 
-// One persistent launch over the work items of a batch of problems (precision 0 = FP64, 1 = FP32
-// separated pairs); `counter` must be zero; grid = number of persistent workgroups.
-void launch_assemble_persistent(int precision, const int4* items, int64_t nitems, unsigned long long* counter,
-                                const BatchProb* probs, const double* ss_table, const int32_t* ss_off,
-                                const int32_t* ss_cnt, int grid, hipStream_t s);
+// One persistent launch over the separated-pair tiles of a batch of problems (precision 0 = FP64,
+// 1 = FP32; tile variant as for launch_regular; items: int4(problem, subdomain, first test triangle,
+// first trial triangle)); `counter` must be zero; grid = number of persistent workgroups.
+void launch_assemble_persistent(int precision, int variant, const int4* items, int64_t nitems,
+                                unsigned long long* counter, const BatchProb* probs, int grid, hipStream_t s);
 
 // Signed local transmission values and column indices per triangle record.
 void launch_gram_local(const DomDesc* doms, int ndom, int64_t nrec, const int32_t* rec_dom,
@@ -218,6 +221,25 @@ void launch_gs_residual(const DomDesc* doms, const int32_t* dof_dom, const int32
                         double* w, hipStream_t s);
 void launch_nonfinite_check(const float* A, int64_t n, int* flag, hipStream_t s);
 
+// Preconditioner blocks of many problems inverted together: each n x n diagonal block (of T_i or
+// of one connected component of Gamma_i) is copied into an S x S slot of a bucket of equal S >= n,
+// with the identity in the padding (the inverse of diag(A, I) is diag(A^-1, I)), so that a bucket
+// is one batched in-place inversion.
+struct PadBlock {
+    const void* src;     // first entry of the block (complex128 when f64, else complex64)
+    float* dst;          // where the inverse goes (complex64, leading dimension ld)
+    int64_t ld;          // leading dimension of src and dst (the E_i of the block's subdomain)
+    int32_t n;           // order of the block
+    int32_t f64;         // src is complex128
+};
+// buf + z S^2 (ld S) <- block z (symmetrised (A + A^T)/2 when sym), identity in the padding
+void launch_pad_gather(const PadBlock* blocks, int nblocks, int S, int sym, float* buf, hipStream_t s);
+// block z's destination <- the leading n x n part of buf + z S^2
+void launch_pad_scatter(const PadBlock* blocks, int nblocks, int S, const float* buf, hipStream_t s);
+// y = A x for one n x n complex128 block A (ld lda), complex64 x and y; part: ceil(n/256) * n
+// complex64 scratch
+void launch_cgemv_f64src(const double* A, int64_t lda, const float* x, int n, float* part, float* y, hipStream_t s);
+
 // Multi-RHS block products (gemm.hip).
 // mode 0: operator blocks [K_i | T_i]; mode 1: preconditioner blocks T_i^-1 (passed as T).
 void launch_split_A(const GemmDesc* descs, const DomDesc* doms, const int4* tiles, int64_t ntiles, const float* T,
@@ -244,6 +266,9 @@ void launch_adam(float* p, const float* g, float* m1, float* m2, int64_t n, floa
 void launch_gather_rows(const float* X, const int* idx, int B, int cols, float* Xb, hipStream_t s);
 void launch_cgemm_hn(int m, int n, int k, const float* A, int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc,
                      hipStream_t s);
+// C = op(A) B in complex128, op(A) = A (m x k) or A^H (A stored k x m) (POD of FP64 snapshots)
+void launch_zgemm(int m, int n, int k, bool herm_a, const double* A, int64_t lda, const double* B, int64_t ldb,
+                  double* C, int64_t ldc, hipStream_t s);
 void launch_c128_to_c64(const double* X, int64_t ld, int64_t n, int cols, float* Y, hipStream_t s);
 void launch_c64_to_c128(const float* X, int64_t n, int cols, double* Y, int64_t ld, hipStream_t s);
 }  // namespace mtf

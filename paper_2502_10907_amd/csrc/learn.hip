@@ -156,6 +156,67 @@ __global__ __launch_bounds__(256) void k_cgemm_hn(int m, int n, int k, const flo
 }
 
 // complex128 [cols][ld] -> complex64 [cols][n]
+// C = op(A) B in complex128 (column-major): op(A) = A (m x k, ld lda) when HERM is false, A^H (A
+// stored k x m, ld lda) when true.  64 x 64 tile, k-tile 8, each thread 4 x 4 outputs; FP64 FMA.
+template <bool HERM>
+__global__ __launch_bounds__(256) void k_zgemm(int m, int n, int k, const double* __restrict__ A, int64_t lda,
+                                               const double* __restrict__ B, int64_t ldb, double* __restrict__ C,
+                                               int64_t ldc) {
+    __shared__ double2 As[8][64 + 1];
+    __shared__ double2 Bs[8][64 + 1];
+    const int tid = threadIdx.x;
+    const int tr = tid & 15, tc = tid >> 4;
+    const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
+    double acc[4][4][2];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) acc[i][j][0] = acc[i][j][1] = 0.0;
+    const double2* A2 = reinterpret_cast<const double2*>(A);
+    const double2* B2 = reinterpret_cast<const double2*>(B);
+    for (int k0 = 0; k0 < k; k0 += 8) {
+        for (int e = tid; e < 512; e += 256) {
+            const int kk = e & 7, r = e >> 3;
+            const int gk = k0 + kk;
+            const int gr = row0 + r;
+            double2 a = make_double2(0.0, 0.0);
+            if (gr < m && gk < k) {
+                if (HERM) {
+                    a = A2[gk + (int64_t)gr * lda];
+                    a.y = -a.y;                          // conjugate
+                } else {
+                    a = A2[gr + (int64_t)gk * lda];
+                }
+            }
+            As[kk][r] = a;
+            const int gc = col0 + r;
+            Bs[kk][r] = (gc < n && gk < k) ? B2[gk + (int64_t)gc * ldb] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+            double2 a[4], b[4];
+            for (int i = 0; i < 4; ++i) a[i] = As[kk][tr + 16 * i];
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tc + 16 * j];
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    acc[i][j][0] = fma(a[i].x, b[j].x, fma(-a[i].y, b[j].y, acc[i][j][0]));
+                    acc[i][j][1] = fma(a[i].x, b[j].y, fma(a[i].y, b[j].x, acc[i][j][1]));
+                }
+        }
+        __syncthreads();
+    }
+    for (int i = 0; i < 4; ++i) {
+        const int gr = row0 + tr + 16 * i;
+        if (gr >= m) continue;
+        for (int j = 0; j < 4; ++j) {
+            const int gc = col0 + tc + 16 * j;
+            if (gc >= n) continue;
+            double* c = C + 2 * (gr + (int64_t)gc * ldc);
+            c[0] = acc[i][j][0];
+            c[1] = acc[i][j][1];
+        }
+    }
+}
+
 __global__ void k_c128_to_c64(const double* __restrict__ X, int64_t ld, int64_t n, int cols, float* __restrict__ Y) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
@@ -211,6 +272,17 @@ void launch_cgemm_hn(int m, int n, int k, const float* A, int64_t lda, const flo
                      hipStream_t s) {
     if (m <= 0 || n <= 0) return;
     hipLaunchKernelGGL(k_cgemm_hn, dim3(gridn(m, 64), gridn(n, 64)), dim3(256), 0, s, m, n, k, A, lda, B, ldb, C, ldc);
+}
+
+void launch_zgemm(int m, int n, int k, bool herm_a, const double* A, int64_t lda, const double* B, int64_t ldb,
+                  double* C, int64_t ldc, hipStream_t s) {
+    if (m <= 0 || n <= 0) return;
+    if (herm_a)
+        hipLaunchKernelGGL(k_zgemm<true>, dim3(gridn(m, 64), gridn(n, 64)), dim3(256), 0, s, m, n, k, A, lda, B, ldb, C,
+                           ldc);
+    else
+        hipLaunchKernelGGL(k_zgemm<false>, dim3(gridn(m, 64), gridn(n, 64)), dim3(256), 0, s, m, n, k, A, lda, B, ldb,
+                           C, ldc);
 }
 
 void launch_c128_to_c64(const double* X, int64_t ld, int64_t n, int cols, float* Y, hipStream_t s) {

@@ -89,21 +89,18 @@ void orthonormalise(std::vector<cd>& X, int m, int q) {
     }
 }
 
-void upload_c64(DevBuf<float>& d, const std::vector<cd>& h, hipStream_t s) {
-    std::vector<float> f(2 * h.size());
-    for (size_t i = 0; i < h.size(); ++i) { f[2 * i] = (float)h[i].real(); f[2 * i + 1] = (float)h[i].imag(); }
-    d.upload(f, s);
-    HIPCHK(hipStreamSynchronize(s));
+void upload_c128(DevBuf<double>& d, const std::vector<cd>& h, hipStream_t s) {
+    d.alloc(2 * h.size());
+    HIPCHK(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(cd), hipMemcpyHostToDevice, s));
 }
 
-std::vector<cd> download_c64(const float* d, size_t n, hipStream_t s) {
-    std::vector<float> f(2 * n);
-    HIPCHK(hipMemcpyAsync(f.data(), d, f.size() * sizeof(float), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+std::vector<cd> download_c128(const double* d, size_t n, hipStream_t s) {
     std::vector<cd> h(n);
-    for (size_t i = 0; i < n; ++i) h[i] = cd(f[2 * i], f[2 * i + 1]);
+    HIPCHK(hipMemcpyAsync(h.data(), d, n * sizeof(cd), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
     return h;
 }
+
 
 }  // namespace
 
@@ -196,11 +193,10 @@ int mtf_pod_build(mtf_problem p, int32_t nsnap, const void* U_dev, int64_t ldu, 
             throw ArgError("mtf_pod_build: bad sizes or pointers");
         DeviceGuard g(dev);
         const int q = std::min<int>(nsnap, r + 16);
-        DevBuf<float> U, G, X, Y, Z, Phi;
-        U.alloc(2 * (size_t)N * nsnap);
-        launch_c128_to_c64(static_cast<const double*>(U_dev), ldu, N, nsnap, U.p, s);
+        const double* U = static_cast<const double*>(U_dev);
+        DevBuf<double> G, X, Y, Z;
         G.alloc(2 * (size_t)nsnap * nsnap);
-        launch_cgemm_hn(nsnap, nsnap, (int)N, U.p, N, U.p, N, G.p, nsnap, s);   // G = U^H U
+        launch_zgemm(nsnap, nsnap, (int)N, true, U, ldu, U, ldu, G.p, nsnap, s);   // G = U^H U
         // subspace iteration on G
         uint64_t st = 0x5EEDull + nsnap;
         std::vector<cd> Xh((size_t)nsnap * q);
@@ -209,9 +205,9 @@ int mtf_pod_build(mtf_problem p, int32_t nsnap, const void* U_dev, int64_t ldu, 
         Y.alloc(2 * (size_t)nsnap * q);
         std::vector<double> prev(q, 0.0);
         for (int it = 0; it < 60; ++it) {
-            upload_c64(X, Xh, s);
-            launch_cgemm_f32(nsnap, q, nsnap, 1.f, 0.f, G.p, nsnap, X.p, nsnap, 0.f, nullptr, 0, Y.p, nsnap, s);
-            std::vector<cd> Yh = download_c64(Y.p, (size_t)nsnap * q, s);
+            upload_c128(X, Xh, s);
+            launch_zgemm(nsnap, q, nsnap, false, G.p, nsnap, X.p, nsnap, Y.p, nsnap, s);
+            std::vector<cd> Yh = download_c128(Y.p, (size_t)nsnap * q, s);
             // Rayleigh quotients for the convergence test
             std::vector<double> rq(q);
             for (int j = 0; j < q; ++j) {
@@ -224,12 +220,12 @@ int mtf_pod_build(mtf_problem p, int32_t nsnap, const void* U_dev, int64_t ldu, 
             double ch = 0.0;
             for (int j = 0; j < r; ++j) ch = std::max(ch, std::fabs(rq[j] - prev[j]) / std::max(1e-300, std::fabs(rq[j])));
             prev = rq;
-            if (it > 3 && ch < 1e-6) break;
+            if (it > 3 && ch < 1e-10) break;
         }
         // Rayleigh-Ritz: H = X^H G X (q x q Hermitian) as a real symmetric 2q x 2q matrix
-        upload_c64(X, Xh, s);
-        launch_cgemm_f32(nsnap, q, nsnap, 1.f, 0.f, G.p, nsnap, X.p, nsnap, 0.f, nullptr, 0, Y.p, nsnap, s);
-        std::vector<cd> GX = download_c64(Y.p, (size_t)nsnap * q, s);
+        upload_c128(X, Xh, s);
+        launch_zgemm(nsnap, q, nsnap, false, G.p, nsnap, X.p, nsnap, Y.p, nsnap, s);
+        std::vector<cd> GX = download_c128(Y.p, (size_t)nsnap * q, s);
         std::vector<cd> H((size_t)q * q);
         for (int i = 0; i < q; ++i)
             for (int j = 0; j < q; ++j) {
@@ -281,10 +277,8 @@ int mtf_pod_build(mtf_problem p, int32_t nsnap, const void* U_dev, int64_t ldu, 
                 for (int k = 0; k < nsnap; ++k) Zh[(size_t)j * nsnap + k] += Xh[(size_t)i * nsnap + k] * keep[j][i] * sc;
             sv[j] = std::sqrt(lam[j]);
         }
-        upload_c64(Z, Zh, s);
-        Phi.alloc(2 * (size_t)N * r);
-        launch_cgemm_f32((int)N, r, nsnap, 1.f, 0.f, U.p, N, Z.p, nsnap, 0.f, nullptr, 0, Phi.p, N, s);
-        launch_c64_to_c128(Phi.p, N, r, static_cast<double*>(Phi_dev), ldphi, s);
+        upload_c128(Z, Zh, s);
+        launch_zgemm((int)N, r, nsnap, false, U, ldu, Z.p, nsnap, static_cast<double*>(Phi_dev), ldphi, s);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(s));
         return MTF_OK;
@@ -300,14 +294,8 @@ int mtf_pod_project(mtf_problem p, int32_t r, const void* Phi_dev, int64_t ldphi
         problem_info(p, &dev, &s, &N);
         if (r < 1 || n < 1 || !Phi_dev || !X_dev || !C_dev || ldphi < N || ldx < N) throw ArgError("mtf_pod_project: bad arguments");
         DeviceGuard g(dev);
-        DevBuf<float> P, X, C;
-        P.alloc(2 * (size_t)N * r);
-        X.alloc(2 * (size_t)N * n);
-        C.alloc(2 * (size_t)r * n);
-        launch_c128_to_c64(static_cast<const double*>(Phi_dev), ldphi, N, r, P.p, s);
-        launch_c128_to_c64(static_cast<const double*>(X_dev), ldx, N, n, X.p, s);
-        launch_cgemm_hn(r, n, (int)N, P.p, N, X.p, N, C.p, r, s);
-        launch_c64_to_c128(C.p, r, n, static_cast<double*>(C_dev), r, s);
+        launch_zgemm(r, n, (int)N, true, static_cast<const double*>(Phi_dev), ldphi, static_cast<const double*>(X_dev),
+                     ldx, static_cast<double*>(C_dev), r, s);     // C = Phi^H X
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(s));
         return MTF_OK;
@@ -323,14 +311,8 @@ int mtf_pod_expand(mtf_problem p, int32_t r, const void* Phi_dev, int64_t ldphi,
         problem_info(p, &dev, &s, &N);
         if (r < 1 || n < 1 || !Phi_dev || !X_dev || !C_dev || ldphi < N || ldx < N) throw ArgError("mtf_pod_expand: bad arguments");
         DeviceGuard g(dev);
-        DevBuf<float> P, C, X;
-        P.alloc(2 * (size_t)N * r);
-        C.alloc(2 * (size_t)r * n);
-        X.alloc(2 * (size_t)N * n);
-        launch_c128_to_c64(static_cast<const double*>(Phi_dev), ldphi, N, r, P.p, s);
-        launch_c128_to_c64(static_cast<const double*>(C_dev), r, r, n, C.p, s);
-        launch_cgemm_f32((int)N, n, r, 1.f, 0.f, P.p, N, C.p, r, 0.f, nullptr, 0, X.p, N, s);
-        launch_c64_to_c128(X.p, N, n, static_cast<double*>(X_dev), ldx, s);
+        launch_zgemm((int)N, n, r, false, static_cast<const double*>(Phi_dev), ldphi, static_cast<const double*>(C_dev),
+                     r, static_cast<double*>(X_dev), ldx, s);     // X = Phi C
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(s));
         return MTF_OK;

@@ -26,6 +26,9 @@ struct OomError : std::runtime_error {
 struct NonFiniteError : std::runtime_error {
     explicit NonFiniteError(const std::string& s) : std::runtime_error(s) {}
 };
+struct UnsupportedError : std::runtime_error {
+    explicit UnsupportedError(const std::string& s) : std::runtime_error(s) {}
+};
 
 #define HIPCHK(x)                                                                          \
     do {                                                                                   \
@@ -101,6 +104,8 @@ int guarded(F&& f) {
         return fail(MTF_ERR_OOM, e.what());
     } catch (const NonFiniteError& e) {
         return fail(MTF_ERR_NONFINITE, e.what());
+    } catch (const UnsupportedError& e) {
+        return fail(MTF_ERR_UNSUPPORTED, e.what());
     } catch (const HipError& e) {
         return fail(MTF_ERR_HIP, e.what());
     } catch (const std::bad_alloc&) {

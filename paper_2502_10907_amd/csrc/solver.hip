@@ -1398,6 +1398,67 @@ __global__ __launch_bounds__(256) void k_cgemv_part(const float2* __restrict__ A
     part[z * sp + (int64_t)blockIdx.y * n + r] = make_float2(re, im);
 }
 
+// k_cgemv_part for a complex128 matrix (converted to FP32 on load), one matrix.
+__global__ __launch_bounds__(256) void k_cgemv_part_f64src(const double2* __restrict__ A, int64_t lda,
+                                                           const float2* __restrict__ x, int n,
+                                                           float2* __restrict__ part) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    const int c0 = blockIdx.y * 256, c1 = min(n, c0 + 256);
+    if (r >= n) return;
+    const double2* Ar = A + r;
+    float re = 0.f, im = 0.f;
+    for (int k = c0; k < c1; ++k) {
+        const double2 ad = Ar[(int64_t)k * lda];
+        const float2 a = make_float2((float)ad.x, (float)ad.y), b = x[k];
+        re = fmaf(a.x, b.x, fmaf(-a.y, b.y, re));
+        im = fmaf(a.x, b.y, fmaf(a.y, b.x, im));
+    }
+    part[(int64_t)blockIdx.y * n + r] = make_float2(re, im);
+}
+
+// Padded gather of preconditioner blocks: workgroup (x, z) fills 256 consecutive entries (in
+// column-major order) of slot z.  The transposed read of the symmetrisation is uncoalesced; the
+// gather streams each block once and is small beside the inversion.
+__global__ __launch_bounds__(256) void k_pad_gather(const PadBlock* __restrict__ blocks, int S, int sym,
+                                                    float2* __restrict__ buf) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t SS = (int64_t)S * S;
+    if (e >= SS) return;
+    const int64_t z = blockIdx.y;
+    const PadBlock b = blocks[z];
+    const int r = (int)(e % S), c = (int)(e / S);
+    float2 v = make_float2(r == c ? 1.f : 0.f, 0.f);
+    if (r < b.n && c < b.n) {
+        if (b.f64) {
+            const double2* A = static_cast<const double2*>(b.src);
+            double2 a = A[r + (int64_t)c * b.ld];
+            if (sym) {
+                const double2 t = A[c + (int64_t)r * b.ld];
+                a = make_double2(0.5 * (a.x + t.x), 0.5 * (a.y + t.y));
+            }
+            v = make_float2((float)a.x, (float)a.y);
+        } else {
+            const float2* A = static_cast<const float2*>(b.src);
+            v = A[r + (int64_t)c * b.ld];
+            if (sym) {
+                const float2 t = A[c + (int64_t)r * b.ld];
+                v = make_float2(0.5f * (v.x + t.x), 0.5f * (v.y + t.y));
+            }
+        }
+    }
+    buf[z * SS + e] = v;
+}
+
+__global__ __launch_bounds__(256) void k_pad_scatter(const PadBlock* __restrict__ blocks, int S,
+                                                     const float2* __restrict__ buf) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t z = blockIdx.y;
+    const PadBlock b = blocks[z];
+    if (e >= (int64_t)b.n * b.n) return;
+    const int r = (int)(e % b.n), c = (int)(e / b.n);
+    reinterpret_cast<float2*>(b.dst)[r + (int64_t)c * b.ld] = buf[z * (int64_t)S * S + r + (int64_t)c * S];
+}
+
 __global__ void k_cgemv_sum(const float2* __restrict__ part, int n, int nch, int64_t sp, float2* __restrict__ y,
                             int64_t sy) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1596,6 +1657,28 @@ int launch_cinv_small_f32(float* A, int64_t lda, int64_t stride, int n, int batc
     if (n <= 0 || n > 64 || batch <= 0) return -1;
     hipLaunchKernelGGL(k_cinv_small, dim3((unsigned)batch), dim3(1024), 0, s, A, lda, stride, n, info);
     return 0;
+}
+
+void launch_pad_gather(const PadBlock* blocks, int nblocks, int S, int sym, float* buf, hipStream_t s) {
+    if (nblocks <= 0) return;
+    hipLaunchKernelGGL(k_pad_gather, dim3(gridn((int64_t)S * S, 256), (unsigned)nblocks), dim3(256), 0, s, blocks, S,
+                       sym, reinterpret_cast<float2*>(buf));
+}
+
+void launch_pad_scatter(const PadBlock* blocks, int nblocks, int S, const float* buf, hipStream_t s) {
+    if (nblocks <= 0) return;
+    hipLaunchKernelGGL(k_pad_scatter, dim3(gridn((int64_t)S * S, 256), (unsigned)nblocks), dim3(256), 0, s, blocks, S,
+                       reinterpret_cast<const float2*>(buf));
+}
+
+void launch_cgemv_f64src(const double* A, int64_t lda, const float* x, int n, float* part, float* y, hipStream_t s) {
+    if (n <= 0) return;
+    const int nch = (n + 255) / 256;
+    hipLaunchKernelGGL(k_cgemv_part_f64src, dim3((unsigned)nch, (unsigned)nch), dim3(256), 0, s,
+                       reinterpret_cast<const double2*>(A), lda, reinterpret_cast<const float2*>(x), n,
+                       reinterpret_cast<float2*>(part));
+    hipLaunchKernelGGL(k_cgemv_sum, dim3(gridn(n, 256), 1u), dim3(256), 0, s, reinterpret_cast<const float2*>(part), n,
+                       nch, (int64_t)nch * n, reinterpret_cast<float2*>(y), (int64_t)0);
 }
 
 void launch_nonfinite_check(const float* A, int64_t n, int* flag, hipStream_t s) {

@@ -5,6 +5,8 @@ times: FP64 assembly, block Gauss-Seidel T^-1 preconditioner, GMRES to 1e-6) and
 4x4x4 partition at h = 1/24 (N = 103,680, FP32 blocks).  Sampled entries include touching
 pairs (Sauter-Schwab) and both operators; the solution is checked through oracle rows of M.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -149,3 +151,113 @@ def test_full_size_tinv_residual(c2):
         r = np.linalg.norm(S @ (z[o:o + E] * (-2 * rho)) - vN) / np.linalg.norm(vN)
         print(f"[T_{i}^-1 full size] E={E} residual {r:.2e}", flush=True)
         assert r < 1e-4
+
+
+# ---------------------------------------------------------------------------
+# solutions against the oracle's LU solutions (stored by tests/golden/make_*.py, oracle only)
+# ---------------------------------------------------------------------------
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _elementwise(x, ref):
+    """Largest |x_m - ref_m| over max |ref|: every entry of the solution, not a norm."""
+    return float(np.abs(x - ref).max() / np.abs(ref).max())
+
+
+def test_full_size_solution_matches_oracle_lu(c2):
+    """The bench configuration's solve (FP64 assembly, block Gauss-Seidel T^-1, GMRES) against the
+    oracle's LU solution of the same N = 27,648 system, entry by entry.  With the FP64 residual at
+    rtol the error is at most cond(M) rtol; the LU's condition estimate bounds it.  The mixed path
+    (complex64 blocks, relaxed complex64 products, FP64 refinement) reaches the 1e-6 target once its
+    FP64 residual is driven to 1e-8."""
+    cfg, P, pb = c2
+    g = np.load(os.path.join(GOLDEN, "cube2x2x2_h16_solution.npz"))
+    xo, bo, rcond = g["x"], g["b"], float(g["rcond"])
+    b = torch.zeros((1, P.N), dtype=torch.complex128, device="cuda")
+    P.rhs_plane_waves(cfg["d"], cfg["p"], b)
+    assert np.abs(b[0].cpu().numpy() - bo).max() < 1e-13 * np.abs(bo).max()
+    P.assemble(mtf.FP64)
+    for rtol in (1e-6, 1e-10):
+        x = torch.zeros_like(b)
+        st = P.solve(b, x, rtol=rtol, preconditioner=mtf.PREC_BLOCK_TINV_GS, max_iters=4000)[0]
+        err = _elementwise(x[0].cpu().numpy(), xo)
+        print(f"[C2 FP64 rtol {rtol:g}] iterations {st.iterations} residual {st.rel_residual:.2e} "
+              f"entrywise error vs oracle LU {err:.2e} (1/rcond {1 / rcond:.1e})", flush=True)
+        assert st.converged and err <= min(1e-3, 4 * rtol / rcond)
+        if rtol == 1e-10:
+            assert err < 1e-8
+    for name, flags in (("rounded FP64 blocks", mtf.ASSEMBLE_ROUND_FP64), ("FP32 quadrature", 0)):
+        P.assemble(mtf.FP32_MIXED, flags=flags)
+        for rtol in (1e-6, 1e-8):
+            x = torch.zeros_like(b)
+            st = P.solve(b, x, rtol=rtol, precision=mtf.FP32_MIXED, preconditioner=mtf.PREC_BLOCK_TINV_GS,
+                         max_iters=4000)[0]
+            err = _elementwise(x[0].cpu().numpy(), xo)
+            print(f"[C2 mixed, {name}, rtol {rtol:g}] iterations {st.iterations} refinements {st.refinements} "
+                  f"residual {st.rel_residual:.2e} entrywise error vs oracle LU {err:.2e}", flush=True)
+            assert st.converged and err <= min(1e-3, 4 * rtol / rcond)
+            if rtol == 1e-8:
+                assert err <= 1e-6
+
+
+def test_full_size_cluster_batch_matches_oracle():
+    """The 64-cluster batch in the bench's launch configuration (one persistent FP64 assembly of all
+    clusters, preconditioners built together, GMRES per cluster): sampled entries of T_i, K_i of the
+    largest and smallest clusters against the oracle's entries computed one by one (touching pairs
+    included), and the four smallest clusters' solutions against the oracle's LU solutions, entry by
+    entry, in FP64 and on the mixed path."""
+    cl = mi.config_clusters(64, seed=0)
+    g = np.load(os.path.join(GOLDEN, "clusters64_smallest4_solutions.npz"))
+    small = [int(i) for i in g["indices"]]
+    print(f"\n[case] 64 clusters, FP64 batch; oracle solutions of clusters {small}", flush=True)
+
+    def problems():
+        out = []
+        for c in cl:
+            m = c["mesh"]
+            P = mtf.Problem(0)
+            P.set_mesh(m.xyz, m.tri, m.label, m.M)
+            P.set_materials(c["k0"], c["eps_r"], c["mu_r"])
+            out.append(P)
+        return out
+
+    probs = problems()
+    B = mtf.Batch(probs)
+    B.assemble(mtf.FP64)
+    sizes = sorted((P.N, i) for i, P in enumerate(probs))
+    rng = np.random.default_rng(21)
+    for _, ci in (sizes[-1], sizes[-2], sizes[0]):
+        pb = sy.Problem.from_config(cl[ci])
+        _check_entries(probs[ci], pb, mtf.FP64, rng, [0, 1], 6, 1e-11)
+    bs = [torch.zeros((1, P.N), dtype=torch.complex128, device="cuda") for P in probs]
+    for P, c, b in zip(probs, cl, bs):
+        P.rhs_plane_waves(c["d"], c["p"], b)
+    for ci in small:
+        assert np.abs(bs[ci][0].cpu().numpy() - g[f"b_{ci}"]).max() < 1e-13 * np.abs(g[f"b_{ci}"]).max()
+    xs = [torch.zeros_like(b) for b in bs]
+    st = B.solve(bs, xs, rtol=1e-10, precision=mtf.FP64, preconditioner=mtf.PREC_BLOCK_TINV_GS)
+    assert all(s.converged for s in st)
+    for ci in small:
+        err = _elementwise(xs[ci][0].cpu().numpy(), g[f"x_{ci}"])
+        print(f"[cluster {ci} FP64 rtol 1e-10] iterations {st[ci].iterations} entrywise error {err:.2e}", flush=True)
+        assert err < 1e-7
+    B.close()
+    for P in probs:
+        P.close()
+    del probs, B
+
+    probs = problems()
+    B = mtf.Batch(probs)
+    B.assemble(mtf.FP32_MIXED)
+    xs = [torch.zeros_like(b) for b in bs]
+    st = B.solve(bs, xs, rtol=1e-8, precision=mtf.FP32_MIXED, preconditioner=mtf.PREC_BLOCK_TINV_GS)
+    assert all(s.converged and s.rel_residual <= 1e-8 for s in st)
+    for ci in small:
+        err = _elementwise(xs[ci][0].cpu().numpy(), g[f"x_{ci}"])
+        print(f"[cluster {ci} mixed rtol 1e-8] iterations {st[ci].iterations} refinements {st[ci].refinements} "
+              f"entrywise error {err:.2e}", flush=True)
+        assert err <= 1e-6
+    B.close()
+    for P in probs:
+        P.close()

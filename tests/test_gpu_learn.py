@@ -3,7 +3,8 @@
 * MLP gradients: FP32 kernels vs the FP64 reverse-mode oracle (itself pinned by finite
   differences); FP32 accumulation over <= 256 terms bounds the relative error by ~1e-4.
 * POD: singular values and leading subspace vs the SVD of the same snapshots (numpy, FP64);
-  the library works in complex64, bound 1e-4.
+  the library works in complex128 (Gram matrix, subspace iteration to a 1e-10 change of the
+  Rayleigh quotients), bound 1e-9 on the singular values and the projections.
 """
 import numpy as np
 import pytest
@@ -65,16 +66,16 @@ def test_pod_matches_svd():
     Phi = torch.zeros((r, N), dtype=torch.complex128, device="cuda")
     sv = P.pod_build(Ud, r, Phi)
     Us, S, _ = np.linalg.svd(U, full_matrices=False)
-    assert np.allclose(sv, S[:r], rtol=1e-4)
+    assert np.allclose(sv, S[:r], rtol=1e-9)
     F = Phi.cpu().numpy().T
-    assert np.abs(F.conj().T @ F - np.eye(r)).max() < 1e-4
+    assert np.abs(F.conj().T @ F - np.eye(r)).max() < 1e-9
     # same leading subspace: projection of the exact singular vectors onto span(Phi)
     res = Us[:, :r] - F @ (F.conj().T @ Us[:, :r])
-    assert np.linalg.norm(res) < 1e-3
+    assert np.linalg.norm(res) < 1e-7
     # project / expand
     Cc = torch.zeros((nsnap, r), dtype=torch.complex128, device="cuda")
     P.pod_project(Phi, Ud, Cc)
-    assert np.abs(Cc.cpu().numpy() - (F.conj().T @ U).T).max() < 1e-4 * np.abs(U).max()
+    assert np.abs(Cc.cpu().numpy() - (F.conj().T @ U).T).max() < 1e-12 * np.abs(U).max()
     X = torch.zeros_like(Ud)
     P.pod_expand(Phi, Cc, X)
-    assert np.abs(X.cpu().numpy().T - F @ (F.conj().T @ U)).max() < 1e-4 * np.abs(U).max()
+    assert np.abs(X.cpu().numpy().T - F @ (F.conj().T @ U)).max() < 1e-12 * np.abs(U).max()

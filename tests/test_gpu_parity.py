@@ -598,3 +598,125 @@ def test_componentwise_exterior_block(cluster):
     assert st.converged and st.rel_residual <= 1e-10
     xh = xs[0].cpu().numpy()
     assert np.linalg.norm(xh - c.x) / np.linalg.norm(c.x) < 1e-7
+
+
+def _fresh(cfg, precisions=(mtf.FP64,)):
+    return _gpu_problem(cfg, precisions)
+
+
+def _check_blocks_against_lapack(case, P, sym, tag):
+    """z = P x (block Jacobi) of problem P against LAPACK solves with the oracle's T_i, symmetrised
+    when `sym`, per connected component of Gamma_0 (cond(block) x 3e-5, the FP32 inversion bound)."""
+    runs = _components(case.pb.spaces[0])
+    rng = np.random.default_rng(17)
+    x = rng.standard_normal(case.pb.N) + 1j * rng.standard_normal(case.pb.N)
+    xt = torch.tensor(x[None, :], device="cuda")
+    zt = torch.zeros_like(xt)
+    P.apply_preconditioner(xt, zt, mtf.PREC_BLOCK_TINV)
+    z = zt[0].cpu().numpy()
+    for i in range(case.pb.M + 1):
+        o, E, rho = case.pb.offsets[i], case.pb.E[i], case.pb.rho[i]
+        S = 0.5 * (case.T[i] + case.T[i].T) if sym else case.T[i]
+        for lo, hi in (runs if i == 0 else [(0, E)]):
+            Sc = S[lo:hi, lo:hi]
+            refD = -0.5 / rho * np.linalg.solve(Sc, x[o + E + lo:o + E + hi])
+            refN = 0.5 * rho * np.linalg.solve(Sc, x[o + lo:o + hi])
+            tol = np.linalg.cond(Sc) * 3e-5
+            eD = np.linalg.norm(z[o + lo:o + hi] - refD) / np.linalg.norm(refD)
+            eN = np.linalg.norm(z[o + E + lo:o + E + hi] - refN) / np.linalg.norm(refN)
+            print(f"[{tag} T_{i}^-1 dofs {lo}:{hi}] errors {eD:.2e} {eN:.2e} bound {tol:.1e}", flush=True)
+            assert eD <= tol and eN <= tol
+
+
+def test_batch_preconditioner_build_matches_lapack(cluster, sphere):
+    """Blocks of several problems built together (every diagonal block, or component block, padded
+    to a bucket of equal order and inverted in one batch) against LAPACK solves with the oracle's
+    symmetrised blocks; then the batch solve from those blocks reaches the LU solution."""
+    Pc, Ps = _fresh(cluster.cfg), _fresh(sphere.cfg, (mtf.FP64, mtf.FP32_MIXED))   # FP64 and FP32 sources
+    B = mtf.Batch([Pc, Ps])
+    B.build_preconditioner()
+    _check_blocks_against_lapack(cluster, Pc, True, "batch build cluster")
+    _check_blocks_against_lapack(sphere, Ps, True, "batch build sphere")
+    bs = [torch.tensor(c.b[None, :], device="cuda") for c in (cluster, sphere)]
+    xs = [torch.zeros_like(b) for b in bs]
+    st = B.solve(bs, xs, rtol=1e-10, preconditioner=mtf.PREC_BLOCK_TINV_GS, max_iters=3000)
+    for s, x, c in zip(st, xs, (cluster, sphere)):
+        assert s.converged and s.rel_residual <= 1e-10
+        assert np.linalg.norm(x[0].cpu().numpy() - c.x) / np.linalg.norm(c.x) < 1e-7
+    B.close()
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_preconditioner_rebuild_from_T_per_component(cluster, batched, monkeypatch):
+    """With the symmetric-part check threshold at 0 every block fails its check and is rebuilt as the
+    inverse of T_i itself, per connected component of Gamma_0: z = P x against LAPACK solves with the
+    oracle's unsymmetrised component blocks.  Single-problem and batched builds."""
+    monkeypatch.setenv("MTF_PC_SYM_TOL", "0")
+    P = _fresh(cluster.cfg)
+    if batched:
+        B = mtf.Batch([P])
+        B.build_preconditioner()
+    _check_blocks_against_lapack(cluster, P, False, "rebuilt" + (" batched" if batched else ""))
+    b = torch.tensor(cluster.b[None, :], device="cuda")
+    x = torch.zeros_like(b)
+    st = P.solve(b, x, rtol=1e-10, preconditioner=mtf.PREC_BLOCK_TINV_GS, max_iters=3000)[0]
+    assert st.converged and np.linalg.norm(x[0].cpu().numpy() - cluster.x) / np.linalg.norm(cluster.x) < 1e-7
+    if batched:
+        B.close()
+
+
+def test_batch_solve_default_cycle_restarts(sphere):
+    """mtf_batch_solve with max_iters 0 runs cycles of at most 1,000 Arnoldi steps: the sphere without
+    a preconditioner needs about 1,030 steps to 1e-10, so the default cycle must restart, and the
+    restarted solve must still reach the oracle's LU solution."""
+    P = _fresh(sphere.cfg)
+    B = mtf.Batch([P])
+    b = torch.tensor(sphere.b[None, :], device="cuda")
+    x = torch.zeros_like(b)
+    st = B.solve([b], [x], rtol=1e-10, preconditioner=mtf.PREC_NONE, max_iters=0)[0]
+    print(f"[batch default cycle] iterations {st.iterations} refinements {st.refinements} "
+          f"residual {st.rel_residual:.2e}", flush=True)
+    assert st.converged and st.rel_residual <= 1e-10
+    assert st.iterations > 1000 and st.refinements >= 1
+    assert np.linalg.norm(x[0].cpu().numpy() - sphere.x) / np.linalg.norm(sphere.x) < 1e-7
+    B.close()
+
+
+@pytest.mark.parametrize("prec", [mtf.FP64, mtf.FP32_MIXED])
+def test_tile_variants_and_autotuned_launch_agree(prec, ragged, sphere):
+    """Every tile variant (tile shape, workgroup size, occupancy) and the autotuned choice give the
+    same blocks up to the order of the atomic additions, in single-problem and persistent batch
+    launches; the ragged case's triangle counts are not multiples of any tile side."""
+    tol = 1e-13 if prec == mtf.FP64 else 2e-6
+    for case in (ragged, sphere):
+        P = _fresh(case.cfg, ())
+        ref = None
+        for v in range(mtf.TILE_VARIANTS):
+            P.assemble(prec, flags=mtf.assemble_tile(v))
+            assert P.assembly_variant() == v
+            blocks = [P.copy_block(i, w, prec) for i in range(P.M + 1) for w in (mtf.BLOCK_T, mtf.BLOCK_K)]
+            if ref is None:
+                ref = blocks
+                continue
+            for a, b in zip(blocks, ref):
+                assert np.abs(a - b).max() <= tol * np.abs(b).max(), (v, mtf.tile_variant(v))
+        P.assemble(prec)                                    # autotuned
+        assert 0 <= P.assembly_variant() < mtf.TILE_VARIANTS
+        for i in range(P.M + 1):
+            assert np.abs(P.copy_block(i, mtf.BLOCK_T, prec) - ref[2 * i]).max() <= tol * np.abs(ref[2 * i]).max()
+    # persistent batch launches
+    probs = [_fresh(c.cfg, ()) for c in (ragged, sphere)]
+    B = mtf.Batch(probs)
+    for v in (0, 1, 3):
+        B.assemble(prec, flags=mtf.assemble_tile(v))
+        assert B.assembly_stats()[2][0] == v
+        for Pb, c in zip(probs, (ragged, sphere)):
+            blk = c.T[0] if prec == mtf.FP64 else None
+            a = Pb.copy_block(0, mtf.BLOCK_T, prec)
+            if blk is not None:
+                assert np.abs(a - blk).max() < 1e-11 * np.abs(blk).max()
+    B.assemble(prec)
+    variant, grid = B.assembly_stats()[2]
+    assert 0 <= variant < mtf.TILE_VARIANTS and grid > 0
+    print(f"[autotuner] {mtf.tuning_log()}", flush=True)
+    B.close()
