@@ -281,6 +281,23 @@ typedef struct {
 int mtf_solve(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int64_t ld,
               const mtf_solve_opts* opts, mtf_solve_stats* stats);
 
+/* Single-trace (PMCHWT) formulation for M = 1 (the remark on the PMCHWT in Section 3.2): adding
+ * the two row blocks of Problem 2 with u_1 = -u_0 leaves one unknown pair u = u_0 = (u_0D, u_0N)
+ * on Gamma_0 and the system 2 (A_0 - A_1) u = 2 u_inc, discretely
+ *     M_STF = 2 A_0 + 2 Sigma A_1 Sigma,   phi^1_m = Sigma_mm phi^0_m (Sigma = -I on the reversed
+ *     closed surface), A_i the Galerkin blocks [[K_i, T_i/rho_i], [-rho_i T_i, K_i]]
+ * applied as R M C with the MTF product (C u = [u; -Sigma u], R y = y_0 - Sigma y_1; the
+ * transmission blocks cancel).  Vectors are complex128 [nrhs][ld], ld >= 2 E_0, ordered (u_0D,
+ * u_0N); the right-hand side is the first 2 E_0 entries of mtf_rhs_plane_waves.
+ * mtf_stf_matvec: y = M_STF x.  mtf_solve_stf: GMRES (FP64 operator and Arnoldi, no
+ * preconditioner; opts.precision MTF_FP64 and opts.preconditioner MTF_PREC_NONE, else
+ * MTF_ERR_UNSUPPORTED) until ||b - M_STF x|| <= rtol ||b||.  MTF_ERR_UNSUPPORTED unless M = 1 with
+ * Gamma_0 and Gamma_1 on the same edges.  The far field of u is that of the MTF vector [u, ...]
+ * (mtf_far_field reads only its Gamma_0 entries). */
+int mtf_stf_matvec(mtf_problem p, int32_t nrhs, const void* x_dev, void* y_dev, int64_t ld);
+int mtf_solve_stf(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int64_t ld,
+                  const mtf_solve_opts* opts, mtf_solve_stats* stats);
+
 /* z = P x for nrhs complex128 vectors (x_dev, z_dev: [nrhs][ld], ld >= N, no aliasing) with
  * the right preconditioner `preconditioner` (MTF_PREC_BLOCK_TINV or MTF_PREC_BLOCK_TINV_GS, as
  * defined for mtf_solve).  Builds S_i^-1 on first use (from the FP32 blocks if assembled, else

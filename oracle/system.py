@@ -170,3 +170,40 @@ def gmres(matvec, b, rtol=1e-6, max_iters=2000, x0=None):
     y = np.linalg.solve(np.triu(H[:it, :it]), g[:it])
     x = x + V[:it].T @ y
     return x, it, hist
+
+
+# ---------------------------------------------------------------------------
+# single-trace (PMCHWT) formulation for M = 1 (remark on the PMCHWT, Section 3.2)
+# ---------------------------------------------------------------------------
+
+def stf_sign_map(pb: Problem):
+    """For M = 1 (Gamma_0 and Gamma_1 the same triangles with opposite orientations): sigma[m] with
+    phi^1_m = sigma[m] phi^0_m.  Both spaces order their dofs by edge vertex ids; sigma is +1 where
+    the two spaces name the same triangle tau+ of the edge, else -1 (for a reversed closed surface
+    every tau+ changes side, so sigma = -1 throughout)."""
+    if pb.M != 1:
+        raise ValueError("the single-trace formulation here is for M = 1")
+    s0, s1 = pb.spaces
+    if not np.array_equal(s0.edges, s1.edges):
+        raise ValueError("Gamma_0 and Gamma_1 must carry the same edges")
+    return np.where(s0.tris[s0.plus[:, 0]] == s1.tris[s1.plus[:, 0]], 1.0, -1.0)
+
+
+def stf_matrix(pb: Problem, T, K):
+    """The single-trace (PMCHWT) matrix for M = 1 on the unknown u = u_0 (coefficients of Gamma_0's
+    traces): adding row block 1 of Problem 2, tested with the same functions phi^1_m = sigma_m phi^0_m
+    in Gamma_1's pairing (the opposite of Gamma_0's, hence the factor -sigma), to row block 0, with
+    the transmission condition u_1 = -u_0, i.e. c_1 = -Sigma c_0, gives
+        M_STF = 2 A_0 + 2 Sigma A_1 Sigma,   A_i = [[K_i, T_i / rho_i], [-rho_i T_i, K_i]],
+    the discrete form of 2 (A_0 - A_1) u_0 of the remark (the transmission terms cancel).  The
+    right-hand side is the Gamma_0 rows of the MTF right-hand side."""
+    sig = stf_sign_map(pb)
+    E = pb.E[0]
+    out = np.zeros((2 * E, 2 * E), dtype=np.complex128)
+    for i, w in ((0, np.ones(E)), (1, sig)):
+        S = w[:, None] * w[None, :]
+        out[:E, :E] += 2.0 * S * K[i]
+        out[:E, E:] += (2.0 / pb.rho[i]) * S * T[i]
+        out[E:, :E] += -2.0 * pb.rho[i] * S * T[i]
+        out[E:, E:] += 2.0 * S * K[i]
+    return out

@@ -91,6 +91,8 @@ _SIGS = {
     "mtf_matvec": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.c_int32]),
     "mtf_matvec_noalloc": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.c_int32]),
     "mtf_solve": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
+    "mtf_solve_stf": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64, C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
+    "mtf_stf_matvec": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int64]),
     "mtf_far_field": (C.c_int, [_P, C.c_int32, _P, C.c_int64, C.c_int32, _dp, _dp]),
     "mtf_assembly_stats": (C.c_int, [_P, _lp, _dp]),
     "mtf_batch_create": (C.c_int, [C.POINTER(_P), C.c_int32, C.POINTER(_P)]),
@@ -356,6 +358,30 @@ class Problem:
         st = (SolveStats * nrhs)()
         code = _check(_lib.mtf_solve(self._h, nrhs, pb, px, ld, C.byref(o), st))
         self.last_status = code
+        return [Stats(s.iterations, s.refinements, bool(s.converged), s.rel_residual, s.t_precond_s, s.t_solve_s,
+                      s.reorthogonalizations) for s in st]
+
+    # -- single-trace formulation (M = 1) --------------------------------------------
+    def stf_matvec(self, x, y):
+        """y = M_STF x for vectors [nrhs, >= 2 E_0] of (u_0D, u_0N)."""
+        n = 2 * int(self.E[0])
+        px, nrhs, ld = _dev(x, n)
+        py, nrhs2, ld2 = _dev(y, n)
+        if (nrhs, ld) != (nrhs2, ld2):
+            raise ValueError("x and y shapes differ")
+        _check(_lib.mtf_stf_matvec(self._h, nrhs, px, py, ld))
+
+    def solve_stf(self, b, x, rtol: float = 1e-6, max_iters: int = 0, graph: bool = True) -> list[Stats]:
+        """GMRES on the single-trace system (FP64, no preconditioner); b, x: [nrhs, >= 2 E_0]."""
+        n = 2 * int(self.E[0])
+        pb, nrhs, ld = _dev(b, n)
+        px, nrhs2, ld2 = _dev(x, n)
+        if (nrhs, ld) != (nrhs2, ld2):
+            raise ValueError("b and x shapes differ")
+        o = SolveOpts(C.sizeof(SolveOpts), FP64, PREC_NONE, int(max_iters), 0, 0 if graph else SOLVE_EAGER,
+                      float(rtol), 0.0, None)
+        st = (SolveStats * nrhs)()
+        _check(_lib.mtf_solve_stf(self._h, nrhs, pb, px, ld, C.byref(o), st))
         return [Stats(s.iterations, s.refinements, bool(s.converged), s.rel_residual, s.t_precond_s, s.t_solve_s,
                       s.reorthogonalizations) for s in st]
 

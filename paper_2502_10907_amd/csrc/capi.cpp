@@ -169,6 +169,10 @@ struct mtf_problem_s {
     hipEvent_t gj_fork[2] = {nullptr, nullptr}, gj_join[2] = {nullptr, nullptr};
     hipEvent_t gj_start = nullptr, gj_done[2] = {nullptr, nullptr};
     GmresWork gw;
+    // single-trace (PMCHWT) operator mode for M = 1: GMRES vectors are (u_D, u_N) on Gamma_0
+    bool stf = false;
+    DevBuf<int8_t> stf_sign;         // phi^1_m = sign_m phi^0_m
+    DevBuf<double> stf_x, stf_y;     // full-length MTF vectors around the product
 
     ~mtf_problem_s() {
         if (ev0) (void)hipEventDestroy(ev0);
@@ -1309,7 +1313,7 @@ double batch_build_tinv(const std::vector<mtf_problem>& ps, bool force_full, hip
 
 void gmres_alloc(mtf_problem p, int maxit, int nb, bool flex) {
     GmresWork& w = p->gw;
-    const int64_t n = p->sk.N;
+    const int64_t n = p->stf ? 2 * (int64_t)p->sk.dom[0].E : p->sk.N;
     // a workspace allocated for at least n unknowns, maxit steps and nb columns serves as it is (the
     // buffers are laid out from w.n, w.maxit and w.nb)
     if (w.cap_n >= n && w.maxit >= maxit && w.nb >= nb) {
@@ -1416,9 +1420,47 @@ void apply_inner(mtf_problem p, const double* src, double* dst, int nb, int prec
         apply_pc(p, pc, prec, nb, src, z);
         in = z;
     }
+    if (p->stf) {
+        // single-trace operator R M C (M = 1), through the MTF product
+        const int64_t E = p->sk.dom[0].E;
+        for (int b = 0; b < nb; ++b) {
+            launch_stf_expand(in + 2 * n * b, p->stf_sign.p, E, p->stf_x.p, p->stream);
+            matvec1(p, p->stf_x.p, p->stf_y.p, prec);
+            launch_stf_reduce(p->stf_y.p, p->stf_sign.p, E, dst + 2 * n * b, p->stream);
+        }
+        return;
+    }
     if (prec == MTF_BF16_SPLIT) apply_gemm(p, 0, nb, in, n, dst);
     else
         for (int b = 0; b < nb; ++b) matvec1(p, in + 2 * n * b, dst + 2 * n * b, prec);
+}
+
+// Enters the single-trace mode for M = 1 (sign map and full-length vectors prepared); throws for
+// other problems.
+void stf_prepare(mtf_problem p) {
+    if (p->sk.M != 1) throw UnsupportedError("the single-trace formulation needs M = 1");
+    const Domain& d0 = p->sk.dom[0];
+    const Domain& d1 = p->sk.dom[1];
+    if (d0.E != d1.E || d0.edge_vtx != d1.edge_vtx)
+        throw UnsupportedError("the single-trace formulation needs Gamma_0 and Gamma_1 on the same edges");
+    if (!p->stf_sign.p) {
+        std::vector<int8_t> sg(d0.E);
+        for (int m = 0; m < d0.E; ++m)
+            sg[m] = d0.tri[d0.plus[2 * m]] == d1.tri[d1.plus[2 * m]] ? int8_t(1) : int8_t(-1);
+        p->stf_sign.upload(sg, p->stream);
+    }
+    p->stf_x.alloc(2 * p->sk.N);
+    p->stf_y.alloc(2 * p->sk.N);
+}
+
+// y = M_STF x for nb vectors of length 2 E_0 (ld)
+void stf_matvec(mtf_problem p, const double* x, double* y, int64_t ld, int nb) {
+    const int64_t E = p->sk.dom[0].E;
+    for (int b = 0; b < nb; ++b) {
+        launch_stf_expand(x + 2 * ld * b, p->stf_sign.p, E, p->stf_x.p, p->stream);
+        matvec1(p, p->stf_x.p, p->stf_y.p, MTF_FP64);
+        launch_stf_reduce(p->stf_y.p, p->stf_sign.p, E, y + 2 * ld * b, p->stream);
+    }
 }
 
 // One GMRES cycle for nb right-hand sides in lockstep: residual slab R (ld n), corrections added to
@@ -1807,6 +1849,82 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
     return status;
 }
 
+// GMRES on the single-trace system M_STF u = b (M = 1, FP64 operator, no preconditioner): cycles
+// until the FP64 residual of the single-trace operator meets rtol.
+int solve_stf_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int64_t ld, const mtf_solve_opts* o,
+                   mtf_solve_stats* stats) {
+    if (!p->has_mesh || !p->has_mat) throw StateError("mtf_solve_stf before mesh/materials");
+    mtf_solve_opts opts;
+    std::memset(&opts, 0, sizeof(opts));
+    opts.struct_size = sizeof(opts);
+    opts.rtol = 1e-6;
+    if (o) {
+        if (o->struct_size < (int)sizeof(mtf_solve_opts)) throw ArgError("mtf_solve_opts.struct_size too small");
+        opts = *o;
+    }
+    const int64_t n = 2 * (int64_t)p->sk.dom[0].E;
+    if (nrhs < 1 || !b_dev || !x_dev || ld < n) throw ArgError("mtf_solve_stf: bad nrhs, pointers or ld");
+    if (!(opts.rtol > 0.0) || !(opts.rtol < 1.0)) throw ArgError("rtol must be in (0, 1)");
+    if (opts.max_iters < 0 || opts.max_refinements < 0) throw ArgError("negative iteration limits");
+    if (opts.precision != MTF_FP64) throw UnsupportedError("mtf_solve_stf runs the FP64 operator only");
+    if (opts.preconditioner != MTF_PREC_NONE) throw UnsupportedError("mtf_solve_stf has no preconditioner");
+    if (opts.flags & ~MTF_SOLVE_EAGER) throw ArgError("mtf_solve_stf accepts MTF_SOLVE_EAGER only");
+    if (!p->have64) throw StateError("mtf_solve_stf needs the FP64 blocks");
+    DeviceGuard g(p->device);
+    stf_prepare(p);
+    struct Mode {
+        mtf_problem p;
+        ~Mode() { p->stf = false; }
+    } mode{p};
+    p->stf = true;
+    const int maxit = opts.max_iters ? opts.max_iters : (int)std::min<int64_t>(n, 4000);
+    const int maxref = opts.max_refinements ? opts.max_refinements : 10;
+    gmres_alloc(p, maxit, 1, false);
+    GmresWork& w = p->gw;
+    hipStream_t s = p->stream;
+    int status = MTF_OK;
+    for (int r = 0; r < nrhs; ++r) {
+        auto t0 = std::chrono::steady_clock::now();
+        const double* B = static_cast<const double*>(b_dev) + 2 * ld * (int64_t)r;
+        double* X = static_cast<double*>(x_dev) + 2 * ld * (int64_t)r;
+        if (opts.x0_dev)
+            HIPCHK(hipMemcpyAsync(X, static_cast<const double*>(opts.x0_dev) + 2 * ld * (int64_t)r, 2 * n * sizeof(double),
+                                  hipMemcpyDeviceToDevice, s));
+        else launch_fill(X, 2 * n, 0.0, s);
+        const double bn = norms_dev(p, B, n, 1)[0];
+        int iters = 0, refin = 0;
+        double rel = 1.0;
+        bool conv = false;
+        std::vector<int> itv, reorth(1, 0);
+        std::vector<double> est;
+        for (int outer = 0; outer <= maxref; ++outer) {
+            stf_matvec(p, X, w.r.p, n, 1);
+            launch_axpby(w.r.p, B, n, 1.0, 0.0, -1.0, s);           // r = b - M_STF x
+            const double rn = norms_dev(p, w.r.p, n, 1)[0];
+            rel = bn > 0 ? rn / bn : 0.0;
+            if (outer > 0) ++refin;
+            conv = rel <= opts.rtol;
+            if (conv || outer == maxref) break;
+            const std::vector<double> tol(1, 0.9 * opts.rtol * bn / rn);
+            gmres_cycle(p, w.r.p, X, ld, 1, MTF_FP64, MTF_PREC_NONE, tol, maxit, itv, est, reorth,
+                        (opts.flags & MTF_SOLVE_EAGER) == 0, 1.0, false);
+            iters += itv[0];
+        }
+        if (stats) {
+            mtf_solve_stats& st = stats[r];
+            st.iterations = iters;
+            st.refinements = refin;
+            st.converged = conv ? 1 : 0;
+            st.reorthogonalizations = reorth[0];
+            st.rel_residual = rel;
+            st.t_precond_s = 0.0;
+            st.t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        if (!conv) status = MTF_NOT_CONVERGED;
+    }
+    return status;
+}
+
 bool finite_all(const double* a, int64_t n) {
     for (int64_t i = 0; i < n; ++i)
         if (!std::isfinite(a[i])) return false;
@@ -2161,6 +2279,29 @@ int mtf_solve(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int64
     return guarded([&] {
         if (!p) throw ArgError("problem is NULL");
         return solve_impl(p, nrhs, b_dev, x_dev, ld, opts, stats);
+    });
+}
+
+int mtf_solve_stf(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int64_t ld, const mtf_solve_opts* opts,
+                  mtf_solve_stats* stats) {
+    return guarded([&] {
+        if (!p) throw ArgError("problem is NULL");
+        return solve_stf_impl(p, nrhs, b_dev, x_dev, ld, opts, stats);
+    });
+}
+
+int mtf_stf_matvec(mtf_problem p, int32_t nrhs, const void* x_dev, void* y_dev, int64_t ld) {
+    return guarded([&] {
+        if (!p) throw ArgError("problem is NULL");
+        if (!p->has_mesh || !p->has_mat) throw StateError("mtf_stf_matvec before mesh/materials");
+        if (!p->have64) throw StateError("mtf_stf_matvec needs the FP64 blocks");
+        if (nrhs < 1 || !x_dev || !y_dev || x_dev == y_dev) throw ArgError("bad arguments");
+        DeviceGuard g(p->device);
+        stf_prepare(p);
+        if (ld < 2 * (int64_t)p->sk.dom[0].E) throw ArgError("ld < 2 E_0");
+        stf_matvec(p, static_cast<const double*>(x_dev), static_cast<double*>(y_dev), ld, nrhs);
+        HIPCHK(hipGetLastError());
+        return MTF_OK;
     });
 }
 
@@ -2618,6 +2759,7 @@ int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, c
                 ao.struct_size = sizeof(ao);
                 ao.precision = MTF_FP64;
                 ao.singular_order = 4;
+                ao.flags = MTF_ASSEMBLE_TILE(b->last_variant);   // the batch's tuned tiles, no new trials
                 assemble_impl(p, &ao);       // the preconditioner stays: it was built from the FP32 blocks
             }
             const int r = solve_impl(p, 1, b_dev[i], x_dev[i], p->sk.N, &o, stats ? stats + i : nullptr);

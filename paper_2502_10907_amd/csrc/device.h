@@ -220,6 +220,11 @@ void launch_gs_residual(const DomDesc* doms, const int32_t* dof_dom, const int32
                         const int32_t* other_dom, const int32_t* dom_stage, int stage, const double* v, const double* z,
                         double* w, hipStream_t s);
 void launch_nonfinite_check(const float* A, int64_t n, int* flag, hipStream_t s);
+// Single-trace formulation for M = 1 through the MTF product: full = [x; -Sigma x] (x = (u_D, u_N)
+// on Gamma_0, 2E entries; sig[E] = +-1 with phi^1_m = sig_m phi^0_m), and y = full_y[0:2E] -
+// Sigma full_y[2E:4E].
+void launch_stf_expand(const double* x, const int8_t* sig, int64_t E, double* full, hipStream_t s);
+void launch_stf_reduce(const double* full, const int8_t* sig, int64_t E, double* y, hipStream_t s);
 
 // Preconditioner blocks of many problems inverted together: each n x n diagonal block (of T_i or
 // of one connected component of Gamma_i) is copied into an S x S slot of a bucket of equal S >= n,

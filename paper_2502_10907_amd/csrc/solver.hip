@@ -1459,6 +1459,27 @@ __global__ __launch_bounds__(256) void k_pad_scatter(const PadBlock* __restrict_
     reinterpret_cast<float2*>(b.dst)[r + (int64_t)c * b.ld] = buf[z * (int64_t)S * S + r + (int64_t)c * S];
 }
 
+// Single-trace operator for M = 1 through the MTF product: full = C x = [x; -Sigma x] (u_1 = -u_0)
+// before it, y = R full_y = full_y[0:2E] - Sigma full_y[2E:4E] after it.
+__global__ void k_stf_expand(const double2* __restrict__ x, const int8_t* __restrict__ sig, int64_t E,
+                             double2* __restrict__ full) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 2 * E) return;
+    const double2 v = x[e];
+    const double sg = -(double)sig[e % E];
+    full[e] = v;
+    full[2 * E + e] = make_double2(sg * v.x, sg * v.y);
+}
+
+__global__ void k_stf_reduce(const double2* __restrict__ full, const int8_t* __restrict__ sig, int64_t E,
+                             double2* __restrict__ y) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 2 * E) return;
+    const double2 a = full[e], b = full[2 * E + e];
+    const double sg = (double)sig[e % E];
+    y[e] = make_double2(a.x - sg * b.x, a.y - sg * b.y);
+}
+
 __global__ void k_cgemv_sum(const float2* __restrict__ part, int n, int nch, int64_t sp, float2* __restrict__ y,
                             int64_t sy) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1679,6 +1700,16 @@ void launch_cgemv_f64src(const double* A, int64_t lda, const float* x, int n, fl
                        reinterpret_cast<float2*>(part));
     hipLaunchKernelGGL(k_cgemv_sum, dim3(gridn(n, 256), 1u), dim3(256), 0, s, reinterpret_cast<const float2*>(part), n,
                        nch, (int64_t)nch * n, reinterpret_cast<float2*>(y), (int64_t)0);
+}
+
+void launch_stf_expand(const double* x, const int8_t* sig, int64_t E, double* full, hipStream_t s) {
+    hipLaunchKernelGGL(k_stf_expand, dim3(gridn(2 * E, 256)), dim3(256), 0, s, reinterpret_cast<const double2*>(x), sig,
+                       E, reinterpret_cast<double2*>(full));
+}
+
+void launch_stf_reduce(const double* full, const int8_t* sig, int64_t E, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(k_stf_reduce, dim3(gridn(2 * E, 256)), dim3(256), 0, s, reinterpret_cast<const double2*>(full),
+                       sig, E, reinterpret_cast<double2*>(y));
 }
 
 void launch_nonfinite_check(const float* A, int64_t n, int* flag, hipStream_t s) {

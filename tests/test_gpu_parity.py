@@ -720,3 +720,32 @@ def test_tile_variants_and_autotuned_launch_agree(prec, ragged, sphere):
     assert 0 <= variant < mtf.TILE_VARIANTS and grid > 0
     print(f"[autotuner] {mtf.tuning_log()}", flush=True)
     B.close()
+
+
+def test_single_trace_formulation_matches_oracle(sphere, ragged):
+    """PMCHWT / single-trace formulation for M = 1: the library's operator (the MTF product between
+    the sign maps C and R) against the oracle's M_STF = 2 A_0 + 2 Sigma A_1 Sigma on a random vector,
+    and its GMRES solution against the oracle's LU solution; problems with M != 1 are refused."""
+    c = sphere
+    P = c.P
+    E = int(P.E[0])
+    Ms = sy.stf_matrix(c.pb, c.T, c.K)
+    rng = np.random.default_rng(13)
+    x = rng.standard_normal(2 * E) + 1j * rng.standard_normal(2 * E)
+    xt = torch.tensor(x[None, :], device="cuda")
+    yt = torch.zeros_like(xt)
+    P.stf_matvec(xt, yt)
+    ref = Ms @ x
+    assert np.abs(yt[0].cpu().numpy() - ref).max() < 1e-12 * np.abs(ref).max()
+    b = c.b[:2 * E]
+    u_ref = np.linalg.solve(Ms, b)
+    bt = torch.tensor(b[None, :], device="cuda")
+    ut = torch.zeros_like(bt)
+    st = P.solve_stf(bt, ut, rtol=1e-10)[0]
+    err = np.abs(ut[0].cpu().numpy() - u_ref).max() / np.abs(u_ref).max()
+    print(f"[STF sphere] iterations {st.iterations} residual {st.rel_residual:.2e} entrywise error {err:.2e}", flush=True)
+    assert st.converged and err < 1e-7
+    with pytest.raises(mtf.MTFError) as e:
+        ragged.P.stf_matvec(torch.zeros((1, 2 * int(ragged.P.E[0])), dtype=torch.complex128, device="cuda"),
+                            torch.zeros((1, 2 * int(ragged.P.E[0])), dtype=torch.complex128, device="cuda"))
+    assert e.value.code == -7

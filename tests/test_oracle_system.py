@@ -139,3 +139,55 @@ def test_mie_optical_theorem(x):
     a2 = a.copy()
     a2[1] = -a2[1]
     assert abs(2 / x ** 2 * np.sum((2 * n + 1) * (a2 + b).real) - qsca) > 1e-3 * qsca
+
+
+@pytest.fixture(scope="module")
+def sphere80():
+    cfg = mi.config_sphere(1)
+    pb = sy.Problem.from_config(cfg)
+    T, K, G = sy.assemble_blocks(pb)
+    return cfg, pb, T, K, G
+
+
+def test_stf_is_the_summed_mtf_system(sphere80):
+    """The single-trace matrix equals R M C, with M the oracle's MTF matrix of the same sphere,
+    C x = [x; -Sigma x] (u_1 = -u_0) and R = [I, -Sigma] (row block 1 moved to Gamma_0's test
+    functions and pairing): the transmission blocks cancel exactly.  Sigma = -I on a reversed closed
+    surface."""
+    cfg, pb, T, K, G = sphere80
+    sig = sy.stf_sign_map(pb)
+    assert np.all(sig == -1.0)
+    E = pb.E[0]
+    S = np.concatenate([sig, sig])
+    Mx = sy.dense_matrix(pb, T, K, G)
+    C = np.vstack([np.eye(2 * E), -np.diag(S)])
+    R = np.hstack([np.eye(2 * E), -np.diag(S)])
+    Ms = sy.stf_matrix(pb, T, K)
+    assert np.abs(R @ Mx @ C - Ms).max() < 1e-13 * np.abs(Ms).max()
+    # without the cancellation (the transmission blocks kept with one sign) the identity fails
+    Gs = G[(0, 1)]
+    assert np.abs(Gs).max() > 1e-3 * np.abs(Ms).max()
+
+
+@pytest.mark.slow
+def test_stf_far_field_converges_to_mie():
+    """STF(1) for the dielectric sphere (eps_r = 2, k0 = 1): complex far field against the Mie series
+    under refinement (80 -> 320 triangles), and the same discrete far field as MTF(1) within the
+    discretisation error."""
+    errs = []
+    for sub in (1, 2):
+        cfg = mi.config_sphere(sub)
+        pb = sy.Problem.from_config(cfg)
+        T, K, G = sy.assemble_blocks(pb)
+        b = sy.rhs(pb, cfg["d"], cfg["p"])[:, 0]
+        E = pb.E[0]
+        u = sy.solve_direct(sy.stf_matrix(pb, T, K), b[:2 * E])
+        x = sy.solve_direct(sy.dense_matrix(pb, T, K, G), b)
+        th = np.linspace(0.05, np.pi - 0.05, 40)
+        dirs = np.concatenate([np.stack([np.sin(th), 0 * th, np.cos(th)], 1), np.stack([0 * th, np.sin(th), np.cos(th)], 1)])
+        ref = mie.far_field(1.0, 1.0, 2.0, dirs)
+        ff = op.far_field(pb.xyz, pb.spaces[0], pb.k0, pb.rho[0], u[:E], u[E:], dirs)
+        fm = op.far_field(pb.xyz, pb.spaces[0], pb.k0, pb.rho[0], x[:E], x[E:2 * E], dirs)
+        errs.append(np.linalg.norm(ff - ref) / np.linalg.norm(ref))
+        assert np.linalg.norm(ff - fm) / np.linalg.norm(ref) < 0.15
+    assert errs[1] < 0.05 and errs[1] < errs[0] / 3.0, errs
