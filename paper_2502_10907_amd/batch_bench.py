@@ -1,7 +1,8 @@
 """Batched assembly of many uneven scatterers: one persistent launch vs one launch set per problem.
 
-Usage: python -m paper_2502_10907_amd.batch_bench [nclusters] [precision 0|1] [solve 0|1]
-Then (solve=1) every cluster is solved for one plane wave (d = +z, x-polarised) by mtf_batch_solve
+Usage: python -m paper_2502_10907_amd.batch_bench [nclusters] [precision 0|1] [solve 0|1|2]
+Then (solve=2) the preconditioner blocks of every cluster are built together, or (solve=1) every
+cluster is solved for one plane wave (d = +z, x-polarised) by mtf_batch_solve
 to ||b - Mx|| <= 1e-6 ||b||: GMRES on the assembled operator with FP64 refinement.
 Workload: clusters of 1-8 disjoint dielectric spheres (Fibonacci-hull meshes, 200-2000 triangles
 per sphere, radii U[0.3,1], eps_r ~ U[1.5,4], k0 = 1.5, SplitMix64 seed 0).  Prints one JSON line.
@@ -38,6 +39,7 @@ def main(nclusters=64, precision=1, solve=1):
     B = mtf.Batch(probs)
     grid, t_batch = B.assemble(precision)          # includes the autotuning trials on first call
     grid, t_batch = B.assemble(precision)          # timed, tuned
+    _, (t_tiles, t_touch), (variant, _) = B.assembly_stats()
     print(f"[batch] persistent launch {t_batch:.3f} s with {grid} workgroups", flush=True)
     torch.cuda.synchronize()
     # one assembly launch set per problem, back to back on the same stream
@@ -51,10 +53,18 @@ def main(nclusters=64, precision=1, solve=1):
     out = {"workload": f"{nclusters} clusters of 1-8 dielectric spheres (200-2000 triangles each), k0=1.5",
            "precision": "fp32 separated pairs + fp64 touching" if precision else "fp64",
            "spheres": int(sum(c["mesh"].M for c in cl)), "triangles": int(tri), "ordered_pairs": pairs,
-           "t_host_setup_s": t_setup, "persistent_grid": grid, "t_batch_persistent_s": t_batch,
+           "t_host_setup_s": t_setup, "persistent_grid": grid, "tile_variant": variant,
+           "tile_shape": mtf.tile_variant(variant), "t_batch_assembly_s": t_batch, "t_persistent_launch_s": t_tiles,
+           "t_touching_pairs_s": t_touch, "t_batch_persistent_s": t_batch,
            "t_per_problem_launches_s": t_seq, "pairs_per_s_batch": pairs / t_batch,
            "pairs_per_s_per_problem": pairs / t_seq}
-    if solve:
+    if solve == 2:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.build_preconditioner()
+        torch.cuda.synchronize()
+        out["t_precond_build_s"] = time.perf_counter() - t0
+    elif solve:
         # one plane wave per cluster; GMRES on the assembled operator, FP64 residual (FP64 blocks
         # assembled per problem for its solve and released), block Gauss-Seidel T^-1
         bs = [torch.zeros((1, P.N), dtype=torch.complex128, device="cuda") for P in probs]
