@@ -82,6 +82,21 @@ extern "C" {
  * of the two passes over the basis per step.  Needs a preconditioner (the flexible iteration,
  * whose correction uses the complex128 preconditioned vectors). */
 #define MTF_SOLVE_BASIS_C64 4
+/* Block GMRES over consecutive groups of p right-hand sides (1 <= p <= 32), each group sharing
+ * one Krylov space (block flexible GMRES: Vital 1990; Gutknecht 2006): a block step applies the
+ * preconditioner and the FP64 product to the p vectors of the newest basis block, orthogonalises
+ * them against the whole basis by two passes of block classical Gram-Schmidt on the FP64 matrix
+ * cores (one read of the basis per pass for all p vectors), and orthonormalises the block through
+ * the eigen-decomposition of its Gram matrix with the columns scaled to unit norm (SVQB,
+ * Stathopoulos and Wu 2002; a second pass when the block is ill-conditioned), dropping directions
+ * whose scaled eigenvalue is at most 1e-14, so that the block narrows when the right-hand sides
+ * become dependent.  The block least-squares problem is reduced by Householder reflections on the
+ * host; a group stops when every one of its residuals meets the target, restarts from the
+ * corrected solution when the basis is full (opts.max_iters basis vectors, 0: from free device
+ * memory, at most 24,000), and is checked with the FP64 residual as in the single-vector
+ * iteration.  FP64 operator only (MTF_FP64, else MTF_ERR_UNSUPPORTED); any preconditioner; not
+ * with MTF_SOLVE_BASIS_C64.  stats[i].iterations counts the block steps of i's group. */
+#define MTF_SOLVE_BLOCK(p) ((((p) & 0xff)) << 8)
 
 typedef struct mtf_problem_s* mtf_problem;
 
@@ -231,7 +246,7 @@ typedef struct {
     int32_t max_iters;        /* Arnoldi steps per GMRES cycle; 0: as many as half the free
                                  device memory holds, at most 8000 (2000 for lockstep batches) */
     int32_t max_refinements;  /* outer FP64 refinement steps (MTF_FP32_MIXED), 0 = 10        */
-    int32_t flags;            /* 0, or MTF_SOLVE_EAGER, MTF_SOLVE_PC_FULL, MTF_SOLVE_BASIS_C64 */
+    int32_t flags;            /* 0, or MTF_SOLVE_EAGER, MTF_SOLVE_PC_FULL, MTF_SOLVE_BASIS_C64, MTF_SOLVE_BLOCK(p) */
     double  rtol;             /* ||b - M x||_2 <= rtol ||b||_2 with the FP64 operator        */
     double  inner_rtol;       /* inner GMRES tolerance of a refinement step, 0 = 1e-3*... */
     const void* x0_dev;       /* complex128 initial guess [nrhs][ld] or NULL (zero)          */

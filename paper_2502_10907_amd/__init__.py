@@ -36,6 +36,11 @@ PREC_NONE, PREC_BLOCK_TINV, PREC_BLOCK_TINV_GS = 0, 1, 2
 SOLVE_EAGER = 1
 SOLVE_PC_FULL = 2
 SOLVE_BASIS_C64 = 4
+
+
+def SOLVE_BLOCK(p: int) -> int:
+    """mtf_solve_opts.flags bits of block GMRES over groups of p right-hand sides (MTF_SOLVE_BLOCK)."""
+    return (int(p) & 0xFF) << 8
 ASSEMBLE_ROUND_FP64 = 1
 
 
@@ -340,7 +345,7 @@ class Problem:
 
     def solve(self, b, x, rtol: float = 1e-6, precision: int = FP64, preconditioner: int = PREC_BLOCK_TINV,
               max_iters: int = 0, max_refinements: int = 0, inner_rtol: float = 0.0, x0=None,
-              graph: bool = True, pc_full: bool = False, basis_c64: bool = False) -> list[Stats]:
+              graph: bool = True, pc_full: bool = False, basis_c64: bool = False, block: int = 0) -> list[Stats]:
         pb, nrhs, ld = _dev(b, self.N)
         px, nrhs2, ld2 = _dev(x, self.N)
         if (nrhs, ld) != (nrhs2, ld2):
@@ -353,7 +358,7 @@ class Problem:
         o = SolveOpts(C.sizeof(SolveOpts), int(precision), int(preconditioner), int(max_iters),
                       int(max_refinements),
                       (0 if graph else SOLVE_EAGER) | (SOLVE_PC_FULL if pc_full else 0) |
-                      (SOLVE_BASIS_C64 if basis_c64 else 0),
+                      (SOLVE_BASIS_C64 if basis_c64 else 0) | SOLVE_BLOCK(block),
                       float(rtol), float(inner_rtol), x0p)
         st = (SolveStats * nrhs)()
         code = _check(_lib.mtf_solve(self._h, nrhs, pb, px, ld, C.byref(o), st))

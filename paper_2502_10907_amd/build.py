@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmtf.so")
-SOURCES = ["skeleton.cpp", "quadrature.cpp", "capi.cpp", "learn_api.cpp", "assembly.hip", "solver.hip", "gemm.hip", "learn.hip"]
+SOURCES = ["skeleton.cpp", "quadrature.cpp", "capi.cpp", "learn_api.cpp", "assembly.hip", "solver.hip", "gemm.hip", "learn.hip", "block.hip"]
 ARCH = os.environ.get("MTF_OFFLOAD_ARCH", "gfx950")
 
 

@@ -14,6 +14,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -33,6 +34,7 @@ constexpr int kGjPanel = 256; // block width of the Gauss-Jordan inversion (64-w
 constexpr double kPcSymTol = 1e-3;   // largest ||T_i S_i^-1 v - v|| / ||v|| of a symmetric-part block
 constexpr int kSync = 8;      // Arnoldi steps between host reads of the Hessenberg columns
 constexpr int kMaxBatch = 64; // right-hand sides per lockstep GMRES batch (MFMA products)
+constexpr int kMaxBlock = 32; // right-hand sides per block of block GMRES
 constexpr int kUpdGroups = 8; // partial-sum groups of the basis update
 constexpr int kBatchCycle = 1000;  // Arnoldi steps per cycle in mtf_batch_solve when max_iters is 0
 constexpr int kEagerBatches = 2;   // Arnoldi batches of a cycle launched eagerly before a graph is captured
@@ -1726,6 +1728,478 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
     return steps;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Block flexible GMRES: q right-hand sides share one Krylov space (block Arnoldi with the FP64
+// block Gram-Schmidt contractions of block.hip, a rank-revealing orthonormalisation of each new
+// block, and the block least-squares problem reduced by Householder reflections on the host).
+
+// A = U diag(w) U^H for a Hermitian n x n matrix A (column-major), by cyclic Jacobi rotations:
+// each (p, q) entry is first made real by a phase on column/row q, then zeroed by a real rotation.
+void herm_eig(int n, std::vector<cd> A, std::vector<double>& w, std::vector<cd>& U) {
+    U.assign((size_t)n * n, cd(0.0, 0.0));
+    for (int i = 0; i < n; ++i) U[(size_t)i * n + i] = 1.0;
+    auto at = [&](int r, int c) -> cd& { return A[(size_t)c * n + r]; };
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int c = 0; c < n; ++c)
+            for (int r = 0; r < n; ++r) {
+                const double v = std::norm(at(r, c));
+                tot += v;
+                if (r != c) off += v;
+            }
+        if (off <= 1e-32 * tot) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const cd apq = at(p, q);
+                const double r = std::abs(apq);
+                if (r <= 1e-300) continue;
+                const cd d = std::conj(apq) / r;             // column q *= d makes A(p, q) = r
+                for (int k = 0; k < n; ++k) at(k, q) *= d;
+                for (int k = 0; k < n; ++k) at(q, k) *= std::conj(d);
+                for (int k = 0; k < n; ++k) U[(size_t)q * n + k] *= d;
+                const double a = at(p, p).real(), b = at(q, q).real();
+                const double tau = (b - a) / (2.0 * r);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::abs(tau) + std::sqrt(1.0 + tau * tau));
+                const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+                for (int k = 0; k < n; ++k) {                // columns p, q of A J
+                    const cd x = at(k, p), y = at(k, q);
+                    at(k, p) = c * x - s * y;
+                    at(k, q) = s * x + c * y;
+                }
+                for (int k = 0; k < n; ++k) {                // rows p, q of J^T (A J)
+                    const cd x = at(p, k), y = at(q, k);
+                    at(p, k) = c * x - s * y;
+                    at(q, k) = s * x + c * y;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const cd x = U[(size_t)p * n + k], y = U[(size_t)q * n + k];
+                    U[(size_t)p * n + k] = c * x - s * y;
+                    U[(size_t)q * n + k] = s * x + c * y;
+                }
+            }
+    }
+    w.resize(n);
+    for (int i = 0; i < n; ++i) w[i] = at(i, i).real();
+}
+
+// Orthonormal basis of the span of n vectors W from their Gram matrix G = W^H W (column-major):
+// Q = W T (n x k) and W ~= Q S (k x n), with the columns scaled to unit norm first and directions
+// whose scaled eigenvalue is at most `keep` dropped (rank revealing); a column whose squared norm
+// is at most 1e-26 ref2[c] counts as zero.  lmin: the smallest kept eigenvalue.
+struct Svqb {
+    int k = 0;
+    std::vector<cd> T, S;   // T: n x k, S: k x n, column-major
+    double lmin = 1.0;
+};
+Svqb svqb(int n, const std::vector<cd>& G, const std::vector<double>& ref2, double keep) {
+    std::vector<double> D(n, 0.0);
+    for (int c = 0; c < n; ++c) {
+        const double g = G[(size_t)c * n + c].real();
+        if (g > 0.0 && g > 1e-26 * ref2[c]) D[c] = 1.0 / std::sqrt(g);
+    }
+    std::vector<cd> Gs((size_t)n * n);
+    for (int c = 0; c < n; ++c)
+        for (int r = 0; r < n; ++r) Gs[(size_t)c * n + r] = D[r] * G[(size_t)c * n + r] * D[c];
+    std::vector<double> w;
+    std::vector<cd> U;
+    herm_eig(n, Gs, w, U);
+    std::vector<int> idx;
+    for (int i = 0; i < n; ++i)
+        if (w[i] > keep) idx.push_back(i);
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return w[a] > w[b]; });
+    Svqb o;
+    o.k = (int)idx.size();
+    o.T.assign((size_t)n * o.k, cd(0.0, 0.0));
+    o.S.assign((size_t)o.k * n, cd(0.0, 0.0));
+    for (int kk = 0; kk < o.k; ++kk) {
+        const int e = idx[kk];
+        const double sw = std::sqrt(w[e]);
+        o.lmin = std::min(o.lmin, w[e]);
+        for (int c = 0; c < n; ++c) {
+            const cd u = U[(size_t)e * n + c];
+            o.T[(size_t)kk * n + c] = D[c] * u / sw;
+            o.S[(size_t)c * o.k + kk] = D[c] > 0.0 ? sw * std::conj(u) / D[c] : cd(0.0, 0.0);
+        }
+    }
+    return o;
+}
+
+// Runs f(0..count-1) on up to 16 host threads (inline when the work is small).
+template <typename F>
+void host_parallel(int count, bool big, F&& f) {
+    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+    const int nt = big ? std::min<int>({count, 16, hw}) : 1;
+    if (nt <= 1) {
+        for (int i = 0; i < count; ++i) f(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t] {
+            for (int i = t; i < count; i += nt) f(i);
+        });
+    for (std::thread& x : th) x.join();
+}
+
+// Householder reduction of the block Hessenberg matrix, column by column as Arnoldi delivers it,
+// applied to the block right-hand side E_1 S_0 as well (one column per right-hand side): after a
+// block step the rows below the triangular part hold each right-hand side's residual.
+struct BlockLsq {
+    int w2 = 0;                   // reflector capacity (twice the largest block)
+    int q = 0;                    // right-hand sides
+    int64_t gld = 0;              // rows of G
+    std::vector<double> refl;     // reflector m: w2 complex at refl + 2 m w2 (rows m ..)
+    std::vector<int> len;
+    std::vector<double> tau;
+    std::vector<double> G;        // gld x q complex, column-major
+    void init(int cap_cols, int64_t rows, int pmax, int nq) {
+        w2 = 2 * pmax;
+        q = nq;
+        gld = rows;
+        refl.assign((size_t)2 * cap_cols * w2, 0.0);
+        len.assign(cap_cols, 0);
+        tau.assign(cap_cols, 0.0);
+        G.assign((size_t)2 * rows * nq, 0.0);
+    }
+    // y (complex, row 0 at y) <- H_m y
+    void apply(int m, double* y) const {
+        const double t = tau[m];
+        if (t == 0.0) return;
+        const double* v = refl.data() + (size_t)2 * m * w2;
+        double* ym = y + 2 * (int64_t)m;
+        const int L = len[m];
+        double sr = 0.0, si = 0.0;
+        for (int k = 0; k < L; ++k) {           // s = v^H y
+            sr += v[2 * k] * ym[2 * k] + v[2 * k + 1] * ym[2 * k + 1];
+            si += v[2 * k] * ym[2 * k + 1] - v[2 * k + 1] * ym[2 * k];
+        }
+        sr *= t;
+        si *= t;
+        for (int k = 0; k < L; ++k) {           // y -= v (tau s)
+            ym[2 * k] -= v[2 * k] * sr - v[2 * k + 1] * si;
+            ym[2 * k + 1] -= v[2 * k] * si + v[2 * k + 1] * sr;
+        }
+    }
+    // reflector m from y[m .. m + L - 1], which becomes (alpha, 0, ..., 0)
+    void make(int m, int L, double* y) {
+        double* x = y + 2 * (int64_t)m;
+        double nx2 = 0.0;
+        for (int k = 0; k < L; ++k) nx2 += x[2 * k] * x[2 * k] + x[2 * k + 1] * x[2 * k + 1];
+        double* v = refl.data() + (size_t)2 * m * w2;
+        len[m] = L;
+        if (!(nx2 > 0.0)) {
+            tau[m] = 0.0;
+            return;
+        }
+        const double nx = std::sqrt(nx2);
+        const double ax0 = std::hypot(x[0], x[1]);
+        const double pr = ax0 > 0.0 ? x[0] / ax0 : 1.0, pi = ax0 > 0.0 ? x[1] / ax0 : 0.0;
+        const double ar = -pr * nx, ai = -pi * nx;                 // alpha = -e^{i arg x0} ||x||
+        for (int k = 0; k < 2 * L; ++k) v[k] = x[k];
+        v[0] -= ar;
+        v[1] -= ai;
+        tau[m] = 1.0 / (nx2 + nx * ax0);                           // 2 / ||v||^2
+        x[0] = ar;
+        x[1] = ai;
+        for (int k = 1; k < L; ++k) x[2 * k] = x[2 * k + 1] = 0.0;
+    }
+};
+
+struct BlockWork {
+    DevBuf<double> V, Z, Wa, Wb, hd, pdot, pupd, R, Y, T, tmp, npart;
+    DevBuf<int> cnt, info;
+    double* hh = nullptr;           // pinned staging of hd
+    ~BlockWork() {
+        if (hh) (void)hipHostFree(hh);
+    }
+};
+
+// Block flexible GMRES over groups of pb right-hand sides (FP64 operator and Arnoldi).
+int block_solve(mtf_problem p, int32_t nrhs, const double* Bp, double* Xp, int64_t ld, const mtf_solve_opts& opts,
+                int pb, int pc, mtf_solve_stats* stats, double t_pc) {
+    const int64_t n = p->sk.N;
+    hipStream_t s = p->stream;
+    const bool use_pc = pc != MTF_PREC_NONE;
+    const int maxref = opts.max_refinements ? opts.max_refinements : 10;
+    const int pmax = std::min<int>(pb, nrhs);
+    const int ppad = ((pmax + 15) / 16) * 16;
+    // basis capacity (vectors in Z; V holds up to pmax more): opts.max_iters, else from memory
+    int64_t dmax = opts.max_iters;
+    if (dmax == 0) {
+        size_t freeb = 0, totalb = 0;
+        HIPCHK(hipMemGetInfo(&freeb, &totalb));
+        const double budget = 0.5 * (double)freeb;
+        const double a = 16.0, b = 16.0 * (use_pc ? 2.0 : 1.0) * (double)n;   // R (d^2) + V, Z (d n)
+        dmax = (int64_t)((-b + std::sqrt(b * b + 4.0 * a * budget)) / (2.0 * a));
+        dmax = std::min<int64_t>(dmax, 24000);
+    }
+    dmax = std::min<int64_t>(dmax, n);
+    dmax = std::max<int64_t>(dmax, pmax);
+    const int64_t vcap = dmax + pmax;
+    BlockWork bw;
+    bw.V.alloc((size_t)2 * vcap * n);
+    if (use_pc) bw.Z.alloc((size_t)2 * dmax * n);
+    bw.Wa.alloc((size_t)2 * pmax * n);
+    bw.Wb.alloc((size_t)2 * pmax * n);
+    bw.tmp.alloc((size_t)2 * n);
+    bw.npart.alloc((size_t)kNblk * pmax);
+    const size_t hcount = (size_t)2 * (2 * vcap * ppad + ppad * ppad);   // H1, H2, Gram (complex)
+    bw.hd.alloc(hcount);
+    HIPCHK(hipHostMalloc((void**)&bw.hh, hcount * sizeof(double), hipHostMallocDefault));
+    int64_t pd = 0, pu = 0;
+    for (int pp = 1; pp <= pmax; ++pp)
+        for (int64_t j = 1; j <= vcap; ++j) {
+            pd = std::max(pd, plan_bdot(n, (int)j, pp).part_elems);
+            pu = std::max(pu, plan_bupd(n, (int)j, pp).part_elems);
+        }
+    bw.pdot.alloc((size_t)2 * pd);
+    bw.pupd.alloc((size_t)2 * pu);
+    bw.R.alloc((size_t)2 * dmax * dmax);
+    bw.Y.alloc((size_t)2 * dmax * pmax);
+    bw.T.alloc((size_t)2 * pmax * pmax);
+    bw.cnt.alloc(pmax);
+    bw.info.alloc(1);
+    double* H1 = bw.hd.p;
+    double* H2 = bw.hd.p + (size_t)2 * vcap * ppad;
+    double* Gd = bw.hd.p + (size_t)4 * vcap * ppad;
+    double* zbase = use_pc ? bw.Z.p : bw.V.p;
+
+    auto norms = [&](const double* v, int64_t ldv, int nb) {
+        launch_norm2(v, ldv, n, bw.npart.p, kNblk, nb, s);
+        std::vector<double> h((size_t)kNblk * nb);
+        HIPCHK(hipMemcpyAsync(h.data(), bw.npart.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        sync(p);
+        std::vector<double> out(nb);
+        for (int b = 0; b < nb; ++b) {
+            double t = 0.0;
+            for (int k = 0; k < kNblk; ++k) t += h[(size_t)b * kNblk + k];
+            out[b] = std::sqrt(t);
+        }
+        return out;
+    };
+    // Gram matrix of k vectors at W (host, k x k column-major)
+    auto gram = [&](const double* W, int k) {
+        launch_bdot(plan_bdot(n, k, k), W, n, k, W, n, k, n, bw.pdot.p, Gd, ppad, s);
+        std::vector<cd> G((size_t)k * k);
+        HIPCHK(hipMemcpyAsync(bw.hh, Gd, (size_t)2 * k * ppad * sizeof(double), hipMemcpyDeviceToHost, s));
+        sync(p);
+        for (int i = 0; i < k; ++i)
+            for (int c = 0; c < k; ++c) G[(size_t)c * k + i] = cd(bw.hh[2 * (i * ppad + c)], bw.hh[2 * (i * ppad + c) + 1]);
+        return G;
+    };
+    // dst (k' vectors) = src (k vectors) T for a host k x k' matrix T (column-major)
+    auto combine = [&](const double* src, int k, const std::vector<cd>& T, int kk, double* dst) {
+        std::vector<double> th((size_t)2 * k * kk);
+        for (int c = 0; c < kk; ++c)
+            for (int i = 0; i < k; ++i) {
+                th[2 * ((size_t)i * kk + c)] = T[(size_t)c * k + i].real();     // [i][c] layout
+                th[2 * ((size_t)i * kk + c) + 1] = T[(size_t)c * k + i].imag();
+            }
+        HIPCHK(hipMemcpyAsync(bw.T.p, th.data(), th.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_bupd(plan_bupd(n, k, kk), src, n, k, bw.T.p, kk, 1, kk, n, bw.pupd.p, nullptr, n, dst, n, 1.0, 0.0, s);
+        sync(p);   // th leaves scope
+    };
+    // W (k vectors) -> orthonormal Q at dst with W ~= Q S; a second pass when the first was ill-conditioned
+    auto orthonormalize = [&](int k, const std::vector<cd>& G, const std::vector<double>& ref2, double* dst,
+                              std::vector<cd>& S) {
+        Svqb a = svqb(k, G, ref2, 1e-14);
+        if (a.k == 0) {
+            S.clear();
+            return 0;
+        }
+        if (a.lmin > 1e-8) {
+            combine(bw.Wa.p, k, a.T, a.k, dst);
+            S = a.S;
+            return a.k;
+        }
+        combine(bw.Wa.p, k, a.T, a.k, bw.Wb.p);
+        const std::vector<cd> G2 = gram(bw.Wb.p, a.k);
+        Svqb b2 = svqb(a.k, G2, std::vector<double>(a.k, 1.0), 1e-14);
+        combine(bw.Wb.p, a.k, b2.T, b2.k, dst);
+        S.assign((size_t)b2.k * k, cd(0.0, 0.0));        // S = S2 S1
+        for (int c = 0; c < k; ++c)
+            for (int r = 0; r < b2.k; ++r) {
+                cd t = 0.0;
+                for (int m = 0; m < a.k; ++m) t += b2.S[(size_t)m * b2.k + r] * a.S[(size_t)c * a.k + m];
+                S[(size_t)c * b2.k + r] = t;
+            }
+        return b2.k;
+    };
+
+    int status = MTF_OK;
+    for (int g0 = 0; g0 < nrhs; g0 += pb) {
+        const int q = std::min(pb, nrhs - g0);
+        auto t0 = std::chrono::steady_clock::now();
+        const double* B = Bp + 2 * ld * (int64_t)g0;
+        double* X = Xp + 2 * ld * (int64_t)g0;
+        for (int c = 0; c < q; ++c) {
+            if (opts.x0_dev)
+                HIPCHK(hipMemcpyAsync(X + 2 * ld * c, static_cast<const double*>(opts.x0_dev) + 2 * ld * (int64_t)(g0 + c),
+                                      2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            else launch_fill(X + 2 * ld * c, 2 * n, 0.0, s);
+        }
+        const std::vector<double> bn = norms(B, ld, q);
+        std::vector<double> rel(q, 1.0);
+        std::vector<char> conv(q, 0);
+        std::vector<int> refin(q, 0);
+        int steps_total = 0;
+        for (int outer = 0; outer <= maxref; ++outer) {
+            for (int c = 0; c < q; ++c) {                                // W = B - M X (FP64)
+                double* wc = bw.Wa.p + 2 * n * c;
+                matvec1(p, X + 2 * ld * c, wc, MTF_FP64);
+                launch_axpby(wc, B + 2 * ld * c, n, 1.0, 0.0, -1.0, s);
+            }
+            const std::vector<double> rn = norms(bw.Wa.p, n, q);
+            bool all = true;
+            std::vector<double> ref2(q), tol(q);
+            for (int c = 0; c < q; ++c) {
+                rel[c] = bn[c] > 0.0 ? rn[c] / bn[c] : 0.0;
+                if (outer > 0 && !conv[c]) ++refin[c];
+                conv[c] = rel[c] <= opts.rtol;
+                ref2[c] = conv[c] ? 0.0 : rn[c] * rn[c];                 // converged columns drop out
+                tol[c] = 0.9 * opts.rtol * bn[c];
+                if (!conv[c]) all = false;
+            }
+            if (all || outer == maxref) break;
+            // V_1 S_0 = R (the residual block)
+            for (int c = 0; c < q; ++c)
+                if (conv[c]) launch_fill(bw.Wa.p + 2 * n * c, 2 * n, 0.0, s);
+            std::vector<cd> S;
+            int pk = orthonormalize(q, gram(bw.Wa.p, q), ref2, bw.V.p, S);
+            BlockLsq ls;
+            ls.init((int)dmax, vcap, pmax, q);
+            for (int c = 0; c < q; ++c)
+                for (int r = 0; r < pk; ++r) {
+                    ls.G[2 * ((size_t)c * vcap + r)] = S[(size_t)c * pk + r].real();
+                    ls.G[2 * ((size_t)c * vcap + r) + 1] = S[(size_t)c * pk + r].imag();
+                }
+            int64_t ncol = 0, nrow = pk;     // columns of the Hessenberg matrix reduced; basis vectors
+            int steps = 0;
+            std::vector<double> hc;
+            while (pk > 0 && ncol + pk <= dmax) {
+                const double* vk = bw.V.p + 2 * n * (nrow - pk);
+                double* zk = zbase + 2 * n * ncol;
+                if (use_pc)
+                    for (int c = 0; c < pk; ++c) {
+                        if (pc == MTF_PREC_BLOCK_TINV_GS) precond1_gs(p, vk + 2 * n * c, zk + 2 * n * c, bw.tmp.p);
+                        else precond1(p, vk + 2 * n * c, zk + 2 * n * c);
+                    }
+                for (int c = 0; c < pk; ++c) matvec1(p, zk + 2 * n * c, bw.Wa.p + 2 * n * c, MTF_FP64);
+                // two passes of block classical Gram-Schmidt against the nrow basis vectors
+                const int j = (int)nrow;
+                const BlockDotPlan pdp = plan_bdot(n, j, pk);
+                const BlockUpdPlan pup = plan_bupd(n, j, pk);
+                launch_bdot(pdp, bw.V.p, n, j, bw.Wa.p, n, pk, n, bw.pdot.p, H1, ppad, s);
+                launch_bupd(pup, bw.V.p, n, j, H1, ppad, 1, pk, n, bw.pupd.p, bw.Wa.p, n, bw.Wa.p, n, -1.0, 1.0, s);
+                launch_bdot(pdp, bw.V.p, n, j, bw.Wa.p, n, pk, n, bw.pdot.p, H2, ppad, s);
+                launch_bupd(pup, bw.V.p, n, j, H2, ppad, 1, pk, n, bw.pupd.p, bw.Wa.p, n, bw.Wa.p, n, -1.0, 1.0, s);
+                launch_bdot(plan_bdot(n, pk, pk), bw.Wa.p, n, pk, bw.Wa.p, n, pk, n, bw.pdot.p, Gd, ppad, s);
+                const size_t hj = (size_t)2 * j * ppad * sizeof(double);
+                HIPCHK(hipMemcpyAsync(bw.hh, H1, hj, hipMemcpyDeviceToHost, s));
+                HIPCHK(hipMemcpyAsync(bw.hh + (H2 - H1), H2, hj, hipMemcpyDeviceToHost, s));
+                HIPCHK(hipMemcpyAsync(bw.hh + (Gd - H1), Gd, (size_t)2 * ppad * ppad * sizeof(double),
+                                      hipMemcpyDeviceToHost, s));
+                sync(p);
+                const double* h1 = bw.hh;
+                const double* h2 = bw.hh + (size_t)2 * vcap * ppad;
+                const double* gh = bw.hh + (size_t)4 * vcap * ppad;
+                std::vector<cd> G((size_t)pk * pk);
+                for (int i = 0; i < pk; ++i)
+                    for (int c = 0; c < pk; ++c) G[(size_t)c * pk + i] = cd(gh[2 * (i * ppad + c)], gh[2 * (i * ppad + c) + 1]);
+                std::vector<double> r2(pk);
+                for (int c = 0; c < pk; ++c) {
+                    double t = G[(size_t)c * pk + c].real();
+                    for (int i = 0; i < j; ++i) {
+                        const size_t e = 2 * ((size_t)i * ppad + c);
+                        t += std::norm(cd(h1[e] + h2[e], h1[e + 1] + h2[e + 1]));
+                    }
+                    r2[c] = t;                                           // ||M z_c||^2
+                }
+                std::vector<cd> Sn;
+                const int pnew = orthonormalize(pk, G, r2, bw.V.p + 2 * n * nrow, Sn);
+                // new block column of the Hessenberg matrix: rows 0..j-1 from the projections, then S
+                const int64_t rows = nrow + pnew;
+                hc.assign((size_t)2 * rows * pk, 0.0);
+                for (int c = 0; c < pk; ++c) {
+                    double* y = hc.data() + (size_t)2 * rows * c;
+                    for (int i = 0; i < j; ++i) {
+                        const size_t e = 2 * ((size_t)i * ppad + c);
+                        y[2 * i] = h1[e] + h2[e];
+                        y[2 * i + 1] = h1[e + 1] + h2[e + 1];
+                    }
+                    for (int r = 0; r < pnew; ++r) {
+                        y[2 * (j + r)] = Sn[(size_t)c * pnew + r].real();
+                        y[2 * (j + r) + 1] = Sn[(size_t)c * pnew + r].imag();
+                    }
+                }
+                // earlier reflectors on the new columns (independent columns: host threads)
+                host_parallel(pk, ncol * pk > 8192, [&](int c) {
+                    double* y = hc.data() + (size_t)2 * rows * c;
+                    for (int64_t m = 0; m < ncol; ++m) ls.apply((int)m, y);
+                });
+                for (int c = 0; c < pk; ++c) {
+                    const int64_t col = ncol + c;
+                    double* y = hc.data() + (size_t)2 * rows * c;
+                    ls.make((int)col, (int)(rows - col), y);
+                    for (int c2 = c + 1; c2 < pk; ++c2) ls.apply((int)col, hc.data() + (size_t)2 * rows * c2);
+                    for (int r = 0; r < q; ++r) ls.apply((int)col, ls.G.data() + (size_t)2 * vcap * r);
+                    HIPCHK(hipMemcpyAsync(bw.R.p + (size_t)2 * col * dmax, y, (size_t)2 * (col + 1) * sizeof(double),
+                                          hipMemcpyHostToDevice, s));
+                }
+                ncol += pk;
+                nrow = rows;
+                pk = pnew;
+                ++steps;
+                bool done = true;
+                for (int c = 0; c < q; ++c) {
+                    if (ref2[c] == 0.0) continue;
+                    double t = 0.0;
+                    for (int64_t r = ncol; r < nrow; ++r) {
+                        const size_t e = 2 * ((size_t)c * vcap + r);
+                        t += ls.G[e] * ls.G[e] + ls.G[e + 1] * ls.G[e + 1];
+                    }
+                    if (std::sqrt(t) > tol[c]) done = false;
+                }
+                sync(p);   // the R columns were copied from hc
+                if (done) break;
+            }
+            steps_total += steps;
+            if (ncol == 0) break;
+            // X += Z Y, Y = R^-1 G(0:ncol, :)
+            std::vector<double> yh((size_t)2 * dmax * q, 0.0);
+            for (int c = 0; c < q; ++c)
+                std::memcpy(yh.data() + (size_t)2 * dmax * c, ls.G.data() + (size_t)2 * vcap * c,
+                            (size_t)2 * ncol * sizeof(double));
+            HIPCHK(hipMemcpyAsync(bw.Y.p, yh.data(), yh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+            std::vector<int> cn(q, (int)ncol);
+            HIPCHK(hipMemcpyAsync(bw.cnt.p, cn.data(), q * sizeof(int), hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemsetAsync(bw.info.p, 0, sizeof(int), s));
+            launch_trsv_upper(bw.R.p, dmax, 0, bw.cnt.p, bw.Y.p, dmax, bw.info.p, q, s);
+            launch_bupd(plan_bupd(n, (int)ncol, q), zbase, n, (int)ncol, bw.Y.p, 1, dmax, q, n, bw.pupd.p, X, ld, X, ld,
+                        1.0, 1.0, s);
+            int info = 0;
+            HIPCHK(hipMemcpyAsync(&info, bw.info.p, sizeof(int), hipMemcpyDeviceToHost, s));
+            sync(p);
+            if (info) throw NonFiniteError("block GMRES: zero pivot in the least-squares factor");
+        }
+        const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (int c = 0; c < q; ++c) {
+            if (stats) {
+                mtf_solve_stats& st = stats[g0 + c];
+                st.iterations = steps_total;
+                st.refinements = refin[c];
+                st.converged = conv[c] ? 1 : 0;
+                st.reorthogonalizations = steps_total;
+                st.rel_residual = rel[c];
+                st.t_precond_s = (g0 + c) == 0 ? t_pc : 0.0;
+                st.t_solve_s = dt;
+            }
+            if (!conv[c]) status = MTF_NOT_CONVERGED;
+        }
+    }
+    return status;
+}
+
 int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int64_t ld, const mtf_solve_opts* o,
                mtf_solve_stats* stats) {
     if (!p->has_mesh || !p->has_mat) throw StateError("mtf_solve before mesh/materials");
@@ -1751,13 +2225,23 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
     DeviceGuard g(p->device);
     const int pc = opts.preconditioner;
     const bool use_pc = pc != MTF_PREC_NONE;
-    if (opts.flags & ~(MTF_SOLVE_EAGER | MTF_SOLVE_PC_FULL | MTF_SOLVE_BASIS_C64)) throw ArgError("unknown solve flags");
+    if (opts.flags & ~(MTF_SOLVE_EAGER | MTF_SOLVE_PC_FULL | MTF_SOLVE_BASIS_C64 | MTF_SOLVE_BLOCK(0xff)))
+        throw ArgError("unknown solve flags");
     const bool basis_c64 = (opts.flags & MTF_SOLVE_BASIS_C64) != 0;
+    const int block = (opts.flags >> 8) & 0xff;
+    if (block > 0) {
+        if (block > kMaxBlock) throw ArgError("block GMRES takes at most 32 right-hand sides per block");
+        if (prec != MTF_FP64) throw UnsupportedError("block GMRES runs with the FP64 operator only");
+        if (basis_c64) throw UnsupportedError("block GMRES keeps its basis in complex128");
+    }
     if (basis_c64 && !use_pc) throw ArgError("MTF_SOLVE_BASIS_C64 needs a preconditioner (the flexible iteration)");
     const bool graph = (opts.flags & MTF_SOLVE_EAGER) == 0;
     const bool pc_full = (opts.flags & MTF_SOLVE_PC_FULL) != 0;
     double t_pc = 0;
     if (use_pc && (!p->have_tinv || p->pc_force_full != pc_full)) { build_tinv(p, pc_full); t_pc = p->t_precond; }
+    if (block > 0)
+        return block_solve(p, nrhs, static_cast<const double*>(b_dev), static_cast<double*>(x_dev), ld, opts, block, pc,
+                           stats, t_pc);
     // right-hand sides advance in lockstep batches when the products are GEMMs
     const int nbmax = prec == MTF_BF16_SPLIT ? std::min<int>(nrhs, kMaxBatch) : 1;
     if (maxit == 0) {

@@ -277,3 +277,28 @@ void launch_zgemm(int m, int n, int k, bool herm_a, const double* A, int64_t lda
 void launch_c128_to_c64(const double* X, int64_t ld, int64_t n, int cols, float* Y, hipStream_t s);
 void launch_c64_to_c128(const float* X, int64_t n, int cols, double* Y, int64_t ld, hipStream_t s);
 }  // namespace mtf
+
+namespace mtf {
+// Block Krylov contractions on the FP64 matrix cores (block.hip).  Vectors are complex128, each
+// contiguous, vector i of a set at base + 2 i ld doubles.
+struct BlockDotPlan {
+    int itiles = 0, ctiles = 0, ppad = 0, nchunk = 0;
+    int64_t nc = 0;
+    int64_t part_elems = 0;   // complex partial sums the launch needs
+};
+struct BlockUpdPlan {
+    int64_t ntile = 0;
+    int ctiles = 0, ppad = 0, nsplit = 0, ksplit = 0;
+    int64_t part_elems = 0;
+};
+BlockDotPlan plan_bdot(int64_t n, int j, int p);
+BlockUpdPlan plan_bupd(int64_t n, int j, int p);
+// H[i * hld + c] = V_i^H W_c for i < j, c < p (hld >= p); part: plan.part_elems complex
+void launch_bdot(const BlockDotPlan& pl, const double* V, int64_t ldv, int j, const double* W, int64_t ldw, int p,
+                 int64_t n, double* part, double* H, int hld, hipStream_t s);
+// Y_c = beta Yin_c + alpha sum_{i < j} V_i H(i, c), H(i, c) at complex index i hs_i + c hs_c; Y may
+// alias Yin (same ld); Yin is not read when beta is 0; part: plan.part_elems complex
+void launch_bupd(const BlockUpdPlan& pl, const double* V, int64_t ldv, int j, const double* H, int64_t hs_i,
+                 int64_t hs_c, int p, int64_t n, double* part, const double* Yin, int64_t ldyin, double* Y,
+                 int64_t ldy, double alpha, double beta, hipStream_t s);
+}  // namespace mtf
