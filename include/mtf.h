@@ -60,6 +60,8 @@ extern "C" {
 #define MTF_BF16_SPLIT         2   /* products with many right-hand sides on MFMA: the complex64
                                       blocks split into bfloat16 hi/lo planes, three bf16
                                       products per real product, FP32 accumulation          */
+#define MTF_FP64_MFMA          3   /* mtf_matvec only: FP64 products of up to 32 right-hand
+                                      sides on the FP64 matrix cores from the whole FP64 blocks */
 
 #define MTF_BLOCK_T            0
 #define MTF_BLOCK_K            1
@@ -89,7 +91,7 @@ extern "C" {
  * cores (one read of the basis per pass for all p vectors), and orthonormalises the block through
  * the eigen-decomposition of its Gram matrix with the columns scaled to unit norm (SVQB,
  * Stathopoulos and Wu 2002; a second pass when the block is ill-conditioned), dropping directions
- * whose scaled eigenvalue is at most 1e-14, so that the block narrows when the right-hand sides
+ * whose scaled eigenvalue is at most 1e-24, so that the block narrows when the right-hand sides
  * become dependent.  The block least-squares problem is reduced by Householder reflections on the
  * host; a group stops when every one of its residuals meets the target, restarts from the
  * corrected solution when the basis is full (opts.max_iters basis vectors, 0: from free device
@@ -212,7 +214,9 @@ int mtf_rhs_plane_waves(mtf_problem p, int32_t nrhs, const double* d, const doub
  * MTF_BF16_SPLIT applies every subdomain's 2x2 Calderon block to all nrhs
  * columns as one GEMM, [Y_iD | Y_iN] = [K_i | T_i] [[2X_iD, 2X_iN], [2/rho X_iN,
  * -2 rho X_iD]], on MFMA (needs the MTF_FP32_MIXED blocks; relative error of the
- * product ~1e-5). */
+ * product ~1e-5).  MTF_FP64_MFMA (nrhs <= 32, FP64 blocks) computes the same GEMM in FP64 on
+ * v_mfma_f64_16x16x4f64, T_i and K_i read once for all nrhs vectors (block GMRES uses it for its
+ * block products); the result equals the MTF_FP64 product up to summation order. */
 int mtf_matvec(mtf_problem p, int32_t nrhs, const void* x_dev, void* y_dev, int64_t ld,
                int32_t precision);
 

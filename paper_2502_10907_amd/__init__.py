@@ -31,6 +31,7 @@ _lib = C.CDLL(LIB_PATH)
 OK, NOT_CONVERGED = 0, 1
 ERR_NAMES = {-1: "ARG", -2: "MESH", -3: "NONFINITE", -4: "HIP", -5: "OOM", -6: "STATE", -7: "UNSUPPORTED"}
 FP64, FP32_MIXED, BF16_SPLIT = 0, 1, 2
+FP64_MFMA = 3      # mtf_matvec only: FP64 products of up to 32 vectors on the FP64 matrix cores
 BLOCK_T, BLOCK_K = 0, 1
 PREC_NONE, PREC_BLOCK_TINV, PREC_BLOCK_TINV_GS = 0, 1, 2
 SOLVE_EAGER = 1

@@ -184,6 +184,153 @@ __global__ __launch_bounds__(256) void k_bupd_finish(const double2* __restrict__
     Y[(int64_t)c * ldy + e] = y;
 }
 
+
+// Multi-right-hand-side FP64 product of the diagonal blocks (the 2 A_i part of M) for q vectors:
+// one wavefront per (subdomain, 64 rows, 16 right-hand sides, k-range):
+//     yD += K (2 x_D) + T ((2 / rho) x_N),   yN += K (2 x_N) + T (-2 rho x_D)
+// over its k-range of columns of T_i, K_i (complex128, column-major, read whole), written as
+// partial sums per k-range; k_mmv_finish adds them up with the transmission terms.
+__global__ __launch_bounds__(64) void k_mmv(const DomDesc* __restrict__ doms, const int4* __restrict__ items,
+                                            const double2* __restrict__ T, const double2* __restrict__ K,
+                                            const double2* __restrict__ x, int64_t ldx, int q,
+                                            const int64_t* __restrict__ pbase, int kc, double2* __restrict__ part) {
+    const int4 it = items[blockIdx.x];               // (dom, row0, rhs0, split)
+    const DomDesc dd = doms[it.x];
+    const int E = dd.E;
+    const int lane = threadIdx.x;
+    const int r = lane & 15, ks = lane >> 4;
+    const int row0 = it.y, c = it.z + r;
+    const int kb = it.w * kc;
+    const int ke = kb + kc < E ? kb + kc : E;
+    const int cc = c < q ? c : q - 1;
+    const double2* xd = x + (int64_t)cc * ldx + dd.off;
+    const double2* xn = xd + E;
+    const double rho = dd.rho;
+    const double2* Tb = T + dd.mat0;
+    const double2* Kb = K + dd.mat0;
+    int rowc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int rr = row0 + 16 * b + r;
+        rowc[b] = rr < E ? rr : E - 1;                  // rows past E are computed, never stored
+    }
+    d4 aDr[4], aDi[4], aNr[4], aNi[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        aDr[b] = d4{0.0, 0.0, 0.0, 0.0};
+        aDi[b] = aDr[b];
+        aNr[b] = aDr[b];
+        aNi[b] = aDr[b];
+    }
+    for (int k0 = kb; k0 < ke; k0 += 16) {
+        const int kk = k0 + 4 * ks;
+        double2 vd[4], vn[4];
+        if (kk + 4 <= ke) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                vd[t] = xd[kk + t];
+                vn[t] = xn[kk + t];
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const bool ok = kk + t < ke;
+                vd[t] = ok ? xd[kk + t] : make_double2(0.0, 0.0);
+                vn[t] = ok ? xn[kk + t] : make_double2(0.0, 0.0);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int col = kk + t < ke ? kk + t : ke - 1;     // its B values are zero past ke
+            const double2* Kc = Kb + (int64_t)col * E;
+            const double2* Tc = Tb + (int64_t)col * E;
+            // scaled right-hand operands: 2 x_D, 2 x_N, (2 / rho) x_N, -2 rho x_D
+            const double dr = 2.0 * vd[t].x, di = 2.0 * vd[t].y;
+            const double nr = 2.0 * vn[t].x, ni = 2.0 * vn[t].y;
+            const double tnr = nr / rho, tni = ni / rho;
+            const double tdr = -rho * dr, tdi = -rho * di;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const double2 kv = Kc[rowc[b]];
+                const double2 tv = Tc[rowc[b]];
+                // (a)(b) = (ar br - ai bi) + i (ar bi + ai br)
+                aDr[b] = mfma(kv.x, dr, aDr[b]);
+                aDr[b] = mfma(-kv.y, di, aDr[b]);
+                aDi[b] = mfma(kv.x, di, aDi[b]);
+                aDi[b] = mfma(kv.y, dr, aDi[b]);
+                aDr[b] = mfma(tv.x, tnr, aDr[b]);
+                aDr[b] = mfma(-tv.y, tni, aDr[b]);
+                aDi[b] = mfma(tv.x, tni, aDi[b]);
+                aDi[b] = mfma(tv.y, tnr, aDi[b]);
+                aNr[b] = mfma(kv.x, nr, aNr[b]);
+                aNr[b] = mfma(-kv.y, ni, aNr[b]);
+                aNi[b] = mfma(kv.x, ni, aNi[b]);
+                aNi[b] = mfma(kv.y, nr, aNi[b]);
+                aNr[b] = mfma(tv.x, tdr, aNr[b]);
+                aNr[b] = mfma(-tv.y, tdi, aNr[b]);
+                aNi[b] = mfma(tv.x, tdi, aNi[b]);
+                aNi[b] = mfma(tv.y, tdr, aNi[b]);
+            }
+        }
+    }
+    if (c >= q) return;
+    // partial sums of split s: part[pbase[dom] + ((s q + rhs) 2 + side) E + row]
+    double2* outD = part + pbase[it.x] + ((int64_t)(it.w * q + c) * 2) * E;
+    double2* outN = outD + E;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int rr = row0 + 16 * b + 4 * e + ks;
+            if (rr < E) {
+                outD[rr] = make_double2(aDr[b][e], aDi[b][e]);
+                outN[rr] = make_double2(aNr[b][e], aNi[b][e]);
+            }
+        }
+}
+
+// y_j = sum over splits of the partial diagonal-block products + the transmission terms G x_j, for
+// every dof of every subdomain and right-hand side j < q
+__global__ __launch_bounds__(256) void k_mmv_finish(const DomDesc* __restrict__ doms, const int32_t* __restrict__ dof_dom,
+                                                    int64_t ndof, const int32_t* __restrict__ dplus,
+                                                    const int32_t* __restrict__ dminus, const double* __restrict__ gval,
+                                                    const int64_t* __restrict__ gcol, const double2* __restrict__ part,
+                                                    const int64_t* __restrict__ pbase, const int* __restrict__ nsplit,
+                                                    int q, const double2* __restrict__ x, int64_t ldx,
+                                                    double2* __restrict__ y, int64_t ldy) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (g >= ndof || j >= q) return;
+    const int dom = dof_dom[g];
+    const DomDesc dd = doms[dom];
+    const int64_t m = g - dd.dof0;
+    const int E = dd.E;
+    double yD[2] = {0.0, 0.0}, yN[2] = {0.0, 0.0};
+    const double2* pb = part + pbase[dom];
+    for (int s = 0; s < nsplit[dom]; ++s) {
+        const double2 a = pb[((int64_t)(s * q + j) * 2) * E + m];
+        const double2 b = pb[((int64_t)(s * q + j) * 2 + 1) * E + m];
+        yD[0] += a.x; yD[1] += a.y;
+        yN[0] += b.x; yN[1] += b.y;
+    }
+    const double2* xj = x + (int64_t)j * ldx;
+    for (int side = 0; side < 2; ++side) {
+        const int32_t* pm = side == 0 ? dplus : dminus;
+        const int64_t rec = dd.rec0 + pm[2 * g];
+        const int a = pm[2 * g + 1];
+        for (int c = 0; c < 3; ++c) {
+            const double v = gval[9 * rec + 3 * a + c];
+            const double2 xd = xj[gcol[6 * rec + c]];
+            const double2 xn = xj[gcol[6 * rec + 3 + c]];
+            yD[0] += v * xd.x; yD[1] += v * xd.y;
+            yN[0] += v * xn.x; yN[1] += v * xn.y;
+        }
+    }
+    double2* yj = y + (int64_t)j * ldy;
+    yj[dd.off + m] = make_double2(yD[0], yD[1]);
+    yj[dd.off + E + m] = make_double2(yN[0], yN[1]);
+}
+
 inline unsigned gridn(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -244,6 +391,21 @@ void launch_bupd(const BlockUpdPlan& pl, const double* V, int64_t ldv, int j, co
     hipLaunchKernelGGL(k_bupd_finish, dim3(gridn(n, 256), (unsigned)p), dim3(256), 0, s,
                        reinterpret_cast<const double2*>(part), j > 0 ? pl.nsplit : 0, pl.ppad, p, n,
                        reinterpret_cast<const double2*>(Yin), ldyin, reinterpret_cast<double2*>(Y), ldy, alpha, beta);
+}
+
+
+void launch_mmv(const DomDesc* doms, const int4* items, int64_t nitems, const double* T, const double* K, const double* x,
+                int64_t ldx, int q, const int64_t* pbase, int kc, double* part, const int32_t* dof_dom, int64_t ndof,
+                const int32_t* dplus, const int32_t* dminus, const double* gval, const int64_t* gcol,
+                const int* nsplit, double* y, int64_t ldy, hipStream_t s) {
+    if (q <= 0) return;
+    if (nitems > 0)
+        hipLaunchKernelGGL(k_mmv, dim3((unsigned)nitems), dim3(64), 0, s, doms, items,
+                           reinterpret_cast<const double2*>(T), reinterpret_cast<const double2*>(K),
+                           reinterpret_cast<const double2*>(x), ldx, q, pbase, kc, reinterpret_cast<double2*>(part));
+    hipLaunchKernelGGL(k_mmv_finish, dim3(gridn(ndof, 256), (unsigned)q), dim3(256), 0, s, doms, dof_dom, ndof, dplus,
+                       dminus, gval, gcol, reinterpret_cast<const double2*>(part), pbase, nsplit, q,
+                       reinterpret_cast<const double2*>(x), ldx, reinterpret_cast<double2*>(y), ldy);
 }
 
 }  // namespace mtf

@@ -35,6 +35,12 @@ constexpr double kPcSymTol = 1e-3;   // largest ||T_i S_i^-1 v - v|| / ||v|| of 
 constexpr int kSync = 8;      // Arnoldi steps between host reads of the Hessenberg columns
 constexpr int kMaxBatch = 64; // right-hand sides per lockstep GMRES batch (MFMA products)
 constexpr int kMaxBlock = 32; // right-hand sides per block of block GMRES
+// smallest kept eigenvalue of a block's scaled Gram matrix (singular value 1e-12 of a unit column):
+// a direction dropped below it leaves an error of that size in the Arnoldi relation
+constexpr double kBlockKeep = 1e-24;
+// blocks of at least this many vectors use the FP64 multi-RHS product (whole blocks, read once for
+// the block); narrower ones the symmetric-read product per vector
+constexpr int kMmvMin = 3;
 constexpr int kUpdGroups = 8; // partial-sum groups of the basis update
 constexpr int kBatchCycle = 1000;  // Arnoldi steps per cycle in mtf_batch_solve when max_iters is 0
 constexpr int kEagerBatches = 2;   // Arnoldi batches of a cycle launched eagerly before a graph is captured
@@ -115,6 +121,16 @@ void swap_work(GmresWork& a, GmresWork& b) {
 
 }  // namespace
 
+// Work items and partial sums of the FP64 multi-right-hand-side product (launch_mmv) for q vectors.
+struct MmvPlan {
+    DevBuf<int4> items;
+    DevBuf<int64_t> pbase;
+    DevBuf<int> nsplit;
+    DevBuf<double> part;
+    int64_t nitems = 0;
+    int q = 0;
+};
+
 struct mtf_problem_s {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -151,6 +167,7 @@ struct mtf_problem_s {
     bool have64 = false, have32 = false, have_tinv = false;
     int tinv_prec = MTF_FP64;        // blocks the T_i^-1 preconditioner was built from (MTF_FP64 / MTF_FP32_MIXED)
     GemmOp gm, gp;                   // multi-RHS MFMA products: operator blocks, preconditioner blocks
+    MmvPlan mmv;                     // FP64 multi-RHS MFMA product
     // block Gauss-Seidel stages: stage 0 = {Omega_0}, then colour classes of the subdomain graph
     DevBuf<int4> d_stage_tiles, d_pctiles;    // preconditioner tiles per Gauss-Seidel stage, and all of them
     int64_t npctiles = 0;
@@ -712,6 +729,42 @@ void matvec1(mtf_problem p, const double* x, double* y, int prec, double* part =
     launch_matvec_sym_finish(p->d_doms.p, p->d_dof_dom.p, p->ndof, p->d_dplus.p, p->d_dminus.p, p->d_gval.p,
                              p->d_gcol.p, p->d_near_ptr.p, p->d_near_col.p,
                              prec == MTF_FP64 ? p->near64.p : p->near32.p, part, x, y, s);
+}
+
+constexpr int kMmvCols = 1536;   // columns of T_i, K_i per work item of the FP64 multi-RHS product
+
+// Y = M X for q <= 32 vectors (ld ldx, ldy) with the FP64 multi-RHS product on the matrix cores;
+// the work items (largest column ranges first) and partial sums are kept per q.
+void matvec_mmv(mtf_problem p, int q, const double* X, int64_t ldx, double* Y, int64_t ldy) {
+    MmvPlan& mp = p->mmv;
+    hipStream_t s = p->stream;
+    if (mp.q != q) {
+        std::vector<int4> items;
+        std::vector<int64_t> pbase;
+        std::vector<int> nsp;
+        int64_t tot = 0;
+        for (size_t d = 0; d < p->doms.size(); ++d) {
+            const int E = p->doms[d].E;
+            const int ns = (E + kMmvCols - 1) / kMmvCols;
+            pbase.push_back(tot);
+            nsp.push_back(ns);
+            tot += (int64_t)ns * q * 2 * E;
+            for (int sp = 0; sp < ns; ++sp)
+                for (int r0 = 0; r0 < E; r0 += 64)
+                    for (int c0 = 0; c0 < q; c0 += 16) items.push_back(make_int4((int)d, r0, c0, sp));
+        }
+        auto span = [&](const int4& it) { return std::min(kMmvCols, p->doms[it.x].E - it.w * kMmvCols); };
+        std::stable_sort(items.begin(), items.end(), [&](const int4& a, const int4& b) { return span(a) > span(b); });
+        mp.items.upload(items, s);
+        mp.pbase.upload(pbase, s);
+        mp.nsplit.upload(nsp, s);
+        mp.part.alloc((size_t)2 * tot);
+        mp.nitems = (int64_t)items.size();
+        mp.q = q;
+        sync(p);
+    }
+    launch_mmv(p->d_doms.p, mp.items.p, mp.nitems, p->T64.p, p->K64.p, X, ldx, q, mp.pbase.p, kMmvCols, mp.part.p,
+               p->d_dof_dom.p, p->ndof, p->d_dplus.p, p->d_dminus.p, p->d_gval.p, p->d_gcol.p, mp.nsplit.p, Y, ldy, s);
 }
 
 // Partial sums of the allocation-free product (mtf_matvec_noalloc): a fixed array in device
@@ -2002,7 +2055,7 @@ int block_solve(mtf_problem p, int32_t nrhs, const double* Bp, double* Xp, int64
     // W (k vectors) -> orthonormal Q at dst with W ~= Q S; a second pass when the first was ill-conditioned
     auto orthonormalize = [&](int k, const std::vector<cd>& G, const std::vector<double>& ref2, double* dst,
                               std::vector<cd>& S) {
-        Svqb a = svqb(k, G, ref2, 1e-14);
+        Svqb a = svqb(k, G, ref2, kBlockKeep);
         if (a.k == 0) {
             S.clear();
             return 0;
@@ -2014,7 +2067,7 @@ int block_solve(mtf_problem p, int32_t nrhs, const double* Bp, double* Xp, int64
         }
         combine(bw.Wa.p, k, a.T, a.k, bw.Wb.p);
         const std::vector<cd> G2 = gram(bw.Wb.p, a.k);
-        Svqb b2 = svqb(a.k, G2, std::vector<double>(a.k, 1.0), 1e-14);
+        Svqb b2 = svqb(a.k, G2, std::vector<double>(a.k, 1.0), kBlockKeep);
         combine(bw.Wb.p, a.k, b2.T, b2.k, dst);
         S.assign((size_t)b2.k * k, cd(0.0, 0.0));        // S = S2 S1
         for (int c = 0; c < k; ++c)
@@ -2084,7 +2137,9 @@ int block_solve(mtf_problem p, int32_t nrhs, const double* Bp, double* Xp, int64
                         if (pc == MTF_PREC_BLOCK_TINV_GS) precond1_gs(p, vk + 2 * n * c, zk + 2 * n * c, bw.tmp.p);
                         else precond1(p, vk + 2 * n * c, zk + 2 * n * c);
                     }
-                for (int c = 0; c < pk; ++c) matvec1(p, zk + 2 * n * c, bw.Wa.p + 2 * n * c, MTF_FP64);
+                if (pk >= kMmvMin) matvec_mmv(p, pk, zk, n, bw.Wa.p, n);
+                else
+                    for (int c = 0; c < pk; ++c) matvec1(p, zk + 2 * n * c, bw.Wa.p + 2 * n * c, MTF_FP64);
                 // two passes of block classical Gram-Schmidt against the nrow basis vectors
                 const int j = (int)nrow;
                 const BlockDotPlan pdp = plan_bdot(n, j, pk);
@@ -2674,9 +2729,16 @@ int mtf_matvec(mtf_problem p, int32_t nrhs, const void* x_dev, void* y_dev, int6
         if (!p->has_mesh || !p->has_mat) throw StateError("mtf_matvec before mesh/materials");
         if (nrhs < 1 || !x_dev || !y_dev || ld < p->sk.N) throw ArgError("bad arguments");
         if (x_dev == y_dev) throw ArgError("x and y must not alias");
-        check_prec_available(p, precision);
+        if (precision == MTF_FP64_MFMA) {
+            if (nrhs > kMaxBlock) throw ArgError("MTF_FP64_MFMA takes at most 32 vectors");
+            check_prec_available(p, MTF_FP64);
+        } else {
+            check_prec_available(p, precision);
+        }
         DeviceGuard g(p->device);
-        if (precision == MTF_BF16_SPLIT) {
+        if (precision == MTF_FP64_MFMA) {
+            matvec_mmv(p, nrhs, static_cast<const double*>(x_dev), ld, static_cast<double*>(y_dev), ld);
+        } else if (precision == MTF_BF16_SPLIT) {
             matvec_gemm(p, nrhs, static_cast<const double*>(x_dev), ld, static_cast<double*>(y_dev));
         } else {
             for (int r = 0; r < nrhs; ++r)

@@ -130,6 +130,71 @@ def test_full_size_entries_fp32_c3():
     _check_entries(P, pb, mtf.FP32_MIXED, np.random.default_rng(2), [0, 1, 64], 8, 3e-5)
 
 
+def _oracle_row_blocks(pb, i, rows):
+    """Oracle rows `rows` of both row blocks of subdomain i of M: T_i, K_i rows and the transmission
+    rows G^ij (j adjacent to i)."""
+    sp = pb.spaces[i]
+    Tr, Kr = op.rows_TK(pb.xyz, sp, rows, pb.k[i])
+    G = [(j, op.gram_twisted(pb.xyz, sp, pb.spaces[j])[rows]) for j in sk.neighbours(pb.label, i)]
+    return Tr, Kr, G
+
+
+def _apply_rows(pb, i, rows, blocks, xs):
+    """(indices, values) of the sampled rows of M x: 2 A_i x_i + sum_j G^ij x_j."""
+    Tr, Kr, G = blocks
+    o, E = pb.offsets[i], pb.E[i]
+    xD, xN = xs[o:o + E], xs[o + E:o + 2 * E]
+    yD = 2 * (Kr @ xD) + (2 / pb.rho[i]) * (Tr @ xN)
+    yN = -2 * pb.rho[i] * (Tr @ xD) + 2 * (Kr @ xN)
+    for j, Gij in G:
+        oj, Ej = pb.offsets[j], pb.E[j]
+        yD = yD + Gij @ xs[oj:oj + Ej]
+        yN = yN + Gij @ xs[oj + Ej:oj + 2 * Ej]
+    return o + rows, o + E + rows, yD, yN
+
+
+def test_full_size_block_gmres_c3():
+    """The 4x4x4 partition at h = 1/24 (N = 103,680) with 16 of its plane-wave right-hand sides
+    (8 Fibonacci directions x 2 polarisations) solved as one block (block GMRES, FP64 operator,
+    block Gauss-Seidel preconditioner) to an FP64 residual of 1e-6.  Checked for two of them
+    through oracle rows of M: 8 sampled rows of the exterior block Omega_0 (E_0 = 10,368) and 6 of
+    a sub-cube, each residual entry bounded by the residual norm."""
+    print("\n[case] 4x4x4 cube h=1/24 full size, block GMRES over 16 right-hand sides", flush=True)
+    cfg = mi.config_cube_multi_rhs(4, 24, 128)
+    m = cfg["mesh"]
+    P = mtf.Problem(0)
+    P.set_mesh(m.xyz, m.tri, m.label, m.M)
+    P.set_materials(cfg["k0"], cfg["eps_r"], cfg["mu_r"])
+    P.assemble(mtf.FP64)
+    assert P.N == 103680
+    d, p = cfg["d"][:16], cfg["p"][:16]
+    b = torch.zeros((16, P.N), dtype=torch.complex128, device="cuda")
+    P.rhs_plane_waves(d, p, b)
+    x = torch.zeros_like(b)
+    st = P.solve(b, x, rtol=1e-6, preconditioner=mtf.PREC_BLOCK_TINV_GS, block=16)
+    print(f"[c3 block 16] block steps {st[0].iterations} residual max {max(s.rel_residual for s in st):.2e} "
+          f"time {st[0].t_solve_s:.2f} s", flush=True)
+    assert all(s.converged and s.rel_residual <= 1e-6 for s in st)
+    pb = sy.Problem.from_config(cfg)
+    rng = np.random.default_rng(7)
+    sampled = []
+    for i, nrow in ((0, 8), (37, 6)):
+        rows = rng.choice(pb.E[i], nrow, replace=False)
+        sampled.append((i, rows, _oracle_row_blocks(pb, i, rows)))
+    for col in (0, 9):
+        bo = sy.rhs(pb, d[col:col + 1], p[col:col + 1])[:, 0]
+        assert np.abs(b[col].cpu().numpy() - bo).max() < 1e-13 * np.abs(bo).max()
+        xs = x[col].cpu().numpy()
+        bound = 1.05e-6 * np.linalg.norm(bo)
+        for i, rows, blocks in sampled:
+            iD, iN, yD, yN = _apply_rows(pb, i, rows, blocks, xs)
+            print(f"[c3 block 16] rhs {col} domain {i}: max residual entry "
+                  f"{max(np.abs(bo[iD] - yD).max(), np.abs(bo[iN] - yN).max()) / np.linalg.norm(bo):.2e} ||b||",
+                  flush=True)
+            assert np.abs(bo[iD] - yD).max() <= bound, (col, i)
+            assert np.abs(bo[iN] - yN).max() <= bound, (col, i)
+
+
 def test_full_size_tinv_residual(c2):
     """S_i^-1, S_i = (T_i + T_i^T)/2, from the complex64 inversion at full size (E_0 = 4,608,
     E_1 = 1,152): the block-Jacobi preconditioner applied to a random vector, checked through
