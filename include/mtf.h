@@ -320,7 +320,11 @@ int mtf_solve_stf(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, i
 /* z = P x for nrhs complex128 vectors (x_dev, z_dev: [nrhs][ld], ld >= N, no aliasing) with
  * the right preconditioner `preconditioner` (MTF_PREC_BLOCK_TINV or MTF_PREC_BLOCK_TINV_GS, as
  * defined for mtf_solve).  Builds S_i^-1 on first use (from the FP32 blocks if assembled, else
- * from the FP64 ones).  Stream-ordered. */
+ * from the FP64 ones).  Stream-ordered.  With MTF_PREC_MULTI or'ed in (nrhs <= 32) all vectors are
+ * preconditioned together: each complex64 block is read whole once for all of them and applied in
+ * FP64 arithmetic on the FP64 matrix cores, one launch per Gauss-Seidel stage (block GMRES uses
+ * this form; it synchronises). */
+#define MTF_PREC_MULTI 0x100
 int mtf_apply_preconditioner(mtf_problem p, int32_t preconditioner, int32_t nrhs, const void* x_dev,
                              void* z_dev, int64_t ld);
 

@@ -34,6 +34,7 @@ FP64, FP32_MIXED, BF16_SPLIT = 0, 1, 2
 FP64_MFMA = 3      # mtf_matvec only: FP64 products of up to 32 vectors on the FP64 matrix cores
 BLOCK_T, BLOCK_K = 0, 1
 PREC_NONE, PREC_BLOCK_TINV, PREC_BLOCK_TINV_GS = 0, 1, 2
+PREC_MULTI = 0x100   # mtf_apply_preconditioner: all vectors together on the FP64 matrix cores
 SOLVE_EAGER = 1
 SOLVE_PC_FULL = 2
 SOLVE_BASIS_C64 = 4
@@ -327,12 +328,13 @@ class Problem:
             raise ValueError("x and y shapes differ")
         _check(_lib.mtf_matvec_noalloc(self._h, nrhs, px, py, ld, int(precision)))
 
-    def apply_preconditioner(self, x, z, preconditioner: int = PREC_BLOCK_TINV):
+    def apply_preconditioner(self, x, z, preconditioner: int = PREC_BLOCK_TINV, multi: bool = False):
         px, nrhs, ld = _dev(x, self.N)
         pz, nrhs2, ld2 = _dev(z, self.N)
         if (nrhs, ld) != (nrhs2, ld2):
             raise ValueError("x and z shapes differ")
-        _check(_lib.mtf_apply_preconditioner(self._h, int(preconditioner), nrhs, px, pz, ld))
+        _check(_lib.mtf_apply_preconditioner(self._h, int(preconditioner) | (PREC_MULTI if multi else 0), nrhs, px,
+                                             pz, ld))
 
     def time_matvec(self, x, y, reps: int = 20, precision: int = FP64):
         """(mean seconds per dense block-kernel launch, mean seconds per whole product), HIP events."""

@@ -331,6 +331,153 @@ __global__ __launch_bounds__(256) void k_mmv_finish(const DomDesc* __restrict__ 
     yj[dd.off + E + m] = make_double2(yN[0], yN[1]);
 }
 
+
+// Block preconditioner P_i = 1/2 [[0, -S_i^-1 / rho_i], [rho_i S_i^-1, 0]] on q vectors from the whole
+// complex64 blocks (promoted to FP64 on the matrix cores), one wavefront per (subdomain, 64 rows,
+// 16 right-hand sides, k-range) of one Gauss-Seidel stage:
+//     zD += S^-1 (-x_N / (2 rho)),   zN += S^-1 (rho x_D / 2)
+// as partial sums per k-range (part layout as for k_mmv); k_pcmm_finish adds them up.
+__global__ __launch_bounds__(64) void k_pcmm(const DomDesc* __restrict__ doms, const int4* __restrict__ items,
+                                             const float2* __restrict__ S, const double2* __restrict__ x, int64_t ldx,
+                                             int q, const int64_t* __restrict__ pbase, int kc,
+                                             double2* __restrict__ part) {
+    const int4 it = items[blockIdx.x];
+    const DomDesc dd = doms[it.x];
+    const int E = dd.E;
+    const int lane = threadIdx.x;
+    const int r = lane & 15, ks = lane >> 4;
+    const int row0 = it.y, c = it.z + r;
+    const int kb = it.w * kc;
+    const int ke = kb + kc < E ? kb + kc : E;
+    const int cc = c < q ? c : q - 1;
+    const double2* xd = x + (int64_t)cc * ldx + dd.off;
+    const double2* xn = xd + E;
+    const double sD = 0.5 * dd.rho, sN = -0.5 / dd.rho;
+    const float2* Sb = S + dd.mat0;
+    int rowc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int rr = row0 + 16 * b + r;
+        rowc[b] = rr < E ? rr : E - 1;
+    }
+    d4 aDr[4], aDi[4], aNr[4], aNi[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        aDr[b] = d4{0.0, 0.0, 0.0, 0.0};
+        aDi[b] = aDr[b];
+        aNr[b] = aDr[b];
+        aNi[b] = aDr[b];
+    }
+    for (int k0 = kb; k0 < ke; k0 += 16) {
+        const int kk = k0 + 4 * ks;
+        double2 vd[4], vn[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const bool ok = kk + t < ke;
+            vd[t] = ok ? xd[kk + t] : make_double2(0.0, 0.0);
+            vn[t] = ok ? xn[kk + t] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int col = kk + t < ke ? kk + t : ke - 1;
+            const float2* Sc = Sb + (int64_t)col * E;
+            const double nr = sN * vn[t].x, ni = sN * vn[t].y;     // into zD
+            const double dr = sD * vd[t].x, di = sD * vd[t].y;     // into zN
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const float2 sv = Sc[rowc[b]];
+                const double ar = sv.x, ai = sv.y;
+                aDr[b] = mfma(ar, nr, aDr[b]);
+                aDr[b] = mfma(-ai, ni, aDr[b]);
+                aDi[b] = mfma(ar, ni, aDi[b]);
+                aDi[b] = mfma(ai, nr, aDi[b]);
+                aNr[b] = mfma(ar, dr, aNr[b]);
+                aNr[b] = mfma(-ai, di, aNr[b]);
+                aNi[b] = mfma(ar, di, aNi[b]);
+                aNi[b] = mfma(ai, dr, aNi[b]);
+            }
+        }
+    }
+    if (c >= q) return;
+    double2* outD = part + pbase[it.x] + ((int64_t)(it.w * q + c) * 2) * E;
+    double2* outN = outD + E;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int rr = row0 + 16 * b + 4 * e + ks;
+            if (rr < E) {
+                outD[rr] = make_double2(aDr[b][e], aDi[b][e]);
+                outN[rr] = make_double2(aNr[b][e], aNi[b][e]);
+            }
+        }
+}
+
+// z_j (rows of the listed dofs) = sum over splits of the partial block-preconditioner products
+__global__ __launch_bounds__(256) void k_pcmm_finish(const DomDesc* __restrict__ doms, const int32_t* __restrict__ dof_dom,
+                                                     const int32_t* __restrict__ list, int64_t nlist,
+                                                     const double2* __restrict__ part, const int64_t* __restrict__ pbase,
+                                                     const int* __restrict__ nsplit, int q, double2* __restrict__ z,
+                                                     int64_t ldz) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (t >= nlist || j >= q) return;
+    const int64_t g = list ? list[t] : t;
+    const int dom = dof_dom[g];
+    const DomDesc dd = doms[dom];
+    const int64_t m = g - dd.dof0;
+    const int E = dd.E;
+    double zD[2] = {0.0, 0.0}, zN[2] = {0.0, 0.0};
+    const double2* pb = part + pbase[dom];
+    for (int s = 0; s < nsplit[dom]; ++s) {
+        const double2 a = pb[((int64_t)(s * q + j) * 2) * E + m];
+        const double2 b = pb[((int64_t)(s * q + j) * 2 + 1) * E + m];
+        zD[0] += a.x; zD[1] += a.y;
+        zN[0] += b.x; zN[1] += b.y;
+    }
+    double2* zj = z + (int64_t)j * ldz;
+    zj[dd.off + m] = make_double2(zD[0], zD[1]);
+    zj[dd.off + E + m] = make_double2(zN[0], zN[1]);
+}
+
+// Gauss-Seidel stage input for q vectors: w = v - (transmission from the subdomains of earlier
+// stages) z, for the listed dofs (both traces)
+__global__ __launch_bounds__(256) void k_gs_residual_q(const DomDesc* __restrict__ doms, const int32_t* __restrict__ dof_dom,
+                                                       const int32_t* __restrict__ list, int64_t nlist,
+                                                       const int32_t* __restrict__ dplus, const int32_t* __restrict__ dminus,
+                                                       const double* __restrict__ gval, const int64_t* __restrict__ gcol,
+                                                       const int32_t* __restrict__ other_dom,
+                                                       const int32_t* __restrict__ dom_stage, int stage,
+                                                       const double2* __restrict__ v, const double2* __restrict__ z,
+                                                       double2* __restrict__ w, int64_t ld, int q) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (t >= nlist || j >= q) return;
+    const int64_t g = list[t];
+    const DomDesc dd = doms[dof_dom[g]];
+    const int64_t m = g - dd.dof0;
+    const int64_t iD = dd.off + m, iN = dd.off + dd.E + m;
+    const double2* vj = v + (int64_t)j * ld;
+    const double2* zj = z + (int64_t)j * ld;
+    double2 yD = vj[iD], yN = vj[iN];
+    for (int side = 0; side < 2; ++side) {
+        const int32_t* pm = side == 0 ? dplus : dminus;
+        const int64_t rec = dd.rec0 + pm[2 * g];
+        if (dom_stage[other_dom[rec]] >= stage) continue;      // neighbour not swept yet
+        const int a = pm[2 * g + 1];
+        for (int c = 0; c < 3; ++c) {
+            const double gv = gval[9 * rec + 3 * a + c];
+            const double2 zd = zj[gcol[6 * rec + c]];
+            const double2 zn = zj[gcol[6 * rec + 3 + c]];
+            yD.x -= gv * zd.x; yD.y -= gv * zd.y;
+            yN.x -= gv * zn.x; yN.y -= gv * zn.y;
+        }
+    }
+    double2* wj = w + (int64_t)j * ld;
+    wj[iD] = yD;
+    wj[iN] = yN;
+}
+
 inline unsigned gridn(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -406,6 +553,28 @@ void launch_mmv(const DomDesc* doms, const int4* items, int64_t nitems, const do
     hipLaunchKernelGGL(k_mmv_finish, dim3(gridn(ndof, 256), (unsigned)q), dim3(256), 0, s, doms, dof_dom, ndof, dplus,
                        dminus, gval, gcol, reinterpret_cast<const double2*>(part), pbase, nsplit, q,
                        reinterpret_cast<const double2*>(x), ldx, reinterpret_cast<double2*>(y), ldy);
+}
+
+
+void launch_pcmm(const DomDesc* doms, const int4* items, int64_t nitems, const float* S, const double* x, int64_t ldx,
+                 int q, const int64_t* pbase, int kc, double* part, const int32_t* dof_dom, const int32_t* list,
+                 int64_t nlist, const int* nsplit, double* z, int64_t ldz, hipStream_t s) {
+    if (q <= 0 || nlist <= 0) return;
+    if (nitems > 0)
+        hipLaunchKernelGGL(k_pcmm, dim3((unsigned)nitems), dim3(64), 0, s, doms, items, reinterpret_cast<const float2*>(S),
+                           reinterpret_cast<const double2*>(x), ldx, q, pbase, kc, reinterpret_cast<double2*>(part));
+    hipLaunchKernelGGL(k_pcmm_finish, dim3(gridn(nlist, 256), (unsigned)q), dim3(256), 0, s, doms, dof_dom, list, nlist,
+                       reinterpret_cast<const double2*>(part), pbase, nsplit, q, reinterpret_cast<double2*>(z), ldz);
+}
+
+void launch_gs_residual_q(const DomDesc* doms, const int32_t* dof_dom, const int32_t* list, int64_t nlist,
+                          const int32_t* dplus, const int32_t* dminus, const double* gval, const int64_t* gcol,
+                          const int32_t* other_dom, const int32_t* dom_stage, int stage, const double* v,
+                          const double* z, double* w, int64_t ld, int q, hipStream_t s) {
+    if (q <= 0 || nlist <= 0) return;
+    hipLaunchKernelGGL(k_gs_residual_q, dim3(gridn(nlist, 256), (unsigned)q), dim3(256), 0, s, doms, dof_dom, list, nlist,
+                       dplus, dminus, gval, gcol, other_dom, dom_stage, stage, reinterpret_cast<const double2*>(v),
+                       reinterpret_cast<const double2*>(z), reinterpret_cast<double2*>(w), ld, q);
 }
 
 }  // namespace mtf

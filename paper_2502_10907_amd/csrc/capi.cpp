@@ -131,6 +131,17 @@ struct MmvPlan {
     int q = 0;
 };
 
+// Work items of the block preconditioner (launch_pcmm) for q vectors: items of Gauss-Seidel stage st
+// at [item0[st], item0[st + 1]) (one stage holding every subdomain for the block-Jacobi form).
+struct PcmmPlan {
+    DevBuf<int4> items;
+    DevBuf<int64_t> pbase;
+    DevBuf<int> nsplit;
+    DevBuf<double> part;
+    std::vector<int64_t> item0;
+    int q = 0, pc = -1;
+};
+
 struct mtf_problem_s {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -168,6 +179,7 @@ struct mtf_problem_s {
     int tinv_prec = MTF_FP64;        // blocks the T_i^-1 preconditioner was built from (MTF_FP64 / MTF_FP32_MIXED)
     GemmOp gm, gp;                   // multi-RHS MFMA products: operator blocks, preconditioner blocks
     MmvPlan mmv;                     // FP64 multi-RHS MFMA product
+    PcmmPlan pcmm;                   // block preconditioner on the FP64 matrix cores
     // block Gauss-Seidel stages: stage 0 = {Omega_0}, then colour classes of the subdomain graph
     DevBuf<int4> d_stage_tiles, d_pctiles;    // preconditioner tiles per Gauss-Seidel stage, and all of them
     int64_t npctiles = 0;
@@ -765,6 +777,69 @@ void matvec_mmv(mtf_problem p, int q, const double* X, int64_t ldx, double* Y, i
     }
     launch_mmv(p->d_doms.p, mp.items.p, mp.nitems, p->T64.p, p->K64.p, X, ldx, q, mp.pbase.p, kMmvCols, mp.part.p,
                p->d_dof_dom.p, p->ndof, p->d_dplus.p, p->d_dminus.p, p->d_gval.p, p->d_gcol.p, mp.nsplit.p, Y, ldy, s);
+}
+
+// Z = P X for q <= 32 vectors (ld ld) with the block preconditioner read whole on the matrix cores:
+// per Gauss-Seidel stage the stage input for all q vectors (into W, q x ld), then one launch over
+// the stage's subdomains; for MTF_PREC_BLOCK_TINV one launch over every subdomain.
+void precond_block(mtf_problem p, int pc, int q, const double* X, double* Z, double* W, int64_t ld) {
+    PcmmPlan& pp = p->pcmm;
+    hipStream_t s = p->stream;
+    const int nd = (int)p->doms.size();
+    const int nst = pc == MTF_PREC_BLOCK_TINV_GS ? (int)p->stage_tile0.size() - 1 : 1;
+    if (pp.q != q || pp.pc != pc) {
+        std::vector<int4> items;
+        std::vector<int64_t> pbase(nd);
+        std::vector<int> nsp(nd);
+        int64_t tot = 0;
+        for (int d = 0; d < nd; ++d) {
+            const int E = p->doms[d].E;
+            nsp[d] = (E + kMmvCols - 1) / kMmvCols;
+            pbase[d] = tot;
+            tot += (int64_t)nsp[d] * q * 2 * E;
+        }
+        pp.item0.assign(1, 0);
+        auto span = [&](const int4& it) { return std::min(kMmvCols, p->doms[it.x].E - it.w * kMmvCols); };
+        for (int st = 0; st < nst; ++st) {
+            const size_t first = items.size();
+            for (int d = 0; d < nd; ++d) {
+                if (nst > 1 && p->dom_colour[d] != st) continue;
+                const int E = p->doms[d].E;
+                for (int sp = 0; sp < nsp[d]; ++sp)
+                    for (int r0 = 0; r0 < E; r0 += 64)
+                        for (int c0 = 0; c0 < q; c0 += 16) items.push_back(make_int4(d, r0, c0, sp));
+            }
+            std::stable_sort(items.begin() + first, items.end(),
+                             [&](const int4& a, const int4& b) { return span(a) > span(b); });
+            pp.item0.push_back((int64_t)items.size());
+        }
+        pp.items.upload(items, s);
+        pp.pbase.upload(pbase, s);
+        pp.nsplit.upload(nsp, s);
+        pp.part.alloc((size_t)2 * tot);
+        pp.q = q;
+        pp.pc = pc;
+        sync(p);
+    }
+    for (int st = 0; st < nst; ++st) {
+        const int4* it = pp.items.p + pp.item0[st];
+        const int64_t nit = pp.item0[st + 1] - pp.item0[st];
+        if (nst == 1) {
+            launch_pcmm(p->d_doms.p, it, nit, p->Tinv.p, X, ld, q, pp.pbase.p, kMmvCols, pp.part.p, p->d_dof_dom.p,
+                        nullptr, p->ndof, pp.nsplit.p, Z, ld, s);
+            continue;
+        }
+        const int32_t* dl = p->d_stage_dofs.p + p->stage_dof0[st];
+        const int64_t ndl = p->stage_dof0[st + 1] - p->stage_dof0[st];
+        const double* in = X;
+        if (st > 0) {
+            launch_gs_residual_q(p->d_doms.p, p->d_dof_dom.p, dl, ndl, p->d_dplus.p, p->d_dminus.p, p->d_gval.p,
+                                 p->d_gcol.p, p->d_other_dom.p, p->d_dom_stage.p, st, X, Z, W, ld, q, s);
+            in = W;
+        }
+        launch_pcmm(p->d_doms.p, it, nit, p->Tinv.p, in, ld, q, pp.pbase.p, kMmvCols, pp.part.p, p->d_dof_dom.p, dl, ndl,
+                    pp.nsplit.p, Z, ld, s);
+    }
 }
 
 // Partial sums of the allocation-free product (mtf_matvec_noalloc): a fixed array in device
@@ -1807,9 +1882,16 @@ void herm_eig(int n, std::vector<cd> A, std::vector<double>& w, std::vector<cd>&
                 const double r = std::abs(apq);
                 if (r <= 1e-300) continue;
                 const cd d = std::conj(apq) / r;             // column q *= d makes A(p, q) = r
-                for (int k = 0; k < n; ++k) at(k, q) *= d;
-                for (int k = 0; k < n; ++k) at(q, k) *= std::conj(d);
-                for (int k = 0; k < n; ++k) U[(size_t)q * n + k] *= d;
+                // plain complex products (std::complex's operator* guards against infinities and NaNs
+                // through a library call, too slow for this inner loop; the values here are finite)
+                const double dr = d.real(), di = d.imag();
+                auto mul = [](cd& z, double br, double bi) {
+                    const double zr = z.real(), zi = z.imag();
+                    z = cd(zr * br - zi * bi, zr * bi + zi * br);
+                };
+                for (int k = 0; k < n; ++k) mul(at(k, q), dr, di);
+                for (int k = 0; k < n; ++k) mul(at(q, k), dr, -di);
+                for (int k = 0; k < n; ++k) mul(U[(size_t)q * n + k], dr, di);
                 const double a = at(p, p).real(), b = at(q, q).real();
                 const double tau = (b - a) / (2.0 * r);
                 const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::abs(tau) + std::sqrt(1.0 + tau * tau));
@@ -1959,15 +2041,28 @@ struct BlockLsq {
 };
 
 struct BlockWork {
-    DevBuf<double> V, Z, Wa, Wb, hd, pdot, pupd, R, Y, T, tmp, npart;
+    DevBuf<double> V, Z, Wa, Wb, Wt, hd, pdot, pupd, R, Y, T, tmp, npart;
     DevBuf<int> cnt, info;
-    double* hh = nullptr;           // pinned staging of hd
+    double* hh[2] = {nullptr, nullptr};   // pinned: projections and Gram matrix of a block step (two steps in flight)
+    double* hg = nullptr;                 // pinned: Gram matrix of an orthonormalisation pass
+    double* ht = nullptr;                 // pinned: combination matrix T
+    double* hc = nullptr;                 // pinned: new block column of the Hessenberg matrix (reduced in place)
     ~BlockWork() {
-        if (hh) (void)hipHostFree(hh);
+        for (double* q : {hh[0], hh[1], hg, ht, hc})
+            if (q) (void)hipHostFree(q);
     }
 };
 
-// Block flexible GMRES over groups of pb right-hand sides (FP64 operator and Arnoldi).
+double* pinned(size_t count) {
+    double* q = nullptr;
+    HIPCHK(hipHostMalloc((void**)&q, count * sizeof(double), hipHostMallocDefault));
+    return q;
+}
+
+// Block flexible GMRES over groups of pb right-hand sides (FP64 operator and Arnoldi).  The host's
+// reduction of a block column of the Hessenberg matrix overlaps the next block step on the GPU,
+// which is launched as soon as the new basis block is formed (and discarded when the reduction
+// shows convergence).
 int block_solve(mtf_problem p, int32_t nrhs, const double* Bp, double* Xp, int64_t ld, const mtf_solve_opts& opts,
                 int pb, int pc, mtf_solve_stats* stats, double t_pc) {
     const int64_t n = p->sk.N;
@@ -1994,11 +2089,16 @@ int block_solve(mtf_problem p, int32_t nrhs, const double* Bp, double* Xp, int64
     if (use_pc) bw.Z.alloc((size_t)2 * dmax * n);
     bw.Wa.alloc((size_t)2 * pmax * n);
     bw.Wb.alloc((size_t)2 * pmax * n);
+    if (pc == MTF_PREC_BLOCK_TINV_GS) bw.Wt.alloc((size_t)2 * pmax * n);
     bw.tmp.alloc((size_t)2 * n);
     bw.npart.alloc((size_t)kNblk * pmax);
     const size_t hcount = (size_t)2 * (2 * vcap * ppad + ppad * ppad);   // H1, H2, Gram (complex)
     bw.hd.alloc(hcount);
-    HIPCHK(hipHostMalloc((void**)&bw.hh, hcount * sizeof(double), hipHostMallocDefault));
+    bw.hh[0] = pinned(hcount);
+    bw.hh[1] = pinned(hcount);
+    bw.hg = pinned((size_t)2 * ppad * ppad);
+    bw.ht = pinned((size_t)2 * pmax * pmax);
+    bw.hc = pinned((size_t)2 * vcap * pmax);
     int64_t pd = 0, pu = 0;
     for (int pp = 1; pp <= pmax; ++pp)
         for (int64_t j = 1; j <= vcap; ++j) {
@@ -2030,29 +2130,32 @@ int block_solve(mtf_problem p, int32_t nrhs, const double* Bp, double* Xp, int64
         }
         return out;
     };
-    // Gram matrix of k vectors at W (host, k x k column-major)
-    auto gram = [&](const double* W, int k) {
-        launch_bdot(plan_bdot(n, k, k), W, n, k, W, n, k, n, bw.pdot.p, Gd, ppad, s);
+    auto gram_of = [&](const double* g, int k) {      // host k x k column-major from the [i][c] staging
         std::vector<cd> G((size_t)k * k);
-        HIPCHK(hipMemcpyAsync(bw.hh, Gd, (size_t)2 * k * ppad * sizeof(double), hipMemcpyDeviceToHost, s));
-        sync(p);
         for (int i = 0; i < k; ++i)
-            for (int c = 0; c < k; ++c) G[(size_t)c * k + i] = cd(bw.hh[2 * (i * ppad + c)], bw.hh[2 * (i * ppad + c) + 1]);
+            for (int c = 0; c < k; ++c) G[(size_t)c * k + i] = cd(g[2 * (i * ppad + c)], g[2 * (i * ppad + c) + 1]);
         return G;
     };
-    // dst (k' vectors) = src (k vectors) T for a host k x k' matrix T (column-major)
+    // Gram matrix of k vectors at W (synchronises)
+    auto gram = [&](const double* W, int k) {
+        launch_bdot(plan_bdot(n, k, k), W, n, k, W, n, k, n, bw.pdot.p, Gd, ppad, s);
+        HIPCHK(hipMemcpyAsync(bw.hg, Gd, (size_t)2 * k * ppad * sizeof(double), hipMemcpyDeviceToHost, s));
+        sync(p);
+        return gram_of(bw.hg, k);
+    };
+    // dst (k' vectors) = src (k vectors) T for a host k x k' matrix T (column-major); stream-ordered
+    // (the pinned staging of T is rewritten only after a later synchronisation)
     auto combine = [&](const double* src, int k, const std::vector<cd>& T, int kk, double* dst) {
-        std::vector<double> th((size_t)2 * k * kk);
         for (int c = 0; c < kk; ++c)
             for (int i = 0; i < k; ++i) {
-                th[2 * ((size_t)i * kk + c)] = T[(size_t)c * k + i].real();     // [i][c] layout
-                th[2 * ((size_t)i * kk + c) + 1] = T[(size_t)c * k + i].imag();
+                bw.ht[2 * ((size_t)i * kk + c)] = T[(size_t)c * k + i].real();     // [i][c] layout
+                bw.ht[2 * ((size_t)i * kk + c) + 1] = T[(size_t)c * k + i].imag();
             }
-        HIPCHK(hipMemcpyAsync(bw.T.p, th.data(), th.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(bw.T.p, bw.ht, (size_t)2 * k * kk * sizeof(double), hipMemcpyHostToDevice, s));
         launch_bupd(plan_bupd(n, k, kk), src, n, k, bw.T.p, kk, 1, kk, n, bw.pupd.p, nullptr, n, dst, n, 1.0, 0.0, s);
-        sync(p);   // th leaves scope
     };
-    // W (k vectors) -> orthonormal Q at dst with W ~= Q S; a second pass when the first was ill-conditioned
+    // the k vectors in Wa -> orthonormal Q at dst with Wa ~= Q S; a second pass when the first was
+    // ill-conditioned
     auto orthonormalize = [&](int k, const std::vector<cd>& G, const std::vector<double>& ref2, double* dst,
                               std::vector<cd>& S) {
         Svqb a = svqb(k, G, ref2, kBlockKeep);
@@ -2077,6 +2180,34 @@ int block_solve(mtf_problem p, int32_t nrhs, const double* Bp, double* Xp, int64
                 S[(size_t)c * b2.k + r] = t;
             }
         return b2.k;
+    };
+    // one block step on the GPU: Z_k = P V_k, W = M Z_k, two block Gram-Schmidt passes against the
+    // nrow basis vectors, the Gram matrix of W; projections and Gram matrix copied to hh[buf]
+    auto launch_step = [&](int64_t ncol_, int64_t nrow_, int pk_, int buf) {
+        const double* vk = bw.V.p + 2 * n * (nrow_ - pk_);
+        double* zk = zbase + 2 * n * ncol_;
+        if (use_pc && pk_ >= kMmvMin) precond_block(p, pc, pk_, vk, zk, bw.Wt.p, n);
+        else if (use_pc)
+            for (int c = 0; c < pk_; ++c) {
+                if (pc == MTF_PREC_BLOCK_TINV_GS) precond1_gs(p, vk + 2 * n * c, zk + 2 * n * c, bw.tmp.p);
+                else precond1(p, vk + 2 * n * c, zk + 2 * n * c);
+            }
+        if (pk_ >= kMmvMin) matvec_mmv(p, pk_, zk, n, bw.Wa.p, n);
+        else
+            for (int c = 0; c < pk_; ++c) matvec1(p, zk + 2 * n * c, bw.Wa.p + 2 * n * c, MTF_FP64);
+        const int j = (int)nrow_;
+        const BlockDotPlan pdp = plan_bdot(n, j, pk_);
+        const BlockUpdPlan pup = plan_bupd(n, j, pk_);
+        launch_bdot(pdp, bw.V.p, n, j, bw.Wa.p, n, pk_, n, bw.pdot.p, H1, ppad, s);
+        launch_bupd(pup, bw.V.p, n, j, H1, ppad, 1, pk_, n, bw.pupd.p, bw.Wa.p, n, bw.Wa.p, n, -1.0, 1.0, s);
+        launch_bdot(pdp, bw.V.p, n, j, bw.Wa.p, n, pk_, n, bw.pdot.p, H2, ppad, s);
+        launch_bupd(pup, bw.V.p, n, j, H2, ppad, 1, pk_, n, bw.pupd.p, bw.Wa.p, n, bw.Wa.p, n, -1.0, 1.0, s);
+        launch_bdot(plan_bdot(n, pk_, pk_), bw.Wa.p, n, pk_, bw.Wa.p, n, pk_, n, bw.pdot.p, Gd, ppad, s);
+        const size_t hj = (size_t)2 * j * ppad * sizeof(double);
+        double* hb = bw.hh[buf];
+        HIPCHK(hipMemcpyAsync(hb, H1, hj, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hb + (H2 - H1), H2, hj, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hb + (Gd - H1), Gd, (size_t)2 * ppad * ppad * sizeof(double), hipMemcpyDeviceToHost, s));
     };
 
     int status = MTF_OK;
@@ -2114,9 +2245,9 @@ int block_solve(mtf_problem p, int32_t nrhs, const double* Bp, double* Xp, int64
                 if (!conv[c]) all = false;
             }
             if (all || outer == maxref) break;
-            // V_1 S_0 = R (the residual block)
             for (int c = 0; c < q; ++c)
                 if (conv[c]) launch_fill(bw.Wa.p + 2 * n * c, 2 * n, 0.0, s);
+            // V_1 S_0 = R (the residual block)
             std::vector<cd> S;
             int pk = orthonormalize(q, gram(bw.Wa.p, q), ref2, bw.V.p, S);
             BlockLsq ls;
@@ -2127,40 +2258,15 @@ int block_solve(mtf_problem p, int32_t nrhs, const double* Bp, double* Xp, int64
                     ls.G[2 * ((size_t)c * vcap + r) + 1] = S[(size_t)c * pk + r].imag();
                 }
             int64_t ncol = 0, nrow = pk;     // columns of the Hessenberg matrix reduced; basis vectors
-            int steps = 0;
-            std::vector<double> hc;
-            while (pk > 0 && ncol + pk <= dmax) {
-                const double* vk = bw.V.p + 2 * n * (nrow - pk);
-                double* zk = zbase + 2 * n * ncol;
-                if (use_pc)
-                    for (int c = 0; c < pk; ++c) {
-                        if (pc == MTF_PREC_BLOCK_TINV_GS) precond1_gs(p, vk + 2 * n * c, zk + 2 * n * c, bw.tmp.p);
-                        else precond1(p, vk + 2 * n * c, zk + 2 * n * c);
-                    }
-                if (pk >= kMmvMin) matvec_mmv(p, pk, zk, n, bw.Wa.p, n);
-                else
-                    for (int c = 0; c < pk; ++c) matvec1(p, zk + 2 * n * c, bw.Wa.p + 2 * n * c, MTF_FP64);
-                // two passes of block classical Gram-Schmidt against the nrow basis vectors
+            int steps = 0, buf = 0;
+            if (pk > 0 && pk <= dmax) launch_step(ncol, nrow, pk, buf);
+            else pk = 0;
+            while (pk > 0) {
+                sync(p);                                                  // step data in hh[buf]
                 const int j = (int)nrow;
-                const BlockDotPlan pdp = plan_bdot(n, j, pk);
-                const BlockUpdPlan pup = plan_bupd(n, j, pk);
-                launch_bdot(pdp, bw.V.p, n, j, bw.Wa.p, n, pk, n, bw.pdot.p, H1, ppad, s);
-                launch_bupd(pup, bw.V.p, n, j, H1, ppad, 1, pk, n, bw.pupd.p, bw.Wa.p, n, bw.Wa.p, n, -1.0, 1.0, s);
-                launch_bdot(pdp, bw.V.p, n, j, bw.Wa.p, n, pk, n, bw.pdot.p, H2, ppad, s);
-                launch_bupd(pup, bw.V.p, n, j, H2, ppad, 1, pk, n, bw.pupd.p, bw.Wa.p, n, bw.Wa.p, n, -1.0, 1.0, s);
-                launch_bdot(plan_bdot(n, pk, pk), bw.Wa.p, n, pk, bw.Wa.p, n, pk, n, bw.pdot.p, Gd, ppad, s);
-                const size_t hj = (size_t)2 * j * ppad * sizeof(double);
-                HIPCHK(hipMemcpyAsync(bw.hh, H1, hj, hipMemcpyDeviceToHost, s));
-                HIPCHK(hipMemcpyAsync(bw.hh + (H2 - H1), H2, hj, hipMemcpyDeviceToHost, s));
-                HIPCHK(hipMemcpyAsync(bw.hh + (Gd - H1), Gd, (size_t)2 * ppad * ppad * sizeof(double),
-                                      hipMemcpyDeviceToHost, s));
-                sync(p);
-                const double* h1 = bw.hh;
-                const double* h2 = bw.hh + (size_t)2 * vcap * ppad;
-                const double* gh = bw.hh + (size_t)4 * vcap * ppad;
-                std::vector<cd> G((size_t)pk * pk);
-                for (int i = 0; i < pk; ++i)
-                    for (int c = 0; c < pk; ++c) G[(size_t)c * pk + i] = cd(gh[2 * (i * ppad + c)], gh[2 * (i * ppad + c) + 1]);
+                const double* h1 = bw.hh[buf];
+                const double* h2 = h1 + (size_t)2 * vcap * ppad;
+                const std::vector<cd> G = gram_of(h1 + (size_t)4 * vcap * ppad, pk);
                 std::vector<double> r2(pk);
                 for (int c = 0; c < pk; ++c) {
                     double t = G[(size_t)c * pk + c].real();
@@ -2172,11 +2278,13 @@ int block_solve(mtf_problem p, int32_t nrhs, const double* Bp, double* Xp, int64
                 }
                 std::vector<cd> Sn;
                 const int pnew = orthonormalize(pk, G, r2, bw.V.p + 2 * n * nrow, Sn);
-                // new block column of the Hessenberg matrix: rows 0..j-1 from the projections, then S
                 const int64_t rows = nrow + pnew;
-                hc.assign((size_t)2 * rows * pk, 0.0);
+                const bool more = pnew > 0 && ncol + pk + pnew <= dmax;
+                if (more) launch_step(ncol + pk, rows, pnew, buf ^ 1);   // overlaps the reduction below
+                // new block column: rows 0..j-1 from the projections, then S
+                double* hc = bw.hc;
                 for (int c = 0; c < pk; ++c) {
-                    double* y = hc.data() + (size_t)2 * rows * c;
+                    double* y = hc + (size_t)2 * rows * c;
                     for (int i = 0; i < j; ++i) {
                         const size_t e = 2 * ((size_t)i * ppad + c);
                         y[2 * i] = h1[e] + h2[e];
@@ -2189,18 +2297,20 @@ int block_solve(mtf_problem p, int32_t nrhs, const double* Bp, double* Xp, int64
                 }
                 // earlier reflectors on the new columns (independent columns: host threads)
                 host_parallel(pk, ncol * pk > 8192, [&](int c) {
-                    double* y = hc.data() + (size_t)2 * rows * c;
+                    double* y = hc + (size_t)2 * rows * c;
                     for (int64_t m = 0; m < ncol; ++m) ls.apply((int)m, y);
                 });
                 for (int c = 0; c < pk; ++c) {
                     const int64_t col = ncol + c;
-                    double* y = hc.data() + (size_t)2 * rows * c;
+                    double* y = hc + (size_t)2 * rows * c;
                     ls.make((int)col, (int)(rows - col), y);
-                    for (int c2 = c + 1; c2 < pk; ++c2) ls.apply((int)col, hc.data() + (size_t)2 * rows * c2);
+                    for (int c2 = c + 1; c2 < pk; ++c2) ls.apply((int)col, hc + (size_t)2 * rows * c2);
                     for (int r = 0; r < q; ++r) ls.apply((int)col, ls.G.data() + (size_t)2 * vcap * r);
-                    HIPCHK(hipMemcpyAsync(bw.R.p + (size_t)2 * col * dmax, y, (size_t)2 * (col + 1) * sizeof(double),
-                                          hipMemcpyHostToDevice, s));
                 }
+                // R columns ncol .. ncol + pk - 1 (rows 0 .. ncol + pk - 1; zero below the diagonal)
+                HIPCHK(hipMemcpy2DAsync(bw.R.p + (size_t)2 * ncol * dmax, (size_t)2 * dmax * sizeof(double), hc,
+                                        (size_t)2 * rows * sizeof(double), (size_t)2 * (ncol + pk) * sizeof(double), pk,
+                                        hipMemcpyHostToDevice, s));
                 ncol += pk;
                 nrow = rows;
                 pk = pnew;
@@ -2215,12 +2325,13 @@ int block_solve(mtf_problem p, int32_t nrhs, const double* Bp, double* Xp, int64
                     }
                     if (std::sqrt(t) > tol[c]) done = false;
                 }
-                sync(p);   // the R columns were copied from hc
-                if (done) break;
+                if (done || !more) break;
+                buf ^= 1;
             }
             steps_total += steps;
             if (ncol == 0) break;
-            // X += Z Y, Y = R^-1 G(0:ncol, :)
+            // X += Z Y, Y = R^-1 G(0:ncol, :)   (after a step launched past convergence, which
+            // touches neither Z(0:ncol) nor R)
             std::vector<double> yh((size_t)2 * dmax * q, 0.0);
             for (int c = 0; c < q; ++c)
                 std::memcpy(yh.data() + (size_t)2 * dmax * c, ls.G.data() + (size_t)2 * vcap * c,
@@ -2858,11 +2969,23 @@ int mtf_apply_preconditioner(mtf_problem p, int32_t preconditioner, int32_t nrhs
         if (!p->has_mesh || !p->has_mat) throw StateError("mtf_apply_preconditioner before mesh/materials");
         if (nrhs < 1 || !x_dev || !z_dev || ld < p->sk.N) throw ArgError("bad arguments");
         if (x_dev == z_dev) throw ArgError("x and z must not alias");
+        const bool multi = (preconditioner & MTF_PREC_MULTI) != 0;
+        preconditioner &= ~MTF_PREC_MULTI;
         if (preconditioner != MTF_PREC_BLOCK_TINV && preconditioner != MTF_PREC_BLOCK_TINV_GS)
             throw ArgError("preconditioner must be MTF_PREC_BLOCK_TINV or MTF_PREC_BLOCK_TINV_GS");
+        if (multi && nrhs > kMaxBlock) throw ArgError("MTF_PREC_MULTI takes at most 32 vectors");
         if (!p->have64 && !p->have32) throw StateError("mtf_apply_preconditioner before mtf_assemble");
         DeviceGuard g(p->device);
         if (!p->have_tinv) build_tinv(p, false);
+        if (multi) {
+            DevBuf<double> w;
+            if (preconditioner == MTF_PREC_BLOCK_TINV_GS) w.alloc((size_t)2 * ld * nrhs);
+            precond_block(p, preconditioner, nrhs, static_cast<const double*>(x_dev), static_cast<double*>(z_dev), w.p,
+                          ld);
+            HIPCHK(hipGetLastError());
+            sync(p);                                                 // w is released on return
+            return MTF_OK;
+        }
         DevBuf<double> w;
         if (preconditioner == MTF_PREC_BLOCK_TINV_GS) w.alloc(2 * p->sk.N);
         for (int r = 0; r < nrhs; ++r) {

@@ -309,4 +309,15 @@ void launch_mmv(const DomDesc* doms, const int4* items, int64_t nitems, const do
                 int64_t ldx, int q, const int64_t* pbase, int kc, double* part, const int32_t* dof_dom, int64_t ndof,
                 const int32_t* dplus, const int32_t* dminus, const double* gval, const int64_t* gcol,
                 const int* nsplit, double* y, int64_t ldy, hipStream_t s);
+// z = P x for q vectors on the dofs of one Gauss-Seidel stage (list: its dofs, or null for all nlist
+// dofs), P_i from the whole complex64 blocks S (FP64 arithmetic on the matrix cores); work items
+// and partial sums as for launch_mmv
+void launch_pcmm(const DomDesc* doms, const int4* items, int64_t nitems, const float* S, const double* x, int64_t ldx,
+                 int q, const int64_t* pbase, int kc, double* part, const int32_t* dof_dom, const int32_t* list,
+                 int64_t nlist, const int* nsplit, double* z, int64_t ldz, hipStream_t s);
+// w = v - (transmission from earlier stages) z for q vectors (ld), on the listed dofs of stage `stage`
+void launch_gs_residual_q(const DomDesc* doms, const int32_t* dof_dom, const int32_t* list, int64_t nlist,
+                          const int32_t* dplus, const int32_t* dminus, const double* gval, const int64_t* gcol,
+                          const int32_t* other_dom, const int32_t* dom_stage, int stage, const double* v,
+                          const double* z, double* w, int64_t ld, int q, hipStream_t s);
 }  // namespace mtf
