@@ -88,11 +88,12 @@ extern "C" {
  * one Krylov space (block flexible GMRES: Vital 1990; Gutknecht 2006): a block step applies the
  * preconditioner and the FP64 product to the p vectors of the newest basis block, orthogonalises
  * them against the whole basis by two passes of block classical Gram-Schmidt on the FP64 matrix
- * cores (one read of the basis per pass for all p vectors), and orthonormalises the block through
- * the eigen-decomposition of its Gram matrix with the columns scaled to unit norm (SVQB,
- * Stathopoulos and Wu 2002; a second pass when the block is ill-conditioned), dropping directions
- * whose scaled eigenvalue is at most 1e-24, so that the block narrows when the right-hand sides
- * become dependent.  The block least-squares problem is reduced by Householder reflections on the
+ * cores (one read of the basis per pass for all p vectors), and orthonormalises the block from
+ * its Gram matrix with the columns scaled to unit norm (Cholesky QR, with diagonal pivoting so
+ * that it reveals the rank; a second pass when the block is ill-conditioned), dropping directions
+ * whose pivot is at most 1e-15 (noise of the Gram matrix), so that the block narrows when the
+ * right-hand sides become dependent.  The products use MTF_FP64_MFMA and the preconditioner
+ * MTF_PREC_MULTI for blocks of 3 or more vectors.  The block least-squares problem is reduced by Householder reflections on the
  * host; a group stops when every one of its residuals meets the target, restarts from the
  * corrected solution when the basis is full (opts.max_iters basis vectors, 0: from free device
  * memory, at most 24,000), and is checked with the FP64 residual as in the single-vector

@@ -35,9 +35,11 @@ constexpr double kPcSymTol = 1e-3;   // largest ||T_i S_i^-1 v - v|| / ||v|| of 
 constexpr int kSync = 8;      // Arnoldi steps between host reads of the Hessenberg columns
 constexpr int kMaxBatch = 64; // right-hand sides per lockstep GMRES batch (MFMA products)
 constexpr int kMaxBlock = 32; // right-hand sides per block of block GMRES
-// smallest kept eigenvalue of a block's scaled Gram matrix (singular value 1e-12 of a unit column):
-// a direction dropped below it leaves an error of that size in the Arnoldi relation
-constexpr double kBlockKeep = 1e-24;
+// smallest kept pivot of the pivoted Cholesky factorisation of a block's scaled Gram matrix: the
+// squared norm of what a unit column adds to the span of those kept before it.  Forming the Gram
+// matrix rounds at 1e-16 relative, so smaller pivots are noise; a direction dropped below it leaves
+// an error of at most 3e-8 of its column in the Arnoldi relation.
+constexpr double kBlockKeep = 1e-15;
 // blocks of at least this many vectors use the FP64 multi-RHS product (whole blocks, read once for
 // the block); narrower ones the symmetric-read product per vector
 constexpr int kMmvMin = 3;
@@ -762,8 +764,8 @@ void matvec_mmv(mtf_problem p, int q, const double* X, int64_t ldx, double* Y, i
             nsp.push_back(ns);
             tot += (int64_t)ns * q * 2 * E;
             for (int sp = 0; sp < ns; ++sp)
-                for (int r0 = 0; r0 < E; r0 += 64)
-                    for (int c0 = 0; c0 < q; c0 += 16) items.push_back(make_int4((int)d, r0, c0, sp));
+                for (int r0 = 0; r0 < E; r0 += mmv_rows(q))
+                    for (int c0 = 0; c0 < q; c0 += mmv_rhs_step(q)) items.push_back(make_int4((int)d, r0, c0, sp));
         }
         auto span = [&](const int4& it) { return std::min(kMmvCols, p->doms[it.x].E - it.w * kMmvCols); };
         std::stable_sort(items.begin(), items.end(), [&](const int4& a, const int4& b) { return span(a) > span(b); });
@@ -806,8 +808,8 @@ void precond_block(mtf_problem p, int pc, int q, const double* X, double* Z, dou
                 if (nst > 1 && p->dom_colour[d] != st) continue;
                 const int E = p->doms[d].E;
                 for (int sp = 0; sp < nsp[d]; ++sp)
-                    for (int r0 = 0; r0 < E; r0 += 64)
-                        for (int c0 = 0; c0 < q; c0 += 16) items.push_back(make_int4(d, r0, c0, sp));
+                    for (int r0 = 0; r0 < E; r0 += mmv_rows(q))
+                        for (int c0 = 0; c0 < q; c0 += mmv_rhs_step(q)) items.push_back(make_int4(d, r0, c0, sp));
             }
             std::stable_sort(items.begin() + first, items.end(),
                              [&](const int4& a, const int4& b) { return span(a) > span(b); });
@@ -1861,66 +1863,12 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
 // block Gram-Schmidt contractions of block.hip, a rank-revealing orthonormalisation of each new
 // block, and the block least-squares problem reduced by Householder reflections on the host).
 
-// A = U diag(w) U^H for a Hermitian n x n matrix A (column-major), by cyclic Jacobi rotations:
-// each (p, q) entry is first made real by a phase on column/row q, then zeroed by a real rotation.
-void herm_eig(int n, std::vector<cd> A, std::vector<double>& w, std::vector<cd>& U) {
-    U.assign((size_t)n * n, cd(0.0, 0.0));
-    for (int i = 0; i < n; ++i) U[(size_t)i * n + i] = 1.0;
-    auto at = [&](int r, int c) -> cd& { return A[(size_t)c * n + r]; };
-    for (int sweep = 0; sweep < 64; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int c = 0; c < n; ++c)
-            for (int r = 0; r < n; ++r) {
-                const double v = std::norm(at(r, c));
-                tot += v;
-                if (r != c) off += v;
-            }
-        if (off <= 1e-32 * tot) break;
-        for (int p = 0; p < n - 1; ++p)
-            for (int q = p + 1; q < n; ++q) {
-                const cd apq = at(p, q);
-                const double r = std::abs(apq);
-                if (r <= 1e-300) continue;
-                const cd d = std::conj(apq) / r;             // column q *= d makes A(p, q) = r
-                // plain complex products (std::complex's operator* guards against infinities and NaNs
-                // through a library call, too slow for this inner loop; the values here are finite)
-                const double dr = d.real(), di = d.imag();
-                auto mul = [](cd& z, double br, double bi) {
-                    const double zr = z.real(), zi = z.imag();
-                    z = cd(zr * br - zi * bi, zr * bi + zi * br);
-                };
-                for (int k = 0; k < n; ++k) mul(at(k, q), dr, di);
-                for (int k = 0; k < n; ++k) mul(at(q, k), dr, -di);
-                for (int k = 0; k < n; ++k) mul(U[(size_t)q * n + k], dr, di);
-                const double a = at(p, p).real(), b = at(q, q).real();
-                const double tau = (b - a) / (2.0 * r);
-                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::abs(tau) + std::sqrt(1.0 + tau * tau));
-                const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
-                for (int k = 0; k < n; ++k) {                // columns p, q of A J
-                    const cd x = at(k, p), y = at(k, q);
-                    at(k, p) = c * x - s * y;
-                    at(k, q) = s * x + c * y;
-                }
-                for (int k = 0; k < n; ++k) {                // rows p, q of J^T (A J)
-                    const cd x = at(p, k), y = at(q, k);
-                    at(p, k) = c * x - s * y;
-                    at(q, k) = s * x + c * y;
-                }
-                for (int k = 0; k < n; ++k) {
-                    const cd x = U[(size_t)p * n + k], y = U[(size_t)q * n + k];
-                    U[(size_t)p * n + k] = c * x - s * y;
-                    U[(size_t)q * n + k] = s * x + c * y;
-                }
-            }
-    }
-    w.resize(n);
-    for (int i = 0; i < n; ++i) w[i] = at(i, i).real();
-}
-
 // Orthonormal basis of the span of n vectors W from their Gram matrix G = W^H W (column-major):
-// Q = W T (n x k) and W ~= Q S (k x n), with the columns scaled to unit norm first and directions
-// whose scaled eigenvalue is at most `keep` dropped (rank revealing); a column whose squared norm
-// is at most 1e-26 ref2[c] counts as zero.  lmin: the smallest kept eigenvalue.
+// Q = W T (n x k) and W ~= Q S (k x n).  The columns are scaled to unit norm, then the scaled Gram
+// matrix is factored by Cholesky with diagonal pivoting (the largest remaining pivot first, as in
+// LAPACK's pstrf), which stops once that pivot is at most `keep`: the factorisation reveals the
+// rank, and the columns left over are expressed in the kept ones (their rows of S).  A column
+// whose squared norm is at most 1e-26 ref2[c] counts as zero.  lmin: the smallest kept pivot.
 struct Svqb {
     int k = 0;
     std::vector<cd> T, S;   // T: n x k, S: k x n, column-major
@@ -1932,29 +1880,63 @@ Svqb svqb(int n, const std::vector<cd>& G, const std::vector<double>& ref2, doub
         const double g = G[(size_t)c * n + c].real();
         if (g > 0.0 && g > 1e-26 * ref2[c]) D[c] = 1.0 / std::sqrt(g);
     }
-    std::vector<cd> Gs((size_t)n * n);
-    for (int c = 0; c < n; ++c)
-        for (int r = 0; r < n; ++r) Gs[(size_t)c * n + r] = D[r] * G[(size_t)c * n + r] * D[c];
-    std::vector<double> w;
-    std::vector<cd> U;
-    herm_eig(n, Gs, w, U);
-    std::vector<int> idx;
-    for (int i = 0; i < n; ++i)
-        if (w[i] > keep) idx.push_back(i);
-    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return w[a] > w[b]; });
-    Svqb o;
-    o.k = (int)idx.size();
-    o.T.assign((size_t)n * o.k, cd(0.0, 0.0));
-    o.S.assign((size_t)o.k * n, cd(0.0, 0.0));
-    for (int kk = 0; kk < o.k; ++kk) {
-        const int e = idx[kk];
-        const double sw = std::sqrt(w[e]);
-        o.lmin = std::min(o.lmin, w[e]);
-        for (int c = 0; c < n; ++c) {
-            const cd u = U[(size_t)e * n + c];
-            o.T[(size_t)kk * n + c] = D[c] * u / sw;
-            o.S[(size_t)c * o.k + kk] = D[c] > 0.0 ? sw * std::conj(u) / D[c] : cd(0.0, 0.0);
+    // A: scaled Gram matrix (row-major, Hermitian), updated in place to its Schur complements
+    std::vector<cd> A((size_t)n * n);
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) A[(size_t)r * n + c] = D[r] * G[(size_t)c * n + r] * D[c];
+    std::vector<cd> R((size_t)n * n, cd(0.0, 0.0));      // row-major, rows 0..k-1
+    std::vector<int> perm(n);
+    for (int i = 0; i < n; ++i) perm[i] = i;
+    auto at = [&](int r, int c) -> cd& { return A[(size_t)r * n + c]; };
+    int k = 0;
+    double lmin = 1.0;
+    for (; k < n; ++k) {
+        int j = k;
+        for (int i = k + 1; i < n; ++i)
+            if (at(i, i).real() > at(j, j).real()) j = i;
+        const double piv = at(j, j).real();
+        if (!(piv > keep)) break;
+        if (j != k) {                                     // symmetric swap of k and j
+            for (int c = 0; c < n; ++c) std::swap(at(k, c), at(j, c));
+            for (int r = 0; r < n; ++r) std::swap(at(r, k), at(r, j));
+            for (int m = 0; m < k; ++m) std::swap(R[(size_t)m * n + k], R[(size_t)m * n + j]);
+            std::swap(perm[k], perm[j]);
         }
+        const double rkk = std::sqrt(piv);
+        lmin = std::min(lmin, piv);
+        R[(size_t)k * n + k] = rkk;
+        for (int c = k + 1; c < n; ++c) R[(size_t)k * n + c] = at(k, c) / rkk;
+        for (int r = k + 1; r < n; ++r) {
+            const cd a = std::conj(R[(size_t)k * n + r]);
+            const double ar = a.real(), ai = a.imag();
+            for (int c = k + 1; c < n; ++c) {               // A(r, c) -= conj(R(k, r)) R(k, c)
+                const cd b = R[(size_t)k * n + c];
+                at(r, c) -= cd(ar * b.real() - ai * b.imag(), ar * b.imag() + ai * b.real());
+            }
+        }
+    }
+    Svqb o;
+    o.k = k;
+    o.lmin = k > 0 ? lmin : 0.0;
+    // inverse of the leading k x k triangle R11 (upper triangular, column by column)
+    std::vector<cd> Ri((size_t)k * k, cd(0.0, 0.0));   // row-major
+    for (int c = 0; c < k; ++c) {
+        Ri[(size_t)c * k + c] = 1.0 / R[(size_t)c * n + c];
+        for (int r = c - 1; r >= 0; --r) {
+            cd t = 0.0;
+            for (int m = r + 1; m <= c; ++m) t += R[(size_t)r * n + m] * Ri[(size_t)m * k + c];
+            Ri[(size_t)r * k + c] = -t / R[(size_t)r * n + r];
+        }
+    }
+    // T = D P(:, 0:k) R11^-1;  S = [R11 R12] P^T D^-1
+    o.T.assign((size_t)n * k, cd(0.0, 0.0));
+    o.S.assign((size_t)k * n, cd(0.0, 0.0));
+    for (int kk = 0; kk < k; ++kk)
+        for (int m = 0; m <= kk; ++m) o.T[(size_t)kk * n + perm[m]] = D[perm[m]] * Ri[(size_t)m * k + kk];
+    for (int m = 0; m < n; ++m) {
+        const int c = perm[m];
+        if (!(D[c] > 0.0)) continue;
+        for (int r = 0; r < k && r <= m; ++r) o.S[(size_t)c * k + r] = R[(size_t)r * n + m] / D[c];
     }
     return o;
 }
@@ -1991,10 +1973,10 @@ struct BlockLsq {
         w2 = 2 * pmax;
         q = nq;
         gld = rows;
-        refl.assign((size_t)2 * cap_cols * w2, 0.0);
-        len.assign(cap_cols, 0);
-        tau.assign(cap_cols, 0.0);
-        G.assign((size_t)2 * rows * nq, 0.0);
+        refl.resize((size_t)2 * cap_cols * w2);
+        len.resize(cap_cols);
+        tau.resize(cap_cols);
+        G.assign((size_t)2 * rows * nq, 0.0);     // reflectors are written before they are read
     }
     // y (complex, row 0 at y) <- H_m y
     void apply(int m, double* y) const {
@@ -2211,6 +2193,7 @@ int block_solve(mtf_problem p, int32_t nrhs, const double* Bp, double* Xp, int64
     };
 
     int status = MTF_OK;
+    BlockLsq ls;
     for (int g0 = 0; g0 < nrhs; g0 += pb) {
         const int q = std::min(pb, nrhs - g0);
         auto t0 = std::chrono::steady_clock::now();
@@ -2250,7 +2233,6 @@ int block_solve(mtf_problem p, int32_t nrhs, const double* Bp, double* Xp, int64
             // V_1 S_0 = R (the residual block)
             std::vector<cd> S;
             int pk = orthonormalize(q, gram(bw.Wa.p, q), ref2, bw.V.p, S);
-            BlockLsq ls;
             ls.init((int)dmax, vcap, pmax, q);
             for (int c = 0; c < q; ++c)
                 for (int r = 0; r < pk; ++r) {

@@ -302,9 +302,11 @@ void launch_bupd(const BlockUpdPlan& pl, const double* V, int64_t ldv, int j, co
                  int64_t hs_c, int p, int64_t n, double* part, const double* Yin, int64_t ldyin, double* Y,
                  int64_t ldy, double alpha, double beta, hipStream_t s);
 // y_j = M x_j for q vectors (complex128, ld ldx / ldy, q <= 32) from the whole FP64 blocks on the
-// matrix cores: work items (dom, row0, rhs0, split) of 64 rows x 16 right-hand sides x kc columns
-// (kc a multiple of 16), partial sums of split s of subdomain d at part + pbase[d] (complex,
-// nsplit[d] q 2 E_d of them), then the transmission terms.
+// matrix cores: work items (dom, row0, rhs0, split) of mmv_rows(q) rows x mmv_rhs_step(q)
+// right-hand sides x kc columns (kc a multiple of 16), partial sums of split s of subdomain d at
+// part + pbase[d] (complex, nsplit[d] q 2 E_d of them), then the transmission terms.
+inline int mmv_rows(int) { return 64; }
+inline int mmv_rhs_step(int) { return 16; }
 void launch_mmv(const DomDesc* doms, const int4* items, int64_t nitems, const double* T, const double* K, const double* x,
                 int64_t ldx, int q, const int64_t* pbase, int kc, double* part, const int32_t* dof_dom, int64_t ndof,
                 const int32_t* dplus, const int32_t* dminus, const double* gval, const int64_t* gcol,
