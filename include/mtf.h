@@ -393,17 +393,23 @@ int mtf_batch_assembly_stats(mtf_batch b, int64_t* counts, double* seconds, int3
 int mtf_batch_build_preconditioner(mtf_batch b, int32_t flags);
 
 /* mtf_solve of problem i on b_dev[i] -> x_dev[i] (one right-hand side each, ld = N_i) with
- * common options, problem after problem; stats[n] may be NULL.  The preconditioner blocks of the
- * problems lacking them are first built together (mtf_batch_build_preconditioner); stats[0]
- * receives that build's time in t_precond_s.  A problem without FP64 blocks gets them assembled
- * (default options) for its residual checks and released after its solve.  Preconditioner blocks
- * that a problem did not hold before the call are released after its solve (also when the call
- * fails).  A problem without GMRES work buffers of its own uses the batch's, allocated for the
- * largest problem met and kept until mtf_batch_destroy.  Device memory needed beyond the assembled
- * blocks: the preconditioner blocks of every problem (half the bytes of the complex64 T_i, K_i),
- * one problem's FP64 blocks at a time and the batch's GMRES buffers.  max_iters 0 here means cycles
- * of at most 1,000 Arnoldi steps (not the free-memory length of mtf_solve): a batch is many small
- * solves, whose Krylov storage would otherwise be sized from free memory. */
+ * common options; stats[n] may be NULL.  The preconditioner blocks of the problems lacking them are
+ * first built together (mtf_batch_build_preconditioner); stats[0] receives that build's time in
+ * t_precond_s.  The problems are then solved on up to 4 streams at once (the environment variable
+ * MTF_BATCH_LANES sets 1-8; 1 solves problem after problem on the problems' own streams), each
+ * stream a host thread taking the next problem, largest first; with more than one, the call starts
+ * with a device synchronisation and ends when every solve is complete.  A problem without FP64
+ * blocks gets them assembled (default options) for its residual checks and released after its
+ * solve; with opts.precision MTF_FP32_MIXED a problem without complex64 blocks gets them rounded
+ * from its FP64 blocks (MTF_ASSEMBLE_ROUND_FP64) for its solve only.  Preconditioner blocks that a
+ * problem did not hold before the call are released after its solve (also when the call fails).
+ * A problem without GMRES work buffers of its own uses one of the batch's (one per stream,
+ * allocated for the largest problem that stream met and kept until mtf_batch_destroy).  Device
+ * memory needed beyond the assembled blocks: the preconditioner blocks of every problem (half the
+ * bytes of the complex64 T_i, K_i), per stream one problem's temporary blocks and GMRES buffers.
+ * max_iters 0 here means cycles of at most 1,000 Arnoldi steps (not the free-memory length of
+ * mtf_solve): a batch is many small solves, whose Krylov storage would otherwise be sized from free
+ * memory. */
 int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, const mtf_solve_opts* opts,
                     mtf_solve_stats* stats);
 

@@ -4,12 +4,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <complex>
 #include <cstring>
+#include <exception>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -3074,7 +3076,9 @@ struct mtf_batch_s {
     int64_t nitems = 0, nsample = 0;
     int items_variant = -1;           // tile variant of d_items
     int last_variant = 0, last_grid = 0;
-    GmresWork gw;                     // GMRES workspace lent to each problem's solve in turn
+    static constexpr int kLanes = 8;
+    GmresWork gw[kLanes];             // GMRES workspaces, each lent to the solves of one lane in turn
+    hipStream_t lane[kLanes] = {};    // solve lanes (default priority, non-blocking), created on first use
     hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
     double last_tiles_s = 0.0;        // device time of the last persistent launch alone
     double last_total_s = 0.0;        // and of the whole last assembly (touching pairs included)
@@ -3082,6 +3086,8 @@ struct mtf_batch_s {
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
         if (e2) (void)hipEventDestroy(e2);
+        for (hipStream_t& l : lane)
+            if (l) (void)hipStreamDestroy(l);
     }
 };
 
@@ -3350,11 +3356,12 @@ int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, c
         }
         struct Release {
             mtf_problem p;
-            bool tmp64 = false, tmpinv = false, tmpwork = false;
+            bool tmp64 = false, tmpinv = false, tmpwork = false, tmp32 = false;
             ~Release() {
                 if (!p) return;
                 (void)hipStreamSynchronize(p->stream);
                 if (tmp64) { p->T64.reset(); p->K64.reset(); p->near64.reset(); p->have64 = false; }
+                if (tmp32) { p->T32.reset(); p->K32.reset(); p->near32.reset(); p->have32 = false; p->gm.haveA = false; }
                 if (tmpinv) { p->Tinv.reset(); p->have_tinv = false; p->gp.haveA = false; }
                 if (tmpwork) p->gw.release();
             }
@@ -3378,24 +3385,27 @@ int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, c
                 }
             }
         }
-        // problems not reached when a solve fails: release the preconditioner blocks built above
-        size_t next = 0;
-        struct Rest {
-            const std::vector<mtf_problem>& ps;
-            const std::vector<char>& tmp;
-            size_t& next;
-            ~Rest() {
-                for (size_t j = next; j < ps.size(); ++j)
-                    if (tmp[j]) { ps[j]->Tinv.reset(); ps[j]->have_tinv = false; ps[j]->gp.haveA = false; }
-            }
-        } rest{b->probs, tmpinv, next};
+        // The problems are solved on `lanes` streams at once, each lane a host thread taking the next
+        // problem (largest first) with a workspace of its own: the GMRES steps of small problems are
+        // latency-bound, and independent problems overlap.  MTF_BATCH_LANES sets the count (1-8,
+        // default 4; 1 solves one after another on the problems' own streams).
+        int lanes = 4;
+        if (const char* e = std::getenv("MTF_BATCH_LANES")) lanes = std::atoi(e);
+        lanes = std::max(1, std::min<int>(lanes, std::min<size_t>(mtf_batch_s::kLanes, np)));
+        std::vector<size_t> order(np);
+        for (size_t i = 0; i < np; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return b->probs[x]->sk.N > b->probs[y]->sk.N; });
+        std::vector<char> done(np, 0);
+        std::atomic<size_t> counter{0};
+        std::atomic<bool> abort{false};
+        std::mutex mu;
+        std::exception_ptr err;
         int status = MTF_OK;
-        for (size_t i = 0; i < np; ++i) {
+        auto solve_one = [&](size_t i, GmresWork& lw) {
             mtf_problem p = b->probs[i];
-            next = i + 1;
             Release rel{p, !p->have64, (bool)tmpinv[i], false};
-            // a problem without a workspace of its own borrows the batch's (allocated once, for the
-            // largest problem met so far), so the Krylov buffers are not allocated per problem
+            // a problem without a workspace of its own borrows the lane's (allocated once, for the
+            // largest problem the lane met), so the Krylov buffers are not allocated per problem
             struct Lend {
                 GmresWork& a;
                 GmresWork& b;
@@ -3403,8 +3413,8 @@ int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, c
                 ~Lend() {
                     if (on) swap_work(a, b);
                 }
-            } lend{p->gw, b->gw, (bool)tmpwork[i]};
-            if (lend.on) swap_work(p->gw, b->gw);
+            } lend{p->gw, lw, (bool)tmpwork[i]};
+            if (lend.on) swap_work(p->gw, lw);
             if (rel.tmp64) {
                 mtf_assembly_opts ao{};
                 ao.struct_size = sizeof(ao);
@@ -3413,9 +3423,75 @@ int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, c
                 ao.flags = MTF_ASSEMBLE_TILE(b->last_variant);   // the batch's tuned tiles, no new trials
                 assemble_impl(p, &ao);       // the preconditioner stays: it was built from the FP32 blocks
             }
+            if (o.precision == MTF_FP32_MIXED && !p->have32) {
+                // complex64 blocks rounded from the FP64 ones for this solve only (no second quadrature)
+                mtf_assembly_opts ao{};
+                ao.struct_size = sizeof(ao);
+                ao.precision = MTF_FP32_MIXED;
+                ao.singular_order = 4;
+                ao.flags = MTF_ASSEMBLE_ROUND_FP64;
+                rel.tmp32 = true;
+                assemble_impl(p, &ao);       // the preconditioner stays: it was built from the FP64 blocks
+            }
             const int r = solve_impl(p, 1, b_dev[i], x_dev[i], p->sk.N, &o, stats ? stats + i : nullptr);
-            if (r != MTF_OK) status = r;
             if (stats) stats[i].t_precond_s = i == 0 ? t_pc : 0.0;
+            return r;
+        };
+        if (lanes == 1) {
+            for (size_t k = 0; k < np; ++k) {
+                const size_t i = order[k];
+                try {
+                    const int r = solve_one(i, b->gw[0]);
+                    if (r != MTF_OK) status = r;
+                    done[i] = 1;
+                } catch (...) {
+                    for (size_t j = 0; j < np; ++j)
+                        if (!done[j] && j != i && tmpinv[j]) { b->probs[j]->Tinv.reset(); b->probs[j]->have_tinv = false; b->probs[j]->gp.haveA = false; }
+                    throw;
+                }
+            }
+            return status;
+        }
+        for (int l = 0; l < lanes; ++l)
+            if (!b->lane[l]) HIPCHK(hipStreamCreateWithFlags(&b->lane[l], hipStreamNonBlocking));
+        HIPCHK(hipDeviceSynchronize());          // inputs and preconditioner blocks complete
+        auto lane_fn = [&](int l) {
+            try {
+                DeviceGuard dg(b->device);
+                for (;;) {
+                    if (abort.load()) return;
+                    const size_t k = counter.fetch_add(1);
+                    if (k >= np) return;
+                    const size_t i = order[k];
+                    mtf_problem p = b->probs[i];
+                    struct OnLane {
+                        mtf_problem p;
+                        hipStream_t own;
+                        ~OnLane() {
+                            (void)hipStreamSynchronize(p->stream);
+                            p->stream = own;
+                        }
+                    } on{p, p->stream};
+                    p->stream = b->lane[l];
+                    const int r = solve_one(i, b->gw[l]);
+                    std::lock_guard<std::mutex> lk(mu);
+                    if (r != MTF_OK) status = r;
+                    done[i] = 1;
+                }
+            } catch (...) {
+                std::lock_guard<std::mutex> lk(mu);
+                if (!err) err = std::current_exception();
+                abort = true;
+            }
+        };
+        std::vector<std::thread> th;
+        for (int l = 0; l < lanes; ++l) th.emplace_back(lane_fn, l);
+        for (std::thread& t : th) t.join();
+        if (err) {
+            // problems not solved: release the preconditioner blocks built above
+            for (size_t j = 0; j < np; ++j)
+                if (!done[j] && tmpinv[j]) { b->probs[j]->Tinv.reset(); b->probs[j]->have_tinv = false; b->probs[j]->gp.haveA = false; }
+            std::rethrow_exception(err);
         }
         return status;
     });

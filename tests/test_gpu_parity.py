@@ -317,11 +317,18 @@ def test_batch_persistent_assembly_matches_single(prec, sphere, ragged):
     B.close()
 
 
-def test_batch_solve(sphere):
+@pytest.mark.parametrize("lanes", ["1", "3"])
+@pytest.mark.parametrize("prec", [mtf.FP64, mtf.FP32_MIXED])
+def test_batch_solve(sphere, cube, lanes, prec, monkeypatch):
+    """Three problems of different sizes solved by mtf_batch_solve one after another (one lane) or
+    on three streams at once, in FP64 or on the mixed path with complex64 blocks rounded from the
+    FP64 ones for each solve (relaxed complex64 products, FP64 refinement): every solution equals
+    the oracle's LU solution (1e-7 at rtol 1e-10 in FP64, 1e-6 at rtol 1e-9 mixed)."""
+    monkeypatch.setenv("MTF_BATCH_LANES", lanes)
     cl = _cluster_cfg()
     probs, bs, xs, refs = [], [], [], []
     from oracle import system as osy
-    for cfg in (sphere.cfg, cl):
+    for cfg in (sphere.cfg, cl, cube.cfg):
         m = cfg["mesh"]
         P = mtf.Problem(0)
         P.set_mesh(m.xyz, m.tri, m.label, m.M)
@@ -331,15 +338,24 @@ def test_batch_solve(sphere):
         P.rhs_plane_waves(cfg["d"], cfg["p"], b)
         bs.append(b)
         xs.append(torch.zeros_like(b))
-        pb = osy.Problem.from_config(cfg)
-        T, K, G = osy.assemble_blocks(pb)
-        refs.append(osy.solve_direct(osy.dense_matrix(pb, T, K, G), osy.rhs(pb, cfg["d"], cfg["p"])[:, 0]))
+        if cfg is sphere.cfg:
+            refs.append(sphere.x)
+        elif cfg is cube.cfg:
+            refs.append(cube.x)
+        else:
+            pb = osy.Problem.from_config(cfg)
+            T, K, G = osy.assemble_blocks(pb)
+            refs.append(osy.solve_direct(osy.dense_matrix(pb, T, K, G), osy.rhs(pb, cfg["d"], cfg["p"])[:, 0]))
     B = mtf.Batch(probs)
     B.assemble(mtf.FP64)
-    st = B.solve(bs, xs, rtol=1e-10, max_iters=3000)
-    for s, x, ref in zip(st, xs, refs):
-        assert s.converged
-        assert np.linalg.norm(x[0].cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-7
+    rtol = 1e-10 if prec == mtf.FP64 else 1e-9
+    st = B.solve(bs, xs, rtol=rtol, precision=prec, max_iters=3000)
+    for k, (s, x, ref) in enumerate(zip(st, xs, refs)):
+        err = np.linalg.norm(x[0].cpu().numpy() - ref) / np.linalg.norm(ref)
+        print(f"[batch lanes={lanes} prec={prec} problem {k}] iterations {s.iterations} refinements {s.refinements} "
+              f"residual {s.rel_residual:.1e} error {err:.1e}", flush=True)
+        assert s.converged and s.rel_residual <= rtol
+        assert err < (1e-7 if prec == mtf.FP64 else 1e-6)
     B.close()
 
 
