@@ -279,13 +279,15 @@ def sphere_cluster(rng: SplitMix64, tmin=200, tmax=2000, rmin=0.3, rmax=1.0,
             if np.linalg.norm(c - c2) < r + r2 + gap * min(r, r2):
                 ok = False
                 break
-        if ok or tries > 10000:
+        if ok:
             spheres.append((c, r, t_s))
+        elif tries > 10000:
+            raise RuntimeError("sphere_cluster: no room for another disjoint sphere after 10000 tries")
     eps = [rng.uniform(emin, emax) for _ in spheres]
     xyz, tri, lab = [], [], []
     off = 0
     for sid, (c, r, t_s) in enumerate(spheres, start=1):
-        m = fibonacci_sphere_mesh(t_s // 2 + 2, r, c, sid)
+        m = morton_vertex_order(fibonacci_sphere_mesh(t_s // 2 + 2, r, c, sid))
         xyz.append(m.xyz)
         tri.append(m.tri + off)
         lab.append(m.label)
@@ -293,8 +295,33 @@ def sphere_cluster(rng: SplitMix64, tmin=200, tmax=2000, rmin=0.3, rmax=1.0,
     mesh = Mesh(xyz=np.concatenate(xyz), tri=np.concatenate(tri).astype(np.int32),
                 label=np.concatenate(lab).astype(np.int32), M=len(spheres),
                 meta={"kind": "sphere_cluster", "radii": [s[1] for s in spheres],
-                      "tri_per_sphere": [s[2] for s in spheres]})
+                      "tri_per_sphere": [s[2] for s in spheres], "vertex_order": "morton per sphere"})
     return mesh, np.array([1.0] + eps)
+
+
+def morton_vertex_order(mesh: Mesh) -> Mesh:
+    """The same mesh with its vertices numbered along a Morton (Z-order) curve through the bounding
+    box (20 bits per axis), so that nearby vertices have nearby numbers, as a mesher's numbering
+    has.  The raw Fibonacci points are numbered along a spiral whose consecutive points are far
+    apart; the RWG dofs follow the vertex numbering (edges sorted by their vertex ids).  A cluster
+    numbers each sphere's vertices in turn, so that the dofs of one sphere stay together."""
+    lo, hi = mesh.xyz.min(axis=0), mesh.xyz.max(axis=0)
+    span = np.where(hi > lo, hi - lo, 1.0)
+    q = np.clip(((mesh.xyz - lo) / span * 1048575.0).astype(np.uint64), 0, 1048575)
+
+    def spread(x):                       # 20 bits -> every third bit of 60
+        x = x & np.uint64(0xFFFFF)
+        for sh, mask in ((32, 0x1F00000000FFFF), (16, 0x1F0000FF0000FF), (8, 0x100F00F00F00F00F),
+                         (4, 0x10C30C30C30C30C3), (2, 0x1249249249249249)):
+            x = (x | (x << np.uint64(sh))) & np.uint64(mask)
+        return x
+
+    key = spread(q[:, 0]) | (spread(q[:, 1]) << np.uint64(1)) | (spread(q[:, 2]) << np.uint64(2))
+    order = np.argsort(key, kind="stable")
+    new_id = np.empty_like(order)
+    new_id[order] = np.arange(order.size)
+    return Mesh(xyz=mesh.xyz[order], tri=new_id[mesh.tri].astype(np.int32), label=mesh.label, M=mesh.M,
+                meta=dict(mesh.meta, vertex_order="morton"))
 
 
 # ---------------------------------------------------------------------------
