@@ -293,6 +293,8 @@ template <typename R, typename S>
 struct TileAcc {
     R v[kAccOps<R>][S::SX][S::SY][2];    // [operator][test slot][trial slot][re, im]
     int first_x[S::SX], first_y[S::SY];  // first slot of the same dof, -1 when unused
+    int order_x[S::SX], order_y[S::SY];  // the distinct slots: test ones by increasing dof, trial ones in slot order
+    int nx, ny;                          // number of distinct test and trial dofs
 };
 
 // WHICH 0: T into v[0]; 1: K into v[0]; 2: T into v[0] and K into v[1]
@@ -364,6 +366,33 @@ __device__ __attribute__((always_inline)) inline void regular_tile(const int4 ti
         else acc->first_y[sl] = f;
     }
     __syncthreads();
+    // compact lists of the distinct slots for the scatter, the test dofs in increasing order: the
+    // lanes of a wavefront then add into neighbouring rows of one column of T or K, and their
+    // atomics share cache lines
+    for (int e = tid; e < SX + SY; e += NT) {
+        if (e < SX) {
+            if (acc->first_x[e] != e) continue;
+            const int d = rec[e / 3].dof[e % 3];
+            int rank = 0;
+            for (int q = 0; q < SX; ++q)
+                if (acc->first_x[q] == q && rec[q / 3].dof[q % 3] < d) ++rank;
+            acc->order_x[rank] = e;
+        } else {
+            const int sl = e - SX;
+            if (acc->first_y[sl] != sl) continue;
+            int rank = 0;
+            for (int q = 0; q < sl; ++q) rank += acc->first_y[q] == q;
+            acc->order_y[rank] = sl;
+        }
+    }
+    if (tid == 0) {
+        int nx = 0, ny = 0;
+        for (int q = 0; q < SX; ++q) nx += acc->first_x[q] == q;
+        for (int q = 0; q < SY; ++q) ny += acc->first_y[q] == q;
+        acc->nx = nx;
+        acc->ny = ny;
+    }
+    __syncthreads();
     const int ix = tid / TY, iy = tid % TY;
     const int tx = tile.y + ix, ty = tile.z + iy;
     bool valid = tx < dd.T && ty < dd.T;
@@ -430,14 +459,16 @@ __device__ __attribute__((always_inline)) inline void regular_tile(const int4 ti
     }
     // distinct (test dof, trial dof) entries of the tile from accumulator `op` into `out`
     auto scatter = [&](int op, R* out) {
-        for (int e = tid; e < SX * SY; e += NT) {
-            const int x = e % SX, y = e / SX;
-            if (acc->first_x[x] != x || acc->first_y[y] != y) continue;
+        // neighbouring lanes take the real and imaginary parts of one entry, so one atomic
+        // instruction covers a contiguous run of the column when the tile's test dofs are
+        const int nx = acc->nx, ny = acc->ny;
+        for (int e = tid; e < nx * ny * 2; e += NT) {
+            const int part = e & 1, xy = e >> 1;
+            const int x = acc->order_x[xy % nx], y = acc->order_y[xy / nx];
             const R re = acc->v[op][x][y][0], im = acc->v[op][x][y][1];
             if (re == R(0) && im == R(0)) continue;
             const int64_t idx = 2 * (dd.mat0 + (int64_t)rec[x / 3].dof[x % 3] + (int64_t)rec[TX + y / 3].dof[y % 3] * dd.E);
-            atomic_add(out + idx, re);
-            atomic_add(out + idx + 1, im);
+            atomic_add(out + idx + part, part ? im : re);
         }
     };
     __syncthreads();

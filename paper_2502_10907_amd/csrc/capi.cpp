@@ -543,6 +543,8 @@ void tune_store(const std::string& key, const TuneChoice& c) {
     }
 }
 
+static_assert(kTileVariants == MTF_TILE_VARIANTS, "the public tile-variant count must match the compiled variants");
+
 int shape_class(double mean_tri) { return mean_tri <= 1.0 ? 0 : (int)std::floor(std::log2(mean_tri)); }
 
 // Separated-pair tile list of the problem for tile variant v (subdomain, first test and trial

@@ -65,7 +65,6 @@ void launch_fill_f(float* p, int64_t n, float v, hipStream_t s);
 void launch_tri_setup_rule(const double* xyz, const int32_t* verts, int64_t nrec, const double* bary18,
                            const double* w6, TriGeom* geom, hipStream_t s);
 
-// Separated pairs over tiles (int4: dom, x0, y0, unused) of 16 x 16 triangles.
 // Separated-pair tiles: variant v (0..kTileVariants-1) is a tile of tx test x ty trial triangles
 // (tx * ty threads) compiled for at least `occ` resident waves per SIMD; tiles: int4(subdomain,
 // first test triangle, first trial triangle, 0) stepping by tx and ty.  precision 0 = FP64 blocks,

@@ -62,12 +62,30 @@ Skeleton build_skeleton(int64_t nv, const double* xyz, int64_t nt, const int32_t
         tris_of[label[2 * t]].push_back((int32_t)t);
         tris_of[label[2 * t + 1]].push_back((int32_t)t);
     }
-    // Each Gamma_i's triangles in the order of a Morton (Z-order) curve through their centroids:
-    // 16 consecutive triangles then form a compact patch, so the assembly tiles share more dofs
-    // and scatter fewer distinct entries.  Only summation order depends on it.  The environment
-    // variable MTF_TRIANGLE_ORDER=input keeps the input order (for measuring the difference).
+    // Each Gamma_i's triangles are put in an order in which TX consecutive ones form a compact
+    // patch, so that an assembly tile shares dofs between its triangles and scatters fewer
+    // distinct entries.  Default: by their vertex ids (smallest, middle, largest), the order the
+    // RWG dofs follow (edges are numbered by their vertex ids), so a tile's test dofs also lie close
+    // together and the atomics of its scatter share cache lines.  MTF_TRIANGLE_ORDER=morton orders
+    // them along a Morton (Z-order) curve through their centroids instead (compact patches whatever
+    // the vertex numbering), =input keeps the input order.  Only summation order depends on it.
     const char* ord = std::getenv("MTF_TRIANGLE_ORDER");
-    if (!(ord && std::string(ord) == "input")) {
+    const std::string order = ord ? std::string(ord) : std::string("vertex");
+    if (order != "vertex" && order != "morton" && order != "input")
+        throw ArgError("MTF_TRIANGLE_ORDER must be vertex, morton or input");
+    if (order == "vertex") {
+        auto sorted3 = [&](int32_t t, int32_t* v) {
+            for (int a = 0; a < 3; ++a) v[a] = tri[3 * t + a];
+            std::sort(v, v + 3);
+        };
+        for (auto& l : tris_of)
+            std::stable_sort(l.begin(), l.end(), [&](int32_t x, int32_t y) {
+                int32_t a[3], b[3];
+                sorted3(x, a);
+                sorted3(y, b);
+                return std::lexicographical_compare(a, a + 3, b, b + 3);
+            });
+    } else if (order == "morton") {
         double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
         for (int64_t v = 0; v < nv; ++v)
             for (int k = 0; k < 3; ++k) {
