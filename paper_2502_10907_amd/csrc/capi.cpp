@@ -186,6 +186,7 @@ struct mtf_problem_s {
     PcmmPlan pcmm;                   // block preconditioner on the FP64 matrix cores
     // block Gauss-Seidel stages: stage 0 = {Omega_0}, then colour classes of the subdomain graph
     DevBuf<int4> d_stage_tiles, d_pctiles;    // preconditioner tiles per Gauss-Seidel stage, and all of them
+    DevBuf<int2> d_pc_slots;                  // per row chunk (DomDesc::chunk0 + B): partial slots its tiles write
     int64_t npctiles = 0;
     std::vector<int> dom_colour;              // Gauss-Seidel stage of each subdomain (Omega_0: 0)
     std::vector<char> pc_full;                // 1: the block is T_i^-1 itself, read whole
@@ -255,6 +256,7 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
     // record and dof tables concatenated over subdomains
     std::vector<DomDesc> doms(M + 1);
     int64_t rec = 0, dof = 0, mat = 0, part = 0;
+    int32_t chunks = 0;
     for (int i = 0; i <= M; ++i) {
         const Domain& d = sk.dom[i];
         DomDesc& dd = doms[i];
@@ -267,7 +269,9 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
         dd.T = d.T;
         dd.E = d.E;
         dd.nchunk = (d.E + kChunk - 1) / kChunk;
+        dd.chunk0 = chunks;
         dd.rho = 1.0;
+        chunks += dd.nchunk;
         rec += d.T;
         dof += d.E;
         mat += (int64_t)d.E * d.E;
@@ -874,7 +878,7 @@ double* scratch_on(int device) {
 
 void precond1(mtf_problem p, const double* x, double* z) {
     launch_precond_sym(p->d_doms.p, p->d_pctiles.p, p->npctiles, p->Tinv.p, x, p->part.p, p->stream);
-    launch_precond_sym_finish(p->d_doms.p, p->d_dof_dom.p, p->ndof, p->part.p, z, nullptr, p->stream);
+    launch_precond_sym_finish(p->d_doms.p, p->d_dof_dom.p, p->ndof, p->part.p, p->d_pc_slots.p, z, nullptr, p->stream);
 }
 
 // z = P_GS x: one block Gauss-Seidel sweep over the stages with the T_i^-1 block of each subdomain;
@@ -894,7 +898,7 @@ void precond1_gs(mtf_problem p, const double* x, double* z, double* w) {
             in = w;
         }
         launch_precond_sym(p->d_doms.p, tiles, ntl, p->Tinv.p, in, p->part.p, s);
-        launch_precond_sym_finish(p->d_doms.p, p->d_dof_dom.p, nd, p->part.p, z, dl, s);
+        launch_precond_sym_finish(p->d_doms.p, p->d_dof_dom.p, nd, p->part.p, p->d_pc_slots.p, z, dl, s);
     }
 }
 
@@ -993,22 +997,61 @@ void block_gj_inverse(float* X, int n, int64_t ld, int64_t stride, int batch, in
     }
 }
 
-// Preconditioner tile lists from the per-subdomain kind: upper tiles (w = 0) of a symmetric block,
-// every tile (w = 1) of a whole one; all subdomains, and per Gauss-Seidel stage.
-void build_pc_tiles(mtf_problem p) {
+std::vector<std::pair<int, int>> dof_components(const Domain& d);
+
+// Preconditioner tile lists (all subdomains, and per Gauss-Seidel stage) and the partial slots each
+// row chunk sums.  A block inverted over the connected components of Gamma_i (contiguous dof
+// ranges, zero between components; `per_component`) lists only the 64 x 64 tiles that meet a
+// component's diagonal block: with Imin(J) = lo(component holding dof 64 J) / 64, nondecreasing in
+// J, tile (I, J), I <= J, meets one iff I >= Imin(J) (the component must reach from row chunk I
+// to column chunk J).  A symmetric block lists those tiles (I <= J); the rows of chunk B then get
+// transposed parts from tiles (I, B), I in [Imin(B), B], in slots I, and direct parts from tiles
+// (B, J), J in [B, Jmax(B)], in slots J + 1, Jmax(B) the last J with Imin(J) <= B: slots
+// [Imin(B), Jmax(B) + 1].  A whole-use block (the inverse of T_i itself) lists both orders and
+// uses direct parts only: slots [Imin(B) + 1, Jmax(B) + 1].  A connected Gamma_i has Imin = 0.
+void build_pc_tiles(mtf_problem p, bool per_component) {
     const auto& D = p->doms;
+    const int nd = (int)D.size();
+    std::vector<std::vector<int>> imin(nd), jmax(nd);
+    std::vector<int2> slots;
+    for (int i = 0; i < nd; ++i) {
+        const int nb = D[i].nchunk;
+        std::vector<std::pair<int, int>> comps;
+        if (per_component && D[i].E > 0) comps = dof_components(p->sk.dom[i]);
+        std::vector<int>& lo = imin[i];
+        std::vector<int>& hi = jmax[i];
+        lo.assign(nb, 0);
+        hi.assign(nb, nb - 1);
+        if (!comps.empty()) {
+            size_t c = 0;
+            for (int J = 0; J < nb; ++J) {
+                while (comps[c].second <= J * kChunk) ++c;
+                lo[J] = comps[c].first / kChunk;
+            }
+            int J = 0;
+            for (int B = 0; B < nb; ++B) {
+                while (J + 1 < nb && lo[J + 1] <= B) ++J;
+                hi[B] = std::max(J, B);
+            }
+        }
+        for (int B = 0; B < nb; ++B)
+            slots.push_back(make_int2(p->pc_full[i] ? lo[B] + 1 : lo[B], hi[B] + 1));
+    }
     auto tiles_of = [&](int i, std::vector<int4>& out) {
         const int nb = D[i].nchunk;
+        const bool full = p->pc_full[i] != 0;
         for (int bj = 0; bj < nb; ++bj)
-            for (int bi = 0; bi < nb; ++bi)
-                if (p->pc_full[i] || bi <= bj) out.push_back(make_int4(i, bi, bj, p->pc_full[i] ? 1 : 0));
+            for (int bi = 0; bi < nb; ++bi) {
+                const bool meets = bi <= bj ? bi >= imin[i][bj] : (full && bj >= imin[i][bi]);
+                if (meets) out.push_back(make_int4(i, bi, bj, full ? 1 : 0));
+            }
     };
     std::vector<int4> all, st;
     std::vector<int64_t> st0{0};
-    for (int i = 0; i < (int)D.size(); ++i) tiles_of(i, all);
+    for (int i = 0; i < nd; ++i) tiles_of(i, all);
     const int ncol = *std::max_element(p->dom_colour.begin(), p->dom_colour.end());
     for (int c = 0; c <= ncol; ++c) {
-        for (int i = 0; i < (int)D.size(); ++i)
+        for (int i = 0; i < nd; ++i)
             if (p->dom_colour[i] == c) tiles_of(i, st);
         st0.push_back((int64_t)st.size());
     }
@@ -1016,6 +1059,7 @@ void build_pc_tiles(mtf_problem p) {
     p->npctiles = (int64_t)all.size();
     p->d_stage_tiles.upload(st, p->stream);
     p->stage_tile0 = st0;
+    p->d_pc_slots.upload(slots, p->stream);
 }
 
 // Connected components of Gamma_i (its triangles joined through shared dofs) as dof ranges
@@ -1234,7 +1278,7 @@ void build_tinv(mtf_problem p, bool force_full) {
     HIPCHK(hipMemcpyAsync(h, info.p, sizeof(h), hipMemcpyDeviceToHost, s));
     sync(p);
     if (h[0] || h[1]) throw NonFiniteError("block preconditioner: singular pivot or non-finite inverse of T_i");
-    build_pc_tiles(p);
+    build_pc_tiles(p, !force_full);
     sync(p);
     p->have_tinv = true;
     p->tinv_prec = p->have32 ? MTF_FP32_MIXED : MTF_FP64;
@@ -1435,7 +1479,7 @@ double batch_build_tinv(const std::vector<mtf_problem>& ps, bool force_full, hip
     HIPCHK(hipStreamSynchronize(s));
     if (h[0] || h[1]) throw NonFiniteError("block preconditioner: singular pivot or non-finite inverse of T_i");
     for (mtf_problem p : ps) {
-        build_pc_tiles(p);
+        build_pc_tiles(p, !force_full);
         p->have_tinv = true;
         p->tinv_prec = p->have32 ? MTF_FP32_MIXED : MTF_FP64;
         p->pc_force_full = force_full;

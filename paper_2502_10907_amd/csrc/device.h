@@ -28,7 +28,7 @@ struct DomDesc {
     int64_t part0;    // first partial-sum slot of the domain in the matvec workspace
     int32_t T, E;
     int32_t nchunk;   // column chunks of the dense matvec
-    int32_t pad;
+    int32_t chunk0;   // first entry of the domain's per-chunk tables (preconditioner slot ranges)
     double k, rho;
 };
 
@@ -206,11 +206,13 @@ void launch_matvec_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int64
                               const int32_t* ncol, const double* nval, const double* part, const double* x, double* y,
                               hipStream_t s);
 // Symmetric-read preconditioner product (tiles I <= J of the complex64 inverse of the symmetric
-// part of T_i), its finishing kernel, and the in-place symmetrisation A <- (A + A^T)/2.
+// part of T_i), its finishing kernel, and the in-place symmetrisation A <- (A + A^T)/2.  The
+// finishing kernel sums, for a row of chunk B of domain i, the partial slots
+// slots[doms[i].chunk0 + B].x .. .y (inclusive): the slots its tiles wrote.
 void launch_precond_sym(const DomDesc* doms, const int4* stiles, int64_t ntiles, const float* Tinv, const double* x,
                         double* part, hipStream_t s);
-void launch_precond_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int64_t ndof, const double* part, double* z,
-                               const int32_t* list, hipStream_t s);
+void launch_precond_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int64_t ndof, const double* part,
+                               const int2* slots, double* z, const int32_t* list, hipStream_t s);
 void launch_zero_offdiag_f32(float* A, int E, const int32_t* cid, hipStream_t s);   // A[r,c] = 0 where cid[r] != cid[c]
 void launch_symmetrize_f32(float* A, int n, hipStream_t s);
 // w_i = v_i - sum_j G^ij z_j for the dofs in `list` (one block Gauss-Seidel stage)

@@ -271,7 +271,7 @@ __global__ __launch_bounds__(256, 2) void k_mv_sym(const DomDesc* __restrict__ d
 // I <= J are read, each entry used as (r, c) and, off the diagonal, as (c, r); in a diagonal tile
 // the strict lower triangle is dropped and the diagonal halved).  Tiles flagged in their fourth
 // component belong to a subdomain whose block is the inverse of T_i itself: every tile (I, J) is
-// listed and used directly only, and the tiles J = 0 clear the transposed slot of their rows.  Same
+// listed and used directly only (the transposed slots of its rows are not summed).  Same
 // lane layout within a column group, addressing and partial-slot layout as k_mv_sym; FP32
 // arithmetic.  One workgroup per tile: wavefront w takes the four column groups of columns
 // c0 + 16 w .. c0 + 16 w + 15 and issues all of its loads (8 KB) at once, so that a Gauss-Seidel
@@ -386,18 +386,14 @@ __global__ __launch_bounds__(256) void k_pc_sym(const DomDesc* __restrict__ doms
     }
     double* p = pbase + 2 * ((int64_t)(2 * (J + 1) + wv) * E + r);
     *reinterpret_cast<double2*>(p) = make_double2(sr, si);
-    if (full && J == 0) {                               // slot 0 (the transposed slot) is unused
-        double* z0 = pbase + 2 * ((int64_t)wv * E + r);
-        *reinterpret_cast<double2*>(z0) = make_double2(0.0, 0.0);
-    }
 }
 
-// z_iD = -1/(2 rho) v_N, z_iN = rho/2 v_D from the nb + 1 slots of k_pc_sym (all dofs, or the dofs
-// of `list`); 16 rows per workgroup, 16 lanes per row.
+// z_iD = -1/(2 rho) v_N, z_iN = rho/2 v_D from the slots of k_pc_sym that the row's tiles wrote
+// (all dofs, or the dofs of `list`); 16 rows per workgroup, 16 lanes per row.
 __global__ __launch_bounds__(256) void k_pc_sym_finish(const DomDesc* __restrict__ doms,
                                                        const int32_t* __restrict__ dof_dom, int64_t ndof,
-                                                       const double* __restrict__ part, double* __restrict__ z,
-                                                       const int32_t* __restrict__ list) {
+                                                       const double* __restrict__ part, const int2* __restrict__ slots,
+                                                       double* __restrict__ z, const int32_t* __restrict__ list) {
     const int sl = threadIdx.x & 15;
     const int64_t t = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
     const bool live = t < ndof;
@@ -406,8 +402,9 @@ __global__ __launch_bounds__(256) void k_pc_sym_finish(const DomDesc* __restrict
     const DomDesc dd = doms[dof_dom[g]];
     const int64_t m = g - dd.dof0;
     const int E = dd.E;
+    const int2 rng = slots[dd.chunk0 + (int)(m / 64)];
     double acc[4] = {0, 0, 0, 0};
-    for (int c = sl; c < dd.nchunk + 1; c += 16) {
+    for (int c = rng.x + sl; c <= rng.y; c += 16) {
         const double* pD = part + 2 * (dd.part0 + (int64_t)(2 * c) * E + m);
         const double* pN = part + 2 * (dd.part0 + (int64_t)(2 * c + 1) * E + m);
         acc[0] += pD[0]; acc[1] += pD[1];
@@ -1544,10 +1541,10 @@ void launch_precond_sym(const DomDesc* doms, const int4* stiles, int64_t ntiles,
     hipLaunchKernelGGL(k_pc_sym, dim3((unsigned)ntiles), dim3(256), 0, s, doms, stiles, Tinv, x, part);
 }
 
-void launch_precond_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int64_t ndof, const double* part, double* z,
-                               const int32_t* list, hipStream_t s) {
+void launch_precond_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int64_t ndof, const double* part,
+                               const int2* slots, double* z, const int32_t* list, hipStream_t s) {
     if (ndof <= 0) return;
-    hipLaunchKernelGGL(k_pc_sym_finish, dim3(gridn(ndof, 16)), dim3(256), 0, s, doms, dof_dom, ndof, part, z, list);
+    hipLaunchKernelGGL(k_pc_sym_finish, dim3(gridn(ndof, 16)), dim3(256), 0, s, doms, dof_dom, ndof, part, slots, z, list);
 }
 
 void launch_zero_offdiag_f32(float* A, int E, const int32_t* cid, hipStream_t s) {
