@@ -78,6 +78,14 @@ extern "C" {
  * instead of from its symmetric part; see mtf_solve.  Rebuilds the blocks when the last build
  * used the other kind. */
 #define MTF_SOLVE_PC_FULL 2
+/* Build every block of the T_i^-1 preconditioners as the inverse of T_i itself, per connected
+ * component of Gamma_i (read whole when applied), at once: no symmetric-part attempt, no check
+ * and no rebuilds.  The build then costs one inversion per block where the default costs a second
+ * one for every block that fails its check, and a check product per block; each application reads
+ * twice the entries of a symmetric-part block.  For batches of short solves (tens of steps), where
+ * the build outweighs the applications.  Excludes MTF_SOLVE_PC_FULL.  Rebuilds the blocks when
+ * the last build used another kind. */
+#define MTF_SOLVE_PC_DIRECT 8
 /* Store the Krylov basis in complex64 (compressed-basis GMRES: Aliaga, Anzt, Grutzmacher,
  * Quintana-Orti and Tomas): the Arnoldi arithmetic and the candidate vector stay complex128,
  * each orthonormal basis vector is rounded to complex64 when it is stored, which halves the bytes
@@ -251,7 +259,7 @@ typedef struct {
     int32_t max_iters;        /* Arnoldi steps per GMRES cycle; 0: as many as half the free
                                  device memory holds, at most 8000 (2000 for lockstep batches) */
     int32_t max_refinements;  /* outer FP64 refinement steps (MTF_FP32_MIXED), 0 = 10        */
-    int32_t flags;            /* 0, or MTF_SOLVE_EAGER, MTF_SOLVE_PC_FULL, MTF_SOLVE_BASIS_C64, MTF_SOLVE_BLOCK(p) */
+    int32_t flags;            /* 0, or MTF_SOLVE_EAGER, MTF_SOLVE_PC_FULL, MTF_SOLVE_PC_DIRECT, MTF_SOLVE_BASIS_C64, MTF_SOLVE_BLOCK(p) */
     double  rtol;             /* ||b - M x||_2 <= rtol ||b||_2 with the FP64 operator        */
     double  inner_rtol;       /* inner GMRES tolerance of a refinement step, 0 = 1e-3*... */
     const void* x0_dev;       /* complex128 initial guess [nrhs][ld] or NULL (zero)          */
@@ -281,7 +289,8 @@ typedef struct {
  * has several connected components (the exterior of disjoint scatterers), S_i is taken block
  * diagonal over them, each component's block inverted on its own.
  * A block whose T_i is ill-conditioned enough that ||T_i S_i^-1 v - v|| > 1e-3 ||v|| on a
- * fixed vector v is rebuilt as T_i^-1 and read whole (every block with MTF_SOLVE_PC_FULL).
+ * fixed vector v is rebuilt as T_i^-1 (per component) and read whole (every block at once with
+ * MTF_SOLVE_PC_DIRECT; the whole T_i^-1, components or not, with MTF_SOLVE_PC_FULL).
  * MTF_PREC_BLOCK_TINV_GS applies one block Gauss-Seidel sweep instead: Omega_0
  * first, then the colour classes of the subdomain adjacency graph (subdomains
  * of one class share no interface and are done together), each block solving
@@ -387,7 +396,7 @@ int mtf_batch_assembly_stats(mtf_batch b, int64_t* counts, double* seconds, int3
  * problem is padded with the identity to an order rounded up to 128 and the blocks of equal padded
  * order are inverted as one batch (blocked Gauss-Jordan on FP32 matrix cores), instead of one
  * problem after another.  From the FP32 blocks where assembled, else from the FP64 ones.  flags:
- * 0 or MTF_SOLVE_PC_FULL.  The blocks stay with their problems (used by mtf_solve,
+ * 0, MTF_SOLVE_PC_FULL or MTF_SOLVE_PC_DIRECT.  The blocks stay with their problems (used by mtf_solve,
  * mtf_apply_preconditioner and mtf_batch_solve) until a new assembly of their source precision.
  * Synchronises. */
 int mtf_batch_build_preconditioner(mtf_batch b, int32_t flags);

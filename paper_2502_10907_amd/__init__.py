@@ -37,6 +37,7 @@ PREC_NONE, PREC_BLOCK_TINV, PREC_BLOCK_TINV_GS = 0, 1, 2
 PREC_MULTI = 0x100   # mtf_apply_preconditioner: all vectors together on the FP64 matrix cores
 SOLVE_EAGER = 1
 SOLVE_PC_FULL = 2
+SOLVE_PC_DIRECT = 8
 SOLVE_BASIS_C64 = 4
 
 
@@ -348,7 +349,8 @@ class Problem:
 
     def solve(self, b, x, rtol: float = 1e-6, precision: int = FP64, preconditioner: int = PREC_BLOCK_TINV,
               max_iters: int = 0, max_refinements: int = 0, inner_rtol: float = 0.0, x0=None,
-              graph: bool = True, pc_full: bool = False, basis_c64: bool = False, block: int = 0) -> list[Stats]:
+              graph: bool = True, pc_full: bool = False, basis_c64: bool = False, block: int = 0,
+              pc_direct: bool = False) -> list[Stats]:
         pb, nrhs, ld = _dev(b, self.N)
         px, nrhs2, ld2 = _dev(x, self.N)
         if (nrhs, ld) != (nrhs2, ld2):
@@ -361,7 +363,8 @@ class Problem:
         o = SolveOpts(C.sizeof(SolveOpts), int(precision), int(preconditioner), int(max_iters),
                       int(max_refinements),
                       (0 if graph else SOLVE_EAGER) | (SOLVE_PC_FULL if pc_full else 0) |
-                      (SOLVE_BASIS_C64 if basis_c64 else 0) | SOLVE_BLOCK(block),
+                      (SOLVE_PC_DIRECT if pc_direct else 0) | (SOLVE_BASIS_C64 if basis_c64 else 0) |
+                      SOLVE_BLOCK(block),
                       float(rtol), float(inner_rtol), x0p)
         st = (SolveStats * nrhs)()
         code = _check(_lib.mtf_solve(self._h, nrhs, pb, px, ld, C.byref(o), st))
@@ -542,17 +545,19 @@ class Batch:
                                              cfg.ctypes.data_as(_ip)))
         return counts, (float(sec[0]), float(sec[1])), (int(cfg[0]), int(cfg[1]))
 
-    def build_preconditioner(self, pc_full: bool = False):
+    def build_preconditioner(self, pc_full: bool = False, pc_direct: bool = False):
         """T_i^-1 preconditioner blocks of every problem, built together."""
-        _check(_lib.mtf_batch_build_preconditioner(self._h, SOLVE_PC_FULL if pc_full else 0))
+        _check(_lib.mtf_batch_build_preconditioner(self._h, (SOLVE_PC_FULL if pc_full else 0) |
+                                                   (SOLVE_PC_DIRECT if pc_direct else 0)))
 
     def solve(self, bs, xs, rtol=1e-6, precision=FP64, preconditioner=PREC_BLOCK_TINV, max_iters=0, graph=True,
-              basis_c64=False):
+              basis_c64=False, pc_direct=False):
         n = len(self.problems)
         pb = (_P * n)(*[_dev(b, p.N)[0].value for b, p in zip(bs, self.problems)])
         px = (_P * n)(*[_dev(x, p.N)[0].value for x, p in zip(xs, self.problems)])
         o = SolveOpts(C.sizeof(SolveOpts), int(precision), int(preconditioner), int(max_iters), 0,
-                      (0 if graph else SOLVE_EAGER) | (SOLVE_BASIS_C64 if basis_c64 else 0), float(rtol), 0.0, None)
+                      (0 if graph else SOLVE_EAGER) | (SOLVE_BASIS_C64 if basis_c64 else 0) |
+                      (SOLVE_PC_DIRECT if pc_direct else 0), float(rtol), 0.0, None)
         st = (SolveStats * n)()
         _check(_lib.mtf_batch_solve(self._h, pb, px, C.byref(o), st))
         return [Stats(s.iterations, s.refinements, bool(s.converged), s.rel_residual, s.t_precond_s, s.t_solve_s,

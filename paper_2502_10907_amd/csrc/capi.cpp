@@ -190,7 +190,7 @@ struct mtf_problem_s {
     int64_t npctiles = 0;
     std::vector<int> dom_colour;              // Gauss-Seidel stage of each subdomain (Omega_0: 0)
     std::vector<char> pc_full;                // 1: the block is T_i^-1 itself, read whole
-    bool pc_force_full = false;               // the blocks were built with MTF_SOLVE_PC_FULL
+    int pc_kind = 0;                          // how the blocks were built (PcKind)
     DevBuf<int32_t> d_stage_dofs, d_dom_stage;
     std::vector<int64_t> stage_tile0, stage_dof0;   // [nstage + 1] offsets
     double t_precond = 0;
@@ -238,6 +238,20 @@ double pc_sym_tol() {
     char* end = nullptr;
     const double v = std::strtod(e, &end);
     return (end && *end == 0 && v >= 0.0) ? v : kPcSymTol;
+}
+
+// How the T_i^-1 preconditioner blocks are built: from the symmetric part S_i (per connected
+// component of Gamma_i), each block checked and rebuilt from T_i where S_i^-1 fails; from T_i
+// directly (per component); or from the whole T_i.
+enum PcKind { kPcSym = 0, kPcDirect = 1, kPcWhole = 2 };
+
+int pc_kind_of(int flags) {
+    const bool whole = (flags & MTF_SOLVE_PC_FULL) != 0, direct = (flags & MTF_SOLVE_PC_DIRECT) != 0;
+    if (whole && direct) throw ArgError("MTF_SOLVE_PC_FULL and MTF_SOLVE_PC_DIRECT exclude each other");
+    if (whole) return kPcWhole;
+    // with the check threshold at 0 every symmetric-part block would be rebuilt
+    if (direct || pc_sym_tol() <= 0.0) return kPcDirect;
+    return kPcSym;
 }
 
 void upload_doms(mtf_problem p) {
@@ -1104,10 +1118,11 @@ void ensure_gj_streams(mtf_problem p);
 // falls from the cube of the whole order to the sum of the components' cubes.  S_i differs from T_i
 // by the two-order quadrature difference of touching pairs; where T_i is ill-conditioned that
 // difference is amplified in the inverse.  So every block is checked on a fixed vector v: when
-// ||T_i (S_i^-1 v) - v|| > kPcSymTol ||v|| (or when `force_full`), the block is rebuilt as the
-// inverse of T_i itself and read whole.
-void build_tinv(mtf_problem p, bool force_full) {
-    if (p->have_tinv && p->pc_force_full == force_full) return;
+// ||T_i (S_i^-1 v) - v|| > kPcSymTol ||v||, the block is rebuilt as the inverse of T_i itself (per
+// component) and read whole.  kind kPcDirect builds every block that way at once (no symmetric
+// attempt, no check); kPcWhole inverts the whole T_i, components or not.
+void build_tinv(mtf_problem p, int kind) {
+    if (p->have_tinv && p->pc_kind == kind) return;
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = p->stream;
     const auto& D = p->doms;
@@ -1137,7 +1152,7 @@ void build_tinv(mtf_problem p, bool force_full) {
         T32 = tcopy.p;
     }
     HIPCHK(hipMemcpyAsync(p->Tinv.p, T32, 2 * p->mat_entries * sizeof(float), hipMemcpyDeviceToDevice, s));
-    p->pc_full.assign(nd, force_full ? 1 : 0);
+    p->pc_full.assign(nd, kind != kPcSym ? 1 : 0);
     for (int i = 0; i < nd; ++i)
         if (D[i].E > 0 && !p->pc_full[i]) launch_symmetrize_f32(p->Tinv.p + 2 * D[i].mat0, D[i].E, s);
     // several components: block diagonal over them (entries between components cleared)
@@ -1145,7 +1160,7 @@ void build_tinv(mtf_problem p, bool force_full) {
     std::vector<std::vector<int32_t>> cidh(nd);        // kept until the build synchronises
     std::vector<DevBuf<int32_t>> cids(nd);
     for (int i = 0; i < nd; ++i) {
-        if (D[i].E == 0 || p->pc_full[i]) continue;
+        if (D[i].E == 0 || kind == kPcWhole) continue;
         comps[i] = dof_components(p->sk.dom[i]);
         if (comps[i].empty()) continue;
         std::vector<int32_t>& cid = cidh[i];
@@ -1202,7 +1217,7 @@ void build_tinv(mtf_problem p, bool force_full) {
         HIPCHK(hipEventRecord(p->gj_done[l], p->gj_lane[l]));
         HIPCHK(hipStreamWaitEvent(s, p->gj_done[l], 0));
     }
-    if (!force_full && emax > 0) {
+    if (kind == kPcSym && emax > 0) {
         // check ||T_i (X_i v) - v|| / ||v|| with v_m = (cos m, sin 2m) per block
         std::vector<float> vh(2 * emax);
         for (int64_t m = 0; m < emax; ++m) { vh[2 * m] = (float)std::cos((double)m); vh[2 * m + 1] = (float)std::sin(2.0 * m); }
@@ -1278,11 +1293,11 @@ void build_tinv(mtf_problem p, bool force_full) {
     HIPCHK(hipMemcpyAsync(h, info.p, sizeof(h), hipMemcpyDeviceToHost, s));
     sync(p);
     if (h[0] || h[1]) throw NonFiniteError("block preconditioner: singular pivot or non-finite inverse of T_i");
-    build_pc_tiles(p, !force_full);
+    build_pc_tiles(p, kind != kPcWhole);
     sync(p);
     p->have_tinv = true;
     p->tinv_prec = p->have32 ? MTF_FP32_MIXED : MTF_FP64;
-    p->pc_force_full = force_full;
+    p->pc_kind = kind;
     p->gp.haveA = false;
     p->t_precond = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -1302,13 +1317,13 @@ void ensure_gj_streams(mtf_problem p) {
 // The T_i^-1 preconditioner blocks of every problem of a batch, built together (same blocks as
 // build_tinv: the inverse of the symmetric part of each T_i, or of each connected component's
 // diagonal block of it, checked on a fixed vector and rebuilt from T_i itself where the check
-// fails).  A batch of many small problems has hundreds of diagonal blocks of different orders;
+// fails; or as `kind` asks).  A batch of many small problems has hundreds of diagonal blocks of different orders;
 // inverted one problem after another they are a long chain of small launches (the 64-wide leaf
 // inversions occupy one CU each).  Here every block is copied into a slot of a bucket of equal
 // padded order S (n rounded up to 128, the identity in the padding), and each bucket is one
 // batched blocked Gauss-Jordan inversion, the buckets spread over two streams.  All problems
 // share the stream s.  Returns the wall time of the build.
-double batch_build_tinv(const std::vector<mtf_problem>& ps, bool force_full, hipStream_t s) {
+double batch_build_tinv(const std::vector<mtf_problem>& ps, int kind, hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
     struct Blk {
         int prob, dom;
@@ -1321,13 +1336,13 @@ double batch_build_tinv(const std::vector<mtf_problem>& ps, bool force_full, hip
         const auto& D = p->doms;
         p->Tinv.alloc(2 * (p->mat_entries + 64));
         launch_fill_f(p->Tinv.p, 2 * (p->mat_entries + 64), 0.f, s);
-        p->pc_full.assign(D.size(), force_full ? 1 : 0);
+        p->pc_full.assign(D.size(), kind != kPcSym ? 1 : 0);
         p->have_tinv = false;
         for (int i = 0; i < (int)D.size(); ++i) {
             const int64_t E = D[i].E;
             if (E == 0) continue;
             std::vector<std::pair<int, int>> comps;
-            if (!force_full) comps = dof_components(p->sk.dom[i]);
+            if (kind != kPcWhole) comps = dof_components(p->sk.dom[i]);
             if (comps.empty()) comps.emplace_back(0, (int)E);
             for (const auto& c : comps) {
                 const int64_t o = D[i].mat0 + c.first + (int64_t)c.first * E;
@@ -1446,8 +1461,8 @@ double batch_build_tinv(const std::vector<mtf_problem>& ps, bool force_full, hip
 
     std::vector<int> all(blocks.size());
     for (size_t k = 0; k < blocks.size(); ++k) all[k] = (int)k;
-    const std::vector<int> order = invert(all, force_full ? 0 : 1, !force_full);
-    if (!force_full) {
+    const std::vector<int> order = invert(all, kind == kPcSym ? 1 : 0, kind == kPcSym);
+    if (kind == kPcSym) {
         // ||T_i (X_i v) - v|| / ||v|| per subdomain (over its components); rebuild the failures
         std::map<std::pair<int, int>, std::pair<double, double>> err;
         int64_t uo = 0;
@@ -1479,10 +1494,10 @@ double batch_build_tinv(const std::vector<mtf_problem>& ps, bool force_full, hip
     HIPCHK(hipStreamSynchronize(s));
     if (h[0] || h[1]) throw NonFiniteError("block preconditioner: singular pivot or non-finite inverse of T_i");
     for (mtf_problem p : ps) {
-        build_pc_tiles(p, !force_full);
+        build_pc_tiles(p, kind != kPcWhole);
         p->have_tinv = true;
         p->tinv_prec = p->have32 ? MTF_FP32_MIXED : MTF_FP64;
-        p->pc_force_full = force_full;
+        p->pc_kind = kind;
         p->gp.haveA = false;
     }
     HIPCHK(hipStreamSynchronize(s));
@@ -2421,7 +2436,7 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
     DeviceGuard g(p->device);
     const int pc = opts.preconditioner;
     const bool use_pc = pc != MTF_PREC_NONE;
-    if (opts.flags & ~(MTF_SOLVE_EAGER | MTF_SOLVE_PC_FULL | MTF_SOLVE_BASIS_C64 | MTF_SOLVE_BLOCK(0xff)))
+    if (opts.flags & ~(MTF_SOLVE_EAGER | MTF_SOLVE_PC_FULL | MTF_SOLVE_PC_DIRECT | MTF_SOLVE_BASIS_C64 | MTF_SOLVE_BLOCK(0xff)))
         throw ArgError("unknown solve flags");
     const bool basis_c64 = (opts.flags & MTF_SOLVE_BASIS_C64) != 0;
     const int block = (opts.flags >> 8) & 0xff;
@@ -2432,9 +2447,9 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
     }
     if (basis_c64 && !use_pc) throw ArgError("MTF_SOLVE_BASIS_C64 needs a preconditioner (the flexible iteration)");
     const bool graph = (opts.flags & MTF_SOLVE_EAGER) == 0;
-    const bool pc_full = (opts.flags & MTF_SOLVE_PC_FULL) != 0;
+    const int pc_kind = pc_kind_of(opts.flags);
     double t_pc = 0;
-    if (use_pc && (!p->have_tinv || p->pc_force_full != pc_full)) { build_tinv(p, pc_full); t_pc = p->t_precond; }
+    if (use_pc && (!p->have_tinv || p->pc_kind != pc_kind)) { build_tinv(p, pc_kind); t_pc = p->t_precond; }
     if (block > 0)
         return block_solve(p, nrhs, static_cast<const double*>(b_dev), static_cast<double*>(x_dev), ld, opts, block, pc,
                            stats, t_pc);
@@ -3006,7 +3021,7 @@ int mtf_apply_preconditioner(mtf_problem p, int32_t preconditioner, int32_t nrhs
         if (multi && nrhs > kMaxBlock) throw ArgError("MTF_PREC_MULTI takes at most 32 vectors");
         if (!p->have64 && !p->have32) throw StateError("mtf_apply_preconditioner before mtf_assemble");
         DeviceGuard g(p->device);
-        if (!p->have_tinv) build_tinv(p, false);
+        if (!p->have_tinv) build_tinv(p, pc_kind_of(0));
         if (multi) {
             DevBuf<double> w;
             if (preconditioner == MTF_PREC_BLOCK_TINV_GS) w.alloc((size_t)2 * ld * nrhs);
@@ -3360,13 +3375,15 @@ int mtf_batch_assembly_stats(mtf_batch b, int64_t* counts, double* seconds, int3
 int mtf_batch_build_preconditioner(mtf_batch b, int32_t flags) {
     return guarded([&] {
         if (!b) throw ArgError("batch is NULL");
-        if (flags & ~MTF_SOLVE_PC_FULL) throw ArgError("flags: only MTF_SOLVE_PC_FULL is accepted");
+        if (flags & ~(MTF_SOLVE_PC_FULL | MTF_SOLVE_PC_DIRECT))
+            throw ArgError("flags: only MTF_SOLVE_PC_FULL or MTF_SOLVE_PC_DIRECT are accepted");
+        const int kind = pc_kind_of(flags);
         DeviceGuard g(b->device);
         for (mtf_problem p : b->probs) {
             if (!p->has_mesh || !p->has_mat) throw StateError("problem lost its mesh or materials");
             if (!p->have32 && !p->have64) throw StateError("mtf_batch_build_preconditioner: assemble the batch first");
         }
-        batch_build_tinv(b->probs, (flags & MTF_SOLVE_PC_FULL) != 0, b->stream);
+        batch_build_tinv(b->probs, kind, b->stream);
         return MTF_OK;
     });
 }
@@ -3389,7 +3406,7 @@ int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, c
             o = *opts;
         }
         if (o.max_iters == 0) o.max_iters = kBatchCycle;
-        const bool pc_full = (o.flags & MTF_SOLVE_PC_FULL) != 0;
+        const int pc_kind = pc_kind_of(o.flags);
         DeviceGuard g(b->device);
         // what each problem held before the call; whatever the call creates beyond that is released
         // when the problem's solve ends, also when it ends with an error
@@ -3419,11 +3436,11 @@ int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, c
             for (size_t i = 0; i < np; ++i) {
                 mtf_problem p = b->probs[i];
                 if (!p->have32 && !p->have64) throw StateError("mtf_batch_solve: assemble the batch first");
-                if (!p->have_tinv || p->pc_force_full != pc_full) need.push_back(p);
+                if (!p->have_tinv || p->pc_kind != pc_kind) need.push_back(p);
             }
             if (!need.empty()) {
                 try {
-                    t_pc = batch_build_tinv(need, pc_full, b->stream);
+                    t_pc = batch_build_tinv(need, pc_kind, b->stream);
                 } catch (...) {
                     for (size_t i = 0; i < np; ++i)
                         if (tmpinv[i]) { b->probs[i]->Tinv.reset(); b->probs[i]->have_tinv = false; }

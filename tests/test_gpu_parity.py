@@ -681,6 +681,33 @@ def test_preconditioner_rebuild_from_T_per_component(cluster, batched, monkeypat
         B.close()
 
 
+@pytest.mark.parametrize("batched", [False, True])
+def test_direct_preconditioner_per_component(cluster, batched):
+    """MTF_SOLVE_PC_DIRECT: every block is the inverse of T_i itself per connected component of
+    Gamma_0, built at once (no symmetric attempt, no check): z = P x against LAPACK solves with the
+    oracle's unsymmetrised component blocks; the Gauss-Seidel solve from those blocks reaches the LU
+    solution.  Single-problem and batched builds; the flag excludes MTF_SOLVE_PC_FULL."""
+    P = _fresh(cluster.cfg)
+    b = torch.tensor(cluster.b[None, :], device="cuda")
+    x = torch.zeros_like(b)
+    if batched:
+        B = mtf.Batch([P])
+        B.build_preconditioner(pc_direct=True)
+        _check_blocks_against_lapack(cluster, P, False, "direct batched")
+        st = B.solve([b], [x], rtol=1e-10, preconditioner=mtf.PREC_BLOCK_TINV_GS, max_iters=3000, pc_direct=True)[0]
+        with pytest.raises(mtf.MTFError):
+            B.build_preconditioner(pc_full=True, pc_direct=True)
+        B.close()
+    else:
+        st = P.solve(b, x, rtol=1e-10, preconditioner=mtf.PREC_BLOCK_TINV_GS, max_iters=3000, pc_direct=True)[0]
+        _check_blocks_against_lapack(cluster, P, False, "direct")
+        with pytest.raises(mtf.MTFError):
+            P.solve(b, torch.zeros_like(b), preconditioner=mtf.PREC_BLOCK_TINV, pc_full=True, pc_direct=True)
+    print(f"[direct{' batched' if batched else ''}] iterations {st.iterations} residual {st.rel_residual:.2e}", flush=True)
+    assert st.converged and st.rel_residual <= 1e-10
+    assert np.linalg.norm(x[0].cpu().numpy() - cluster.x) / np.linalg.norm(cluster.x) < 1e-7
+
+
 def test_batch_solve_default_cycle_restarts(sphere):
     """mtf_batch_solve with max_iters 0 runs cycles of at most 1,000 Arnoldi steps: the sphere without
     a preconditioner needs about 1,030 steps to 1e-10, so the default cycle must restart, and the
