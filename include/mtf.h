@@ -407,7 +407,9 @@ int mtf_batch_build_preconditioner(mtf_batch b, int32_t flags);
  * t_precond_s.  The problems are then solved on up to 4 streams at once (the environment variable
  * MTF_BATCH_LANES sets 1-8; 1 solves problem after problem on the problems' own streams), each
  * stream a host thread taking the next problem, largest first; with more than one, the call starts
- * with a device synchronisation and ends when every solve is complete.  A problem without FP64
+ * with a device synchronisation and ends when every solve is complete, and each solve reads its
+ * Hessenberg columns every 4 Arnoldi steps instead of 8 (the other streams keep the GPU busy
+ * meanwhile, and fewer steps are spent past convergence).  A problem without FP64
  * blocks gets them assembled (default options) for its residual checks and released after its
  * solve; with opts.precision MTF_FP32_MIXED a problem without complex64 blocks gets them rounded
  * from its FP64 blocks (MTF_ASSEMBLE_ROUND_FP64) for its solve only.  Preconditioner blocks that a

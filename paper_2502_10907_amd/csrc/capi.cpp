@@ -34,7 +34,10 @@ constexpr int kChunk = 64;    // columns per dense-matvec workgroup (matches sol
 constexpr int kNblk = 32;     // partial sums of GMRES norms
 constexpr int kGjPanel = 256; // block width of the Gauss-Jordan inversion (64-wide leaves inside)
 constexpr double kPcSymTol = 1e-3;   // largest ||T_i S_i^-1 v - v|| / ||v|| of a symmetric-part block
-constexpr int kSync = 8;      // Arnoldi steps between host reads of the Hessenberg columns
+constexpr int kSync = 8;      // Arnoldi steps between host reads of the Hessenberg columns (the most)
+// ... of a problem solved on one of several batch lanes: the other lanes keep the GPU busy while
+// one waits for its host read, and a shorter interval spends fewer steps past convergence
+constexpr int kSyncLanes = 4;
 constexpr int kMaxBatch = 64; // right-hand sides per lockstep GMRES batch (MFMA products)
 constexpr int kMaxBlock = 32; // right-hand sides per block of block GMRES
 // smallest kept pivot of the pivoted Cholesky factorisation of a block's scaled Gram matrix: the
@@ -191,6 +194,7 @@ struct mtf_problem_s {
     std::vector<int> dom_colour;              // Gauss-Seidel stage of each subdomain (Omega_0: 0)
     std::vector<char> pc_full;                // 1: the block is T_i^-1 itself, read whole
     int pc_kind = 0;                          // how the blocks were built (PcKind)
+    int gmres_sync = kSync;                   // Arnoldi steps between host reads of its GMRES cycles
     DevBuf<int32_t> d_stage_dofs, d_dom_stage;
     std::vector<int64_t> stage_tile0, stage_dof0;   // [nstage + 1] offsets
     double t_precond = 0;
@@ -1663,13 +1667,13 @@ void stf_matvec(mtf_problem p, const double* x, double* y, int64_t ld, int nb) {
 // step j applies the operator to the once-projected candidate u_j, then one pass over the basis
 // gives the coefficients and a second pass forms q_j and u_{j+1}; Hessenberg column j-1 becomes
 // final at step j.  The Hessenberg matrix stays on the device; the host receives the final columns
-// every kSync steps and applies the Givens rotations.  Each right-hand side stops at its own step.
+// every kSync steps (p->gmres_sync, at most kSync) and applies the Givens rotations.  Each right-hand side stops at its own step.
 // With a preconditioner the iteration is flexible: the preconditioned candidates zt_j = P u_j are
 // kept, and since U = Q R (R upper triangular from the reorthogonalisation coefficients) the
 // correction is Zt R^-1 y, so M times the correction matches the Arnoldi relation exactly even
 // though P is applied in FP32.
 // Every kernel of a step reads the step index from the device and works on step-invariant
-// buffers, so the kSync steps between two host reads (plus the staging of the final columns and
+// buffers, so the steps between two host reads (plus the staging of the final columns and
 // their copy to pinned host memory) are captured once as a HIP graph and replayed (`graph`), or
 // launched one by one; both run the same kernels.
 // Returns the number of Arnoldi steps taken; it[b], est[b] (recurrence residual / ||r_b||) per column.
@@ -1678,6 +1682,7 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
                 std::vector<int>& reorth, bool graph, double relax, bool c64) {
     GmresWork& w = p->gw;
     hipStream_t s = p->stream;
+    const int nsync = std::max(1, std::min(kSync, p->gmres_sync));   // steps between host reads
     const int64_t n = w.n;
     const int64_t ldh = w.maxit + 1;
     const int64_t hstride = ldh * (int64_t)w.maxit;
@@ -1709,13 +1714,13 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
                        flex ? w.zfix.p : nullptr, flex ? w.Zt.p : nullptr, w.H.p, ldh, hstride, w.hg.p, nct,
                        flex ? w.Rf.p : nullptr, hstride, c64, nb, s);
     };
-    // kSync steps j0 .. j0+kSync-1 (j0 odd), then the final columns j0-1 .. j0+kSync-2 staged in Hst
+    // nsync steps j0 .. j0+nsync-1 (j0 odd), then the final columns j0-1 .. j0+nsync-2 staged in Hst
     // (the caller copies them to one of the two host areas)
-    const size_t stage_doubles = (size_t)2 * ldh * kSync * nb;
+    const size_t stage_doubles = (size_t)2 * ldh * nsync * nb;
     const size_t stage_bytes = stage_doubles * sizeof(double);
     auto batch = [&](int j0) {
-        for (int q = 0; q < kSync; ++q) step(j0 + q);
-        launch_stage_cols(w.H.p, ldh, hstride, jslot(j0 + kSync), kSync + 1, kSync, w.Hst.p, nb, s);
+        for (int q = 0; q < nsync; ++q) step(j0 + q);
+        launch_stage_cols(w.H.p, ldh, hstride, jslot(j0 + nsync), nsync + 1, nsync, w.Hst.p, nb, s);
     };
     for (hipEvent_t& e : w.ev)
         if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -1837,8 +1842,8 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
         pend[0] = pend[1];
         --npend;
         HIPCHK(hipEventSynchronize(w.ev[q.area]));
-        process(q.c0, kSync, w.host + q.area * stage_doubles);
-        done_cols = q.c0 + kSync;
+        process(q.c0, nsync, w.host + q.area * stage_doubles);
+        done_cols = q.c0 + nsync;
     };
     auto far = [&]() {
         for (int b = 0; b < nb; ++b)
@@ -1847,9 +1852,9 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
     };
     while (live > 0) {
         const int want = far() ? 2 : 1;
-        while (npend < want && j + kSync <= maxit) {
+        while (npend < want && j + nsync <= maxit) {
             launch_batch(j);
-            j += kSync;
+            j += nsync;
         }
         if (npend > 0) {
             finish_oldest();
@@ -3536,6 +3541,11 @@ int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, c
                         }
                     } on{p, p->stream};
                     p->stream = b->lane[l];
+                    struct SyncSteps {
+                        mtf_problem p;
+                        ~SyncSteps() { p->gmres_sync = kSync; }
+                    } sync_steps{p};
+                    p->gmres_sync = kSyncLanes;
                     const int r = solve_one(i, b->gw[l]);
                     std::lock_guard<std::mutex> lk(mu);
                     if (r != MTF_OK) status = r;
