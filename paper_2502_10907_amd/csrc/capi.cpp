@@ -1682,7 +1682,9 @@ int gmres_cycle(mtf_problem p, const double* R, double* X, int64_t ldx, int nb, 
                 std::vector<int>& reorth, bool graph, double relax, bool c64) {
     GmresWork& w = p->gw;
     hipStream_t s = p->stream;
-    const int nsync = std::max(1, std::min(kSync, p->gmres_sync));   // steps between host reads
+    // steps between host reads: even, since the replayed batch of steps alternates the two step-index
+    // slots and must start on the same parity every time
+    const int nsync = std::max(2, std::min(kSync, p->gmres_sync) & ~1);
     const int64_t n = w.n;
     const int64_t ldh = w.maxit + 1;
     const int64_t hstride = ldh * (int64_t)w.maxit;
