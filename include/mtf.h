@@ -138,7 +138,14 @@ int mtf_problem_destroy(mtf_problem p);
  * the triangle-pair classes.  Fails with MTF_ERR_MESH when a Gamma_i is not a
  * closed, consistently oriented 2-manifold (every Gamma_i edge shared by exactly
  * two Gamma_i triangles traversing it in opposite directions), when a triangle
- * is degenerate, or when a subdomain has no triangle.  Arrays are copied. */
+ * is degenerate, or when a subdomain has no triangle.  Arrays are copied.
+ * The RWG_i dofs are the edges of Gamma_i ordered by their vertex ids (smaller
+ * id, then larger), so a vertex numbering that keeps nearby vertices close keeps
+ * nearby dofs close.  Each Gamma_i's triangles are stored in the order of their
+ * sorted vertex ids (the dofs' order), which the assembly tiles follow; the
+ * environment variable MTF_TRIANGLE_ORDER=morton orders them along a Morton curve
+ * through their centroids instead, =input keeps the input order (any other value
+ * fails with MTF_ERR_ARG).  Only the summation order of the blocks depends on it. */
 int mtf_set_mesh(mtf_problem p, int64_t nv, const double* xyz, int64_t nt,
                  const int32_t* tri, const int32_t* label, int32_t M);
 

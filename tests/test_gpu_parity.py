@@ -92,6 +92,25 @@ def test_blocks_fp64(name, request):
         assert _rel(c.P.copy_block(i, mtf.BLOCK_K), c.K[i]) < 1e-11 * max(1.0, np.abs(c.T[i]).max() / np.abs(c.K[i]).max())
 
 
+@pytest.mark.parametrize("order", ["vertex", "morton", "input"])
+def test_triangle_orders_give_the_oracle_blocks(order, ragged, monkeypatch):
+    """Each Gamma_i's triangles stored by vertex ids (default), along a Morton curve or in the input
+    order (MTF_TRIANGLE_ORDER): only the summation order of the tiles changes, so the FP64 blocks
+    match the oracle's at every order; an unknown order is rejected."""
+    monkeypatch.setenv("MTF_TRIANGLE_ORDER", order)
+    P = _gpu_problem(ragged.cfg)
+    for i in range(ragged.pb.M + 1):
+        assert _rel(P.copy_block(i, mtf.BLOCK_T), ragged.T[i]) < 1e-11
+        assert _rel(P.copy_block(i, mtf.BLOCK_K), ragged.K[i]) < 1e-11 * max(1.0, np.abs(ragged.T[i]).max() / np.abs(ragged.K[i]).max())
+    P.close()
+    monkeypatch.setenv("MTF_TRIANGLE_ORDER", "hilbert")
+    m = ragged.cfg["mesh"]
+    Q = mtf.Problem(0)
+    with pytest.raises(mtf.MTFError):
+        Q.set_mesh(m.xyz, m.tri, m.label, m.M)
+    Q.close()
+
+
 @pytest.mark.parametrize("name", CASES)
 def test_blocks_fp32(name, request):
     c = request.getfixturevalue(name)
