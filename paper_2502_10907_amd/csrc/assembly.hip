@@ -411,8 +411,12 @@ __device__ __attribute__((always_inline)) inline void regular_tile(const int4 ti
         R D[3];
         for (int i = 0; i < 3; ++i) D[i] = (R)(X.c[i] - Y.c[i]);
         Moments<R>& m = mom;
-        // FP64: one outer quadrature point at a time (the FP64 phase evaluations would otherwise spill)
+        // FP64: one outer quadrature point at a time (the FP64 phase evaluations would otherwise spill);
+        // at three resident waves per SIMD (168 VGPRs) also two inner points at a time, which costs
+        // a few spilled registers outside the loop but hides more FP64 latency (64 clusters: 0.49 s
+        // against 0.57 s at two waves with all six inner points unrolled)
         constexpr int kUnrollQ = std::is_same<R, double>::value ? 1 : 6;
+        constexpr int kUnrollR = std::is_same<R, double>::value && S::OCC >= 3 ? 2 : 6;
 #pragma unroll kUnrollQ
         for (int q = 0; q < 6; ++q) {
             const R x0 = X.q[3 * q], x1 = X.q[3 * q + 1], x2 = X.q[3 * q + 2];
@@ -420,7 +424,7 @@ __device__ __attribute__((always_inline)) inline void regular_tile(const int4 ti
             const R dx0 = D[0] + x0, dx1 = D[1] + x1, dx2 = D[2] + x2;
             R s0[2] = {0, 0}, sy[3][2] = {{0, 0}, {0, 0}, {0, 0}};
             R t0[2] = {0, 0}, ty[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-#pragma unroll
+#pragma unroll kUnrollR
             for (int r = 0; r < 6; ++r) {
                 const R y0 = Y.q[3 * r], y1 = Y.q[3 * r + 1], y2 = Y.q[3 * r + 2];
                 const R d0 = dx0 - y0, d1 = dx1 - y1, d2 = dx2 - y2;
