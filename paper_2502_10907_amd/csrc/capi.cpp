@@ -1417,7 +1417,7 @@ double batch_build_tinv(const std::vector<mtf_problem>& ps, int kind, hipStream_
             float* bb = buf.p + 2 * bslot[bi];
             launch_pad_gather(dpb.p + boff[bi], cnt, S, sym, bb, ls);
             block_gj_inverse(bb, S, S, (int64_t)S * S, cnt, info.p, ls, kGjPanel, tmp[l].p, &la[l]);
-            launch_pad_scatter(dpb.p + boff[bi], cnt, S, bb, ls);
+            launch_pad_scatter(dpb.p + boff[bi], cnt, S, bb, info.p + 1, ls);   // checks every copied entry
             ++bi;
         }
         for (int l = 0; l < 2; ++l) {
@@ -1491,7 +1491,6 @@ double batch_build_tinv(const std::vector<mtf_problem>& ps, int kind, hipStream_
         }
         if (!redo.empty()) invert(redo, 0, false);
     }
-    for (mtf_problem p : ps) launch_nonfinite_check(p->Tinv.p, 2 * p->mat_entries, info.p + 1, s);
     HIPCHK(hipGetLastError());
     int h[2];
     HIPCHK(hipMemcpyAsync(h, info.p, sizeof(h), hipMemcpyDeviceToHost, s));

@@ -241,7 +241,8 @@ struct PadBlock {
 // buf + z S^2 (ld S) <- block z (symmetrised (A + A^T)/2 when sym), identity in the padding
 void launch_pad_gather(const PadBlock* blocks, int nblocks, int S, int sym, float* buf, hipStream_t s);
 // block z's destination <- the leading n x n part of buf + z S^2
-void launch_pad_scatter(const PadBlock* blocks, int nblocks, int S, const float* buf, hipStream_t s);
+// the leading n x n of every slot back to its block; *flag |= 1 when a copied entry is not finite
+void launch_pad_scatter(const PadBlock* blocks, int nblocks, int S, const float* buf, int* flag, hipStream_t s);
 // y = A x for one n x n complex128 block A (ld lda), complex64 x and y; part: ceil(n/256) * n
 // complex64 scratch
 void launch_cgemv_f64src(const double* A, int64_t lda, const float* x, int n, float* part, float* y, hipStream_t s);

@@ -1447,13 +1447,15 @@ __global__ __launch_bounds__(256) void k_pad_gather(const PadBlock* __restrict__
 }
 
 __global__ __launch_bounds__(256) void k_pad_scatter(const PadBlock* __restrict__ blocks, int S,
-                                                     const float2* __restrict__ buf) {
+                                                     const float2* __restrict__ buf, int* __restrict__ flag) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t z = blockIdx.y;
     const PadBlock b = blocks[z];
     if (e >= (int64_t)b.n * b.n) return;
     const int r = (int)(e % b.n), c = (int)(e / b.n);
-    reinterpret_cast<float2*>(b.dst)[r + (int64_t)c * b.ld] = buf[z * (int64_t)S * S + r + (int64_t)c * S];
+    const float2 v = buf[z * (int64_t)S * S + r + (int64_t)c * S];
+    if (!isfinite(v.x) || !isfinite(v.y)) atomicOr(flag, 1);
+    reinterpret_cast<float2*>(b.dst)[r + (int64_t)c * b.ld] = v;
 }
 
 // Single-trace operator for M = 1 through the MTF product: full = C x = [x; -Sigma x] (u_1 = -u_0)
@@ -1683,10 +1685,10 @@ void launch_pad_gather(const PadBlock* blocks, int nblocks, int S, int sym, floa
                        sym, reinterpret_cast<float2*>(buf));
 }
 
-void launch_pad_scatter(const PadBlock* blocks, int nblocks, int S, const float* buf, hipStream_t s) {
+void launch_pad_scatter(const PadBlock* blocks, int nblocks, int S, const float* buf, int* flag, hipStream_t s) {
     if (nblocks <= 0) return;
     hipLaunchKernelGGL(k_pad_scatter, dim3(gridn((int64_t)S * S, 256), (unsigned)nblocks), dim3(256), 0, s, blocks, S,
-                       reinterpret_cast<const float2*>(buf));
+                       reinterpret_cast<const float2*>(buf), flag);
 }
 
 void launch_cgemv_f64src(const double* A, int64_t lda, const float* x, int n, float* part, float* y, hipStream_t s) {
