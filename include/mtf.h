@@ -179,7 +179,7 @@ typedef struct {
  * flags |= MTF_ASSEMBLE_TILE(v) forces variant v instead (0 <= v < MTF_TILE_VARIANTS; see
  * mtf_tile_variant).  Every variant computes the same sums; only the order of the atomic
  * additions differs. */
-#define MTF_TILE_VARIANTS 5
+#define MTF_TILE_VARIANTS 7
 #define MTF_ASSEMBLE_TILE(v) ((((v) + 1) & 0xff) << 8)
 
 /* With MTF_FP32_MIXED: the complex64 blocks are the FP64 blocks (assembled before) rounded to
@@ -354,7 +354,10 @@ int mtf_far_field(mtf_problem p, int32_t nrhs, const void* x_dev, int64_t ld, in
                   const double* dir, double* out);
 
 /* Tile variant v: tiles of tx test x ty trial triangles (one pair per thread, tx * ty threads per
- * workgroup), compiled for at least `occupancy` resident waves per SIMD.  Any output may be NULL. */
+ * workgroup), compiled for at least `occupancy` resident waves per SIMD.  Variants 5 and 6 list each
+ * unordered pair of triangle groups once and evaluate both orders of a triangle pair from one
+ * quadrature (the kernels depend on the distance only: T of the reversed pair is the same value,
+ * K a second epilogue on relabelled moments).  Any output may be NULL. */
 int mtf_tile_variant(int32_t v, int32_t* tx, int32_t* ty, int32_t* occupancy);
 
 /* Tile variant used by the last mtf_assemble of p (-1 before the first). */

@@ -137,7 +137,7 @@ def header_symbols() -> list[str]:
     return sorted(set(re.findall(r"\b(mtf_[a-z0-9_]+)\s*\(", txt)))
 
 
-TILE_VARIANTS = 5
+TILE_VARIANTS = 7
 
 
 def assemble_tile(v: int) -> int:

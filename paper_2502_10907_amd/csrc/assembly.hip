@@ -283,17 +283,25 @@ constexpr int kAccOps = std::is_same<R, double>::value ? 1 : 2;
 // Shape of a tile of separated pairs: TX test triangles x TY trial triangles, one pair per
 // thread, and the minimum number of resident waves per SIMD asked of the compiler (OCC; 1 leaves the
 // register budget to the compiler).  The variants are the autotuner's choices (tile_variant()).
-template <int TX_, int TY_, int OCC_>
+// SYM: the tile list holds each unordered pair of triangle groups once (test group <= trial group,
+// TX == TY) and the tile evaluates the quadrature of each unordered triangle pair once, for both
+// orders: the moments of the reversed pair (Y, X) are those of (X, Y) with Mx <-> My, Nx <-> Ny,
+// Nxy -> -Nxy and D -> -D (the kernels depend on |x - y| only), so T(Y, X) = T(X, Y) (written to
+// both positions) and K(Y, X) is a second epilogue on the relabelled moments.  In a tile on the
+// diagonal only the pairs with test triangle < trial triangle are evaluated.
+template <int TX_, int TY_, int OCC_, bool SYM_ = false>
 struct TileShape {
     static constexpr int TX = TX_, TY = TY_, NT = TX_ * TY_, OCC = OCC_;
     static constexpr int SX = 3 * TX_, SY = 3 * TY_;     // accumulator slots per side
+    static constexpr bool SYM = SYM_;
+    static_assert(!SYM_ || TX_ == TY_, "a symmetric tile needs equal test and trial groups");
 };
 
 template <typename R, typename S>
 struct TileAcc {
     R v[kAccOps<R>][S::SX][S::SY][2];    // [operator][test slot][trial slot][re, im]
     int first_x[S::SX], first_y[S::SY];  // first slot of the same dof, -1 when unused
-    int order_x[S::SX], order_y[S::SY];  // the distinct slots: test ones by increasing dof, trial ones in slot order
+    int order_x[S::SX], order_y[S::SY];  // the distinct slots of each side by increasing dof
     int nx, ny;                          // number of distinct test and trial dofs
 };
 
@@ -313,6 +321,19 @@ struct LdsSink {
             atomicAdd(&acc->v[0][x][y][0], WHICH == 0 ? Tre : Kre);
             atomicAdd(&acc->v[0][x][y][1], WHICH == 0 ? Tim : Kim);
         }
+    }
+};
+
+// K of the reversed pair (test dof a on the trial-side triangle, trial dof b on the test-side one),
+// added into v[0] at (test-side slot of b, trial-side slot of a); scattered to (row of a, column of b)
+template <typename R, typename S>
+struct LdsSinkRev {
+    TileAcc<R, S>* acc;
+    int sx, sy;
+    __device__ void operator()(int a, int b, R, R, R Kre, R Kim) const {
+        const int x = acc->first_x[sx + b], y = acc->first_y[sy + a];
+        atomicAdd(&acc->v[0][x][y][0], Kre);
+        atomicAdd(&acc->v[0][x][y][1], Kim);
     }
 };
 
@@ -380,8 +401,10 @@ __device__ __attribute__((always_inline)) inline void regular_tile(const int4 ti
         } else {
             const int sl = e - SX;
             if (acc->first_y[sl] != sl) continue;
+            const int d = rec[TX + sl / 3].dof[sl % 3];
             int rank = 0;
-            for (int q = 0; q < sl; ++q) rank += acc->first_y[q] == q;
+            for (int q = 0; q < SY; ++q)
+                if (acc->first_y[q] == q && rec[TX + q / 3].dof[q % 3] < d) ++rank;
             acc->order_y[rank] = sl;
         }
     }
@@ -396,6 +419,7 @@ __device__ __attribute__((always_inline)) inline void regular_tile(const int4 ti
     const int ix = tid / TY, iy = tid % TY;
     const int tx = tile.y + ix, ty = tile.z + iy;
     bool valid = tx < dd.T && ty < dd.T;
+    if (S::SYM && tile.y == tile.z && ix >= iy) valid = false;     // the other order of a diagonal tile
     const LRec<R>& X = rec[ix];
     const LRec<R>& Y = rec[TX + iy];
     if (valid) {
@@ -462,29 +486,36 @@ __device__ __attribute__((always_inline)) inline void regular_tile(const int4 ti
                     LdsSink<R, S, kAccOps<R> == 2 ? 2 : 0>{acc, 3 * ix, 3 * iy});
     }
     // distinct (test dof, trial dof) entries of the tile from accumulator `op` into `out`
-    auto scatter = [&](int op, R* out) {
-        // neighbouring lanes take the real and imaginary parts of one entry, so one atomic
-        // instruction covers a contiguous run of the column when the tile's test dofs are
+    // distinct (test dof, trial dof) entries of accumulator `op` into `out`: at (test dof, trial
+    // dof), or (`rev`) at (trial dof, test dof).  Neighbouring lanes take the real and imaginary
+    // parts of one entry and walk the row side's dofs in increasing order, so one atomic
+    // instruction covers a contiguous run of a column when those dofs are
+    auto scatter = [&](int op, R* out, bool rev) {
         const int nx = acc->nx, ny = acc->ny;
+        const int nr = rev ? ny : nx;
         for (int e = tid; e < nx * ny * 2; e += NT) {
             const int part = e & 1, xy = e >> 1;
-            const int x = acc->order_x[xy % nx], y = acc->order_y[xy / nx];
+            const int x = rev ? acc->order_x[xy / nr] : acc->order_x[xy % nr];
+            const int y = rev ? acc->order_y[xy % nr] : acc->order_y[xy / nr];
             const R re = acc->v[op][x][y][0], im = acc->v[op][x][y][1];
             if (re == R(0) && im == R(0)) continue;
-            const int64_t idx = 2 * (dd.mat0 + (int64_t)rec[x / 3].dof[x % 3] + (int64_t)rec[TX + y / 3].dof[y % 3] * dd.E);
+            const int64_t dx = rec[x / 3].dof[x % 3], dy = rec[TX + y / 3].dof[y % 3];
+            const int64_t idx = 2 * (dd.mat0 + (rev ? dy + dx * dd.E : dx + dy * dd.E));
             atomic_add(out + idx + part, part ? im : re);
         }
     };
+    auto clear = [&]() {
+        R* z = &acc->v[0][0][0][0];
+        for (int e = tid; e < SX * SY * 2; e += NT) z[e] = R(0);
+    };
     __syncthreads();
-    scatter(0, T);
+    scatter(0, T, false);
+    if (S::SYM) scatter(0, T, true);                 // T of the reversed pair: the same values, transposed
     if constexpr (kAccOps<R> == 2) {
-        scatter(1, K);
+        scatter(1, K, false);
     } else {
         __syncthreads();
-        {
-            R* z = &acc->v[0][0][0][0];
-            for (int e = tid; e < SX * SY * 2; e += NT) z[e] = R(0);
-        }
+        clear();
         __syncthreads();
         if (valid) {
             // the K pass repeats the epilogue from the moments still held in registers (only its K
@@ -495,7 +526,30 @@ __device__ __attribute__((always_inline)) inline void regular_tile(const int4 ti
             epilogue<R>(mom, X.p, Y.p, X.coef, Y.coef, D, k, X.sg, Y.sg, LdsSink<R, S, 1>{acc, 3 * ix, 3 * iy});
         }
         __syncthreads();
-        scatter(0, K);
+        scatter(0, K, false);
+    }
+    if constexpr (S::SYM) {
+        // K of the reversed pair (Y, X) from the relabelled moments, transposed into place
+        __syncthreads();
+        clear();
+        __syncthreads();
+        if (valid) {
+            const R k = (R)dd.k;
+            R D[3];
+            for (int i = 0; i < 3; ++i) D[i] = (R)(Y.c[i] - X.c[i]);
+            for (int i = 0; i < 3; ++i)
+                for (int c = 0; c < 2; ++c) {
+                    const R mx = mom.Mx[i][c], nx = mom.Nx[i][c];
+                    mom.Mx[i][c] = mom.My[i][c];
+                    mom.My[i][c] = mx;
+                    mom.Nx[i][c] = mom.Ny[i][c];
+                    mom.Ny[i][c] = nx;
+                    mom.Nxy[i][c] = -mom.Nxy[i][c];
+                }
+            epilogue<R>(mom, Y.p, X.p, Y.coef, X.coef, D, k, Y.sg, X.sg, LdsSinkRev<R, S>{acc, 3 * ix, 3 * iy});
+        }
+        __syncthreads();
+        scatter(0, K, true);
     }
 }
 
@@ -821,6 +875,8 @@ using TV1 = TileShape<8, 32, 2>;
 using TV2 = TileShape<32, 8, 2>;
 using TV3 = TileShape<16, 8, 2>;
 using TV4 = TileShape<16, 16, 3>;
+using TV5 = TileShape<16, 16, 3, true>;
+using TV6 = TileShape<16, 16, 2, true>;
 
 template <typename F>
 void with_variant(int v, F&& f) {
@@ -830,6 +886,8 @@ void with_variant(int v, F&& f) {
         case 2: f(TV2{}); break;
         case 3: f(TV3{}); break;
         case 4: f(TV4{}); break;
+        case 5: f(TV5{}); break;
+        case 6: f(TV6{}); break;
         default: throw std::invalid_argument("unknown tile variant");
     }
 }
@@ -841,6 +899,12 @@ void tile_variant_shape(int v, int* tx, int* ty, int* occ) {
         *ty = S::TY;
         *occ = S::OCC;
     });
+}
+
+bool tile_variant_sym(int v) {
+    bool sym = false;
+    with_variant(v, [&](auto sh) { sym = decltype(sh)::SYM; });
+    return sym;
 }
 
 void launch_regular(int precision, int variant, const int4* tiles, int64_t ntiles, const DomDesc* doms,

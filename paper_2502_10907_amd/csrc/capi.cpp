@@ -575,11 +575,12 @@ void ensure_tiles(mtf_problem p, int v) {
     if (p->tile_variant == v) return;
     int tx, ty, occ;
     tile_variant_shape(v, &tx, &ty, &occ);
+    const bool sym = tile_variant_sym(v);
     std::vector<int4> tiles;
     for (int i = 0; i <= p->sk.M; ++i) {
         const int T = p->sk.dom[i].T;
         for (int x0 = 0; x0 < T; x0 += tx)
-            for (int y0 = 0; y0 < T; y0 += ty) tiles.push_back(make_int4(i, x0, y0, 0));
+            for (int y0 = sym ? x0 : 0; y0 < T; y0 += ty) tiles.push_back(make_int4(i, x0, y0, 0));
     }
     p->d_tiles.upload(tiles, p->stream);
     p->ntiles = (int64_t)tiles.size();
@@ -3168,13 +3169,14 @@ void batch_items(mtf_batch b, int v) {
     std::vector<int> order(b->probs.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
     std::sort(order.begin(), order.end(), [&](int x, int y) { return b->probs[x]->mat_entries > b->probs[y]->mat_entries; });
+    const bool sym = tile_variant_sym(v);
     std::vector<int4> items;
     for (int pi : order) {
         const mtf_problem p = b->probs[pi];
         for (int i = 0; i <= p->sk.M; ++i) {
             const int T = p->sk.dom[i].T;
             for (int x0 = 0; x0 < T; x0 += tx)
-                for (int y0 = 0; y0 < T; y0 += ty) items.push_back(make_int4(pi, i, x0, y0));
+                for (int y0 = sym ? x0 : 0; y0 < T; y0 += ty) items.push_back(make_int4(pi, i, x0, y0));
         }
     }
     b->d_items.upload(items, b->stream);

@@ -69,8 +69,11 @@ void launch_tri_setup_rule(const double* xyz, const int32_t* verts, int64_t nrec
 // (tx * ty threads) compiled for at least `occ` resident waves per SIMD; tiles: int4(subdomain,
 // first test triangle, first trial triangle, 0) stepping by tx and ty.  precision 0 = FP64 blocks,
 // 1 = FP32 (T, K point to double or float).
-constexpr int kTileVariants = 5;
+constexpr int kTileVariants = 7;
 void tile_variant_shape(int v, int* tx, int* ty, int* occ);
+// variant v lists each unordered pair of triangle groups once and evaluates both orders of a
+// triangle pair from one quadrature (its tiles: test group <= trial group)
+bool tile_variant_sym(int v);
 void launch_regular(int precision, int variant, const int4* tiles, int64_t ntiles, const DomDesc* doms,
                     const TriGeom* geom, const int32_t* verts, const int32_t* tdof, const int8_t* tsign, void* T,
                     void* K, hipStream_t s);
