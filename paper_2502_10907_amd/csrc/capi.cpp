@@ -2500,9 +2500,13 @@ int solve_impl(mtf_problem p, int32_t nrhs, const void* b_dev, void* x_dev, int6
         int total = 0;
         double delta = -1.0;
         for (int outer = 0; outer <= maxref; ++outer) {
-            // true residuals with the FP64 operator
+            // true residuals with the FP64 operator (r = b itself from the zero initial guess)
             for (int b = 0; b < nb; ++b) {
                 double* rb = w.r.p + 2 * n * b;
+                if (outer == 0 && !opts.x0_dev) {
+                    HIPCHK(hipMemcpyAsync(rb, B + 2 * ld * b, 2 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+                    continue;
+                }
                 matvec1(p, X + 2 * ld * b, rb, MTF_FP64);
                 launch_axpby(rb, B + 2 * ld * b, n, 1.0, 0.0, -1.0, s);   // r = b - M x
             }
