@@ -1122,14 +1122,17 @@ __global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, in
 // optional skipped bands of rows and columns (see CGemm).  C may alias D: each output element is
 // read and written by the same lane.
 // Workgroup tile 128 x 64 complex, k-tile 16, four wavefronts in 2 x 2, each owning 64 x 32 as two
-// 32 x 32 MFMA tiles; per pair of k: re*re, im*(-im), re*im and im*re products, FP32 accumulation.
+// 32 x 32 MFMA tiles.  Each complex product takes three real ones (Gauss's product, the 3M method):
+// P1 = sum re*re, P2 = sum im*im, P3 = sum (re+im)*(re+im), then re = P1 - P2, im = P3 - P1 - P2;
+// FP32 accumulation.  Its error bound is normwise (Higham, Accuracy and Stability, section 23.2.4),
+// a little above the four-product form's and far below what a preconditioner's inverse needs.
 // MFMA lane layout: first operand row l%32, k l/32; second operand k l/32, column l%32; result
 // register i holds row (i/4)*8 + (l/32)*4 + i%4, column l%32.  Each tile is computed transposed
 // (first operand B^T, second A^T), so that lane l holds matrix row l%32: the epilogue's loads and
 // stores of C and D run down the columns (256 contiguous bytes per half-wavefront).
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-__global__ __launch_bounds__(256) void k_cgemm_mfma(const CGemm g) {
+__global__ __launch_bounds__(256, 3) void k_cgemm_mfma(const CGemm g) {
     constexpr int TM = 128, TN = 64, BK = 16;
     __shared__ float Ar[BK][TM], Ai[BK][TM];
     __shared__ float Br[BK][TN + 1], Bi[BK][TN + 1];
@@ -1140,7 +1143,7 @@ __global__ __launch_bounds__(256) void k_cgemm_mfma(const CGemm g) {
     const float2* A2 = reinterpret_cast<const float2*>(g.A) + z * g.sA;
     const float2* B2 = reinterpret_cast<const float2*>(g.B) + z * g.sB;
     const int m = g.m, n = g.n, k = g.k;
-    floatx16 cr0 = {}, cr1 = {}, ci0 = {}, ci1 = {};
+    floatx16 p10 = {}, p11 = {}, p20 = {}, p21 = {}, p30 = {}, p31 = {};
     const int ar_row = tid & 127, ar_k = (tid >> 7) * 8;     // A tile loader: one row, 8 k values
     const int bk = tid & 15, bc = tid >> 4;                   // B tile loader: one k, columns bc + 16q
     const int gr = row0 + ar_row;
@@ -1188,14 +1191,13 @@ __global__ __launch_bounds__(256) void k_cgemm_mfma(const CGemm g) {
             const int r0 = wm * 64 + (lane & 31);
             const float a0r = Ar[kk][r0], a0i = Ai[kk][r0];
             const float a1r = Ar[kk][r0 + 32], a1i = Ai[kk][r0 + 32];
-            cr0 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_r, a0r, cr0, 0, 0, 0);
-            ci0 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_i, a0r, ci0, 0, 0, 0);
-            cr1 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_r, a1r, cr1, 0, 0, 0);
-            ci1 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_i, a1r, ci1, 0, 0, 0);
-            cr0 = __builtin_amdgcn_mfma_f32_32x32x2f32(-b_i, a0i, cr0, 0, 0, 0);
-            ci0 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_r, a0i, ci0, 0, 0, 0);
-            cr1 = __builtin_amdgcn_mfma_f32_32x32x2f32(-b_i, a1i, cr1, 0, 0, 0);
-            ci1 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_r, a1i, ci1, 0, 0, 0);
+            const float b_s = b_r + b_i, a0s = a0r + a0i, a1s = a1r + a1i;
+            p10 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_r, a0r, p10, 0, 0, 0);
+            p11 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_r, a1r, p11, 0, 0, 0);
+            p20 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_i, a0i, p20, 0, 0, 0);
+            p21 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_i, a1i, p21, 0, 0, 0);
+            p30 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_s, a0s, p30, 0, 0, 0);
+            p31 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_s, a1s, p31, 0, 0, 0);
         }
         __syncthreads();
     }
@@ -1203,8 +1205,9 @@ __global__ __launch_bounds__(256) void k_cgemm_mfma(const CGemm g) {
     float* Dz = g.D + 2 * z * g.sD;
 #pragma unroll
     for (int sub = 0; sub < 2; ++sub) {
-        const floatx16& xr = sub == 0 ? cr0 : cr1;
-        const floatx16& xi = sub == 0 ? ci0 : ci1;
+        const floatx16& q1 = sub == 0 ? p10 : p11;
+        const floatx16& q2 = sub == 0 ? p20 : p21;
+        const floatx16& q3 = sub == 0 ? p30 : p31;
         const int row = row0 + wm * 64 + sub * 32 + (lane & 31);
         if (row >= m) continue;
         const int64_t prow = row + (g.band_cd && row >= g.rg0 ? g.rgw : 0);
@@ -1213,8 +1216,9 @@ __global__ __launch_bounds__(256) void k_cgemm_mfma(const CGemm g) {
             const int col = col0 + wn * 32 + (i / 4) * 8 + (lane >> 5) * 4 + (i % 4);
             if (col >= n) continue;
             const int64_t pcol = col + (g.band_cd && col >= g.cg0 ? g.cgw : 0);
-            float re = g.ar * xr[i] - g.ai * xi[i];
-            float im = g.ar * xi[i] + g.ai * xr[i];
+            const float xr = q1[i] - q2[i], xi = q3[i] - q1[i] - q2[i];
+            float re = g.ar * xr - g.ai * xi;
+            float im = g.ar * xi + g.ai * xr;
             if (g.beta != 0.f) {
                 const float* c = Cz + 2 * (prow + pcol * g.ldc);
                 re += g.beta * c[0];
