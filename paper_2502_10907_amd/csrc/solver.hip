@@ -389,35 +389,47 @@ __global__ __launch_bounds__(256) void k_pc_sym(const DomDesc* __restrict__ doms
 }
 
 // z_iD = -1/(2 rho) v_N, z_iN = rho/2 v_D from the slots of k_pc_sym that the row's tiles wrote
-// (all dofs, or the dofs of `list`); 16 rows per workgroup, 16 lanes per row.
+// (all dofs, or the dofs of `list`).  64 rows per workgroup, one per lane, so that every load of a
+// slot reads the consecutive rows' entries at once; the four wavefronts take every fourth slot and
+// meet in LDS.
 __global__ __launch_bounds__(256) void k_pc_sym_finish(const DomDesc* __restrict__ doms,
                                                        const int32_t* __restrict__ dof_dom, int64_t ndof,
                                                        const double* __restrict__ part, const int2* __restrict__ slots,
                                                        double* __restrict__ z, const int32_t* __restrict__ list) {
-    const int sl = threadIdx.x & 15;
-    const int64_t t = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    __shared__ double red[3][4][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t t = (int64_t)blockIdx.x * 64 + lane;
     const bool live = t < ndof;
     const int64_t ts = live ? t : ndof - 1;
     const int64_t g = list ? list[ts] : ts;
     const DomDesc dd = doms[dof_dom[g]];
     const int64_t m = g - dd.dof0;
-    const int E = dd.E;
+    const int64_t E = dd.E;
     const int2 rng = slots[dd.chunk0 + (int)(m / 64)];
+    const double2* pb = reinterpret_cast<const double2*>(part) + dd.part0 + m;
     double acc[4] = {0, 0, 0, 0};
-    for (int c = rng.x + sl; c <= rng.y; c += 16) {
-        const double* pD = part + 2 * (dd.part0 + (int64_t)(2 * c) * E + m);
-        const double* pN = part + 2 * (dd.part0 + (int64_t)(2 * c + 1) * E + m);
-        acc[0] += pD[0]; acc[1] += pD[1];
-        acc[2] += pN[0]; acc[3] += pN[1];
+#pragma unroll 4
+    for (int c = rng.x + wv; c <= rng.y; c += 4) {
+        const double2 d = pb[2 * c * E], n = pb[(2 * c + 1) * E];
+        acc[0] += d.x; acc[1] += d.y;
+        acc[2] += n.x; acc[3] += n.y;
     }
+    if (wv > 0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = row16_sum(acc[q]);
-    if (sl != 0 || !live) return;
+        for (int q = 0; q < 4; ++q) red[wv - 1][q][lane] = acc[q];
+    }
+    __syncthreads();
+    if (wv != 0 || !live) return;
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += red[w][q][lane];
     const double a = -0.5 / dd.rho, b = 0.5 * dd.rho;
     double* oD = z + 2 * (dd.off + m);
     double* oN = z + 2 * (dd.off + E + m);
-    oD[0] = a * acc[2]; oD[1] = a * acc[3];
-    oN[0] = b * acc[0]; oN[1] = b * acc[1];
+    *reinterpret_cast<double2*>(oD) = make_double2(a * acc[2], a * acc[3]);
+    *reinterpret_cast<double2*>(oN) = make_double2(b * acc[0], b * acc[1]);
 }
 
 // A[r, c] <- 0 where the dofs r and c lie in different connected components (cid[r] != cid[c]) of the
@@ -469,9 +481,9 @@ __global__ void k_near_diff(const DomDesc* __restrict__ doms, const int32_t* __r
 }
 
 // Finishing kernel of the symmetric-read product: nb + 1 partial slots per row, the touching-pair
-// correction of the lower triangle and the transmission part.  16 rows per workgroup; the 16 lanes
-// of a row split the slots, the correction terms and the two transmission triangles and are
-// reduced with shuffles.
+// correction of the lower triangle and the transmission part.  64 rows per workgroup, one per lane,
+// so that every load of a slot reads the consecutive rows' entries at once; the four wavefronts
+// take every fourth slot, correction term and transmission term and meet in LDS.
 __global__ __launch_bounds__(256) void k_mv_sym_finish(const DomDesc* __restrict__ doms,
                                                        const int32_t* __restrict__ dof_dom, int64_t ndof,
                                                        const int32_t* __restrict__ dplus,
@@ -480,25 +492,28 @@ __global__ __launch_bounds__(256) void k_mv_sym_finish(const DomDesc* __restrict
                                                        const int64_t* __restrict__ nptr, const int32_t* __restrict__ ncol,
                                                        const double* __restrict__ nval, const double* __restrict__ part,
                                                        const double* __restrict__ x, double* __restrict__ y) {
-    const int sl = threadIdx.x & 15;
-    const int64_t g = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    __shared__ double red[3][4][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t g = (int64_t)blockIdx.x * 64 + lane;
     const bool live = g < ndof;
     const int64_t gs = live ? g : ndof - 1;
     double acc[4] = {0, 0, 0, 0};     // yD re, im, yN re, im
     const DomDesc dd = doms[dof_dom[gs]];
     const int64_t m = gs - dd.dof0;
-    const int E = dd.E;
+    const int64_t E = dd.E;
     const int nslot = dd.nchunk + 1;
-    for (int c = sl; c < nslot; c += 16) {
-        const double* pD = part + 2 * (dd.part0 + (int64_t)(2 * c) * E + m);
-        const double* pN = part + 2 * (dd.part0 + (int64_t)(2 * c + 1) * E + m);
-        acc[0] += pD[0]; acc[1] += pD[1];
-        acc[2] += pN[0]; acc[3] += pN[1];
+    const double2* pb = reinterpret_cast<const double2*>(part) + dd.part0 + m;
+#pragma unroll 4
+    for (int c = wv; c < nslot; c += 4) {
+        const double2 d = pb[2 * c * E], n = pb[(2 * c + 1) * E];
+        acc[0] += d.x; acc[1] += d.y;
+        acc[2] += n.x; acc[3] += n.y;
     }
     const double rho = dd.rho;
     const double* xD = x + 2 * dd.off;
     const double* xN = x + 2 * (dd.off + E);
-    for (int64_t k = nptr[gs] + sl; k < nptr[gs + 1]; k += 16) {
+    for (int64_t k = nptr[gs] + wv; k < nptr[gs + 1]; k += 4) {
         const int64_t n = ncol[k];
         const double* v = nval + 4 * k;
         const double tr = v[0], ti = v[1], kr = v[2], ki = v[3];
@@ -508,8 +523,8 @@ __global__ __launch_bounds__(256) void k_mv_sym_finish(const DomDesc* __restrict
         acc[2] += -2.0 * rho * (tr * dr - ti * di) + 2.0 * (kr * nr - ki * ni);
         acc[3] += -2.0 * rho * (tr * di + ti * dr) + 2.0 * (kr * ni + ki * nr);
     }
-    if (sl < 6) {
-        const int side = sl / 3, c = sl % 3;
+    for (int j = wv; j < 6; j += 4) {
+        const int side = j / 3, c = j % 3;
         const int32_t* pm = side == 0 ? dplus : dminus;
         const int64_t rec = dd.rec0 + pm[2 * gs];
         const int a = pm[2 * gs + 1];
@@ -519,13 +534,20 @@ __global__ __launch_bounds__(256) void k_mv_sym_finish(const DomDesc* __restrict
         acc[0] += v * xd[0]; acc[1] += v * xd[1];
         acc[2] += v * xn[0]; acc[3] += v * xn[1];
     }
+    if (wv > 0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = row16_sum(acc[q]);
-    if (sl != 0 || !live) return;
+        for (int q = 0; q < 4; ++q) red[wv - 1][q][lane] = acc[q];
+    }
+    __syncthreads();
+    if (wv != 0 || !live) return;
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += red[w][q][lane];
     double* oD = y + 2 * (dd.off + m);
     double* oN = y + 2 * (dd.off + E + m);
-    oD[0] = acc[0]; oD[1] = acc[1];
-    oN[0] = acc[2]; oN[1] = acc[3];
+    *reinterpret_cast<double2*>(oD) = make_double2(acc[0], acc[1]);
+    *reinterpret_cast<double2*>(oN) = make_double2(acc[2], acc[3]);
 }
 
 // Block Gauss-Seidel stage input: w_i = v_i - sum_j G^ij z_j for the dofs of one stage (z holds
@@ -1537,7 +1559,7 @@ void launch_matvec_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int64
                               const int32_t* dminus, const double* gval, const int64_t* gcol, const int64_t* nptr,
                               const int32_t* ncol, const double* nval, const double* part, const double* x, double* y,
                               hipStream_t s) {
-    hipLaunchKernelGGL(k_mv_sym_finish, dim3(gridn(ndof, 16)), dim3(256), 0, s, doms, dof_dom, ndof, dplus, dminus, gval,
+    hipLaunchKernelGGL(k_mv_sym_finish, dim3(gridn(ndof, 64)), dim3(256), 0, s, doms, dof_dom, ndof, dplus, dminus, gval,
                        gcol, nptr, ncol, nval, part, x, y);
 }
 
@@ -1550,7 +1572,7 @@ void launch_precond_sym(const DomDesc* doms, const int4* stiles, int64_t ntiles,
 void launch_precond_sym_finish(const DomDesc* doms, const int32_t* dof_dom, int64_t ndof, const double* part,
                                const int2* slots, double* z, const int32_t* list, hipStream_t s) {
     if (ndof <= 0) return;
-    hipLaunchKernelGGL(k_pc_sym_finish, dim3(gridn(ndof, 16)), dim3(256), 0, s, doms, dof_dom, ndof, part, slots, z, list);
+    hipLaunchKernelGGL(k_pc_sym_finish, dim3(gridn(ndof, 64)), dim3(256), 0, s, doms, dof_dom, ndof, part, slots, z, list);
 }
 
 void launch_zero_offdiag_f32(float* A, int E, const int32_t* cid, hipStream_t s) {
