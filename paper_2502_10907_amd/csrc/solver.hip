@@ -1156,8 +1156,8 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 __global__ __launch_bounds__(256, 3) void k_cgemm_mfma(const CGemm g) {
     constexpr int TM = 128, TN = 64, BK = 16;
-    __shared__ float Ar[BK][TM], Ai[BK][TM];
-    __shared__ float Br[BK][TN + 1], Bi[BK][TN + 1];
+    __shared__ float Ar[2][BK][TM], Ai[2][BK][TM];          // two k-tiles: one read, one filled
+    __shared__ float Br[2][BK][TN + 1], Bi[2][BK][TN + 1];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wm = wv & 1, wn = wv >> 1;
     const int row0 = blockIdx.x * TM, col0 = blockIdx.y * TN;
@@ -1191,28 +1191,35 @@ __global__ __launch_bounds__(256, 3) void k_cgemm_mfma(const CGemm g) {
             vb[q] = (gc < n && gk < k) ? B2[gk + pc[q] * g.ldb] : make_float2(0.f, 0.f);
         }
     };
-    fetch(0);
-    for (int k0 = 0; k0 < k; k0 += BK) {
+    auto stash = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            Ar[ar_k + q][ar_row] = va[q].x;
-            Ai[ar_k + q][ar_row] = va[q].y;
+            Ar[buf][ar_k + q][ar_row] = va[q].x;
+            Ai[buf][ar_k + q][ar_row] = va[q].y;
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            Br[bk][bc + 16 * q] = vb[q].x;
-            Bi[bk][bc + 16 * q] = vb[q].y;
+            Br[buf][bk][bc + 16 * q] = vb[q].x;
+            Bi[buf][bk][bc + 16 * q] = vb[q].y;
         }
-        __syncthreads();
-        if (k0 + BK < k) fetch(k0 + BK);
+    };
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    // one barrier per k-tile: it orders the reads of buffer `cur` before its refill two tiles on,
+    // and the refill of the other buffer before its reads in the next tile
+    int cur = 0;
+    for (int k0 = 0; k0 < k; k0 += BK) {
+        const bool more = k0 + BK < k;
+        if (more) fetch(k0 + BK);
 #pragma unroll
         for (int kp = 0; kp < BK; kp += 2) {
             const int kk = kp + (lane >> 5);
             const int cc = wn * 32 + (lane & 31);
-            const float b_r = Br[kk][cc], b_i = Bi[kk][cc];
+            const float b_r = Br[cur][kk][cc], b_i = Bi[cur][kk][cc];
             const int r0 = wm * 64 + (lane & 31);
-            const float a0r = Ar[kk][r0], a0i = Ai[kk][r0];
-            const float a1r = Ar[kk][r0 + 32], a1i = Ai[kk][r0 + 32];
+            const float a0r = Ar[cur][kk][r0], a0i = Ai[cur][kk][r0];
+            const float a1r = Ar[cur][kk][r0 + 32], a1i = Ai[cur][kk][r0 + 32];
             const float b_s = b_r + b_i, a0s = a0r + a0i, a1s = a1r + a1i;
             p10 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_r, a0r, p10, 0, 0, 0);
             p11 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_r, a1r, p11, 0, 0, 0);
@@ -1221,7 +1228,9 @@ __global__ __launch_bounds__(256, 3) void k_cgemm_mfma(const CGemm g) {
             p30 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_s, a0s, p30, 0, 0, 0);
             p31 = __builtin_amdgcn_mfma_f32_32x32x2f32(b_s, a1s, p31, 0, 0, 0);
         }
+        if (more) stash(cur ^ 1);
         __syncthreads();
+        cur ^= 1;
     }
     const float* Cz = g.C ? g.C + 2 * z * g.sC : nullptr;
     float* Dz = g.D + 2 * z * g.sD;
