@@ -194,6 +194,12 @@ struct mtf_problem_s {
     std::vector<int> dom_colour;              // Gauss-Seidel stage of each subdomain (Omega_0: 0)
     std::vector<char> pc_full;                // 1: the block is T_i^-1 itself, read whole
     int pc_kind = 0;                          // how the blocks were built (PcKind)
+    // host-side structure that depends on the mesh only, kept across builds (cleared by a new mesh):
+    // the connected components of each Gamma_i, and what the uploaded tile lists were built for
+    std::vector<std::vector<std::pair<int, int>>> comp_cache;
+    bool comp_cached = false;
+    int tiles_built_for = -1;                 // per_component flag of the uploaded lists (-1: none)
+    std::vector<char> tiles_built_full;       // pc_full they were built with
     int gmres_sync = kSync;                   // Arnoldi steps between host reads of its GMRES cycles
     DevBuf<int32_t> d_stage_dofs, d_dom_stage;
     std::vector<int64_t> stage_tile0, stage_dof0;   // [nstage + 1] offsets
@@ -429,6 +435,9 @@ void set_mesh_impl(mtf_problem p, int64_t nv, const double* xyz, int64_t nt, con
     HIPCHK(hipGetLastError());
     sync(p);   // host vectors above go out of scope
     p->sk = std::move(sk);
+    p->comp_cache.clear();
+    p->comp_cached = false;
+    p->tiles_built_for = -1;
     p->has_mesh = true;
     p->have64 = p->have32 = p->have_tinv = false;
     p->T64.reset(); p->K64.reset(); p->T32.reset(); p->K32.reset(); p->Tinv.reset();
@@ -1018,6 +1027,17 @@ void block_gj_inverse(float* X, int n, int64_t ld, int64_t stride, int batch, in
 
 std::vector<std::pair<int, int>> dof_components(const Domain& d);
 
+// dof_components of every Gamma_i of the problem's mesh, computed on first use
+const std::vector<std::pair<int, int>>& domain_components(mtf_problem p, int i) {
+    if (!p->comp_cached) {
+        p->comp_cache.assign(p->sk.dom.size(), {});
+        for (size_t d = 0; d < p->sk.dom.size(); ++d)
+            if (p->sk.dom[d].E > 0) p->comp_cache[d] = dof_components(p->sk.dom[d]);
+        p->comp_cached = true;
+    }
+    return p->comp_cache[i];
+}
+
 // Preconditioner tile lists (all subdomains, and per Gauss-Seidel stage) and the partial slots each
 // row chunk sums.  A block inverted over the connected components of Gamma_i (contiguous dof
 // ranges, zero between components; `per_component`) lists only the 64 x 64 tiles that meet a
@@ -1029,6 +1049,8 @@ std::vector<std::pair<int, int>> dof_components(const Domain& d);
 // [Imin(B), Jmax(B) + 1].  A whole-use block (the inverse of T_i itself) lists both orders and
 // uses direct parts only: slots [Imin(B) + 1, Jmax(B) + 1].  A connected Gamma_i has Imin = 0.
 void build_pc_tiles(mtf_problem p, bool per_component) {
+    // the lists depend on the mesh, the component flag and pc_full only
+    if (p->tiles_built_for == (per_component ? 1 : 0) && p->tiles_built_full == p->pc_full) return;
     const auto& D = p->doms;
     const int nd = (int)D.size();
     std::vector<std::vector<int>> imin(nd), jmax(nd);
@@ -1036,7 +1058,7 @@ void build_pc_tiles(mtf_problem p, bool per_component) {
     for (int i = 0; i < nd; ++i) {
         const int nb = D[i].nchunk;
         std::vector<std::pair<int, int>> comps;
-        if (per_component && D[i].E > 0) comps = dof_components(p->sk.dom[i]);
+        if (per_component && D[i].E > 0) comps = domain_components(p, i);
         std::vector<int>& lo = imin[i];
         std::vector<int>& hi = jmax[i];
         lo.assign(nb, 0);
@@ -1079,6 +1101,8 @@ void build_pc_tiles(mtf_problem p, bool per_component) {
     p->d_stage_tiles.upload(st, p->stream);
     p->stage_tile0 = st0;
     p->d_pc_slots.upload(slots, p->stream);
+    p->tiles_built_for = per_component ? 1 : 0;
+    p->tiles_built_full = p->pc_full;
 }
 
 // Connected components of Gamma_i (its triangles joined through shared dofs) as dof ranges
@@ -1166,7 +1190,7 @@ void build_tinv(mtf_problem p, int kind) {
     std::vector<DevBuf<int32_t>> cids(nd);
     for (int i = 0; i < nd; ++i) {
         if (D[i].E == 0 || kind == kPcWhole) continue;
-        comps[i] = dof_components(p->sk.dom[i]);
+        comps[i] = domain_components(p, i);
         if (comps[i].empty()) continue;
         std::vector<int32_t>& cid = cidh[i];
         cid.resize(D[i].E);
@@ -1347,7 +1371,7 @@ double batch_build_tinv(const std::vector<mtf_problem>& ps, int kind, hipStream_
             const int64_t E = D[i].E;
             if (E == 0) continue;
             std::vector<std::pair<int, int>> comps;
-            if (kind != kPcWhole) comps = dof_components(p->sk.dom[i]);
+            if (kind != kPcWhole) comps = domain_components(p, i);
             if (comps.empty()) comps.emplace_back(0, (int)E);
             for (const auto& c : comps) {
                 const int64_t o = D[i].mat0 + c.first + (int64_t)c.first * E;
