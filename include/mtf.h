@@ -407,8 +407,10 @@ int mtf_batch_assembly_stats(mtf_batch b, int64_t* counts, double* seconds, int3
  * order are inverted as one batch (blocked Gauss-Jordan on FP32 matrix cores), instead of one
  * problem after another.  From the FP32 blocks where assembled, else from the FP64 ones.  flags:
  * 0, MTF_SOLVE_PC_FULL or MTF_SOLVE_PC_DIRECT.  The blocks stay with their problems (used by mtf_solve,
- * mtf_apply_preconditioner and mtf_batch_solve) until a new assembly of their source precision.
- * Synchronises. */
+ * mtf_apply_preconditioner and mtf_batch_solve) until a new assembly of their source precision;
+ * a later build reuses their storage.  The build's padded work buffers (the buckets and the
+ * panel buffers of the inversion) stay with the batch for the next build, growing when a build
+ * needs more, until mtf_batch_destroy.  Synchronises. */
 int mtf_batch_build_preconditioner(mtf_batch b, int32_t flags);
 
 /* mtf_solve of problem i on b_dev[i] -> x_dev[i] (one right-hand side each, ld = N_i) with
@@ -427,7 +429,10 @@ int mtf_batch_build_preconditioner(mtf_batch b, int32_t flags);
  * A problem without GMRES work buffers of its own uses one of the batch's (one per stream,
  * allocated for the largest problem that stream met and kept until mtf_batch_destroy).  Device
  * memory needed beyond the assembled blocks: the preconditioner blocks of every problem (half the
- * bytes of the complex64 T_i, K_i), per stream one problem's temporary blocks and GMRES buffers.
+ * bytes of the complex64 T_i, K_i), the build's padded work buffers (kept with the batch), per
+ * stream one problem's temporary blocks and GMRES buffers.  A caller that solves the same batch
+ * again after a new assembly builds the blocks with mtf_batch_build_preconditioner first, so that
+ * they and their storage stay with the problems instead of being allocated for every call.
  * max_iters 0 here means cycles of at most 1,000 Arnoldi steps (not the free-memory length of
  * mtf_solve): a batch is many small solves, whose Krylov storage would otherwise be sized from free
  * memory. */

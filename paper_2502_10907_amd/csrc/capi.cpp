@@ -1352,7 +1352,14 @@ void ensure_gj_streams(mtf_problem p) {
 // padded order S (n rounded up to 128, the identity in the padding), and each bucket is one
 // batched blocked Gauss-Jordan inversion, the buckets spread over two streams.  All problems
 // share the stream s.  Returns the wall time of the build.
-double batch_build_tinv(const std::vector<mtf_problem>& ps, int kind, hipStream_t s) {
+// Work buffers of batch_build_tinv: the padded buckets and the two lanes' panel buffers.  Kept by
+// the caller from one build to the next (they only grow), so that a repeated build allocates and
+// frees no device memory.
+struct GjScratch {
+    DevBuf<float> buf, tmp[2];
+};
+
+double batch_build_tinv(const std::vector<mtf_problem>& ps, int kind, hipStream_t s, GjScratch* keep = nullptr) {
     auto t0 = std::chrono::steady_clock::now();
     struct Blk {
         int prob, dom;
@@ -1430,9 +1437,15 @@ double batch_build_tinv(const std::vector<mtf_problem>& ps, int kind, hipStream_
         }
         DevBuf<PadBlock> dpb;
         dpb.upload(hb, s);
-        DevBuf<float> buf, tmp[2];
-        buf.alloc(2 * slots);
-        for (int l = 0; l < 2; ++l) tmp[l].alloc(2 * tmp_need[l]);
+        GjScratch local;
+        GjScratch& sc = keep ? *keep : local;
+        auto grow = [](DevBuf<float>& d, int64_t count) {
+            if (d.n < (size_t)count) d.alloc((size_t)count);
+        };
+        grow(sc.buf, 2 * slots);
+        for (int l = 0; l < 2; ++l) grow(sc.tmp[l], 2 * tmp_need[l]);
+        DevBuf<float>& buf = sc.buf;
+        DevBuf<float>* tmp = sc.tmp;
         HIPCHK(hipEventRecord(p0->gj_start, s));
         for (int l = 0; l < 2; ++l) HIPCHK(hipStreamWaitEvent(p0->gj_lane[l], p0->gj_start, 0));
         size_t bi = 0;
@@ -3178,6 +3191,7 @@ struct mtf_batch_s {
     hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
     double last_tiles_s = 0.0;        // device time of the last persistent launch alone
     double last_total_s = 0.0;        // and of the whole last assembly (touching pairs included)
+    GjScratch gj;                     // work buffers of the preconditioner build, kept between builds
     ~mtf_batch_s() {
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
@@ -3419,7 +3433,7 @@ int mtf_batch_build_preconditioner(mtf_batch b, int32_t flags) {
             if (!p->has_mesh || !p->has_mat) throw StateError("problem lost its mesh or materials");
             if (!p->have32 && !p->have64) throw StateError("mtf_batch_build_preconditioner: assemble the batch first");
         }
-        batch_build_tinv(b->probs, kind, b->stream);
+        batch_build_tinv(b->probs, kind, b->stream, &b->gj);
         return MTF_OK;
     });
 }
@@ -3476,7 +3490,7 @@ int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, c
             }
             if (!need.empty()) {
                 try {
-                    t_pc = batch_build_tinv(need, pc_kind, b->stream);
+                    t_pc = batch_build_tinv(need, pc_kind, b->stream, &b->gj);
                 } catch (...) {
                     for (size_t i = 0; i < np; ++i)
                         if (tmpinv[i]) { b->probs[i]->Tinv.reset(); b->probs[i]->have_tinv = false; }
