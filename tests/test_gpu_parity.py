@@ -681,6 +681,31 @@ def test_batch_preconditioner_build_matches_lapack(cluster, sphere):
     B.close()
 
 
+def test_batch_preconditioner_rebuilds_reuse_storage(cluster, sphere):
+    """A batch keeps the build's padded work buffers, and the problems their blocks, from one build to
+    the next: builds per component, then of whole blocks (larger buckets: the work buffers grow),
+    then per component again after a new assembly (blocks stale, storage kept) each match LAPACK
+    solves with the oracle's blocks, and the batch solve from the last build reaches the LU solution."""
+    Pc, Ps = _fresh(cluster.cfg), _fresh(sphere.cfg)
+    B = mtf.Batch([Pc, Ps])
+    B.build_preconditioner(pc_direct=True)
+    _check_blocks_against_lapack(cluster, Pc, False, "rebuilds: first cluster")
+    _check_blocks_against_lapack(sphere, Ps, False, "rebuilds: first sphere")
+    B.build_preconditioner(pc_full=True)
+    _check_blocks_against_lapack(sphere, Ps, False, "rebuilds: whole sphere")   # one component: same blocks
+    B.assemble(mtf.FP64)
+    B.build_preconditioner(pc_direct=True)
+    _check_blocks_against_lapack(cluster, Pc, False, "rebuilds: again cluster")
+    _check_blocks_against_lapack(sphere, Ps, False, "rebuilds: again sphere")
+    bs = [torch.tensor(c.b[None, :], device="cuda") for c in (cluster, sphere)]
+    xs = [torch.zeros_like(b) for b in bs]
+    st = B.solve(bs, xs, rtol=1e-10, preconditioner=mtf.PREC_BLOCK_TINV_GS, max_iters=3000, pc_direct=True)
+    for s, x, c in zip(st, xs, (cluster, sphere)):
+        assert s.converged and s.rel_residual <= 1e-10
+        assert np.linalg.norm(x[0].cpu().numpy() - c.x) / np.linalg.norm(c.x) < 1e-7
+    B.close()
+
+
 @pytest.mark.parametrize("batched", [False, True])
 def test_preconditioner_rebuild_from_T_per_component(cluster, batched, monkeypatch):
     """With the symmetric-part check threshold at 0 every block fails its check and is rebuilt as the
