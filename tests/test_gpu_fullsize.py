@@ -268,7 +268,8 @@ def test_full_size_solution_matches_oracle_lu(c2):
 
 def test_full_size_cluster_batch_matches_oracle():
     """The 64-cluster batch in the bench's launch configuration (one persistent FP64 assembly of all
-    clusters, preconditioners built together as T_i^-1 per component, GMRES per cluster): sampled entries of T_i, K_i of the
+    clusters, preconditioners built together as T_i^-1 per component before the solve, GMRES per
+    cluster; the mixed path lets the solve build them): sampled entries of T_i, K_i of the
     largest and smallest clusters against the oracle's entries computed one by one (touching pairs
     included), and the four smallest clusters' solutions against the oracle's LU solutions, entry by
     entry, in FP64 and on the mixed path."""
@@ -301,6 +302,7 @@ def test_full_size_cluster_batch_matches_oracle():
     for ci in small:
         assert np.abs(bs[ci][0].cpu().numpy() - g[f"b_{ci}"]).max() < 1e-13 * np.abs(g[f"b_{ci}"]).max()
     xs = [torch.zeros_like(b) for b in bs]
+    B.build_preconditioner(pc_direct=True)      # as bench.py does: the blocks stay with the problems
     st = B.solve(bs, xs, rtol=1e-10, precision=mtf.FP64, preconditioner=mtf.PREC_BLOCK_TINV_GS, pc_direct=True)
     assert all(s.converged for s in st)
     for ci in small:
