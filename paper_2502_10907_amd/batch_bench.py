@@ -1,7 +1,8 @@
 """Batched assembly of many uneven scatterers: one persistent launch vs one launch set per problem.
 
 Usage: python -m paper_2502_10907_amd.batch_bench [nclusters] [precision 0|1] [solve 0|1|2]
-Then (solve=2) the preconditioner blocks of every cluster are built together, or (solve=1) every
+Then (solve=2) the preconditioner blocks of every cluster are built together (solve=3: built from
+T_i directly, per component, as the benchmark's step does), or (solve=1) every
 cluster is solved for one plane wave (d = +z, x-polarised) by mtf_batch_solve
 to ||b - Mx|| <= 1e-6 ||b||: GMRES on the assembled operator with FP64 refinement.
 Workload: clusters of 1-8 disjoint dielectric spheres (Fibonacci-hull meshes, 200-2000 triangles
@@ -58,10 +59,10 @@ def main(nclusters=64, precision=1, solve=1):
            "t_touching_pairs_s": t_touch, "t_batch_persistent_s": t_batch,
            "t_per_problem_launches_s": t_seq, "pairs_per_s_batch": pairs / t_batch,
            "pairs_per_s_per_problem": pairs / t_seq}
-    if solve == 2:
+    if solve in (2, 3):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        B.build_preconditioner()
+        B.build_preconditioner(pc_direct=solve == 3)
         torch.cuda.synchronize()
         out["t_precond_build_s"] = time.perf_counter() - t0
     elif solve:
