@@ -1,6 +1,6 @@
 """Batched assembly of many uneven scatterers: one persistent launch vs one launch set per problem.
 
-Usage: python -m paper_2502_10907_amd.batch_bench [nclusters] [precision 0|1] [solve 0|1|2]
+Usage: python -m paper_2502_10907_amd.batch_bench [nclusters] [precision 0|1] [solve 0|1|2|3]
 Then (solve=2) the preconditioner blocks of every cluster are built together (solve=3: built from
 T_i directly, per component, as the benchmark's step does), or (solve=1) every
 cluster is solved for one plane wave (d = +z, x-polarised) by mtf_batch_solve
