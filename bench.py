@@ -310,7 +310,7 @@ def main():
         cpu_worker(args.cpu_worker)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU: --gpus must be 1"}))
         sys.exit(2)
     cpu = None
     if not args.no_cpu_baseline and args.nclusters == 64:

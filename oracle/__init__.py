@@ -29,6 +29,6 @@ Preconditioning"):
 Textbook closed forms that pin the oracle live with the tests
 (``tests/_closed_forms.py``), not here.
 
-Readings where the paper is silent or inconsistent are documented in
-the design doc of the repository and restated at the function that takes them.
+Where the paper is silent or inconsistent, the reading taken is stated at
+the function that takes it.
 """
