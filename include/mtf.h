@@ -302,7 +302,7 @@ typedef struct {
  * first, then the colour classes of the subdomain adjacency graph (subdomains
  * of one class share no interface and are done together), each block solving
  * with P_i after subtracting the transmission terms of the blocks already done.  Right
- * preconditioning leaves the judged residual ||b - M x|| unchanged.  With either
+ * preconditioning leaves the residual that decides convergence, ||b - M x||, unchanged.  With either
  * preconditioner the iteration is flexible (the preconditioned vectors are kept),
  * so the FP32 application of P does not limit the attainable FP64 residual.
  * MTF_FP32_MIXED runs the inner GMRES with relaxed products (one right-hand side
