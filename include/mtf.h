@@ -424,15 +424,18 @@ int mtf_batch_build_preconditioner(mtf_batch b, int32_t flags);
  * meanwhile, and fewer steps are spent past convergence).  A problem without FP64
  * blocks gets them assembled (default options) for its residual checks and released after its
  * solve; with opts.precision MTF_FP32_MIXED a problem without complex64 blocks gets them rounded
- * from its FP64 blocks (MTF_ASSEMBLE_ROUND_FP64) for its solve only.  Preconditioner blocks that a
- * problem did not hold before the call are released after its solve (also when the call fails).
+ * from its FP64 blocks (MTF_ASSEMBLE_ROUND_FP64) for its solve only, into buffers that each stream
+ * keeps (grown to the largest problem it met, until mtf_batch_destroy) and lends to its solves.
+ * Preconditioner blocks that a problem did not hold before the call are released after its solve
+ * (also when the call fails).
  * A problem without GMRES work buffers of its own uses one of the batch's (one per stream,
  * allocated for the largest problem that stream met and kept until mtf_batch_destroy).  Device
  * memory needed beyond the assembled blocks: the preconditioner blocks of every problem (half the
  * bytes of the complex64 T_i, K_i), the build's padded work buffers (kept with the batch), per
- * stream one problem's temporary blocks and GMRES buffers.  A caller that solves the same batch
- * again after a new assembly builds the blocks with mtf_batch_build_preconditioner first, so that
- * they and their storage stay with the problems instead of being allocated for every call.
+ * stream one problem's temporary blocks (its complex64 blocks kept with the batch) and GMRES
+ * buffers.  A caller that solves the same batch again after a new assembly builds the blocks with
+ * mtf_batch_build_preconditioner first, so that they and their storage stay with the problems
+ * instead of being allocated for every call.
  * max_iters 0 here means cycles of at most 1,000 Arnoldi steps (not the free-memory length of
  * mtf_solve): a batch is many small solves, whose Krylov storage would otherwise be sized from free
  * memory. */

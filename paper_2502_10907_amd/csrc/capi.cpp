@@ -507,7 +507,8 @@ void assemble_prepare(mtf_problem p, int prec) {
 // Touching-pair corrections of the lower triangle for the blocks of `prec` (after their assembly).
 void near_corrections(mtf_problem p, int prec) {
     DevBuf<double>& out = prec == MTF_FP64 ? p->near64 : p->near32;
-    out.alloc(4 * std::max<int64_t>(p->near_nnz, 1));
+    const size_t need = 4 * (size_t)std::max<int64_t>(p->near_nnz, 1);
+    if (out.n < need) out.alloc(need);        // a buffer lent by a batch lane may be larger
     if (prec == MTF_FP64)
         launch_near_diff_f64(p->d_doms.p, p->d_dof_dom.p, p->ndof, p->d_near_ptr.p, p->d_near_col.p, p->T64.p, p->K64.p,
                              out.p, p->stream);
@@ -646,7 +647,9 @@ void assemble_impl(mtf_problem p, const mtf_assembly_opts* o) {
     if (flags & MTF_ASSEMBLE_ROUND_FP64) {
         // complex64 blocks rounded from the FP64 ones (padding included)
         if (!p->have64) throw StateError("MTF_ASSEMBLE_ROUND_FP64 needs the FP64 blocks: assemble MTF_FP64 first");
-        p->T32.alloc(n2); p->K32.alloc(n2);
+        // (buffers lent by a batch lane may be larger than this problem's blocks)
+        if (p->T32.n < (size_t)n2) p->T32.alloc(n2);
+        if (p->K32.n < (size_t)n2) p->K32.alloc(n2);
         HIPCHK(hipEventRecord(p->ev0, s));
         launch_copy_block_f64_to_f32(p->T64.p, p->T32.p, n2, s);
         launch_copy_block_f64_to_f32(p->K64.p, p->K32.p, n2, s);
@@ -3192,6 +3195,12 @@ struct mtf_batch_s {
     double last_tiles_s = 0.0;        // device time of the last persistent launch alone
     double last_total_s = 0.0;        // and of the whole last assembly (touching pairs included)
     GjScratch gj;                     // work buffers of the preconditioner build, kept between builds
+    // complex64 blocks of a lane, lent to each problem the lane solves on the mixed path (rounded
+    // from its FP64 blocks for that solve only), so that no solve allocates or frees them
+    struct LaneC64 {
+        DevBuf<float> T32, K32;
+        DevBuf<double> near32;
+    } c64[kLanes];
     ~mtf_batch_s() {
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
@@ -3470,11 +3479,22 @@ int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, c
         struct Release {
             mtf_problem p;
             bool tmp64 = false, tmpinv = false, tmpwork = false, tmp32 = false;
+            mtf_batch_s::LaneC64* lend32 = nullptr;   // the complex64 blocks are the lane's: give them back
             ~Release() {
                 if (!p) return;
                 (void)hipStreamSynchronize(p->stream);
                 if (tmp64) { p->T64.reset(); p->K64.reset(); p->near64.reset(); p->have64 = false; }
-                if (tmp32) { p->T32.reset(); p->K32.reset(); p->near32.reset(); p->have32 = false; p->gm.haveA = false; }
+                if (tmp32) {
+                    if (lend32) {
+                        swap_buf(p->T32, lend32->T32);
+                        swap_buf(p->K32, lend32->K32);
+                        swap_buf(p->near32, lend32->near32);
+                    } else {
+                        p->T32.reset(); p->K32.reset(); p->near32.reset();
+                    }
+                    p->have32 = false;
+                    p->gm.haveA = false;
+                }
                 if (tmpinv) { p->Tinv.reset(); p->have_tinv = false; p->gp.haveA = false; }
                 if (tmpwork) p->gw.release();
             }
@@ -3514,7 +3534,7 @@ int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, c
         std::mutex mu;
         std::exception_ptr err;
         int status = MTF_OK;
-        auto solve_one = [&](size_t i, GmresWork& lw) {
+        auto solve_one = [&](size_t i, GmresWork& lw, mtf_batch_s::LaneC64& lc) {
             mtf_problem p = b->probs[i];
             Release rel{p, !p->have64, (bool)tmpinv[i], false};
             // a problem without a workspace of its own borrows the lane's (allocated once, for the
@@ -3543,6 +3563,10 @@ int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, c
                 ao.precision = MTF_FP32_MIXED;
                 ao.singular_order = 4;
                 ao.flags = MTF_ASSEMBLE_ROUND_FP64;
+                swap_buf(p->T32, lc.T32);    // the lane's buffers, grown to the largest problem it met
+                swap_buf(p->K32, lc.K32);
+                swap_buf(p->near32, lc.near32);
+                rel.lend32 = &lc;
                 rel.tmp32 = true;
                 assemble_impl(p, &ao);       // the preconditioner stays: it was built from the FP64 blocks
             }
@@ -3554,7 +3578,7 @@ int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, c
             for (size_t k = 0; k < np; ++k) {
                 const size_t i = order[k];
                 try {
-                    const int r = solve_one(i, b->gw[0]);
+                    const int r = solve_one(i, b->gw[0], b->c64[0]);
                     if (r != MTF_OK) status = r;
                     done[i] = 1;
                 } catch (...) {
@@ -3591,7 +3615,7 @@ int mtf_batch_solve(mtf_batch b, const void* const* b_dev, void* const* x_dev, c
                         ~SyncSteps() { p->gmres_sync = kSync; }
                     } sync_steps{p};
                     p->gmres_sync = kSyncLanes;
-                    const int r = solve_one(i, b->gw[l]);
+                    const int r = solve_one(i, b->gw[l], b->c64[l]);
                     std::lock_guard<std::mutex> lk(mu);
                     if (r != MTF_OK) status = r;
                     done[i] = 1;
