@@ -341,7 +341,8 @@ def test_batch_persistent_assembly_matches_single(prec, sphere, ragged):
 def test_batch_solve(sphere, cube, lanes, prec, monkeypatch):
     """Three problems of different sizes solved by mtf_batch_solve one after another (one lane) or
     on three streams at once, in FP64 or on the mixed path with complex64 blocks rounded from the
-    FP64 ones for each solve (relaxed complex64 products, FP64 refinement): every solution equals
+    FP64 ones for each solve into the stream's own buffers (grown by the largest problem it meets and
+    lent to the smaller ones; relaxed complex64 products, FP64 refinement): every solution equals
     the oracle's LU solution (1e-7 at rtol 1e-10 in FP64, 1e-6 at rtol 1e-9 mixed)."""
     monkeypatch.setenv("MTF_BATCH_LANES", lanes)
     cl = _cluster_cfg()
